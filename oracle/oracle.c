@@ -1,0 +1,497 @@
+/*
+ * Plain FP64 CPU oracle for the multigrid Poisson solve and the projection
+ * time step of "Neural Physics" (Chen, Heaney, Pain, arXiv 2402.17913).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; it shares no source with the HIP path.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark use it.
+ *
+ * Every routine is a direct, unfused loop over cells, written to be checked
+ * against the paper by eye.  Floating point is FP64 throughout.
+ *
+ * Grid convention.  A d-dimensional grid (d = 2 or 3) of n cells per axis,
+ * cell index (i, j, k) with i fastest: idx = (k*n + j)*n + i.  Cell i has its
+ * centre at (i + 1/2) h.  Two boundary treatments, both realised as padding
+ * (ghost values) as in Section 2.1 ("additional ghost cells or halo nodes"):
+ *   OR_BC_DIRICHLET0: ghost = -(adjacent interior value), i.e. the padding
+ *                     that makes the solution vanish on the cell faces that
+ *                     bound the domain (reading of the paper's zero padding
+ *                     for a cell-centred grid);
+ *   OR_BC_PERIODIC:   ghost = value on the opposite side (wrap).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_BC_DIRICHLET0 0
+#define OR_BC_PERIODIC 1
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOCONV (-2)
+
+typedef int64_t i64;
+
+static i64 ncells(int d, i64 n) { return d == 2 ? n * n : n * n * n; }
+
+/* Value of grid function x at integer cell position (i, j, k), where each
+ * coordinate may lie one cell (or, for prolongation corners, one cell in
+ * several axes) outside [0, n).  Out-of-range axes are resolved one at a
+ * time by the boundary rule, so a corner ghost under DIRICHLET0 carries the
+ * product of the per-axis sign flips. */
+static double ghost_at(const double *x, int d, i64 n, int bc, i64 i, i64 j, i64 k)
+{
+    double sign = 1.0;
+    i64 c[3] = {i, j, k};
+    for (int a = 0; a < d; ++a) {
+        if (c[a] < 0) {
+            if (bc == OR_BC_PERIODIC) c[a] += n;
+            else { c[a] = -1 - c[a]; sign = -sign; }
+        } else if (c[a] >= n) {
+            if (bc == OR_BC_PERIODIC) c[a] -= n;
+            else { c[a] = 2 * n - 1 - c[a]; sign = -sign; }
+        }
+    }
+    if (d == 2) c[2] = 0;
+    return sign * x[(c[2] * n + c[1]) * n + c[0]];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Operator.  A x = (2d x_c - sum of the 2d face neighbours)/h^2: the
+ * central second-difference diffusion filter of Section 2.1 (the 5-point
+ * 3x3 filter with centre 4) and its 3D 7-point form of Appendix A (centre 6),
+ * with unit diffusivity and without the factor dt.  A is the negative
+ * discrete Laplacian, i.e. the paper's positive filter. */
+void or_apply_A(int d, i64 n, double h, int bc, const double *x, double *y)
+{
+    const double inv_h2 = 1.0 / (h * h);
+    const i64 nz = d == 3 ? n : 1;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                double s = ghost_at(x, d, n, bc, i - 1, j, k) + ghost_at(x, d, n, bc, i + 1, j, k)
+                         + ghost_at(x, d, n, bc, i, j - 1, k) + ghost_at(x, d, n, bc, i, j + 1, k);
+                if (d == 3)
+                    s += ghost_at(x, d, n, bc, i, j, k - 1) + ghost_at(x, d, n, bc, i, j, k + 1);
+                const double xc = x[(k * n + j) * n + i];
+                y[(k * n + j) * n + i] = (2.0 * d * xc - s) * inv_h2;
+            }
+}
+
+/* Residual r = f - A x (Appendix B, the residual of A*T = b). */
+void or_residual(int d, i64 n, double h, int bc, const double *f, const double *x, double *r)
+{
+    const i64 m = ncells(d, n);
+    or_apply_A(d, n, h, bc, x, r);
+    for (i64 c = 0; c < m; ++c) r[c] = f[c] - r[c];
+}
+
+static double dot(i64 m, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (i64 c = 0; c < m; ++c) s += a[c] * b[c];
+    return s;
+}
+
+/* Relative residual ||f - A x||_2 / ||f||_2, the convergence gauge that
+ * replaces the paper's successive-difference L1 norm (Section 3.2).  This is
+ * the judge of every result, whatever produced x. */
+double or_rel_res(int d, i64 n, double h, int bc, const double *f, const double *x)
+{
+    const i64 m = ncells(d, n);
+    double *r = malloc(sizeof(double) * m);
+    or_residual(d, n, h, bc, f, x, r);
+    const double nr = sqrt(dot(m, r, r)), nf = sqrt(dot(m, f, f));
+    free(r);
+    return nf > 0.0 ? nr / nf : nr;
+}
+
+/* One weighted-Jacobi sweep: every cell is updated from the old iterate,
+ * x_new = x + omega (f - A x) / A_00, with A_00 = 2d/h^2 the centre weight of
+ * the filter (Section 2.2, relaxed Jacobi dividing by the filter centre;
+ * Appendix B, division of the residual by A_0,0 / A_0,0,0).  Writes x_out,
+ * which must not alias x_in. */
+void or_jacobi(int d, i64 n, double h, int bc, double omega, const double *f, const double *x_in,
+               double *x_out)
+{
+    const i64 m = ncells(d, n);
+    const double a00 = 2.0 * d / (h * h);
+    or_apply_A(d, n, h, bc, x_in, x_out);
+    for (i64 c = 0; c < m; ++c) x_out[c] = x_in[c] + omega * (f[c] - x_out[c]) / a00;
+}
+
+/* Restriction (Section 2.2 and Appendix B): the coarse value is the average
+ * of the 2^d fine cells it covers, i.e. a 2x2 (2x2x2) filter of 1/4 (1/8)
+ * applied with stride 2.  n is the fine size. */
+void or_restrict(int d, i64 n, const double *r, double *fc)
+{
+    const i64 nc = n / 2, nzc = d == 3 ? nc : 1;
+    const double w = d == 3 ? 0.125 : 0.25;
+    for (i64 K = 0; K < nzc; ++K)
+        for (i64 J = 0; J < nc; ++J)
+            for (i64 I = 0; I < nc; ++I) {
+                double s = 0.0;
+                for (int c = 0; c < (d == 3 ? 2 : 1); ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a) {
+                            const i64 k = d == 3 ? 2 * K + c : 0;
+                            s += r[(k * n + 2 * J + b) * n + 2 * I + a];
+                        }
+                fc[(K * nc + J) * nc + I] = w * s;
+            }
+}
+
+/* Prolongation and correction x += P e.  The paper's prolongation copies a
+ * coarse value to its 2^d fine cells (Section 2.2); the configured transfer
+ * here is its cell-centred linear refinement: along each axis a fine cell
+ * takes 3/4 of its own coarse cell and 1/4 of the coarse neighbour on its
+ * side, and the d-dimensional weights are the products (9/16, 3/16, 3/16,
+ * 1/16 in 2D).  Coarse ghosts follow the boundary rule.  nc is the coarse
+ * size. */
+void or_prolong_add(int d, i64 nc, int bc, const double *e, double *x)
+{
+    const i64 n = 2 * nc, nz = d == 3 ? n : 1;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 own[3] = {i / 2, j / 2, k / 2};
+                const i64 nb[3] = {(i % 2) ? i / 2 + 1 : i / 2 - 1, (j % 2) ? j / 2 + 1 : j / 2 - 1,
+                                   (k % 2) ? k / 2 + 1 : k / 2 - 1};
+                double s = 0.0;
+                for (int c = 0; c < (d == 3 ? 2 : 1); ++c)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a) {
+                            const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) *
+                                             (d == 3 ? (c ? 0.25 : 0.75) : 1.0);
+                            s += w * ghost_at(e, d, nc, bc, a ? nb[0] : own[0], b ? nb[1] : own[1],
+                                              d == 3 ? (c ? nb[2] : own[2]) : 0);
+                        }
+                x[(k * n + j) * n + i] += s;
+            }
+}
+
+/* Dense Cholesky factorisation A = L L^T in place (lower triangle), m x m. */
+static int cholesky(i64 m, double *a)
+{
+    for (i64 j = 0; j < m; ++j) {
+        double s = a[j * m + j];
+        for (i64 p = 0; p < j; ++p) s -= a[j * m + p] * a[j * m + p];
+        if (!(s > 0.0)) return OR_EINVAL;
+        const double ljj = sqrt(s);
+        a[j * m + j] = ljj;
+        for (i64 i = j + 1; i < m; ++i) {
+            double t = a[i * m + j];
+            for (i64 p = 0; p < j; ++p) t -= a[i * m + p] * a[j * m + p];
+            a[i * m + j] = t / ljj;
+        }
+    }
+    return OR_OK;
+}
+
+/* Exact coarsest-grid solve (Section 2.2, "solve the system exactly"): the
+ * matrix of A on the coarsest grid is assembled column by column from the
+ * operator itself, factorised by Cholesky and applied to the residual, so
+ * x <- x + A^{-1} (f - A x).  For a periodic grid A is singular with the
+ * constants as null space; the matrix A + 1 1^T / m is solved instead, which
+ * for a mean-free right-hand side yields the mean-free solution of A x = f. */
+int or_coarse_solve(int d, i64 n, double h, int bc, const double *f, double *x)
+{
+    const i64 m = ncells(d, n);
+    double *a = malloc(sizeof(double) * m * m), *e = calloc(m, sizeof(double));
+    double *col = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
+    for (i64 j = 0; j < m; ++j) {
+        e[j] = 1.0;
+        or_apply_A(d, n, h, bc, e, col);
+        e[j] = 0.0;
+        for (i64 i = 0; i < m; ++i) a[i * m + j] = col[i] + (bc == OR_BC_PERIODIC ? 1.0 / m : 0.0);
+    }
+    int st = cholesky(m, a);
+    if (st == OR_OK) {
+        or_residual(d, n, h, bc, f, x, r);
+        for (i64 i = 0; i < m; ++i) { /* forward: L y = r */
+            double t = r[i];
+            for (i64 p = 0; p < i; ++p) t -= a[i * m + p] * r[p];
+            r[i] = t / a[i * m + i];
+        }
+        for (i64 i = m - 1; i >= 0; --i) { /* backward: L^T z = y */
+            double t = r[i];
+            for (i64 p = i + 1; p < m; ++p) t -= a[p * m + i] * r[p];
+            r[i] = t / a[i * m + i];
+        }
+        for (i64 i = 0; i < m; ++i) x[i] += r[i];
+    }
+    free(a); free(e); free(col); free(r);
+    return st;
+}
+
+/* One V(nu1, nu2) cycle on the level with n cells per axis and spacing h
+ * (Section 2.2, the multigrid cycle steps (1)-(8)): nu1 Jacobi sweeps,
+ * residual, restriction, recursive cycle for the coarse error from a zero
+ * guess, prolongation and correction, nu2 Jacobi sweeps.  Each coarser level
+ * re-discretises the operator with its own spacing 2h (Appendix B: the
+ * filters change between layers because the grid spacing changes). */
+int or_vcycle(int d, i64 n, double h, int bc, int nu1, int nu2, double omega, i64 n_coarsest,
+              const double *f, double *x)
+{
+    if (n <= n_coarsest) return or_coarse_solve(d, n, h, bc, f, x);
+    const i64 m = ncells(d, n), nc = n / 2, mc = ncells(d, nc);
+    double *t = malloc(sizeof(double) * m);
+    double *fc = malloc(sizeof(double) * mc), *ec = calloc(mc, sizeof(double));
+    for (int s = 0; s < nu1; ++s) {
+        or_jacobi(d, n, h, bc, omega, f, x, t);
+        memcpy(x, t, sizeof(double) * m);
+    }
+    or_residual(d, n, h, bc, f, x, t);
+    or_restrict(d, n, t, fc);
+    int st = or_vcycle(d, nc, 2.0 * h, bc, nu1, nu2, omega, n_coarsest, fc, ec);
+    or_prolong_add(d, nc, bc, ec, x);
+    for (int s = 0; s < nu2; ++s) {
+        or_jacobi(d, n, h, bc, omega, f, x, t);
+        memcpy(x, t, sizeof(double) * m);
+    }
+    free(t); free(fc); free(ec);
+    return st;
+}
+
+static int is_pow2(i64 n) { return n > 0 && (n & (n - 1)) == 0; }
+
+/* Solve driver.  The paper starts from a zero estimate (Section 2.2, the
+ * initial estimate of the solution is zero) and chains cycles; here cycles
+ * run until ||f - A x||_2 / ||f||_2 <= tol, tested before every cycle, or
+ * exactly fixed_cycles cycles when fixed_cycles > 0.  For a periodic grid the
+ * right-hand side is first made mean-free (compatibility of the singular
+ * problem) and the returned solution is the mean-free one.
+ * hist (may be NULL) receives the relative residual before each cycle and
+ * after the last one, at most hist_len entries. */
+int or_mg_solve(int d, i64 n, double h, int bc, const double *f_in, double *x, double tol, int nu1,
+                int nu2, double omega, int max_cycles, int fixed_cycles, int warm_start,
+                i64 n_coarsest, int *cycles_out, double *rel_res_out, double *hist, int hist_len)
+{
+    if ((d != 2 && d != 3) || !is_pow2(n) || n < 4 || !is_pow2(n_coarsest) || n_coarsest < 2 ||
+        !(h > 0.0) || !(tol > 0.0) || nu1 < 0 || nu2 < 0)
+        return OR_EINVAL;
+    const i64 m = ncells(d, n);
+    double *f = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
+    memcpy(f, f_in, sizeof(double) * m);
+    if (bc == OR_BC_PERIODIC) {
+        double mean = 0.0;
+        for (i64 c = 0; c < m; ++c) mean += f[c];
+        mean /= (double)m;
+        for (i64 c = 0; c < m; ++c) f[c] -= mean;
+    }
+    const double nf = sqrt(dot(m, f, f));
+    int st = OR_OK, k = 0;
+    double rr = 0.0;
+    if (nf == 0.0) {
+        memset(x, 0, sizeof(double) * m);
+    } else {
+        if (!warm_start) memset(x, 0, sizeof(double) * m);
+        for (;;) {
+            or_residual(d, n, h, bc, f, x, r);
+            rr = sqrt(dot(m, r, r)) / nf;
+            if (hist && k < hist_len) hist[k] = rr;
+            if (fixed_cycles > 0) {
+                if (k >= fixed_cycles) break;
+            } else {
+                if (rr <= tol) break;
+                if (k >= max_cycles) { st = OR_ENOCONV; break; }
+            }
+            int s = or_vcycle(d, n, h, bc, nu1, nu2, omega, n_coarsest, f, x);
+            if (s != OR_OK) { st = s; break; }
+            ++k;
+        }
+        if (bc == OR_BC_PERIODIC) {
+            double mean = 0.0;
+            for (i64 c = 0; c < m; ++c) mean += x[c];
+            mean /= (double)m;
+            for (i64 c = 0; c < m; ++c) x[c] -= mean;
+        }
+    }
+    if (cycles_out) *cycles_out = k;
+    if (rel_res_out) *rel_res_out = rr;
+    free(f); free(r);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Scalar advection-diffusion step (Section 2.1, predictor-corrector of the
+ * advection-diffusion filter).  With R(T) = sum_e a_e (T[+e] - T[-e])/(2h)
+ * - nu (discrete Laplacian of T), the predictor is T~ = T^n - dt R(T^n) and
+ * the corrector T^{n+1} = T^n - dt R((T~ + T^n)/2).  a holds d velocity
+ * arrays at the cells (collocated; NULL for no advection).  The central
+ * differences are the paper's first-derivative filters; the Laplacian is
+ * the negative of the diffusion filter's action. */
+static void ad_rate(int d, i64 n, double h, int bc, double nu, const double *const *a,
+                    const double *T, double *R)
+{
+    const i64 nz = d == 3 ? n : 1;
+    or_apply_A(d, n, h, bc, T, R); /* R = -Lap T */
+    for (i64 c = 0; c < ncells(d, n); ++c) R[c] *= nu;
+    if (!a) return;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 c = (k * n + j) * n + i;
+                double adv = a[0][c] * (ghost_at(T, d, n, bc, i + 1, j, k) - ghost_at(T, d, n, bc, i - 1, j, k))
+                           + a[1][c] * (ghost_at(T, d, n, bc, i, j + 1, k) - ghost_at(T, d, n, bc, i, j - 1, k));
+                if (d == 3)
+                    adv += a[2][c] * (ghost_at(T, d, n, bc, i, j, k + 1) - ghost_at(T, d, n, bc, i, j, k - 1));
+                R[c] += adv / (2.0 * h);
+            }
+}
+
+int or_ad_scalar_step(int d, i64 n, double h, int bc, double *T, const double *const *a, double dt,
+                      double nu)
+{
+    if ((d != 2 && d != 3) || n < 3 || !(h > 0.0)) return OR_EINVAL;
+    const i64 m = ncells(d, n);
+    double *R = malloc(sizeof(double) * m), *Tp = malloc(sizeof(double) * m);
+    ad_rate(d, n, h, bc, nu, a, T, R);
+    for (i64 c = 0; c < m; ++c) Tp[c] = T[c] - dt * R[c];            /* predictor */
+    for (i64 c = 0; c < m; ++c) Tp[c] = 0.5 * (Tp[c] + T[c]);        /* T^{n+1/2} */
+    ad_rate(d, n, h, bc, nu, a, Tp, R);
+    for (i64 c = 0; c < m; ++c) T[c] = T[c] - dt * R[c];              /* corrector */
+    free(R); free(Tp);
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Projection time step on a periodic staggered (MAC) grid (Section 2.4,
+ * the projection algorithm).  Pressure p sits at cell centres; velocity
+ * component q_c sits on the faces normal to axis c: q_c[idx] lives at
+ * idx + e_c/2.  Periodic boundaries only. */
+
+static i64 wrap_idx(int d, i64 n, i64 i, i64 j, i64 k)
+{
+    i = (i + n) % n; j = (j + n) % n; k = d == 3 ? (k + n) % n : 0;
+    return (k * n + j) * n + i;
+}
+
+/* Divergence at cell centres: (D q)[idx] = sum_c (q_c[idx] - q_c[idx - e_c]) / h. */
+void or_divergence(int d, i64 n, double h, const double *const *q, double *div)
+{
+    const i64 nz = d == 3 ? n : 1;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 c = (k * n + j) * n + i;
+                double s = (q[0][c] - q[0][wrap_idx(d, n, i - 1, j, k)])
+                         + (q[1][c] - q[1][wrap_idx(d, n, i, j - 1, k)]);
+                if (d == 3) s += q[2][c] - q[2][wrap_idx(d, n, i, j, k - 1)];
+                div[c] = s / h;
+            }
+}
+
+/* Gradient on faces: (G p)_c[idx] = (p[idx + e_c] - p[idx]) / h. */
+void or_gradient(int d, i64 n, double h, const double *p, double *const *g)
+{
+    const i64 nz = d == 3 ? n : 1;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 c = (k * n + j) * n + i;
+                g[0][c] = (p[wrap_idx(d, n, i + 1, j, k)] - p[c]) / h;
+                g[1][c] = (p[wrap_idx(d, n, i, j + 1, k)] - p[c]) / h;
+                if (d == 3) g[2][c] = (p[wrap_idx(d, n, i, j, k + 1)] - p[c]) / h;
+            }
+}
+
+/* Advecting velocity component e evaluated on the faces of component c.
+ * e == c: the value on the face itself.  e != c: the average of the four
+ * e-faces that surround the c-face, at idx, idx + e_c, idx - e_e and
+ * idx + e_c - e_e. */
+static double adv_vel(int d, i64 n, const double *const *a, int c, int e, i64 i, i64 j, i64 k)
+{
+    if (e == c) return a[e][wrap_idx(d, n, i, j, k)];
+    i64 oc[3] = {0, 0, 0}, oe[3] = {0, 0, 0};
+    oc[c] = 1; oe[e] = 1;
+    return 0.25 * (a[e][wrap_idx(d, n, i, j, k)] + a[e][wrap_idx(d, n, i + oc[0], j + oc[1], k + oc[2])]
+                 + a[e][wrap_idx(d, n, i - oe[0], j - oe[1], k - oe[2])]
+                 + a[e][wrap_idx(d, n, i + oc[0] - oe[0], j + oc[1] - oe[1], k + oc[2] - oe[2])]);
+}
+
+/* Momentum rate for component c (Section 2.3 momentum form and the
+ * discretised momentum equation of the projection algorithm, sigma = 0):
+ *   F_c(q) = sum_e a_e (q_c[+e] - q_c[-e])/(2h) - nu Lap(q_c) + (G p)_c
+ * with a = the lagged velocity u^n interpolated to the c-faces. */
+static void mom_rate(int d, i64 n, double h, double nu, const double *const *a, const double *p,
+                     int c, const double *qc, double *F)
+{
+    const i64 nz = d == 3 ? n : 1;
+    const double inv_h2 = 1.0 / (h * h);
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 ix = (k * n + j) * n + i;
+                double adv = 0.0, lap = -2.0 * d * qc[ix];
+                for (int e = 0; e < d; ++e) {
+                    i64 o[3] = {0, 0, 0};
+                    o[e] = 1;
+                    const double qp = qc[wrap_idx(d, n, i + o[0], j + o[1], k + o[2])];
+                    const double qm = qc[wrap_idx(d, n, i - o[0], j - o[1], k - o[2])];
+                    adv += adv_vel(d, n, a, c, e, i, j, k) * (qp - qm) / (2.0 * h);
+                    lap += qp + qm;
+                }
+                i64 o[3] = {0, 0, 0};
+                o[c] = 1;
+                const double gp = (p[wrap_idx(d, n, i + o[0], j + o[1], k + o[2])] - p[ix]) / h;
+                F[ix] = adv - nu * lap * inv_h2 + gp;
+            }
+}
+
+/* Explicit momentum stages of the projection step: predictor
+ * q~ = q^n - dt F(q^n), corrector q* = q^n - dt F((q~ + q^n)/2), advecting
+ * velocity lagged at u^n (second-order predictor-corrector of Section 2.1
+ * applied to each component, Section 2.3).  q is overwritten with q*. */
+void or_ns_momentum(int d, i64 n, double h, double dt, double nu, double *const *q, const double *p)
+{
+    const i64 m = ncells(d, n);
+    double *a[3] = {0, 0, 0}, *F = malloc(sizeof(double) * m), *half[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) {
+        a[c] = malloc(sizeof(double) * m);
+        memcpy(a[c], q[c], sizeof(double) * m);
+        half[c] = malloc(sizeof(double) * m);
+    }
+    for (int c = 0; c < d; ++c) {
+        mom_rate(d, n, h, nu, (const double *const *)a, p, c, a[c], F);
+        for (i64 x = 0; x < m; ++x) half[c][x] = 0.5 * ((a[c][x] - dt * F[x]) + a[c][x]);
+    }
+    for (int c = 0; c < d; ++c) {
+        mom_rate(d, n, h, nu, (const double *const *)a, p, c, half[c], F);
+        for (i64 x = 0; x < m; ++x) q[c][x] = a[c][x] - dt * F[x];
+    }
+    for (int c = 0; c < d; ++c) { free(a[c]); free(half[c]); }
+    free(F);
+}
+
+/* Full projection step (the projection algorithm of Section 2.4):
+ *  1. momentum predictor-corrector to q* with the old pressure gradient;
+ *  2. pressure correction: A dp = -(1/dt) D q*, A = -Lap (the paper's
+ *     positive filter), solved by the multigrid driver from a zero guess;
+ *  3. velocity correction dq = -dt G dp (explicit gradient);
+ *  4. p <- p + dp;  5. q <- q* + dq.
+ * Periodic boundaries.  Solver settings as for or_mg_solve. */
+int or_ns_step(int d, i64 n, double h, double *u, double *v, double *w, double *p, double dt,
+               double nu, double tol, int nu1, int nu2, double omega, int max_cycles,
+               int fixed_cycles, i64 n_coarsest, int *cycles_out, double *rel_res_out)
+{
+    if ((d != 2 && d != 3) || (d == 3 && !w) || !(dt > 0.0) || nu < 0.0) return OR_EINVAL;
+    const i64 m = ncells(d, n);
+    double *q[3] = {u, v, w};
+    or_ns_momentum(d, n, h, dt, nu, q, p);
+    double *rhs = malloc(sizeof(double) * m), *dp = calloc(m, sizeof(double));
+    or_divergence(d, n, h, (const double *const *)q, rhs);
+    for (i64 c = 0; c < m; ++c) rhs[c] *= -1.0 / dt;
+    int st = or_mg_solve(d, n, h, OR_BC_PERIODIC, rhs, dp, tol, nu1, nu2, omega, max_cycles,
+                         fixed_cycles, 0, n_coarsest, cycles_out, rel_res_out, NULL, 0);
+    double *g[3] = {0, 0, 0};
+    for (int c = 0; c < d; ++c) g[c] = malloc(sizeof(double) * m);
+    or_gradient(d, n, h, dp, g);
+    for (int c = 0; c < d; ++c)
+        for (i64 x = 0; x < m; ++x) q[c][x] -= dt * g[c][x];
+    for (i64 x = 0; x < m; ++x) p[x] += dp[x];
+    for (int c = 0; c < d; ++c) free(g[c]);
+    free(rhs); free(dp);
+    return st;
+}
