@@ -1,0 +1,174 @@
+/*
+ * neuphys.h -- C ABI of libneuphys.so: MI355X (gfx950) multigrid Poisson
+ * solver and incompressible projection step after "Neural Physics"
+ * (Chen, Heaney, Pain, arXiv 2402.17913).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers (hipMalloc'd memory, e.g. a torch
+ *    tensor's data_ptr()) owned by the caller, unless a parameter says
+ *    "host".  Layout: unpadded, contiguous, x fastest; a 2D field is
+ *    [ny][nx], a 3D field [nz][ny][nx] (a torch tensor of shape (ny, nx) or
+ *    (nz, ny, nx)).  Cell i along an axis has its centre at (i + 1/2) h.
+ *  - Grids: ndim in {2, 3}, every axis the same size n, n a power of two,
+ *    4 <= n <= 8192 in 2D, 4 <= n <= 1024 in 3D.  Anything else is
+ *    NP_EINVAL and leaves every buffer untouched.
+ *  - Boundary conditions are ghost values ("padding", Section 2.1):
+ *    NP_BC_DIRICHLET0 sets the ghost to minus the adjacent interior value
+ *    (zero on the boundary faces of the cell-centred grid); NP_BC_PERIODIC
+ *    wraps.
+ *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null
+ *    stream).  Every call returns after its work on that stream is
+ *    complete: convergence decisions need the residual norm on the host.
+ *  - Errors are returned as np_status, never thrown; np_last_error() gives
+ *    a message for the calling thread's last non-OK status.  Calls are
+ *    thread-safe for distinct streams; the per-shape workspaces are cached
+ *    inside the library and released by np_release_all().
+ *  - The operator is A = -Lap_h, the paper's positive 5-point (2D) and
+ *    7-point (3D) diffusion filters (Section 2.1 and Appendix A) with unit
+ *    diffusivity: (A x)_c = (2d x_c - sum of the 2d face neighbours) / h^2.
+ */
+#ifndef NEUPHYS_H
+#define NEUPHYS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NP_OK = 0,
+    NP_EINVAL = -1,   /* bad argument; buffers untouched */
+    NP_ENOCONV = -2,  /* tolerance not reached in max_cycles (or divergence); x holds the last iterate */
+    NP_ENAN = -3,     /* a non-finite residual norm was seen; x holds the last iterate */
+    NP_EHIP = -4,     /* HIP runtime error */
+    NP_ENOMEM = -5    /* device allocation failed */
+} np_status;
+
+typedef enum { NP_BC_DIRICHLET0 = 0, NP_BC_PERIODIC = 1 } np_bc;
+
+/* Storage precision of the smoothing and transfer steps.  NP_FP64: plain
+ * FP64 V-cycles.  NP_FP32 / NP_BF16: mixed-precision iterative refinement --
+ * FP64 residual and update, inner V-cycles storing fields in FP32 / BF16 with
+ * FP32 arithmetic, FP64 coarsest solve. */
+typedef enum { NP_FP64 = 0, NP_FP32 = 1, NP_BF16 = 2 } np_prec;
+
+typedef struct {
+    int ndim;       /* 2 or 3 */
+    int64_t n[3];   /* n[0] = nx (fastest), n[1] = ny, n[2] = nz (ignored in 2D) */
+} np_dims;
+
+typedef struct {
+    int nu1, nu2;         /* pre-/post-smoothing weighted-Jacobi sweeps per level (default 2, 2) */
+    double omega;         /* Jacobi relaxation weight (default 2/3) */
+    int max_cycles;       /* cap on V-cycles (FP64) or outer refinement steps (mixed), default 200 */
+    int fixed_cycles;     /* > 0: run exactly this many cycles / outer steps and ignore tol */
+    np_prec smooth_prec;  /* default NP_FP64 */
+    int inner_cycles;     /* mixed only: V-cycles per refinement step; 0 = library default */
+    int warm_start;       /* 0: x is zeroed first (the paper's zero initial estimate); 2: x is the initial guess */
+    void *stream;         /* hipStream_t to run on; NULL = null stream */
+} np_mg_opts;
+
+typedef struct {
+    int cycles;           /* V-cycles run (all precisions, inner cycles included) */
+    int outer_iters;      /* refinement steps (mixed), = cycles for FP64 */
+    int used_fallback;    /* reserved for learned warm starts: 1 if the guess was rejected */
+    double rel_res;       /* final ||f - A x||_2 / ||f||_2 in FP64 (f mean-free when periodic) */
+    double rho_est;       /* geometric mean residual reduction per cycle / outer step */
+    double hist[256];     /* rel_res before each cycle / outer step and after the last */
+} np_mg_stats;
+
+/* Fills *opts with the defaults listed above. */
+void np_default_opts(np_mg_opts *opts);
+
+/*
+ * Multigrid solve of A x = rhs (the implicit system of Section 2.2 and
+ * Appendix B: residual, restriction by 2^d-cell averaging, Jacobi smoothing
+ * dividing by the filter centre, prolongation, exact coarsest solve on the
+ * 4^d grid, re-discretised operator with spacing 2^l h on level l).  Cycles
+ * are V(nu1, nu2) cycles with cell-centred (bi/tri)linear prolongation.
+ * rhs: device, read-only, FP64.  x: device, FP64, in/out (see warm_start).
+ * Stops when ||rhs - A x||_2 / ||rhs||_2 <= tol, tested before each cycle
+ * (or after opts->fixed_cycles cycles).  Periodic: rhs is made mean-free on
+ * an internal copy and the mean-free solution is returned.  A zero rhs
+ * returns x = 0, 0 cycles.  opts, stats: host, nullable.
+ */
+np_status mg_poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, double *x,
+                           double tol, const np_mg_opts *opts, np_mg_stats *stats);
+
+/*
+ * One projection time step of the incompressible Navier-Stokes equations
+ * (Section 2.4, the projection algorithm; momentum discretised as in
+ * Sections 2.1 and 2.3 with sigma = 0) on a periodic staggered grid:
+ * p at cell centres; u[k][j][i] on the x-face between cells i and i+1,
+ * v on the y-face between rows j and j+1, w on the z-face.  Steps:
+ * predictor q~ = q^n - dt F(q^n), corrector q* = q^n - dt F((q~ + q^n)/2)
+ * with F(q) = (a . grad_c) q - nu Lap q + G p^n, a = u^n on the faces
+ * (central differences); then A dp = -(1/dt) D q* solved by mg_poisson_solve
+ * from a zero guess to tol; q = q* - dt G dp; p += dp.
+ * u, v, p (and w in 3D; NULL in 2D): device, FP64, in/out.  h: cell size.
+ * bc must be NP_BC_PERIODIC.  stats receive the pressure solve's numbers.
+ */
+np_status ns_projection_step(np_dims dims, double h, double *u, double *v, double *w, double *p,
+                             double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
+                             np_mg_stats *stats);
+
+/*
+ * One scalar advection-diffusion step, the second-order predictor-corrector
+ * of Section 2.1 (the combined advection-diffusion filter applied to
+ * (T~ + T^n)/2): T~ = T - dt R(T), T <- T - dt R((T~ + T)/2) with
+ * R(T) = sum_e a_e (T[+e] - T[-e]) / (2h) - nu Lap T.  Unlike the solver,
+ * any n >= 3 is accepted (all axes equal).  T: device FP64 in/out.
+ * a: host array of ndim device pointers to collocated velocity fields, or
+ * NULL for pure diffusion.  opts: only opts->stream is used.
+ */
+np_status np_ad_scalar_step(np_dims dims, double h, double *T, const double *const *a, double dt,
+                            double nu, np_bc bc, const np_mg_opts *opts);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *np_last_error(void);
+
+/* Frees every cached workspace (level hierarchies, scratch) on every device. */
+void np_release_all(void);
+
+/* ---------------------------------------------------------------------- */
+/* Single-operator entry points.  They run one step of the cycle on caller
+ * buffers (device, FP64, layout as above) so each kernel can be checked on
+ * its own; n is the size of the grid named first. */
+
+/* y = A x (Section 2.1 diffusion filter, Appendix A 3D form). */
+np_status np_op_apply(np_dims dims, double h, np_bc bc, const double *x, double *y, void *stream);
+/* x_out = x_in + omega (f - A x_in) / A_00, A_00 = 2d/h^2 (Section 2.2, relaxed Jacobi;
+ * Appendix B, division by the filter centre).  x_out must not alias x_in. */
+np_status np_op_jacobi(np_dims dims, double h, np_bc bc, double omega, const double *f,
+                       const double *x_in, double *x_out, void *stream);
+/* fc = R (f - A x): residual then 2^d-cell average (Section 2.2 restriction;
+ * Appendix B restriction recursion).  fc has n/2 cells per axis. */
+np_status np_op_resid_restrict(np_dims dims, double h, np_bc bc, const double *f, const double *x,
+                               double *fc, void *stream);
+/* x += P ec, cell-centred (bi/tri)linear prolongation of the coarse error ec
+ * (n/2 cells per axis) onto x (n cells per axis), coarse ghosts by bc. */
+np_status np_op_prolong_add(np_dims dims, np_bc bc, const double *ec, double *x, void *stream);
+/* One V(nu1, nu2) cycle x <- V(x, f) with the settings of opts (nullable; FP64 only). */
+np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double *x,
+                       const np_mg_opts *opts);
+/* *out (host) = ||f - A x||_2 computed in FP64 by the library's reduction. */
+np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const double *f, const double *x,
+                           double *out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Kernel timing for the benchmark: while enabled, the library brackets every
+ * launch of the finest-level smoothing kernels with HIP events on the stream
+ * it launches them on.  np_prof_read returns (host) the number of such
+ * launches and the sum of their durations in milliseconds since the last
+ * enable, plus the algorithmic bytes those launches move by the library's
+ * byte model. */
+void np_prof_enable(int on);
+np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEUPHYS_H */

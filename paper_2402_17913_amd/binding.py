@@ -1,0 +1,198 @@
+"""ctypes binding of libneuphys.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: tensors must already be on the GPU, contiguous and of
+the dtype the entry point expects.  If the library is not built, importing
+the binding raises immediately -- there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libneuphys.so")
+
+NP_OK, NP_EINVAL, NP_ENOCONV, NP_ENAN, NP_EHIP, NP_ENOMEM = 0, -1, -2, -3, -4, -5
+BC_DIRICHLET0, BC_PERIODIC = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
+_STATUS = {0: "NP_OK", -1: "NP_EINVAL", -2: "NP_ENOCONV", -3: "NP_ENAN", -4: "NP_EHIP", -5: "NP_ENOMEM"}
+
+
+class NpDims(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int64 * 3)]
+
+
+class NpMgOpts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
+                ("max_cycles", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
+                ("smooth_prec", ctypes.c_int), ("inner_cycles", ctypes.c_int),
+                ("warm_start", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class NpMgStats(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("used_fallback", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("rho_est", ctypes.c_double), ("hist", ctypes.c_double * 256)]
+
+    def as_dict(self):
+        n = min(256, max(self.outer_iters, self.cycles) + 1)
+        return dict(cycles=self.cycles, outer_iters=self.outer_iters,
+                    used_fallback=self.used_fallback, rel_res=self.rel_res,
+                    rho_est=self.rho_est, hist=list(self.hist[:n]))
+
+
+class NeuphysError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__("%s -> %s: %s" % (fn, _STATUS.get(status, status), msg))
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_SIGS = {
+    "np_default_opts": (None, [ctypes.POINTER(NpMgOpts)]),
+    "np_last_error": (ctypes.c_char_p, []),
+    "np_release_all": (None, []),
+    "mg_poisson_solve": (_I, [NpDims, _D, _I, _P, _P, _D, ctypes.POINTER(NpMgOpts),
+                              ctypes.POINTER(NpMgStats)]),
+    "ns_projection_step": (_I, [NpDims, _D, _P, _P, _P, _P, _D, _D, _I, _D,
+                                ctypes.POINTER(NpMgOpts), ctypes.POINTER(NpMgStats)]),
+    "np_ad_scalar_step": (_I, [NpDims, _D, _P, _P, _D, _D, _I, ctypes.POINTER(NpMgOpts)]),
+    "np_op_apply": (_I, [NpDims, _D, _I, _P, _P, _P]),
+    "np_op_jacobi": (_I, [NpDims, _D, _I, _D, _P, _P, _P, _P]),
+    "np_op_resid_restrict": (_I, [NpDims, _D, _I, _P, _P, _P, _P]),
+    "np_op_prolong_add": (_I, [NpDims, _I, _P, _P, _P]),
+    "np_op_vcycle": (_I, [NpDims, _D, _I, _P, _P, ctypes.POINTER(NpMgOpts)]),
+    "np_op_resid_norm": (_I, [NpDims, _D, _I, _P, _P, ctypes.POINTER(_D), _P]),
+    "np_prof_enable": (None, [_I]),
+    "np_prof_read": (_I, [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libneuphys.so is not built (expected at %s); run "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def _check(fn, st):
+    if st != NP_OK:
+        raise NeuphysError(fn, st, lib.np_last_error().decode())
+
+
+def _dims(t):
+    if t.dim() not in (2, 3):
+        raise ValueError("fields must be 2D or 3D tensors")
+    n = list(reversed(t.shape)) + [1] * (3 - t.dim())
+    return NpDims(t.dim(), (ctypes.c_int64 * 3)(*n))
+
+
+def _dev(t, dtype=torch.float64):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype):
+        raise ValueError("expected a contiguous %s CUDA tensor" % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_opts(nu1=2, nu2=2, omega=2.0 / 3.0, max_cycles=200, fixed_cycles=0, smooth_prec=FP64,
+              inner_cycles=0, warm_start=0):
+    o = NpMgOpts()
+    lib.np_default_opts(ctypes.byref(o))
+    o.nu1, o.nu2, o.omega = nu1, nu2, omega
+    o.max_cycles, o.fixed_cycles = max_cycles, fixed_cycles
+    o.smooth_prec, o.inner_cycles, o.warm_start = smooth_prec, inner_cycles, warm_start
+    o.stream = _stream()
+    return o
+
+
+def mg_poisson_solve(rhs, x, h, bc, tol=1e-10, check=True, **opts):
+    """Solves A x = rhs in place in x; returns (status, stats dict)."""
+    o = make_opts(**opts)
+    st = NpMgStats()
+    s = lib.mg_poisson_solve(_dims(rhs), h, bc, _dev(rhs), _dev(x), tol, ctypes.byref(o),
+                             ctypes.byref(st))
+    if check:
+        _check("mg_poisson_solve", s)
+    return s, st.as_dict()
+
+
+def ns_projection_step(u, v, w, p, h, dt, nu, bc=BC_PERIODIC, tol=1e-10, check=True, **opts):
+    o = make_opts(**opts)
+    st = NpMgStats()
+    s = lib.ns_projection_step(_dims(p), h, _dev(u), _dev(v), _dev(w), _dev(p), dt, nu, bc, tol,
+                               ctypes.byref(o), ctypes.byref(st))
+    if check:
+        _check("ns_projection_step", s)
+    return s, st.as_dict()
+
+
+def np_ad_scalar_step(T, h, dt, nu, bc, a=None):
+    arr = None
+    if a is not None:
+        arr = (ctypes.c_void_p * 3)(*[_dev(c).value for c in a] + [None] * (3 - len(a)))
+    o = make_opts()
+    s = lib.np_ad_scalar_step(_dims(T), h, _dev(T), ctypes.cast(arr, ctypes.c_void_p) if arr else None,
+                              dt, nu, bc, ctypes.byref(o))
+    _check("np_ad_scalar_step", s)
+
+
+def np_op_apply(x, y, h, bc):
+    _check("np_op_apply", lib.np_op_apply(_dims(x), h, bc, _dev(x), _dev(y), _stream()))
+
+
+def np_op_jacobi(f, x_in, x_out, h, bc, omega=2.0 / 3.0):
+    _check("np_op_jacobi", lib.np_op_jacobi(_dims(x_in), h, bc, omega, _dev(f), _dev(x_in),
+                                            _dev(x_out), _stream()))
+
+
+def np_op_resid_restrict(f, x, fc, h, bc):
+    _check("np_op_resid_restrict", lib.np_op_resid_restrict(_dims(x), h, bc, _dev(f), _dev(x),
+                                                            _dev(fc), _stream()))
+
+
+def np_op_prolong_add(ec, x, bc):
+    _check("np_op_prolong_add", lib.np_op_prolong_add(_dims(x), bc, _dev(ec), _dev(x), _stream()))
+
+
+def np_op_vcycle(f, x, h, bc, **opts):
+    o = make_opts(**opts)
+    _check("np_op_vcycle", lib.np_op_vcycle(_dims(x), h, bc, _dev(f), _dev(x), ctypes.byref(o)))
+
+
+def np_op_resid_norm(f, x, h, bc):
+    out = ctypes.c_double(0.0)
+    _check("np_op_resid_norm", lib.np_op_resid_norm(_dims(x), h, bc, _dev(f), _dev(x),
+                                                    ctypes.byref(out), _stream()))
+    return out.value
+
+
+def np_prof_enable(on):
+    lib.np_prof_enable(1 if on else 0)
+
+
+def np_prof_read():
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
+    _check("np_prof_read", lib.np_prof_read(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return n.value, ms.value, by.value
+
+
+def np_release_all():
+    lib.np_release_all()

@@ -1,0 +1,288 @@
+// Device kernels of the multigrid cycle (gfx950).  Included by mg.hip only.
+//
+// Grid of n = 2^lg cells per axis, index c = (k*n + j)*n + i, x fastest.
+// Ghost rule: bc == 0 (Dirichlet-0) ghost = -(own value); bc == 1 wraps.
+// The operator is A x = (2d x_c - sum of face neighbours) * inv_h2.
+#pragma once
+
+#include "np_internal.h"
+
+namespace np {
+
+// Sum of the 2d face neighbours of cell c = (i, j, k), read through `ld`
+// (a functor index -> value); ghosts by the boundary rule.  Summation order
+// x-, x+, y-, y+, z-, z+.
+template <int D, class C, class L>
+__device__ __forceinline__ C nb_sum(const L &ld, int64_t c, int i, int j, int k, int lg, int bc,
+                                    C xc) {
+    const int n = 1 << lg;
+    const int64_t sy = int64_t(1) << lg;
+    const C xm = i > 0 ? ld(c - 1) : (bc ? ld(c + (n - 1)) : -xc);
+    const C xp = i < n - 1 ? ld(c + 1) : (bc ? ld(c - (n - 1)) : -xc);
+    const C ym = j > 0 ? ld(c - sy) : (bc ? ld(c + (n - 1) * sy) : -xc);
+    const C yp = j < n - 1 ? ld(c + sy) : (bc ? ld(c - (n - 1) * sy) : -xc);
+    C s = ((xm + xp) + ym) + yp;
+    if (D == 3) {
+        const int64_t sz = int64_t(1) << (2 * lg);
+        const C zm = k > 0 ? ld(c - sz) : (bc ? ld(c + (n - 1) * sz) : -xc);
+        const C zp = k < n - 1 ? ld(c + sz) : (bc ? ld(c - (n - 1) * sz) : -xc);
+        s = (s + zm) + zp;
+    }
+    return s;
+}
+
+template <class S> struct Ld {
+    const S *p;
+    __device__ __forceinline__ typename St<S>::C operator()(int64_t q) const { return St<S>::ld(p + q); }
+};
+
+template <int D>
+__device__ __forceinline__ void decode(int64_t c, int lg, int &i, int &j, int &k) {
+    const int n = 1 << lg;
+    i = int(c & (n - 1));
+    j = int((c >> lg) & (n - 1));
+    k = D == 3 ? int(c >> (2 * lg)) : 0;
+}
+
+// r = f - A x at cell c.
+template <int D, class S>
+__device__ __forceinline__ typename St<S>::C resid_at(const S *__restrict__ f, const S *__restrict__ x,
+                                                      int64_t c, int i, int j, int k, int lg, int bc,
+                                                      typename St<S>::C inv_h2) {
+    typedef typename St<S>::C C;
+    const C xc = St<S>::ld(x + c);
+    const C s = nb_sum<D, C>(Ld<S>{x}, c, i, j, k, lg, bc, xc);
+    return St<S>::ld(f + c) - (C(2 * D) * xc - s) * inv_h2;
+}
+
+// One weighted-Jacobi sweep x_out = x_in + wdiag (f - A x_in), wdiag = omega/A_00.
+// ZERO: x_in is identically zero (first sweep on a coarse level), x_out = wdiag f.
+template <int D, class S, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_jacobi(const S *__restrict__ f, const S *__restrict__ xin,
+                                                   S *__restrict__ xout, int lg, int bc,
+                                                   typename St<S>::C inv_h2,
+                                                   typename St<S>::C wdiag) {
+    typedef typename St<S>::C C;
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    const C fc = St<S>::ld(f + c);
+    if (ZERO) {
+        St<S>::st(xout + c, wdiag * fc);
+        return;
+    }
+    int i, j, k;
+    decode<D>(c, lg, i, j, k);
+    const C xc = St<S>::ld(xin + c);
+    const C s = nb_sum<D, C>(Ld<S>{xin}, c, i, j, k, lg, bc, xc);
+    St<S>::st(xout + c, xc + wdiag * (fc - (C(2 * D) * xc - s) * inv_h2));
+}
+
+// fc = R (f - A x): one thread per coarse cell averages the residual of its
+// 2^d children (z outer, then y, then x).  lg is the fine level's log2 size.
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(const S *__restrict__ f,
+                                                           const S *__restrict__ x,
+                                                           S *__restrict__ fc, int lg, int bc,
+                                                           typename St<S>::C inv_h2) {
+    typedef typename St<S>::C C;
+    const int lgc = lg - 1;
+    const int64_t mc = int64_t(1) << (D * lgc);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= mc) return;
+    int I, J, K;
+    decode<D>(c, lgc, I, J, K);
+    C acc = C(0);
+    for (int kk = 0; kk < (D == 3 ? 2 : 1); ++kk)
+        for (int jj = 0; jj < 2; ++jj)
+            for (int ii = 0; ii < 2; ++ii) {
+                const int i = 2 * I + ii, j = 2 * J + jj, k = D == 3 ? 2 * K + kk : 0;
+                const int64_t cf = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
+                acc += resid_at<D, S>(f, x, cf, i, j, k, lg, bc, inv_h2);
+            }
+    St<S>::st(fc + c, acc * C(D == 3 ? 0.125 : 0.25));
+}
+
+// Coarse index along one axis for the linear prolongation: the neighbour of
+// the own coarse cell on the side of fine cell `i`, with its ghost sign.
+__device__ __forceinline__ void pro_axis(int i, int nc, int bc, int &own, int &nb, float &sgn) {
+    own = i >> 1;
+    nb = (i & 1) ? own + 1 : own - 1;
+    sgn = 1.0f;
+    if (nb < 0) {
+        if (bc) nb = nc - 1;
+        else { nb = 0; sgn = -1.0f; }
+    } else if (nb >= nc) {
+        if (bc) nb = 0;
+        else { nb = nc - 1; sgn = -1.0f; }
+    }
+}
+
+// x += P ec, one thread per fine cell.  Per axis the own coarse cell has
+// weight 3/4 and the neighbour 1/4; ghost neighbours carry the sign of the
+// boundary rule.  lgc is the coarse level's log2 size.
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec, S *__restrict__ x,
+                                                        int lgc, int bc) {
+    typedef typename St<S>::C C;
+    const int lg = lgc + 1, nc = 1 << lgc;
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int i, j, k;
+    decode<D>(c, lg, i, j, k);
+    int oi, ni, oj, nj, ok = 0, nk = 0;
+    float si, sj, sk = 1.0f;
+    pro_axis(i, nc, bc, oi, ni, si);
+    pro_axis(j, nc, bc, oj, nj, sj);
+    if (D == 3) pro_axis(k, nc, bc, ok, nk, sk);
+    C s = C(0);
+    for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(D == 3 ? (cz ? 0.25 : 0.75) : 1.0);
+                const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
+                const int64_t q = (int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
+                                  (a ? ni : oi);
+                s += w * (sg * St<S>::ld(ec + q));
+            }
+    St<S>::st(x + c, St<S>::ld(x + c) + s);
+}
+
+// Exact solve on the 4^d coarsest grid: x <- x + Minv (f - A x), Minv the
+// dense FP64 inverse (periodic: of A + 1 1^T / m).  One workgroup of 64.
+template <int D, class S>
+__global__ __launch_bounds__(64) void k_coarse(const S *__restrict__ f, S *__restrict__ x,
+                                               const double *__restrict__ Minv, int bc, double inv_h2,
+                                               int zero) {
+    constexpr int m = D == 3 ? 64 : 16;
+    __shared__ double xs[64], rs[64];
+    const int t = threadIdx.x;
+    if (t < m) xs[t] = zero ? 0.0 : double(St<S>::ld(x + t));
+    __syncthreads();
+    if (t < m) {
+        int i, j, k;
+        decode<D>(t, 2, i, j, k);
+        struct {
+            const double *p;
+            __device__ double operator()(int64_t q) const { return p[q]; }
+        } ldx{xs};
+        const double s = nb_sum<D, double>(ldx, t, i, j, k, 2, bc, xs[t]);
+        rs[t] = double(St<S>::ld(f + t)) - (double(2 * D) * xs[t] - s) * inv_h2;
+    }
+    __syncthreads();
+    if (t < m) {
+        double acc = 0.0;
+        for (int q = 0; q < m; ++q) acc += Minv[t * m + q] * rs[q];
+        St<S>::st(x + t, typename St<S>::C(xs[t] + acc));
+    }
+}
+
+// Partial sums of (f - A x)^2 in FP64 over a fixed grid of blocks.
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_resid_sq(const S *__restrict__ f, const S *__restrict__ x,
+                                                     double *__restrict__ partial, int lg, int bc,
+                                                     typename St<S>::C inv_h2) {
+    const int64_t m = int64_t(1) << (D * lg);
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        const double r = double(resid_at<D, S>(f, x, c, i, j, k, lg, bc, inv_h2));
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Partial sums of v (square = 0) or v^2 (square = 1) in FP64.
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_sum(const S *__restrict__ v, int64_t m, int square,
+                                                double *__restrict__ partial) {
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        const double a = double(St<S>::ld(v + c));
+        acc += square ? a * a : a;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// out[slot] = sum of partial[0..np) in a fixed order (sqrt when root).
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int np,
+                                                     double *__restrict__ out, int root) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < np; b += blockDim.x) acc += partial[b];
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) out[0] = root ? sqrt(acc) : acc;
+}
+
+// v[c] -= sum[0] * scale (mean removal with the sum left on the device).
+__global__ __launch_bounds__(kBlock) void k_sub_scaled(double *__restrict__ v, int64_t m,
+                                                       const double *__restrict__ sum, double scale) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < m) v[c] -= sum[0] * scale;
+}
+
+// FP64 refinement step of the mixed-precision solve: x_out = x + e (e in the
+// inner precision; has_e = 0 means e = 0 and x_out is not written),
+// r = f - A x_out in FP64, r_lo = r rounded to the inner precision, and FP64
+// partial sums of r^2.  Neighbour values of x_out are formed on the fly, so
+// x and x_out must be different buffers.
+template <int D, class SL>
+__global__ __launch_bounds__(kBlock) void k_ir_resid(const double *__restrict__ x,
+                                                     const SL *__restrict__ e,
+                                                     double *__restrict__ xout,
+                                                     const double *__restrict__ f,
+                                                     SL *__restrict__ rlo,
+                                                     double *__restrict__ partial, int lg, int bc,
+                                                     double inv_h2, int has_e) {
+    const int64_t m = int64_t(1) << (D * lg);
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        struct {
+            const double *x;
+            const SL *e;
+            int he;
+            __device__ double operator()(int64_t q) const {
+                return he ? x[q] + double(St<SL>::ld(e + q)) : x[q];
+            }
+        } ldx{x, e, has_e};
+        const double xc = ldx(c);
+        const double s = nb_sum<D, double>(ldx, c, i, j, k, lg, bc, xc);
+        const double r = f[c] - (double(2 * D) * xc - s) * inv_h2;
+        if (has_e) xout[c] = xc;
+        St<SL>::st(rlo + c, typename St<SL>::C(r));
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// y = A x (FP64).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_apply(const double *__restrict__ x, double *__restrict__ y, int lg,
+                                                  int bc, double inv_h2) {
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int i, j, k;
+    decode<D>(c, lg, i, j, k);
+    const double xc = x[c];
+    const double s = nb_sum<D, double>(Ld<double>{x}, c, i, j, k, lg, bc, xc);
+    y[c] = (double(2 * D) * xc - s) * inv_h2;
+}
+
+// Fill with zeros (used instead of a memset so the work stays in kernels).
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_zero(S *__restrict__ v, int64_t m) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < m) St<S>::st(v + c, typename St<S>::C(0));
+}
+
+}  // namespace np

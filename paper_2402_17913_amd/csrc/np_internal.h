@@ -1,0 +1,115 @@
+// Internal declarations shared by the translation units of libneuphys.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "neuphys.h"
+
+namespace np {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define NP_HIP_TRY(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::np::set_error("%s:%d: %s -> %s", __FILE__, __LINE__, #expr,                  \
+                            hipGetErrorString(e_));                                        \
+            return NP_EHIP;                                                                \
+        }                                                                                  \
+    } while (0)
+
+#define NP_TRY(expr)                                                                       \
+    do {                                                                                   \
+        np_status s_ = (expr);                                                             \
+        if (s_ != NP_OK) return s_;                                                        \
+    } while (0)
+
+// Checks the launch that was just enqueued.
+#define NP_LAUNCH_CHECK() NP_HIP_TRY(hipGetLastError())
+
+// --------------------------------------------------------- storage types
+// BF16 is kept as raw 16-bit patterns; conversions are written out here:
+// float -> bf16 rounds to nearest, ties to even; NaN stays NaN.
+struct bf16 {
+    uint16_t u;
+};
+
+__device__ __forceinline__ float bf16_to_float(uint16_t u) { return __uint_as_float(uint32_t(u) << 16); }
+
+__device__ __forceinline__ uint16_t float_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+// Storage traits: C is the arithmetic type for fields stored as S.
+template <class S> struct St;
+template <> struct St<double> {
+    typedef double C;
+    static __device__ __forceinline__ double ld(const double *p) { return *p; }
+    static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+};
+template <> struct St<float> {
+    typedef float C;
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+};
+template <> struct St<bf16> {
+    typedef float C;
+    static __device__ __forceinline__ float ld(const bf16 *p) { return bf16_to_float(p->u); }
+    static __device__ __forceinline__ void st(bf16 *p, float v) { p->u = float_to_bf16(v); }
+};
+
+inline size_t prec_bytes(np_prec p) { return p == NP_FP64 ? 8 : (p == NP_FP32 ? 4 : 2); }
+
+// ------------------------------------------------------------ reductions
+constexpr int kRedBlocks = 1024;  // fixed partial count: deterministic reduction order
+constexpr int kBlock = 256;
+
+// Sum over a 64-wide wavefront (xor butterfly), then over the waves of the block
+// through LDS; the result is valid in thread 0.  Fixed order: deterministic.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double wsum[kBlock / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wsum[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += wsum[i];
+    __syncthreads();
+    return s;
+}
+
+// -------------------------------------------------------------- profiling
+// Event bracketing of the finest-level smoothing launches (np_prof_*).
+bool prof_on();
+np_status prof_begin(hipStream_t s, void **tok);
+np_status prof_end(hipStream_t s, void *tok, double bytes);
+
+// ----------------------------------------------------------------- helpers
+inline bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+inline int ilog2(int64_t n) {
+    int l = 0;
+    while ((int64_t(1) << l) < n) ++l;
+    return l;
+}
+inline unsigned blocks_for(int64_t m, int per = kBlock) { return unsigned((m + per - 1) / per); }
+
+// Validates a grid for the multigrid entry points; returns log2(n) or -1.
+int check_grid(const np_dims &dims);
+
+// Workspace cache lifetime.
+void release_mg_cache();
+void release_ns_cache();
+
+}  // namespace np

@@ -57,13 +57,14 @@ def sine_rhs(d, n, seed=0, n_modes=8, kmax=8):
     rng = np.random.default_rng(seed)
     ks = rng.integers(1, kmax + 1, size=(n_modes, d))
     c = rng.uniform(-1.0, 1.0, size=n_modes)
-    X, h = _mesh(d, n)
+    x, h = cell_centres(n)
     f = np.zeros((n,) * d)
     modes = []
     for m in range(n_modes):
-        term = np.full((n,) * d, c[m])
-        for a in range(d):
-            term = term * np.sin(ks[m, a] * np.pi * X[a])
+        # separable product; array axis d-1-a carries coordinate a
+        term = np.array(c[m])
+        for a in reversed(range(d)):
+            term = np.multiply.outer(term, np.sin(ks[m, a] * np.pi * x))
         f += term
         modes.append((float(c[m]), tuple(int(v) for v in ks[m])))
     return dict(f=f, h=h, modes=modes)

@@ -1,0 +1,224 @@
+"""GPU parity of the multigrid path against the FP64 oracle (run on an MI355X).
+
+FP64 bar: relative difference max|gpu - oracle| / max|oracle| <= 1e-12 for the
+same number of cycles (operators alone: <= 1e-13).  Mixed precision and
+tolerance-stopped solves are judged by the oracle's own residual evaluator.
+"""
+import numpy as np
+import pytest
+
+from paper_2402_17913_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DIR, PER = 0, 1
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_17913_amd import binding
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+SHAPES = [(2, 4), (2, 8), (2, 64), (2, 256), (3, 4), (3, 8), (3, 32), (3, 64)]
+
+
+# ------------------------------------------------------------- single operators
+@pytest.mark.parametrize("d,n", SHAPES)
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_apply_and_jacobi(B, orc, d, n, bc):
+    say("apply/jacobi", d, n, bc)
+    rng = np.random.default_rng(100 + n * d + bc)
+    h = 1.0 / n
+    x, f = rng.standard_normal((n,) * d), rng.standard_normal((n,) * d)
+    y = dev(np.zeros_like(x))
+    B.np_op_apply(dev(x), y, h, bc)
+    assert rel(host(y), orc.apply_A(x, h, bc)) < 1e-13
+    xo = dev(np.zeros_like(x))
+    B.np_op_jacobi(dev(f), dev(x), xo, h, bc)
+    assert rel(host(xo), orc.jacobi(f, x, h, bc)) < 1e-13
+
+
+@pytest.mark.parametrize("d,n", [s for s in SHAPES if s[1] >= 8])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_restrict_and_prolong(B, orc, d, n, bc):
+    say("restrict/prolong", d, n, bc)
+    rng = np.random.default_rng(200 + n * d + bc)
+    h = 1.0 / n
+    x, f = rng.standard_normal((n,) * d), rng.standard_normal((n,) * d)
+    fc = dev(np.zeros((n // 2,) * d))
+    B.np_op_resid_restrict(dev(f), dev(x), fc, h, bc)
+    assert rel(host(fc), orc.restrict(orc.residual(f, x, h, bc))) < 1e-13
+    ec = rng.standard_normal((n // 2,) * d)
+    xg = dev(x)
+    B.np_op_prolong_add(dev(ec), xg, bc)
+    assert rel(host(xg), orc.prolong_add(ec, x, bc)) < 1e-14
+
+
+@pytest.mark.parametrize("d,n", [(2, 4), (2, 16), (2, 128), (3, 4), (3, 16), (3, 32)])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_one_vcycle(B, orc, d, n, bc):
+    say("vcycle", d, n, bc)
+    rng = np.random.default_rng(300 + n * d + bc)
+    h = 1.0 / n
+    x, f = rng.standard_normal((n,) * d), rng.standard_normal((n,) * d)
+    if bc == PER:
+        f -= f.mean()
+    xg = dev(x)
+    B.np_op_vcycle(dev(f), xg, h, bc)
+    assert rel(host(xg), orc.vcycle(f, x, h, bc)) < 1e-12
+
+
+def test_resid_norm(B, orc):
+    rng = np.random.default_rng(5)
+    x, f = rng.standard_normal((64, 64, 64)), rng.standard_normal((64, 64, 64))
+    got = B.np_op_resid_norm(dev(f), dev(x), 1 / 64, DIR)
+    ref = np.linalg.norm(orc.residual(f, x, 1 / 64, DIR))
+    assert abs(got - ref) / ref < 1e-13
+
+
+# ----------------------------------------------------------------- full solves
+def _parity_solve(B, orc, f, h, bc, tol=1e-10):
+    ref = orc.mg_solve(f, h, bc, tol=tol)
+    assert ref.status == 0
+    xg = dev(np.zeros_like(f))
+    st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, tol=tol, fixed_cycles=ref.cycles)
+    assert stats["cycles"] == ref.cycles
+    x = host(xg)
+    assert rel(x, ref.x) < 1e-12, rel(x, ref.x)
+    hist = np.array(stats["hist"])
+    # residual norms agree to rounding of ||A x|| (absolute, in units of ||f||)
+    assert np.max(np.abs(hist - ref.hist)) < 1e-13
+    # tolerance-stopped run: the oracle judges the residual
+    xg2 = dev(np.zeros_like(f))
+    st, stats2 = B.mg_poisson_solve(dev(f), xg2, h, bc, tol=tol)
+    assert abs(stats2["cycles"] - ref.cycles) <= 1
+    assert orc.rel_res(f - (f.mean() if bc == PER else 0.0), host(xg2), h, bc) <= tol
+    return x, stats
+
+
+def test_solve_config_2d_128_dirichlet(B, orc):
+    """128^2 unit square, zero Dirichlet, manufactured sin.sin + 8 modes source."""
+    say("solve C1 128^2")
+    g = inputs.manufactured_2d(128, seed=0)
+    x, stats = _parity_solve(B, orc, g["f"], g["h"], DIR)
+    assert stats["rel_res"] <= 1e-10
+
+
+@pytest.mark.parametrize("d,n,bc", [(2, 4, DIR), (2, 8, PER), (2, 64, PER), (2, 512, DIR),
+                                    (3, 4, DIR), (3, 8, DIR), (3, 16, PER), (3, 64, DIR)])
+def test_solve_shapes(B, orc, d, n, bc):
+    say("solve", d, n, bc)
+    h = 1.0 / n if bc == DIR else 2 * np.pi / n
+    f = inputs.sine_rhs(d, n, seed=n + d)["f"] if bc == DIR else \
+        np.random.default_rng(n + d).standard_normal((n,) * d)
+    _parity_solve(B, orc, f, h, bc)
+
+
+def test_zero_rhs_and_warm_start(B, orc):
+    import torch
+    n = 32
+    xg = dev(np.ones((n, n)))
+    st, stats = B.mg_poisson_solve(dev(np.zeros((n, n))), xg, 1 / n, DIR, warm_start=2)
+    assert stats["cycles"] == 0 and torch.all(xg == 0)
+    g = inputs.manufactured_2d(n, seed=1)
+    ref = orc.mg_solve(g["f"], g["h"], DIR)
+    xg = dev(ref.x)
+    st, stats = B.mg_poisson_solve(dev(g["f"]), xg, g["h"], DIR, warm_start=2)
+    assert stats["cycles"] == 0  # a converged guess needs no cycle
+    assert np.all(host(xg) == ref.x)
+
+
+def test_error_paths(B):
+    import torch
+    x = torch.zeros((12, 12), dtype=torch.float64, device="cuda")
+    x0 = x.clone()
+    with pytest.raises(B.NeuphysError) as e:
+        B.mg_poisson_solve(x.clone(), x, 1 / 12, DIR)
+    assert e.value.status == B.NP_EINVAL and torch.equal(x, x0)
+    f = torch.ones((16, 16), dtype=torch.float64, device="cuda")
+    f[3, 4] = float("nan")
+    xg = torch.zeros_like(f)
+    with pytest.raises(B.NeuphysError) as e:
+        B.mg_poisson_solve(f, xg, 1 / 16, DIR)
+    assert e.value.status == B.NP_ENAN
+    f = torch.ones((64, 64), dtype=torch.float64, device="cuda")
+    st, stats = B.mg_poisson_solve(f, torch.zeros_like(f), 1 / 64, DIR, max_cycles=1, check=False)
+    assert st == B.NP_ENOCONV and stats["cycles"] == 1
+    with pytest.raises(B.NeuphysError):
+        B.mg_poisson_solve(f, torch.zeros_like(f), -1.0, DIR)
+
+
+# ----------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("d,n,bc", [(2, 128, DIR), (3, 64, DIR), (2, 256, PER), (3, 32, PER)])
+def test_mixed_precision_reaches_tolerance(B, orc, prec, d, n, bc):
+    say("mixed", prec, d, n, bc)
+    h = 1.0 / n if bc == DIR else 2 * np.pi / n
+    f = inputs.sine_rhs(d, n, seed=7)["f"] if bc == DIR else \
+        np.random.default_rng(n).standard_normal((n,) * d)
+    ref = orc.mg_solve(f, h, bc, tol=1e-12)
+    xg = dev(np.zeros_like(f))
+    p = B.FP32 if prec == "fp32" else B.BF16
+    st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, tol=1e-10, smooth_prec=p)
+    x = host(xg)
+    fm = f - f.mean() if bc == PER else f
+    rr = orc.rel_res(fm, x, h, bc)
+    say("  outer", stats["outer_iters"], "cycles", stats["cycles"], "rel_res", rr,
+        "err vs fp64 oracle", rel(x, ref.x))
+    assert rr <= 1e-10
+    assert abs(rr - stats["rel_res"]) <= 1e-3 * rr
+
+
+# --------------------------------------------------------- full size, bench shape
+@pytest.mark.slow
+def test_full_size_3d_256(B, orc):
+    """256^3 Dirichlet with the benchmark's source: one V-cycle from zero is compared
+    element by element with the oracle; the converged FP64 and mixed solves are judged
+    by the oracle's residual and by the closed-form discrete solution's error bound."""
+    say("full size 256^3")
+    n = 256
+    g = inputs.sine_rhs(3, n, seed=0)
+    f, h = g["f"], g["h"]
+    xg = dev(np.zeros_like(f))
+    fg = dev(f)
+    B.np_op_vcycle(fg, xg, h, DIR)
+    ref1 = orc.vcycle(f, np.zeros_like(f), h, DIR)
+    assert rel(host(xg), ref1) < 1e-12
+    lam_min = (12 / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    for p in (B.FP64, B.FP32):
+        xg = dev(np.zeros_like(f))
+        st, stats = B.mg_poisson_solve(fg, xg, h, DIR, tol=1e-10, smooth_prec=p)
+        x = host(xg)
+        rr = orc.rel_res(f, x, h, DIR)
+        say("  prec", p, "cycles", stats["cycles"], "rel_res", rr)
+        assert rr <= 1e-10
+        x1 = np.sin(np.pi * (np.arange(n) + 0.5) * h)
+        uh = np.zeros_like(f)
+        for c, ks in g["modes"]:
+            lam = (4 / h ** 2) * sum(np.sin(k * np.pi * h / 2) ** 2 for k in ks)
+            term = np.array(c / lam)
+            for a in reversed(range(3)):
+                term = np.multiply.outer(term, np.sin(ks[a] * np.pi * (np.arange(n) + 0.5) * h))
+            uh += term
+        del x1
+        assert np.linalg.norm(x - uh) <= rr * np.linalg.norm(f) / lam_min * (1 + 1e-6) + \
+            1e-13 * np.linalg.norm(uh)
