@@ -28,24 +28,52 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_path(B, fg, xg, h, prec, steps, warmup, profile):
+def time_path(B, fg, xg, h, prec, steps, warmup):
+    """Wall time of `steps` solves (graph-replayed cycles, no per-kernel events)."""
     import torch
     for _ in range(warmup):
         B.mg_poisson_solve(fg, xg, h, B.BC_DIRICHLET0, tol=TOL, smooth_prec=prec)
     torch.cuda.synchronize()
-    if profile:
-        B.np_prof_enable(True)
     t0 = time.perf_counter()
     stats = None
     for _ in range(steps):
         _, stats = B.mg_poisson_solve(fg, xg, h, B.BC_DIRICHLET0, tol=TOL, smooth_prec=prec)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = None
-    if profile:
-        prof = B.np_prof_read()
-        B.np_prof_enable(False)
-    return dt, stats, prof
+    return time.perf_counter() - t0, stats
+
+
+def kernel_times(B, fg, xg, h, prec, steps):
+    """Per-kind duration of the finest-level kernels over `steps` solves, each launch
+    bracketed by HIP events on the stream it runs on (graph replay is off while timing)."""
+    import torch
+    out = {}
+    for name, mask in (("down", B.PROF_DOWN), ("down_zero", B.PROF_DOWN_ZERO), ("up", B.PROF_UP)):
+        B.np_prof_enable(mask)
+        for _ in range(steps):
+            B.mg_poisson_solve(fg, xg, h, B.BC_DIRICHLET0, tol=TOL, smooth_prec=prec)
+        torch.cuda.synchronize()
+        n, ms, by = B.np_prof_read()
+        B.np_prof_enable(0)
+        if n:
+            out[name] = dict(launches=n, avg_us=1e3 * ms / n, bytes_per_launch=by / n,
+                             gbs=(by / n) / (ms / n * 1e-3) / 1e9)
+    return out
+
+
+def copy_bandwidth(reps=5):
+    """Measured device copy rate (torch's copy kernel, 512 MiB read + 512 MiB write)."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return 2 * a.numel() * 8 / dt / 1e9
 
 
 def cpu_baseline(f, h, cycles_needed):
@@ -94,17 +122,24 @@ def main():
     fg = torch.from_numpy(f).cuda()
     xg = torch.zeros_like(fg)
     dofs = f.size
+    copy_gbs = copy_bandwidth()
+    log("device copy: %.0f GB/s" % copy_gbs)
     res = {}
     for name, prec in (("fp64", B.FP64), ("fp32", B.FP32), ("bf16", B.BF16)):
-        dt, stats, prof = time_path(B, fg, xg, h, prec, args.steps, args.warmup, profile=True)
+        dt, stats = time_path(B, fg, xg, h, prec, args.steps, args.warmup)
+        prof = kernel_times(B, fg, xg, h, prec, max(1, min(args.steps, 3)))
         res[name] = dict(seconds=dt, stats=stats, prof=prof, dofs_per_s=dofs * args.steps / dt)
+        log("  kernels: " + ", ".join("%s %.1f us %.0f GB/s" % (k, v["avg_us"], v["gbs"])
+                                      for k, v in prof.items()))
         log("%s: %.3f ms/solve, %d cycles, %d outer, rel_res %.3e, %.3e DOF/s" % (
             name, 1e3 * dt / args.steps, stats["cycles"], stats["outer_iters"], stats["rel_res"],
             res[name]["dofs_per_s"]))
 
     head = "fp32"
-    launches, ms, by = res[head]["prof"]
-    achieved = (by / launches) / (ms / launches * 1e-3) / 1e9 if launches else 0.0
+    kt = res[head]["prof"]
+    # dominant finest-level kernel of the headline path: largest total time
+    dom = max(kt, key=lambda k: kt[k]["launches"] * kt[k]["avg_us"])
+    achieved = kt[dom]["gbs"]
     line = {
         "metric": "DOFs/s to 1e-10 rel. residual (MG V-cycle), learned/mixed vs plain FP64",
         "value": res[head]["dofs_per_s"],
@@ -134,17 +169,19 @@ def main():
             "mixed_over_plain": res[head]["dofs_per_s"] / res["fp64"]["dofs_per_s"],
         },
         "roofline": {
-            "kernel": "finest-level smoothing (FP32 storage)",
+            "kernel": {"down": "fused 2 Jacobi sweeps + residual + restriction, level 0",
+                       "down_zero": "fused zero-guess sweeps + residual + restriction, level 0",
+                       "up": "fused prolongation + 2 Jacobi sweeps, level 0"}[dom] + " (FP32 storage)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "launches": launches,
-            "avg_us": 1e3 * ms / launches if launches else None,
-            "fp64_kernel_achieved": (lambda p: (p[2] / p[0]) / (p[1] / p[0] * 1e-3) / 1e9
-                                     if p[0] else None)(res["fp64"]["prof"]),
+            "avg_us": kt[dom]["avg_us"],
+            "bytes_per_launch": kt[dom]["bytes_per_launch"],
+            "copy_measured_gbs": copy_gbs,
+            "level0_kernels": {p: res[p]["prof"] for p in res},
         },
         "cpu_baseline": None,
     }

@@ -158,14 +158,28 @@ np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const double *f, co
                            double *out, void *stream);
 
 /* ---------------------------------------------------------------------- */
-/* Kernel timing for the benchmark: while enabled, the library brackets every
- * launch of the finest-level smoothing kernels with HIP events on the stream
- * it launches them on.  np_prof_read returns (host) the number of such
- * launches and the sum of their durations in milliseconds since the last
- * enable, plus the algorithmic bytes those launches move by the library's
- * byte model. */
-void np_prof_enable(int on);
+/* Kernel timing for the benchmark.  np_prof_enable(mask) starts bracketing
+ * every finest-level launch of the selected kinds with HIP events on the
+ * stream it is launched on (and disables graph replay meanwhile, so each
+ * launch is seen); mask bits: 1 fused smoothing + residual + restriction,
+ * 2 the same from a zero iterate, 4 fused prolongation + smoothing,
+ * 8 single Jacobi sweep; 0 stops.  np_prof_read returns (host) the number
+ * of bracketed launches since the last enable, the sum of their durations in
+ * milliseconds and the algorithmic bytes they move (each field read once,
+ * each output written once). */
+void np_prof_enable(int mask);
 np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
+
+/* Tuning knobs (process-wide; used by the autotuner): "fused" (0/1: fused
+ * level kernels for V(2,2)), "graphs" (0/1: replay cycles from HIP graphs),
+ * "fmin2"/"fmin3" (smallest level size handled by fused kernels), "bz2"/"bz3"
+ * (even number of planes per workgroup in fused kernels, 0 = automatic),
+ * "inner_fp32"/"inner_bf16" (default inner cycles per refinement step),
+ * "batch" (cycles enqueued before the first host read of the convergence
+ * state).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
+ * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */
+np_status np_set_tuning(const char *key, int value);
+int np_get_tuning(const char *key);
 
 #ifdef __cplusplus
 }

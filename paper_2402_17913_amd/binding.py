@@ -68,6 +68,8 @@ _SIGS = {
     "np_op_resid_norm": (_I, [NpDims, _D, _I, _P, _P, ctypes.POINTER(_D), _P]),
     "np_prof_enable": (None, [_I]),
     "np_prof_read": (_I, [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "np_set_tuning": (_I, [ctypes.c_char_p, _I]),
+    "np_get_tuning": (_I, [ctypes.c_char_p]),
 }
 
 
@@ -182,8 +184,19 @@ def np_op_resid_norm(f, x, h, bc):
     return out.value
 
 
-def np_prof_enable(on):
-    lib.np_prof_enable(1 if on else 0)
+PROF_DOWN, PROF_DOWN_ZERO, PROF_UP, PROF_JACOBI = 1, 2, 4, 8
+
+
+def np_prof_enable(mask):
+    lib.np_prof_enable(int(mask))
+
+
+def np_set_tuning(key, value):
+    _check("np_set_tuning", lib.np_set_tuning(key.encode(), int(value)))
+
+
+def np_get_tuning(key):
+    return lib.np_get_tuning(key.encode())
 
 
 def np_prof_read():

@@ -8,6 +8,8 @@
 #include <tuple>
 #include <vector>
 
+#include "mg_fused.h"
+#include "mg_level.h"
 #include "mg_kernels.h"
 #include "np_internal.h"
 
@@ -52,7 +54,7 @@ struct ProfRec {
     double bytes;
 };
 std::mutex g_prof_mu;
-bool g_prof = false;
+int g_prof = 0;
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_event_pool;
 
@@ -68,7 +70,7 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-bool prof_on() { return g_prof; }
+int prof_on() { return g_prof; }
 
 np_status prof_begin(hipStream_t s, void **tok) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -94,22 +96,65 @@ np_status prof_end(hipStream_t s, void *tok, double bytes) {
     return NP_OK;
 }
 
+// ----------------------------------------------------------------- tuning
+// Runtime knobs (np_set_tuning): kernel selection and launch shapes.  The
+// autotuner sets them; defaults are the measured best on gfx950.
+struct Tuning {
+    int fused = 0;        // fused (temporally blocked) level kernels for V(2,2)
+    int tail = 1;         // one-workgroup V-cycle below 16^3 / 64^2
+    int graphs = 1;       // replay cycles from captured HIP graphs
+    int fmin2 = 32;       // smallest 2D level handled by fused kernels
+    int fmin3 = 16;       // smallest 3D level handled by fused kernels
+    int bz2 = 0;          // rows per workgroup in 2D fused kernels (0 = automatic)
+    int bz3 = 0;          // planes per workgroup in 3D fused kernels (0 = automatic)
+    int inner_fp32 = 3;   // default inner cycles per refinement step
+    int inner_bf16 = 2;
+    int batch = 4;        // first batch of cycles enqueued before reading the controller
+};
+static Tuning g_tune;
+
 // -------------------------------------------------------------- hierarchy
 // Level l has n_l = n / 2^l cells per axis, l = 0..L with n_L = 4.  Level 0
 // of the plain FP64 path uses the caller's x and rhs; t[0] is its ping-pong
 // partner.  The mixed path keeps the correction e, the rounded residual and
 // the ping-pong buffer of level 0 in x[0], f[0], t[0].
+constexpr int kPartials = 65536;  // per-workgroup partial sums (fixed order)
+
+struct GraphKey {
+    int kind;  // 0: FP64 cycle, 1: mixed first step, 2: mixed step a->b, 3: mixed step b->a
+    int zero0, check;
+    const void *x, *f;
+    double h;
+    int nu1, nu2, inner;
+    double omega;
+    bool operator==(const GraphKey &o) const {
+        return kind == o.kind && zero0 == o.zero0 && check == o.check && x == o.x && f == o.f && h == o.h &&
+               nu1 == o.nu1 && nu2 == o.nu2 && inner == o.inner && omega == o.omega;
+    }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t used;
+};
+
 struct Hier {
     int dev = 0, d = 0, lg = 0, L = 0, bc = 0;
     np_prec prec = NP_FP64;
     size_t es = 8;
+    bool levels = false;      // level buffers allocated
     std::vector<void *> x, f, t;
     double *Minv = nullptr;
     double Minv_h = -1.0;     // level-0 spacing Minv was built for
-    double *red = nullptr;    // kRedBlocks partials followed by 8 scalar slots
+    double *red = nullptr;    // kPartials partials followed by 8 scalar slots
     double *hred = nullptr;   // pinned host mirror of the scalar slots
     double *f64 = nullptr;    // FP64 copy of the rhs (periodic mean removal)
     double *x64 = nullptr;    // second FP64 solution buffer (mixed path)
+    Ctl *ctl = nullptr;       // device controller
+    Ctl *hctl = nullptr;      // pinned host mirror
+    hipStream_t cap = nullptr;  // capture stream
+    std::vector<GraphEntry> graphs;
+    uint64_t tick = 0;
     std::mutex mu;            // one solve at a time per workspace
 };
 
@@ -129,7 +174,13 @@ np_status dmalloc(void **p, size_t bytes) {
     return NP_OK;
 }
 
+void drop_graphs(Hier *H) {
+    for (auto &g : H->graphs) (void)hipGraphExecDestroy(g.exec);
+    H->graphs.clear();
+}
+
 void free_hier(Hier *H) {
+    drop_graphs(H);
     for (auto *p : H->x) if (p) (void)hipFree(p);
     for (auto *p : H->f) if (p) (void)hipFree(p);
     for (auto *p : H->t) if (p) (void)hipFree(p);
@@ -138,33 +189,47 @@ void free_hier(Hier *H) {
     if (H->hred) (void)hipHostFree(H->hred);
     if (H->f64) (void)hipFree(H->f64);
     if (H->x64) (void)hipFree(H->x64);
+    if (H->ctl) (void)hipFree(H->ctl);
+    if (H->hctl) (void)hipHostFree(H->hctl);
+    if (H->cap) (void)hipStreamDestroy(H->cap);
     delete H;
 }
 
-np_status alloc_hier(Hier *H) {
+np_status alloc_base(Hier *H) {
+    NP_TRY(dmalloc((void **)&H->Minv, sizeof(double) * 64 * 64));
+    NP_TRY(dmalloc((void **)&H->red, sizeof(double) * (kPartials + 8)));
+    NP_TRY(dmalloc((void **)&H->ctl, sizeof(Ctl)));
+    if (hipHostMalloc((void **)&H->hred, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&H->hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipHostMalloc failed");
+        return NP_ENOMEM;
+    }
+    NP_HIP_TRY(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
+    return NP_OK;
+}
+}  // namespace
+
+// Allocates the level buffers on first use.
+static np_status ensure_levels(Hier *H) {
+    if (H->levels) return NP_OK;
     const int L = H->L;
     H->x.assign(L + 1, nullptr);
     H->f.assign(L + 1, nullptr);
     H->t.assign(L + 1, nullptr);
+    const bool own0 = H->prec != NP_FP64;  // plain FP64 uses the caller's x and rhs on level 0
     for (int l = 0; l <= L; ++l) {
         const size_t bytes = size_t(cells(H->d, H->lg - l)) * H->es;
-        const bool own0 = H->prec != NP_FP64;  // plain FP64 uses the caller's x, rhs on level 0
         if (l > 0 || own0) {
             NP_TRY(dmalloc(&H->x[l], bytes));
             NP_TRY(dmalloc(&H->f[l], bytes));
         }
         NP_TRY(dmalloc(&H->t[l], bytes));
     }
-    NP_TRY(dmalloc((void **)&H->Minv, sizeof(double) * 64 * 64));
-    NP_TRY(dmalloc((void **)&H->red, sizeof(double) * (kRedBlocks + 8)));
-    if (hipHostMalloc((void **)&H->hred, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess) {
-        set_error("hipHostMalloc failed");
-        return NP_ENOMEM;
-    }
     if (H->prec != NP_FP64) NP_TRY(dmalloc((void **)&H->x64, sizeof(double) * cells(H->d, H->lg)));
+    H->levels = true;
     return NP_OK;
 }
-}  // namespace
 
 static np_status get_hier(int d, int lg, int bc, np_prec prec, Hier **out) {
     int dev = 0;
@@ -184,7 +249,7 @@ static np_status get_hier(int d, int lg, int bc, np_prec prec, Hier **out) {
     H->bc = bc;
     H->prec = prec;
     H->es = prec_bytes(prec);
-    np_status st = alloc_hier(H);
+    np_status st = alloc_base(H);
     if (st != NP_OK) {
         free_hier(H);
         return st;
@@ -273,113 +338,341 @@ struct CycleOpts {
     double omega = 2.0 / 3.0;
 };
 
+// Fused tile shapes: 3D tiles are 64 (x) by 16 (y) columns including the halo;
+// 2D tiles are 256 columns wide.
+template <int D> struct Tile {
+    static constexpr int TX = D == 3 ? 64 : 256;
+    static constexpr int TY = D == 3 ? 16 : 1;
+};
+
 template <int D, class S> struct Ops {
     typedef typename St<S>::C C;
 
     static np_status jacobi(const S *f, const S *xin, S *xout, int lg, int bc, double h, double omega,
-                            bool zero, hipStream_t s, bool finest) {
+                            bool zero, hipStream_t s, bool finest, const int *stop) {
         const int64_t m = cells(D, lg);
         const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
         void *tok = nullptr;
-        const bool prof = finest && prof_on();
+        const bool prof = finest && (prof_on() & kProfJacobi);
         if (prof) NP_TRY(prof_begin(s, &tok));
         if (zero)
             hipLaunchKernelGGL((k_jacobi<D, S, true>), dim3(blocks_for(m)), dim3(kBlock), 0, s, f, xin,
-                               xout, lg, bc, inv_h2, wdiag);
+                               xout, lg, bc, inv_h2, wdiag, stop);
         else
             hipLaunchKernelGGL((k_jacobi<D, S, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, f, xin,
-                               xout, lg, bc, inv_h2, wdiag);
+                               xout, lg, bc, inv_h2, wdiag, stop);
         NP_LAUNCH_CHECK();
         if (prof) NP_TRY(prof_end(s, tok, double(m) * sizeof(S) * (zero ? 2 : 3)));
         return NP_OK;
     }
 
-    static np_status resid_restrict(const S *f, const S *x, S *fc, int lg, int bc, double h,
-                                    hipStream_t s) {
-        const int64_t mc = cells(D, lg - 1);
-        hipLaunchKernelGGL((k_resid_restrict<D, S>), dim3(blocks_for(mc)), dim3(kBlock), 0, s, f, x, fc,
-                           lg, bc, C(1.0 / (h * h)));
+    // Jacobi sweep used inside cycles; with partial != null it also reduces
+    // ||f - A x_in||^2 into one partial per workgroup (count in *np).
+    static np_status sweep(const S *f, const S *xin, S *xout, int lg, int bc, double h, double omega, bool zero,
+                           double *partial, int *np, hipStream_t s, bool finest, const int *stop) {
+        const int64_t m = cells(D, lg);
+        const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+        unsigned nb = unsigned((m + kSweepCells - 1) / kSweepCells);
+        if (partial) nb = std::min<unsigned>(nb, kPartials);
+        void *tok = nullptr;
+        const bool prof = finest && (prof_on() & kProfJacobi);
+        if (prof) NP_TRY(prof_begin(s, &tok));
+        if (zero)
+            hipLaunchKernelGGL((k_sweep<D, S, true, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial, lg,
+                               bc, inv_h2, wdiag, stop);
+        else if (partial)
+            hipLaunchKernelGGL((k_sweep<D, S, false, true>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial,
+                               lg, bc, inv_h2, wdiag, stop);
+        else
+            hipLaunchKernelGGL((k_sweep<D, S, false, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial,
+                               lg, bc, inv_h2, wdiag, stop);
+        NP_LAUNCH_CHECK();
+        if (prof) NP_TRY(prof_end(s, tok, double(m) * sizeof(S) * (zero ? 2 : 3)));
+        if (np) *np = int(nb);
+        return NP_OK;
+    }
+
+    // Residual + restriction inside cycles (block kernel where the level is wide enough).
+    static np_status restrict_(const S *f, const S *x, S *fc, int lg, int bc, double h, hipStream_t s,
+                               const int *stop) {
+        const int n = 1 << lg;
+        if (n >= RBlk<D>::FX) {
+            const int64_t nb = int64_t(n / RBlk<D>::FX) * (n / 2) * (D == 3 ? n / 2 : 1);
+            hipLaunchKernelGGL((k_restrict<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, f, x, fc, lg, bc,
+                               C(1.0 / (h * h)), stop);
+            NP_LAUNCH_CHECK();
+            return NP_OK;
+        }
+        return resid_restrict(f, x, fc, lg, bc, h, s, stop);
+    }
+
+    static np_status tail(const S *f, S *x, const double *Minv, int lg, int bc, double h, const CycleOpts &o,
+                          hipStream_t s, const int *stop) {
+        hipLaunchKernelGGL((k_tail<D, S>), dim3(1), dim3(Tail<D>::NT), 0, s, f, x, Minv, lg, bc, h, o.omega, o.nu1,
+                           o.nu2, stop);
         NP_LAUNCH_CHECK();
         return NP_OK;
     }
 
-    static np_status prolong_add(const S *ec, S *x, int lgc, int bc, hipStream_t s) {
+    static np_status resid_restrict(const S *f, const S *x, S *fc, int lg, int bc, double h, hipStream_t s,
+                                    const int *stop) {
+        const int64_t mc = cells(D, lg - 1);
+        hipLaunchKernelGGL((k_resid_restrict<D, S>), dim3(blocks_for(mc)), dim3(kBlock), 0, s, f, x, fc,
+                           lg, bc, C(1.0 / (h * h)), stop);
+        NP_LAUNCH_CHECK();
+        return NP_OK;
+    }
+
+    static np_status prolong_add(const S *ec, S *x, int lgc, int bc, hipStream_t s, const int *stop) {
         const int64_t m = cells(D, lgc + 1);
-        hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc);
+        hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc,
+                           stop);
         NP_LAUNCH_CHECK();
         return NP_OK;
     }
 
     static np_status coarse(const S *f, S *x, const double *Minv, int bc, double hc, bool zero,
-                            hipStream_t s) {
+                            hipStream_t s, const int *stop) {
         hipLaunchKernelGGL((k_coarse<D, S>), dim3(1), dim3(64), 0, s, f, x, Minv, bc, 1.0 / (hc * hc),
-                           zero ? 1 : 0);
+                           zero ? 1 : 0, stop);
         NP_LAUNCH_CHECK();
         return NP_OK;
     }
 
-    // red[kRedBlocks + slot] = ||f - A x||_2 (device).
-    static np_status resid_norm(const S *f, const S *x, int lg, int bc, double h, double *red, int slot,
-                                hipStream_t s) {
+    // Partials of ||f - A x||^2 (one per workgroup, <= kRedBlocks) into red.
+    static np_status resid_sq(const S *f, const S *x, int lg, int bc, double h, double *red, hipStream_t s,
+                              const int *stop, int *np) {
         const int64_t m = cells(D, lg);
         const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m));
+        (void)stop;
         hipLaunchKernelGGL((k_resid_sq<D, S>), dim3(nb), dim3(kBlock), 0, s, f, x, red, lg, bc,
                            C(1.0 / (h * h)));
         NP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, red, int(nb), red + kRedBlocks + slot, 1);
-        NP_LAUNCH_CHECK();
+        *np = int(nb);
         return NP_OK;
     }
 
-    // One V(nu1, nu2) cycle on the hierarchy.  Level 0 works on (x0, f0) with
-    // t0 as ping-pong partner; zero0 means x0 is known to be zero on entry.
-    // On return the level-0 iterate is in x0.
-    static np_status vcycle(Hier *H, S *x0, const S *f0, S *t0, bool zero0, double h, const CycleOpts &o,
-                            hipStream_t s) {
+    // One fused pass over a level (see mg_fused.h).  Returns the number of
+    // workgroups (= partial sums written when NORM).
+    template <int NJ, int PRE, bool RES, bool NORM>
+    static np_status fused(const S *xin, const S *f, S *xout, const S *ec, S *fc, double *partial, int lg, int bc,
+                           double h, double omega, hipStream_t s, const int *stop, bool finest, int *nblk) {
+        constexpr int TX = Tile<D>::TX, TY = Tile<D>::TY;
+        constexpr int H = NJ + (RES ? 1 : 0);
+        constexpr int BX = TX - 2 * H, BY = D == 3 ? TY - 2 * H : 1;
+        const int n = 1 << lg;
+        FusedArgs<S> a;
+        a.xin = xin; a.f = f; a.xout = xout; a.ec = ec; a.fc = fc; a.partial = partial; a.stop = stop;
+        a.lg = lg; a.bc = bc;
+        a.tiles_x = (n + BX - 1) / BX;
+        a.tiles_y = D == 3 ? (n + BY - 1) / BY : 1;
+        const int tiles = a.tiles_x * a.tiles_y;
+        int bz = D == 3 ? g_tune.bz3 : g_tune.bz2;
+        if (bz <= 0) {
+            // enough workgroups to fill the chip, without making the marching halo dominant
+            bz = n;
+            while (bz > 8 && int64_t(tiles) * (n / bz) < 1024) bz >>= 1;
+        }
+        if (bz > n) bz = n;
+        if (bz < 2) bz = 2;
+        a.bz = bz;
+        a.nblocks = tiles * (n / bz);
+        if (NORM && a.nblocks > kPartials) {
+            set_error("fused launch needs %d partials (max %d)", a.nblocks, kPartials);
+            return NP_EINVAL;
+        }
+        a.inv_h2 = C(1.0 / (h * h));
+        a.wdiag = C(omega * h * h / (2.0 * D));
+        void *tok = nullptr;
+        const int kind = PRE == PRE_PROLONG ? kProfUp : (PRE == PRE_ZERO ? kProfDownZero : kProfDown);
+        const bool prof = finest && (prof_on() & kind);
+        if (prof) NP_TRY(prof_begin(s, &tok));
+        hipLaunchKernelGGL((k_fused<D, S, TX, TY, NJ, PRE, RES, NORM>), dim3(a.nblocks), dim3(256), 0, s, a);
+        NP_LAUNCH_CHECK();
+        if (prof) {
+            // algorithmic bytes: stage-0 input (x unless zero guess, f), output x, coarse in/out
+            const double m = double(cells(D, lg)), es = double(sizeof(S));
+            double by = m * es;                                   // f
+            if (PRE != PRE_ZERO) by += m * es;                    // x in
+            if (NJ > 0) by += m * es;                             // x out
+            if (PRE == PRE_PROLONG) by += m * es / (1 << D);      // coarse error
+            if (RES) by += m * es / (1 << D);                     // restricted residual
+            NP_TRY(prof_end(s, tok, by));
+        }
+        if (nblk) *nblk = a.nblocks;
+        return NP_OK;
+    }
+
+    // Enqueues one V(nu1, nu2) cycle on the hierarchy.  Level 0 works on
+    // (x0, f0) with t0 as partner; zero0: x0 is zero on entry (it is not
+    // read); check: the residual norm of x0 is reduced and the controller's
+    // stop rule runs before the rest of the cycle.  The level-0 result is in x0.
+    static np_status cycle(Hier *H, S *x0, const S *f0, S *t0, bool zero0, bool check, double h,
+                           const CycleOpts &o, hipStream_t s) {
         const int L = H->L, bc = H->bc;
-        std::vector<S *> cur(L + 1), oth(L + 1);
+        const int *stop = &H->ctl->stop;
+        const bool fz = g_tune.fused && o.nu1 == 2 && o.nu2 == 2;
+        const int fmin = D == 3 ? g_tune.fmin3 : g_tune.fmin2;
+        std::vector<S *> cur(L + 1), oth(L + 1), res(L + 1);
         std::vector<const S *> F(L + 1);
+        std::vector<bool> fl(L + 1);
         for (int l = 0; l <= L; ++l) {
             cur[l] = l == 0 ? x0 : (S *)H->x[l];
             oth[l] = l == 0 ? t0 : (S *)H->t[l];
             F[l] = l == 0 ? f0 : (const S *)H->f[l];
+            fl[l] = fz && l < L && (1 << (H->lg - l)) >= fmin;
         }
+        int tl = 0;  // level handed to the one-workgroup tail (0 = none)
+        if (g_tune.tail && o.nu1 >= 1)
+            for (int l = 1; l <= L; ++l)
+                if (H->lg - l <= Tail<D>::LG && H->lg - l > 2 && !fl[l]) { tl = l; break; }
         double hl = h;
+        // ------------------------------------------------------------ down
         for (int l = 0; l < L; ++l, hl *= 2.0) {
             const int lg = H->lg - l;
-            bool zero = l > 0 || zero0;
-            if (zero && o.nu1 == 0) {
+            const bool zero = l > 0 || zero0;
+            S *fc = (S *)H->f[l + 1];
+            if (fl[l]) {
+                int nb = 0;
+                if (zero) {
+                    NP_TRY((fused<1, PRE_ZERO, true, false>(nullptr, F[l], oth[l], nullptr, fc, nullptr, lg, bc, hl,
+                                                            o.omega, s, stop, l == 0, &nb)));
+                } else if (check && l == 0) {
+                    NP_TRY((fused<2, PRE_NONE, true, true>(cur[l], F[l], oth[l], nullptr, fc, H->red, lg, bc, hl,
+                                                           o.omega, s, stop, true, &nb)));
+                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+                    NP_LAUNCH_CHECK();
+                } else {
+                    NP_TRY((fused<2, PRE_NONE, true, false>(cur[l], F[l], oth[l], nullptr, fc, nullptr, lg, bc, hl,
+                                                            o.omega, s, stop, l == 0, &nb)));
+                }
+                std::swap(cur[l], oth[l]);  // the smoothed iterate is in the partner buffer
+                continue;
+            }
+            bool zf = zero;
+            if (zf && o.nu1 == 0) {
                 hipLaunchKernelGGL((k_zero<S>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, cur[l],
-                                   cells(D, lg));
+                                   cells(D, lg), stop);
                 NP_LAUNCH_CHECK();
-                zero = false;
+                zf = false;
+            }
+            if (check && l == 0 && !zero && o.nu1 == 0) {
+                int nb = 0;
+                NP_TRY(resid_sq(F[0], cur[0], lg, bc, hl, H->red, s, stop, &nb));
+                hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+                NP_LAUNCH_CHECK();
             }
             for (int it = 0; it < o.nu1; ++it) {
-                NP_TRY(jacobi(F[l], cur[l], oth[l], lg, bc, hl, o.omega, zero && it == 0, s, l == 0));
+                const bool ck = check && l == 0 && !zero && it == 0;  // residual of the input iterate
+                int nb = 0;
+                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, zf && it == 0, ck ? H->red : nullptr, &nb, s,
+                             l == 0, stop));
+                if (ck) {
+                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+                    NP_LAUNCH_CHECK();
+                }
                 std::swap(cur[l], oth[l]);
             }
-            NP_TRY(resid_restrict(F[l], cur[l], (S *)H->f[l + 1], lg, bc, hl, s));
+            NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
+            if (l + 1 == tl) { hl *= 2.0; break; }
         }
-        // coarsest level: exact solve (zero guess unless the whole grid is 4^d)
-        NP_TRY(coarse(F[L], cur[L], H->Minv, bc, hl, L > 0 || zero0, s));
-        for (int l = L - 1; l >= 0; --l) {
+        if (tl > 0) {
+            // levels tl .. L in one workgroup; hl is the spacing of level tl
+            hl = h * double(int64_t(1) << tl);
+            NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop));
+            res[tl] = cur[tl];
+        } else {
+            // coarsest level: exact solve (zero guess unless the whole grid is 4^d)
+            if (L == 0 && check && !zero0) {
+                int nb = 0;
+                NP_TRY(resid_sq(F[0], cur[0], H->lg, bc, hl, H->red, s, stop, &nb));
+                hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+                NP_LAUNCH_CHECK();
+            }
+            NP_TRY(coarse(F[L], cur[L], H->Minv, bc, hl, L > 0 || zero0, s, stop));
+            res[L] = cur[L];
+        }
+        // -------------------------------------------------------------- up
+        for (int l = (tl > 0 ? tl : L) - 1; l >= 0; --l) {
             hl *= 0.5;
             const int lg = H->lg - l;
-            NP_TRY(prolong_add(cur[l + 1], cur[l], lg - 1, bc, s));
+            if (fl[l]) {
+                // pre-smoothed iterate in cur[l]; result into the other buffer
+                NP_TRY((fused<2, PRE_PROLONG, false, false>(cur[l], F[l], oth[l], res[l + 1], nullptr, nullptr, lg,
+                                                            bc, hl, o.omega, s, stop, l == 0, nullptr)));
+                std::swap(cur[l], oth[l]);
+                res[l] = cur[l];
+                continue;
+            }
+            NP_TRY(prolong_add(res[l + 1], cur[l], lg - 1, bc, s, stop));
             for (int it = 0; it < o.nu2; ++it) {
-                NP_TRY(jacobi(F[l], cur[l], oth[l], lg, bc, hl, o.omega, false, s, l == 0));
+                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, false, nullptr, nullptr, s, l == 0, stop));
                 std::swap(cur[l], oth[l]);
             }
+            res[l] = cur[l];
         }
-        if (cur[0] != x0)
-            NP_HIP_TRY(hipMemcpyAsync(x0, cur[0], sizeof(S) * cells(D, H->lg), hipMemcpyDeviceToDevice, s));
+        if (res[0] != x0) {
+            hipLaunchKernelGGL((k_copy<S>), dim3(blocks_for(cells(D, H->lg))), dim3(kBlock), 0, s, res[0], x0,
+                               cells(D, H->lg), stop);
+            NP_LAUNCH_CHECK();
+        }
         return NP_OK;
     }
 };
 
+// --------------------------------------------------------- graph replay
+// Captures `enqueue` into a graph on the hierarchy's capture stream (cached by
+// key) and launches it on s; without graphs, enqueues directly on s.
+template <class F>
+static np_status run_graph(Hier *H, const GraphKey &key, hipStream_t s, F enqueue) {
+    // timed runs bracket individual launches with events: no graphs then
+    if (!g_tune.graphs || prof_on()) return enqueue(s);
+    for (auto &g : H->graphs)
+        if (g.key == key) {
+            g.used = ++H->tick;
+            NP_HIP_TRY(hipGraphLaunch(g.exec, s));
+            return NP_OK;
+        }
+    NP_HIP_TRY(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
+    np_status st = enqueue(H->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(H->cap, &graph);
+    if (st != NP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return NP_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        set_error("graph instantiation failed: %s", hipGetErrorString(e));
+        return NP_EHIP;
+    }
+    if (H->graphs.size() >= 12) {  // evict the least recently used
+        size_t v = 0;
+        for (size_t i = 1; i < H->graphs.size(); ++i)
+            if (H->graphs[i].used < H->graphs[v].used) v = i;
+        (void)hipGraphExecDestroy(H->graphs[v].exec);
+        H->graphs.erase(H->graphs.begin() + v);
+    }
+    H->graphs.push_back(GraphEntry{key, exec, ++H->tick});
+    NP_HIP_TRY(hipGraphLaunch(exec, s));
+    return NP_OK;
+}
+
 // --------------------------------------------------------- solve helpers
 static np_status read_scalars(Hier *H, int count, hipStream_t s) {
-    NP_HIP_TRY(hipMemcpyAsync(H->hred, H->red + kRedBlocks, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+    NP_HIP_TRY(hipMemcpyAsync(H->hred, H->red + kPartials, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return NP_OK;
+}
+
+static np_status read_ctl(Hier *H, hipStream_t s) {
+    NP_HIP_TRY(hipMemcpyAsync(H->hctl, H->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }
@@ -389,7 +682,7 @@ static np_status dsum(Hier *H, const double *v, int64_t m, int square, int slot,
     const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m));
     hipLaunchKernelGGL((k_sum<double>), dim3(nb), dim3(kBlock), 0, s, v, m, square, H->red);
     NP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->red + kRedBlocks + slot,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->red + kPartials + slot,
                        square);
     NP_LAUNCH_CHECK();
     return NP_OK;
@@ -397,7 +690,7 @@ static np_status dsum(Hier *H, const double *v, int64_t m, int square, int slot,
 
 static np_status remove_mean(Hier *H, double *v, int64_t m, hipStream_t s) {
     NP_TRY(dsum(H, v, m, 0, 7, s));
-    hipLaunchKernelGGL(k_sub_scaled, dim3(blocks_for(m)), dim3(kBlock), 0, s, v, m, H->red + kRedBlocks + 7,
+    hipLaunchKernelGGL(k_sub_scaled, dim3(blocks_for(m)), dim3(kBlock), 0, s, v, m, H->red + kPartials + 7,
                        1.0 / double(m));
     NP_LAUNCH_CHECK();
     return NP_OK;
@@ -411,118 +704,159 @@ static void fill_opts(const np_mg_opts *opts, CycleOpts &co, np_mg_opts &o) {
     co.omega = o.omega;
 }
 
-struct Track {
-    np_mg_stats *st;
-    int n = 0;
-    double first = 0.0;
-    void push(double rr) {
-        if (n == 0) first = rr;
-        if (st && n < 256) st->hist[n] = rr;
-        ++n;
-    }
-};
+// Initialises the device controller (k done, history entry 0 if known).
+static np_status init_ctl(Hier *H, const np_mg_opts &o, double nf, double tol, int k0, double h0, hipStream_t s) {
+    Ctl *c = H->hctl;
+    std::memset(c, 0, sizeof(Ctl));
+    c->stop = kRunning;
+    c->k = k0;
+    c->fixed = o.fixed_cycles;
+    c->maxc = o.max_cycles;
+    c->nf = nf;
+    c->tol = tol;
+    c->nhist = k0;
+    if (k0 > 0) c->hist[0] = h0;
+    NP_HIP_TRY(hipMemcpyAsync(H->ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return NP_OK;
+}
 
-static void finish_stats(np_mg_stats *st, const Track &tr, int cycles, int outer, double rr) {
+// Host-side stop rule for the iterate known before any cycle (rr = 1 for a zero
+// guess); returns true when no cycle may run.
+static bool stop_before_first(const np_mg_opts &o, double tol, np_status *st) {
+    *st = NP_OK;
+    if (o.fixed_cycles > 0) return false;
+    if (1.0 <= tol) return true;
+    if (o.max_cycles <= 0) {
+        set_error("tolerance %.3g not reached in 0 cycles", tol);
+        *st = NP_ENOCONV;
+        return true;
+    }
+    return false;
+}
+
+static np_status status_of(const Ctl &c, double tol) {
+    switch (c.stop) {
+    case kConverged:
+    case kFixedDone: return NP_OK;
+    case kNonFinite: set_error("non-finite residual norm after %d cycles", c.k); return NP_ENAN;
+    case kDiverged: set_error("residual grew in three consecutive cycles (cycle %d)", c.k); return NP_ENOCONV;
+    default:
+        set_error("tolerance %.3g not reached in %d cycles (rel_res %.3g)", tol, c.k,
+                  c.nhist > 0 ? c.hist[c.nhist - 1] : -1.0);
+        return NP_ENOCONV;
+    }
+}
+
+static void fill_stats(np_mg_stats *st, const Ctl &c, int cycles, int outer) {
     if (!st) return;
     st->cycles = cycles;
     st->outer_iters = outer;
-    st->rel_res = rr;
-    const int steps = tr.n - 1;
-    st->rho_est = (steps > 0 && tr.first > 0.0 && rr > 0.0) ? std::pow(rr / tr.first, 1.0 / steps) : 0.0;
+    const int n = c.nhist;
+    for (int i = 0; i < n && i < 256; ++i) st->hist[i] = c.hist[i];
+    st->rel_res = n > 0 ? c.hist[n - 1] : 0.0;
+    st->rho_est = (n > 1 && c.hist[0] > 0.0 && c.hist[n - 1] > 0.0)
+                      ? std::pow(c.hist[n - 1] / c.hist[0], 1.0 / (n - 1)) : 0.0;
 }
 
-// Decides whether to stop after seeing rr with k cycles done.  Returns 1 to
-// stop (status in *st), 0 to continue.
-static int stop_rule(const np_mg_opts &o, double tol, double rr, int k, const Track &tr, double prev[3],
-                     np_status *st) {
-    if (!std::isfinite(rr)) {
-        set_error("non-finite residual norm after %d cycles", k);
-        *st = NP_ENAN;
-        return 1;
-    }
-    if (o.fixed_cycles > 0) {
-        if (k >= o.fixed_cycles) { *st = NP_OK; return 1; }
-        return 0;
-    }
-    if (rr <= tol) { *st = NP_OK; return 1; }
-    if (k >= o.max_cycles) {
-        set_error("tolerance %.3g not reached in %d cycles (rel_res %.3g)", tol, k, rr);
-        *st = NP_ENOCONV;
-        return 1;
-    }
-    // divergence guard: the residual grew in three consecutive cycles
-    if (tr.n >= 4 && prev[0] < prev[1] && prev[1] < prev[2] && prev[2] < rr) {
-        set_error("residual grew in three consecutive cycles (rel_res %.3g)", rr);
-        *st = NP_ENOCONV;
-        return 1;
-    }
-    return 0;
+// How many more cycles to enqueue before reading the controller again.
+static int next_batch(const Ctl &c, const np_mg_opts &o) {
+    if (o.fixed_cycles > 0) return std::max(1, o.fixed_cycles - c.k + 1);
+    const int n = c.nhist;
+    if (n < 2 || !(c.hist[n - 1] > 0.0) || !(c.hist[n - 2] > 0.0)) return g_tune.batch;
+    double rho = c.hist[n - 1] / c.hist[n - 2];
+    rho = std::min(0.95, std::max(0.02, rho));
+    const double need = std::log(c.tol / c.hist[n - 1]) / std::log(rho);
+    int b = int(std::ceil(need)) + 1;
+    return std::max(1, std::min(b, 32));
 }
 
 template <int D>
 static np_status solve_fp64(Hier *H, const double *f, double *x, double h, double tol, const np_mg_opts &o,
                             const CycleOpts &co, hipStream_t s, bool x_zero, double nf, np_mg_stats *stats) {
     typedef Ops<D, double> O;
-    Track tr{stats};
-    double prev[3] = {0, 0, 0};
-    int k = 0;
-    np_status st = NP_OK;
-    double rr = 1.0;
-    for (;;) {
-        if (!(k == 0 && x_zero)) {
-            NP_TRY(O::resid_norm(f, x, H->lg, H->bc, h, H->red, 0, s));
-            NP_TRY(read_scalars(H, 1, s));
-            rr = H->hred[0] / nf;
-        } else {
-            rr = 1.0;  // r = f exactly for a zero iterate
-        }
-        tr.push(rr);
-        if (stop_rule(o, tol, rr, k, tr, prev, &st)) break;
-        prev[0] = prev[1]; prev[1] = prev[2]; prev[2] = rr;
-        NP_TRY(O::vcycle(H, x, f, (double *)H->t[0], k == 0 && x_zero, h, co, s));
-        ++k;
+    NP_TRY(ensure_levels(H));
+    double *t0 = (double *)H->t[0];
+    np_status st0;
+    if (x_zero && stop_before_first(o, tol, &st0)) {
+        Ctl c{};
+        c.nhist = 1;
+        c.hist[0] = 1.0;
+        fill_stats(stats, c, 0, 0);
+        return st0;
     }
-    finish_stats(stats, tr, k, k, rr);
-    return st;
+    NP_TRY(init_ctl(H, o, nf, tol, x_zero ? 1 : 0, 1.0, s));
+    if (x_zero) {
+        GraphKey k0{0, 1, 0, x, f, h, co.nu1, co.nu2, 0, co.omega};
+        NP_TRY(run_graph(H, k0, s, [&](hipStream_t q) { return O::cycle(H, x, f, t0, true, false, h, co, q); }));
+    }
+    GraphKey key{0, 0, 1, x, f, h, co.nu1, co.nu2, 0, co.omega};
+    int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
+    for (;;) {
+        for (int b = 0; b < batch; ++b)
+            NP_TRY(run_graph(H, key, s, [&](hipStream_t q) { return O::cycle(H, x, f, t0, false, true, h, co, q); }));
+        NP_TRY(read_ctl(H, s));
+        if (H->hctl->stop) break;
+        batch = next_batch(*H->hctl, o);
+    }
+    const Ctl c = *H->hctl;
+    fill_stats(stats, c, c.k, c.k);
+    return status_of(c, tol);
 }
 
 template <int D, class SL>
 static np_status solve_mixed(Hier *H, const double *f, double *x, double h, double tol, const np_mg_opts &o,
-                             const CycleOpts &co, hipStream_t s, double nf, np_mg_stats *stats) {
+                             const CycleOpts &co, hipStream_t s, double nf, bool warm, np_mg_stats *stats) {
     typedef Ops<D, SL> O;
+    NP_TRY(ensure_levels(H));
     const int64_t m = cells(D, H->lg);
-    const int inner = o.inner_cycles > 0 ? o.inner_cycles : (H->prec == NP_BF16 ? 2 : 3);
+    const int inner = o.inner_cycles > 0 ? o.inner_cycles
+                                         : (H->prec == NP_BF16 ? g_tune.inner_bf16 : g_tune.inner_fp32);
     SL *e = (SL *)H->x[0], *rlo = (SL *)H->f[0], *tt = (SL *)H->t[0];
     double *xa = x, *xb = H->x64;
-    Track tr{stats};
-    double prev[3] = {0, 0, 0};
-    int k = 0, cycles = 0;
-    np_status st = NP_OK;
-    double rr = 1.0;
-    const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m));
-    for (;;) {
-        // x <- x + e (from the second step on), r = f - A x, r_lo = round(r), ||r||
-        hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, s, xa, e, xb, f, rlo, H->red,
-                           H->lg, H->bc, 1.0 / (h * h), k > 0 ? 1 : 0);
-        NP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->red + kRedBlocks, 1);
-        NP_LAUNCH_CHECK();
-        if (k > 0) std::swap(xa, xb);
-        NP_TRY(read_scalars(H, 1, s));
-        rr = H->hred[0] / nf;
-        tr.push(rr);
-        if (stop_rule(o, tol, rr, k, tr, prev, &st)) break;
-        prev[0] = prev[1]; prev[1] = prev[2]; prev[2] = rr;
-        // inner V-cycles on A e = r_lo from e = 0
-        for (int c = 0; c < inner; ++c) {
-            NP_TRY(O::vcycle(H, e, rlo, tt, c == 0, h, co, s));
-            ++cycles;
-        }
-        ++k;
+    np_status st0;
+    if (!warm && stop_before_first(o, tol, &st0)) {
+        Ctl c{};
+        c.nhist = 1;
+        c.hist[0] = 1.0;
+        fill_stats(stats, c, 0, 0);
+        return st0;
     }
-    if (xa != x) NP_HIP_TRY(hipMemcpyAsync(x, xa, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
-    finish_stats(stats, tr, cycles, k, rr);
-    return st;
+    NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
+    const unsigned nb = unsigned(std::min<int64_t>((m + kIrCells - 1) / kIrCells, kPartials));
+    const int *stop = &H->ctl->stop;
+    // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles
+    auto step = [&](hipStream_t q, const double *xin, double *xout, int has_e) -> np_status {
+        hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, q, xin, e, xout, f, rlo, H->red, H->lg,
+                           H->bc, 1.0 / (h * h), has_e, stop);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, q, H->red, int(nb), H->ctl);
+        NP_LAUNCH_CHECK();
+        for (int c = 0; c < inner; ++c) NP_TRY(O::cycle(H, e, rlo, tt, c == 0, false, h, co, q));
+        return NP_OK;
+    };
+    GraphKey k1{1, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    GraphKey ka{2, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    GraphKey kb{3, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    NP_TRY(run_graph(H, k1, s, [&](hipStream_t q) { return step(q, xa, nullptr, 0); }));
+    int launched = 1;
+    int batch = o.fixed_cycles > 0 ? o.fixed_cycles : std::max(1, g_tune.batch / 2);
+    for (;;) {
+        for (int b = 0; b < batch; ++b, ++launched) {
+            if (launched & 1)
+                NP_TRY(run_graph(H, ka, s, [&](hipStream_t q) { return step(q, xa, xb, 1); }));
+            else
+                NP_TRY(run_graph(H, kb, s, [&](hipStream_t q) { return step(q, xb, xa, 1); }));
+        }
+        NP_TRY(read_ctl(H, s));
+        if (H->hctl->stop) break;
+        batch = next_batch(*H->hctl, o);
+    }
+    const Ctl c = *H->hctl;
+    // the iterate whose residual was checked last: x_a after an even number of updates
+    if (c.k & 1) NP_HIP_TRY(hipMemcpyAsync(x, xb, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    fill_stats(stats, c, c.k * inner, c.k);
+    return status_of(c, tol);
 }
 
 }  // namespace np
@@ -551,14 +885,14 @@ extern "C" void np_release_all(void) {
     release_ns_cache();
 }
 
-extern "C" void np_prof_enable(int on) {
+extern "C" void np_prof_enable(int mask) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &r : g_prof_recs) {
         g_event_pool.push_back(r.a);
         g_event_pool.push_back(r.b);
     }
     g_prof_recs.clear();
-    g_prof = on != 0;
+    g_prof = mask;
 }
 
 extern "C" np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes) {
@@ -577,6 +911,51 @@ extern "C" np_status np_prof_read(int64_t *launches, double *total_ms, double *b
     return NP_OK;
 }
 
+extern "C" np_status np_set_tuning(const char *key, int value) {
+    clear_error();
+    if (!key) { set_error("null key"); return NP_EINVAL; }
+    struct { const char *k; int *v; int lo, hi; } tab[] = {
+        {"fused", &g_tune.fused, 0, 1},         {"graphs", &g_tune.graphs, 0, 1},
+        {"tail", &g_tune.tail, 0, 1},
+        {"fmin2", &g_tune.fmin2, 4, 1 << 14},   {"fmin3", &g_tune.fmin3, 4, 1 << 12},
+        {"bz2", &g_tune.bz2, 0, 1 << 14},       {"bz3", &g_tune.bz3, 0, 1 << 12},
+        {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
+        {"batch", &g_tune.batch, 1, 64},
+    };
+    for (auto &e : tab)
+        if (std::strcmp(e.k, key) == 0) {
+            if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1))) {
+                set_error("value %d out of range for %s", value, key);
+                return NP_EINVAL;
+            }
+            *e.v = value;
+            // cached graphs bake launch shapes in: drop them
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            for (auto &kv : g_cache) {
+                std::lock_guard<std::mutex> l2(kv.second->mu);
+                drop_graphs(kv.second);
+            }
+            return NP_OK;
+        }
+    set_error("unknown tuning key '%s'", key);
+    return NP_EINVAL;
+}
+
+extern "C" int np_get_tuning(const char *key) {
+    if (!key) return -1;
+    if (!std::strcmp(key, "fused")) return g_tune.fused;
+    if (!std::strcmp(key, "graphs")) return g_tune.graphs;
+    if (!std::strcmp(key, "tail")) return g_tune.tail;
+    if (!std::strcmp(key, "fmin2")) return g_tune.fmin2;
+    if (!std::strcmp(key, "fmin3")) return g_tune.fmin3;
+    if (!std::strcmp(key, "bz2")) return g_tune.bz2;
+    if (!std::strcmp(key, "bz3")) return g_tune.bz3;
+    if (!std::strcmp(key, "inner_fp32")) return g_tune.inner_fp32;
+    if (!std::strcmp(key, "inner_bf16")) return g_tune.inner_bf16;
+    if (!std::strcmp(key, "batch")) return g_tune.batch;
+    return -1;
+}
+
 // Common validation of the solver's scalar arguments.
 static np_status check_solve_args(const np_dims &dims, double h, int bc, const void *rhs, const void *x,
                                   double tol, const np_mg_opts &o, int *lg) {
@@ -591,7 +970,8 @@ static np_status check_solve_args(const np_dims &dims, double h, int bc, const v
         return NP_EINVAL;
     }
     if (!(o.omega > 0.0 && o.omega < 2.0)) { set_error("omega must be in (0, 2)"); return NP_EINVAL; }
-    if (o.max_cycles < 0 || o.fixed_cycles < 0 || o.inner_cycles < 0 || o.inner_cycles > 64) {
+    if (o.max_cycles < 0 || o.fixed_cycles < 0 || o.inner_cycles < 0 || o.inner_cycles > 64 ||
+        o.fixed_cycles > 100000 || o.max_cycles > 100000) {
         set_error("bad cycle counts");
         return NP_EINVAL;
     }
@@ -618,17 +998,16 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
     if (stats) std::memset(stats, 0, sizeof *stats);
     const int d = dims.ndim;
     hipStream_t s = (hipStream_t)o.stream;
-    Hier *Hp = nullptr;
-    NP_TRY(get_hier(d, lg, bc, NP_FP64, &Hp));
-    Hier *H = Hp;
+    Hier *H = nullptr;
+    NP_TRY(get_hier(d, lg, bc, NP_FP64, &H));
     Hier *HL = nullptr;
     if (o.smooth_prec != NP_FP64) NP_TRY(get_hier(d, lg, bc, o.smooth_prec, &HL));
     std::lock_guard<std::mutex> lk(H->mu);
     std::unique_lock<std::mutex> lk2;
     if (HL) lk2 = std::unique_lock<std::mutex>(HL->mu);
     const int64_t m = cells(d, lg);
-    NP_TRY(ensure_coarse(H, h, s));
-    if (HL) NP_TRY(ensure_coarse(HL, h, s));
+    if (!HL) NP_TRY(ensure_coarse(H, h, s));
+    else NP_TRY(ensure_coarse(HL, h, s));
     const double *f = rhs;
     if (bc == NP_BC_PERIODIC) {
         if (!H->f64) NP_TRY(dmalloc((void **)&H->f64, sizeof(double) * m));
@@ -645,7 +1024,7 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
     }
     const bool warm = o.warm_start == 2;
     if (nf == 0.0 || !warm) {
-        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m);
+        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
         NP_LAUNCH_CHECK();
     }
     if (nf == 0.0) {
@@ -658,13 +1037,13 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
         st = d == 2 ? solve_fp64<2>(H, f, x, h, tol, o, co, s, !warm, nf, stats)
                     : solve_fp64<3>(H, f, x, h, tol, o, co, s, !warm, nf, stats);
     } else if (o.smooth_prec == NP_FP32) {
-        st = d == 2 ? solve_mixed<2, float>(HL, f, x, h, tol, o, co, s, nf, stats)
-                    : solve_mixed<3, float>(HL, f, x, h, tol, o, co, s, nf, stats);
+        st = d == 2 ? solve_mixed<2, float>(HL, f, x, h, tol, o, co, s, nf, warm, stats)
+                    : solve_mixed<3, float>(HL, f, x, h, tol, o, co, s, nf, warm, stats);
     } else {
-        st = d == 2 ? solve_mixed<2, bf16>(HL, f, x, h, tol, o, co, s, nf, stats)
-                    : solve_mixed<3, bf16>(HL, f, x, h, tol, o, co, s, nf, stats);
+        st = d == 2 ? solve_mixed<2, bf16>(HL, f, x, h, tol, o, co, s, nf, warm, stats)
+                    : solve_mixed<3, bf16>(HL, f, x, h, tol, o, co, s, nf, warm, stats);
     }
-    if (st == NP_EHIP || st == NP_ENOMEM) return st;
+    if (st == NP_EHIP || st == NP_ENOMEM || st == NP_EINVAL) return st;
     if (bc == NP_BC_PERIODIC) NP_TRY(remove_mean(H, x, m, s));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return st;
@@ -709,9 +1088,9 @@ extern "C" np_status np_op_jacobi(np_dims dims, double h, np_bc bc, double omega
     if (!f || !x_in || !x_out || x_in == x_out) { set_error("null or aliased array"); return NP_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     if (dims.ndim == 2)
-        NP_TRY((Ops<2, double>::jacobi(f, x_in, x_out, lg, bc, h, omega, false, s, false)));
+        NP_TRY((Ops<2, double>::jacobi(f, x_in, x_out, lg, bc, h, omega, false, s, false, nullptr)));
     else
-        NP_TRY((Ops<3, double>::jacobi(f, x_in, x_out, lg, bc, h, omega, false, s, false)));
+        NP_TRY((Ops<3, double>::jacobi(f, x_in, x_out, lg, bc, h, omega, false, s, false, nullptr)));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }
@@ -723,8 +1102,8 @@ extern "C" np_status np_op_resid_restrict(np_dims dims, double h, np_bc bc, cons
     if (lg < 3) { set_error("need n >= 8 to restrict"); return NP_EINVAL; }
     if (!f || !x || !fc) { set_error("null array"); return NP_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
-    if (dims.ndim == 2) NP_TRY((Ops<2, double>::resid_restrict(f, x, fc, lg, bc, h, s)));
-    else NP_TRY((Ops<3, double>::resid_restrict(f, x, fc, lg, bc, h, s)));
+    if (dims.ndim == 2) NP_TRY((Ops<2, double>::resid_restrict(f, x, fc, lg, bc, h, s, nullptr)));
+    else NP_TRY((Ops<3, double>::resid_restrict(f, x, fc, lg, bc, h, s, nullptr)));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }
@@ -735,8 +1114,8 @@ extern "C" np_status np_op_prolong_add(np_dims dims, np_bc bc, const double *ec,
     if (lg < 3) { set_error("need n >= 8 to prolongate onto"); return NP_EINVAL; }
     if (!ec || !x) { set_error("null array"); return NP_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
-    if (dims.ndim == 2) NP_TRY((Ops<2, double>::prolong_add(ec, x, lg - 1, bc, s)));
-    else NP_TRY((Ops<3, double>::prolong_add(ec, x, lg - 1, bc, s)));
+    if (dims.ndim == 2) NP_TRY((Ops<2, double>::prolong_add(ec, x, lg - 1, bc, s, nullptr)));
+    else NP_TRY((Ops<3, double>::prolong_add(ec, x, lg - 1, bc, s, nullptr)));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }
@@ -757,9 +1136,14 @@ extern "C" np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double
     Hier *H = nullptr;
     NP_TRY(get_hier(dims.ndim, lg, bc, NP_FP64, &H));
     std::lock_guard<std::mutex> lk(H->mu);
+    NP_TRY(ensure_levels(H));
     NP_TRY(ensure_coarse(H, h, s));
-    if (dims.ndim == 2) NP_TRY((Ops<2, double>::vcycle(H, x, f, (double *)H->t[0], false, h, co, s)));
-    else NP_TRY((Ops<3, double>::vcycle(H, x, f, (double *)H->t[0], false, h, co, s)));
+    const int zero = 0;
+    NP_HIP_TRY(hipMemcpyAsync(&H->ctl->stop, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    if (dims.ndim == 2)
+        NP_TRY((Ops<2, double>::cycle(H, x, f, (double *)H->t[0], false, false, h, co, s)));
+    else
+        NP_TRY((Ops<3, double>::cycle(H, x, f, (double *)H->t[0], false, false, h, co, s)));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }
@@ -773,8 +1157,11 @@ extern "C" np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const do
     Hier *H = nullptr;
     NP_TRY(get_hier(dims.ndim, lg, bc, NP_FP64, &H));
     std::lock_guard<std::mutex> lk(H->mu);
-    if (dims.ndim == 2) NP_TRY((Ops<2, double>::resid_norm(f, x, lg, bc, h, H->red, 0, s)));
-    else NP_TRY((Ops<3, double>::resid_norm(f, x, lg, bc, h, H->red, 0, s)));
+    int nb = 0;
+    if (dims.ndim == 2) NP_TRY((Ops<2, double>::resid_sq(f, x, lg, bc, h, H->red, s, nullptr, &nb)));
+    else NP_TRY((Ops<3, double>::resid_sq(f, x, lg, bc, h, H->red, s, nullptr, &nb)));
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->red + kPartials, 1);
+    NP_LAUNCH_CHECK();
     NP_TRY(read_scalars(H, 1, s));
     *out = H->hred[0];
     return NP_OK;

@@ -61,8 +61,9 @@ template <int D, class S, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_jacobi(const S *__restrict__ f, const S *__restrict__ xin,
                                                    S *__restrict__ xout, int lg, int bc,
                                                    typename St<S>::C inv_h2,
-                                                   typename St<S>::C wdiag) {
+                                                   typename St<S>::C wdiag, const int *stop) {
     typedef typename St<S>::C C;
+    if (stop && *stop) return;
     const int64_t m = int64_t(1) << (D * lg);
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= m) return;
@@ -84,8 +85,9 @@ template <int D, class S>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(const S *__restrict__ f,
                                                            const S *__restrict__ x,
                                                            S *__restrict__ fc, int lg, int bc,
-                                                           typename St<S>::C inv_h2) {
+                                                           typename St<S>::C inv_h2, const int *stop) {
     typedef typename St<S>::C C;
+    if (stop && *stop) return;
     const int lgc = lg - 1;
     const int64_t mc = int64_t(1) << (D * lgc);
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -123,8 +125,9 @@ __device__ __forceinline__ void pro_axis(int i, int nc, int bc, int &own, int &n
 // boundary rule.  lgc is the coarse level's log2 size.
 template <int D, class S>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec, S *__restrict__ x,
-                                                        int lgc, int bc) {
+                                                        int lgc, int bc, const int *stop) {
     typedef typename St<S>::C C;
+    if (stop && *stop) return;
     const int lg = lgc + 1, nc = 1 << lgc;
     const int64_t m = int64_t(1) << (D * lg);
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -154,8 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec
 template <int D, class S>
 __global__ __launch_bounds__(64) void k_coarse(const S *__restrict__ f, S *__restrict__ x,
                                                const double *__restrict__ Minv, int bc, double inv_h2,
-                                               int zero) {
+                                               int zero, const int *stop) {
     constexpr int m = D == 3 ? 64 : 16;
+    if (stop && *stop) return;
     __shared__ double xs[64], rs[64];
     const int t = threadIdx.x;
     if (t < m) xs[t] = zero ? 0.0 : double(St<S>::ld(x + t));
@@ -229,8 +233,9 @@ __global__ __launch_bounds__(kBlock) void k_sub_scaled(double *__restrict__ v, i
 // FP64 refinement step of the mixed-precision solve: x_out = x + e (e in the
 // inner precision; has_e = 0 means e = 0 and x_out is not written),
 // r = f - A x_out in FP64, r_lo = r rounded to the inner precision, and FP64
-// partial sums of r^2.  Neighbour values of x_out are formed on the fly, so
-// x and x_out must be different buffers.
+// partial sums of r^2, one per workgroup of kIrCells cells.  Neighbour values
+// of x_out are formed on the fly, so x and x_out must be different buffers.
+constexpr int kIrCells = 4 * kBlock;
 template <int D, class SL>
 __global__ __launch_bounds__(kBlock) void k_ir_resid(const double *__restrict__ x,
                                                      const SL *__restrict__ e,
@@ -238,30 +243,84 @@ __global__ __launch_bounds__(kBlock) void k_ir_resid(const double *__restrict__ 
                                                      const double *__restrict__ f,
                                                      SL *__restrict__ rlo,
                                                      double *__restrict__ partial, int lg, int bc,
-                                                     double inv_h2, int has_e) {
+                                                     double inv_h2, int has_e, const int *stop) {
+    if (stop && *stop) return;
     const int64_t m = int64_t(1) << (D * lg);
     double acc = 0.0;
-    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
-         c += int64_t(gridDim.x) * blockDim.x) {
-        int i, j, k;
-        decode<D>(c, lg, i, j, k);
-        struct {
-            const double *x;
-            const SL *e;
-            int he;
-            __device__ double operator()(int64_t q) const {
-                return he ? x[q] + double(St<SL>::ld(e + q)) : x[q];
-            }
-        } ldx{x, e, has_e};
-        const double xc = ldx(c);
-        const double s = nb_sum<D, double>(ldx, c, i, j, k, lg, bc, xc);
-        const double r = f[c] - (double(2 * D) * xc - s) * inv_h2;
-        if (has_e) xout[c] = xc;
-        St<SL>::st(rlo + c, typename St<SL>::C(r));
-        acc += r * r;
+    struct {
+        const double *x;
+        const SL *e;
+        int he;
+        __device__ double operator()(int64_t q) const {
+            return he ? x[q] + double(St<SL>::ld(e + q)) : x[q];
+        }
+    } ldx{x, e, has_e};
+    for (int64_t base = int64_t(blockIdx.x) * kIrCells; base < m; base += int64_t(gridDim.x) * kIrCells)
+#pragma unroll
+    for (int u = 0; u < kIrCells / kBlock; ++u) {
+        const int64_t c = base + u * kBlock + threadIdx.x;
+        if (c < m) {
+            int i, j, k;
+            decode<D>(c, lg, i, j, k);
+            const double xc = ldx(c);
+            const double s = nb_sum<D, double>(ldx, c, i, j, k, lg, bc, xc);
+            const double r = f[c] - (double(2 * D) * xc - s) * inv_h2;
+            if (has_e) xout[c] = xc;
+            St<SL>::st(rlo + c, typename St<SL>::C(r));
+            acc += r * r;
+        }
     }
     acc = block_sum(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Solve controller kept in device memory so that cycles can be enqueued (and
+// replayed from graphs) without a host round trip per cycle.
+struct Ctl {
+    int stop;       // 0 running; otherwise the reason (StopReason)
+    int k;          // cycles (or refinement steps) completed
+    int fixed;      // > 0: stop after exactly this many
+    int maxc;       // cap
+    double nf;      // ||f||_2
+    double tol;
+    int nhist;
+    int pad;
+    double hist[256];
+};
+enum StopReason { kRunning = 0, kConverged = 1, kFixedDone = 2, kMaxCycles = 3, kNonFinite = 4, kDiverged = 5 };
+
+// Convergence check before cycle k: rr = sqrt(sum of partials)/||f|| (fixed
+// summation order), recorded in hist[k]; then the stop rule: non-finite,
+// fixed count reached, rr <= tol, k >= max, or three consecutive increases.
+__global__ __launch_bounds__(kBlock) void k_check(const double *__restrict__ partial, int np,
+                                                  Ctl *__restrict__ c) {
+    if (c->stop) return;
+    // four interleaved accumulators (fixed assignment): deterministic
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = threadIdx.x;
+    for (; b + 3 * kBlock < np; b += 4 * kBlock) {
+        a0 += partial[b];
+        a1 += partial[b + kBlock];
+        a2 += partial[b + 2 * kBlock];
+        a3 += partial[b + 3 * kBlock];
+    }
+    for (; b < np; b += kBlock) a0 += partial[b];
+    double acc = block_sum((a0 + a1) + (a2 + a3));
+    if (threadIdx.x != 0) return;
+    const int k = c->k;
+    const double rr = sqrt(acc) / c->nf;
+    if (k < 256) c->hist[k] = rr;
+    c->nhist = k + 1 < 256 ? k + 1 : 256;
+    int st = kRunning;
+    if (!(rr <= 1.0e300)) st = kNonFinite;  // NaN or Inf
+    else if (c->fixed > 0) { if (k >= c->fixed) st = kFixedDone; }
+    else if (rr <= c->tol) st = kConverged;
+    else if (k >= c->maxc) st = kMaxCycles;
+    else if (k >= 3 && k < 256 && c->hist[k - 3] < c->hist[k - 2] && c->hist[k - 2] < c->hist[k - 1] &&
+             c->hist[k - 1] < rr)
+        st = kDiverged;
+    if (st != kRunning) c->stop = st;
+    else c->k = k + 1;
 }
 
 // y = A x (FP64).
@@ -278,9 +337,19 @@ __global__ __launch_bounds__(kBlock) void k_apply(const double *__restrict__ x, 
     y[c] = (double(2 * D) * xc - s) * inv_h2;
 }
 
+// dst = src (gated copy used inside captured cycles).
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_copy(const S *__restrict__ src, S *__restrict__ dst, int64_t m,
+                                                 const int *stop) {
+    if (stop && *stop) return;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < m) dst[c] = src[c];
+}
+
 // Fill with zeros (used instead of a memset so the work stays in kernels).
 template <class S>
-__global__ __launch_bounds__(kBlock) void k_zero(S *__restrict__ v, int64_t m) {
+__global__ __launch_bounds__(kBlock) void k_zero(S *__restrict__ v, int64_t m, const int *stop) {
+    if (stop && *stop) return;
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c < m) St<S>::st(v + c, typename St<S>::C(0));
 }

@@ -1,0 +1,222 @@
+// Level kernels of the default (unfused) multigrid path, tuned for gfx950:
+//  - k_sweep:     one weighted-Jacobi sweep, two cells per thread, optionally
+//                 reducing ||f - A x_in||^2 of its input (the residual the sweep
+//                 computes anyway) into one partial sum per workgroup;
+//  - k_restrict:  residual and 2^d-cell average with coalesced fine-grid reads:
+//                 a workgroup owns a 64 x 2 x 2 (3D) / 128 x 2 (2D) block of fine
+//                 cells, each thread one residual, children summed through LDS;
+//  - k_tail:      the whole V-cycle below a level of 16^3 (3D) / 64^2 (2D) cells
+//                 in one workgroup, every level resident in LDS.
+// Arithmetic per cell is that of mg_kernels.h (same expressions and orders).
+#pragma once
+
+#include "mg_kernels.h"
+#include "np_internal.h"
+
+namespace np {
+
+constexpr int kSweepCells = 2 * kBlock;  // cells per workgroup of k_sweep
+
+template <int D, class S, bool ZERO, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ f, const S *__restrict__ xin,
+                                                  S *__restrict__ xout, double *__restrict__ partial, int lg,
+                                                  int bc, typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                  const int *stop) {
+    typedef typename St<S>::C C;
+    if (stop && *stop) return;
+    const int64_t m = int64_t(1) << (D * lg);
+    double acc = 0.0;
+    for (int64_t base = int64_t(blockIdx.x) * kSweepCells; base < m; base += int64_t(gridDim.x) * kSweepCells)
+#pragma unroll
+    for (int u = 0; u < kSweepCells / kBlock; ++u) {
+        const int64_t c = base + u * kBlock + threadIdx.x;
+        if (c < m) {
+            const C fc = St<S>::ld(f + c);
+            if (ZERO) {
+                St<S>::st(xout + c, wdiag * fc);
+            } else {
+                int i, j, k;
+                decode<D>(c, lg, i, j, k);
+                const C xc = St<S>::ld(xin + c);
+                const C s = nb_sum<D, C>(Ld<S>{xin}, c, i, j, k, lg, bc, xc);
+                const C r = fc - (C(2 * D) * xc - s) * inv_h2;
+                if (NORM) acc += double(r) * double(r);
+                St<S>::st(xout + c, xc + wdiag * r);
+            }
+        }
+    }
+    if (NORM) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
+// Fine cells per workgroup along x in k_restrict.
+template <int D> struct RBlk {
+    static constexpr int FX = D == 3 ? 64 : 128;
+};
+
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_restrict(const S *__restrict__ f, const S *__restrict__ x,
+                                                     S *__restrict__ fc, int lg, int bc,
+                                                     typename St<S>::C inv_h2, const int *stop) {
+    typedef typename St<S>::C C;
+    constexpr int FX = RBlk<D>::FX;
+    __shared__ C r[kBlock];
+    if (stop && *stop) return;
+    const int n = 1 << lg, nc = n >> 1, tid = threadIdx.x;
+    const int bxn = n / FX;
+    // workgroup -> (x block, coarse row J, coarse plane K)
+    const int b = blockIdx.x;
+    const int bx = b % bxn, J = (b / bxn) % nc, K = D == 3 ? b / (bxn * nc) : 0;
+    const int a = tid % FX, yb = (tid / FX) & 1, zb = D == 3 ? tid / (2 * FX) : 0;
+    const int i = bx * FX + a, j = 2 * J + yb, k = D == 3 ? 2 * K + zb : 0;
+    const int64_t c = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
+    r[tid] = resid_at<D, S>(f, x, c, i, j, k, lg, bc, inv_h2);
+    __syncthreads();
+    if (tid < FX / 2) {
+        C acc = C(0);
+        for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) acc += r[(cz * 2 + cy) * FX + 2 * tid + cx];
+        const int I = bx * (FX / 2) + tid;
+        St<S>::st(fc + ((int64_t(K) * nc + J) * nc + I), acc * C(D == 3 ? 0.125 : 0.25));
+    }
+}
+
+// ------------------------------------------------------------- coarse tail
+template <int D> struct Tail {
+    static constexpr int LG = D == 3 ? 4 : 6;  // finest level handled: 16^3 / 64^2
+    static constexpr int64_t cells(int lg) { return int64_t(1) << (D * lg); }
+    static constexpr int64_t levels_sum() {
+        int64_t s = 0;
+        for (int l = LG; l >= 2; --l) s += cells(l);
+        return s;
+    }
+    static constexpr int NT = D == 3 ? 512 : 1024;  // threads (3D FP64 needs the registers)
+};
+
+template <int D, class C> struct LdsLd {
+    const C *p;
+    __device__ __forceinline__ C operator()(int64_t q) const { return p[q]; }
+};
+
+// V(nu1, nu2) cycle from a zero iterate on levels lg_t .. 2 in one workgroup.
+// f_t: right-hand side of level lg_t (global); x_t: result (global).  h_t:
+// spacing of level lg_t.  nu1 >= 1.
+template <int D, class S>
+__global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t, S *__restrict__ x_t,
+                                               const double *__restrict__ Minv, int lg_t, int bc, double h_t,
+                                               double omega, int nu1, int nu2, const int *stop) {
+    typedef typename St<S>::C C;
+    constexpr int NT = Tail<D>::NT;
+    __shared__ C xs[Tail<D>::levels_sum()];
+    __shared__ C fs[Tail<D>::levels_sum()];
+    __shared__ C ts[Tail<D>::cells(Tail<D>::LG)];
+    if (stop && *stop) return;
+    const int tid = threadIdx.x;
+    // level l starts after the finer levels lg_t .. l+1 (geometric sum)
+    auto off = [&](int l) -> int64_t {
+        return ((int64_t(1) << (D * (lg_t + 1))) - (int64_t(1) << (D * (l + 1)))) / ((int64_t(1) << D) - 1);
+    };
+    const int64_t mt = int64_t(1) << (D * lg_t);
+    for (int64_t c = tid; c < mt; c += NT) fs[off(lg_t) + c] = St<S>::ld(f_t + c);
+    __syncthreads();
+    double h = h_t;
+    // ------------------------------------------------------------- down
+    for (int lg = lg_t; lg > 2; --lg, h *= 2.0) {
+        const int64_t m = int64_t(1) << (D * lg);
+        C *X = xs + off(lg), *F = fs + off(lg);
+        const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+        // first sweep from zero, then the rest ping-pong through ts
+        for (int64_t c = tid; c < m; c += NT) X[c] = wdiag * F[c];
+        __syncthreads();
+        for (int it = 1; it < nu1; ++it) {
+            for (int64_t c = tid; c < m; c += NT) {
+                int i, j, k;
+                decode<D>(c, lg, i, j, k);
+                const C xc = X[c];
+                const C s = nb_sum<D, C>(LdsLd<D, C>{X}, c, i, j, k, lg, bc, xc);
+                ts[c] = xc + wdiag * (F[c] - (C(2 * D) * xc - s) * inv_h2);
+            }
+            __syncthreads();
+            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
+            __syncthreads();
+        }
+        // residual and restriction into the next level's rhs
+        const int lgc = lg - 1;
+        const int64_t mc = int64_t(1) << (D * lgc);
+        C *Fc = fs + off(lgc);
+        for (int64_t cc = tid; cc < mc; cc += NT) {
+            int I, J, K;
+            decode<D>(cc, lgc, I, J, K);
+            C acc = C(0);
+            for (int kk = 0; kk < (D == 3 ? 2 : 1); ++kk)
+                for (int jj = 0; jj < 2; ++jj)
+                    for (int ii = 0; ii < 2; ++ii) {
+                        const int i = 2 * I + ii, j = 2 * J + jj, k = D == 3 ? 2 * K + kk : 0;
+                        const int64_t cf = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
+                        const C xc = X[cf];
+                        const C s = nb_sum<D, C>(LdsLd<D, C>{X}, cf, i, j, k, lg, bc, xc);
+                        acc += F[cf] - (C(2 * D) * xc - s) * inv_h2;
+                    }
+            Fc[cc] = acc * C(D == 3 ? 0.125 : 0.25);
+        }
+        __syncthreads();
+    }
+    // ------------------------------------------------- coarsest (zero guess)
+    {
+        constexpr int m = D == 3 ? 64 : 16;
+        C *X = xs + off(2), *F = fs + off(2);
+        if (tid < m) {
+            double acc = 0.0;
+            for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * double(F[q]);
+            X[tid] = C(0.0 + acc);
+        }
+        __syncthreads();
+    }
+    // --------------------------------------------------------------- up
+    for (int lg = 3; lg <= lg_t; ++lg) {
+        h *= 0.5;
+        const int64_t m = int64_t(1) << (D * lg);
+        const int lgc = lg - 1, nc = 1 << lgc;
+        C *X = xs + off(lg), *F = fs + off(lg), *E = xs + off(lgc);
+        const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+        for (int64_t c = tid; c < m; c += NT) {
+            int i, j, k;
+            decode<D>(c, lg, i, j, k);
+            int oi, ni, oj, nj, ok = 0, nk = 0;
+            float si, sj, sk = 1.0f;
+            pro_axis(i, nc, bc, oi, ni, si);
+            pro_axis(j, nc, bc, oj, nj, sj);
+            if (D == 3) pro_axis(k, nc, bc, ok, nk, sk);
+            C s = C(0);
+            for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(D == 3 ? (cz ? 0.25 : 0.75) : 1.0);
+                        const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
+                        const int64_t q = (int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
+                                          (a ? ni : oi);
+                        s += w * (sg * E[q]);
+                    }
+            X[c] = X[c] + s;
+        }
+        __syncthreads();
+        for (int it = 0; it < nu2; ++it) {
+            for (int64_t c = tid; c < m; c += NT) {
+                int i, j, k;
+                decode<D>(c, lg, i, j, k);
+                const C xc = X[c];
+                const C s = nb_sum<D, C>(LdsLd<D, C>{X}, c, i, j, k, lg, bc, xc);
+                ts[c] = xc + wdiag * (F[c] - (C(2 * D) * xc - s) * inv_h2);
+            }
+            __syncthreads();
+            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
+            __syncthreads();
+        }
+    }
+    for (int64_t c = tid; c < mt; c += NT) St<S>::st(x_t + c, xs[off(lg_t) + c]);
+}
+
+}  // namespace np

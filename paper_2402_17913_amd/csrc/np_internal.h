@@ -91,8 +91,15 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // -------------------------------------------------------------- profiling
-// Event bracketing of the finest-level smoothing launches (np_prof_*).
-bool prof_on();
+// Event bracketing of finest-level launches (np_prof_*).  prof_on() returns
+// the mask of kernel kinds being timed.
+enum ProfKind {
+    kProfDown = 1,      // smoothing + residual + restriction (iterate read)
+    kProfDownZero = 2,  // the same from a zero iterate
+    kProfUp = 4,        // prolongation + correction + smoothing
+    kProfJacobi = 8,    // single Jacobi sweep
+};
+int prof_on();
 np_status prof_begin(hipStream_t s, void **tok);
 np_status prof_end(hipStream_t s, void *tok, double bytes);
 

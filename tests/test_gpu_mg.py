@@ -73,7 +73,8 @@ def test_restrict_and_prolong(B, orc, d, n, bc):
     assert rel(host(xg), orc.prolong_add(ec, x, bc)) < 1e-14
 
 
-@pytest.mark.parametrize("d,n", [(2, 4), (2, 16), (2, 128), (3, 4), (3, 16), (3, 32)])
+@pytest.mark.parametrize("d,n", [(2, 4), (2, 16), (2, 128), (2, 512), (3, 4), (3, 16), (3, 32),
+                                 (3, 64), (3, 128)])
 @pytest.mark.parametrize("bc", [DIR, PER])
 def test_one_vcycle(B, orc, d, n, bc):
     say("vcycle", d, n, bc)
@@ -85,6 +86,43 @@ def test_one_vcycle(B, orc, d, n, bc):
     xg = dev(x)
     B.np_op_vcycle(dev(f), xg, h, bc)
     assert rel(host(xg), orc.vcycle(f, x, h, bc)) < 1e-12
+
+
+@pytest.mark.parametrize("knobs", [dict(fused=1), dict(graphs=0), dict(fused=1, bz3=2, bz2=2),
+                                   dict(fused=1, fmin2=4, fmin3=4), dict(tail=0), dict(fused=1, tail=0)])
+def test_kernel_variants_agree(B, orc, knobs):
+    """Fused level kernels (also with the smallest marching chunks and down to 4^d),
+    direct launches and the per-level kernels without the one-workgroup tail all give
+    the oracle's cycles."""
+    old = {k: B.np_get_tuning(k) for k in knobs}
+    try:
+        for k, v in knobs.items():
+            B.np_set_tuning(k, v)
+        for d, n, bc in [(2, 64, DIR), (2, 256, PER), (3, 32, PER), (3, 64, DIR)]:
+            say("variant", knobs, d, n, bc)
+            rng = np.random.default_rng(n + d)
+            h = 1.0 / n
+            x, f = rng.standard_normal((n,) * d), rng.standard_normal((n,) * d)
+            if bc == PER:
+                f -= f.mean()
+            xg = dev(x)
+            B.np_op_vcycle(dev(f), xg, h, bc)
+            assert rel(host(xg), orc.vcycle(f, x, h, bc)) < 1e-12
+            ref = orc.mg_solve(f, h, bc, fixed_cycles=3)
+            xg = dev(np.zeros_like(f))
+            st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, fixed_cycles=3)
+            assert stats["cycles"] == 3 and rel(host(xg), ref.x) < 1e-12
+    finally:
+        for k, v in old.items():
+            B.np_set_tuning(k, v)
+
+
+def test_tuning_knobs_validate(B):
+    with pytest.raises(B.NeuphysError):
+        B.np_set_tuning("no_such_knob", 1)
+    with pytest.raises(B.NeuphysError):
+        B.np_set_tuning("bz3", 3)
+    assert B.np_get_tuning("fused") == 0 and B.np_get_tuning("tail") == 1
 
 
 def test_resid_norm(B, orc):
