@@ -47,7 +47,11 @@ def kernel_times(B, fg, xg, h, prec, steps):
     bracketed by HIP events on the stream it runs on (graph replay is off while timing)."""
     import torch
     out = {}
-    for name, mask in (("down", B.PROF_DOWN), ("down_zero", B.PROF_DOWN_ZERO), ("up", B.PROF_UP)):
+    kinds = (("sweep", B.PROF_JACOBI), ("sweep_zero", B.PROF_SWEEP_ZERO), ("restrict", B.PROF_RESTRICT),
+             ("prolong", B.PROF_PROLONG),
+             ("refine", B.PROF_REFINE), ("fused_down", B.PROF_DOWN), ("fused_down_zero", B.PROF_DOWN_ZERO),
+             ("fused_up", B.PROF_UP))
+    for name, mask in kinds:
         B.np_prof_enable(mask)
         for _ in range(steps):
             B.mg_poisson_solve(fg, xg, h, B.BC_DIRICHLET0, tol=TOL, smooth_prec=prec)
@@ -74,6 +78,24 @@ def copy_bandwidth(reps=5):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     return 2 * a.numel() * 8 / dt / 1e9
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, if the kernel's source is unchanged since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_sweep_fp32_poisson3d_256.md")
+    if kernel != "sweep" or not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m1 = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    m2 = re.search(r"kernel_source_sha256_16: (\w+)", txt)
+    src = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", "mg_level.h")).read()
+    body = src[src.index("template <int D, class S, bool ZERO, bool NORM>"):src.index("// Fine cells per workgroup along x")]
+    if not (m1 and m2) or hashlib.sha256(body.encode()).hexdigest()[:16] != m2.group(1):
+        return None
+    return int(m1.group(1))
 
 
 def cpu_baseline(f, h, cycles_needed):
@@ -169,15 +191,20 @@ def main():
             "mixed_over_plain": res[head]["dofs_per_s"] / res["fp64"]["dofs_per_s"],
         },
         "roofline": {
-            "kernel": {"down": "fused 2 Jacobi sweeps + residual + restriction, level 0",
-                       "down_zero": "fused zero-guess sweeps + residual + restriction, level 0",
-                       "up": "fused prolongation + 2 Jacobi sweeps, level 0"}[dom] + " (FP32 storage)",
+            "kernel": {"sweep": "k_sweep: weighted-Jacobi sweep, finest level",
+                       "sweep_zero": "k_sweep: Jacobi sweep from a zero iterate, finest level",
+                       "restrict": "k_restrict: residual + restriction, finest level",
+                       "prolong": "k_prolong_add: prolongation + correction, finest level",
+                       "refine": "k_ir_resid: FP64 update + residual of the refinement",
+                       "fused_down": "k_fused: 2 sweeps + residual + restriction, finest level",
+                       "fused_down_zero": "k_fused: zero-guess sweeps + residual + restriction",
+                       "fused_up": "k_fused: prolongation + 2 sweeps, finest level"}[dom] + " (FP32 storage)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom),
             "avg_us": kt[dom]["avg_us"],
             "bytes_per_launch": kt[dom]["bytes_per_launch"],
             "copy_measured_gbs": copy_gbs,

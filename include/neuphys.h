@@ -163,7 +163,9 @@ np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const double *f, co
  * stream it is launched on (and disables graph replay meanwhile, so each
  * launch is seen); mask bits: 1 fused smoothing + residual + restriction,
  * 2 the same from a zero iterate, 4 fused prolongation + smoothing,
- * 8 single Jacobi sweep; 0 stops.  np_prof_read returns (host) the number
+ * 8 Jacobi sweep, 16 residual + restriction, 32 prolongation + correction,
+ * 64 FP64 update + residual of the mixed-precision refinement, 128 Jacobi
+ * sweep from a zero iterate; 0 stops.  np_prof_read returns (host) the number
  * of bracketed launches since the last enable, the sum of their durations in
  * milliseconds and the algorithmic bytes they move (each field read once,
  * each output written once). */

@@ -185,6 +185,7 @@ def np_op_resid_norm(f, x, h, bc):
 
 
 PROF_DOWN, PROF_DOWN_ZERO, PROF_UP, PROF_JACOBI = 1, 2, 4, 8
+PROF_RESTRICT, PROF_PROLONG, PROF_REFINE, PROF_SWEEP_ZERO = 16, 32, 64, 128
 
 
 def np_prof_enable(mask):

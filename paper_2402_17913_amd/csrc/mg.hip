@@ -118,7 +118,8 @@ static Tuning g_tune;
 // of the plain FP64 path uses the caller's x and rhs; t[0] is its ping-pong
 // partner.  The mixed path keeps the correction e, the rounded residual and
 // the ping-pong buffer of level 0 in x[0], f[0], t[0].
-constexpr int kPartials = 65536;  // per-workgroup partial sums (fixed order)
+constexpr int kPartials = 65536;
+constexpr unsigned kNormBlocks = 2048;  // workgroups of a sweep that also reduces the residual norm  // per-workgroup partial sums (fixed order)
 
 struct GraphKey {
     int kind;  // 0: FP64 cycle, 1: mixed first step, 2: mixed step a->b, 3: mixed step b->a
@@ -345,6 +346,10 @@ template <int D> struct Tile {
     static constexpr int TY = D == 3 ? 16 : 1;
 };
 
+// log2 size of the finest level of the cycle being enqueued (for profiling
+// the finest-level launches only).
+static thread_local int H_lg_top = -1;
+
 template <int D, class S> struct Ops {
     typedef typename St<S>::C C;
 
@@ -373,9 +378,9 @@ template <int D, class S> struct Ops {
         const int64_t m = cells(D, lg);
         const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
         unsigned nb = unsigned((m + kSweepCells - 1) / kSweepCells);
-        if (partial) nb = std::min<unsigned>(nb, kPartials);
+        if (partial) nb = std::min<unsigned>(nb, kNormBlocks);  // few partials: a cheap check
         void *tok = nullptr;
-        const bool prof = finest && (prof_on() & kProfJacobi);
+        const bool prof = finest && (prof_on() & (zero ? kProfSweepZero : kProfJacobi));
         if (prof) NP_TRY(prof_begin(s, &tok));
         if (zero)
             hipLaunchKernelGGL((k_sweep<D, S, true, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial, lg,
@@ -398,9 +403,16 @@ template <int D, class S> struct Ops {
         const int n = 1 << lg;
         if (n >= RBlk<D>::FX) {
             const int64_t nb = int64_t(n / RBlk<D>::FX) * (n / 2) * (D == 3 ? n / 2 : 1);
+            void *tok = nullptr;
+            const bool prof = lg == H_lg_top && (prof_on() & kProfRestrict);
+            if (prof) NP_TRY(prof_begin(s, &tok));
             hipLaunchKernelGGL((k_restrict<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, f, x, fc, lg, bc,
                                C(1.0 / (h * h)), stop);
             NP_LAUNCH_CHECK();
+            if (prof) {
+                const double m = double(cells(D, lg));
+                NP_TRY(prof_end(s, tok, m * 2 * sizeof(S) + m / (1 << D) * sizeof(S)));
+            }
             return NP_OK;
         }
         return resid_restrict(f, x, fc, lg, bc, h, s, stop);
@@ -425,9 +437,13 @@ template <int D, class S> struct Ops {
 
     static np_status prolong_add(const S *ec, S *x, int lgc, int bc, hipStream_t s, const int *stop) {
         const int64_t m = cells(D, lgc + 1);
+        void *tok = nullptr;
+        const bool prof = lgc + 1 == H_lg_top && (prof_on() & kProfProlong);
+        if (prof) NP_TRY(prof_begin(s, &tok));
         hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc,
                            stop);
         NP_LAUNCH_CHECK();
+        if (prof) NP_TRY(prof_end(s, tok, double(m) * 2 * sizeof(S) + double(m) / (1 << D) * sizeof(S)));
         return NP_OK;
     }
 
@@ -511,6 +527,7 @@ template <int D, class S> struct Ops {
                            const CycleOpts &o, hipStream_t s) {
         const int L = H->L, bc = H->bc;
         const int *stop = &H->ctl->stop;
+        H_lg_top = H->lg;
         const bool fz = g_tune.fused && o.nu1 == 2 && o.nu2 == 2;
         const int fmin = D == 3 ? g_tune.fmin3 : g_tune.fmin2;
         std::vector<S *> cur(L + 1), oth(L + 1), res(L + 1);
@@ -827,9 +844,13 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
     const int *stop = &H->ctl->stop;
     // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles
     auto step = [&](hipStream_t q, const double *xin, double *xout, int has_e) -> np_status {
+        void *tok = nullptr;
+        const bool prof = prof_on() & kProfRefine;
+        if (prof) NP_TRY(prof_begin(q, &tok));
         hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, q, xin, e, xout, f, rlo, H->red, H->lg,
                            H->bc, 1.0 / (h * h), has_e, stop);
         NP_LAUNCH_CHECK();
+        if (prof) NP_TRY(prof_end(q, tok, double(m) * (has_e ? 8 + sizeof(SL) + 8 + 8 + sizeof(SL) : 8 + 8 + sizeof(SL))));
         hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, q, H->red, int(nb), H->ctl);
         NP_LAUNCH_CHECK();
         for (int c = 0; c < inner; ++c) NP_TRY(O::cycle(H, e, rlo, tt, c == 0, false, h, co, q));

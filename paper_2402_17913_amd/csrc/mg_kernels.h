@@ -130,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec
     if (stop && *stop) return;
     const int lg = lgc + 1, nc = 1 << lgc;
     const int64_t m = int64_t(1) << (D * lg);
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t c = int64_t(sizeof(S) < 8 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= m) return;
     int i, j, k;
     decode<D>(c, lg, i, j, k);
@@ -255,7 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_ir_resid(const double *__restrict__ 
             return he ? x[q] + double(St<SL>::ld(e + q)) : x[q];
         }
     } ldx{x, e, has_e};
-    for (int64_t base = int64_t(blockIdx.x) * kIrCells; base < m; base += int64_t(gridDim.x) * kIrCells)
+    const unsigned blk = blockIdx.x;
+    for (int64_t base = int64_t(blk) * kIrCells; base < m; base += int64_t(gridDim.x) * kIrCells)
 #pragma unroll
     for (int u = 0; u < kIrCells / kBlock; ++u) {
         const int64_t c = base + u * kBlock + threadIdx.x;

@@ -26,7 +26,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ f, const
     if (stop && *stop) return;
     const int64_t m = int64_t(1) << (D * lg);
     double acc = 0.0;
-    for (int64_t base = int64_t(blockIdx.x) * kSweepCells; base < m; base += int64_t(gridDim.x) * kSweepCells)
+    // XCD-contiguous order for cache-resident (FP32/BF16) fields; measured slower
+    // for FP64 fields, which stream from HBM
+    const unsigned blk = sizeof(S) < 8 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    for (int64_t base = int64_t(blk) * kSweepCells; base < m; base += int64_t(gridDim.x) * kSweepCells)
 #pragma unroll
     for (int u = 0; u < kSweepCells / kBlock; ++u) {
         const int64_t c = base + u * kBlock + threadIdx.x;
@@ -67,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const S *__restrict__ f, co
     const int n = 1 << lg, nc = n >> 1, tid = threadIdx.x;
     const int bxn = n / FX;
     // workgroup -> (x block, coarse row J, coarse plane K)
-    const int b = blockIdx.x;
+    const int b = int(sizeof(S) < 8 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x);
     const int bx = b % bxn, J = (b / bxn) % nc, K = D == 3 ? b / (bxn * nc) : 0;
     const int a = tid % FX, yb = (tid / FX) & 1, zb = D == 3 ? tid / (2 * FX) : 0;
     const int i = bx * FX + a, j = 2 * J + yb, k = D == 3 ? 2 * K + zb : 0;

@@ -90,6 +90,13 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
+// XCD-aware workgroup order.  The dispatcher hands workgroup i to XCD i mod 8;
+// remapping ids so that XCD x runs the contiguous range [x G/8, (x+1) G/8)
+// keeps neighbouring rows and planes of a stencil in the same L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned g) {
+    return (g & 7u) == 0u ? (b & 7u) * (g >> 3) + (b >> 3) : b;
+}
+
 // -------------------------------------------------------------- profiling
 // Event bracketing of finest-level launches (np_prof_*).  prof_on() returns
 // the mask of kernel kinds being timed.
@@ -98,6 +105,10 @@ enum ProfKind {
     kProfDownZero = 2,  // the same from a zero iterate
     kProfUp = 4,        // prolongation + correction + smoothing
     kProfJacobi = 8,    // single Jacobi sweep
+    kProfRestrict = 16, // residual + restriction
+    kProfProlong = 32,  // prolongation + correction
+    kProfRefine = 64,   // FP64 update + residual of the mixed-precision refinement
+    kProfSweepZero = 128,  // Jacobi sweep from a zero iterate
 };
 int prof_on();
 np_status prof_begin(hipStream_t s, void **tok);
