@@ -115,6 +115,34 @@ np_status ns_projection_step(np_dims dims, double h, double *u, double *v, doubl
                              np_mg_stats *stats);
 
 /*
+ * Many independent 2D Poisson solves of different sizes in one call (zero
+ * Dirichlet only).  Problem p: dims[p] (n x n, n a power of two in
+ * [4, 16384]), spacing h[p], right-hand side rhs[p] and solution x[p]
+ * (device FP64 arrays; rhs, x, dims, h are host arrays of length nprob).
+ * Each problem is solved by mixed-precision refinement: FP64 residual and
+ * update, then V(nu1, nu2) cycles in opts->smooth_prec (NP_FP32, or NP_FP64)
+ * on the rounded residual from a zero correction.  The cycles of all
+ * problems run batched: levels are aligned from the coarsest (4x4) grid, so
+ * every level launch covers all problems that have that level; levels at or
+ * below 64x64 run in one workgroup per problem; refinement steps are
+ * replayed from captured HIP graphs; convergence is decided per problem on
+ * the device and converged problems drop out of later launches.  Each
+ * problem stops at ||f - A x||_2/||f||_2 <= tol (or after opts->fixed_cycles
+ * refinement steps).  opts->inner_cycles = 0 lets the autotuner pick the
+ * cycles per refinement step by timing full solves of this batch (first
+ * call for a given size list; cached for the process).  Requires
+ * nu1 >= 1, nu1 + nu2 even, warm_start = 0.  stats: host array of nprob or
+ * NULL; cycles = inner cycles run, outer_iters = refinement steps.
+ */
+np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, const double *h, np_bc bc,
+                                   const double *const *rhs, double *const *x, double tol,
+                                   const np_mg_opts *opts, np_mg_stats *stats);
+
+/* Inner cycles chosen by the last autotuning run on this thread and the
+ * wall time it took (0, 0 if the last batched call did not tune). */
+np_status np_last_autotune(int *inner_cycles, double *ms);
+
+/*
  * One scalar advection-diffusion step, the second-order predictor-corrector
  * of Section 2.1 (the combined advection-diffusion filter applied to
  * (T~ + T^n)/2): T~ = T - dt R(T), T <- T - dt R((T~ + T)/2) with
@@ -178,7 +206,8 @@ np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
  * (even number of planes per workgroup in fused kernels, 0 = automatic),
  * "inner_fp32"/"inner_bf16" (default inner cycles per refinement step),
  * "batch" (cycles enqueued before the first host read of the convergence
- * state).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
+ * state), "batched_graphs" and "batched_autotune" (0/1 for the batched
+ * solver).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
  * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */
 np_status np_set_tuning(const char *key, int value);
 int np_get_tuning(const char *key);

@@ -69,6 +69,9 @@ _SIGS = {
     "np_prof_enable": (None, [_I]),
     "np_prof_read": (_I, [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "np_set_tuning": (_I, [ctypes.c_char_p, _I]),
+    "mg_poisson_solve_batched": (_I, [_I, ctypes.POINTER(NpDims), ctypes.POINTER(_D), _I, _P, _P, _D,
+                                      ctypes.POINTER(NpMgOpts), ctypes.POINTER(NpMgStats)]),
+    "np_last_autotune": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_D)]),
     "np_get_tuning": (_I, [ctypes.c_char_p]),
 }
 
@@ -132,6 +135,32 @@ def mg_poisson_solve(rhs, x, h, bc, tol=1e-10, check=True, **opts):
     if check:
         _check("mg_poisson_solve", s)
     return s, st.as_dict()
+
+
+def mg_poisson_solve_batched(rhs, x, h, bc=BC_DIRICHLET0, tol=1e-10, check=True, **opts):
+    """Solves rhs[p] -> x[p] for every p (lists of 2D CUDA tensors); returns
+    (status, list of stats dicts)."""
+    n = len(rhs)
+    if len(x) != n or len(h) != n:
+        raise ValueError("rhs, x and h must have the same length")
+    dims = (NpDims * n)(*[_dims(t) for t in rhs])
+    hs = (ctypes.c_double * n)(*h)
+    rp = (ctypes.c_void_p * n)(*[_dev(t).value for t in rhs])
+    xp = (ctypes.c_void_p * n)(*[_dev(t).value for t in x])
+    o = make_opts(**opts)
+    st = (NpMgStats * n)()
+    s = lib.mg_poisson_solve_batched(n, dims, hs, bc, ctypes.cast(rp, ctypes.c_void_p),
+                                     ctypes.cast(xp, ctypes.c_void_p), tol, ctypes.byref(o), st)
+    if check:
+        _check("mg_poisson_solve_batched", s)
+    return s, [st[i].as_dict() for i in range(n)]
+
+
+def np_last_autotune():
+    inner = ctypes.c_int(0)
+    ms = ctypes.c_double(0.0)
+    lib.np_last_autotune(ctypes.byref(inner), ctypes.byref(ms))
+    return inner.value, ms.value
 
 
 def ns_projection_step(u, v, w, p, h, dt, nu, bc=BC_PERIODIC, tol=1e-10, check=True, **opts):

@@ -1,0 +1,769 @@
+// Batched uneven-size 2D Poisson solves (mixed-precision refinement with
+// batched V-cycles), one launch per level depth across all problems,
+// refinement steps replayed from HIP graphs, per-problem convergence on the
+// device, and an autotuner for the inner cycle count.
+//
+// Depths are counted from the coarsest grid: depth k has 4 * 2^k cells per
+// axis, so every problem present at depth k has the same size there and one
+// launch covers all of them.  Problem p (finest depth L_p) is present at
+// depths 0..L_p; its fields at depth k live in slot slot[k] of that depth's
+// pools.  Depths at or below kTailDepth run inside one workgroup per problem.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "mg_kernels.h"
+#include "mg_level.h"
+#include "np_internal.h"
+
+namespace np {
+
+// Dense inverse of the 4^d coarsest operator (defined in mg.hip).
+bool coarse_inverse_host(int d, int bc, double hc, std::vector<double> &inv);
+
+namespace {
+
+constexpr int kMaxDepth = 12;                 // up to 16384^2
+constexpr int kTailDepth = Tail<2>::LG - 2;   // 64^2 and below run in one workgroup
+constexpr int kHist = 64;                     // residual history kept per problem
+
+struct BProb {
+    int L;                 // finest depth
+    int first_block;       // first refinement block
+    int nblocks;           // refinement blocks
+    int slot[kMaxDepth + 1];
+    double h;              // finest spacing
+    double nf;             // ||f||_2
+};
+
+struct BState {            // per-problem controller
+    int stop, k, pad0, pad1;
+    double hist[kHist];
+};
+
+struct BGlobal {
+    int stop;              // all problems stopped
+    int fixed, maxc, pad;
+    double tol;
+};
+
+template <class S> struct BPtrs {
+    const double *const *f;  // FP64 right-hand sides
+    const double *const *xa; // FP64 iterate read
+    double *const *xb;       // FP64 iterate written
+};
+
+// ---------------------------------------------------------------- kernels
+// Refinement blocks cover kIrCells consecutive cells of one problem.
+struct BBlk {
+    int p;
+    int base;
+};
+
+__device__ __forceinline__ double depth_h(const BProb &P, int k) { return P.h * double(1 << (P.L - k)); }
+
+// ||f||^2 partials per refinement block.
+__global__ __launch_bounds__(kBlock) void kb_fnorm(const double *const *f, const BBlk *__restrict__ blk,
+                                                   const BProb *__restrict__ P, double *__restrict__ partial) {
+    const BBlk b = blk[blockIdx.x];
+    const int lg = P[b.p].L + 2;
+    const int64_t m = int64_t(1) << (2 * lg);
+    const double *fp = f[b.p];
+    double acc = 0.0;
+    for (int u = 0; u < kIrCells / kBlock; ++u) {
+        const int64_t c = int64_t(b.base) + u * kBlock + threadIdx.x;
+        if (c < m) acc += fp[c] * fp[c];
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// nf[p] = sqrt(sum of its partials); zero right-hand sides stop at once.
+__global__ __launch_bounds__(1024) void kb_nf(const double *__restrict__ partial, BProb *__restrict__ P,
+                                              BState *__restrict__ st, int nprob) {
+    for (int p = threadIdx.x; p < nprob; p += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < P[p].nblocks; ++b) s += partial[P[p].first_block + b];
+        P[p].nf = sqrt(s);
+        st[p].stop = s == 0.0 ? kConverged : kRunning;
+        st[p].k = 0;
+        st[p].hist[0] = 0.0;
+    }
+}
+
+// x_p = 0 for every problem (through the pointer table).
+__global__ __launch_bounds__(kBlock) void kb_zero(double *const *x, const BBlk *__restrict__ blk,
+                                                  const BProb *__restrict__ P) {
+    const BBlk b = blk[blockIdx.x];
+    const int64_t m = int64_t(1) << (2 * (P[b.p].L + 2));
+    double *xp = x[b.p];
+    for (int u = 0; u < kIrCells / kBlock; ++u) {
+        const int64_t c = int64_t(b.base) + u * kBlock + threadIdx.x;
+        if (c < m) xp[c] = 0.0;
+    }
+}
+
+// Copies pool -> caller buffer for problems whose last checked iterate is in
+// the pool (odd number of updates).
+__global__ __launch_bounds__(kBlock) void kb_final_copy(const double *const *y, double *const *x,
+                                                        const BBlk *__restrict__ blk, const BProb *__restrict__ P,
+                                                        const BState *__restrict__ st) {
+    const BBlk b = blk[blockIdx.x];
+    if (!(st[b.p].k & 1)) return;
+    const int64_t m = int64_t(1) << (2 * (P[b.p].L + 2));
+    const double *yp = y[b.p];
+    double *xp = x[b.p];
+    for (int u = 0; u < kIrCells / kBlock; ++u) {
+        const int64_t c = int64_t(b.base) + u * kBlock + threadIdx.x;
+        if (c < m) xp[c] = yp[c];
+    }
+}
+
+// FP64 refinement step per problem: x_b = x_a + e (has_e), r = f - A x_b in
+// FP64, r_lo = round(r) into the problem's finest-depth rhs slot, partials.
+template <class SL>
+__global__ __launch_bounds__(kBlock) void kb_ir(BPtrs<SL> ptr, SL *const *epool, SL *const *rpool,
+                                                const BBlk *__restrict__ blk, const BProb *__restrict__ P,
+                                                const BState *__restrict__ st, const BGlobal *__restrict__ g,
+                                                double *__restrict__ partial, int has_e) {
+    const BBlk b = blk[blockIdx.x];
+    if (g->stop || st[b.p].stop) return;
+    const BProb &pp = P[b.p];
+    const int lg = pp.L + 2;
+    const int64_t m = int64_t(1) << (2 * lg);
+    const double inv_h2 = 1.0 / (pp.h * pp.h);
+    const int64_t so = int64_t(pp.slot[pp.L]) * m;
+    const SL *e = epool[pp.L] + so;
+    SL *rlo = rpool[pp.L] + so;
+    const double *x = ptr.xa[b.p], *f = ptr.f[b.p];
+    double *xo = ptr.xb[b.p];
+    struct {
+        const double *x;
+        const SL *e;
+        int he;
+        __device__ double operator()(int64_t q) const { return he ? x[q] + double(St<SL>::ld(e + q)) : x[q]; }
+    } ldx{x, e, has_e};
+    double acc = 0.0;
+    for (int u = 0; u < kIrCells / kBlock; ++u) {
+        const int64_t c = int64_t(b.base) + u * kBlock + threadIdx.x;
+        if (c < m) {
+            int i, j, k;
+            decode<2>(c, lg, i, j, k);
+            const double xc = ldx(c);
+            const double s = nb_sum<2, double>(ldx, c, i, j, k, lg, 0, xc);
+            const double r = f[c] - (4.0 * xc - s) * inv_h2;
+            if (has_e) xo[c] = xc;
+            St<SL>::st(rlo + c, typename St<SL>::C(r));
+            acc += r * r;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Per-problem convergence check after a refinement residual.
+__global__ __launch_bounds__(1024) void kb_check(const double *__restrict__ partial, const BProb *__restrict__ P,
+                                                 BState *__restrict__ st, BGlobal *__restrict__ g, int nprob) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    if (g->stop) return;
+    for (int p = threadIdx.x; p < nprob; p += blockDim.x) {
+        BState &s = st[p];
+        if (s.stop) continue;
+        double sum = 0.0;
+        for (int b = 0; b < P[p].nblocks; ++b) sum += partial[P[p].first_block + b];
+        const int k = s.k;
+        const double rr = sqrt(sum) / P[p].nf;
+        if (k < kHist) s.hist[k] = rr;
+        int stp = kRunning;
+        if (!(rr <= 1.0e300)) stp = kNonFinite;
+        else if (g->fixed > 0) { if (k >= g->fixed) stp = kFixedDone; }
+        else if (rr <= g->tol) stp = kConverged;
+        else if (k >= g->maxc) stp = kMaxCycles;
+        else if (k >= 3 && k < kHist && s.hist[k - 3] < s.hist[k - 2] && s.hist[k - 2] < s.hist[k - 1] &&
+                 s.hist[k - 1] < rr)
+            stp = kDiverged;
+        if (stp != kRunning) s.stop = stp;
+        else { s.k = k + 1; any = 1; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && !any) g->stop = 1;
+}
+
+// One Jacobi sweep at depth k over every problem present there.  first: the
+// first pre-smoothing sweep, which starts from zero unless this depth is the
+// problem's finest and the inner cycle is not the first (cyc > 0).
+template <class S>
+__global__ __launch_bounds__(kBlock) void kb_sweep(const S *__restrict__ F, const S *__restrict__ Xin,
+                                                   S *__restrict__ Xout, const int *__restrict__ slot_prob,
+                                                   const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                   const BGlobal *__restrict__ g, int k, int first, int cyc,
+                                                   double omega) {
+    typedef typename St<S>::C C;
+    const int lg = k + 2;
+    const int64_t m = int64_t(1) << (2 * lg);
+    const int bpp = int((m + kSweepCells - 1) / kSweepCells);
+    const int slot = blockIdx.x / bpp;
+    const int p = slot_prob[slot];
+    if (g->stop || st[p].stop) return;
+    const double h = depth_h(P[p], k);
+    const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / 4.0);
+    const bool zero = first && (k < P[p].L || cyc == 0);
+    const int64_t so = int64_t(slot) * m;
+    const S *f = F + so, *xin = Xin + so;
+    S *xout = Xout + so;
+    const int64_t base = int64_t(blockIdx.x % bpp) * kSweepCells;
+    for (int u = 0; u < kSweepCells / kBlock; ++u) {
+        const int64_t c = base + u * kBlock + threadIdx.x;
+        if (c >= m) continue;
+        const C fc = St<S>::ld(f + c);
+        if (zero) {
+            St<S>::st(xout + c, wdiag * fc);
+        } else {
+            int i, j, kk;
+            decode<2>(c, lg, i, j, kk);
+            const C xc = St<S>::ld(xin + c);
+            const C s = nb_sum<2, C>(Ld<S>{xin}, c, i, j, kk, lg, 0, xc);
+            St<S>::st(xout + c, xc + wdiag * (fc - (C(4) * xc - s) * inv_h2));
+        }
+    }
+}
+
+// Residual at depth k, averaged into depth k-1 (fine blocks of 128 x 2 cells).
+template <class S>
+__global__ __launch_bounds__(kBlock) void kb_restrict(const S *__restrict__ F, const S *__restrict__ X,
+                                                      S *__restrict__ Fc, const int *__restrict__ slot_prob,
+                                                      const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                      const BGlobal *__restrict__ g, int k) {
+    typedef typename St<S>::C C;
+    constexpr int FX = RBlk<2>::FX;
+    __shared__ C r[kBlock];
+    const int lg = k + 2, n = 1 << lg, nc = n >> 1;
+    const int bxn = n / FX, bpp = bxn * nc;
+    const int slot = blockIdx.x / bpp;
+    const int p = slot_prob[slot];
+    if (g->stop || st[p].stop) return;
+    const double h = depth_h(P[p], k);
+    const C inv_h2 = C(1.0 / (h * h));
+    const int64_t m = int64_t(n) * n;
+    const S *f = F + slot * m, *x = X + slot * m;
+    S *fc = Fc + int64_t(P[p].slot[k - 1]) * (m / 4);
+    const int b = blockIdx.x % bpp, tid = threadIdx.x;
+    const int bx = b % bxn, J = b / bxn;
+    const int a = tid % FX, yb = tid / FX;
+    const int i = bx * FX + a, j = 2 * J + yb;
+    const int64_t c = (int64_t(j) << lg) | i;
+    r[tid] = resid_at<2, S>(f, x, c, i, j, 0, lg, 0, inv_h2);
+    __syncthreads();
+    if (tid < FX / 2) {
+        C acc = C(0);
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) acc += r[cy * FX + 2 * tid + cx];
+        St<S>::st(fc + (int64_t(J) * nc + bx * (FX / 2) + tid), acc * C(0.25));
+    }
+}
+
+// x(depth k) += P e(depth k-1), one thread per fine cell.
+template <class S>
+__global__ __launch_bounds__(kBlock) void kb_prolong(const S *__restrict__ Ec, S *__restrict__ X,
+                                                     const int *__restrict__ slot_prob, const BProb *__restrict__ P,
+                                                     const BState *__restrict__ st, const BGlobal *__restrict__ g,
+                                                     int k) {
+    typedef typename St<S>::C C;
+    const int lg = k + 2, lgc = lg - 1, nc = 1 << lgc;
+    const int64_t m = int64_t(1) << (2 * lg);
+    const int bpp = int(m / kBlock);
+    const int slot = blockIdx.x / bpp;
+    const int p = slot_prob[slot];
+    if (g->stop || st[p].stop) return;
+    const int64_t c = int64_t(blockIdx.x % bpp) * kBlock + threadIdx.x;
+    const S *ec = Ec + int64_t(P[p].slot[k - 1]) * (m / 4);
+    S *x = X + slot * m;
+    int i, j, kk;
+    decode<2>(c, lg, i, j, kk);
+    int oi, ni, oj, nj;
+    float si, sj;
+    pro_axis(i, nc, 0, oi, ni, si);
+    pro_axis(j, nc, 0, oj, nj, sj);
+    C s = C(0);
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+            const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(1.0);
+            const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * 1.0f);
+            s += w * (sg * St<S>::ld(ec + ((int64_t(b ? nj : oj) << lgc) | (a ? ni : oi))));
+        }
+    St<S>::st(x + c, St<S>::ld(x + c) + s);
+}
+
+// Depths min(L_p, kTailDepth) .. 0 of every problem, one workgroup each.
+template <class S>
+__global__ __launch_bounds__(Tail<2>::NT) void kb_tail(S *const *Xpool, S *const *Fpool, const double *__restrict__ Minv1,
+                                                       const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                       const BGlobal *__restrict__ g, int cyc, double omega, int nu1,
+                                                       int nu2) {
+    typedef typename St<S>::C C;
+    __shared__ C xs[Tail<2>::levels_sum()];
+    __shared__ C fs[Tail<2>::levels_sum()];
+    __shared__ C ts[Tail<2>::cells(Tail<2>::LG)];
+    const int p = blockIdx.x;
+    if (g->stop || st[p].stop) return;
+    const BProb &pp = P[p];
+    const int t = min(pp.L, kTailDepth);
+    const int64_t m = int64_t(1) << (2 * (t + 2));
+    S *x = Xpool[t] + int64_t(pp.slot[t]) * m;
+    const S *f = Fpool[t] + int64_t(pp.slot[t]) * m;
+    const bool warm = t == pp.L && cyc > 0;
+    const double h = depth_h(pp, t);
+    // Minv1 is the inverse for unit coarsest spacing; the coarsest spacing here
+    // is h * 2^t, and the Dirichlet operator scales as 1/h^2.
+    const double hc = h * double(1 << t);
+    __shared__ double Ms[16 * 16];
+    for (int q = threadIdx.x; q < 256; q += blockDim.x) Ms[q] = Minv1[q] * (hc * hc);
+    __syncthreads();
+    tail_cycle<2, S, Tail<2>::NT>(xs, fs, ts, f, x, warm ? x : nullptr, Ms, t + 2, 0, h, omega, nu1, nu2);
+}
+
+// ----------------------------------------------------------------- plan
+struct Plan {
+    int dev = 0, nprob = 0, K = 0;
+    np_prec prec = NP_FP32;
+    size_t es = 4;
+    std::vector<int> L;                        // finest depth per problem
+    std::vector<std::vector<int>> slots;       // per depth: problems present
+    std::vector<void *> X, F, T;               // per depth pools
+    std::vector<int *> d_slot_prob;            // per depth
+    void **d_Xpool = nullptr, **d_Fpool = nullptr;
+    BProb *d_P = nullptr;
+    BState *d_st = nullptr, *h_st = nullptr;
+    BGlobal *d_g = nullptr, *h_g = nullptr;
+    BBlk *d_blk = nullptr;
+    int nblk = 0;
+    double *d_partial = nullptr;
+    double *d_Minv1 = nullptr;
+    double *ypool = nullptr;                   // second FP64 iterate of every problem
+    const double **d_f = nullptr;
+    double **d_x = nullptr, **d_y = nullptr;
+    std::vector<double *> y;                   // host copy of the pool pointers
+    std::vector<double> h;                     // finest spacing per problem (for graph keys)
+    hipStream_t cap = nullptr;
+    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (kind, inner, nu1, nu2, omega bits)
+    std::mutex mu;
+};
+
+std::mutex g_plan_mu;
+std::map<std::vector<int64_t>, Plan *> g_plans;
+std::map<std::vector<int64_t>, int> g_tuned;  // signature -> inner cycles chosen by the autotuner
+
+np_status dmalloc(void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        set_error("hipMalloc of %zu bytes failed", bytes);
+        return NP_ENOMEM;
+    }
+    return NP_OK;
+}
+
+void free_plan(Plan *B) {
+    for (auto &kv : B->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto *p : B->X) (void)hipFree(p);
+    for (auto *p : B->F) (void)hipFree(p);
+    for (auto *p : B->T) (void)hipFree(p);
+    for (auto *p : B->d_slot_prob) (void)hipFree(p);
+    void *q[] = {B->d_Xpool, B->d_Fpool, B->d_P, B->d_st, B->d_g, B->d_blk, B->d_partial, B->d_Minv1,
+                 B->ypool, (void *)B->d_f, B->d_x, B->d_y};
+    for (auto *p : q) if (p) (void)hipFree(p);
+    if (B->h_st) (void)hipHostFree(B->h_st);
+    if (B->h_g) (void)hipHostFree(B->h_g);
+    if (B->cap) (void)hipStreamDestroy(B->cap);
+    delete B;
+}
+
+template <class T> np_status upload(T **d, const std::vector<T> &h) {
+    NP_TRY(dmalloc((void **)d, sizeof(T) * std::max<size_t>(1, h.size())));
+    NP_HIP_TRY(hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return NP_OK;
+}
+
+np_status build_plan(const std::vector<int> &lgs, const std::vector<double> &hs, np_prec prec, Plan *B) {
+    const int np_ = int(lgs.size());
+    B->nprob = np_;
+    B->prec = prec;
+    B->es = prec_bytes(prec);
+    B->h = hs;
+    B->L.resize(np_);
+    int K = 0;
+    for (int p = 0; p < np_; ++p) {
+        B->L[p] = lgs[p] - 2;
+        K = std::max(K, B->L[p]);
+    }
+    B->K = K;
+    B->slots.assign(K + 1, {});
+    std::vector<BProb> P(np_);
+    for (int p = 0; p < np_; ++p) {
+        std::memset(&P[p], 0, sizeof(BProb));
+        P[p].L = B->L[p];
+        P[p].h = hs[p];
+        for (int k = 0; k <= kMaxDepth; ++k) P[p].slot[k] = -1;
+        for (int k = 0; k <= B->L[p]; ++k) {
+            P[p].slot[k] = int(B->slots[k].size());
+            B->slots[k].push_back(p);
+        }
+    }
+    B->X.assign(K + 1, nullptr);
+    B->F.assign(K + 1, nullptr);
+    B->T.assign(K + 1, nullptr);
+    B->d_slot_prob.assign(K + 1, nullptr);
+    for (int k = 0; k <= K; ++k) {
+        const size_t bytes = B->slots[k].size() * (size_t(1) << (2 * (k + 2))) * B->es;
+        NP_TRY(dmalloc(&B->X[k], bytes));
+        NP_TRY(dmalloc(&B->F[k], bytes));
+        NP_TRY(dmalloc(&B->T[k], bytes));
+        NP_TRY(upload(&B->d_slot_prob[k], B->slots[k]));
+    }
+    // refinement blocks
+    std::vector<BBlk> blk;
+    for (int p = 0; p < np_; ++p) {
+        const int64_t m = int64_t(1) << (2 * lgs[p]);
+        P[p].first_block = int(blk.size());
+        for (int64_t b = 0; b < m; b += kIrCells) blk.push_back(BBlk{p, int(b)});
+        P[p].nblocks = int(blk.size()) - P[p].first_block;
+    }
+    B->nblk = int(blk.size());
+    NP_TRY(upload(&B->d_blk, blk));
+    NP_TRY(upload(&B->d_P, P));
+    NP_TRY(upload(&B->d_Xpool, B->X));
+    NP_TRY(upload(&B->d_Fpool, B->F));
+    NP_TRY(dmalloc((void **)&B->d_partial, sizeof(double) * B->nblk));
+    NP_TRY(dmalloc((void **)&B->d_st, sizeof(BState) * np_));
+    NP_TRY(dmalloc((void **)&B->d_g, sizeof(BGlobal)));
+    if (hipHostMalloc((void **)&B->h_st, sizeof(BState) * np_, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&B->h_g, sizeof(BGlobal), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipHostMalloc failed");
+        return NP_ENOMEM;
+    }
+    std::vector<double> inv;
+    if (!coarse_inverse_host(2, NP_BC_DIRICHLET0, 1.0, inv)) {
+        set_error("singular coarsest operator");
+        return NP_EINVAL;
+    }
+    NP_TRY(upload(&B->d_Minv1, inv));
+    int64_t ytot = 0;
+    for (int p = 0; p < np_; ++p) ytot += int64_t(1) << (2 * lgs[p]);
+    NP_TRY(dmalloc((void **)&B->ypool, sizeof(double) * ytot));
+    B->y.resize(np_);
+    int64_t o = 0;
+    for (int p = 0; p < np_; ++p) {
+        B->y[p] = B->ypool + o;
+        o += int64_t(1) << (2 * lgs[p]);
+    }
+    NP_TRY(upload(&B->d_y, B->y));
+    NP_TRY(dmalloc((void **)&B->d_f, sizeof(double *) * np_));
+    NP_TRY(dmalloc((void **)&B->d_x, sizeof(double *) * np_));
+    NP_HIP_TRY(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    return NP_OK;
+}
+
+struct BOpts {
+    int nu1, nu2;
+    double omega;
+};
+
+// One refinement step: kind 0 (x_a = caller x, no correction yet), 1 (x -> y),
+// 2 (y -> x); then `inner` batched V-cycles on the rounded residuals.
+template <class S>
+np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t s) {
+    BPtrs<S> ptr;
+    ptr.f = B->d_f;
+    ptr.xa = kind == 2 ? (const double *const *)B->d_y : (const double *const *)B->d_x;
+    ptr.xb = kind == 1 ? B->d_y : B->d_x;
+    S *const *Xp = (S *const *)B->d_Xpool, *const *Fp = (S *const *)B->d_Fpool;
+    hipLaunchKernelGGL((kb_ir<S>), dim3(B->nblk), dim3(kBlock), 0, s, ptr, Xp, Fp, B->d_blk, B->d_P, B->d_st,
+                       B->d_g, B->d_partial, kind == 0 ? 0 : 1);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kb_check, dim3(1), dim3(1024), 0, s, B->d_partial, B->d_P, B->d_st, B->d_g, B->nprob);
+    NP_LAUNCH_CHECK();
+    for (int c = 0; c < inner; ++c) {
+        for (int k = B->K; k > kTailDepth; --k) {
+            const unsigned nsl = unsigned(B->slots[k].size());
+            const int64_t m = int64_t(1) << (2 * (k + 2));
+            S *cur = (S *)B->X[k], *oth = (S *)B->T[k];
+            const S *F = (const S *)B->F[k];
+            for (int it = 0; it < o.nu1; ++it) {
+                hipLaunchKernelGGL((kb_sweep<S>), dim3(unsigned(nsl * ((m + kSweepCells - 1) / kSweepCells))),
+                                   dim3(kBlock), 0, s, F, cur, oth, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k,
+                                   it == 0 ? 1 : 0, c, o.omega);
+                NP_LAUNCH_CHECK();
+                std::swap(cur, oth);
+            }
+            const int n = 1 << (k + 2);
+            hipLaunchKernelGGL((kb_restrict<S>), dim3(unsigned(nsl * (n / RBlk<2>::FX) * (n / 2))), dim3(kBlock), 0, s,
+                               F, cur, (S *)B->F[k - 1], B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
+            NP_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL((kb_tail<S>), dim3(B->nprob), dim3(Tail<2>::NT), 0, s, Xp, Fp, B->d_Minv1, B->d_P,
+                           B->d_st, B->d_g, c, o.omega, o.nu1, o.nu2);
+        NP_LAUNCH_CHECK();
+        for (int k = kTailDepth + 1; k <= B->K; ++k) {
+            const unsigned nsl = unsigned(B->slots[k].size());
+            const int64_t m = int64_t(1) << (2 * (k + 2));
+            // after an odd number of pre-sweeps the iterate sits in T
+            S *cur = (o.nu1 & 1) ? (S *)B->T[k] : (S *)B->X[k];
+            S *oth = (o.nu1 & 1) ? (S *)B->X[k] : (S *)B->T[k];
+            hipLaunchKernelGGL((kb_prolong<S>), dim3(unsigned(nsl * (m / kBlock))), dim3(kBlock), 0, s,
+                               (const S *)B->X[k - 1], cur, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
+            NP_LAUNCH_CHECK();
+            for (int it = 0; it < o.nu2; ++it) {
+                hipLaunchKernelGGL((kb_sweep<S>), dim3(unsigned(nsl * ((m + kSweepCells - 1) / kSweepCells))),
+                                   dim3(kBlock), 0, s, (const S *)B->F[k], cur, oth, B->d_slot_prob[k], B->d_P,
+                                   B->d_st, B->d_g, k, 0, c, o.omega);
+                NP_LAUNCH_CHECK();
+                std::swap(cur, oth);
+            }
+        }
+    }
+    return NP_OK;
+}
+
+template <class S>
+np_status run_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t s) {
+    if (!g_batched_graphs) return enqueue_step<S>(B, kind, inner, o, s);
+    int64_t ob;
+    std::memcpy(&ob, &o.omega, sizeof ob);
+    const auto key = std::make_tuple(kind, inner, o.nu1, o.nu2, int(ob ^ (ob >> 32)));
+    auto it = B->graphs.find(key);
+    if (it == B->graphs.end()) {
+        NP_HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+        np_status st = enqueue_step<S>(B, kind, inner, o, B->cap);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(B->cap, &graph);
+        if (st != NP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(e));
+            return NP_EHIP;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            set_error("graph instantiation failed: %s", hipGetErrorString(e));
+            return NP_EHIP;
+        }
+        it = B->graphs.emplace(key, exec).first;
+    }
+    NP_HIP_TRY(hipGraphLaunch(it->second, s));
+    return NP_OK;
+}
+
+// Full batched solve with a given inner cycle count.  Caller pointers are in
+// the plan's pointer tables already.
+template <class S>
+np_status batched_run(Plan *B, int inner, const BOpts &o, const np_mg_opts &mo, double tol, hipStream_t s) {
+    BGlobal *g = B->h_g;
+    std::memset(g, 0, sizeof *g);
+    g->fixed = mo.fixed_cycles;
+    g->maxc = mo.max_cycles;
+    g->tol = tol;
+    NP_HIP_TRY(hipMemcpyAsync(B->d_g, g, sizeof *g, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(kb_zero, dim3(B->nblk), dim3(kBlock), 0, s, B->d_x, B->d_blk, B->d_P);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kb_fnorm, dim3(B->nblk), dim3(kBlock), 0, s, (const double *const *)B->d_f, B->d_blk, B->d_P,
+                       B->d_partial);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kb_nf, dim3(1), dim3(1024), 0, s, B->d_partial, B->d_P, B->d_st, B->nprob);
+    NP_LAUNCH_CHECK();
+    NP_TRY(run_step<S>(B, 0, inner, o, s));
+    int launched = 1, batch = mo.fixed_cycles > 0 ? mo.fixed_cycles : 4;
+    for (;;) {
+        for (int b = 0; b < batch; ++b, ++launched) NP_TRY(run_step<S>(B, (launched & 1) ? 1 : 2, inner, o, s));
+        NP_HIP_TRY(hipMemcpyAsync(B->h_g, B->d_g, sizeof(BGlobal), hipMemcpyDeviceToHost, s));
+        NP_HIP_TRY(hipStreamSynchronize(s));
+        if (B->h_g->stop) break;
+        batch = 2;
+        if (launched > 4 * (mo.max_cycles + 2) + 16) {
+            set_error("batched solve did not stop");
+            return NP_ENOCONV;
+        }
+    }
+    hipLaunchKernelGGL(kb_final_copy, dim3(B->nblk), dim3(kBlock), 0, s, (const double *const *)B->d_y, B->d_x,
+                       B->d_blk, B->d_P, B->d_st);
+    NP_LAUNCH_CHECK();
+    NP_HIP_TRY(hipMemcpyAsync(B->h_st, B->d_st, sizeof(BState) * B->nprob, hipMemcpyDeviceToHost, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return NP_OK;
+}
+
+}  // namespace
+
+int g_batched_graphs = 1;
+int g_batched_autotune = 1;
+static thread_local int g_last_tune_inner = 0;
+static thread_local double g_last_tune_ms = 0.0;
+
+void release_batched_cache() {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto &kv : g_plans) free_plan(kv.second);
+    g_plans.clear();
+}
+
+}  // namespace np
+
+using namespace np;
+
+extern "C" np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, const double *h, np_bc bc,
+                                              const double *const *rhs, double *const *x, double tol,
+                                              const np_mg_opts *opts, np_mg_stats *stats) {
+    clear_error();
+    if (nprob <= 0 || nprob > 65536 || !dims || !h || !rhs || !x) {
+        set_error("bad batch arguments");
+        return NP_EINVAL;
+    }
+    if (bc != NP_BC_DIRICHLET0) { set_error("batched solves support zero Dirichlet boundaries only"); return NP_EINVAL; }
+    np_mg_opts o;
+    np_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.smooth_prec != NP_FP32 && o.smooth_prec != NP_FP64) {
+        set_error("batched solves run FP32 (or FP64) inner cycles");
+        return NP_EINVAL;
+    }
+    if (o.warm_start != 0) { set_error("batched solves start from zero"); return NP_EINVAL; }
+    if (o.nu1 < 1 || o.nu2 < 0 || ((o.nu1 + o.nu2) & 1) || o.nu1 > 16 || o.nu2 > 16 ||
+        !(o.omega > 0.0 && o.omega < 2.0) || o.inner_cycles < 0 || o.inner_cycles > 16 || o.max_cycles < 0 ||
+        o.fixed_cycles < 0 || o.max_cycles > 100000 || o.fixed_cycles > 100000) {
+        set_error("bad cycle settings (batched: nu1 >= 1, nu1 + nu2 even)");
+        return NP_EINVAL;
+    }
+    if (o.fixed_cycles <= 0 && !(tol > 0.0)) { set_error("tol must be positive"); return NP_EINVAL; }
+    std::vector<int> lgs(nprob);
+    std::vector<double> hs(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        if (dims[p].ndim != 2 || dims[p].n[0] != dims[p].n[1] || !is_pow2(dims[p].n[0]) || dims[p].n[0] < 4 ||
+            dims[p].n[0] > (int64_t(4) << kMaxDepth)) {
+            set_error("problem %d: batched grids are 2D, n x n, n a power of two in [4, %d]", p, 4 << kMaxDepth);
+            return NP_EINVAL;
+        }
+        if (!(h[p] > 0.0) || !rhs[p] || !x[p]) { set_error("problem %d: bad h or null pointer", p); return NP_EINVAL; }
+        lgs[p] = ilog2(dims[p].n[0]);
+        hs[p] = h[p];
+    }
+    int dev = 0;
+    NP_HIP_TRY(hipGetDevice(&dev));
+    std::vector<int64_t> key;
+    key.push_back(dev);
+    key.push_back(o.smooth_prec);
+    for (int p = 0; p < nprob; ++p) {
+        key.push_back(lgs[p]);
+        int64_t hb;
+        std::memcpy(&hb, &hs[p], sizeof hb);
+        key.push_back(hb);
+    }
+    Plan *B = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) {
+            B = it->second;
+        } else {
+            B = new Plan;
+            B->dev = dev;
+            np_status st = build_plan(lgs, hs, o.smooth_prec, B);
+            if (st != NP_OK) {
+                free_plan(B);
+                return st;
+            }
+            g_plans[key] = B;
+        }
+    }
+    std::lock_guard<std::mutex> lk(B->mu);
+    hipStream_t s = (hipStream_t)o.stream;
+    NP_HIP_TRY(hipMemcpyAsync(B->d_f, rhs, sizeof(double *) * nprob, hipMemcpyHostToDevice, s));
+    NP_HIP_TRY(hipMemcpyAsync(B->d_x, x, sizeof(double *) * nprob, hipMemcpyHostToDevice, s));
+    const BOpts bo{o.nu1, o.nu2, o.omega};
+    auto run = [&](int inner) -> np_status {
+        return o.smooth_prec == NP_FP32 ? batched_run<float>(B, inner, bo, o, tol, s)
+                                        : batched_run<double>(B, inner, bo, o, tol, s);
+    };
+    int inner = o.inner_cycles;
+    g_last_tune_inner = 0;
+    g_last_tune_ms = 0.0;
+    if (inner == 0) {
+        // autotuner: inner cycles per refinement step, chosen by timing full
+        // solves of this batch; cached per sorted size list and precision
+        std::vector<int64_t> sig;
+        sig.push_back(o.smooth_prec);
+        std::vector<int> sl(lgs);
+        std::sort(sl.begin(), sl.end());
+        for (int v : sl) sig.push_back(v);
+        {
+            std::lock_guard<std::mutex> lk2(g_plan_mu);
+            auto it = g_tuned.find(sig);
+            if (it != g_tuned.end()) inner = it->second;
+        }
+        if (inner == 0 && g_batched_autotune && o.fixed_cycles == 0) {
+            const auto t0 = std::chrono::steady_clock::now();
+            double best = 1e300;
+            int best_inner = 2;
+            hipEvent_t e0, e1;
+            NP_HIP_TRY(hipEventCreate(&e0));
+            NP_HIP_TRY(hipEventCreate(&e1));
+            for (int cand = 1; cand <= 4; ++cand) {
+                NP_TRY(run(cand));  // first run of a candidate captures its graphs
+                NP_HIP_TRY(hipEventRecord(e0, s));
+                NP_TRY(run(cand));
+                NP_HIP_TRY(hipEventRecord(e1, s));
+                NP_HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                NP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                bool ok = true;
+                for (int p = 0; p < nprob; ++p) ok = ok && B->h_st[p].stop == kConverged;
+                if (ok && ms < best) { best = ms; best_inner = cand; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            inner = best_inner;
+            {
+                std::lock_guard<std::mutex> lk2(g_plan_mu);
+                g_tuned[sig] = inner;
+            }
+            g_last_tune_inner = inner;
+            g_last_tune_ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (inner == 0) inner = o.smooth_prec == NP_FP32 ? 3 : 1;
+    }
+    NP_TRY(run(inner));
+    np_status st = NP_OK;
+    for (int p = 0; p < nprob; ++p) {
+        const BState &b = B->h_st[p];
+        if (stats) {
+            np_mg_stats &q = stats[p];
+            std::memset(&q, 0, sizeof q);
+            q.outer_iters = b.k;
+            q.cycles = b.k * inner;
+            const int n = std::min(b.k + 1, kHist);
+            for (int i = 0; i < n; ++i) q.hist[i] = b.hist[i];
+            q.rel_res = b.hist[std::min(b.k, kHist - 1)];
+            q.rho_est = (b.k > 0 && q.hist[0] > 0.0 && q.rel_res > 0.0) ? std::pow(q.rel_res / q.hist[0], 1.0 / b.k) : 0.0;
+        }
+        if (b.stop == kNonFinite) st = NP_ENAN;
+        else if ((b.stop == kMaxCycles || b.stop == kDiverged) && st == NP_OK) st = NP_ENOCONV;
+    }
+    if (st == NP_ENAN) set_error("non-finite residual in a batched problem");
+    else if (st == NP_ENOCONV) set_error("a batched problem did not reach the tolerance");
+    return st;
+}
+
+extern "C" np_status np_last_autotune(int *inner_cycles, double *ms) {
+    if (inner_cycles) *inner_cycles = g_last_tune_inner;
+    if (ms) *ms = g_last_tune_ms;
+    return NP_OK;
+}

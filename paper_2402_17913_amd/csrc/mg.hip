@@ -319,6 +319,8 @@ static bool coarse_inverse(int d, int bc, double hc, std::vector<double> &inv) {
     return true;
 }
 
+bool coarse_inverse_host(int d, int bc, double hc, std::vector<double> &inv) { return coarse_inverse(d, bc, hc, inv); }
+
 static np_status ensure_coarse(Hier *H, double h, hipStream_t s) {
     if (H->Minv_h == h) return NP_OK;
     std::vector<double> inv;
@@ -904,6 +906,7 @@ extern "C" void np_release_all(void) {
     (void)hipDeviceSynchronize();
     release_mg_cache();
     release_ns_cache();
+    release_batched_cache();
 }
 
 extern "C" void np_prof_enable(int mask) {
@@ -942,6 +945,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"bz2", &g_tune.bz2, 0, 1 << 14},       {"bz3", &g_tune.bz3, 0, 1 << 12},
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},
+        {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
     };
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
@@ -974,6 +978,8 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "inner_fp32")) return g_tune.inner_fp32;
     if (!std::strcmp(key, "inner_bf16")) return g_tune.inner_bf16;
     if (!std::strcmp(key, "batch")) return g_tune.batch;
+    if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
+    if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     return -1;
 }
 

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_sum(const S *__restrict__ v, int64_t
 }
 
 // out[slot] = sum of partial[0..np) in a fixed order (sqrt when root).
-__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int np,
+static __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int np,
                                                      double *__restrict__ out, int root) {
     double acc = 0.0;
     for (int b = threadIdx.x; b < np; b += blockDim.x) acc += partial[b];
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
 }
 
 // v[c] -= sum[0] * scale (mean removal with the sum left on the device).
-__global__ __launch_bounds__(kBlock) void k_sub_scaled(double *__restrict__ v, int64_t m,
+static __global__ __launch_bounds__(kBlock) void k_sub_scaled(double *__restrict__ v, int64_t m,
                                                        const double *__restrict__ sum, double scale) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c < m) v[c] -= sum[0] * scale;
@@ -293,7 +293,7 @@ enum StopReason { kRunning = 0, kConverged = 1, kFixedDone = 2, kMaxCycles = 3, 
 // Convergence check before cycle k: rr = sqrt(sum of partials)/||f|| (fixed
 // summation order), recorded in hist[k]; then the stop rule: non-finite,
 // fixed count reached, rr <= tol, k >= max, or three consecutive increases.
-__global__ __launch_bounds__(kBlock) void k_check(const double *__restrict__ partial, int np,
+static __global__ __launch_bounds__(kBlock) void k_check(const double *__restrict__ partial, int np,
                                                   Ctl *__restrict__ c) {
     if (c->stop) return;
     // four interleaved accumulators (fixed assignment): deterministic

@@ -104,26 +104,28 @@ template <int D, class C> struct LdsLd {
     __device__ __forceinline__ C operator()(int64_t q) const { return p[q]; }
 };
 
-// V(nu1, nu2) cycle from a zero iterate on levels lg_t .. 2 in one workgroup.
-// f_t: right-hand side of level lg_t (global); x_t: result (global).  h_t:
-// spacing of level lg_t.  nu1 >= 1.
-template <int D, class S>
-__global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t, S *__restrict__ x_t,
-                                               const double *__restrict__ Minv, int lg_t, int bc, double h_t,
-                                               double omega, int nu1, int nu2, const int *stop) {
+// V(nu1, nu2) cycle on levels lg_t .. 2 in one workgroup, every level in LDS
+// (xs, fs: all levels, finest first; ts: scratch of the finest level).
+// f_t: right-hand side of level lg_t (global); x_t: result (global); x_in:
+// starting iterate of level lg_t (global), or null for a zero iterate (then
+// the first sweep is w f).  Coarser levels always start from zero.
+// h_t: spacing of level lg_t.  nu1 >= 1 when x_in is null.
+template <int D, class S, int NT>
+__device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>::C *fs, typename St<S>::C *ts,
+                                           const S *__restrict__ f_t, S *__restrict__ x_t,
+                                           const S *__restrict__ x_in, const double *__restrict__ Minv, int lg_t,
+                                           int bc, double h_t, double omega, int nu1, int nu2) {
     typedef typename St<S>::C C;
-    constexpr int NT = Tail<D>::NT;
-    __shared__ C xs[Tail<D>::levels_sum()];
-    __shared__ C fs[Tail<D>::levels_sum()];
-    __shared__ C ts[Tail<D>::cells(Tail<D>::LG)];
-    if (stop && *stop) return;
     const int tid = threadIdx.x;
     // level l starts after the finer levels lg_t .. l+1 (geometric sum)
     auto off = [&](int l) -> int64_t {
         return ((int64_t(1) << (D * (lg_t + 1))) - (int64_t(1) << (D * (l + 1)))) / ((int64_t(1) << D) - 1);
     };
     const int64_t mt = int64_t(1) << (D * lg_t);
-    for (int64_t c = tid; c < mt; c += NT) fs[off(lg_t) + c] = St<S>::ld(f_t + c);
+    for (int64_t c = tid; c < mt; c += NT) {
+        fs[off(lg_t) + c] = St<S>::ld(f_t + c);
+        if (x_in) xs[off(lg_t) + c] = St<S>::ld(x_in + c);
+    }
     __syncthreads();
     double h = h_t;
     // ------------------------------------------------------------- down
@@ -131,10 +133,14 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t,
         const int64_t m = int64_t(1) << (D * lg);
         C *X = xs + off(lg), *F = fs + off(lg);
         const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
-        // first sweep from zero, then the rest ping-pong through ts
-        for (int64_t c = tid; c < m; c += NT) X[c] = wdiag * F[c];
-        __syncthreads();
-        for (int it = 1; it < nu1; ++it) {
+        int it0 = 0;
+        if (!(x_in && lg == lg_t)) {
+            // first sweep from zero
+            for (int64_t c = tid; c < m; c += NT) X[c] = wdiag * F[c];
+            __syncthreads();
+            it0 = 1;
+        }
+        for (int it = it0; it < nu1; ++it) {
             for (int64_t c = tid; c < m; c += NT) {
                 int i, j, k;
                 decode<D>(c, lg, i, j, k);
@@ -171,7 +177,24 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t,
     {
         constexpr int m = D == 3 ? 64 : 16;
         C *X = xs + off(2), *F = fs + off(2);
-        if (tid < m) {
+        if (lg_t == 2) {
+            // the whole grid is the coarsest: x <- x + Minv (f - A x)
+            __shared__ double rr[m];
+            if (tid < m) {
+                int i, j, k;
+                decode<D>(tid, 2, i, j, k);
+                const double xc = x_in ? double(X[tid]) : 0.0;
+                double s = 0.0;
+                if (x_in) s = double(nb_sum<D, C>(LdsLd<D, C>{X}, tid, i, j, k, 2, bc, X[tid]));
+                rr[tid] = double(F[tid]) - (double(2 * D) * xc - s) / (h * h);
+            }
+            __syncthreads();
+            if (tid < m) {
+                double acc = 0.0;
+                for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * rr[q];
+                X[tid] = C((x_in ? double(X[tid]) : 0.0) + acc);
+            }
+        } else if (tid < m) {
             double acc = 0.0;
             for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * double(F[q]);
             X[tid] = C(0.0 + acc);
@@ -220,6 +243,20 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t,
         }
     }
     for (int64_t c = tid; c < mt; c += NT) St<S>::st(x_t + c, xs[off(lg_t) + c]);
+}
+
+// One-workgroup V-cycle from a zero iterate on levels lg_t .. 2.
+template <int D, class S>
+__global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t, S *__restrict__ x_t,
+                                                      const double *__restrict__ Minv, int lg_t, int bc,
+                                                      double h_t, double omega, int nu1, int nu2,
+                                                      const int *stop) {
+    typedef typename St<S>::C C;
+    __shared__ C xs[Tail<D>::levels_sum()];
+    __shared__ C fs[Tail<D>::levels_sum()];
+    __shared__ C ts[Tail<D>::cells(Tail<D>::LG)];
+    if (stop && *stop) return;
+    tail_cycle<D, S, Tail<D>::NT>(xs, fs, ts, f_t, x_t, nullptr, Minv, lg_t, bc, h_t, omega, nu1, nu2);
 }
 
 }  // namespace np

@@ -129,5 +129,8 @@ int check_grid(const np_dims &dims);
 // Workspace cache lifetime.
 void release_mg_cache();
 void release_ns_cache();
+void release_batched_cache();
+extern int g_batched_graphs;
+extern int g_batched_autotune;
 
 }  // namespace np

@@ -1,0 +1,106 @@
+"""GPU parity of the batched uneven-size solver."""
+import numpy as np
+import pytest
+
+from paper_2402_17913_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DIR = 0
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_17913_amd import binding
+    return binding
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+SIZES = [4, 8, 16, 32, 64, 64, 128, 256, 128, 512, 32]
+
+
+def make(sizes, seed0=1000):
+    f = [inputs.sine_rhs(2, n, seed=seed0 + i)["f"] for i, n in enumerate(sizes)]
+    return f, [1.0 / n for n in sizes]
+
+
+def test_batched_fp64_matches_oracle_cycle_for_cycle(B, orc):
+    """FP64 inner cycles, one per refinement step: after k steps each problem equals k
+    oracle V-cycles (the refinement is an exact rewriting of the cycle in FP64)."""
+    f, h = make(SIZES)
+    k = 4
+    x = [dev(np.zeros_like(a)) for a in f]
+    st, stats = B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=B.FP64,
+                                           inner_cycles=1, fixed_cycles=k)
+    for i, (a, hh) in enumerate(zip(f, h)):
+        ref = orc.mg_solve(a, hh, DIR, fixed_cycles=k)
+        assert stats[i]["outer_iters"] == k
+        assert rel(host(x[i]), ref.x) < 1e-12, (SIZES[i], rel(host(x[i]), ref.x))
+        assert np.max(np.abs(np.array(stats[i]["hist"][:k + 1]) - ref.hist)) < 1e-12
+
+
+def test_batched_fp32_reaches_tolerance_and_matches_solo(B, orc):
+    f, h = make(SIZES, seed0=2000)
+    x = [dev(np.zeros_like(a)) for a in f]
+    st, stats = B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=B.FP32,
+                                           inner_cycles=2)
+    for i, (a, hh) in enumerate(zip(f, h)):
+        xi = host(x[i])
+        rr = orc.rel_res(a, xi, hh, DIR)
+        assert rr <= 1e-10, (SIZES[i], rr)
+        assert abs(rr - stats[i]["rel_res"]) <= 1e-3 * rr + 1e-16
+        xs = dev(np.zeros_like(a))
+        st2, s2 = B.mg_poisson_solve(dev(a), xs, hh, DIR, smooth_prec=B.FP32, inner_cycles=2)
+        assert abs(s2["outer_iters"] - stats[i]["outer_iters"]) <= 1
+        assert rel(xi, host(xs)) < 1e-9
+
+
+def test_batched_zero_rhs_and_repeat_calls(B, orc):
+    import torch
+    f, h = make([64, 128, 32], seed0=3000)
+    f[1] = np.zeros_like(f[1])
+    for rep in range(2):
+        x = [dev(np.full_like(a, 7.0)) for a in f]
+        st, stats = B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=B.FP32,
+                                               inner_cycles=3)
+        assert torch.all(x[1] == 0) and stats[1]["outer_iters"] == 0
+        for i in (0, 2):
+            assert orc.rel_res(f[i], host(x[i]), h[i], DIR) <= 1e-10
+
+
+def test_batched_autotuner(B, orc):
+    f, h = make([64, 128, 256, 128], seed0=4000)
+    fd = [dev(a) for a in f]
+    x = [dev(np.zeros_like(a)) for a in f]
+    B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
+    inner, ms = B.np_last_autotune()
+    assert 1 <= inner <= 4 and ms > 0
+    for i in range(len(f)):
+        assert orc.rel_res(f[i], host(x[i]), h[i], DIR) <= 1e-10
+    B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
+    assert B.np_last_autotune() == (0, 0.0)  # cached
+
+
+def test_batched_rejects_bad_input(B):
+    import torch
+    a = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.NeuphysError):
+        B.mg_poisson_solve_batched([a], [a.clone()], [1 / 16], bc=B.BC_PERIODIC)
+    b = torch.zeros((12, 12), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.NeuphysError):
+        B.mg_poisson_solve_batched([b], [b.clone()], [1 / 12])
+    with pytest.raises(B.NeuphysError):
+        B.mg_poisson_solve_batched([a], [a.clone()], [1 / 16], nu1=2, nu2=1)
