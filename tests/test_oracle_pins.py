@@ -494,3 +494,67 @@ def test_uniform_flow_is_steady(orc):
     q1, p1, cyc, rr, st = orc.ns_step(q, p, 2 * np.pi / n, 0.05, 0.01)
     assert cyc == 0 and np.all(p1 == 0)
     assert np.max(np.abs(q1[0] - 0.4)) < 1e-15 and np.max(np.abs(q1[1] + 0.9)) < 1e-15
+
+
+# ----------------------------------------- learned warm-start network (oracle)
+def test_cnn_oracle_gradients_match_finite_differences():
+    """Analytic backward of the FP64 network against central finite differences on a
+    tiny net (8^3, 2 levels); every layer's weights and biases are probed."""
+    from oracle import cnn
+    levels, n = 2, 8
+    rng = np.random.default_rng(5)
+    params = cnn.init_params(levels, seed=3)
+    params = [(W, rng.standard_normal(16) * 0.1) for W, b in params]
+    params[-1] = (params[-1][0], np.r_[0.05, np.zeros(15)])
+    f = rng.standard_normal((n, n, n))
+    target = rng.standard_normal((n, n, n))
+    loss, grads = cnn.loss_and_grads(params, f, target, levels)
+    eps = 1e-6
+    for k in range(len(params)):
+        W, b = params[k]
+        for idx in [(0, 0, 0), (13, 3, 0), (26, 0, 5)]:
+            if k == 0 and idx[2] != 0:
+                idx = (idx[0], idx[1], 0)
+            if k == len(params) - 1:
+                idx = (idx[0], 0, idx[2])
+            Wp = W.copy(); Wp[idx] += eps
+            Wm = W.copy(); Wm[idx] -= eps
+            pp = list(params); pp[k] = (Wp, b)
+            pm = list(params); pm[k] = (Wm, b)
+            fd = (np.mean((cnn.forward(pp, f, levels) - target) ** 2)
+                  - np.mean((cnn.forward(pm, f, levels) - target) ** 2)) / (2 * eps)
+            g = grads[k][0][idx]
+            assert abs(fd - g) <= 1e-6 * max(abs(fd), 1e-3), (k, idx, fd, g)
+        bp = b.copy(); bp[0] += eps
+        bm = b.copy(); bm[0] -= eps
+        pp = list(params); pp[k] = (W, bp)
+        pm = list(params); pm[k] = (W, bm)
+        fd = (np.mean((cnn.forward(pp, f, levels) - target) ** 2)
+              - np.mean((cnn.forward(pm, f, levels) - target) ** 2)) / (2 * eps)
+        assert abs(fd - grads[k][1][0]) <= 1e-6 * max(abs(fd), 1e-3), (k, fd, grads[k][1][0])
+
+
+def test_cnn_oracle_layers_closed_forms():
+    """Identity filter reproduces the input; a one-hot tap shifts by the tap offset
+    (orientation of every axis); up is exact on constants; pool of up is the
+    coarse field smoothed by the 1D weights (1/8, 3/4, 1/8) per axis."""
+    from oracle import cnn
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((16, 8, 8, 8))
+    W = np.zeros((27, 16, 16))
+    W[13] = np.eye(16)
+    assert np.allclose(cnn.conv(X, W, np.zeros(16)), X)
+    W = np.zeros((27, 16, 16))
+    t = cnn.OFFS.index((1, -1, 1))  # dz = 1, dy = -1, dx = 1
+    W[t] = np.eye(16)
+    Y = cnn.conv(X, W, np.zeros(16))
+    assert np.allclose(Y[:, 2, 5, 3], X[:, 3, 4, 4])
+    assert np.allclose(cnn.up(np.full((2, 4, 4, 4), 3.0)), 3.0)
+    Xc = rng.standard_normal((1, 8, 8, 8))
+    s = np.array([1 / 8, 3 / 4, 1 / 8])
+    ref = Xc.copy() * 0
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                ref += s[dz + 1] * s[dy + 1] * s[dx + 1] * np.roll(Xc, (-dz, -dy, -dx), axis=(1, 2, 3))
+    assert np.allclose(cnn.pool(cnn.up(Xc)), ref)
