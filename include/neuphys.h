@@ -66,14 +66,15 @@ typedef struct {
     int fixed_cycles;     /* > 0: run exactly this many cycles / outer steps and ignore tol */
     np_prec smooth_prec;  /* default NP_FP64 */
     int inner_cycles;     /* mixed only: V-cycles per refinement step; 0 = library default */
-    int warm_start;       /* 0: x is zeroed first (the paper's zero initial estimate); 2: x is the initial guess */
+    int warm_start;       /* 0: x is zeroed first (the paper's zero initial estimate); 1: learned guess
+                             (np_cnn_attach), judged against zero; 2: x is the initial guess */
     void *stream;         /* hipStream_t to run on; NULL = null stream */
 } np_mg_opts;
 
 typedef struct {
     int cycles;           /* V-cycles run (all precisions, inner cycles included) */
     int outer_iters;      /* refinement steps (mixed), = cycles for FP64 */
-    int used_fallback;    /* reserved for learned warm starts: 1 if the guess was rejected */
+    int used_fallback;    /* warm_start = 1 only: 1 if no network fits or the guess was rejected */
     double rel_res;       /* final ||f - A x||_2 / ||f||_2 in FP64 (f mean-free when periodic) */
     double rho_est;       /* geometric mean residual reduction per cycle / outer step */
     double hist[256];     /* rel_res before each cycle / outer step and after the last */
@@ -153,6 +154,58 @@ np_status np_last_autotune(int *inner_cycles, double *ms);
  */
 np_status np_ad_scalar_step(np_dims dims, double h, double *T, const double *const *a, double dt,
                             double nu, np_bc bc, const np_mg_opts *opts);
+
+/* ns_projection_step that also copies the pressure-correction right-hand
+ * side -(1/dt) D q* and the increment dp it solved for into rhs_out and
+ * dp_out (device FP64, n^d each; either may be NULL).  Used to generate
+ * (rhs, dp) training pairs for the learned warm start. */
+np_status ns_projection_step_io(np_dims dims, double h, double *u, double *v, double *w, double *p,
+                                double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
+                                np_mg_stats *stats, double *rhs_out, double *dp_out);
+
+/* ---------------------------------------------------------------------- */
+/* Learned warm start (the hybrid of trained and fixed-weight networks the
+ * paper motivates in Sections 1 and 4).  A periodic 3D U-Net on an n_in^3
+ * grid: per level two 3x3x3 convolutions with ReLU (16 channels), 2x2x2
+ * average between levels (the multigrid restriction filter), cell-centred
+ * trilinear upsampling with additive skips, a final 16 -> 1 convolution.
+ * Weights and activations are BF16, accumulation FP32 (MFMA implicit-GEMM
+ * convolutions); master weights and Adam moments FP32.  Parameter vector:
+ * per convolution in network order, W[27][16][16] (tap, out, in; tap =
+ * (dz+1)*9 + (dy+1)*3 + (dx+1)) then b[16]; 4*levels - 1 convolutions.
+ * All arrays below are device FP32 n_in^3 fields unless said otherwise. */
+typedef struct np_cnn np_cnn;
+/* n_in a power of two, n_in / 2^(levels-1) >= 16, n_in <= 512; weights zero. */
+np_status np_cnn_create(int n_in, int levels, np_cnn **out);
+void np_cnn_destroy(np_cnn *net);
+int64_t np_cnn_num_params(const np_cnn *net);
+/* host float32 arrays of np_cnn_num_params entries; set also resets Adam. */
+np_status np_cnn_set_params(np_cnn *net, const float *host, int64_t count);
+np_status np_cnn_get_params(const np_cnn *net, float *host, int64_t count);
+/* Gradient sums of the last np_cnn_gradients / np_cnn_train_step batch. */
+np_status np_cnn_get_grads(const np_cnn *net, float *host, int64_t count);
+np_status np_cnn_forward(np_cnn *net, const float *in, float *out, void *stream);
+/* in, target: host arrays of `batch` device pointers.  Loss = sum over the
+ * batch of mean((N(in) - target)^2); gradient sums stay in the network. */
+np_status np_cnn_gradients(np_cnn *net, int batch, const float *const *in, const float *const *target,
+                           double *loss, void *stream);
+/* One Adam step (lr, beta 0.9/0.999, eps 1e-8) on the batch-mean gradient. */
+np_status np_cnn_train_step(np_cnn *net, int batch, const float *const *in, const float *const *target,
+                            float lr, double *loss, void *stream);
+/* Training pair from a fine 3D grid: f and p (device FP64, dims) are
+ * restricted by 2x2x2 averaging down to n_in^3 and divided by the rms of the
+ * restricted f (*scale receives it); p, target may be NULL. */
+np_status np_cnn_prepare(np_cnn *net, np_dims dims, const double *f, const double *p, float *in,
+                         float *target, double *scale, void *stream);
+/* Network used by warm_start = 1 (NULL detaches; 3D grids of at least n_in^3
+ * only).  The solver restricts f to n_in^3, predicts, scales back, prolongates
+ * to the fine grid and keeps the guess x0 only if its energy-norm error is
+ * below that of zero, i.e. x0'A x0 - 2 f'x0 < 0 (else x = 0 and
+ * stats.used_fallback = 1). */
+np_status np_cnn_attach(np_cnn *net);
+/* Binary file: "NPCNN1\n", int32 levels, int32 n_in, int64 count, float32[count]. */
+np_status np_cnn_save(const np_cnn *net, const char *path);
+np_status np_cnn_load(const char *path, np_cnn **out);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *np_last_error(void);

@@ -72,6 +72,21 @@ _SIGS = {
     "mg_poisson_solve_batched": (_I, [_I, ctypes.POINTER(NpDims), ctypes.POINTER(_D), _I, _P, _P, _D,
                                       ctypes.POINTER(NpMgOpts), ctypes.POINTER(NpMgStats)]),
     "np_last_autotune": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "ns_projection_step_io": (_I, [NpDims, _D, _P, _P, _P, _P, _D, _D, _I, _D, ctypes.POINTER(NpMgOpts),
+                                   ctypes.POINTER(NpMgStats), _P, _P]),
+    "np_cnn_create": (_I, [_I, _I, ctypes.POINTER(_P)]),
+    "np_cnn_destroy": (None, [_P]),
+    "np_cnn_num_params": (ctypes.c_int64, [_P]),
+    "np_cnn_set_params": (_I, [_P, _P, ctypes.c_int64]),
+    "np_cnn_get_params": (_I, [_P, _P, ctypes.c_int64]),
+    "np_cnn_get_grads": (_I, [_P, _P, ctypes.c_int64]),
+    "np_cnn_forward": (_I, [_P, _P, _P, _P]),
+    "np_cnn_gradients": (_I, [_P, _I, _P, _P, ctypes.POINTER(_D), _P]),
+    "np_cnn_train_step": (_I, [_P, _I, _P, _P, ctypes.c_float, ctypes.POINTER(_D), _P]),
+    "np_cnn_prepare": (_I, [_P, NpDims, _P, _P, _P, _P, ctypes.POINTER(_D), _P]),
+    "np_cnn_attach": (_I, [_P]),
+    "np_cnn_save": (_I, [_P, ctypes.c_char_p]),
+    "np_cnn_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "np_get_tuning": (_I, [ctypes.c_char_p]),
 }
 
@@ -171,6 +186,99 @@ def ns_projection_step(u, v, w, p, h, dt, nu, bc=BC_PERIODIC, tol=1e-10, check=T
     if check:
         _check("ns_projection_step", s)
     return s, st.as_dict()
+
+
+def ns_projection_step_io(u, v, w, p, h, dt, nu, rhs_out=None, dp_out=None, bc=BC_PERIODIC, tol=1e-10,
+                          check=True, **opts):
+    """Projection step that also returns (into rhs_out, dp_out) the pressure-correction
+    right-hand side and increment it solved for."""
+    o = make_opts(**opts)
+    st = NpMgStats()
+    s = lib.ns_projection_step_io(_dims(p), h, _dev(u), _dev(v), _dev(w), _dev(p), dt, nu, bc, tol,
+                                  ctypes.byref(o), ctypes.byref(st), _dev(rhs_out), _dev(dp_out))
+    if check:
+        _check("ns_projection_step_io", s)
+    return s, st.as_dict()
+
+
+class Cnn:
+    """Handle of a learned warm-start network (np_cnn_*)."""
+
+    def __init__(self, n_in=None, levels=None, path=None):
+        self.h = ctypes.c_void_p(None)
+        if path is not None:
+            import struct
+            with open(path, "rb") as fp:
+                head = fp.read(15)
+            levels, n_in = struct.unpack("<ii", head[7:15])
+            _check("np_cnn_load", lib.np_cnn_load(path.encode(), ctypes.byref(self.h)))
+        else:
+            _check("np_cnn_create", lib.np_cnn_create(n_in, levels, ctypes.byref(self.h)))
+        self.n_in, self.levels = n_in, levels
+        self.n = lib.np_cnn_num_params(self.h)
+
+    def close(self):
+        if self.h:
+            lib.np_cnn_destroy(self.h)
+            self.h = ctypes.c_void_p(None)
+
+    def set_params(self, vec):
+        import numpy as np
+        a = np.ascontiguousarray(vec, dtype=np.float32)
+        _check("np_cnn_set_params", lib.np_cnn_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(self.n, dtype=np.float32)
+        _check("np_cnn_get_params", lib.np_cnn_get_params(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+        return a
+
+    def get_grads(self):
+        import numpy as np
+        a = np.empty(self.n, dtype=np.float32)
+        _check("np_cnn_get_grads", lib.np_cnn_get_grads(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size))
+        return a
+
+    def forward(self, x, y):
+        _check("np_cnn_forward", lib.np_cnn_forward(self.h, _dev(x, torch.float32), _dev(y, torch.float32),
+                                                    _stream()))
+
+    def _ptrs(self, ts):
+        arr = (ctypes.c_void_p * len(ts))(*[_dev(t, torch.float32).value for t in ts])
+        return arr
+
+    def gradients(self, xs, ts):
+        loss = ctypes.c_double(0.0)
+        a, b = self._ptrs(xs), self._ptrs(ts)
+        _check("np_cnn_gradients", lib.np_cnn_gradients(self.h, len(xs), ctypes.cast(a, ctypes.c_void_p),
+                                                        ctypes.cast(b, ctypes.c_void_p), ctypes.byref(loss),
+                                                        _stream()))
+        return loss.value
+
+    def train_step(self, xs, ts, lr):
+        loss = ctypes.c_double(0.0)
+        a, b = self._ptrs(xs), self._ptrs(ts)
+        _check("np_cnn_train_step", lib.np_cnn_train_step(self.h, len(xs), ctypes.cast(a, ctypes.c_void_p),
+                                                          ctypes.cast(b, ctypes.c_void_p), lr,
+                                                          ctypes.byref(loss), _stream()))
+        return loss.value
+
+    def prepare(self, f, p, x_in, target):
+        sc = ctypes.c_double(0.0)
+        _check("np_cnn_prepare", lib.np_cnn_prepare(self.h, _dims(f), _dev(f), _dev(p), _dev(x_in, torch.float32),
+                                                    _dev(target, torch.float32) if target is not None else None,
+                                                    ctypes.byref(sc), _stream()))
+        return sc.value
+
+    def attach(self):
+        lib.np_cnn_attach(self.h)
+
+    @staticmethod
+    def detach():
+        lib.np_cnn_attach(None)
+
+    def save(self, path):
+        _check("np_cnn_save", lib.np_cnn_save(self.h, path.encode()))
 
 
 def np_ad_scalar_step(T, h, dt, nu, bc, a=None):

@@ -470,6 +470,16 @@ template <int D, class S> struct Ops {
         return NP_OK;
     }
 
+    // Partials of x (f + r) (k_energy); *np receives their count.
+    static np_status energy(const S *f, const S *x, int lg, int bc, double h, double *red, hipStream_t s, int *np) {
+        const int64_t m = cells(D, lg);
+        const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m));
+        hipLaunchKernelGGL((k_energy<D, S>), dim3(nb), dim3(kBlock), 0, s, f, x, red, lg, bc, C(1.0 / (h * h)));
+        NP_LAUNCH_CHECK();
+        *np = int(nb);
+        return NP_OK;
+    }
+
     // One fused pass over a level (see mg_fused.h).  Returns the number of
     // workgroups (= partial sums written when NORM).
     template <int NJ, int PRE, bool RES, bool NORM>
@@ -1006,14 +1016,17 @@ static np_status check_solve_args(const np_dims &dims, double h, int bc, const v
         set_error("unknown smooth_prec");
         return NP_EINVAL;
     }
-    if (o.warm_start != 0 && o.warm_start != 2) {
-        set_error("warm_start must be 0 or 2 for this entry point");
+    if (o.warm_start != 0 && o.warm_start != 1 && o.warm_start != 2) {
+        set_error("warm_start must be 0 (zero), 1 (learned) or 2 (caller x)");
         return NP_EINVAL;
     }
     return NP_OK;
 }
 
 namespace np {
+np_status cnn_warm_start(int d, int lg, int bc, const double *f, double *x0, const std::vector<void *> &fl,
+                         const std::vector<void *> &xl, double *unused, hipStream_t s, bool *used);
+
 // Solve used by mg_poisson_solve and ns_projection_step.
 np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, double *x, double tol,
                         const np_mg_opts *opts, np_mg_stats *stats) {
@@ -1049,7 +1062,7 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
         set_error("non-finite right-hand side");
         return NP_ENAN;
     }
-    const bool warm = o.warm_start == 2;
+    bool warm = o.warm_start == 2;
     if (nf == 0.0 || !warm) {
         hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
         NP_LAUNCH_CHECK();
@@ -1058,6 +1071,33 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
         if (stats) { stats->cycles = 0; stats->rel_res = 0.0; }
         NP_HIP_TRY(hipStreamSynchronize(s));
         return NP_OK;
+    }
+    int fallback = 0;
+    if (o.warm_start == 1) {
+        // learned initial guess, accepted only if its energy-norm error is
+        // below that of the zero iterate (the residual norm is a poor judge
+        // here: the prolongated prediction's high-frequency interpolation
+        // error is amplified by A and removed by the first smoothing sweeps)
+        NP_TRY(ensure_levels(H));
+        bool used = false;
+        NP_TRY(cnn_warm_start(d, lg, bc, f, x, H->f, H->x, nullptr, s, &used));
+        if (used) {
+            if (bc == NP_BC_PERIODIC) NP_TRY(remove_mean(H, x, m, s));
+            int nb = 0;
+            if (d == 2) NP_TRY((Ops<2, double>::energy(f, x, lg, bc, h, H->red, s, &nb)));
+            else NP_TRY((Ops<3, double>::energy(f, x, lg, bc, h, H->red, s, &nb)));
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->red + kPartials, 0);
+            NP_LAUNCH_CHECK();
+            NP_TRY(read_scalars(H, 1, s));
+            const double gain = H->hred[0];  // ||x*||_A^2 - ||x - x*||_A^2
+            if (!(gain > 0.0)) {
+                used = false;
+                hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
+                NP_LAUNCH_CHECK();
+            }
+        }
+        warm = used;
+        fallback = used ? 0 : 1;
     }
     np_status st;
     if (o.smooth_prec == NP_FP64) {
@@ -1071,6 +1111,7 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
                     : solve_mixed<3, bf16>(HL, f, x, h, tol, o, co, s, nf, warm, stats);
     }
     if (st == NP_EHIP || st == NP_ENOMEM || st == NP_EINVAL) return st;
+    if (stats) stats->used_fallback = fallback;
     if (bc == NP_BC_PERIODIC) NP_TRY(remove_mean(H, x, m, s));
     NP_HIP_TRY(hipStreamSynchronize(s));
     return st;

@@ -200,6 +200,27 @@ __global__ __launch_bounds__(kBlock) void k_resid_sq(const S *__restrict__ f, co
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// Partial sums of x (f + r), r = f - A x, in FP64.  The energy-norm error of
+// x relative to that of the zero iterate is ||x - x*||_A^2 - ||x*||_A^2 =
+// x'Ax - 2 f'x = -sum x (f + r): a positive sum means x is closer to the
+// solution than zero in the norm the V-cycle contracts.
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_energy(const S *__restrict__ f, const S *__restrict__ x,
+                                                   double *__restrict__ partial, int lg, int bc,
+                                                   typename St<S>::C inv_h2) {
+    const int64_t m = int64_t(1) << (D * lg);
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        const double r = double(resid_at<D, S>(f, x, c, i, j, k, lg, bc, inv_h2));
+        acc += double(St<S>::ld(x + c)) * (double(St<S>::ld(f + c)) + r);
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 // Partial sums of v (square = 0) or v^2 (square = 1) in FP64.
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_sum(const S *__restrict__ v, int64_t m, int square,

@@ -231,7 +231,8 @@ void release_ns_cache() {
 
 template <int D>
 static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w, double *p, double dt, double nu,
-                              double tol, const np_mg_opts *opts, np_mg_stats *stats) {
+                              double tol, const np_mg_opts *opts, np_mg_stats *stats, double *rhs_out,
+                              double *dp_out) {
     NsWork *W = nullptr;
     NP_TRY(ns_work(D, lg, &W));
     std::lock_guard<std::mutex> lk(W->mu);
@@ -253,10 +254,12 @@ static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w,
     np_mg_opts o;
     np_default_opts(&o);
     if (opts) o = *opts;
-    o.warm_start = 0;
     np_dims dims{D, {int64_t(1) << lg, int64_t(1) << lg, D == 3 ? int64_t(1) << lg : 1}};
+    if (o.warm_start == 2) o.warm_start = 0;  // the increment always starts from zero or a learned guess
     np_status st = poisson_solve(dims, h, NP_BC_PERIODIC, rhs, dp, tol, &o, stats);
     if (st == NP_EINVAL || st == NP_EHIP || st == NP_ENOMEM) return st;
+    if (rhs_out) NP_HIP_TRY(hipMemcpyAsync(rhs_out, rhs, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    if (dp_out) NP_HIP_TRY(hipMemcpyAsync(dp_out, dp, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL((k_correct<D>), dim3(nb), dim3(kBlock), 0, s, vs, u, v, w, p, dp, lg, dt / h);
     NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipStreamSynchronize(s));
@@ -267,9 +270,9 @@ static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w,
 
 using namespace np;
 
-extern "C" np_status ns_projection_step(np_dims dims, double h, double *u, double *v, double *w, double *p,
-                                        double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
-                                        np_mg_stats *stats) {
+extern "C" np_status ns_projection_step_io(np_dims dims, double h, double *u, double *v, double *w, double *p,
+                                           double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
+                                           np_mg_stats *stats, double *rhs_out, double *dp_out) {
     clear_error();
     const int lg = check_grid(dims);
     if (lg < 0) return NP_EINVAL;
@@ -283,8 +286,14 @@ extern "C" np_status ns_projection_step(np_dims dims, double h, double *u, doubl
         set_error("unknown smooth_prec");
         return NP_EINVAL;
     }
-    if (dims.ndim == 2) return ns_step_impl<2>(lg, h, u, v, nullptr, p, dt, nu, tol, opts, stats);
-    return ns_step_impl<3>(lg, h, u, v, w, p, dt, nu, tol, opts, stats);
+    if (dims.ndim == 2) return ns_step_impl<2>(lg, h, u, v, nullptr, p, dt, nu, tol, opts, stats, rhs_out, dp_out);
+    return ns_step_impl<3>(lg, h, u, v, w, p, dt, nu, tol, opts, stats, rhs_out, dp_out);
+}
+
+extern "C" np_status ns_projection_step(np_dims dims, double h, double *u, double *v, double *w, double *p,
+                                        double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
+                                        np_mg_stats *stats) {
+    return ns_projection_step_io(dims, h, u, v, w, p, dt, nu, bc, tol, opts, stats, nullptr, nullptr);
 }
 
 extern "C" np_status np_ad_scalar_step(np_dims dims, double h, double *T, const double *const *a, double dt,

@@ -1,0 +1,177 @@
+"""GPU parity of the learned warm-start network (forward, gradients, training) and
+of the solver's use of it.  The FP64 reference runs on BF16-rounded weights and
+inputs; the GPU also rounds every activation to BF16, so agreement is judged by
+relative L2 error (<= 2e-2) and cosine similarity (>= 0.999)."""
+import numpy as np
+import pytest
+
+from paper_2402_17913_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2402_17913_amd import binding
+    return binding
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def cosine(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def params_for(levels, seed):
+    from oracle import cnn
+    ps = cnn.init_params(levels, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    out = []
+    for k, (W, b) in enumerate(ps):
+        b = rng.standard_normal(16) * 0.05
+        if k == len(ps) - 1:
+            b[1:] = 0.0
+        out.append((cnn.bf16_round(W), cnn.bf16_round(b).astype(np.float64)))
+    return out
+
+
+@pytest.mark.parametrize("n,levels", [(32, 2), (64, 3)])
+def test_cnn_forward_matches_oracle(B, n, levels):
+    import torch
+    from oracle import cnn
+    print("cnn forward", n, levels, flush=True)
+    ps = params_for(levels, seed=n)
+    rng = np.random.default_rng(7)
+    f = cnn.bf16_round(rng.standard_normal((n, n, n)))
+    ref = cnn.forward(ps, f, levels)
+    net = B.Cnn(n, levels)
+    net.set_params(cnn.flatten(ps).astype(np.float32))
+    x = torch.from_numpy(f.astype(np.float32)).cuda()
+    y = torch.empty_like(x)
+    net.forward(x, y)
+    got = y.cpu().numpy().astype(np.float64)
+    net.close()
+    print("  rel L2", rel_l2(got, ref), "cos", cosine(got, ref), flush=True)
+    assert rel_l2(got, ref) <= 2e-2 and cosine(got, ref) >= 0.999
+
+
+def test_cnn_gradients_match_oracle(B):
+    import torch
+    from oracle import cnn
+    n, levels = 32, 2
+    ps = params_for(levels, seed=3)
+    rng = np.random.default_rng(8)
+    f = cnn.bf16_round(rng.standard_normal((n, n, n)))
+    t = rng.standard_normal((n, n, n)).astype(np.float32).astype(np.float64)
+    loss_ref, grads = cnn.loss_and_grads(ps, f, t, levels)
+    net = B.Cnn(n, levels)
+    net.set_params(cnn.flatten(ps).astype(np.float32))
+    x = torch.from_numpy(f.astype(np.float32)).cuda()
+    tt = torch.from_numpy(t.astype(np.float32)).cuda()
+    loss = net.gradients([x], [tt])
+    g = net.get_grads().astype(np.float64)
+    net.close()
+    gref = cnn.flatten(grads)
+    assert abs(loss - loss_ref) / loss_ref <= 2e-2
+    print("all grads: rel L2 %.3e cos %.6f" % (rel_l2(g, gref), cosine(g, gref)), flush=True)
+    per = 27 * 16 * 16 + 16
+    for k in range(cnn.n_convs(levels)):
+        a, b = g[k * per:(k + 1) * per], gref[k * per:(k + 1) * per]
+        print("  conv %d: rel L2 %.3e cos %.6f" % (k, rel_l2(a, b), cosine(a, b)), flush=True)
+        assert cosine(a, b) >= 0.999 and rel_l2(a, b) <= 5e-2
+    assert cosine(g, gref) >= 0.999 and rel_l2(g, gref) <= 2e-2
+
+
+@pytest.fixture(scope="module")
+def trained(B):
+    """A 2-level net on the 32^3 restriction of 64^3 projection steps, trained on
+    48 pairs from seeds 11..18 (held-out evaluation seed 0)."""
+    from paper_2402_17913_amd import learned
+    net = learned.new_net(32, 2, seed=1)
+    xs, ts, tgen = learned.make_pairs(net, 64, seeds=list(range(11, 19)), steps=6)
+    hist, ttrain = learned.train(net, xs, ts, epochs=30, batch=4, lr=5e-4, seed=0)
+    print("pairs %d gen %.1fs train %.1fs loss %.3e -> %.3e" % (len(xs), tgen, ttrain, hist[0], hist[-1]),
+          flush=True)
+    yield net, hist
+    B.Cnn.detach()
+    net.close()
+
+
+def test_cnn_training_reduces_loss(B, trained):
+    """Training lowers the loss well below the targets' variance (a network that
+    collapsed to a constant output would stop at the variance) and the held-out
+    prediction correlates with the held-out target."""
+    import torch
+    net, hist = trained
+    assert hist[-1] < 0.25 * hist[0]
+    n = 64
+    g = inputs.divfree_velocity(3, n, seed=0)
+    q = [torch.from_numpy(c).cuda() for c in g["q"]]
+    p = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    rhs, dp = torch.empty_like(p), torch.empty_like(p)
+    B.ns_projection_step_io(q[0], q[1], q[2], p, g["h"], g["dt"], 1e-3, rhs_out=rhs, dp_out=dp)
+    xin = torch.empty((32,) * 3, dtype=torch.float32, device="cuda")
+    t, y = torch.empty_like(xin), torch.empty_like(xin)
+    net.prepare(rhs, dp, xin, t)
+    net.forward(xin, y)
+    tt = t.cpu().numpy().astype(np.float64)
+    yy = y.cpu().numpy().astype(np.float64)
+    yy -= yy.mean()
+    var = float(np.mean(tt ** 2))
+    print("held-out: target var %.3e, err %.3e, corr %.4f" % (var, np.mean((yy - tt) ** 2), cosine(yy, tt)),
+          flush=True)
+    assert hist[-1] < 0.2 * var and cosine(yy, tt) >= 0.9
+
+
+def test_learned_warm_start_reaches_tolerance_and_gains(B, orc, trained):
+    import torch
+    net, hist = trained
+    n = 64
+    g = inputs.divfree_velocity(3, n, seed=0)
+    q = [torch.from_numpy(c).cuda() for c in g["q"]]
+    p = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    rhs = torch.empty_like(p)
+    dp = torch.empty_like(p)
+    B.ns_projection_step_io(q[0], q[1], q[2], p, g["h"], g["dt"], 1e-3, rhs_out=rhs, dp_out=dp)
+    f = rhs.cpu().numpy()
+    fm = f - f.mean()
+    res = {}
+    for ws in (0, 1):
+        net.attach() if ws == 1 else B.Cnn.detach()
+        for prec in (B.FP64, B.FP32):
+            x = torch.zeros_like(rhs)
+            st, stats = B.mg_poisson_solve(rhs, x, g["h"], B.BC_PERIODIC, warm_start=ws, smooth_prec=prec)
+            rr = orc.rel_res(fm, x.cpu().numpy(), g["h"], 1)
+            assert rr <= 1e-10
+            res[(ws, prec)] = stats
+            print("warm_start=%d prec=%d cycles=%d outer=%d fallback=%d first rel_res=%.3e" % (
+                ws, prec, stats["cycles"], stats["outer_iters"], stats["used_fallback"], stats["hist"][0]),
+                flush=True)
+    for prec in (B.FP64, B.FP32):
+        assert res[(1, prec)]["used_fallback"] == 0
+        assert res[(1, prec)]["cycles"] <= res[(0, prec)]["cycles"]
+    B.Cnn.detach()
+
+
+def test_learned_warm_start_falls_back(B, orc):
+    """A network with zero weights predicts zero: its energy-norm error equals that
+    of the zero iterate, so the solver falls back and still converges."""
+    import torch
+    net = B.Cnn(16, 1)
+    net.set_params(np.zeros(net.n, dtype=np.float32))
+    net.attach()
+    n = 32
+    g = inputs.divfree_velocity(3, n, seed=2)
+    rng = np.random.default_rng(0)
+    f = rng.standard_normal((n, n, n))
+    fm = f - f.mean()
+    x = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    st, stats = B.mg_poisson_solve(torch.from_numpy(f).cuda(), x, g["h"], B.BC_PERIODIC, warm_start=1)
+    assert stats["used_fallback"] == 1
+    assert orc.rel_res(fm, x.cpu().numpy(), g["h"], 1) <= 1e-10
+    B.Cnn.detach()
+    net.close()
