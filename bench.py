@@ -120,12 +120,154 @@ def cpu_baseline(f, h, cycles_needed):
                        "scaled to the %d cycles of a full solve" % (sample_cycles, t, cycles_needed))
 
 
+def timed(fn, steps, warmup):
+    """Wall time of `steps` calls of fn after `warmup` untimed ones (device synced
+    on both sides); returns (seconds, last result)."""
+    import torch
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+def leg_c1(B, inputs, steps, warmup):
+    """2D Poisson 128^2, Dirichlet-0, manufactured sin(pi x) sin(pi y) + 8 modes, FP64."""
+    import torch
+    g = inputs.manufactured_2d(128, seed=0)
+    f = torch.from_numpy(g["f"]).cuda()
+    x = torch.zeros_like(f)
+    dt, (_, st) = timed(lambda: B.mg_poisson_solve(f, x, g["h"], B.BC_DIRICHLET0, tol=TOL), steps, warmup)
+    return dict(workload="poisson2d_128sq_dirichlet_manufactured_seed0_fp64", dofs=f.numel(),
+                dofs_per_s=f.numel() * steps / dt, ms_per_solve=1e3 * dt / steps, cycles=st["cycles"],
+                rel_res=st["rel_res"])
+
+
+def leg_c2(B, inputs, nsteps=100):
+    """2D NS projection steps, 1024^2 periodic, nu = 1e-3, 100 steps from the seeded
+    divergence-free field; pressure increment from zero, and from the previous step's."""
+    import torch
+    n = 1024
+    g = inputs.divfree_velocity(2, n, seed=0)
+    out = {}
+    for name, ws in (("zero_guess", 0), ("previous_dp_guess", 2)):
+        B.np_release_all()
+        u, v = [torch.from_numpy(c).cuda() for c in g["q"]]
+        p = torch.zeros_like(u)
+        ke0 = float(0.5 * (u.square().sum() + v.square().sum())) * g["h"] ** 2
+        cyc = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            _, st = B.ns_projection_step(u, v, None, p, g["h"], g["dt"], 1e-3, tol=TOL, warm_start=ws)
+            cyc.append(st["cycles"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ke = float(0.5 * (u.square().sum() + v.square().sum())) * g["h"] ** 2
+        cfl = g["dt"] * (float(u.abs().max()) + float(v.abs().max())) / g["h"]
+        out[name] = dict(cell_steps_per_s=n * n * nsteps / dt, ms_per_step=1e3 * dt / nsteps,
+                         mean_cycles=sum(cyc) / len(cyc), max_cycles=max(cyc), kinetic_energy=[ke0, ke],
+                         final_cfl=cfl)
+        log("  C2 %s: %.2f ms/step, %.1f cycles/step" % (name, 1e3 * dt / nsteps, sum(cyc) / len(cyc)))
+    return dict(workload="ns2d_1024sq_periodic_divfree_seed0_nu1e-3_100steps_fp64", steps=nsteps, **out)
+
+
+def leg_c4(B, inputs, steps, warmup):
+    """512 batched 2D Dirichlet solves, sizes drawn by seed 0 from {64..1024}^2, RHS
+    seed 1000 + i; FP32 inner cycles with FP64 refinement, autotuned inner count."""
+    import torch
+    sizes = inputs.batched_sizes(512, seed=0)
+    fs = [torch.from_numpy(inputs.sine_rhs(2, n, seed=1000 + i)["f"]).cuda() for i, n in enumerate(sizes)]
+    xs = [torch.zeros_like(f) for f in fs]
+    hs = [1.0 / n for n in sizes]
+    dofs = sum(n * n for n in sizes)
+    t0 = time.perf_counter()
+    B.mg_poisson_solve_batched(fs, xs, hs, smooth_prec=B.FP32, inner_cycles=0)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    inner, _ = B.np_last_autotune()
+    dt, (_, stats) = timed(lambda: B.mg_poisson_solve_batched(fs, xs, hs, smooth_prec=B.FP32, inner_cycles=0),
+                           steps, warmup)
+    worst = max(s["rel_res"] for s in stats)
+
+    def solo():
+        for f, x, h in zip(fs, xs, hs):
+            B.mg_poisson_solve(f, x, h, B.BC_DIRICHLET0, tol=TOL, smooth_prec=B.FP32)
+    dts, _ = timed(solo, 1, 1)
+    hist = {str(c): sizes.count(c) for c in sorted(set(sizes))}
+    return dict(workload="batched_poisson2d_512_sizes64-1024_seed0_fp32+fp64", problems=len(sizes), dofs=dofs,
+                size_histogram=hist, dofs_per_s=dofs * steps / dt, ms_per_batch=1e3 * dt / steps,
+                first_call_s=setup, autotuned_inner_cycles=inner, worst_rel_res=worst,
+                one_at_a_time_dofs_per_s=dofs / dts, batched_over_one_at_a_time=(dofs * steps / dt) / (dofs / dts))
+
+
+def leg_c5(B, inputs, nsteps=10):
+    """3D projection steps, 256^3 periodic, nu = 1e-3, seed 0 (held out from the
+    network's training seeds 1..20): pressure increment from zero, from the previous
+    step's increment, and from the learned warm start; FP64 and FP32-inner solves."""
+    import torch
+    from paper_2402_17913_amd import learned
+    n = 256
+    wpath = os.path.join(ROOT, "paper_2402_17913_amd", "weights", "ns3d_periodic_256_in128_L4.npcnn")
+    g = inputs.divfree_velocity(3, n, seed=0)
+    out = {}
+    for prec_name, prec in (("fp64", B.FP64), ("fp32", B.FP32)):
+        for name, ws in (("zero_guess", 0), ("previous_dp_guess", 2), ("learned_guess", 1)):
+            B.np_cnn_load(wpath if ws == 1 else None)
+            q = [torch.from_numpy(c).cuda() for c in g["q"]]
+            p = torch.zeros_like(q[0])
+            # untimed: one step from a copy of the state warms workspaces, graphs and
+            # the network for this grid; one step of a zero field then leaves a zero
+            # increment behind, so the first timed step starts from zero under every
+            # variant (there is no previous increment before the first step)
+            qw = [c.clone() for c in q]
+            B.ns_projection_step(qw[0], qw[1], qw[2], p.clone(), g["h"], g["dt"], 1e-3, tol=TOL,
+                                 warm_start=1 if ws == 1 else 0, smooth_prec=prec)
+            for c in qw:
+                c.zero_()
+            B.ns_projection_step(qw[0], qw[1], qw[2], torch.zeros_like(p), g["h"], g["dt"], 1e-3, tol=TOL,
+                                 warm_start=0, smooth_prec=prec)
+            del qw
+            cyc, fb = [], 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                _, st = B.ns_projection_step(q[0], q[1], q[2], p, g["h"], g["dt"], 1e-3, tol=TOL,
+                                             warm_start=ws, smooth_prec=prec)
+                cyc.append(st["cycles"])
+                fb += st["used_fallback"]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            out["%s_%s" % (prec_name, name)] = dict(ms_per_step=1e3 * dt / nsteps, cycles=cyc,
+                                                    fallbacks=fb if ws == 1 else None)
+            log("  C5 %s %s: %.2f ms/step, cycles %s" % (prec_name, name, 1e3 * dt / nsteps, cyc))
+    B.np_cnn_load(None)
+    net = B.Cnn(path=wpath)
+    xin = torch.randn((net.n_in,) * 3, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(xin)
+    dt, _ = timed(lambda: net.forward(xin, y), 10, 2)
+    net.close()
+    meta = json.load(open(os.path.splitext(wpath)[0] + ".json"))
+    return dict(workload="ns3d_256cube_periodic_divfree_seed0_nu1e-3_%dsteps" % nsteps, steps=nsteps,
+                network=dict(n_in=meta["n_in"], levels=meta["levels"], pairs=meta["pairs"],
+                             training_seeds=meta["seeds"], epochs=meta["epochs"],
+                             training_s=meta["training_s"], pair_generation_s=meta["pair_generation_s"],
+                             forward_ms=1e3 * dt / 10),
+                **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--legs", default="c1,c2,c4,c5",
+                    help="other workloads to run after the headline (comma list, '' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -215,6 +357,24 @@ def main():
     if not args.no_cpu:
         log("timing the oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(f, h, res["fp64"]["stats"]["cycles"])
+    legs = [l for l in args.legs.split(",") if l]
+    others = {}
+    for leg in legs:
+        log("workload %s ..." % leg)
+        if leg == "c1":
+            others["c1"] = leg_c1(B, inputs, args.steps, args.warmup)
+        elif leg == "c2":
+            others["c2"] = leg_c2(B, inputs)
+        elif leg == "c4":
+            others["c4"] = leg_c4(B, inputs, max(1, args.steps // 3), 1)
+        elif leg == "c5":
+            others["c5"] = leg_c5(B, inputs)
+        else:
+            sys.exit("unknown leg %s" % leg)
+        B.np_release_all()
+        torch.cuda.empty_cache()
+    if others:
+        line["workloads"] = others
     print(json.dumps(line), flush=True)
 
 

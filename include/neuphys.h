@@ -107,7 +107,10 @@ np_status mg_poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, 
  * predictor q~ = q^n - dt F(q^n), corrector q* = q^n - dt F((q~ + q^n)/2)
  * with F(q) = (a . grad_c) q - nu Lap q + G p^n, a = u^n on the faces
  * (central differences); then A dp = -(1/dt) D q* solved by mg_poisson_solve
- * from a zero guess to tol; q = q* - dt G dp; p += dp.
+ * to tol; q = q* - dt G dp; p += dp.  The increment starts from zero
+ * (opts->warm_start 0), the attached network's guess (1), or the previous
+ * converged step's increment on the same grid size (2; zero when there is
+ * none, e.g. the first step or after np_release_all).
  * u, v, p (and w in 3D; NULL in 2D): device, FP64, in/out.  h: cell size.
  * bc must be NP_BC_PERIODIC.  stats receive the pressure solve's numbers.
  */
@@ -175,7 +178,8 @@ np_status ns_projection_step_io(np_dims dims, double h, double *u, double *v, do
  * (dz+1)*9 + (dy+1)*3 + (dx+1)) then b[16]; 4*levels - 1 convolutions.
  * All arrays below are device FP32 n_in^3 fields unless said otherwise. */
 typedef struct np_cnn np_cnn;
-/* n_in a power of two, n_in / 2^(levels-1) >= 16, n_in <= 512; weights zero. */
+/* n_in a power of two, n_in / 2^(levels-1) >= 16, n_in <= 512; weights zero
+ * (np_cnn_init randomises them). */
 np_status np_cnn_create(int n_in, int levels, np_cnn **out);
 void np_cnn_destroy(np_cnn *net);
 int64_t np_cnn_num_params(const np_cnn *net);
@@ -203,9 +207,35 @@ np_status np_cnn_prepare(np_cnn *net, np_dims dims, const double *f, const doubl
  * below that of zero, i.e. x0'A x0 - 2 f'x0 < 0 (else x = 0 and
  * stats.used_fallback = 1). */
 np_status np_cnn_attach(np_cnn *net);
+/* Re-initialises the weights: He-normal from a seeded host generator (fan-in
+ * 27 for the first convolution, which reads channel 0 only; 27*16 for the
+ * others; the output convolution writes channel 0 only at 0.1 times its
+ * fan-in scale), zero biases, Adam state reset. */
+np_status np_cnn_init(np_cnn *net, uint64_t seed);
 /* Binary file: "NPCNN1\n", int32 levels, int32 n_in, int64 count, float32[count]. */
 np_status np_cnn_save(const np_cnn *net, const char *path);
-np_status np_cnn_load(const char *path, np_cnn **out);
+/* A network from a file written by np_cnn_save, as a caller-owned handle. */
+np_status np_cnn_open(const char *path, np_cnn **out);
+/* Loads weights_path into a library-owned network and attaches it, so that
+ * warm_start = 1 uses it (replacing and freeing any network loaded before);
+ * NULL detaches and frees it.  On error nothing changes. */
+np_status np_cnn_load(const char *weights_path);
+/* Trains a new network and writes it to weights_out (np_cnn_save format).
+ * Pairs i = 0 .. npairs-1: rhs[i], p[i] are device FP64 cubes of dims[i]
+ * (each a power of two >= n_in), a right-hand side and the solution it gives;
+ * each is restricted to n_in^3 by 2^3 averaging and divided by the rms of the
+ * restricted rhs (np_cnn_prepare), held on the device as FP32 for the whole
+ * run (8 n_in^3 bytes per pair).  bc must be NP_BC_PERIODIC.  cfg_json: NULL
+ * or a flat JSON object with any of "n_in" (128), "levels" (4), "epochs" (10),
+ * "batch" (4), "lr" (5e-4), "seed" (0), "verbose" (0: nonzero prints each
+ * finished epoch's loss and elapsed time to stderr); unknown keys are errors.  Seeded
+ * initialisation (np_cnn_init), then per epoch a seeded shuffle and Adam steps
+ * on minibatches (np_cnn_train_step).  epoch_loss: NULL or a host array of
+ * "epochs" entries receiving each epoch's mean MSE.  Runs on the null stream
+ * and returns when the file is written. */
+np_status np_cnn_train(const np_dims *dims, np_bc bc, int npairs, const double *const *rhs,
+                       const double *const *p, const char *cfg_json, const char *weights_out,
+                       double *epoch_loss);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *np_last_error(void);

@@ -86,7 +86,11 @@ _SIGS = {
     "np_cnn_prepare": (_I, [_P, NpDims, _P, _P, _P, _P, ctypes.POINTER(_D), _P]),
     "np_cnn_attach": (_I, [_P]),
     "np_cnn_save": (_I, [_P, ctypes.c_char_p]),
-    "np_cnn_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "np_cnn_open": (_I, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "np_cnn_load": (_I, [ctypes.c_char_p]),
+    "np_cnn_init": (_I, [_P, ctypes.c_uint64]),
+    "np_cnn_train": (_I, [ctypes.POINTER(NpDims), _I, _I, _P, _P, ctypes.c_char_p, ctypes.c_char_p,
+                          ctypes.POINTER(_D)]),
     "np_get_tuning": (_I, [ctypes.c_char_p]),
 }
 
@@ -211,7 +215,7 @@ class Cnn:
             with open(path, "rb") as fp:
                 head = fp.read(15)
             levels, n_in = struct.unpack("<ii", head[7:15])
-            _check("np_cnn_load", lib.np_cnn_load(path.encode(), ctypes.byref(self.h)))
+            _check("np_cnn_open", lib.np_cnn_open(path.encode(), ctypes.byref(self.h)))
         else:
             _check("np_cnn_create", lib.np_cnn_create(n_in, levels, ctypes.byref(self.h)))
         self.n_in, self.levels = n_in, levels
@@ -279,6 +283,35 @@ class Cnn:
 
     def save(self, path):
         _check("np_cnn_save", lib.np_cnn_save(self.h, path.encode()))
+
+    def init(self, seed=0):
+        _check("np_cnn_init", lib.np_cnn_init(self.h, ctypes.c_uint64(seed)))
+
+
+def np_cnn_load(path):
+    """Loads a weight file into a library-owned network used by warm_start=1
+    (None detaches it)."""
+    _check("np_cnn_load", lib.np_cnn_load(path.encode() if path is not None else None))
+
+
+def np_cnn_train(rhs, p, weights_out, cfg=None, bc=BC_PERIODIC):
+    """Trains a network on device FP64 (rhs, p) pairs (lists of 3D tensors) and
+    writes it to weights_out; returns the per-epoch mean loss."""
+    import json
+    n = len(rhs)
+    if len(p) != n:
+        raise ValueError("rhs and p must have the same length")
+    cfg = dict(cfg or {})
+    js = json.dumps(cfg)
+    dims = (NpDims * n)(*[_dims(t) for t in rhs])
+    rp = (ctypes.c_void_p * n)(*[_dev(t).value for t in rhs])
+    pp = (ctypes.c_void_p * n)(*[_dev(t).value for t in p])
+    epochs = int(cfg.get("epochs", 10))
+    hist = (ctypes.c_double * max(epochs, 1))()
+    _check("np_cnn_train", lib.np_cnn_train(dims, bc, n, ctypes.cast(rp, ctypes.c_void_p),
+                                            ctypes.cast(pp, ctypes.c_void_p), js.encode(),
+                                            weights_out.encode(), hist))
+    return list(hist)[:epochs]
 
 
 def np_ad_scalar_step(T, h, dt, nu, bc, a=None):

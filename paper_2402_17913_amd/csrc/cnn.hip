@@ -8,10 +8,14 @@
 // tile (x: row + 2, y: 4 rows + 2, z: 3 planes) and the weights in LDS.
 // The data gradient is the same kernel on the flipped, transposed filter; the
 // weight gradient is an FP32 reduction over voxels.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <random>
+#include <string>
 #include <vector>
 
 #include "mg_kernels.h"
@@ -708,13 +712,9 @@ extern "C" np_status np_cnn_gradients(np_cnn *net, int batch, const float *const
     return grads_for(N, batch, in, target, loss, (hipStream_t)stream);
 }
 
-extern "C" np_status np_cnn_train_step(np_cnn *net, int batch, const float *const *in, const float *const *target,
-                                       float lr, double *loss, void *stream) {
-    clear_error();
-    if (!net || batch <= 0 || !in || !target || !(lr > 0.f)) { set_error("bad argument"); return NP_EINVAL; }
-    Net *N = net->net;
-    std::lock_guard<std::mutex> lk(N->mu);
-    hipStream_t s = (hipStream_t)stream;
+// Gradients of the batch, then one Adam step on their mean.
+static np_status train_step(Net *N, int batch, const float *const *in, const float *const *target, float lr,
+                            double *loss, hipStream_t s) {
     NP_TRY(grads_for(N, batch, in, target, loss, s));
     N->step += 1;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -731,17 +731,19 @@ extern "C" np_status np_cnn_train_step(np_cnn *net, int batch, const float *cons
     return NP_OK;
 }
 
+extern "C" np_status np_cnn_train_step(np_cnn *net, int batch, const float *const *in, const float *const *target,
+                                       float lr, double *loss, void *stream) {
+    clear_error();
+    if (!net || batch <= 0 || !in || !target || !(lr > 0.f)) { set_error("bad argument"); return NP_EINVAL; }
+    Net *N = net->net;
+    std::lock_guard<std::mutex> lk(N->mu);
+    return train_step(N, batch, in, target, lr, loss, (hipStream_t)stream);
+}
+
 // Restricts f (and p) from the fine grid to the network's grid by repeated
 // 2^3 averaging, scales both by 1 / rms(restricted f) and writes FP32 copies.
-extern "C" np_status np_cnn_prepare(np_cnn *net, np_dims dims, const double *f, const double *p, float *in,
-                                    float *target, double *scale, void *stream) {
-    clear_error();
-    const int lg = check_grid(dims);
-    if (lg < 0 || dims.ndim != 3 || !net || !f || !in) { set_error("bad argument"); return NP_EINVAL; }
-    Net *N = net->net;
-    if (lg < N->lg0) { set_error("grid coarser than the network input"); return NP_EINVAL; }
-    std::lock_guard<std::mutex> lk(N->mu);
-    hipStream_t s = (hipStream_t)stream;
+static np_status prepare(Net *N, int lg, const double *f, const double *p, float *in, float *target, double *scale,
+                        hipStream_t s) {
     const int ell = lg - N->lg0;
     std::vector<double *> tmp;
     double *fb = nullptr, *pb = nullptr;
@@ -788,6 +790,17 @@ extern "C" np_status np_cnn_prepare(np_cnn *net, np_dims dims, const double *f, 
     return st;
 }
 
+extern "C" np_status np_cnn_prepare(np_cnn *net, np_dims dims, const double *f, const double *p, float *in,
+                                    float *target, double *scale, void *stream) {
+    clear_error();
+    const int lg = check_grid(dims);
+    if (lg < 0 || dims.ndim != 3 || !net || !f || !in) { set_error("bad argument"); return NP_EINVAL; }
+    Net *N = net->net;
+    if (lg < N->lg0) { set_error("grid coarser than the network input"); return NP_EINVAL; }
+    std::lock_guard<std::mutex> lk(N->mu);
+    return prepare(N, lg, f, p, in, target, scale, (hipStream_t)stream);
+}
+
 extern "C" np_status np_cnn_attach(np_cnn *net) {
     std::lock_guard<std::mutex> lk(g_cnn_mu);
     g_attached = net ? net->net : nullptr;
@@ -812,7 +825,7 @@ extern "C" np_status np_cnn_save(const np_cnn *net, const char *path) {
     return NP_OK;
 }
 
-extern "C" np_status np_cnn_load(const char *path, np_cnn **out) {
+extern "C" np_status np_cnn_open(const char *path, np_cnn **out) {
     clear_error();
     if (!path || !out) { set_error("bad argument"); return NP_EINVAL; }
     FILE *fp = std::fopen(path, "rb");
@@ -836,5 +849,176 @@ extern "C" np_status np_cnn_load(const char *path, np_cnn **out) {
         np_cnn_destroy(*out);
         *out = nullptr;
     }
+    return st;
+}
+
+// Network owned by the library (np_cnn_load).
+static np_cnn *g_owned = nullptr;
+
+extern "C" np_status np_cnn_load(const char *path) {
+    clear_error();
+    np_cnn *net = nullptr;
+    if (path) NP_TRY(np_cnn_open(path, &net));
+    np_cnn *old = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cnn_mu);
+        old = g_owned;
+        g_owned = net;
+        g_attached = net ? net->net : nullptr;
+    }
+    if (old) np_cnn_destroy(old);
+    return NP_OK;
+}
+
+// He-normal weights from a seeded host generator: fan-in 27 for the first
+// convolution (input channel 0 only), 27 x 16 otherwise; the output
+// convolution writes channel 0 only and starts 10x smaller than its fan-in
+// scale (the targets' variance is ~1e-2 of the inputs'; a full-scale first
+// output makes the early Adam steps shrink every layer until the ReLUs die).
+// Biases zero; Adam state reset.
+extern "C" np_status np_cnn_init(np_cnn *net, uint64_t seed) {
+    clear_error();
+    if (!net) { set_error("bad argument"); return NP_EINVAL; }
+    Net *N = net->net;
+    std::vector<float> w(N->npar, 0.f);
+    std::mt19937_64 eng(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int k = 0; k < N->nconv; ++k) {
+        float *W = w.data() + int64_t(k) * kPsz;
+        for (int t = 0; t < kTaps; ++t)
+            for (int o = 0; o < kC; ++o)
+                for (int c = 0; c < kC; ++c) {
+                    double sd;
+                    if (k == 0) sd = c == 0 ? std::sqrt(2.0 / kTaps) : 0.0;
+                    else if (k == N->nconv - 1) sd = o == 0 ? 0.1 * std::sqrt(1.0 / (kTaps * kC)) : 0.0;
+                    else sd = std::sqrt(2.0 / (kTaps * kC));
+                    W[(t * kC + o) * kC + c] = sd > 0.0 ? float(sd * nd(eng)) : 0.f;
+                }
+    }
+    return np_cnn_set_params(net, w.data(), N->npar);
+}
+
+namespace {
+// Reads `"key": number` members of a flat JSON object into the named slots;
+// any other key or form is an error.
+bool parse_cfg(const char *js, const char *const *keys, double *vals, int nkeys, std::string *err) {
+    if (!js) return true;
+    const char *q = js;
+    auto ws = [&]() { while (*q == ' ' || *q == '\t' || *q == '\n' || *q == '\r') ++q; };
+    ws();
+    if (*q != '{') { *err = "configuration must be a JSON object"; return false; }
+    ++q;
+    ws();
+    if (*q == '}') return true;
+    for (;;) {
+        ws();
+        if (*q != '"') { *err = "expected a quoted key"; return false; }
+        const char *k0 = ++q;
+        while (*q && *q != '"') ++q;
+        if (!*q) { *err = "unterminated key"; return false; }
+        const std::string key(k0, q - k0);
+        ++q;
+        ws();
+        if (*q != ':') { *err = "expected ':' after " + key; return false; }
+        ++q;
+        ws();
+        char *end = nullptr;
+        const double v = std::strtod(q, &end);
+        if (end == q || !std::isfinite(v)) { *err = "value of " + key + " is not a number"; return false; }
+        q = end;
+        int idx = -1;
+        for (int i = 0; i < nkeys; ++i)
+            if (key == keys[i]) idx = i;
+        if (idx < 0) { *err = "unknown key " + key; return false; }
+        vals[idx] = v;
+        ws();
+        if (*q == ',') { ++q; continue; }
+        if (*q == '}') {
+            ++q;
+            ws();
+            if (*q) { *err = "text after the object"; return false; }
+            return true;
+        }
+        *err = "expected ',' or '}'";
+        return false;
+    }
+}
+}  // namespace
+
+// Trains a new network on (rhs, p) pairs and writes it to weights_out.
+extern "C" np_status np_cnn_train(const np_dims *dims, np_bc bc, int npairs, const double *const *rhs,
+                                  const double *const *p, const char *cfg_json, const char *weights_out,
+                                  double *epoch_loss) {
+    clear_error();
+    if (!dims || !rhs || !p || !weights_out || npairs <= 0) { set_error("bad argument"); return NP_EINVAL; }
+    if (bc != NP_BC_PERIODIC) { set_error("the network is periodic: bc must be NP_BC_PERIODIC"); return NP_EINVAL; }
+    static const char *const keys[] = {"n_in", "levels", "epochs", "batch", "lr", "seed", "verbose"};
+    double cfg[7] = {128, 4, 10, 4, 5e-4, 0, 0};
+    std::string err;
+    if (!parse_cfg(cfg_json, keys, cfg, 7, &err)) { set_error("configuration: %s", err.c_str()); return NP_EINVAL; }
+    const bool verbose = cfg[6] != 0.0;
+    const int n_in = int(cfg[0]), levels = int(cfg[1]), epochs = int(cfg[2]), batch = int(cfg[3]);
+    const float lr = float(cfg[4]);
+    const uint64_t seed = uint64_t(cfg[5]);
+    if (epochs < 1 || batch < 1 || !(lr > 0.f) || cfg[5] < 0) { set_error("configuration: bad epochs, batch, lr or seed"); return NP_EINVAL; }
+    std::vector<int> lgs(npairs);
+    for (int i = 0; i < npairs; ++i) {
+        lgs[i] = check_grid(dims[i]);
+        if (lgs[i] < 0 || dims[i].ndim != 3 || !rhs[i] || !p[i]) { set_error("pair %d: bad grid or pointer", i); return NP_EINVAL; }
+        if ((int64_t(1) << lgs[i]) < n_in) { set_error("pair %d: grid coarser than n_in", i); return NP_EINVAL; }
+    }
+    np_cnn *net = nullptr;
+    NP_TRY(np_cnn_create(n_in, levels, &net));
+    Net *N = net->net;
+    const int64_t mc = vox(N->lg0);
+    float *buf = nullptr;
+    np_status st = np_cnn_init(net, seed);
+    if (st == NP_OK && hipMalloc((void **)&buf, sizeof(float) * mc * 2 * npairs) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of %lld bytes for the prepared pairs failed", (long long)(sizeof(float) * mc * 2 * npairs));
+        st = NP_ENOMEM;
+    }
+    std::vector<const float *> xin(npairs), tgt(npairs);
+    {
+        std::lock_guard<std::mutex> lk(N->mu);
+        for (int i = 0; i < npairs && st == NP_OK; ++i) {
+            float *xi = buf + mc * 2 * i, *ti = xi + mc;
+            xin[i] = xi;
+            tgt[i] = ti;
+            st = prepare(N, lgs[i], rhs[i], p[i], xi, ti, nullptr, nullptr);
+        }
+        const auto t0 = std::chrono::steady_clock::now();
+        // seeded Fisher-Yates order per epoch, minibatches of `batch` pairs
+        std::mt19937_64 eng(seed ^ 0x9e3779b97f4a7c15ull);
+        std::vector<int> order(npairs);
+        std::vector<const float *> bx, bt;
+        for (int ep = 0; ep < epochs && st == NP_OK; ++ep) {
+            for (int i = 0; i < npairs; ++i) order[i] = i;
+            for (int i = npairs - 1; i > 0; --i) std::swap(order[i], order[eng() % uint64_t(i + 1)]);
+            double tot = 0.0;
+            for (int i0 = 0; i0 < npairs && st == NP_OK; i0 += batch) {
+                const int nb2 = std::min(batch, npairs - i0);
+                bx.assign(nb2, nullptr);
+                bt.assign(nb2, nullptr);
+                for (int j = 0; j < nb2; ++j) {
+                    bx[j] = xin[order[i0 + j]];
+                    bt[j] = tgt[order[i0 + j]];
+                }
+                double l = 0.0;
+                st = train_step(N, nb2, bx.data(), bt.data(), lr, &l, nullptr);
+                tot += l;
+            }
+            if (epoch_loss) epoch_loss[ep] = tot / npairs;
+            if (verbose && st == NP_OK) {
+                const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                std::fprintf(stderr, "np_cnn_train: epoch %d/%d mean mse %.4e (%.1f s)\n", ep + 1, epochs,
+                             tot / npairs, sec);
+                std::fflush(stderr);
+            }
+        }
+    }
+    if (buf) (void)hipFree(buf);
+    if (st == NP_OK) st = np_cnn_save(net, weights_out);
+    np_cnn_destroy(net);
     return st;
 }

@@ -188,6 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_ad_stage(const double *__restrict__ 
 struct NsWork {
     int d = 0, lg = 0;
     double *buf = nullptr;  // 2*d face arrays + rhs + dp
+    bool dp_valid = false;  // dp holds the increment of a converged step on this grid
     std::mutex mu;
 };
 std::mutex g_ns_mu;
@@ -255,9 +256,13 @@ static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w,
     np_default_opts(&o);
     if (opts) o = *opts;
     np_dims dims{D, {int64_t(1) << lg, int64_t(1) << lg, D == 3 ? int64_t(1) << lg : 1}};
-    if (o.warm_start == 2) o.warm_start = 0;  // the increment always starts from zero or a learned guess
+    // warm_start 2: the increment starts from the previous step's (held in the
+    // workspace), or from zero when this grid has none yet
+    if (o.warm_start == 2 && !W->dp_valid) o.warm_start = 0;
+    W->dp_valid = false;
     np_status st = poisson_solve(dims, h, NP_BC_PERIODIC, rhs, dp, tol, &o, stats);
     if (st == NP_EINVAL || st == NP_EHIP || st == NP_ENOMEM) return st;
+    W->dp_valid = st == NP_OK;
     if (rhs_out) NP_HIP_TRY(hipMemcpyAsync(rhs_out, rhs, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
     if (dp_out) NP_HIP_TRY(hipMemcpyAsync(dp_out, dp, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL((k_correct<D>), dim3(nb), dim3(kBlock), 0, s, vs, u, v, w, p, dp, lg, dt / h);

@@ -87,16 +87,17 @@ def test_cnn_gradients_match_oracle(B):
 
 
 @pytest.fixture(scope="module")
-def trained(B):
-    """A 2-level net on the 32^3 restriction of 64^3 projection steps, trained on
-    48 pairs from seeds 11..18 (held-out evaluation seed 0)."""
+def trained(B, tmp_path_factory):
+    """A 2-level net on the 32^3 restriction of 64^3 projection steps, trained by
+    np_cnn_train on 48 pairs from seeds 11..18 (held-out evaluation seed 0)."""
     from paper_2402_17913_amd import learned
-    net = learned.new_net(32, 2, seed=1)
-    xs, ts, tgen = learned.make_pairs(net, 64, seeds=list(range(11, 19)), steps=6)
-    hist, ttrain = learned.train(net, xs, ts, epochs=30, batch=4, lr=5e-4, seed=0)
-    print("pairs %d gen %.1fs train %.1fs loss %.3e -> %.3e" % (len(xs), tgen, ttrain, hist[0], hist[-1]),
+    path = str(tmp_path_factory.mktemp("cnn") / "net.npcnn")
+    rs, ps, tgen = learned.make_pairs(64, seeds=list(range(11, 19)), steps=6, n_keep=32)
+    hist, ttrain = learned.train(rs, ps, path, n_in=32, levels=2, epochs=30, batch=4, lr=5e-4, seed=1)
+    print("pairs %d gen %.1fs train %.1fs loss %.3e -> %.3e" % (len(rs), tgen, ttrain, hist[0], hist[-1]),
           flush=True)
-    yield net, hist
+    net = B.Cnn(path=path)
+    yield net, hist, path
     B.Cnn.detach()
     net.close()
 
@@ -106,7 +107,8 @@ def test_cnn_training_reduces_loss(B, trained):
     collapsed to a constant output would stop at the variance) and the held-out
     prediction correlates with the held-out target."""
     import torch
-    net, hist = trained
+    net, hist, _ = trained
+    assert net.n_in == 32 and net.levels == 2
     assert hist[-1] < 0.25 * hist[0]
     n = 64
     g = inputs.divfree_velocity(3, n, seed=0)
@@ -128,8 +130,11 @@ def test_cnn_training_reduces_loss(B, trained):
 
 
 def test_learned_warm_start_reaches_tolerance_and_gains(B, orc, trained):
+    """The network loaded by np_cnn_load(path) warm-starts the pressure solve: the
+    guess is accepted, the solve still meets the tolerance (judged by the
+    oracle's residual), and it needs no more cycles than from zero."""
     import torch
-    net, hist = trained
+    _, _, path = trained
     n = 64
     g = inputs.divfree_velocity(3, n, seed=0)
     q = [torch.from_numpy(c).cuda() for c in g["q"]]
@@ -141,7 +146,7 @@ def test_learned_warm_start_reaches_tolerance_and_gains(B, orc, trained):
     fm = f - f.mean()
     res = {}
     for ws in (0, 1):
-        net.attach() if ws == 1 else B.Cnn.detach()
+        B.np_cnn_load(path if ws == 1 else None)
         for prec in (B.FP64, B.FP32):
             x = torch.zeros_like(rhs)
             st, stats = B.mg_poisson_solve(rhs, x, g["h"], B.BC_PERIODIC, warm_start=ws, smooth_prec=prec)
@@ -154,7 +159,7 @@ def test_learned_warm_start_reaches_tolerance_and_gains(B, orc, trained):
     for prec in (B.FP64, B.FP32):
         assert res[(1, prec)]["used_fallback"] == 0
         assert res[(1, prec)]["cycles"] <= res[(0, prec)]["cycles"]
-    B.Cnn.detach()
+    B.np_cnn_load(None)
 
 
 def test_learned_warm_start_falls_back(B, orc):
@@ -175,3 +180,19 @@ def test_learned_warm_start_falls_back(B, orc):
     assert orc.rel_res(fm, x.cpu().numpy(), g["h"], 1) <= 1e-10
     B.Cnn.detach()
     net.close()
+
+
+def test_cnn_train_is_deterministic(B, tmp_path):
+    """Same pairs and seed: byte-identical weight files (fixed-order reductions,
+    seeded initialisation and shuffle); another seed gives other weights."""
+    import torch
+    rng = np.random.default_rng(5)
+    rs = [torch.from_numpy(rng.standard_normal((32, 32, 32))).cuda() for _ in range(5)]
+    ps = [torch.from_numpy(rng.standard_normal((32, 32, 32))).cuda() for _ in range(5)]
+    files = []
+    for k, seed in enumerate((3, 3, 4)):
+        path = str(tmp_path / ("w%d.npcnn" % k))
+        B.np_cnn_train(rs, ps, path, dict(n_in=16, levels=1, epochs=2, batch=2, seed=seed))
+        files.append(open(path, "rb").read())
+    assert files[0] == files[1]
+    assert files[0] != files[2]
