@@ -289,7 +289,8 @@ np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
  * (even number of planes per workgroup in fused kernels, 0 = automatic),
  * "inner_fp32"/"inner_bf16" (default inner cycles per refinement step),
  * "batch" (cycles enqueued before the first host read of the convergence
- * state), "batched_graphs" and "batched_autotune" (0/1 for the batched
+ * state), "sweep3" (0/1: z-marching smoothing, restriction and refinement
+ * kernels on 3D levels of n >= 128), "batched_graphs" and "batched_autotune" (0/1 for the batched
  * solver).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
  * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */
 np_status np_set_tuning(const char *key, int value);

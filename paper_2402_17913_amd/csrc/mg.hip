@@ -110,6 +110,7 @@ struct Tuning {
     int inner_fp32 = 3;   // default inner cycles per refinement step
     int inner_bf16 = 2;
     int batch = 4;        // first batch of cycles enqueued before reading the controller
+    int sweep3 = 1;       // z-marching sweep, restriction and refinement kernels on 3D levels of n >= 128
 };
 static Tuning g_tune;
 
@@ -384,7 +385,17 @@ template <int D, class S> struct Ops {
         void *tok = nullptr;
         const bool prof = finest && (prof_on() & (zero ? kProfSweepZero : kProfJacobi));
         if (prof) NP_TRY(prof_begin(s, &tok));
-        if (zero)
+        if (D == 3 && !zero && lg >= 7 && g_tune.sweep3) {
+            constexpr int TX = 128;
+            const int zc = sweep3_planes(lg, TX, kPartials);
+            nb = unsigned((int64_t(1) << (3 * lg)) / (int64_t(kS3Threads) * zc));
+            if (partial)
+                hipLaunchKernelGGL((k_sweep3<S, true, TX>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
+                                   lg, bc, zc, inv_h2, wdiag, stop);
+            else
+                hipLaunchKernelGGL((k_sweep3<S, false, TX>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
+                                   lg, bc, zc, inv_h2, wdiag, stop);
+        } else if (zero)
             hipLaunchKernelGGL((k_sweep<D, S, true, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial, lg,
                                bc, inv_h2, wdiag, stop);
         else if (partial)
@@ -408,8 +419,16 @@ template <int D, class S> struct Ops {
             void *tok = nullptr;
             const bool prof = lg == H_lg_top && (prof_on() & kProfRestrict);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            hipLaunchKernelGGL((k_restrict<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, f, x, fc, lg, bc,
-                               C(1.0 / (h * h)), stop);
+            if (D == 3 && lg >= 7 && g_tune.sweep3) {
+                constexpr int TX = 128;
+                const int zc = sweep3_planes(lg, TX, kPartials);
+                const unsigned nb3 = unsigned((int64_t(1) << (3 * lg)) / (int64_t(kS3Threads) * zc));
+                hipLaunchKernelGGL((k_restrict3<S, TX>), dim3(nb3), dim3(kS3Threads), 0, s, f, x, fc, lg, bc, zc,
+                                   C(1.0 / (h * h)), stop);
+            } else {
+                hipLaunchKernelGGL((k_restrict<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, f, x, fc, lg, bc,
+                                   C(1.0 / (h * h)), stop);
+            }
             NP_LAUNCH_CHECK();
             if (prof) {
                 const double m = double(cells(D, lg));
@@ -852,15 +871,25 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         return st0;
     }
     NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
-    const unsigned nb = unsigned(std::min<int64_t>((m + kIrCells - 1) / kIrCells, kPartials));
+    const bool zm = D == 3 && H->lg >= 7 && g_tune.sweep3;  // z-marching refinement kernel
+    const int zc = zm ? sweep3_planes(H->lg, 128, kPartials) : 0;
+    const unsigned nb = zm ? unsigned(m / (int64_t(kS3Threads) * zc))
+                           : unsigned(std::min<int64_t>((m + kIrCells - 1) / kIrCells, kPartials));
     const int *stop = &H->ctl->stop;
     // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles
     auto step = [&](hipStream_t q, const double *xin, double *xout, int has_e) -> np_status {
         void *tok = nullptr;
         const bool prof = prof_on() & kProfRefine;
         if (prof) NP_TRY(prof_begin(q, &tok));
-        hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, q, xin, e, xout, f, rlo, H->red, H->lg,
-                           H->bc, 1.0 / (h * h), has_e, stop);
+        if (zm && has_e)
+            hipLaunchKernelGGL((k_ir_resid3<SL, 128, true>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
+                               H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
+        else if (zm)
+            hipLaunchKernelGGL((k_ir_resid3<SL, 128, false>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
+                               H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
+        else
+            hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, q, xin, e, xout, f, rlo, H->red,
+                               H->lg, H->bc, 1.0 / (h * h), has_e, stop);
         NP_LAUNCH_CHECK();
         if (prof) NP_TRY(prof_end(q, tok, double(m) * (has_e ? 8 + sizeof(SL) + 8 + 8 + sizeof(SL) : 8 + 8 + sizeof(SL))));
         hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, q, H->red, int(nb), H->ctl);
@@ -954,7 +983,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"fmin2", &g_tune.fmin2, 4, 1 << 14},   {"fmin3", &g_tune.fmin3, 4, 1 << 12},
         {"bz2", &g_tune.bz2, 0, 1 << 14},       {"bz3", &g_tune.bz3, 0, 1 << 12},
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
-        {"batch", &g_tune.batch, 1, 64},
+        {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
     };
     for (auto &e : tab)
@@ -988,6 +1017,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "inner_fp32")) return g_tune.inner_fp32;
     if (!std::strcmp(key, "inner_bf16")) return g_tune.inner_bf16;
     if (!std::strcmp(key, "batch")) return g_tune.batch;
+    if (!std::strcmp(key, "sweep3")) return g_tune.sweep3;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     return -1;

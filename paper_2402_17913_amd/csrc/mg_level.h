@@ -54,6 +54,245 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ f, const
     }
 }
 
+// ------------------------------------------------------------- z-marching
+// 2.5D blocking of 3D level kernels on n >= TX: a workgroup of kS3Threads
+// threads owns a TX x TY column tile and `zc` consecutive planes.  Each thread
+// keeps its column's values of the iterate at z-1, z, z+1 in registers; the
+// in-plane neighbours come from a double-buffered LDS copy of the plane with
+// a one-cell halo.  The loads of plane z+1 are issued before plane z is used,
+// and every lane issues the same loads on every plane (the z+1 value through
+// a clamped address and a sign, one halo cell per thread, threads without one
+// reloading their own cell, the plane after the last one clamped), so the
+// compiler can wait for the older loads only and keep the next plane in
+// flight.  Every value is read from HBM once (halo cells are L2 hits).
+// Workgroups are mapped XCD-contiguously.
+constexpr int kS3Threads = 512;
+
+template <class C, int TX>
+struct ZMarch {
+    static constexpr int TY = kS3Threads / TX;
+    static constexpr int NH = 2 * TY + 2 * TX;  // halo cells of a plane
+    static_assert(NH <= kS3Threads, "one halo cell per thread");
+    typedef C Plane[TY + 2][TX + 2];
+    int n, bc, tx, ty, i, j, k0, hy, hx;
+    int64_t P, col, hsrc;
+    bool hw;                  // this thread has a halo cell
+    C hsg;                    // its sign (-1: Dirichlet ghost)
+    C xm, xc, xp, hv;         // plane k: below, own, above, halo cell
+    C xpp, hn;                // prefetched for plane k + 1
+
+    __device__ ZMarch(int lg, int bc_, int zc) : n(1 << lg), bc(bc_) {
+        const int ntx = n / TX, nty = n / TY;
+        const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+        const int t = int(threadIdx.x);
+        tx = t % TX;
+        ty = t / TX;
+        const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
+        const int x0 = bx * TX, y0 = by * TY;
+        i = x0 + tx;
+        j = y0 + ty;
+        k0 = bz * zc;
+        P = int64_t(1) << (2 * lg);
+        col = (int64_t(j) << lg) + i;
+        // halo cell of thread t: x-halos (2 per row) first, then y-halos (2 per column)
+        hw = t < NH;
+        hy = ty + 1;
+        hx = tx + 1;
+        hsrc = col;
+        hsg = C(1);
+        if (hw) {
+            int gi, gj;
+            if (t < 2 * TY) {
+                hy = (t >> 1) + 1;
+                hx = (t & 1) ? TX + 1 : 0;
+                gj = y0 + hy - 1;
+                gi = (t & 1) ? x0 + TX : x0 - 1;
+            } else {
+                const int u = t - 2 * TY;
+                hx = (u >> 1) + 1;
+                hy = (u & 1) ? TY + 1 : 0;
+                gi = x0 + hx - 1;
+                gj = (u & 1) ? y0 + TY : y0 - 1;
+            }
+            // outside the grid: wrap (periodic) or the adjacent interior cell negated (Dirichlet)
+            const bool out = gi < 0 || gi >= n || gj < 0 || gj >= n;
+            if (gi < 0) gi = bc ? n - 1 : 0;
+            if (gi >= n) gi = bc ? 0 : n - 1;
+            if (gj < 0) gj = bc ? n - 1 : 0;
+            if (gj >= n) gj = bc ? 0 : n - 1;
+            if (out && !bc) hsg = C(-1);
+            hsrc = (int64_t(gj) << lg) + gi;
+        }
+    }
+    // offset of the value above plane k (z + 1) in the column, and its sign
+    __device__ __forceinline__ int64_t up_at(int k) const { return k < n - 1 ? (k + 1) * P : (bc ? 0 : k * P); }
+    __device__ __forceinline__ C up_sg(int k) const { return (k < n - 1 || bc) ? C(1) : C(-1); }
+    // next plane index, clamped to the grid (a harmless reload on the top plane)
+    __device__ __forceinline__ int next(int k) const { return k + 1 < n ? k + 1 : n - 1; }
+
+    template <class V>
+    __device__ __forceinline__ void start(const V &v) {
+        xc = v(k0 * P + col);
+        xm = k0 > 0 ? v((k0 - 1) * P + col) : (bc ? v((n - 1) * P + col) : -xc);
+        xp = up_sg(k0) * v(up_at(k0) + col);
+        hv = hsg * v(k0 * P + hsrc);
+    }
+    // issue the loads of plane k + 1
+    template <class V>
+    __device__ __forceinline__ void prefetch(const V &v, int k) {
+        const int kn = next(k);
+        xpp = up_sg(kn) * v(up_at(kn) + col);
+        hn = hsg * v(kn * P + hsrc);
+    }
+    // publish plane k to LDS buffer b and return the sum of its six face
+    // neighbours in the order x-, x+, y-, y+, z-, z+.  Two buffers and one
+    // barrier per plane: a thread writing a buffer again (plane k + 2) has
+    // passed plane k + 1's barrier, which follows every read of plane k.
+    __device__ __forceinline__ C neighbours(Plane &b) const {
+        b[ty + 1][tx + 1] = xc;
+        if (hw) b[hy][hx] = hv;
+        __syncthreads();
+        const C s = ((b[ty + 1][tx] + b[ty + 1][tx + 2]) + b[ty][tx + 1]) + b[ty + 2][tx + 1];
+        return (s + xm) + xp;
+    }
+    __device__ __forceinline__ void advance() {
+        xm = xc;
+        xc = xp;
+        xp = xpp;
+        hv = hn;
+    }
+};
+
+template <class S> struct LdC {
+    const S *p;
+    __device__ __forceinline__ typename St<S>::C operator()(int64_t q) const { return St<S>::ld(p + q); }
+};
+
+// 3D Jacobi sweep on the z-marching tiles (same arithmetic and summation order
+// as k_sweep).  NORM: per-workgroup partial of r^2.
+template <class S, bool NORM, int TX>
+__global__ __launch_bounds__(kS3Threads) void k_sweep3(const S *__restrict__ f, const S *__restrict__ xin,
+                                                       S *__restrict__ xout, double *__restrict__ partial, int lg,
+                                                       int bc, int zc, typename St<S>::C inv_h2,
+                                                       typename St<S>::C wdiag, const int *stop) {
+    typedef typename St<S>::C C;
+    typedef ZMarch<C, TX> Z;
+    __shared__ typename Z::Plane pl[2];
+    if (stop && *stop) return;
+    Z z(lg, bc, zc);
+    const LdC<S> v{xin};
+    z.start(v);
+    C fc = St<S>::ld(f + z.k0 * z.P + z.col);
+    double acc = 0.0;
+    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
+        z.prefetch(v, k);
+        const C fn = St<S>::ld(f + z.next(k) * z.P + z.col);
+        const C s = z.neighbours(pl[q]);
+        const C r = fc - (C(6) * z.xc - s) * inv_h2;
+        if (NORM) acc += double(r) * double(r);
+        St<S>::st(xout + k * z.P + z.col, z.xc + wdiag * r);
+        z.advance();
+        fc = fn;
+    }
+    if (NORM) {
+        acc = block_sum_n<kS3Threads>(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
+// Residual + restriction on the z-marching tiles: each thread sums the
+// residuals of its column over a pair of planes, then one thread per 2 x 2
+// column group adds the four pair sums (through LDS) and writes the coarse
+// cell, 2^-3 times the sum of its eight children.  zc even.
+template <class S, int TX>
+__global__ __launch_bounds__(kS3Threads) void k_restrict3(const S *__restrict__ f, const S *__restrict__ x,
+                                                          S *__restrict__ fc, int lg, int bc, int zc,
+                                                          typename St<S>::C inv_h2, const int *stop) {
+    typedef typename St<S>::C C;
+    typedef ZMarch<C, TX> Z;
+    __shared__ typename Z::Plane pl[2];
+    __shared__ C rs[Z::TY][TX];
+    if (stop && *stop) return;
+    Z z(lg, bc, zc);
+    const LdC<S> v{x};
+    z.start(v);
+    const int lgc = lg - 1;
+    C f0 = St<S>::ld(f + z.k0 * z.P + z.col);
+    C pair = C(0);
+    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
+        z.prefetch(v, k);
+        const C fn = St<S>::ld(f + z.next(k) * z.P + z.col);
+        const C s = z.neighbours(pl[q]);
+        const C r = f0 - (C(6) * z.xc - s) * inv_h2;
+        if (((k - z.k0) & 1) == 0) {
+            pair = r;
+        } else {
+            pair += r;
+            rs[z.ty][z.tx] = pair;
+            __syncthreads();
+            if (((z.tx | z.ty) & 1) == 0) {
+                const C t = ((rs[z.ty][z.tx] + rs[z.ty][z.tx + 1]) + rs[z.ty + 1][z.tx]) + rs[z.ty + 1][z.tx + 1];
+                const int64_t cc = ((int64_t(k >> 1) << (2 * lgc)) | (int64_t(z.j >> 1) << lgc)) + (z.i >> 1);
+                St<S>::st(fc + cc, t * C(0.125));
+            }
+            // rs is written again two planes later, after plane k + 1's barrier
+        }
+        z.advance();
+        f0 = fn;
+    }
+}
+
+// Refinement step of the mixed path on the z-marching tiles (see
+// k_ir_resid): x_out = x + e (HAS_E; else x_out is not written and e is not
+// read), r = f - A x_out in FP64, r_lo = r rounded, per-workgroup partial of
+// r^2.
+template <class SL, int TX, bool HAS_E>
+__global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restrict__ x, const SL *__restrict__ e,
+                                                          double *__restrict__ xout, const double *__restrict__ f,
+                                                          SL *__restrict__ rlo, double *__restrict__ partial,
+                                                          int lg, int bc, int zc, double inv_h2,
+                                                          const int *stop) {
+    typedef ZMarch<double, TX> Z;
+    __shared__ typename Z::Plane pl[2];
+    if (stop && *stop) return;
+    Z z(lg, bc, zc);
+    struct {
+        const double *x;
+        const SL *e;
+        __device__ __forceinline__ double operator()(int64_t q) const {
+            return HAS_E ? x[q] + double(St<SL>::ld(e + q)) : x[q];
+        }
+    } v{x, e};
+    z.start(v);
+    double fc = f[z.k0 * z.P + z.col];
+    double acc = 0.0;
+    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
+        z.prefetch(v, k);
+        const double fn = f[z.next(k) * z.P + z.col];
+        const double s = z.neighbours(pl[q]);
+        const double r = fc - (6.0 * z.xc - s) * inv_h2;
+        const int64_t c = k * z.P + z.col;
+        if (HAS_E) xout[c] = z.xc;
+        St<SL>::st(rlo + c, typename St<SL>::C(r));
+        acc += r * r;
+        z.advance();
+        fc = fn;
+    }
+    acc = block_sum_n<kS3Threads>(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Planes per workgroup of k_sweep3 on an n^3 level: enough workgroups to fill
+// the chip, and at most `max_blocks` of them (one norm partial each).
+inline int sweep3_planes(int lg, int tx, int64_t max_blocks) {
+    const int n = 1 << lg;
+    const int64_t cols = int64_t(n) * n / kS3Threads;  // column tiles
+    int zc = n >= 256 ? 8 : 4;
+    while (cols * (n / zc) > max_blocks && zc < n) zc *= 2;
+    (void)tx;
+    return zc;
+}
+
 // Fine cells per workgroup along x in k_restrict.
 template <int D> struct RBlk {
     static constexpr int FX = D == 3 ? 64 : 128;

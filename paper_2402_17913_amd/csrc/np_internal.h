@@ -74,10 +74,12 @@ inline size_t prec_bytes(np_prec p) { return p == NP_FP64 ? 8 : (p == NP_FP32 ? 
 constexpr int kRedBlocks = 1024;  // fixed partial count: deterministic reduction order
 constexpr int kBlock = 256;
 
-// Sum over a 64-wide wavefront (xor butterfly), then over the waves of the block
-// through LDS; the result is valid in thread 0.  Fixed order: deterministic.
-__device__ __forceinline__ double block_sum(double v) {
-    __shared__ double wsum[kBlock / 64];
+// Sum over a 64-wide wavefront (xor butterfly), then over the NT / 64 waves of
+// the block (blockDim.x == NT) through LDS; the result is valid in thread 0.
+// Fixed order: deterministic.
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v) {
+    __shared__ double wsum[NT / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -85,10 +87,11 @@ __device__ __forceinline__ double block_sum(double v) {
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += wsum[i];
+        for (int i = 0; i < NT / 64; ++i) s += wsum[i];
     __syncthreads();
     return s;
 }
+__device__ __forceinline__ double block_sum(double v) { return block_sum_n<kBlock>(v); }
 
 // XCD-aware workgroup order.  The dispatcher hands workgroup i to XCD i mod 8;
 // remapping ids so that XCD x runs the contiguous range [x G/8, (x+1) G/8)

@@ -117,6 +117,41 @@ def test_kernel_variants_agree(B, orc, knobs):
             B.np_set_tuning(k, v)
 
 
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_sweep3_matches_direct_sweep(B, orc, bc):
+    """The z-marching 3D sweep (levels of n >= 128) and the direct sweep give the
+    same solves on every precision path (FP64 to 1e-13 after fixed cycles, the
+    mixed paths to their rounding with the same cycle counts), and the FP64 result
+    matches the oracle."""
+    n = 128
+    rng = np.random.default_rng(77 + bc)
+    f = rng.standard_normal((n, n, n))
+    if bc == PER:
+        f -= f.mean()
+    h = 1.0 / n
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("sweep3", v)
+            for prec in (B.FP64, B.FP32, B.BF16):
+                say("sweep3", v, bc, prec)
+                xg = dev(np.zeros_like(f))
+                kw = dict(fixed_cycles=4) if prec == B.FP64 else {}
+                st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, smooth_prec=prec, **kw)
+                out[(v, prec)] = (host(xg), stats)
+    finally:
+        B.np_set_tuning("sweep3", 1)
+    ref = orc.mg_solve(f, h, bc, fixed_cycles=4)
+    assert rel(out[(1, B.FP64)][0], ref.x) < 1e-12
+    assert rel(out[(1, B.FP64)][0], out[(0, B.FP64)][0]) < 1e-13
+    for prec in (B.FP32, B.BF16):
+        a, sa = out[(1, prec)]
+        b, sb = out[(0, prec)]
+        assert sa["cycles"] == sb["cycles"] and sa["outer_iters"] == sb["outer_iters"]
+        assert orc.rel_res(f, a, h, bc) <= 1e-10
+        assert rel(a, b) < 1e-8
+
+
 def test_tuning_knobs_validate(B):
     with pytest.raises(B.NeuphysError):
         B.np_set_tuning("no_such_knob", 1)
