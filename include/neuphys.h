@@ -285,12 +285,13 @@ np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
 
 /* Tuning knobs (process-wide; used by the autotuner): "fused" (0/1: fused
  * level kernels for V(2,2)), "graphs" (0/1: replay cycles from HIP graphs),
- * "fmin2"/"fmin3" (smallest level size handled by fused kernels), "bz2"/"bz3"
+ * "fmin2"/"fmin3" and "fmax2"/"fmax3" (smallest and largest level size
+ * handled by fused kernels), "bz2"/"bz3"
  * (even number of planes per workgroup in fused kernels, 0 = automatic),
  * "inner_fp32"/"inner_bf16" (default inner cycles per refinement step),
  * "batch" (cycles enqueued before the first host read of the convergence
- * state), "sweep3" (0/1: z-marching smoothing, restriction and refinement
- * kernels on 3D levels of n >= 128), "batched_graphs" and "batched_autotune" (0/1 for the batched
+ * state), "sweep3" (0/1: z-marching smoothing, restriction, prolongation
+ * and refinement kernels on 3D levels of n >= 128), "batched_graphs" and "batched_autotune" (0/1 for the batched
  * solver).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
  * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */
 np_status np_set_tuning(const char *key, int value);

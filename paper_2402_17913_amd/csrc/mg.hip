@@ -105,12 +105,14 @@ struct Tuning {
     int graphs = 1;       // replay cycles from captured HIP graphs
     int fmin2 = 32;       // smallest 2D level handled by fused kernels
     int fmin3 = 16;       // smallest 3D level handled by fused kernels
+    int fmax2 = 1 << 14;  // largest 2D level handled by fused kernels
+    int fmax3 = 1 << 12;  // largest 3D level handled by fused kernels
     int bz2 = 0;          // rows per workgroup in 2D fused kernels (0 = automatic)
     int bz3 = 0;          // planes per workgroup in 3D fused kernels (0 = automatic)
     int inner_fp32 = 3;   // default inner cycles per refinement step
     int inner_bf16 = 2;
     int batch = 4;        // first batch of cycles enqueued before reading the controller
-    int sweep3 = 1;       // z-marching sweep, restriction and refinement kernels on 3D levels of n >= 128
+    int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
 };
 static Tuning g_tune;
 
@@ -123,7 +125,7 @@ constexpr int kPartials = 65536;
 constexpr unsigned kNormBlocks = 2048;  // workgroups of a sweep that also reduces the residual norm  // per-workgroup partial sums (fixed order)
 
 struct GraphKey {
-    int kind;  // 0: FP64 cycle, 1: mixed first step, 2: mixed step a->b, 3: mixed step b->a
+    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles
     int zero0, check;
     const void *x, *f;
     double h;
@@ -461,8 +463,14 @@ template <int D, class S> struct Ops {
         void *tok = nullptr;
         const bool prof = lgc + 1 == H_lg_top && (prof_on() & kProfProlong);
         if (prof) NP_TRY(prof_begin(s, &tok));
-        hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc,
-                           stop);
+        if (D == 3 && lgc + 1 >= 7 && g_tune.sweep3) {
+            const int lg = lgc + 1, zc = sweep3_planes(lg, 128, kPartials);
+            hipLaunchKernelGGL((k_prolong3<S, 128>), dim3(unsigned(m / (int64_t(kS3Threads) * zc))),
+                               dim3(kS3Threads), 0, s, ec, x, lg, bc, zc, stop);
+        } else {
+            hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc,
+                               stop);
+        }
         NP_LAUNCH_CHECK();
         if (prof) NP_TRY(prof_end(s, tok, double(m) * 2 * sizeof(S) + double(m) / (1 << D) * sizeof(S)));
         return NP_OK;
@@ -561,6 +569,7 @@ template <int D, class S> struct Ops {
         H_lg_top = H->lg;
         const bool fz = g_tune.fused && o.nu1 == 2 && o.nu2 == 2;
         const int fmin = D == 3 ? g_tune.fmin3 : g_tune.fmin2;
+        const int fmax = D == 3 ? g_tune.fmax3 : g_tune.fmax2;
         std::vector<S *> cur(L + 1), oth(L + 1), res(L + 1);
         std::vector<const S *> F(L + 1);
         std::vector<bool> fl(L + 1);
@@ -568,7 +577,7 @@ template <int D, class S> struct Ops {
             cur[l] = l == 0 ? x0 : (S *)H->x[l];
             oth[l] = l == 0 ? t0 : (S *)H->t[l];
             F[l] = l == 0 ? f0 : (const S *)H->f[l];
-            fl[l] = fz && l < L && (1 << (H->lg - l)) >= fmin;
+            fl[l] = fz && l < L && (1 << (H->lg - l)) >= fmin && (1 << (H->lg - l)) <= fmax;
         }
         int tl = 0;  // level handed to the one-workgroup tail (0 = none)
         if (g_tune.tail && o.nu1 >= 1)
@@ -807,15 +816,20 @@ static void fill_stats(np_mg_stats *st, const Ctl &c, int cycles, int outer) {
                       ? std::pow(c.hist[n - 1] / c.hist[0], 1.0 / (n - 1)) : 0.0;
 }
 
-// How many more cycles to enqueue before reading the controller again.
-static int next_batch(const Ctl &c, const np_mg_opts &o) {
-    if (o.fixed_cycles > 0) return std::max(1, o.fixed_cycles - c.k + 1);
+// How many more cycles (or refinement steps) to enqueue before reading the
+// controller again: the steps the last contraction factor predicts down to
+// tol, plus `tail` when the check of the last one runs only at the start of
+// the next (check_last = false).  An under-estimate costs one host round
+// trip; an over-estimate enqueues steps that run as no-ops.
+static int next_batch(const Ctl &c, const np_mg_opts &o, bool check_last) {
+    const int tail = check_last ? 0 : 1;
+    if (o.fixed_cycles > 0) return std::max(1, o.fixed_cycles - c.k + tail);
     const int n = c.nhist;
     if (n < 2 || !(c.hist[n - 1] > 0.0) || !(c.hist[n - 2] > 0.0)) return g_tune.batch;
     double rho = c.hist[n - 1] / c.hist[n - 2];
     rho = std::min(0.95, std::max(0.02, rho));
     const double need = std::log(c.tol / c.hist[n - 1]) / std::log(rho);
-    int b = int(std::ceil(need)) + 1;
+    int b = int(std::ceil(need)) + tail;
     return std::max(1, std::min(b, 32));
 }
 
@@ -845,7 +859,7 @@ static np_status solve_fp64(Hier *H, const double *f, double *x, double h, doubl
             NP_TRY(run_graph(H, key, s, [&](hipStream_t q) { return O::cycle(H, x, f, t0, false, true, h, co, q); }));
         NP_TRY(read_ctl(H, s));
         if (H->hctl->stop) break;
-        batch = next_batch(*H->hctl, o);
+        batch = next_batch(*H->hctl, o, false);
     }
     const Ctl c = *H->hctl;
     fill_stats(stats, c, c.k, c.k);
@@ -894,17 +908,26 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         if (prof) NP_TRY(prof_end(q, tok, double(m) * (has_e ? 8 + sizeof(SL) + 8 + 8 + sizeof(SL) : 8 + 8 + sizeof(SL))));
         hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, q, H->red, int(nb), H->ctl);
         NP_LAUNCH_CHECK();
+        return NP_OK;
+    };
+    // the inner cycles of one step: e from the rounded residual
+    auto cycles = [&](hipStream_t q) -> np_status {
         for (int c = 0; c < inner; ++c) NP_TRY(O::cycle(H, e, rlo, tt, c == 0, false, h, co, q));
         return NP_OK;
     };
+    // graphs: the first update (x = x0), the updates a -> b and b -> a, the inner cycles;
+    // every batch ends with an update and its check, so that a converged solve
+    // enqueues no further cycles
     GraphKey k1{1, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     GraphKey ka{2, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     GraphKey kb{3, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    GraphKey kc{4, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     NP_TRY(run_graph(H, k1, s, [&](hipStream_t q) { return step(q, xa, nullptr, 0); }));
     int launched = 1;
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles : std::max(1, g_tune.batch / 2);
     for (;;) {
         for (int b = 0; b < batch; ++b, ++launched) {
+            NP_TRY(run_graph(H, kc, s, cycles));
             if (launched & 1)
                 NP_TRY(run_graph(H, ka, s, [&](hipStream_t q) { return step(q, xa, xb, 1); }));
             else
@@ -912,7 +935,7 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         }
         NP_TRY(read_ctl(H, s));
         if (H->hctl->stop) break;
-        batch = next_batch(*H->hctl, o);
+        batch = next_batch(*H->hctl, o, true);
     }
     const Ctl c = *H->hctl;
     // the iterate whose residual was checked last: x_a after an even number of updates
@@ -981,6 +1004,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"fused", &g_tune.fused, 0, 1},         {"graphs", &g_tune.graphs, 0, 1},
         {"tail", &g_tune.tail, 0, 1},
         {"fmin2", &g_tune.fmin2, 4, 1 << 14},   {"fmin3", &g_tune.fmin3, 4, 1 << 12},
+        {"fmax2", &g_tune.fmax2, 4, 1 << 14},   {"fmax3", &g_tune.fmax3, 4, 1 << 12},
         {"bz2", &g_tune.bz2, 0, 1 << 14},       {"bz3", &g_tune.bz3, 0, 1 << 12},
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
@@ -1012,6 +1036,8 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "tail")) return g_tune.tail;
     if (!std::strcmp(key, "fmin2")) return g_tune.fmin2;
     if (!std::strcmp(key, "fmin3")) return g_tune.fmin3;
+    if (!std::strcmp(key, "fmax2")) return g_tune.fmax2;
+    if (!std::strcmp(key, "fmax3")) return g_tune.fmax3;
     if (!std::strcmp(key, "bz2")) return g_tune.bz2;
     if (!std::strcmp(key, "bz3")) return g_tune.bz3;
     if (!std::strcmp(key, "inner_fp32")) return g_tune.inner_fp32;

@@ -282,6 +282,78 @@ __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restri
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// x += P ec on the z-marching tiles (fine level lg, n >= TX).  The workgroup
+// keeps the coarse planes K-1, K, K+1 of its tile (with a one-cell halo,
+// ghost values already carrying the boundary rule: wrapped, or the adjacent
+// interior cell negated per axis for Dirichlet) in an LDS ring; each thread
+// updates its column on fine planes 2K and 2K+1 from eight LDS values, while
+// the coarse plane K+2 is in flight (one coarse cell per thread, clamped
+// loads).  Weights 3/4 (own coarse cell) and 1/4 (neighbour) per axis.
+template <class S, int TX>
+__global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ ec, S *__restrict__ x, int lg, int bc,
+                                                         int zc, const int *stop) {
+    typedef typename St<S>::C C;
+    constexpr int TY = kS3Threads / TX, CX = TX / 2 + 2, CY = TY / 2 + 2;
+    static_assert(CX * CY <= kS3Threads, "one coarse cell per thread");
+    __shared__ C cp[3][CY][CX];
+    if (stop && *stop) return;
+    const int n = 1 << lg, nc = n >> 1, lgc = lg - 1, ntx = n / TX, nty = n / TY;
+    const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+    const int t = int(threadIdx.x), tx = t % TX, ty = t / TX;
+    const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
+    const int x0 = bx * TX, y0 = by * TY, k0 = bz * zc, K0 = k0 >> 1;
+    const int64_t P = int64_t(1) << (2 * lg), col = (int64_t(y0 + ty) << lg) + x0 + tx;
+    // coarse cell loaded by this thread: (cx, cy) in the tile, source column and sign
+    const bool cw = t < CX * CY;
+    const int cx = t % CX, cy = t / CX;
+    int gi = (x0 >> 1) - 1 + cx, gj = (y0 >> 1) - 1 + cy;
+    C csg = C(1);
+    if (gi < 0) { gi = bc ? nc - 1 : 0; if (!bc) csg = -csg; }
+    if (gi >= nc) { gi = bc ? 0 : nc - 1; if (!bc) csg = -csg; }
+    if (gj < 0) { gj = bc ? nc - 1 : 0; if (!bc) csg = -csg; }
+    if (gj >= nc) { gj = bc ? 0 : nc - 1; if (!bc) csg = -csg; }
+    const int64_t csrc = cw ? (int64_t(gj) << lgc) + gi : 0;
+    const int64_t Pc = int64_t(1) << (2 * lgc);
+    // value of coarse plane K (any K in [-1, nc]) at this thread's coarse cell
+    auto cload = [&](int K) -> C {
+        C sg = csg;
+        int kk = K;
+        if (kk < 0) { kk = bc ? nc - 1 : 0; if (!bc) sg = -sg; }
+        if (kk >= nc) { kk = bc ? 0 : nc - 1; if (!bc) sg = -sg; }
+        return sg * St<S>::ld(ec + kk * Pc + csrc);
+    };
+    auto slot = [](int K) { return (K + 3) % 3; };
+    {
+        const C a = cload(K0 - 1), b = cload(K0), c = cload(K0 + 1);
+        if (cw) {
+            cp[slot(K0 - 1)][cy][cx] = a;
+            cp[slot(K0)][cy][cx] = b;
+            cp[slot(K0 + 1)][cy][cx] = c;
+        }
+    }
+    __syncthreads();
+    // own coarse cell in the tile and the neighbour side per axis
+    const int lx = (tx >> 1) + 1, ly = (ty >> 1) + 1;
+    const int nx = lx + ((tx & 1) ? 1 : -1), ny = ly + ((ty & 1) ? 1 : -1);
+    const C w0 = C(0.75), w1 = C(0.25);
+    for (int K = K0; K < K0 + (zc >> 1); ++K) {
+        const int64_t c0 = int64_t(2 * K) * P + col, c1 = c0 + P;
+        const C xa = St<S>::ld(x + c0), xb = St<S>::ld(x + c1);
+        const C nxt = cload(K + 2);  // ring slot of K - 1 after this plane pair
+        const C(&own)[CY][CX] = cp[slot(K)];
+        // in-plane bilinear value of a coarse plane at this column
+        auto bil = [&](const C(&pl)[CY][CX]) -> C {
+            return w0 * (w0 * pl[ly][lx] + w1 * pl[ly][nx]) + w1 * (w0 * pl[ny][lx] + w1 * pl[ny][nx]);
+        };
+        const C eo = bil(own), em = bil(cp[slot(K - 1)]), ep = bil(cp[slot(K + 1)]);
+        St<S>::st(x + c0, xa + (w0 * eo + w1 * em));  // fine plane 2K: neighbour plane K - 1
+        St<S>::st(x + c1, xb + (w0 * eo + w1 * ep));  // fine plane 2K + 1: neighbour plane K + 1
+        __syncthreads();  // every read of slot(K - 1) is done
+        if (cw) cp[slot(K + 2)][cy][cx] = nxt;
+        __syncthreads();
+    }
+}
+
 // Planes per workgroup of k_sweep3 on an n^3 level: enough workgroups to fill
 // the chip, and at most `max_blocks` of them (one norm partial each).
 inline int sweep3_planes(int lg, int tx, int64_t max_blocks) {
