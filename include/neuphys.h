@@ -291,7 +291,8 @@ np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
  * "inner_fp32"/"inner_bf16" (default inner cycles per refinement step),
  * "batch" (cycles enqueued before the first host read of the convergence
  * state), "sweep3" (0/1: z-marching smoothing, restriction, prolongation
- * and refinement kernels on 3D levels of n >= 128), "batched_graphs" and "batched_autotune" (0/1 for the batched
+ * and refinement kernels on 3D levels of n >= 128), "zero2" (0/1: the first
+ * two sweeps from a zero iterate in one pass), "batched_graphs" and "batched_autotune" (0/1 for the batched
  * solver).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
  * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */
 np_status np_set_tuning(const char *key, int value);

@@ -113,6 +113,7 @@ struct Tuning {
     int inner_bf16 = 2;
     int batch = 4;        // first batch of cycles enqueued before reading the controller
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
+    int zero2 = 1;        // first two sweeps from a zero iterate in one pass
 };
 static Tuning g_tune;
 
@@ -378,28 +379,36 @@ template <int D, class S> struct Ops {
 
     // Jacobi sweep used inside cycles; with partial != null it also reduces
     // ||f - A x_in||^2 into one partial per workgroup (count in *np).
-    static np_status sweep(const S *f, const S *xin, S *xout, int lg, int bc, double h, double omega, bool zero,
+    // zmode 0: one sweep of xin; 1: the sweep from a zero iterate (x = w f);
+    // 2: the first two sweeps from a zero iterate in one pass (xin unused).
+    static np_status sweep(const S *f, const S *xin, S *xout, int lg, int bc, double h, double omega, int zmode,
                            double *partial, int *np, hipStream_t s, bool finest, const int *stop) {
         const int64_t m = cells(D, lg);
         const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
         unsigned nb = unsigned((m + kSweepCells - 1) / kSweepCells);
         if (partial) nb = std::min<unsigned>(nb, kNormBlocks);  // few partials: a cheap check
         void *tok = nullptr;
-        const bool prof = finest && (prof_on() & (zero ? kProfSweepZero : kProfJacobi));
+        const bool prof = finest && (prof_on() & (zmode ? kProfSweepZero : kProfJacobi));
         if (prof) NP_TRY(prof_begin(s, &tok));
-        if (D == 3 && !zero && lg >= 7 && g_tune.sweep3) {
+        if (D == 3 && zmode != 1 && lg >= 7 && g_tune.sweep3) {
             constexpr int TX = 128;
             const int zc = sweep3_planes(lg, TX, kPartials);
             nb = unsigned((int64_t(1) << (3 * lg)) / (int64_t(kS3Threads) * zc));
-            if (partial)
+            if (zmode == 2)
+                hipLaunchKernelGGL((k_sweep3<S, false, TX, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout,
+                                   partial, lg, bc, zc, inv_h2, wdiag, stop);
+            else if (partial)
                 hipLaunchKernelGGL((k_sweep3<S, true, TX>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
                                    lg, bc, zc, inv_h2, wdiag, stop);
             else
                 hipLaunchKernelGGL((k_sweep3<S, false, TX>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
                                    lg, bc, zc, inv_h2, wdiag, stop);
-        } else if (zero)
+        } else if (zmode == 1)
             hipLaunchKernelGGL((k_sweep<D, S, true, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial, lg,
                                bc, inv_h2, wdiag, stop);
+        else if (zmode == 2)
+            hipLaunchKernelGGL((k_sweep<D, S, false, false, true>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout,
+                               partial, lg, bc, inv_h2, wdiag, stop);
         else if (partial)
             hipLaunchKernelGGL((k_sweep<D, S, false, true>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial,
                                lg, bc, inv_h2, wdiag, stop);
@@ -407,7 +416,7 @@ template <int D, class S> struct Ops {
             hipLaunchKernelGGL((k_sweep<D, S, false, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial,
                                lg, bc, inv_h2, wdiag, stop);
         NP_LAUNCH_CHECK();
-        if (prof) NP_TRY(prof_end(s, tok, double(m) * sizeof(S) * (zero ? 2 : 3)));
+        if (prof) NP_TRY(prof_end(s, tok, double(m) * sizeof(S) * (zmode ? 2 : 3)));
         if (np) *np = int(nb);
         return NP_OK;
     }
@@ -621,14 +630,17 @@ template <int D, class S> struct Ops {
             }
             for (int it = 0; it < o.nu1; ++it) {
                 const bool ck = check && l == 0 && !zero && it == 0;  // residual of the input iterate
+                // from a zero iterate: the first two sweeps in one pass where there are two
+                const int zm = zf && it == 0 ? (o.nu1 >= 2 && g_tune.zero2 ? 2 : 1) : 0;
                 int nb = 0;
-                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, zf && it == 0, ck ? H->red : nullptr, &nb, s,
-                             l == 0, stop));
+                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, zm, ck ? H->red : nullptr, &nb, s, l == 0,
+                             stop));
                 if (ck) {
                     hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
                     NP_LAUNCH_CHECK();
                 }
                 std::swap(cur[l], oth[l]);
+                if (zm == 2) ++it;
             }
             NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
             if (l + 1 == tl) { hl *= 2.0; break; }
@@ -663,7 +675,7 @@ template <int D, class S> struct Ops {
             }
             NP_TRY(prolong_add(res[l + 1], cur[l], lg - 1, bc, s, stop));
             for (int it = 0; it < o.nu2; ++it) {
-                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, false, nullptr, nullptr, s, l == 0, stop));
+                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, 0, nullptr, nullptr, s, l == 0, stop));
                 std::swap(cur[l], oth[l]);
             }
             res[l] = cur[l];
@@ -1008,6 +1020,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"bz2", &g_tune.bz2, 0, 1 << 14},       {"bz3", &g_tune.bz3, 0, 1 << 12},
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
+        {"zero2", &g_tune.zero2, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
     };
     for (auto &e : tab)
@@ -1044,6 +1057,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "inner_bf16")) return g_tune.inner_bf16;
     if (!std::strcmp(key, "batch")) return g_tune.batch;
     if (!std::strcmp(key, "sweep3")) return g_tune.sweep3;
+    if (!std::strcmp(key, "zero2")) return g_tune.zero2;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     return -1;

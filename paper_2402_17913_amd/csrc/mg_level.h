@@ -1,7 +1,12 @@
 // Level kernels of the default (unfused) multigrid path, tuned for gfx950:
 //  - k_sweep:     one weighted-Jacobi sweep, two cells per thread, optionally
 //                 reducing ||f - A x_in||^2 of its input (the residual the sweep
-//                 computes anyway) into one partial sum per workgroup;
+//                 computes anyway) into one partial sum per workgroup; ZERO:
+//                 the sweep from a zero iterate (x = w f); ZERO2: the first two
+//                 sweeps from a zero iterate in one pass (the iterate after the
+//                 first, w f, is formed on the fly from f);
+//  - k_sweep3, k_restrict3, k_prolong3, k_ir_resid3: the same operations on
+//                 3D levels of n >= 128 with 2.5D (z-marching) blocking;
 //  - k_restrict:  residual and 2^d-cell average with coalesced fine-grid reads:
 //                 a workgroup owns a 64 x 2 x 2 (3D) / 128 x 2 (2D) block of fine
 //                 cells, each thread one residual, children summed through LDS;
@@ -10,6 +15,8 @@
 // Arithmetic per cell is that of mg_kernels.h (same expressions and orders).
 #pragma once
 
+#include <type_traits>
+
 #include "mg_kernels.h"
 #include "np_internal.h"
 
@@ -17,7 +24,15 @@ namespace np {
 
 constexpr int kSweepCells = 2 * kBlock;  // cells per workgroup of k_sweep
 
-template <int D, class S, bool ZERO, bool NORM>
+// Iterate w f read through a functor: the state after a first sweep from a
+// zero iterate, formed on the fly (ZERO2 kernels fuse that sweep and the next).
+template <class S> struct LdW {
+    const S *f;
+    typename St<S>::C w;
+    __device__ __forceinline__ typename St<S>::C operator()(int64_t q) const { return w * St<S>::ld(f + q); }
+};
+
+template <int D, class S, bool ZERO, bool NORM, bool ZERO2 = false>
 __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ f, const S *__restrict__ xin,
                                                   S *__restrict__ xout, double *__restrict__ partial, int lg,
                                                   int bc, typename St<S>::C inv_h2, typename St<S>::C wdiag,
@@ -40,8 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ f, const
             } else {
                 int i, j, k;
                 decode<D>(c, lg, i, j, k);
-                const C xc = St<S>::ld(xin + c);
-                const C s = nb_sum<D, C>(Ld<S>{xin}, c, i, j, k, lg, bc, xc);
+                const C xc = ZERO2 ? wdiag * fc : St<S>::ld(xin + c);
+                const C s = ZERO2 ? nb_sum<D, C>(LdW<S>{f, wdiag}, c, i, j, k, lg, bc, xc)
+                                  : nb_sum<D, C>(Ld<S>{xin}, c, i, j, k, lg, bc, xc);
                 const C r = fc - (C(2 * D) * xc - s) * inv_h2;
                 if (NORM) acc += double(r) * double(r);
                 St<S>::st(xout + c, xc + wdiag * r);
@@ -169,8 +185,9 @@ template <class S> struct LdC {
 };
 
 // 3D Jacobi sweep on the z-marching tiles (same arithmetic and summation order
-// as k_sweep).  NORM: per-workgroup partial of r^2.
-template <class S, bool NORM, int TX>
+// as k_sweep).  NORM: per-workgroup partial of r^2.  ZERO2: the first two
+// sweeps from a zero iterate (xin is not read).
+template <class S, bool NORM, int TX, bool ZERO2 = false>
 __global__ __launch_bounds__(kS3Threads) void k_sweep3(const S *__restrict__ f, const S *__restrict__ xin,
                                                        S *__restrict__ xout, double *__restrict__ partial, int lg,
                                                        int bc, int zc, typename St<S>::C inv_h2,
@@ -180,7 +197,10 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep3(const S *__restrict__ f, 
     __shared__ typename Z::Plane pl[2];
     if (stop && *stop) return;
     Z z(lg, bc, zc);
-    const LdC<S> v{xin};
+    typedef typename std::conditional<ZERO2, LdW<S>, LdC<S>>::type V;
+    V v;
+    if constexpr (ZERO2) v = V{f, wdiag};
+    else v = V{xin};
     z.start(v);
     C fc = St<S>::ld(f + z.k0 * z.P + z.col);
     double acc = 0.0;

@@ -89,16 +89,18 @@ def test_one_vcycle(B, orc, d, n, bc):
 
 
 @pytest.mark.parametrize("knobs", [dict(fused=1), dict(graphs=0), dict(fused=1, bz3=2, bz2=2),
-                                   dict(fused=1, fmin2=4, fmin3=4), dict(tail=0), dict(fused=1, tail=0)])
+                                   dict(fused=1, fmin2=4, fmin3=4), dict(tail=0), dict(fused=1, tail=0),
+                                   dict(zero2=0), dict(sweep3=0, zero2=0), dict(fused=1, fmax2=64, fmax3=32)])
 def test_kernel_variants_agree(B, orc, knobs):
-    """Fused level kernels (also with the smallest marching chunks and down to 4^d),
-    direct launches and the per-level kernels without the one-workgroup tail all give
-    the oracle's cycles."""
+    """Fused level kernels (also with the smallest marching chunks, down to 4^d, and
+    on a range of levels only), direct launches, the per-level kernels without the
+    one-workgroup tail, separate sweeps from a zero iterate and the direct 3D
+    kernels all give the oracle's cycles."""
     old = {k: B.np_get_tuning(k) for k in knobs}
     try:
         for k, v in knobs.items():
             B.np_set_tuning(k, v)
-        for d, n, bc in [(2, 64, DIR), (2, 256, PER), (3, 32, PER), (3, 64, DIR)]:
+        for d, n, bc in [(2, 64, DIR), (2, 256, PER), (3, 32, PER), (3, 64, DIR), (3, 128, PER)]:
             say("variant", knobs, d, n, bc)
             rng = np.random.default_rng(n + d)
             h = 1.0 / n
