@@ -1286,6 +1286,58 @@ extern "C" np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double
     return NP_OK;
 }
 
+// Back-to-back launches of the level sweep the solver uses on this grid (same
+// kernel and launch shape), y = sweep(x), between two events on the stream.
+template <int D, class S>
+static np_status time_sweep(const void *f, const void *x, void *y, int lg, int bc, double h, int reps,
+                            hipStream_t s, double *avg_ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    NP_HIP_TRY(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        set_error("hipEventCreate failed");
+        return NP_EHIP;
+    }
+    np_status st = NP_OK;
+    auto run = [&]() -> np_status {
+        NP_TRY((Ops<D, S>::sweep((const S *)f, (const S *)x, (S *)y, lg, bc, h, 2.0 / 3.0, 0, nullptr, nullptr, s,
+                                 false, nullptr)));
+        return NP_OK;
+    };
+    st = run();  // warm-up
+    if (st == NP_OK && hipEventRecord(a, s) != hipSuccess) st = NP_EHIP;
+    for (int r = 0; r < reps && st == NP_OK; ++r) st = run();
+    float ms = 0.f;
+    if (st == NP_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                        hipEventElapsedTime(&ms, a, b) != hipSuccess))
+        st = NP_EHIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st == NP_EHIP) set_error("event timing failed");
+    if (st == NP_OK) *avg_ms = double(ms) / reps;
+    return st;
+}
+
+extern "C" np_status np_prof_sweep(np_dims dims, double h, np_bc bc, np_prec prec, const void *f, const void *x,
+                                   void *y, int reps, void *stream, double *avg_ms) {
+    clear_error();
+    int lg;
+    NP_TRY(op_prelude(dims, h, bc, &lg));
+    if (!f || !x || !y || !avg_ms || reps < 1 || x == y) { set_error("bad argument"); return NP_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    const bool d3 = dims.ndim == 3;
+    switch (prec) {
+    case NP_FP64: return d3 ? time_sweep<3, double>(f, x, y, lg, bc, h, reps, s, avg_ms)
+                            : time_sweep<2, double>(f, x, y, lg, bc, h, reps, s, avg_ms);
+    case NP_FP32: return d3 ? time_sweep<3, float>(f, x, y, lg, bc, h, reps, s, avg_ms)
+                            : time_sweep<2, float>(f, x, y, lg, bc, h, reps, s, avg_ms);
+    case NP_BF16: return d3 ? time_sweep<3, bf16>(f, x, y, lg, bc, h, reps, s, avg_ms)
+                            : time_sweep<2, bf16>(f, x, y, lg, bc, h, reps, s, avg_ms);
+    }
+    set_error("unknown precision");
+    return NP_EINVAL;
+}
+
 extern "C" np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const double *f, const double *x,
                                       double *out, void *stream) {
     int lg;

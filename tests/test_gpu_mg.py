@@ -154,6 +154,21 @@ def test_sweep3_matches_direct_sweep(B, orc, bc):
         assert rel(a, b) < 1e-8
 
 
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_prof_sweep_is_the_solver_sweep(B, orc, bc):
+    """The timing hook launches the solver's sweep: its output equals one oracle
+    Jacobi sweep (FP64, on the z-marching kernel's 128^3 level), and it reports a
+    positive duration."""
+    n = 128
+    rng = np.random.default_rng(5 + bc)
+    f, x = rng.standard_normal((n, n, n)), rng.standard_normal((n, n, n))
+    h = 1.0 / n
+    y = dev(np.zeros_like(x))
+    ms = B.np_prof_sweep(dev(f), dev(x), y, h, bc, B.FP64, reps=3)
+    assert ms > 0
+    assert rel(host(y), orc.jacobi(f, x, h, bc)) < 1e-13
+
+
 def test_tuning_knobs_validate(B):
     with pytest.raises(B.NeuphysError):
         B.np_set_tuning("no_such_knob", 1)

@@ -558,3 +558,46 @@ def test_cnn_oracle_layers_closed_forms():
             for dx in (-1, 0, 1):
                 ref += s[dz + 1] * s[dy + 1] * s[dx + 1] * np.roll(Xc, (-dz, -dy, -dx), axis=(1, 2, 3))
     assert np.allclose(cnn.pool(cnn.up(Xc)), ref)
+
+
+def test_cnn_oracle_conv_matches_fft_cross_correlation():
+    """The periodic convolution equals circular cross-correlation computed through
+    numpy's FFT: Y[o] = b[o] + sum_c IFFT(conj(FFT(K_oc)) FFT(X_c)), K_oc the 3x3x3
+    filter embedded at offsets (dz, dy, dx) of a periodic n^3 grid."""
+    from oracle import cnn
+    rng = np.random.default_rng(11)
+    n = 8
+    X = rng.standard_normal((16, n, n, n))
+    W = rng.standard_normal((27, 16, 16))
+    b = rng.standard_normal(16)
+    FX = np.fft.fftn(X, axes=(1, 2, 3))
+    ref = np.zeros((16, n, n, n))
+    for o in range(16):
+        acc = np.zeros((n, n, n), dtype=complex)
+        for c in range(16):
+            K = np.zeros((n, n, n))
+            for t, (dz, dy, dx) in enumerate(cnn.OFFS):
+                K[dz % n, dy % n, dx % n] = W[t, o, c]
+            acc += np.conj(np.fft.fftn(K)) * FX[c]
+        ref[o] = np.real(np.fft.ifftn(acc)) + b[o]
+    assert np.max(np.abs(cnn.conv(X, W, b) - ref)) < 1e-11
+
+
+def test_cnn_oracle_backward_passes_are_adjoints():
+    """<L x, y> = <x, L^T y> for the convolution's data gradient, the pooling and the
+    upsampling backward passes, and the weight gradient is d<conv(X, W), Y>/dW."""
+    from oracle import cnn
+    rng = np.random.default_rng(12)
+    n = 8
+    X = rng.standard_normal((16, n, n, n))
+    Y = rng.standard_normal((16, n, n, n))
+    W = rng.standard_normal((27, 16, 16))
+    zero = np.zeros(16)
+    dX, dW, db = cnn.conv_backward(X, W, Y)
+    assert abs(np.sum(cnn.conv(X, W, zero) * Y) - np.sum(X * dX)) < 1e-9 * np.sum(np.abs(X * dX))
+    # linear in W: <conv(X, W), Y> = <W, dW>
+    assert abs(np.sum(cnn.conv(X, W, zero) * Y) - np.sum(W * dW)) < 1e-9 * np.sum(np.abs(W * dW))
+    assert np.allclose(db, Y.sum(axis=(1, 2, 3)))
+    Yc = rng.standard_normal((16, n // 2, n // 2, n // 2))
+    assert abs(np.sum(cnn.pool(X) * Yc) - np.sum(X * cnn.pool_backward(Yc))) < 1e-10
+    assert abs(np.sum(cnn.up(Yc) * X) - np.sum(Yc * cnn.up_backward(X))) < 1e-10
