@@ -52,13 +52,16 @@ def lib():
             "or_ns_momentum": [_d, _i64, _f64, _f64, _f64, _p, _p],
             "or_ns_step": [_d, _i64, _f64, _p, _p, _p, _p, _f64, _f64, _f64, _d, _d, _f64, _d, _d,
                            _i64, _p, _p],
+            "or_prolong_const_add": [_d, _i64, _p, _p],
+            "or_sawtooth": [_d, _i64, _f64, _d, _f64, _d, _d, _i64, _p, _p],
+            "or_saw_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _f64, _d, _d, _d, _d, _i64, _p, _p, _p, _d],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = _f64 if name == "or_rel_res" else (None if name in (
                 "or_apply_A", "or_residual", "or_jacobi", "or_restrict", "or_prolong_add",
-                "or_divergence", "or_gradient", "or_ns_momentum") else ctypes.c_int)
+                "or_divergence", "or_gradient", "or_ns_momentum", "or_prolong_const_add") else ctypes.c_int)
         _lib = L
     return _lib
 
@@ -150,6 +153,38 @@ def vcycle(f, x, h, bc, nu1=2, nu2=2, omega=2.0 / 3.0, n_coarsest=4):
     if st != 0:
         raise RuntimeError("vcycle failed: %d" % st)
     return x
+
+
+def prolong_const_add(e, x):
+    """Returns x + (the paper's copying prolongation of e) (x is not modified)."""
+    e, x = _arr(e), _arr(x).copy()
+    d, nc = _grid(e)
+    assert x.shape == (2 * nc,) * d
+    lib().or_prolong_const_add(d, nc, _ptr(e), _ptr(x))
+    return x
+
+
+def sawtooth(f, x, h, bc, alpha=1.0, nu=1, prolong_const=True, n_coarsest=4):
+    """Returns the iterate after one sawtooth cycle (Appendix B) from x."""
+    f, x = _arr(f), _arr(x).copy()
+    d, n = _grid(x)
+    lib().or_sawtooth(d, n, h, bc, alpha, nu, int(prolong_const), n_coarsest, _ptr(f), _ptr(x))
+    return x
+
+
+def saw_solve(f, h, bc, tol=1e-10, alpha=1.0, nu=1, prolong_const=True, max_cycles=200, fixed_cycles=0,
+              n_coarsest=4):
+    f = _arr(f)
+    d, n = _grid(f)
+    x = np.zeros_like(f)
+    cyc = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(256)
+    st = lib().or_saw_solve(d, n, h, bc, _ptr(f), _ptr(x), tol, alpha, nu, int(prolong_const), max_cycles,
+                            fixed_cycles, n_coarsest, ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist), 256)
+    if st == -1:
+        raise ValueError("oracle saw_solve: invalid arguments")
+    return SolveResult(x, st, cyc.value, rr.value, hist[: min(cyc.value + 1, 256)])
 
 
 class SolveResult:

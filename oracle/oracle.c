@@ -315,6 +315,115 @@ int or_mg_solve(int d, i64 n, double h, int bc, const double *f_in, double *x, d
 }
 
 /* ---------------------------------------------------------------------- */
+/* The paper's own cycle (Section 2.2, the sawtooth cycle; Appendix B, the
+ * multigrid written as a U-Net).  Not the default cycle of the solver; kept
+ * to measure it against V(2,2). */
+
+/* The paper's prolongation (Section 2.2): every fine cell receives the value
+ * of the coarse cell that contains it (a 2x2 / 2x2x2 filter of ones with
+ * stride 2), added to x.  nc is the coarse size. */
+void or_prolong_const_add(int d, i64 nc, const double *e, double *x)
+{
+    const i64 n = 2 * nc, nz = d == 3 ? n : 1;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i)
+                x[(k * n + j) * n + i] += e[((k / 2) * nc + j / 2) * nc + i / 2];
+}
+
+/* One sawtooth cycle, Appendix B: the residual of the finest grid,
+ * r_0 = f - A x; its restrictions r_{l+1} = R r_l down to the coarsest grid
+ * (no smoothing on the way down); then from the coarsest grid up, on every
+ * level the correction starts as r_l / A_00 (the Jacobi step from zero, the
+ * division of the residual by the filter centre) plus the prolongated
+ * correction of the coarser level (none on the coarsest), and is smoothed by
+ * nu relaxed-Jacobi steps e <- e + alpha (r_l - A e) / A_00 on that level's
+ * residual equation; finally x <- x + e_0.  The paper uses alpha = 1, nu = 1
+ * and the copying prolongation (prolong_const = 1).  Coarser levels
+ * re-discretise A with spacing 2^l h. */
+int or_sawtooth(int d, i64 n, double h, int bc, double alpha, int nu, int prolong_const, i64 n_coarsest,
+                const double *f, double *x)
+{
+    int L = 0;
+    while ((n >> L) > n_coarsest) ++L;
+    double **r = calloc(L + 1, sizeof(double *)), **e = calloc(L + 1, sizeof(double *));
+    for (int l = 0; l <= L; ++l) {
+        r[l] = malloc(sizeof(double) * ncells(d, n >> l));
+        e[l] = calloc(ncells(d, n >> l), sizeof(double));
+    }
+    double *t = malloc(sizeof(double) * ncells(d, n));
+    or_residual(d, n, h, bc, f, x, r[0]);
+    for (int l = 0; l < L; ++l) or_restrict(d, n >> l, r[l], r[l + 1]);
+    for (int l = L; l >= 0; --l) {
+        const i64 nl = n >> l, ml = ncells(d, nl);
+        const double hl = h * (double)((i64)1 << l), a00 = 2.0 * d / (hl * hl);
+        for (i64 c = 0; c < ml; ++c) e[l][c] = r[l][c] / a00;
+        if (l < L) {
+            if (prolong_const) or_prolong_const_add(d, nl / 2, e[l + 1], e[l]);
+            else or_prolong_add(d, nl / 2, bc, e[l + 1], e[l]);
+        }
+        for (int s = 0; s < nu; ++s) {
+            or_jacobi(d, nl, hl, bc, alpha, r[l], e[l], t);
+            memcpy(e[l], t, sizeof(double) * ml);
+        }
+    }
+    const i64 m = ncells(d, n);
+    for (i64 c = 0; c < m; ++c) x[c] += e[0][c];
+    for (int l = 0; l <= L; ++l) { free(r[l]); free(e[l]); }
+    free(r); free(e); free(t);
+    return OR_OK;
+}
+
+/* Tolerance driver of the sawtooth cycle, with the same stopping rule,
+ * periodic treatment and outputs as or_mg_solve. */
+int or_saw_solve(int d, i64 n, double h, int bc, const double *f_in, double *x, double tol, double alpha,
+                 int nu, int prolong_const, int max_cycles, int fixed_cycles, i64 n_coarsest, int *cycles_out,
+                 double *rel_res_out, double *hist, int hist_len)
+{
+    if ((d != 2 && d != 3) || !is_pow2(n) || n < 4 || !is_pow2(n_coarsest) || n_coarsest < 2 ||
+        !(h > 0.0) || !(tol > 0.0) || nu < 0)
+        return OR_EINVAL;
+    const i64 m = ncells(d, n);
+    double *f = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
+    memcpy(f, f_in, sizeof(double) * m);
+    if (bc == OR_BC_PERIODIC) {
+        double mean = 0.0;
+        for (i64 c = 0; c < m; ++c) mean += f[c];
+        mean /= (double)m;
+        for (i64 c = 0; c < m; ++c) f[c] -= mean;
+    }
+    const double nf = sqrt(dot(m, f, f));
+    int st = OR_OK, k = 0;
+    double rr = 0.0;
+    memset(x, 0, sizeof(double) * m);
+    if (nf > 0.0) {
+        for (;;) {
+            or_residual(d, n, h, bc, f, x, r);
+            rr = sqrt(dot(m, r, r)) / nf;
+            if (hist && k < hist_len) hist[k] = rr;
+            if (fixed_cycles > 0) {
+                if (k >= fixed_cycles) break;
+            } else {
+                if (rr <= tol) break;
+                if (k >= max_cycles || !(rr < 1e300)) { st = OR_ENOCONV; break; }
+            }
+            or_sawtooth(d, n, h, bc, alpha, nu, prolong_const, n_coarsest, f, x);
+            ++k;
+        }
+        if (bc == OR_BC_PERIODIC) {
+            double mean = 0.0;
+            for (i64 c = 0; c < m; ++c) mean += x[c];
+            mean /= (double)m;
+            for (i64 c = 0; c < m; ++c) x[c] -= mean;
+        }
+    }
+    if (cycles_out) *cycles_out = k;
+    if (rel_res_out) *rel_res_out = rr;
+    free(f); free(r);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Scalar advection-diffusion step (Section 2.1, predictor-corrector of the
  * advection-diffusion filter).  With R(T) = sum_e a_e (T[+e] - T[-e])/(2h)
  * - nu (discrete Laplacian of T), the predictor is T~ = T^n - dt R(T^n) and

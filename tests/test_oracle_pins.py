@@ -601,3 +601,65 @@ def test_cnn_oracle_backward_passes_are_adjoints():
     Yc = rng.standard_normal((16, n // 2, n // 2, n // 2))
     assert abs(np.sum(cnn.pool(X) * Yc) - np.sum(X * cnn.pool_backward(Yc))) < 1e-10
     assert abs(np.sum(cnn.up(Yc) * X) - np.sum(Yc * cnn.up_backward(X))) < 1e-10
+
+
+# ------------------------------------------- the paper's sawtooth cycle (oracle)
+def dense_prolong_const(d, nc):
+    """The paper's copying prolongation: fine cell i takes coarse cell i // 2 per axis."""
+    P1 = np.zeros((2 * nc, nc))
+    for i in range(2 * nc):
+        P1[i, i // 2] = 1.0
+    P = P1
+    for _ in range(d - 1):
+        P = np.kron(P1, P)
+    return P
+
+
+def dense_saw_map(d, n, h, bc, alpha, nu, const, n_coarsest=4):
+    """Linear map r -> e of the sawtooth's up-leg on a level (Appendix B): e = r / A_00
+    plus the prolongated coarse correction of R r, then nu relaxed-Jacobi steps
+    e <- e + alpha (r - A e) / A_00, all assembled from dense matrices."""
+    A = dense_laplacian(d, n, h, bc)
+    m = n ** d
+    dinv = h ** 2 / (2 * d)
+    M = dinv * np.eye(m)
+    if n > n_coarsest:
+        R = dense_restrict(d, n)
+        P = dense_prolong_const(d, n // 2) if const else dense_prolong(d, n // 2, bc)
+        M = M + P @ dense_saw_map(d, n // 2, 2 * h, bc, alpha, nu, const, n_coarsest) @ R
+    J = np.eye(m) - alpha * dinv * A
+    for _ in range(nu):
+        M = J @ M + alpha * dinv * np.eye(m)
+    return M
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (2, 16), (3, 8)])
+@pytest.mark.parametrize("bc", [DIR, PER])
+@pytest.mark.parametrize("alpha,nu,const", [(1.0, 1, True), (2.0 / 3.0, 2, False)])
+def test_sawtooth_error_matrix(orc, d, n, bc, alpha, nu, const):
+    """One oracle sawtooth cycle with f = 0 maps x to (I - M A) x, with M the up-leg map
+    assembled from dense restriction, prolongation (the paper's copy, or linear) and
+    re-discretised level operators."""
+    h = 1.0 / n
+    m = n ** d
+    E_ref = np.eye(m) - dense_saw_map(d, n, h, bc, alpha, nu, const) @ dense_laplacian(d, n, h, bc)
+    f = np.zeros((n,) * d)
+    E = np.stack([vec(orc.sawtooth(f, e.reshape((n,) * d), h, bc, alpha=alpha, nu=nu, prolong_const=const))
+                  for e in np.eye(m)], axis=1)
+    assert np.max(np.abs(E - E_ref)) < 1e-12
+
+
+def test_sawtooth_literal_reading_diverges_and_damped_linear_converges(orc):
+    """Reading of the paper's cycle on Dirichlet Poisson: as printed (alpha = 1, one
+    step, copying prolongation) the error propagator has spectral radius above 1;
+    with alpha = 2/3, two steps and linear prolongation it is a contraction, but a
+    weaker one than V(2,2) (radius of the dense propagators, 2D 16^2)."""
+    n, d = 16, 2
+    h = 1.0 / n
+    A = dense_laplacian(d, n, h, DIR)
+    lit = np.eye(n * n) - dense_saw_map(d, n, h, DIR, 1.0, 1, True) @ A
+    damped = np.eye(n * n) - dense_saw_map(d, n, h, DIR, 2.0 / 3.0, 2, False) @ A
+    rho = lambda E: np.max(np.abs(np.linalg.eigvals(E)))
+    assert rho(lit) > 1.0
+    assert rho(damped) < 1.0
+    assert rho(dense_vcycle_error(d, n, h, DIR)) < rho(damped)
