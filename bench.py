@@ -269,13 +269,46 @@ def leg_c5(B, inputs, nsteps=10):
                 **out)
 
 
+def leg_sawtooth(B, inputs, steps, warmup):
+    """The paper's sawtooth cycle against V(2,2): as printed (alpha = 1, one Jacobi
+    step, copying prolongation) and damped (alpha = 2/3, two steps, linear
+    prolongation), on the 2D 128^2 manufactured source and the 3D 256^3 sine
+    source (Dirichlet, FP64, tol 1e-10): measured contraction per cycle, cycles
+    and time per solve."""
+    import torch
+    out = {}
+    cases = (("2d_128", inputs.manufactured_2d(128, seed=0)), ("3d_256", inputs.sine_rhs(3, 256, seed=0)))
+    variants = (("v22", dict()),
+                ("sawtooth_printed", dict(cycle=B.CYCLE_SAWTOOTH, prolong=B.PROLONG_COPY, nu1=0, nu2=1, omega=1.0,
+                                          max_cycles=40)),
+                ("sawtooth_damped_linear", dict(cycle=B.CYCLE_SAWTOOTH, nu1=0, nu2=2, omega=2.0 / 3.0)))
+    for name, g in cases:
+        f = torch.from_numpy(g["f"]).cuda()
+        x = torch.zeros_like(f)
+        res = {}
+        for vn, kw in variants:
+            dt, (st, stats) = timed(lambda: B.mg_poisson_solve(f, x, g["h"], B.BC_DIRICHLET0, tol=TOL, check=False,
+                                                               **kw), max(1, steps // 2), 1)
+            hist = [v for v in stats["hist"][:stats["cycles"] + 1] if v > 0]
+            tail = hist[-6:]
+            rho = (tail[-1] / tail[0]) ** (1.0 / (len(tail) - 1)) if len(tail) > 1 else None
+            res[vn] = dict(status="converged" if st == 0 else "not converged (status %d)" % st,
+                           cycles=stats["cycles"], rel_res=stats["rel_res"], rho_last5=rho,
+                           ms_per_solve=1e3 * dt / max(1, steps // 2))
+            log("  sawtooth leg %s %s: %s, %d cycles, rho %.3f, %.2f ms" % (
+                name, vn, res[vn]["status"], stats["cycles"], rho or -1, res[vn]["ms_per_solve"]))
+        out[name] = res
+        del f, x
+    return dict(workload="sawtooth_vs_v22_dirichlet_fp64_tol1e-10", **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="c1,c2,c4,c5",
+    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth",
                     help="other workloads to run after the headline (comma list, '' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -400,6 +433,8 @@ def main():
             others["c4"] = leg_c4(B, inputs, max(1, args.steps // 3), 1)
         elif leg == "c5":
             others["c5"] = leg_c5(B, inputs)
+        elif leg == "sawtooth":
+            others["sawtooth"] = leg_sawtooth(B, inputs, args.steps, args.warmup)
         else:
             sys.exit("unknown leg %s" % leg)
         B.np_release_all()

@@ -69,6 +69,12 @@ typedef struct {
     int warm_start;       /* 0: x is zeroed first (the paper's zero initial estimate); 1: learned guess
                              (np_cnn_attach), judged against zero; 2: x is the initial guess */
     void *stream;         /* hipStream_t to run on; NULL = null stream */
+    int cycle;            /* 0: V(nu1, nu2) (default); 1: the paper's sawtooth cycle (Section 2.2;
+                             Appendix B): the residual restricted to the coarsest grid, then per
+                             level from the coarsest up e = r/A_00 + P e_coarse and nu2 relaxed-
+                             Jacobi steps with alpha = omega; FP64 only, nu1 must be 0 */
+    int prolong;          /* sawtooth only: 0 linear (as the V-cycle), 1 the paper's copy of the
+                             coarse value to its 2^d fine cells */
 } np_mg_opts;
 
 typedef struct {

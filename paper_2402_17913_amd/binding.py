@@ -27,7 +27,8 @@ class NpMgOpts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("max_cycles", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
                 ("smooth_prec", ctypes.c_int), ("inner_cycles", ctypes.c_int),
-                ("warm_start", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("warm_start", ctypes.c_int), ("stream", ctypes.c_void_p), ("cycle", ctypes.c_int),
+                ("prolong", ctypes.c_int)]
 
 
 class NpMgStats(ctypes.Structure):
@@ -135,13 +136,18 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+CYCLE_V, CYCLE_SAWTOOTH = 0, 1
+PROLONG_LINEAR, PROLONG_COPY = 0, 1
+
+
 def make_opts(nu1=2, nu2=2, omega=2.0 / 3.0, max_cycles=200, fixed_cycles=0, smooth_prec=FP64,
-              inner_cycles=0, warm_start=0):
+              inner_cycles=0, warm_start=0, cycle=CYCLE_V, prolong=PROLONG_LINEAR):
     o = NpMgOpts()
     lib.np_default_opts(ctypes.byref(o))
     o.nu1, o.nu2, o.omega = nu1, nu2, omega
     o.max_cycles, o.fixed_cycles = max_cycles, fixed_cycles
     o.smooth_prec, o.inner_cycles, o.warm_start = smooth_prec, inner_cycles, warm_start
+    o.cycle, o.prolong = cycle, prolong
     o.stream = _stream()
     return o
 

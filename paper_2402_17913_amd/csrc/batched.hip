@@ -636,6 +636,7 @@ extern "C" np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, co
         return NP_EINVAL;
     }
     if (o.warm_start != 0) { set_error("batched solves start from zero"); return NP_EINVAL; }
+    if (o.cycle != 0 || o.prolong != 0) { set_error("batched solves run V-cycles"); return NP_EINVAL; }
     if (o.nu1 < 1 || o.nu2 < 0 || ((o.nu1 + o.nu2) & 1) || o.nu1 > 16 || o.nu2 > 16 ||
         !(o.omega > 0.0 && o.omega < 2.0) || o.inner_cycles < 0 || o.inner_cycles > 16 || o.max_cycles < 0 ||
         o.fixed_cycles < 0 || o.max_cycles > 100000 || o.fixed_cycles > 100000) {

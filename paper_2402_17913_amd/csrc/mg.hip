@@ -126,7 +126,7 @@ constexpr int kPartials = 65536;
 constexpr unsigned kNormBlocks = 2048;  // workgroups of a sweep that also reduces the residual norm  // per-workgroup partial sums (fixed order)
 
 struct GraphKey {
-    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles
+    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles; 5 sawtooth
     int zero0, check;
     const void *x, *f;
     double h;
@@ -155,6 +155,7 @@ struct Hier {
     double *hred = nullptr;   // pinned host mirror of the scalar slots
     double *f64 = nullptr;    // FP64 copy of the rhs (periodic mean removal)
     double *x64 = nullptr;    // second FP64 solution buffer (mixed path)
+    double *saw = nullptr;    // level-0 correction and its partner (sawtooth cycle)
     Ctl *ctl = nullptr;       // device controller
     Ctl *hctl = nullptr;      // pinned host mirror
     hipStream_t cap = nullptr;  // capture stream
@@ -194,6 +195,7 @@ void free_hier(Hier *H) {
     if (H->hred) (void)hipHostFree(H->hred);
     if (H->f64) (void)hipFree(H->f64);
     if (H->x64) (void)hipFree(H->x64);
+    if (H->saw) (void)hipFree(H->saw);
     if (H->ctl) (void)hipFree(H->ctl);
     if (H->hctl) (void)hipHostFree(H->hctl);
     if (H->cap) (void)hipStreamDestroy(H->cap);
@@ -878,6 +880,79 @@ static np_status solve_fp64(Hier *H, const double *f, double *x, double h, doubl
     return status_of(c, tol);
 }
 
+// One sawtooth cycle (Section 2.2; Appendix B), FP64, every launch gated by the
+// controller: the finest residual (its norm is the convergence check), the
+// residual restricted level by level to the coarsest grid, then on each level
+// from the coarsest up e = r / A_00 + P e_coarse followed by nu2 relaxed-Jacobi
+// steps (alpha = omega) on that level's residual equation, and x += e_0.
+// Buffers: r_0 in t[0], r_l in f[l]; e_0 and its partner in `saw`, e_l and
+// its partner in x[l], t[l].
+template <int D>
+static np_status saw_cycle(Hier *H, const double *f, double *x, double h, const np_mg_opts &o, hipStream_t s) {
+    const int L = H->L, bc = H->bc, lg0 = H->lg;
+    const int *stop = &H->ctl->stop;
+    const int64_t m0 = cells(D, lg0);
+    std::vector<double *> r(L + 1), e(L + 1), t(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        r[l] = l == 0 ? (double *)H->t[0] : (double *)H->f[l];
+        e[l] = l == 0 ? H->saw : (double *)H->x[l];
+        t[l] = l == 0 ? H->saw + m0 : (double *)H->t[l];
+    }
+    const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m0));
+    hipLaunchKernelGGL((k_saw_resid<D>), dim3(nb), dim3(kBlock), 0, s, f, x, r[0], H->red, lg0, bc, 1.0 / (h * h),
+                       stop);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl);
+    NP_LAUNCH_CHECK();
+    for (int l = 0; l < L; ++l) {
+        const int lgc = lg0 - l - 1;
+        hipLaunchKernelGGL((k_restrict_field<D>), dim3(blocks_for(cells(D, lgc))), dim3(kBlock), 0, s, r[l],
+                           r[l + 1], lgc, stop);
+        NP_LAUNCH_CHECK();
+    }
+    std::vector<double *> done(L + 2, nullptr);  // final correction of each level
+    for (int l = L; l >= 0; --l) {
+        const int lg = lg0 - l;
+        const int64_t ml = cells(D, lg);
+        const double hl = h * double(int64_t(1) << l);
+        hipLaunchKernelGGL((k_saw_up<D>), dim3(blocks_for(ml)), dim3(kBlock), 0, s, r[l], done[l + 1], e[l], lg,
+                           bc, hl * hl / (2.0 * D), o.prolong, stop);
+        NP_LAUNCH_CHECK();
+        double *cur = e[l], *oth = t[l];
+        for (int it = 0; it < o.nu2; ++it) {
+            hipLaunchKernelGGL((k_jacobi<D, double, false>), dim3(blocks_for(ml)), dim3(kBlock), 0, s, r[l], cur,
+                               oth, lg, bc, 1.0 / (hl * hl), o.omega * hl * hl / (2.0 * D), stop);
+            NP_LAUNCH_CHECK();
+            std::swap(cur, oth);
+        }
+        done[l] = cur;
+    }
+    hipLaunchKernelGGL(k_add_to, dim3(blocks_for(m0)), dim3(kBlock), 0, s, x, done[0], m0, stop);
+    NP_LAUNCH_CHECK();
+    return NP_OK;
+}
+
+// Tolerance driver of the sawtooth cycle (the check opens every cycle).
+template <int D>
+static np_status solve_saw(Hier *H, const double *f, double *x, double h, double tol, const np_mg_opts &o,
+                           hipStream_t s, double nf, np_mg_stats *stats) {
+    NP_TRY(ensure_levels(H));
+    if (!H->saw) NP_TRY(dmalloc((void **)&H->saw, sizeof(double) * 2 * cells(D, H->lg)));
+    NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
+    GraphKey key{5, o.prolong, 1, x, f, h, 0, o.nu2, 0, o.omega};
+    int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
+    for (;;) {
+        for (int b = 0; b < batch; ++b)
+            NP_TRY(run_graph(H, key, s, [&](hipStream_t q) { return saw_cycle<D>(H, f, x, h, o, q); }));
+        NP_TRY(read_ctl(H, s));
+        if (H->hctl->stop) break;
+        batch = next_batch(*H->hctl, o, false);
+    }
+    const Ctl c = *H->hctl;
+    fill_stats(stats, c, c.k, c.k);
+    return status_of(c, tol);
+}
+
 template <int D, class SL>
 static np_status solve_mixed(Hier *H, const double *f, double *x, double h, double tol, const np_mg_opts &o,
                              const CycleOpts &co, hipStream_t s, double nf, bool warm, np_mg_stats *stats) {
@@ -972,6 +1047,8 @@ extern "C" void np_default_opts(np_mg_opts *o) {
     o->inner_cycles = 0;
     o->warm_start = 0;
     o->stream = nullptr;
+    o->cycle = 0;
+    o->prolong = 0;
 }
 
 extern "C" const char *np_last_error(void) { return g_err.c_str(); }
@@ -1090,6 +1167,16 @@ static np_status check_solve_args(const np_dims &dims, double h, int bc, const v
         set_error("warm_start must be 0 (zero), 1 (learned) or 2 (caller x)");
         return NP_EINVAL;
     }
+    if (o.cycle != 0 && o.cycle != 1) { set_error("cycle must be 0 (V) or 1 (sawtooth)"); return NP_EINVAL; }
+    if (o.prolong != 0 && o.prolong != 1) { set_error("prolong must be 0 (linear) or 1 (copy)"); return NP_EINVAL; }
+    if (o.cycle == 0 && o.prolong != 0) {
+        set_error("the copying prolongation is available with the sawtooth cycle only");
+        return NP_EINVAL;
+    }
+    if (o.cycle == 1 && (o.nu1 != 0 || o.smooth_prec != NP_FP64 || o.warm_start == 1)) {
+        set_error("the sawtooth cycle runs in FP64 with nu1 = 0 and no learned warm start");
+        return NP_EINVAL;
+    }
     return NP_OK;
 }
 
@@ -1170,7 +1257,10 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
         fallback = used ? 0 : 1;
     }
     np_status st;
-    if (o.smooth_prec == NP_FP64) {
+    if (o.cycle == 1) {
+        st = d == 2 ? solve_saw<2>(H, f, x, h, tol, o, s, nf, stats)
+                    : solve_saw<3>(H, f, x, h, tol, o, s, nf, stats);
+    } else if (o.smooth_prec == NP_FP64) {
         st = d == 2 ? solve_fp64<2>(H, f, x, h, tol, o, co, s, !warm, nf, stats)
                     : solve_fp64<3>(H, f, x, h, tol, o, co, s, !warm, nf, stats);
     } else if (o.smooth_prec == NP_FP32) {

@@ -296,6 +296,94 @@ __global__ __launch_bounds__(kBlock) void k_ir_resid(const double *__restrict__ 
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// ---------------------------------------------------- the sawtooth cycle
+// Kernels of the paper's sawtooth cycle (Section 2.2; Appendix B), FP64.
+
+// r = f - A x, with partial sums of r^2 over a fixed grid of blocks.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_saw_resid(const double *__restrict__ f, const double *__restrict__ x,
+                                                      double *__restrict__ r, double *__restrict__ partial, int lg,
+                                                      int bc, double inv_h2, const int *stop) {
+    if (stop && *stop) return;
+    const int64_t m = int64_t(1) << (D * lg);
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m; c += int64_t(gridDim.x) * blockDim.x) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        const double v = resid_at<D, double>(f, x, c, i, j, k, lg, bc, inv_h2);
+        r[c] = v;
+        acc += v * v;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// rc = R r: the 2^d-cell average of a field (no residual).  lgc: coarse size.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_restrict_field(const double *__restrict__ r, double *__restrict__ rc,
+                                                           int lgc, const int *stop) {
+    if (stop && *stop) return;
+    const int64_t mc = int64_t(1) << (D * lgc);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= mc) return;
+    int I, J, K;
+    decode<D>(c, lgc, I, J, K);
+    const int lg = lgc + 1;
+    double s = 0.0;
+    for (int kk = 0; kk < (D == 3 ? 2 : 1); ++kk)
+        for (int jj = 0; jj < 2; ++jj)
+            for (int ii = 0; ii < 2; ++ii)
+                s += r[(int64_t(D == 3 ? 2 * K + kk : 0) << (2 * lg)) | (int64_t(2 * J + jj) << lg) | (2 * I + ii)];
+    rc[c] = s * (D == 3 ? 0.125 : 0.25);
+}
+
+// Start of a level's correction on the way up: e = r / A_00 + P ec, P the
+// paper's copy (pconst) or the linear prolongation; ec null on the coarsest
+// level.  lg: this level's size.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_saw_up(const double *__restrict__ r, const double *__restrict__ ec,
+                                                   double *__restrict__ e, int lg, int bc, double inv_a00, int pconst,
+                                                   const int *stop) {
+    if (stop && *stop) return;
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    double v = r[c] * inv_a00;
+    if (ec) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        const int lgc = lg - 1, nc = 1 << lgc;
+        if (pconst) {
+            v += ec[(int64_t(k >> 1) << (2 * lgc)) | (int64_t(j >> 1) << lgc) | (i >> 1)];
+        } else {
+            int oi, ni, oj, nj, ok = 0, nk = 0;
+            float si, sj, sk = 1.0f;
+            pro_axis(i, nc, bc, oi, ni, si);
+            pro_axis(j, nc, bc, oj, nj, sj);
+            if (D == 3) pro_axis(k, nc, bc, ok, nk, sk);
+            double s = 0.0;
+            for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (D == 3 ? (cz ? 0.25 : 0.75) : 1.0);
+                        const double sg = double((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
+                        s += w * (sg * ec[(int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
+                                          (a ? ni : oi)]);
+                    }
+            v += s;
+        }
+    }
+    e[c] = v;
+}
+
+// x += e.
+static __global__ __launch_bounds__(kBlock) void k_add_to(double *__restrict__ x, const double *__restrict__ e,
+                                                          int64_t m, const int *stop) {
+    if (stop && *stop) return;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < m) x[c] += e[c];
+}
+
 // Solve controller kept in device memory so that cycles can be enqueued (and
 // replayed from graphs) without a host round trip per cycle.
 struct Ctl {
