@@ -39,15 +39,11 @@ def test_default_opts_and_last_error_without_gpu():
     import sys
     sys.path.insert(0, ROOT)
     lib = ctypes.CDLL(path)
-
-    class Opts(ctypes.Structure):
-        _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
-                    ("max_cycles", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
-                    ("smooth_prec", ctypes.c_int), ("inner_cycles", ctypes.c_int),
-                    ("warm_start", ctypes.c_int), ("stream", ctypes.c_void_p)]
-    o = Opts()
+    from paper_2402_17913_amd.binding import NpMgOpts  # the one mirror of np_mg_opts
+    o = NpMgOpts()
     lib.np_default_opts(ctypes.byref(o))
     assert (o.nu1, o.nu2, o.max_cycles) == (2, 2, 200) and abs(o.omega - 2 / 3) < 1e-15
+    assert (o.warm_start, o.cycle, o.prolong) == (0, 0, 0)
     lib.np_last_error.restype = ctypes.c_char_p
     assert lib.np_last_error() == b""
 
