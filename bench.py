@@ -93,13 +93,14 @@ def sweep3_source_hash():
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, head):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
     summary, if the kernel's source is unchanged since the counters were taken."""
     import re
-    if kernel != "sweep" or not os.path.exists(SWEEP3_PROFILE):
+    path = SWEEP3_PROFILE.replace("fp32", head)
+    if kernel != "sweep" or not os.path.exists(path):
         return None
-    txt = open(SWEEP3_PROFILE).read()
+    txt = open(path).read()
     m1 = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
     m2 = re.search(r"kernel_source_sha256_16: (\w+)", txt)
     if not (m1 and m2) or sweep3_source_hash() != m2.group(1):
@@ -341,25 +342,36 @@ def main():
             name, 1e3 * dt / args.steps, stats["cycles"], stats["outer_iters"], stats["rel_res"],
             res[name]["dofs_per_s"]))
 
-    head = "fp32"
+    # the headline is the faster of the two mixed-precision paths
+    head = "bf16" if res["bf16"]["dofs_per_s"] > res["fp32"]["dofs_per_s"] else "fp32"
     kt = res[head]["prof"]
     # dominant finest-level kernel of the headline path: largest total time
     dom = max(kt, key=lambda k: kt[k]["launches"] * kt[k]["avg_us"])
     # live duration of the finest-level sweep: HIP events around back-to-back
     # launches on the library's stream, on this workload's fields
-    sweep_live = {}
+    level_live = {}
     for name, prec, dt in (("fp64", B.FP64, torch.float64), ("fp32", B.FP32, torch.float32),
                            ("bf16", B.BF16, torch.bfloat16)):
         fl, xl = fg.to(dt), (0.5 * fg).to(dt)
         if dt == torch.bfloat16:
             fl, xl = fl.view(torch.int16), xl.view(torch.int16)
         yl = torch.empty_like(xl)
-        ms = B.np_prof_sweep(fl, xl, yl, h, B.BC_DIRICHLET0, prec, reps=SWEEP_REPS)
-        nbytes = 3 * dofs * {"fp64": 8, "fp32": 4, "bf16": 2}[name]
-        sweep_live[name] = dict(avg_us=1e3 * ms, bytes_per_launch=nbytes, gbs=nbytes / (ms * 1e-3) / 1e9)
-        del fl, xl, yl
-    log("  live sweep: " + ", ".join("%s %.1f us %.0f GB/s" % (k, v["avg_us"], v["gbs"])
-                                     for k, v in sweep_live.items()))
+        cl = torch.zeros((N // 2,) * 3, dtype=xl.dtype, device="cuda")
+        sz = {"fp64": 8, "fp32": 4, "bf16": 2}[name]
+        level_live[name] = {}
+        for kind, kname, nbytes, y in ((B.PROF_LEVEL_SWEEP, "sweep", 3 * dofs * sz, yl),
+                                       (B.PROF_LEVEL_RESTRICT, "restrict", (2 * dofs + dofs // 8) * sz, cl),
+                                       (B.PROF_LEVEL_PROLONG, "prolong", (2 * dofs + dofs // 8) * sz, cl)):
+            ms = B.np_prof_level(kind, fl, xl if kind != B.PROF_LEVEL_PROLONG else yl, y, h, B.BC_DIRICHLET0, prec,
+                                 reps=SWEEP_REPS)
+            level_live[name][kname] = dict(avg_us=1e3 * ms, bytes_per_launch=nbytes,
+                                           gbs=nbytes / (ms * 1e-3) / 1e9,
+                                           frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        del fl, xl, yl, cl
+    for name, v in level_live.items():
+        log("  live %s: " % name + ", ".join("%s %.1f us %.0f GB/s" % (k, w["avg_us"], w["gbs"])
+                                             for k, w in v.items()))
+    sweep_live = {k: v["sweep"] for k, v in level_live.items()}
     if dom == "sweep":
         avg_us, nbytes = sweep_live[head]["avg_us"], sweep_live[head]["bytes_per_launch"]
     else:
@@ -376,21 +388,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": {"fp32": "f32+f64", "bf16": "bf16(f32 arith)+f64"}[head],
         "data": "synthetic",
         "config": {
             "workload": "poisson3d_256cube_dirichlet_sine8_seed0_tol1e-10",
             "dofs": dofs,
-            "path": "mixed-precision refinement, FP32 inner V(2,2) cycles, FP64 residual/coarsest",
+            "path": {"fp32": "mixed-precision refinement: FP32 inner V(2,2) cycles, FP64 residual/update/coarsest",
+                     "bf16": "mixed-precision refinement: inner V(2,2) cycles on BF16 storage with FP32 "
+                             "arithmetic, FP64 residual/update/coarsest"}[head],
             "cycles": res[head]["stats"]["cycles"],
             "outer_iters": res[head]["stats"]["outer_iters"],
             "rel_res": res[head]["stats"]["rel_res"],
             "plain_fp64_dofs_per_s": res["fp64"]["dofs_per_s"],
             "plain_fp64_cycles": res["fp64"]["stats"]["cycles"],
             "plain_fp64_ms_per_solve": 1e3 * res["fp64"]["seconds"] / args.steps,
-            "bf16_dofs_per_s": res["bf16"]["dofs_per_s"],
-            "bf16_outer_iters": res["bf16"]["stats"]["outer_iters"],
-            "bf16_cycles": res["bf16"]["stats"]["cycles"],
+            "fp32_mixed_dofs_per_s": res["fp32"]["dofs_per_s"],
+            "fp32_mixed_cycles": res["fp32"]["stats"]["cycles"],
+            "fp32_mixed_outer_iters": res["fp32"]["stats"]["outer_iters"],
+            "bf16_mixed_dofs_per_s": res["bf16"]["dofs_per_s"],
+            "bf16_mixed_cycles": res["bf16"]["stats"]["cycles"],
+            "bf16_mixed_outer_iters": res["bf16"]["stats"]["outer_iters"],
             "mixed_over_plain": res[head]["dofs_per_s"] / res["fp64"]["dofs_per_s"],
         },
         "roofline": {
@@ -401,19 +418,20 @@ def main():
                        "refine": "k_ir_resid3: FP64 update + residual of the refinement",
                        "fused_down": "k_fused: 2 sweeps + residual + restriction, finest level",
                        "fused_down_zero": "k_fused: zero-guess sweeps + residual + restriction",
-                       "fused_up": "k_fused: prolongation + 2 sweeps, finest level"}[dom] + " (FP32 storage)",
+                       "fused_up": "k_fused: prolongation + 2 sweeps, finest level"}[dom] +
+                      {"fp32": " (FP32 storage)", "bf16": " (BF16 storage, two cells per thread)"}[head],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom),
+            "traffic": measured_traffic(dom, head),
             "avg_us": avg_us,
             "bytes_per_launch": nbytes,
             "timing": ("HIP events around %d back-to-back launches on the library stream" % SWEEP_REPS
                        if dom == "sweep" else "HIP events around each launch"),
             "copy_measured_gbs": copy_gbs,
-            "finest_sweep_live": sweep_live,
+            "finest_level_live": level_live,
             "level0_kernels_event_bracketed": {p: res[p]["prof"] for p in res},
         },
         "cpu_baseline": None,

@@ -288,13 +288,15 @@ np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const double *f, co
  * each output written once). */
 void np_prof_enable(int mask);
 np_status np_prof_read(int64_t *launches, double *total_ms, double *bytes);
-/* Measurement hook: `reps` back-to-back launches of the weighted-Jacobi sweep
- * the solver runs on this grid and precision (same kernel and launch shape),
- * y = x + (2/3) (f - A x) / A_00, between two HIP events on `stream`
- * (after one untimed launch); *avg_ms (host) = mean duration per launch.
- * f, x, y: device arrays of the precision (FP64 double, FP32 float, BF16 as
- * uint16 bit patterns), dims as for the solver, y distinct from x. */
-np_status np_prof_sweep(np_dims dims, double h, np_bc bc, np_prec prec, const void *f, const void *x,
+/* Measurement hook: `reps` back-to-back launches of a level kernel the solver
+ * runs on this grid and precision (same kernel and launch shape) between two
+ * HIP events on `stream` (after one untimed launch); *avg_ms (host) = mean
+ * duration per launch.  kind 0: the weighted-Jacobi sweep y = x + (2/3)
+ * (f - A x) / A_00 (y fine, distinct from x); 1: residual and restriction
+ * y = R (f - A x) (y coarse, n/2 per axis); 2: prolongation and correction
+ * x += P y (y coarse; f unused).  f, x, y: device arrays of the precision
+ * (FP64 double, FP32 float, BF16 as uint16 bit patterns); n >= 8. */
+np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x,
                         void *y, int reps, void *stream, double *avg_ms);
 
 /* Tuning knobs (process-wide; used by the autotuner): "fused" (0/1: fused

@@ -93,7 +93,7 @@ _SIGS = {
     "np_cnn_train": (_I, [ctypes.POINTER(NpDims), _I, _I, _P, _P, ctypes.c_char_p, ctypes.c_char_p,
                           ctypes.POINTER(_D)]),
     "np_get_tuning": (_I, [ctypes.c_char_p]),
-    "np_prof_sweep": (_I, [NpDims, _D, _I, _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
+    "np_prof_level": (_I, [NpDims, _D, _I, _I, _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
 }
 
 
@@ -389,12 +389,16 @@ def np_release_all():
     lib.np_release_all()
 
 
-def np_prof_sweep(f, x, y, h, bc, prec, reps=50):
-    """Mean duration (ms) of `reps` back-to-back solver sweeps y = sweep(x) on the
-    current stream (tensors of the precision: float64, float32, or int16 holding
-    BF16 bit patterns)."""
+PROF_LEVEL_SWEEP, PROF_LEVEL_RESTRICT, PROF_LEVEL_PROLONG = 0, 1, 2
+
+
+def np_prof_level(kind, f, x, y, h, bc, prec, reps=50):
+    """Mean duration (ms) of `reps` back-to-back launches of a solver level kernel on
+    the current stream: kind 0 y = sweep(x), 1 y = R (f - A x) (y coarse), 2 x += P y
+    (y coarse; f may be None).  Tensors of the precision: float64, float32, or int16
+    holding BF16 bit patterns."""
     dt = {FP64: torch.float64, FP32: torch.float32, BF16: torch.int16}[prec]
     out = ctypes.c_double(0.0)
-    _check("np_prof_sweep", lib.np_prof_sweep(_dims(x), h, bc, prec, _dev(f, dt), _dev(x, dt), _dev(y, dt), reps,
-                                              _stream(), ctypes.byref(out)))
+    _check("np_prof_level", lib.np_prof_level(_dims(x), h, bc, prec, kind, _dev(f, dt) if f is not None else None,
+                                              _dev(x, dt), _dev(y, dt), reps, _stream(), ctypes.byref(out)))
     return out.value

@@ -393,18 +393,18 @@ template <int D, class S> struct Ops {
         const bool prof = finest && (prof_on() & (zmode ? kProfSweepZero : kProfJacobi));
         if (prof) NP_TRY(prof_begin(s, &tok));
         if (D == 3 && zmode != 1 && lg >= 7 && g_tune.sweep3) {
-            constexpr int TX = 128;
-            const int zc = sweep3_planes(lg, TX, kPartials);
-            nb = unsigned((int64_t(1) << (3 * lg)) / (int64_t(kS3Threads) * zc));
+            constexpr int CPT = ZCfg<S>::CPT;
+            const int zc = sweep3_planes(lg, CPT, kPartials);
+            nb = zblocks(lg, CPT, zc);
             if (zmode == 2)
-                hipLaunchKernelGGL((k_sweep3<S, false, TX, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout,
-                                   partial, lg, bc, zc, inv_h2, wdiag, stop);
+                hipLaunchKernelGGL((k_sweep3<S, false, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
+                                   lg, bc, zc, inv_h2, wdiag, stop);
             else if (partial)
-                hipLaunchKernelGGL((k_sweep3<S, true, TX>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
-                                   lg, bc, zc, inv_h2, wdiag, stop);
+                hipLaunchKernelGGL((k_sweep3<S, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
             else
-                hipLaunchKernelGGL((k_sweep3<S, false, TX>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial,
-                                   lg, bc, zc, inv_h2, wdiag, stop);
+                hipLaunchKernelGGL((k_sweep3<S, false>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, xout, partial, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
         } else if (zmode == 1)
             hipLaunchKernelGGL((k_sweep<D, S, true, false>), dim3(nb), dim3(kBlock), 0, s, f, xin, xout, partial, lg,
                                bc, inv_h2, wdiag, stop);
@@ -433,11 +433,10 @@ template <int D, class S> struct Ops {
             const bool prof = lg == H_lg_top && (prof_on() & kProfRestrict);
             if (prof) NP_TRY(prof_begin(s, &tok));
             if (D == 3 && lg >= 7 && g_tune.sweep3) {
-                constexpr int TX = 128;
-                const int zc = sweep3_planes(lg, TX, kPartials);
-                const unsigned nb3 = unsigned((int64_t(1) << (3 * lg)) / (int64_t(kS3Threads) * zc));
-                hipLaunchKernelGGL((k_restrict3<S, TX>), dim3(nb3), dim3(kS3Threads), 0, s, f, x, fc, lg, bc, zc,
-                                   C(1.0 / (h * h)), stop);
+                constexpr int CPT = ZCfg<S>::CPT;
+                const int zc = sweep3_planes(lg, CPT, kPartials);
+                hipLaunchKernelGGL((k_restrict3<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, f, x, fc, lg,
+                                   bc, zc, C(1.0 / (h * h)), stop);
             } else {
                 hipLaunchKernelGGL((k_restrict<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, f, x, fc, lg, bc,
                                    C(1.0 / (h * h)), stop);
@@ -475,9 +474,10 @@ template <int D, class S> struct Ops {
         const bool prof = lgc + 1 == H_lg_top && (prof_on() & kProfProlong);
         if (prof) NP_TRY(prof_begin(s, &tok));
         if (D == 3 && lgc + 1 >= 7 && g_tune.sweep3) {
-            const int lg = lgc + 1, zc = sweep3_planes(lg, 128, kPartials);
-            hipLaunchKernelGGL((k_prolong3<S, 128>), dim3(unsigned(m / (int64_t(kS3Threads) * zc))),
-                               dim3(kS3Threads), 0, s, ec, x, lg, bc, zc, stop);
+            constexpr int CPT = ZCfg<S>::CPT;
+            const int lg = lgc + 1, zc = sweep3_planes(lg, CPT, kPartials);
+            hipLaunchKernelGGL((k_prolong3<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, ec, x, lg, bc, zc,
+                               stop);
         } else {
             hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc,
                                stop);
@@ -973,8 +973,8 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
     }
     NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
     const bool zm = D == 3 && H->lg >= 7 && g_tune.sweep3;  // z-marching refinement kernel
-    const int zc = zm ? sweep3_planes(H->lg, 128, kPartials) : 0;
-    const unsigned nb = zm ? unsigned(m / (int64_t(kS3Threads) * zc))
+    const int zc = zm ? sweep3_planes(H->lg, 1, kPartials) : 0;
+    const unsigned nb = zm ? zblocks(H->lg, 1, zc)
                            : unsigned(std::min<int64_t>((m + kIrCells - 1) / kIrCells, kPartials));
     const int *stop = &H->ctl->stop;
     // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles
@@ -983,10 +983,10 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         const bool prof = prof_on() & kProfRefine;
         if (prof) NP_TRY(prof_begin(q, &tok));
         if (zm && has_e)
-            hipLaunchKernelGGL((k_ir_resid3<SL, 128, true>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
+            hipLaunchKernelGGL((k_ir_resid3<SL, true>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
                                H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
         else if (zm)
-            hipLaunchKernelGGL((k_ir_resid3<SL, 128, false>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
+            hipLaunchKernelGGL((k_ir_resid3<SL, false>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
                                H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
         else
             hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, q, xin, e, xout, f, rlo, H->red,
@@ -1376,10 +1376,12 @@ extern "C" np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double
     return NP_OK;
 }
 
-// Back-to-back launches of the level sweep the solver uses on this grid (same
-// kernel and launch shape), y = sweep(x), between two events on the stream.
+// Back-to-back launches of a level kernel the solver uses on this grid (same
+// kernel and launch shape) between two events on the stream.  kind 0: the
+// sweep y = sweep(x); 1: the residual restriction y = R (f - A x), y coarse;
+// 2: the prolongation x += P y, y coarse.
 template <int D, class S>
-static np_status time_sweep(const void *f, const void *x, void *y, int lg, int bc, double h, int reps,
+static np_status time_level(int kind, const void *f, void *x, void *y, int lg, int bc, double h, int reps,
                             hipStream_t s, double *avg_ms) {
     hipEvent_t a = nullptr, b = nullptr;
     NP_HIP_TRY(hipEventCreate(&a));
@@ -1388,13 +1390,14 @@ static np_status time_sweep(const void *f, const void *x, void *y, int lg, int b
         set_error("hipEventCreate failed");
         return NP_EHIP;
     }
-    np_status st = NP_OK;
     auto run = [&]() -> np_status {
-        NP_TRY((Ops<D, S>::sweep((const S *)f, (const S *)x, (S *)y, lg, bc, h, 2.0 / 3.0, 0, nullptr, nullptr, s,
-                                 false, nullptr)));
-        return NP_OK;
+        if (kind == 0)
+            return Ops<D, S>::sweep((const S *)f, (const S *)x, (S *)y, lg, bc, h, 2.0 / 3.0, 0, nullptr, nullptr,
+                                    s, false, nullptr);
+        if (kind == 1) return Ops<D, S>::restrict_((const S *)f, (const S *)x, (S *)y, lg, bc, h, s, nullptr);
+        return Ops<D, S>::prolong_add((const S *)y, (S *)x, lg - 1, bc, s, nullptr);
     };
-    st = run();  // warm-up
+    np_status st = run();  // warm-up
     if (st == NP_OK && hipEventRecord(a, s) != hipSuccess) st = NP_EHIP;
     for (int r = 0; r < reps && st == NP_OK; ++r) st = run();
     float ms = 0.f;
@@ -1408,21 +1411,24 @@ static np_status time_sweep(const void *f, const void *x, void *y, int lg, int b
     return st;
 }
 
-extern "C" np_status np_prof_sweep(np_dims dims, double h, np_bc bc, np_prec prec, const void *f, const void *x,
-                                   void *y, int reps, void *stream, double *avg_ms) {
+extern "C" np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f,
+                                   void *x, void *y, int reps, void *stream, double *avg_ms) {
     clear_error();
     int lg;
     NP_TRY(op_prelude(dims, h, bc, &lg));
-    if (!f || !x || !y || !avg_ms || reps < 1 || x == y) { set_error("bad argument"); return NP_EINVAL; }
+    if (!x || !y || !avg_ms || reps < 1 || x == y || kind < 0 || kind > 2 || (kind < 2 && !f) || lg < 3) {
+        set_error("bad argument");
+        return NP_EINVAL;
+    }
     hipStream_t s = (hipStream_t)stream;
     const bool d3 = dims.ndim == 3;
     switch (prec) {
-    case NP_FP64: return d3 ? time_sweep<3, double>(f, x, y, lg, bc, h, reps, s, avg_ms)
-                            : time_sweep<2, double>(f, x, y, lg, bc, h, reps, s, avg_ms);
-    case NP_FP32: return d3 ? time_sweep<3, float>(f, x, y, lg, bc, h, reps, s, avg_ms)
-                            : time_sweep<2, float>(f, x, y, lg, bc, h, reps, s, avg_ms);
-    case NP_BF16: return d3 ? time_sweep<3, bf16>(f, x, y, lg, bc, h, reps, s, avg_ms)
-                            : time_sweep<2, bf16>(f, x, y, lg, bc, h, reps, s, avg_ms);
+    case NP_FP64: return d3 ? time_level<3, double>(kind, f, x, y, lg, bc, h, reps, s, avg_ms)
+                            : time_level<2, double>(kind, f, x, y, lg, bc, h, reps, s, avg_ms);
+    case NP_FP32: return d3 ? time_level<3, float>(kind, f, x, y, lg, bc, h, reps, s, avg_ms)
+                            : time_level<2, float>(kind, f, x, y, lg, bc, h, reps, s, avg_ms);
+    case NP_BF16: return d3 ? time_level<3, bf16>(kind, f, x, y, lg, bc, h, reps, s, avg_ms)
+                            : time_level<2, bf16>(kind, f, x, y, lg, bc, h, reps, s, avg_ms);
     }
     set_error("unknown precision");
     return NP_EINVAL;

@@ -26,10 +26,16 @@ constexpr int kSweepCells = 2 * kBlock;  // cells per workgroup of k_sweep
 
 // Iterate w f read through a functor: the state after a first sweep from a
 // zero iterate, formed on the fly (ZERO2 kernels fuse that sweep and the next).
+template <class S> struct Pair;
 template <class S> struct LdW {
     const S *f;
     typename St<S>::C w;
     __device__ __forceinline__ typename St<S>::C operator()(int64_t q) const { return w * St<S>::ld(f + q); }
+    __device__ __forceinline__ void pair(int64_t q, typename St<S>::C &a, typename St<S>::C &b) const {
+        Pair<S>::ld(f + q, a, b);
+        a *= w;
+        b *= w;
+    }
 };
 
 template <int D, class S, bool ZERO, bool NORM, bool ZERO2 = false>
@@ -72,60 +78,106 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const S *__restrict__ f, const
 
 // ------------------------------------------------------------- z-marching
 // 2.5D blocking of 3D level kernels on n >= TX: a workgroup of kS3Threads
-// threads owns a TX x TY column tile and `zc` consecutive planes.  Each thread
-// keeps its column's values of the iterate at z-1, z, z+1 in registers; the
-// in-plane neighbours come from a double-buffered LDS copy of the plane with
-// a one-cell halo.  The loads of plane z+1 are issued before plane z is used,
-// and every lane issues the same loads on every plane (the z+1 value through
-// a clamped address and a sign, one halo cell per thread, threads without one
-// reloading their own cell, the plane after the last one clamped), so the
+// threads owns a TX x TY column tile and `zc` consecutive planes; each thread
+// owns CPT adjacent columns along x (CPT = 2 for 2-byte storage, so that each
+// access moves 4 bytes; 1 otherwise).  A thread keeps its columns' values of
+// the iterate at z-1, z, z+1 in registers; the in-plane neighbours come from
+// a double-buffered LDS copy of the plane with a one-cell halo.  The loads of
+// plane z+1 are issued before plane z is used, and every lane issues the same
+// loads on every plane (the z+1 value through a clamped address and a sign,
+// one halo slot per thread -- a single cell, loaded as the aligned pair that
+// holds it when CPT = 2, or a run of CPT cells -- threads without a slot
+// reloading their own cells, the plane after the last one clamped), so the
 // compiler can wait for the older loads only and keep the next plane in
 // flight.  Every value is read from HBM once (halo cells are L2 hits).
 // Workgroups are mapped XCD-contiguously.
 constexpr int kS3Threads = 512;
 
-template <class C, int TX>
+// Two adjacent values (at an even index) of a field in storage S, loaded and
+// stored as one vector access.
+template <class S> struct Pair;
+template <> struct Pair<double> {
+    static __device__ __forceinline__ void ld(const double *p, double &a, double &b) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        a = v.x;
+        b = v.y;
+    }
+    static __device__ __forceinline__ void st(double *p, double a, double b) {
+        *reinterpret_cast<double2 *>(p) = make_double2(a, b);
+    }
+};
+template <> struct Pair<float> {
+    static __device__ __forceinline__ void ld(const float *p, float &a, float &b) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        a = v.x;
+        b = v.y;
+    }
+    static __device__ __forceinline__ void st(float *p, float a, float b) {
+        *reinterpret_cast<float2 *>(p) = make_float2(a, b);
+    }
+};
+template <> struct Pair<bf16> {  // element 0 in the low half (little endian)
+    static __device__ __forceinline__ void ld(const bf16 *p, float &a, float &b) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+        a = __uint_as_float(v << 16);
+        b = __uint_as_float(v & 0xffff0000u);
+    }
+    static __device__ __forceinline__ void st(bf16 *p, float a, float b) {
+        *reinterpret_cast<uint32_t *>(p) = uint32_t(float_to_bf16(a)) | (uint32_t(float_to_bf16(b)) << 16);
+    }
+};
+
+// Tile shape of the z-marching kernels for storage S.
+template <class S> struct ZCfg {
+    static constexpr int TX = 128;                     // cells per tile row
+    static constexpr int CPT = sizeof(S) == 2 ? 2 : 1;  // cells per thread along x
+};
+
+template <class C, int TX, int CPT>
 struct ZMarch {
-    static constexpr int TY = kS3Threads / TX;
-    static constexpr int NH = 2 * TY + 2 * TX;  // halo cells of a plane
-    static_assert(NH <= kS3Threads, "one halo cell per thread");
+    static constexpr int TP = TX / CPT;          // threads per tile row
+    static constexpr int TY = kS3Threads / TP;   // tile rows
+    static constexpr int NH = 2 * TY + 2 * TP;   // halo slots: x-halo cells, then y-halo runs of CPT cells
+    static_assert((CPT == 1 || CPT == 2) && TX % CPT == 0 && NH <= kS3Threads, "z-marching tile");
     typedef C Plane[TY + 2][TX + 2];
-    int n, bc, tx, ty, i, j, k0, hy, hx;
+    int n, bc, tp, ty, i, j, k0, hy, hx, hsel;
     int64_t P, col, hsrc;
-    bool hw;                  // this thread has a halo cell
-    C hsg;                    // its sign (-1: Dirichlet ghost)
-    C xm, xc, xp, hv;         // plane k: below, own, above, halo cell
-    C xpp, hn;                // prefetched for plane k + 1
+    bool hw, hrun;            // this thread has a halo slot; the slot is a run of CPT cells
+    C hsg;                    // sign of the slot (-1: Dirichlet ghost)
+    C xm[CPT], xc[CPT], xp[CPT], hv[CPT];  // plane k: below, own, above, halo slot
+    C xpp[CPT], hn[CPT];                   // prefetched for plane k + 1
 
     __device__ ZMarch(int lg, int bc_, int zc) : n(1 << lg), bc(bc_) {
         const int ntx = n / TX, nty = n / TY;
         const int blk = int(xcd_block(blockIdx.x, gridDim.x));
         const int t = int(threadIdx.x);
-        tx = t % TX;
-        ty = t / TX;
+        tp = t % TP;
+        ty = t / TP;
         const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
         const int x0 = bx * TX, y0 = by * TY;
-        i = x0 + tx;
+        i = x0 + CPT * tp;
         j = y0 + ty;
         k0 = bz * zc;
         P = int64_t(1) << (2 * lg);
         col = (int64_t(j) << lg) + i;
-        // halo cell of thread t: x-halos (2 per row) first, then y-halos (2 per column)
         hw = t < NH;
+        hrun = false;
         hy = ty + 1;
-        hx = tx + 1;
+        hx = CPT * tp + 1;
         hsrc = col;
+        hsel = 0;
         hsg = C(1);
         if (hw) {
             int gi, gj;
-            if (t < 2 * TY) {
+            if (t < 2 * TY) {  // x-halo cell of a row
                 hy = (t >> 1) + 1;
                 hx = (t & 1) ? TX + 1 : 0;
                 gj = y0 + hy - 1;
                 gi = (t & 1) ? x0 + TX : x0 - 1;
-            } else {
+            } else {           // y-halo run of CPT cells
                 const int u = t - 2 * TY;
-                hx = (u >> 1) + 1;
+                hrun = true;
+                hx = CPT * (u >> 1) + 1;
                 hy = (u & 1) ? TY + 1 : 0;
                 gi = x0 + hx - 1;
                 gj = (u & 1) ? y0 + TY : y0 - 1;
@@ -137,7 +189,8 @@ struct ZMarch {
             if (gj < 0) gj = bc ? n - 1 : 0;
             if (gj >= n) gj = bc ? 0 : n - 1;
             if (out && !bc) hsg = C(-1);
-            hsrc = (int64_t(gj) << lg) + gi;
+            hsel = CPT == 2 ? (gi & 1) : 0;  // single cell: which half of its aligned pair
+            hsrc = (int64_t(gj) << lg) + (CPT == 2 ? (gi & ~1) : gi);
         }
     }
     // offset of the value above plane k (z + 1) in the column, and its sign
@@ -146,54 +199,97 @@ struct ZMarch {
     // next plane index, clamped to the grid (a harmless reload on the top plane)
     __device__ __forceinline__ int next(int k) const { return k + 1 < n ? k + 1 : n - 1; }
 
+    // this thread's CPT cells at offset q (q even when CPT = 2)
+    template <class V>
+    __device__ __forceinline__ void cells(const V &v, int64_t q, C (&o)[CPT]) const {
+        if constexpr (CPT == 2) v.pair(q, o[0], o[1]);
+        else o[0] = v(q);
+    }
+    // this thread's halo slot on the plane at offset pk
+    template <class V>
+    __device__ __forceinline__ void halo(const V &v, int64_t pk, C (&o)[CPT]) const {
+        if constexpr (CPT == 2) {
+            C a, b;
+            v.pair(pk + hsrc, a, b);
+            o[0] = hsg * (hrun || !hsel ? a : b);
+            o[1] = hsg * b;
+        } else {
+            o[0] = hsg * v(pk + hsrc);
+        }
+    }
     template <class V>
     __device__ __forceinline__ void start(const V &v) {
-        xc = v(k0 * P + col);
-        xm = k0 > 0 ? v((k0 - 1) * P + col) : (bc ? v((n - 1) * P + col) : -xc);
-        xp = up_sg(k0) * v(up_at(k0) + col);
-        hv = hsg * v(k0 * P + hsrc);
+        cells(v, k0 * P + col, xc);
+        if (k0 > 0) cells(v, (k0 - 1) * P + col, xm);
+        else if (bc) cells(v, (n - 1) * P + col, xm);
+        else
+            for (int c = 0; c < CPT; ++c) xm[c] = -xc[c];
+        cells(v, up_at(k0) + col, xp);
+        for (int c = 0; c < CPT; ++c) xp[c] *= up_sg(k0);
+        halo(v, k0 * P, hv);
     }
     // issue the loads of plane k + 1
     template <class V>
     __device__ __forceinline__ void prefetch(const V &v, int k) {
         const int kn = next(k);
-        xpp = up_sg(kn) * v(up_at(kn) + col);
-        hn = hsg * v(kn * P + hsrc);
+        cells(v, up_at(kn) + col, xpp);
+        for (int c = 0; c < CPT; ++c) xpp[c] *= up_sg(kn);
+        halo(v, kn * P, hn);
     }
-    // publish plane k to LDS buffer b and return the sum of its six face
-    // neighbours in the order x-, x+, y-, y+, z-, z+.  Two buffers and one
-    // barrier per plane: a thread writing a buffer again (plane k + 2) has
+    // publish plane k to LDS buffer b and return, per own cell, the sum of its
+    // six face neighbours in the order x-, x+, y-, y+, z-, z+.  Two buffers and
+    // one barrier per plane: a thread writing a buffer again (plane k + 2) has
     // passed plane k + 1's barrier, which follows every read of plane k.
-    __device__ __forceinline__ C neighbours(Plane &b) const {
-        b[ty + 1][tx + 1] = xc;
-        if (hw) b[hy][hx] = hv;
+    __device__ __forceinline__ void neighbours(Plane &b, C (&s)[CPT]) const {
+        for (int c = 0; c < CPT; ++c) b[ty + 1][CPT * tp + c + 1] = xc[c];
+        if (hw) {
+            b[hy][hx] = hv[0];
+            if constexpr (CPT == 2) {
+                if (hrun) b[hy][hx + 1] = hv[1];
+            }
+        }
         __syncthreads();
-        const C s = ((b[ty + 1][tx] + b[ty + 1][tx + 2]) + b[ty][tx + 1]) + b[ty + 2][tx + 1];
-        return (s + xm) + xp;
+        for (int c = 0; c < CPT; ++c) {
+            const int lc = CPT * tp + c + 1;
+            const C t = ((b[ty + 1][lc - 1] + b[ty + 1][lc + 1]) + b[ty][lc]) + b[ty + 2][lc];
+            s[c] = (t + xm[c]) + xp[c];
+        }
     }
     __device__ __forceinline__ void advance() {
-        xm = xc;
-        xc = xp;
-        xp = xpp;
-        hv = hn;
+        for (int c = 0; c < CPT; ++c) {
+            xm[c] = xc[c];
+            xc[c] = xp[c];
+            xp[c] = xpp[c];
+            hv[c] = hn[c];
+        }
     }
 };
 
 template <class S> struct LdC {
     const S *p;
     __device__ __forceinline__ typename St<S>::C operator()(int64_t q) const { return St<S>::ld(p + q); }
+    __device__ __forceinline__ void pair(int64_t q, typename St<S>::C &a, typename St<S>::C &b) const {
+        Pair<S>::ld(p + q, a, b);
+    }
 };
+
+template <class S, int CPT>
+__device__ __forceinline__ void store_cells(S *p, const typename St<S>::C (&v)[CPT]) {
+    if constexpr (CPT == 2) Pair<S>::st(p, v[0], v[1]);
+    else St<S>::st(p, v[0]);
+}
 
 // 3D Jacobi sweep on the z-marching tiles (same arithmetic and summation order
 // as k_sweep).  NORM: per-workgroup partial of r^2.  ZERO2: the first two
 // sweeps from a zero iterate (xin is not read).
-template <class S, bool NORM, int TX, bool ZERO2 = false>
+template <class S, bool NORM, bool ZERO2 = false>
 __global__ __launch_bounds__(kS3Threads) void k_sweep3(const S *__restrict__ f, const S *__restrict__ xin,
                                                        S *__restrict__ xout, double *__restrict__ partial, int lg,
                                                        int bc, int zc, typename St<S>::C inv_h2,
                                                        typename St<S>::C wdiag, const int *stop) {
     typedef typename St<S>::C C;
-    typedef ZMarch<C, TX> Z;
+    constexpr int CPT = ZCfg<S>::CPT;
+    typedef ZMarch<C, ZCfg<S>::TX, CPT> Z;
     __shared__ typename Z::Plane pl[2];
     if (stop && *stop) return;
     Z z(lg, bc, zc);
@@ -201,18 +297,23 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep3(const S *__restrict__ f, 
     V v;
     if constexpr (ZERO2) v = V{f, wdiag};
     else v = V{xin};
+    const LdC<S> vf{f};
     z.start(v);
-    C fc = St<S>::ld(f + z.k0 * z.P + z.col);
+    C fc[CPT], fn[CPT], s[CPT], out[CPT];
+    z.cells(vf, z.k0 * z.P + z.col, fc);
     double acc = 0.0;
     for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
         z.prefetch(v, k);
-        const C fn = St<S>::ld(f + z.next(k) * z.P + z.col);
-        const C s = z.neighbours(pl[q]);
-        const C r = fc - (C(6) * z.xc - s) * inv_h2;
-        if (NORM) acc += double(r) * double(r);
-        St<S>::st(xout + k * z.P + z.col, z.xc + wdiag * r);
+        z.cells(vf, z.next(k) * z.P + z.col, fn);
+        z.neighbours(pl[q], s);
+        for (int c = 0; c < CPT; ++c) {
+            const C r = fc[c] - (C(6) * z.xc[c] - s[c]) * inv_h2;
+            if (NORM) acc += double(r) * double(r);
+            out[c] = z.xc[c] + wdiag * r;
+            fc[c] = fn[c];
+        }
+        store_cells<S, CPT>(xout + k * z.P + z.col, out);
         z.advance();
-        fc = fn;
     }
     if (NORM) {
         acc = block_sum_n<kS3Threads>(acc);
@@ -221,58 +322,70 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep3(const S *__restrict__ f, 
 }
 
 // Residual + restriction on the z-marching tiles: each thread sums the
-// residuals of its column over a pair of planes, then one thread per 2 x 2
-// column group adds the four pair sums (through LDS) and writes the coarse
-// cell, 2^-3 times the sum of its eight children.  zc even.
-template <class S, int TX>
+// residuals of its cells over a pair of planes (with CPT = 2, its own x-pair
+// of cells too), then one thread per coarse cell adds the pair sums of the
+// other children (through LDS) and writes the coarse cell, 2^-3 times the sum
+// of its eight children.  zc even.
+template <class S>
 __global__ __launch_bounds__(kS3Threads) void k_restrict3(const S *__restrict__ f, const S *__restrict__ x,
                                                           S *__restrict__ fc, int lg, int bc, int zc,
                                                           typename St<S>::C inv_h2, const int *stop) {
     typedef typename St<S>::C C;
-    typedef ZMarch<C, TX> Z;
+    constexpr int CPT = ZCfg<S>::CPT, TX = ZCfg<S>::TX;
+    typedef ZMarch<C, TX, CPT> Z;
     __shared__ typename Z::Plane pl[2];
-    __shared__ C rs[Z::TY][TX];
+    __shared__ C rs[Z::TY][Z::TP];
     if (stop && *stop) return;
     Z z(lg, bc, zc);
-    const LdC<S> v{x};
+    const LdC<S> v{x}, vf{f};
     z.start(v);
     const int lgc = lg - 1;
-    C f0 = St<S>::ld(f + z.k0 * z.P + z.col);
+    C f0[CPT], fn[CPT], s[CPT];
+    z.cells(vf, z.k0 * z.P + z.col, f0);
     C pair = C(0);
     for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
         z.prefetch(v, k);
-        const C fn = St<S>::ld(f + z.next(k) * z.P + z.col);
-        const C s = z.neighbours(pl[q]);
-        const C r = f0 - (C(6) * z.xc - s) * inv_h2;
+        z.cells(vf, z.next(k) * z.P + z.col, fn);
+        z.neighbours(pl[q], s);
+        C r = f0[0] - (C(6) * z.xc[0] - s[0]) * inv_h2;
+        if constexpr (CPT == 2) r += f0[1] - (C(6) * z.xc[1] - s[1]) * inv_h2;
         if (((k - z.k0) & 1) == 0) {
             pair = r;
         } else {
             pair += r;
-            rs[z.ty][z.tx] = pair;
+            rs[z.ty][z.tp] = pair;
             __syncthreads();
-            if (((z.tx | z.ty) & 1) == 0) {
-                const C t = ((rs[z.ty][z.tx] + rs[z.ty][z.tx + 1]) + rs[z.ty + 1][z.tx]) + rs[z.ty + 1][z.tx + 1];
-                const int64_t cc = ((int64_t(k >> 1) << (2 * lgc)) | (int64_t(z.j >> 1) << lgc)) + (z.i >> 1);
-                St<S>::st(fc + cc, t * C(0.125));
+            if constexpr (CPT == 2) {
+                if ((z.ty & 1) == 0) {
+                    const C t = rs[z.ty][z.tp] + rs[z.ty + 1][z.tp];
+                    const int64_t cc = ((int64_t(k >> 1) << (2 * lgc)) | (int64_t(z.j >> 1) << lgc)) + (z.i >> 1);
+                    St<S>::st(fc + cc, t * C(0.125));
+                }
+            } else {
+                if (((z.tp | z.ty) & 1) == 0) {
+                    const C t = ((rs[z.ty][z.tp] + rs[z.ty][z.tp + 1]) + rs[z.ty + 1][z.tp]) + rs[z.ty + 1][z.tp + 1];
+                    const int64_t cc = ((int64_t(k >> 1) << (2 * lgc)) | (int64_t(z.j >> 1) << lgc)) + (z.i >> 1);
+                    St<S>::st(fc + cc, t * C(0.125));
+                }
             }
             // rs is written again two planes later, after plane k + 1's barrier
         }
         z.advance();
-        f0 = fn;
+        for (int c = 0; c < CPT; ++c) f0[c] = fn[c];
     }
 }
 
 // Refinement step of the mixed path on the z-marching tiles (see
 // k_ir_resid): x_out = x + e (HAS_E; else x_out is not written and e is not
 // read), r = f - A x_out in FP64, r_lo = r rounded, per-workgroup partial of
-// r^2.
-template <class SL, int TX, bool HAS_E>
+// r^2.  One cell per thread (the FP64 fields dominate its traffic).
+template <class SL, bool HAS_E>
 __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restrict__ x, const SL *__restrict__ e,
                                                           double *__restrict__ xout, const double *__restrict__ f,
                                                           SL *__restrict__ rlo, double *__restrict__ partial,
                                                           int lg, int bc, int zc, double inv_h2,
                                                           const int *stop) {
-    typedef ZMarch<double, TX> Z;
+    typedef ZMarch<double, ZCfg<double>::TX, 1> Z;
     __shared__ typename Z::Plane pl[2];
     if (stop && *stop) return;
     Z z(lg, bc, zc);
@@ -285,14 +398,14 @@ __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restri
     } v{x, e};
     z.start(v);
     double fc = f[z.k0 * z.P + z.col];
-    double acc = 0.0;
+    double acc = 0.0, s[1];
     for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
         z.prefetch(v, k);
         const double fn = f[z.next(k) * z.P + z.col];
-        const double s = z.neighbours(pl[q]);
-        const double r = fc - (6.0 * z.xc - s) * inv_h2;
+        z.neighbours(pl[q], s);
+        const double r = fc - (6.0 * z.xc[0] - s[0]) * inv_h2;
         const int64_t c = k * z.P + z.col;
-        if (HAS_E) xout[c] = z.xc;
+        if (HAS_E) xout[c] = z.xc[0];
         St<SL>::st(rlo + c, typename St<SL>::C(r));
         acc += r * r;
         z.advance();
@@ -306,23 +419,24 @@ __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restri
 // keeps the coarse planes K-1, K, K+1 of its tile (with a one-cell halo,
 // ghost values already carrying the boundary rule: wrapped, or the adjacent
 // interior cell negated per axis for Dirichlet) in an LDS ring; each thread
-// updates its column on fine planes 2K and 2K+1 from eight LDS values, while
+// updates its CPT columns on fine planes 2K and 2K+1 from LDS values, while
 // the coarse plane K+2 is in flight (one coarse cell per thread, clamped
 // loads).  Weights 3/4 (own coarse cell) and 1/4 (neighbour) per axis.
-template <class S, int TX>
+template <class S>
 __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ ec, S *__restrict__ x, int lg, int bc,
                                                          int zc, const int *stop) {
     typedef typename St<S>::C C;
-    constexpr int TY = kS3Threads / TX, CX = TX / 2 + 2, CY = TY / 2 + 2;
+    constexpr int CPT = ZCfg<S>::CPT, TX = ZCfg<S>::TX, TP = TX / CPT;
+    constexpr int TY = kS3Threads / TP, CX = TX / 2 + 2, CY = TY / 2 + 2;
     static_assert(CX * CY <= kS3Threads, "one coarse cell per thread");
     __shared__ C cp[3][CY][CX];
     if (stop && *stop) return;
     const int n = 1 << lg, nc = n >> 1, lgc = lg - 1, ntx = n / TX, nty = n / TY;
     const int blk = int(xcd_block(blockIdx.x, gridDim.x));
-    const int t = int(threadIdx.x), tx = t % TX, ty = t / TX;
+    const int t = int(threadIdx.x), tp = t % TP, ty = t / TP;
     const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
     const int x0 = bx * TX, y0 = by * TY, k0 = bz * zc, K0 = k0 >> 1;
-    const int64_t P = int64_t(1) << (2 * lg), col = (int64_t(y0 + ty) << lg) + x0 + tx;
+    const int64_t P = int64_t(1) << (2 * lg), col = (int64_t(y0 + ty) << lg) + x0 + CPT * tp;
     // coarse cell loaded by this thread: (cx, cy) in the tile, source column and sign
     const bool cw = t < CX * CY;
     const int cx = t % CX, cy = t / CX;
@@ -352,37 +466,61 @@ __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ e
         }
     }
     __syncthreads();
-    // own coarse cell in the tile and the neighbour side per axis
-    const int lx = (tx >> 1) + 1, ly = (ty >> 1) + 1;
-    const int nx = lx + ((tx & 1) ? 1 : -1), ny = ly + ((ty & 1) ? 1 : -1);
+    // per own cell: own coarse column and row in the tile and the neighbour side per axis
+    int lx[CPT], nx[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        const int ti = CPT * tp + c;  // cell index within the tile row
+        lx[c] = (ti >> 1) + 1;
+        nx[c] = lx[c] + ((ti & 1) ? 1 : -1);
+    }
+    const int ly = (ty >> 1) + 1, ny = ly + ((ty & 1) ? 1 : -1);
     const C w0 = C(0.75), w1 = C(0.25);
+    const LdC<S> vx{x};
     for (int K = K0; K < K0 + (zc >> 1); ++K) {
         const int64_t c0 = int64_t(2 * K) * P + col, c1 = c0 + P;
-        const C xa = St<S>::ld(x + c0), xb = St<S>::ld(x + c1);
+        C xa[CPT], xb[CPT];
+        if constexpr (CPT == 2) {
+            vx.pair(c0, xa[0], xa[1]);
+            vx.pair(c1, xb[0], xb[1]);
+        } else {
+            xa[0] = vx(c0);
+            xb[0] = vx(c1);
+        }
         const C nxt = cload(K + 2);  // ring slot of K - 1 after this plane pair
         const C(&own)[CY][CX] = cp[slot(K)];
-        // in-plane bilinear value of a coarse plane at this column
-        auto bil = [&](const C(&pl)[CY][CX]) -> C {
-            return w0 * (w0 * pl[ly][lx] + w1 * pl[ly][nx]) + w1 * (w0 * pl[ny][lx] + w1 * pl[ny][nx]);
-        };
-        const C eo = bil(own), em = bil(cp[slot(K - 1)]), ep = bil(cp[slot(K + 1)]);
-        St<S>::st(x + c0, xa + (w0 * eo + w1 * em));  // fine plane 2K: neighbour plane K - 1
-        St<S>::st(x + c1, xb + (w0 * eo + w1 * ep));  // fine plane 2K + 1: neighbour plane K + 1
+        const C(&below)[CY][CX] = cp[slot(K - 1)];
+        const C(&above)[CY][CX] = cp[slot(K + 1)];
+        for (int c = 0; c < CPT; ++c) {
+            // in-plane bilinear value of a coarse plane at this column
+            auto bil = [&](const C(&pl)[CY][CX]) -> C {
+                return w0 * (w0 * pl[ly][lx[c]] + w1 * pl[ly][nx[c]]) + w1 * (w0 * pl[ny][lx[c]] + w1 * pl[ny][nx[c]]);
+            };
+            const C eo = bil(own), em = bil(below), ep = bil(above);
+            xa[c] = xa[c] + (w0 * eo + w1 * em);  // fine plane 2K: neighbour plane K - 1
+            xb[c] = xb[c] + (w0 * eo + w1 * ep);  // fine plane 2K + 1: neighbour plane K + 1
+        }
+        store_cells<S, CPT>(x + c0, xa);
+        store_cells<S, CPT>(x + c1, xb);
         __syncthreads();  // every read of slot(K - 1) is done
         if (cw) cp[slot(K + 2)][cy][cx] = nxt;
         __syncthreads();
     }
 }
 
-// Planes per workgroup of k_sweep3 on an n^3 level: enough workgroups to fill
-// the chip, and at most `max_blocks` of them (one norm partial each).
-inline int sweep3_planes(int lg, int tx, int64_t max_blocks) {
+// Planes per workgroup of the z-marching kernels on an n^3 level with `cpt`
+// cells per thread: enough workgroups to fill the chip, and at most
+// `max_blocks` of them (one norm partial each).
+inline int sweep3_planes(int lg, int cpt, int64_t max_blocks) {
     const int n = 1 << lg;
-    const int64_t cols = int64_t(n) * n / kS3Threads;  // column tiles
+    const int64_t cols = int64_t(n) * n / (int64_t(kS3Threads) * cpt);  // column tiles
     int zc = n >= 256 ? 8 : 4;
     while (cols * (n / zc) > max_blocks && zc < n) zc *= 2;
-    (void)tx;
     return zc;
+}
+
+// Workgroups of a z-marching launch on an n^3 level (cpt cells per thread, zc planes).
+inline unsigned zblocks(int lg, int cpt, int zc) {
+    return unsigned((int64_t(1) << (3 * lg)) / (int64_t(kS3Threads) * cpt * zc));
 }
 
 // Fine cells per workgroup along x in k_restrict.

@@ -155,18 +155,70 @@ def test_sweep3_matches_direct_sweep(B, orc, bc):
 
 
 @pytest.mark.parametrize("bc", [DIR, PER])
-def test_prof_sweep_is_the_solver_sweep(B, orc, bc):
-    """The timing hook launches the solver's sweep: its output equals one oracle
-    Jacobi sweep (FP64, on the z-marching kernel's 128^3 level), and it reports a
-    positive duration."""
+def test_prof_level_runs_the_solver_kernels(B, orc, bc):
+    """The timing hook launches the solver's level kernels (FP64, 128^3, the z-marching
+    kernels): the sweep's output is one oracle Jacobi sweep, the restriction's is the
+    oracle's restricted residual, and reps + 1 prolongations add reps + 1 times the
+    oracle's P y; every call reports a positive duration."""
     n = 128
     rng = np.random.default_rng(5 + bc)
     f, x = rng.standard_normal((n, n, n)), rng.standard_normal((n, n, n))
+    yc = rng.standard_normal((n // 2,) * 3)
     h = 1.0 / n
     y = dev(np.zeros_like(x))
-    ms = B.np_prof_sweep(dev(f), dev(x), y, h, bc, B.FP64, reps=3)
-    assert ms > 0
+    assert B.np_prof_level(B.PROF_LEVEL_SWEEP, dev(f), dev(x), y, h, bc, B.FP64, reps=3) > 0
     assert rel(host(y), orc.jacobi(f, x, h, bc)) < 1e-13
+    c = dev(np.zeros_like(yc))
+    assert B.np_prof_level(B.PROF_LEVEL_RESTRICT, dev(f), dev(x), c, h, bc, B.FP64, reps=3) > 0
+    assert rel(host(c), orc.restrict(orc.residual(f, x, h, bc))) < 1e-13
+    xg = dev(x)
+    assert B.np_prof_level(B.PROF_LEVEL_PROLONG, None, xg, dev(yc), h, bc, B.FP64, reps=3) > 0
+    ref = x + 4 * (orc.prolong_add(yc, np.zeros_like(x), bc))
+    assert rel(host(xg), ref) < 1e-13
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_bf16_pair_kernels(B, orc, bc):
+    """BF16 storage on the z-marching kernels (two cells per thread): the sweep equals
+    the direct sweep bit for bit; restriction and prolongation match the FP64 oracle on
+    the BF16-rounded inputs to BF16 rounding of their terms."""
+    import torch
+    n = 128
+    h = 1.0 / n
+    rng = np.random.default_rng(21 + bc)
+
+    def b16(a):
+        return torch.from_numpy(a).to(torch.bfloat16).cuda()
+
+    def val(t):
+        return t.float().cpu().numpy().astype(np.float64)
+
+    f, x = b16(rng.standard_normal((n, n, n))), b16(rng.standard_normal((n, n, n)))
+    yc = b16(rng.standard_normal((n // 2,) * 3))
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("sweep3", v)
+            y = torch.zeros_like(x)
+            B.np_prof_level(B.PROF_LEVEL_SWEEP, f.view(torch.int16), x.view(torch.int16), y.view(torch.int16), h, bc,
+                            B.BF16, reps=1)
+            c = torch.zeros_like(yc)
+            B.np_prof_level(B.PROF_LEVEL_RESTRICT, f.view(torch.int16), x.view(torch.int16), c.view(torch.int16), h,
+                            bc, B.BF16, reps=1)
+            xp = x.clone()
+            B.np_prof_level(B.PROF_LEVEL_PROLONG, None, xp.view(torch.int16), yc.view(torch.int16), h, bc, B.BF16,
+                            reps=1)
+            out[v] = (val(y), val(c), val(xp))
+    finally:
+        B.np_set_tuning("sweep3", 1)
+    fv, xv, ycv = val(f), val(x), val(yc)
+    assert np.array_equal(out[1][0], out[0][0])
+    scale = np.max(np.abs(fv)) + 12 * np.max(np.abs(xv)) / h ** 2
+    ref_c = orc.restrict(orc.residual(fv, xv, h, bc))
+    ref_p = xv + 2 * orc.prolong_add(ycv, np.zeros_like(xv), bc)  # warm-up launch + one timed launch
+    for v in (1, 0):
+        assert np.max(np.abs(out[v][1] - ref_c)) <= 8e-3 * scale
+        assert np.max(np.abs(out[v][2] - ref_p)) <= 8e-3 * (np.max(np.abs(xv)) + 2 * np.max(np.abs(ycv)))
 
 
 def test_tuning_knobs_validate(B):
