@@ -55,13 +55,19 @@ def lib():
             "or_prolong_const_add": [_d, _i64, _p, _p],
             "or_sawtooth": [_d, _i64, _f64, _d, _f64, _d, _d, _i64, _p, _p],
             "or_saw_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _f64, _d, _d, _d, _d, _i64, _p, _p, _p, _d],
+            "or_ad_apply": [_p, _i64, _f64, _p, _p],
+            "or_ad_jacobi": [_p, _i64, _f64, _f64, _p, _p, _p],
+            "or_ad_vcycle": [_p, _i64, _f64, _d, _d, _f64, _i64, _p, _p],
+            "or_ad_sawtooth": [_p, _i64, _f64, _f64, _d, _d, _i64, _p, _p],
+            "or_ad_solve": [_p, _i64, _f64, _p, _p, _f64, _d, _d, _d, _f64, _d, _d, _d, _i64, _p, _p, _p, _p, _d],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = _f64 if name == "or_rel_res" else (None if name in (
                 "or_apply_A", "or_residual", "or_jacobi", "or_restrict", "or_prolong_add",
-                "or_divergence", "or_gradient", "or_ns_momentum", "or_prolong_const_add") else ctypes.c_int)
+                "or_divergence", "or_gradient", "or_ns_momentum", "or_prolong_const_add", "or_ad_apply",
+                "or_ad_jacobi") else ctypes.c_int)
         _lib = L
     return _lib
 
@@ -185,6 +191,68 @@ def saw_solve(f, h, bc, tol=1e-10, alpha=1.0, nu=1, prolong_const=True, max_cycl
     if st == -1:
         raise ValueError("oracle saw_solve: invalid arguments")
     return SolveResult(x, st, cyc.value, rr.value, hist[: min(cyc.value + 1, 256)])
+
+
+class AdOp(ctypes.Structure):
+    """The implicit advection-diffusion operator I + dt (a . D) + nu dt (-Laplacian)
+    (scheme 0 upwind, 1 central)."""
+    _fields_ = [("d", ctypes.c_int), ("bc", ctypes.c_int), ("scheme", ctypes.c_int), ("dt", ctypes.c_double),
+                ("nu", ctypes.c_double), ("a", ctypes.c_double * 3)]
+
+
+def ad_op(d, bc, dt, nu, a, scheme=0):
+    aa = list(a) + [0.0] * (3 - len(a))
+    return AdOp(d, bc, scheme, dt, nu, (ctypes.c_double * 3)(*aa))
+
+
+def ad_apply(op, x, h):
+    x = _arr(x)
+    d, n = _grid(x)
+    y = np.empty_like(x)
+    lib().or_ad_apply(ctypes.byref(op), n, h, _ptr(x), _ptr(y))
+    return y
+
+
+def ad_jacobi(op, f, x, h, omega=2.0 / 3.0):
+    f, x = _arr(f), _arr(x)
+    d, n = _grid(x)
+    y = np.empty_like(x)
+    lib().or_ad_jacobi(ctypes.byref(op), n, h, omega, _ptr(f), _ptr(x), _ptr(y))
+    return y
+
+
+def ad_vcycle(op, f, x, h, nu1=2, nu2=2, omega=2.0 / 3.0, n_coarsest=4):
+    f, x = _arr(f), _arr(x).copy()
+    d, n = _grid(x)
+    st = lib().or_ad_vcycle(ctypes.byref(op), n, h, nu1, nu2, omega, n_coarsest, _ptr(f), _ptr(x))
+    if st != 0:
+        raise RuntimeError("ad vcycle failed: %d" % st)
+    return x
+
+
+def ad_sawtooth(op, f, x, h, alpha=1.0, nu=1, prolong_const=True, n_coarsest=4):
+    f, x = _arr(f), _arr(x).copy()
+    d, n = _grid(x)
+    lib().or_ad_sawtooth(ctypes.byref(op), n, h, alpha, nu, int(prolong_const), n_coarsest, _ptr(f), _ptr(x))
+    return x
+
+
+def ad_solve(op, f, h, tol=1e-10, cycle=0, nu1=2, nu2=2, omega=2.0 / 3.0, prolong_const=False, max_cycles=200,
+             fixed_cycles=0, n_coarsest=4):
+    f = _arr(f)
+    d, n = _grid(f)
+    x = np.zeros_like(f)
+    cyc = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist, l1 = np.zeros(512), np.zeros(512)
+    st = lib().or_ad_solve(ctypes.byref(op), n, h, _ptr(f), _ptr(x), tol, cycle, nu1, nu2, omega, int(prolong_const),
+                           max_cycles, fixed_cycles, n_coarsest, ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist),
+                           _ptr(l1), 512)
+    if st == -1:
+        raise ValueError("oracle ad_solve: invalid arguments")
+    res = SolveResult(x, st, cyc.value, rr.value, hist[: min(cyc.value + 1, 512)])
+    res.l1diff = l1[: min(cyc.value, 512)]
+    return res
 
 
 class SolveResult:

@@ -1,6 +1,7 @@
 /*
- * Plain FP64 CPU oracle for the multigrid Poisson solve and the projection
- * time step of "Neural Physics" (Chen, Heaney, Pain, arXiv 2402.17913).
+ * Plain FP64 CPU oracle for the multigrid Poisson solve, the projection
+ * time step and the implicit advection-diffusion multigrid of "Neural
+ * Physics" (Chen, Heaney, Pain, arXiv 2402.17913).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
  * includes this file; it shares no source with the HIP path.  Only the test
@@ -420,6 +421,236 @@ int or_saw_solve(int d, i64 n, double h, int bc, const double *f_in, double *x, 
     if (cycles_out) *cycles_out = k;
     if (rel_res_out) *rel_res_out = rr;
     free(f); free(r);
+    return st;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Implicit advection-diffusion: the backward-Euler step of Section 2.2 (the
+ * implicit advection-diffusion equation and its filter), solved by multigrid
+ * in Section 3.2.  The operator is
+ *   A T = T + dt * sum_e a_e D_e T + nu * dt * (2d T_c - sum of the 2d face
+ *         neighbours) / h^2,
+ * with D_e the derivative along axis e: upwind (scheme 0: the backward
+ * difference (T_c - T_-e)/h for a_e >= 0, the forward one for a_e < 0) or
+ * central (scheme 1: (T_+e - T_-e)/(2h)).  Constant coefficients; ghosts by
+ * the boundary rule.  On coarser levels the same dt, nu and a with the
+ * level's spacing. */
+typedef struct {
+    int d, bc, scheme;
+    double dt, nu, a[3];
+} or_adop;
+
+/* The operator's centre weight c0 and its weights on the -e and +e neighbours. */
+static void adop_weights(const or_adop *op, double h, double *c0, double *cm, double *cp)
+{
+    const double dif = op->nu * op->dt / (h * h);
+    *c0 = 1.0 + 2.0 * op->d * dif;
+    for (int e = 0; e < op->d; ++e) {
+        const double ad = op->a[e] * op->dt / h;
+        cm[e] = -dif;
+        cp[e] = -dif;
+        if (op->scheme == 0) {
+            if (op->a[e] >= 0.0) { *c0 += ad; cm[e] -= ad; }
+            else { *c0 -= ad; cp[e] += ad; }
+        } else {
+            cm[e] -= 0.5 * ad;
+            cp[e] += 0.5 * ad;
+        }
+    }
+}
+
+/* y = A x on a grid of n cells per axis and spacing h. */
+void or_ad_apply(const or_adop *op, i64 n, double h, const double *x, double *y)
+{
+    const int d = op->d;
+    double c0, cm[3], cp[3];
+    adop_weights(op, h, &c0, cm, cp);
+    const i64 nz = d == 3 ? n : 1;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 c = (k * n + j) * n + i;
+                double s = c0 * x[c];
+                s += cm[0] * ghost_at(x, d, n, op->bc, i - 1, j, k) + cp[0] * ghost_at(x, d, n, op->bc, i + 1, j, k);
+                s += cm[1] * ghost_at(x, d, n, op->bc, i, j - 1, k) + cp[1] * ghost_at(x, d, n, op->bc, i, j + 1, k);
+                if (d == 3)
+                    s += cm[2] * ghost_at(x, d, n, op->bc, i, j, k - 1) + cp[2] * ghost_at(x, d, n, op->bc, i, j, k + 1);
+                y[c] = s;
+            }
+}
+
+static void ad_residual(const or_adop *op, i64 n, double h, const double *f, const double *x, double *r)
+{
+    or_ad_apply(op, n, h, x, r);
+    const i64 m = ncells(op->d, n);
+    for (i64 c = 0; c < m; ++c) r[c] = f[c] - r[c];
+}
+
+/* Weighted Jacobi on the operator: x_out = x + omega (f - A x) / c0. */
+void or_ad_jacobi(const or_adop *op, i64 n, double h, double omega, const double *f, const double *x_in,
+                  double *x_out)
+{
+    double c0, cm[3], cp[3];
+    adop_weights(op, h, &c0, cm, cp);
+    or_ad_apply(op, n, h, x_in, x_out);
+    const i64 m = ncells(op->d, n);
+    for (i64 c = 0; c < m; ++c) x_out[c] = x_in[c] + omega * (f[c] - x_out[c]) / c0;
+}
+
+/* Exact solve on the coarsest grid: the matrix assembled column by column
+ * from the operator, Gaussian elimination with partial pivoting (A is not
+ * symmetric); x <- x + A^{-1} (f - A x). */
+int or_ad_coarse_solve(const or_adop *op, i64 n, double h, const double *f, double *x)
+{
+    const i64 m = ncells(op->d, n);
+    double *a = malloc(sizeof(double) * m * m), *e = calloc(m, sizeof(double));
+    double *col = malloc(sizeof(double) * m), *r = malloc(sizeof(double) * m);
+    for (i64 j = 0; j < m; ++j) {
+        e[j] = 1.0;
+        or_ad_apply(op, n, h, e, col);
+        e[j] = 0.0;
+        for (i64 i = 0; i < m; ++i) a[i * m + j] = col[i];
+    }
+    ad_residual(op, n, h, f, x, r);
+    int st = OR_OK;
+    for (i64 p = 0; p < m && st == OR_OK; ++p) {
+        i64 piv = p;
+        for (i64 i = p + 1; i < m; ++i)
+            if (fabs(a[i * m + p]) > fabs(a[piv * m + p])) piv = i;
+        if (!(fabs(a[piv * m + p]) > 0.0)) { st = OR_EINVAL; break; }
+        if (piv != p) {
+            for (i64 q = 0; q < m; ++q) { const double t = a[p * m + q]; a[p * m + q] = a[piv * m + q]; a[piv * m + q] = t; }
+            const double t = r[p]; r[p] = r[piv]; r[piv] = t;
+        }
+        for (i64 i = p + 1; i < m; ++i) {
+            const double l = a[i * m + p] / a[p * m + p];
+            for (i64 q = p; q < m; ++q) a[i * m + q] -= l * a[p * m + q];
+            r[i] -= l * r[p];
+        }
+    }
+    if (st == OR_OK) {
+        for (i64 i = m - 1; i >= 0; --i) {
+            double t = r[i];
+            for (i64 q = i + 1; q < m; ++q) t -= a[i * m + q] * r[q];
+            r[i] = t / a[i * m + i];
+        }
+        for (i64 i = 0; i < m; ++i) x[i] += r[i];
+    }
+    free(a); free(e); free(col); free(r);
+    return st;
+}
+
+/* One V(nu1, nu2) cycle of the operator (the steps of or_vcycle with this
+ * operator, its Jacobi and its exact coarsest solve). */
+int or_ad_vcycle(const or_adop *op, i64 n, double h, int nu1, int nu2, double omega, i64 n_coarsest,
+                 const double *f, double *x)
+{
+    const int d = op->d;
+    if (n <= n_coarsest) return or_ad_coarse_solve(op, n, h, f, x);
+    const i64 m = ncells(d, n), nc = n / 2, mc = ncells(d, nc);
+    double *t = malloc(sizeof(double) * m);
+    double *fc = malloc(sizeof(double) * mc), *ec = calloc(mc, sizeof(double));
+    for (int s = 0; s < nu1; ++s) {
+        or_ad_jacobi(op, n, h, omega, f, x, t);
+        memcpy(x, t, sizeof(double) * m);
+    }
+    ad_residual(op, n, h, f, x, t);
+    or_restrict(d, n, t, fc);
+    int st = or_ad_vcycle(op, nc, 2.0 * h, nu1, nu2, omega, n_coarsest, fc, ec);
+    or_prolong_add(d, nc, op->bc, ec, x);
+    for (int s = 0; s < nu2; ++s) {
+        or_ad_jacobi(op, n, h, omega, f, x, t);
+        memcpy(x, t, sizeof(double) * m);
+    }
+    free(t); free(fc); free(ec);
+    return st;
+}
+
+/* One sawtooth cycle of the operator (the steps of or_sawtooth with this
+ * operator; its centre weight c0 plays the role of A_00). */
+int or_ad_sawtooth(const or_adop *op, i64 n, double h, double alpha, int nu, int prolong_const, i64 n_coarsest,
+                   const double *f, double *x)
+{
+    const int d = op->d;
+    int L = 0;
+    while ((n >> L) > n_coarsest) ++L;
+    double **r = calloc(L + 1, sizeof(double *)), **e = calloc(L + 1, sizeof(double *));
+    for (int l = 0; l <= L; ++l) {
+        r[l] = malloc(sizeof(double) * ncells(d, n >> l));
+        e[l] = calloc(ncells(d, n >> l), sizeof(double));
+    }
+    double *t = malloc(sizeof(double) * ncells(d, n));
+    ad_residual(op, n, h, f, x, r[0]);
+    for (int l = 0; l < L; ++l) or_restrict(d, n >> l, r[l], r[l + 1]);
+    for (int l = L; l >= 0; --l) {
+        const i64 nl = n >> l, ml = ncells(d, nl);
+        const double hl = h * (double)((i64)1 << l);
+        double c0, cm[3], cp[3];
+        adop_weights(op, hl, &c0, cm, cp);
+        for (i64 c = 0; c < ml; ++c) e[l][c] = r[l][c] / c0;
+        if (l < L) {
+            if (prolong_const) or_prolong_const_add(d, nl / 2, e[l + 1], e[l]);
+            else or_prolong_add(d, nl / 2, op->bc, e[l + 1], e[l]);
+        }
+        for (int s = 0; s < nu; ++s) {
+            or_ad_jacobi(op, nl, hl, alpha, r[l], e[l], t);
+            memcpy(e[l], t, sizeof(double) * ml);
+        }
+    }
+    const i64 m = ncells(d, n);
+    for (i64 c = 0; c < m; ++c) x[c] += e[0][c];
+    for (int l = 0; l <= L; ++l) { free(r[l]); free(e[l]); }
+    free(r); free(e); free(t);
+    return OR_OK;
+}
+
+/* Tolerance driver: from x = 0, cycles (cycle 0: V(nu1, nu2) with omega;
+ * cycle 1: sawtooth with alpha = omega, nu2 steps, prolong_const) until
+ * ||f - A x||_2 / ||f||_2 <= tol, tested before every cycle, or exactly
+ * fixed_cycles cycles.  The operator is nonsingular for both boundary rules
+ * (identity term), so no mean is removed.  hist as in or_mg_solve; l1diff
+ * (may be NULL) receives the L1 norm of x_k - x_{k-1} after each cycle, the
+ * paper's convergence gauge of Section 3.2. */
+int or_ad_solve(const or_adop *op, i64 n, double h, const double *f, double *x, double tol, int cycle, int nu1,
+                int nu2, double omega, int prolong_const, int max_cycles, int fixed_cycles, i64 n_coarsest,
+                int *cycles_out, double *rel_res_out, double *hist, double *l1diff, int hist_len)
+{
+    const int d = op->d;
+    if ((d != 2 && d != 3) || !is_pow2(n) || n < 4 || !is_pow2(n_coarsest) || n_coarsest < 1 || !(h > 0.0) ||
+        !(tol > 0.0) || nu1 < 0 || nu2 < 0 || (cycle != 0 && cycle != 1))
+        return OR_EINVAL;
+    const i64 m = ncells(d, n);
+    double *r = malloc(sizeof(double) * m), *xo = malloc(sizeof(double) * m);
+    const double nf = sqrt(dot(m, f, f));
+    int st = OR_OK, k = 0;
+    double rr = 0.0;
+    memset(x, 0, sizeof(double) * m);
+    if (nf > 0.0) {
+        for (;;) {
+            ad_residual(op, n, h, f, x, r);
+            rr = sqrt(dot(m, r, r)) / nf;
+            if (hist && k < hist_len) hist[k] = rr;
+            if (fixed_cycles > 0) {
+                if (k >= fixed_cycles) break;
+            } else {
+                if (rr <= tol) break;
+                if (k >= max_cycles || !(rr < 1e300)) { st = OR_ENOCONV; break; }
+            }
+            memcpy(xo, x, sizeof(double) * m);
+            int s = cycle == 0 ? or_ad_vcycle(op, n, h, nu1, nu2, omega, n_coarsest, f, x)
+                               : or_ad_sawtooth(op, n, h, omega, nu2, prolong_const, n_coarsest, f, x);
+            if (s != OR_OK) { st = s; break; }
+            if (l1diff && k < hist_len) {
+                double l1 = 0.0;
+                for (i64 c = 0; c < m; ++c) l1 += fabs(x[c] - xo[c]);
+                l1diff[k] = l1;
+            }
+            ++k;
+        }
+    }
+    if (cycles_out) *cycles_out = k;
+    if (rel_res_out) *rel_res_out = rr;
+    free(r); free(xo);
     return st;
 }
 

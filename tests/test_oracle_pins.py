@@ -663,3 +663,204 @@ def test_sawtooth_literal_reading_diverges_and_damped_linear_converges(orc):
     assert rho(lit) > 1.0
     assert rho(damped) < 1.0
     assert rho(dense_vcycle_error(d, n, h, DIR)) < rho(damped)
+
+
+# ------------------------- implicit advection-diffusion (Section 2.2, Section 3.2)
+def ad_dense(orc, op, n, h):
+    """The oracle's advection-diffusion operator as a dense matrix, column by column."""
+    d = op.d
+    m = n ** d
+    return np.stack([vec(orc.ad_apply(op, e.reshape((n,) * d), h)) for e in np.eye(m)], axis=1)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_ad_operator_without_velocity_is_identity_plus_diffusion(orc, d, n, bc):
+    """With a = 0 the backward-Euler operator is I + nu dt (-Lap_h), -Lap_h the
+    dense brute-force Laplacian above (boundary ghosts included)."""
+    h, dt, nu = 0.5, 3.0, 0.7
+    op = orc.ad_op(d, bc, dt, nu, [0.0] * d, 0)
+    A = ad_dense(orc, op, n, h)
+    assert np.max(np.abs(A - (np.eye(n ** d) + nu * dt * dense_laplacian(d, n, h, bc)))) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("d", [2, 3])
+def test_ad_operator_fourier_symbol(orc, scheme, d):
+    """Periodic constant-coefficient operator is diagonal in Fourier space: each mode
+    exp(i theta . j) is scaled by 1 + dt sum_e a_e D_e(theta_e) + nu dt sum_e (2 - 2 cos
+    theta_e) / h^2, with D(theta) = (1 - e^{-i theta}) / h for upwind and a >= 0 (the
+    value comes from upstream), (e^{i theta} - 1) / h for a < 0, i sin(theta) / h for
+    central differences."""
+    n, h, dt, nu = 8, 0.5, 1.7, 0.3
+    a = [1.3, -0.6, 0.9][:d]
+    op = orc.ad_op(d, PER, dt, nu, a, scheme)
+    x = np.random.default_rng(5).standard_normal((n,) * d)
+    y = orc.ad_apply(op, x, h)
+    th = 2 * np.pi * np.fft.fftfreq(n)
+    lam = np.ones((n,) * d, dtype=complex)
+    for e in range(d):
+        shape = [1] * d
+        shape[d - 1 - e] = n  # axis e (x fastest) is the last array axis
+        t = th.reshape(shape)
+        if scheme == 1:
+            De = 1j * np.sin(t) / h
+        elif a[e] >= 0:
+            De = (1 - np.exp(-1j * t)) / h
+        else:
+            De = (np.exp(1j * t) - 1) / h
+        lam = lam + dt * a[e] * De + nu * dt * (2 - 2 * np.cos(t)) / h ** 2
+    assert np.max(np.abs(np.fft.fftn(y) - lam * np.fft.fftn(x))) < 1e-10
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_ad_transpose_reverses_the_velocity(orc, scheme):
+    """On a periodic grid the adjoint of the difference operators is the same operator
+    for the reversed flow: A(a)^T = A(-a), for upwind and central advection."""
+    n, h = 8, 1.0
+    A = ad_dense(orc, orc.ad_op(2, PER, 2.0, 0.4, [1.0, -0.5], scheme), n, h)
+    B = ad_dense(orc, orc.ad_op(2, PER, 2.0, 0.4, [-1.0, 0.5], scheme), n, h)
+    assert np.max(np.abs(A.T - B)) < 1e-12
+    assert np.max(np.abs(A - A.T)) > 0.1  # advection makes it non-symmetric
+
+
+def test_ad_upwind_is_an_m_matrix(orc):
+    """Upwind differencing gives non-positive off-diagonals and a diagonal at least the
+    sum of their magnitudes plus one (the identity term) away from Dirichlet walls."""
+    n, h = 8, 1.0
+    A = ad_dense(orc, orc.ad_op(2, DIR, 50.0, 2.0, [1.0, 1.0], 0), n, h)
+    off = A - np.diag(np.diag(A))
+    assert np.all(off <= 0.0)
+    assert np.all(np.diag(A) + off.sum(axis=1) >= 1.0 - 1e-12)
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("bc", [DIR, PER])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_ad_converged_solve_equals_dense_solve(orc, d, n, bc, scheme):
+    h = 1.0
+    op = orc.ad_op(d, bc, 4.0, 0.5, [1.0, -0.7, 0.4][:d], scheme)
+    f = np.random.default_rng(2).standard_normal((n,) * d)
+    r = orc.ad_solve(op, f, h, tol=1e-13)
+    assert r.status == 0
+    x_ref = np.linalg.solve(ad_dense(orc, op, n, h), vec(f))
+    assert np.max(np.abs(vec(r.x) - x_ref)) < 1e-10 * np.max(np.abs(x_ref))
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_ad_coarsest_solve_is_exact(orc, bc):
+    """At or below the coarsest size one cycle is the exact solve (pivoted elimination)."""
+    n, h = 4, 2.0
+    op = orc.ad_op(2, bc, 50.0, 2.0, [1.0, 1.0], 0)
+    f = np.random.default_rng(3).standard_normal((n, n))
+    x = orc.ad_vcycle(op, f, np.zeros_like(f), h)
+    assert np.max(np.abs(vec(x) - np.linalg.solve(ad_dense(orc, op, n, h), vec(f)))) < 1e-12
+
+
+def centre_weight(orc, op, h):
+    """The operator's centre weight A_00: the diagonal of a periodic matrix (no wall
+    ghost folded into it)."""
+    per = orc.ad_op(op.d, PER, op.dt, op.nu, list(op.a)[:op.d], op.scheme)
+    return ad_dense(orc, per, 4, h)[0, 0]
+
+
+def dense_ad_vcycle_error(orc, op, n, h, nu1=2, nu2=2, omega=OMEGA, n_coarsest=4):
+    """V(nu1, nu2) error propagator from dense pieces: Jacobi S = I - omega A / A_00,
+    coarse-grid correction I - P (I - E_c) A_c^{-1} R A, A on each level the operator
+    re-discretised at that level's spacing."""
+    d = op.d
+    A = ad_dense(orc, op, n, h)
+    m = n ** d
+    if n <= n_coarsest:
+        return np.zeros((m, m))
+    S = np.eye(m) - omega * A / centre_weight(orc, op, h)
+    nc = n // 2
+    R, P = dense_restrict(d, n), dense_prolong(d, nc, op.bc)
+    Ac = ad_dense(orc, op, nc, 2 * h)
+    Ec = dense_ad_vcycle_error(orc, op, nc, 2 * h, nu1, nu2, omega, n_coarsest)
+    coarse = (np.eye(nc ** d) - Ec) @ np.linalg.inv(Ac)
+    CGC = np.eye(m) - P @ coarse @ R @ A
+    return np.linalg.matrix_power(S, nu2) @ CGC @ np.linalg.matrix_power(S, nu1)
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_ad_vcycle_error_matrix(orc, d, n, bc):
+    h = 1.0
+    op = orc.ad_op(d, bc, 50.0, 2.0, [1.0, 1.0, -0.5][:d], 0)
+    f = np.zeros((n,) * d)
+    E = np.stack([vec(orc.ad_vcycle(op, f, e.reshape((n,) * d), h)) for e in np.eye(n ** d)], axis=1)
+    assert np.max(np.abs(E - dense_ad_vcycle_error(orc, op, n, h))) < 1e-11
+
+
+def dense_ad_saw_map(orc, op, n, h, alpha, nu, const, n_coarsest=4):
+    """The sawtooth's up-leg map r -> e on a level, as dense_saw_map with the
+    advection-diffusion operator and its centre weight as A_00."""
+    d = op.d
+    A = ad_dense(orc, op, n, h)
+    m = n ** d
+    dinv = 1.0 / centre_weight(orc, op, h)
+    M = dinv * np.eye(m)
+    if n > n_coarsest:
+        R = dense_restrict(d, n)
+        P = dense_prolong_const(d, n // 2) if const else dense_prolong(d, n // 2, op.bc)
+        M = M + P @ dense_ad_saw_map(orc, op, n // 2, 2 * h, alpha, nu, const, n_coarsest) @ R
+    J = np.eye(m) - alpha * dinv * A
+    for _ in range(nu):
+        M = J @ M + alpha * dinv * np.eye(m)
+    return M
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
+@pytest.mark.parametrize("alpha,nu,const", [(1.0, 1, True), (1.0, 1, False), (2.0 / 3.0, 2, False)])
+def test_ad_sawtooth_error_matrix(orc, bc, alpha, nu, const):
+    n, d, h = 16, 2, 1.0
+    op = orc.ad_op(d, bc, 50.0, 2.0, [1.0, 1.0], 0)
+    E_ref = np.eye(n * n) - dense_ad_saw_map(orc, op, n, h, alpha, nu, const) @ ad_dense(orc, op, n, h)
+    f = np.zeros((n, n))
+    E = np.stack([vec(orc.ad_sawtooth(op, f, e.reshape(n, n), h, alpha=alpha, nu=nu, prolong_const=const))
+                  for e in np.eye(n * n)], axis=1)
+    assert np.max(np.abs(E - E_ref)) < 1e-11
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_ad_solution_moments(orc, scheme):
+    """Backward Euler on a periodic grid conserves mass, moves the centroid by a dt per
+    axis and widens the variance by 2 nu dt + (a dt)^2, plus |a| dt h for upwind (its
+    numerical diffusion): summation by parts on the difference operators, exact while the
+    solution is negligible at the wrap (the step's response decays downstream over about
+    5 cells here).  Gaussian, gamma = 10, 512^2."""
+    n, h, dt, nu = 512, 1.0, 4.0, 1.0
+    a = [1.0, -0.5]
+    op = orc.ad_op(2, PER, dt, nu, a, scheme)
+    T0 = inputs.gaussian_2d(n, gamma=10.0)
+    r = orc.ad_solve(op, T0, h, tol=1e-13)
+    assert r.status == 0
+    T = r.x
+    c = (np.arange(n) - (n - 1) / 2) * h
+    for axis, e in ((1, 0), (0, 1)):  # array axis 1 is x (e = 0), axis 0 is y
+        w0, w = T0.sum(axis=1 - axis), T.sum(axis=1 - axis)
+        assert abs(w.sum() - w0.sum()) < 1e-9 * w0.sum()
+        m0, m1 = (c * w0).sum() / w0.sum(), (c * w).sum() / w.sum()
+        assert abs(m1 - m0 - a[e] * dt) < 1e-8
+        v0 = (c ** 2 * w0).sum() / w0.sum() - m0 ** 2
+        v1 = (c ** 2 * w).sum() / w.sum() - m1 ** 2
+        growth = 2 * nu * dt + (a[e] * dt) ** 2 + (abs(a[e]) * dt * h if scheme == 0 else 0.0)
+        assert abs(v1 - v0 - growth) < 1e-7 * growth
+
+
+def test_ad_paper_experiment_readings(orc):
+    """The multigrid experiment of Section 3.2 (128^2, Dirichlet, u = v = 1, nu = 2,
+    dt = 50, Gaussian gamma = 10, upwind, zero first guess), gauged as there by the L1
+    norm of the change between successive iterates.  As printed (alpha = 1, one step,
+    copying prolongation) the sawtooth diverges; with linear prolongation it reduces
+    the gauge by over three orders in 50 cycles, as reported; V(2,2) converges fast."""
+    n = 128
+    op = orc.ad_op(2, DIR, 50.0, 2.0, [1.0, 1.0], 0)
+    T0 = inputs.gaussian_2d(n, gamma=10.0)
+    lit = orc.ad_solve(op, T0, 1.0, cycle=1, nu2=1, omega=1.0, prolong_const=True, fixed_cycles=50)
+    lin = orc.ad_solve(op, T0, 1.0, cycle=1, nu2=1, omega=1.0, prolong_const=False, fixed_cycles=50)
+    v = orc.ad_solve(op, T0, 1.0, tol=1e-10)
+    assert lit.l1diff[-1] > lit.l1diff[0]
+    assert lin.l1diff[-1] < 1e-3 * lin.l1diff[0]
+    assert v.status == 0 and v.cycles < 30
