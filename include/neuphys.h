@@ -164,6 +164,44 @@ np_status np_last_autotune(int *inner_cycles, double *ms);
 np_status np_ad_scalar_step(np_dims dims, double h, double *T, const double *const *a, double dt,
                             double nu, np_bc bc, const np_mg_opts *opts);
 
+/* ---------------------------------------------------------------------- */
+/* Implicit advection-diffusion (Section 2.2, the backward-Euler operator of
+ * the advection-diffusion equation; its multigrid solve is the experiment of
+ * Section 3.2).  One time step A T^{n+1} = T^n with
+ *   A T = T + dt sum_e a_e D_e T + nu dt (2d T_c - sum of face neighbours) / h^2,
+ * D_e the first difference along axis e: upwind (scheme 0: (T_c - T_{c-e})/h
+ * for a_e >= 0, (T_{c+e} - T_c)/h for a_e < 0) or central (scheme 1:
+ * (T_{c+e} - T_{c-e})/(2h)).  Constant coefficients; ghosts by the boundary
+ * rule.  Coarser levels re-discretise with their own spacing, dt and a fixed. */
+typedef struct {
+    double dt;     /* time step, > 0 */
+    double nu;     /* diffusivity, >= 0 */
+    double a[3];   /* advection velocity along x, y, z (a[2] ignored in 2D) */
+    int scheme;    /* 0 upwind, 1 central */
+} np_ad_op;
+
+/*
+ * Multigrid solve of A x = rhs for the operator above, FP64.  opts as for
+ * mg_poisson_solve: cycle 0 is V(nu1, nu2) with relaxed Jacobi dividing by
+ * the filter centre A_00, linear prolongation and the exact (pivoted) solve on
+ * the 4^d grid; cycle 1 is the paper's sawtooth (nu1 = 0, nu2 steps with
+ * alpha = omega, prolong 0 linear / 1 copy).  smooth_prec must be NP_FP64 and
+ * warm_start 0 (x zeroed: the paper's zero first estimate) or 2 (x is the
+ * guess).  Stops when ||rhs - A x||_2 / ||rhs||_2 <= tol, tested before each
+ * cycle, or after fixed_cycles; three successive increases end it with
+ * NP_ENOCONV.  rhs, x: device FP64 n^d.  l1_change: host, nullable, 256
+ * entries: entry k receives ||x_{k+1} - x_k||_1 over cycle k + 1 (the
+ * convergence gauge of Section 3.2), zero past the last cycle.  opts, stats:
+ * host, nullable.  A zero rhs returns x = 0, 0 cycles.
+ */
+np_status np_ad_implicit_solve(np_dims dims, double h, np_bc bc, const np_ad_op *op, const double *rhs, double *x,
+                               double tol, const np_mg_opts *opts, np_mg_stats *stats, double *l1_change);
+
+/* y = A x for the operator above (device FP64 n^d, y must not alias x);
+ * synchronises the stream. */
+np_status np_ad_apply(np_dims dims, double h, np_bc bc, const np_ad_op *op, const double *x, double *y,
+                      void *stream);
+
 /* ns_projection_step that also copies the pressure-correction right-hand
  * side -(1/dt) D q* and the increment dp it solved for into rhs_out and
  * dp_out (device FP64, n^d each; either may be NULL).  Used to generate

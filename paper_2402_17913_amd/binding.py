@@ -43,6 +43,17 @@ class NpMgStats(ctypes.Structure):
                     rho_est=self.rho_est, hist=list(self.hist[:n]))
 
 
+class NpAdOp(ctypes.Structure):
+    """Backward-Euler advection-diffusion operator (scheme 0 upwind, 1 central)."""
+    _fields_ = [("dt", ctypes.c_double), ("nu", ctypes.c_double), ("a", ctypes.c_double * 3),
+                ("scheme", ctypes.c_int)]
+
+
+def ad_op(dt, nu, a, scheme=0):
+    aa = list(a) + [0.0] * (3 - len(a))
+    return NpAdOp(dt, nu, (ctypes.c_double * 3)(*aa), scheme)
+
+
 class NeuphysError(RuntimeError):
     def __init__(self, fn, status, msg):
         super().__init__("%s -> %s: %s" % (fn, _STATUS.get(status, status), msg))
@@ -94,6 +105,9 @@ _SIGS = {
                           ctypes.POINTER(_D)]),
     "np_get_tuning": (_I, [ctypes.c_char_p]),
     "np_prof_level": (_I, [NpDims, _D, _I, _I, _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
+    "np_ad_implicit_solve": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _D, ctypes.POINTER(NpMgOpts),
+                                  ctypes.POINTER(NpMgStats), ctypes.POINTER(_D)]),
+    "np_ad_apply": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _P]),
 }
 
 
@@ -329,6 +343,27 @@ def np_ad_scalar_step(T, h, dt, nu, bc, a=None):
     s = lib.np_ad_scalar_step(_dims(T), h, _dev(T), ctypes.cast(arr, ctypes.c_void_p) if arr else None,
                               dt, nu, bc, ctypes.byref(o))
     _check("np_ad_scalar_step", s)
+
+
+def np_ad_implicit_solve(rhs, x, h, bc, op, tol=1e-10, check=True, l1=False, **opts):
+    """Solves the backward-Euler advection-diffusion system A x = rhs in place in x
+    (op from ad_op); returns (status, stats dict), with stats["l1_change"] the
+    per-cycle L1 change of the iterate when l1 is set."""
+    o = make_opts(**opts)
+    st = NpMgStats()
+    buf = (ctypes.c_double * 256)() if l1 else None
+    s = lib.np_ad_implicit_solve(_dims(rhs), h, bc, ctypes.byref(op), _dev(rhs), _dev(x), tol, ctypes.byref(o),
+                                 ctypes.byref(st), buf)
+    if check:
+        _check("np_ad_implicit_solve", s)
+    d = st.as_dict()
+    if l1:
+        d["l1_change"] = list(buf[:min(256, st.cycles)])
+    return s, d
+
+
+def np_ad_apply(x, y, h, bc, op):
+    _check("np_ad_apply", lib.np_ad_apply(_dims(x), h, bc, ctypes.byref(op), _dev(x), _dev(y), _stream()))
 
 
 def np_op_apply(x, y, h, bc):

@@ -1,0 +1,182 @@
+// Device kernels of the implicit advection-diffusion multigrid (gfx950), FP64.
+// Included by mg.hip after mg_kernels.h.
+//
+// The backward-Euler operator of Section 2.2 with constant coefficients,
+// re-discretised on every level with that level's spacing:
+//   (A x)_c = c0 x_c + sum_e (cm[e] x_{c - e} + cp[e] x_{c + e}),
+// with the weights of AdW (see ad_weights in mg.hip); ghosts by the boundary
+// rule (Dirichlet-0: -(own value); periodic: wrap).  The centre weight c0 is
+// the filter centre A_00 that Jacobi divides by.
+#pragma once
+
+#include "mg_kernels.h"
+
+namespace np {
+
+struct AdW {
+    double c0;
+    double cm[3], cp[3];
+};
+
+// (A x)_c at cell c = (i, j, k).
+template <int D>
+__device__ __forceinline__ double ad_ax(const double *__restrict__ x, int64_t c, int i, int j, int k, int lg, int bc,
+                                        const AdW &W) {
+    const int n = 1 << lg;
+    const int64_t sy = int64_t(1) << lg;
+    const double xc = x[c];
+    const double xm = i > 0 ? x[c - 1] : (bc ? x[c + (n - 1)] : -xc);
+    const double xp = i < n - 1 ? x[c + 1] : (bc ? x[c - (n - 1)] : -xc);
+    const double ym = j > 0 ? x[c - sy] : (bc ? x[c + (n - 1) * sy] : -xc);
+    const double yp = j < n - 1 ? x[c + sy] : (bc ? x[c - (n - 1) * sy] : -xc);
+    double s = W.c0 * xc + (W.cm[0] * xm + W.cp[0] * xp) + (W.cm[1] * ym + W.cp[1] * yp);
+    if (D == 3) {
+        const int64_t sz = int64_t(1) << (2 * lg);
+        const double zm = k > 0 ? x[c - sz] : (bc ? x[c + (n - 1) * sz] : -xc);
+        const double zp = k < n - 1 ? x[c + sz] : (bc ? x[c - (n - 1) * sz] : -xc);
+        s += W.cm[2] * zm + W.cp[2] * zp;
+    }
+    return s;
+}
+
+// y = A x.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ad_apply(const double *__restrict__ x, double *__restrict__ y, int lg,
+                                                     int bc, AdW W) {
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int i, j, k;
+    decode<D>(c, lg, i, j, k);
+    y[c] = ad_ax<D>(x, c, i, j, k, lg, bc, W);
+}
+
+// One relaxed-Jacobi sweep x_out = x_in + omega (f - A x_in) / c0 (wdiag =
+// omega / c0).  ZERO: x_in is identically zero, x_out = wdiag f.  NORM: the
+// grid is strided (gridDim.x <= the partial count) and each workgroup writes
+// its share of ||f - A x_in||^2 to partial[blockIdx.x] (fixed order).
+template <int D, bool ZERO, bool NORM>
+__global__ __launch_bounds__(kBlock) void k_ad_sweep(const double *__restrict__ f, const double *__restrict__ xin,
+                                                     double *__restrict__ xout, double *__restrict__ partial, int lg,
+                                                     int bc, AdW W, double wdiag, const int *stop) {
+    if (stop && *stop) return;
+    const int64_t m = int64_t(1) << (D * lg);
+    if (!NORM) {
+        const int64_t c = int64_t(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
+        if (c >= m) return;
+        if (ZERO) {
+            xout[c] = wdiag * f[c];
+            return;
+        }
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        xout[c] = xin[c] + wdiag * (f[c] - ad_ax<D>(xin, c, i, j, k, lg, bc, W));
+        return;
+    }
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m; c += int64_t(gridDim.x) * blockDim.x) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        const double r = f[c] - ad_ax<D>(xin, c, i, j, k, lg, bc, W);
+        xout[c] = xin[c] + wdiag * r;
+        acc += r * r;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// r = f - A x; with partial != null each workgroup of the strided grid also
+// writes its share of ||r||^2 (r may be null: the norm alone).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ad_resid(const double *__restrict__ f, const double *__restrict__ x,
+                                                     double *__restrict__ r, double *__restrict__ partial, int lg,
+                                                     int bc, AdW W, const int *stop) {
+    if (stop && *stop) return;
+    const int64_t m = int64_t(1) << (D * lg);
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m; c += int64_t(gridDim.x) * blockDim.x) {
+        int i, j, k;
+        decode<D>(c, lg, i, j, k);
+        const double v = f[c] - ad_ax<D>(x, c, i, j, k, lg, bc, W);
+        if (r) r[c] = v;
+        acc += v * v;
+    }
+    if (!partial) return;
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// fc = R (f - A x): one thread per coarse cell averages the residual of its
+// 2^d children.  lg is the fine level's log2 size.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_ad_resid_restrict(const double *__restrict__ f,
+                                                              const double *__restrict__ x, double *__restrict__ fc,
+                                                              int lg, int bc, AdW W, const int *stop) {
+    if (stop && *stop) return;
+    const int lgc = lg - 1;
+    const int64_t mc = int64_t(1) << (D * lgc);
+    const int64_t c = int64_t(xcd_block(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
+    if (c >= mc) return;
+    int I, J, K;
+    decode<D>(c, lgc, I, J, K);
+    double acc = 0.0;
+    for (int kk = 0; kk < (D == 3 ? 2 : 1); ++kk)
+        for (int jj = 0; jj < 2; ++jj)
+            for (int ii = 0; ii < 2; ++ii) {
+                const int i = 2 * I + ii, j = 2 * J + jj, k = D == 3 ? 2 * K + kk : 0;
+                const int64_t cf = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
+                acc += f[cf] - ad_ax<D>(x, cf, i, j, k, lg, bc, W);
+            }
+    fc[c] = acc * (D == 3 ? 0.125 : 0.25);
+}
+
+// Exact solve on the 4^d coarsest grid: x <- x + Minv (f - A x), Minv the
+// dense inverse of the level's operator.  One workgroup of 64.
+template <int D>
+__global__ __launch_bounds__(64) void k_ad_coarse(const double *__restrict__ f, double *__restrict__ x,
+                                                  const double *__restrict__ Minv, int bc, AdW W, int zero,
+                                                  const int *stop) {
+    constexpr int m = D == 3 ? 64 : 16;
+    if (stop && *stop) return;
+    __shared__ double xs[64], rs[64];
+    const int t = threadIdx.x;
+    if (t < m) xs[t] = zero ? 0.0 : x[t];
+    __syncthreads();
+    if (t < m) {
+        int i, j, k;
+        decode<D>(t, 2, i, j, k);
+        rs[t] = f[t] - ad_ax<D>(xs, t, i, j, k, 2, bc, W);
+    }
+    __syncthreads();
+    if (t < m) {
+        double s = 0.0;
+        for (int q = 0; q < m; ++q) s += Minv[t * m + q] * rs[q];
+        x[t] = xs[t] + s;
+    }
+}
+
+// Partials of ||a - b||_1 (||a||_1 when b is null) over a strided grid (fixed
+// order), gated by the controller: the change of the iterate over the cycle
+// just run.
+static __global__ __launch_bounds__(kBlock) void k_l1_diff(const double *__restrict__ a, const double *__restrict__ b,
+                                                         int64_t m, double *__restrict__ partial, const int *stop) {
+    if (stop && *stop) return;
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m; c += int64_t(gridDim.x) * blockDim.x)
+        acc += fabs(b ? a[c] - b[c] : a[c]);
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Sums the partials of k_l1_diff into out[k - 1], k the controller's count of
+// cycles started (the cycle just run), while the controller runs.
+static __global__ __launch_bounds__(kBlock) void k_l1_store(const double *__restrict__ partial, int np,
+                                                          const Ctl *__restrict__ c, double *__restrict__ out) {
+    if (c->stop) return;
+    double a = 0.0;
+    for (int b = threadIdx.x; b < np; b += kBlock) a += partial[b];
+    a = block_sum(a);
+    if (threadIdx.x == 0 && c->k >= 1 && c->k <= 256) out[c->k - 1] = a;
+}
+
+}  // namespace np

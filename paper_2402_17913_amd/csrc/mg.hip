@@ -11,6 +11,7 @@
 #include "mg_fused.h"
 #include "mg_level.h"
 #include "mg_kernels.h"
+#include "ad_kernels.h"
 #include "np_internal.h"
 
 namespace np {
@@ -126,15 +127,19 @@ constexpr int kPartials = 65536;
 constexpr unsigned kNormBlocks = 2048;  // workgroups of a sweep that also reduces the residual norm  // per-workgroup partial sums (fixed order)
 
 struct GraphKey {
-    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles; 5 sawtooth
+    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles; 5 sawtooth;
+               // advection-diffusion: 6 V-cycle, 7 sawtooth
     int zero0, check;
     const void *x, *f;
     double h;
     int nu1, nu2, inner;
     double omega;
+    double ad[5];  // advection-diffusion operator: dt, nu, a[3] (zero otherwise)
+    int ad_scheme, ad_l1;
     bool operator==(const GraphKey &o) const {
         return kind == o.kind && zero0 == o.zero0 && check == o.check && x == o.x && f == o.f && h == o.h &&
-               nu1 == o.nu1 && nu2 == o.nu2 && inner == o.inner && omega == o.omega;
+               nu1 == o.nu1 && nu2 == o.nu2 && inner == o.inner && omega == o.omega &&
+               std::memcmp(ad, o.ad, sizeof ad) == 0 && ad_scheme == o.ad_scheme && ad_l1 == o.ad_l1;
     }
 };
 struct GraphEntry {
@@ -156,6 +161,11 @@ struct Hier {
     double *f64 = nullptr;    // FP64 copy of the rhs (periodic mean removal)
     double *x64 = nullptr;    // second FP64 solution buffer (mixed path)
     double *saw = nullptr;    // level-0 correction and its partner (sawtooth cycle)
+    double *ad_minv = nullptr;  // advection-diffusion: inverse of the coarsest operator
+    double ad_key[6] = {-1.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // ad_minv built for: coarsest spacing, dt, nu, a[3]
+    int ad_key_scheme = -1;
+    double *xold = nullptr;   // advection-diffusion: iterate before the cycle (change gauge)
+    double *ad_l1 = nullptr;  // advection-diffusion: per-cycle L1 change (256 slots)
     Ctl *ctl = nullptr;       // device controller
     Ctl *hctl = nullptr;      // pinned host mirror
     hipStream_t cap = nullptr;  // capture stream
@@ -196,6 +206,9 @@ void free_hier(Hier *H) {
     if (H->f64) (void)hipFree(H->f64);
     if (H->x64) (void)hipFree(H->x64);
     if (H->saw) (void)hipFree(H->saw);
+    if (H->ad_minv) (void)hipFree(H->ad_minv);
+    if (H->xold) (void)hipFree(H->xold);
+    if (H->ad_l1) (void)hipFree(H->ad_l1);
     if (H->ctl) (void)hipFree(H->ctl);
     if (H->hctl) (void)hipHostFree(H->hctl);
     if (H->cap) (void)hipStreamDestroy(H->cap);
@@ -1450,5 +1463,371 @@ extern "C" np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const do
     NP_LAUNCH_CHECK();
     NP_TRY(read_scalars(H, 1, s));
     *out = H->hred[0];
+    return NP_OK;
+}
+
+// ------------------------------------- implicit advection-diffusion multigrid
+// The backward-Euler step of Section 2.2 with constant velocity a and
+// diffusivity nu, A T^{n+1} = T^n, solved as in Section 3.2 by multigrid:
+// V(nu1, nu2) cycles with relaxed Jacobi (dividing by the filter centre),
+// residual restriction by 2^d averaging, linear prolongation and the exact
+// solve on the 4^d grid, or the paper's sawtooth cycle.  Every level uses the
+// operator re-discretised at its own spacing (dt and a fixed).  FP64.
+
+// Weights of the operator at spacing h: identity, nu dt (-Lap_h), and dt a_e
+// times the upwind (scheme 0: backward difference for a_e >= 0, forward for
+// a_e < 0) or central (scheme 1) first difference along each axis.
+static AdW ad_weights(const np_ad_op &op, int d, double h) {
+    AdW W{};
+    const double dif = op.nu * op.dt / (h * h);
+    W.c0 = 1.0 + 2.0 * d * dif;
+    for (int e = 0; e < d; ++e) {
+        const double c = op.a[e] * op.dt / h;
+        W.cm[e] = -dif;
+        W.cp[e] = -dif;
+        if (op.scheme == 0) {
+            if (op.a[e] >= 0.0) {
+                W.c0 += c;
+                W.cm[e] -= c;
+            } else {
+                W.c0 -= c;
+                W.cp[e] += c;
+            }
+        } else {
+            W.cm[e] -= 0.5 * c;
+            W.cp[e] += 0.5 * c;
+        }
+    }
+    return W;
+}
+
+// Inverse of the operator on the 4^d coarsest grid at spacing hc (dense
+// assembly from the stencil and its ghost rule, Gauss-Jordan elimination
+// with partial pivoting: A is not symmetric), cached on the hierarchy.
+static np_status ad_coarse(Hier *H, const np_ad_op &op, double hc, hipStream_t s) {
+    const double key[6] = {hc, op.dt, op.nu, op.a[0], op.a[1], op.a[2]};
+    if (H->ad_minv && std::memcmp(key, H->ad_key, sizeof key) == 0 && H->ad_key_scheme == op.scheme) return NP_OK;
+    const int d = H->d, m = d == 3 ? 64 : 16;
+    const AdW W = ad_weights(op, d, hc);
+    std::vector<double> A(size_t(m) * m, 0.0), I(size_t(m) * m, 0.0);
+    for (int c = 0; c < m; ++c) {
+        const int ix[3] = {c & 3, (c >> 2) & 3, c >> 4};
+        A[size_t(c) * m + c] += W.c0;
+        for (int e = 0; e < d; ++e)
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double w = sgn < 0 ? W.cm[e] : W.cp[e];
+                int nb[3] = {ix[0], ix[1], ix[2]};
+                nb[e] += sgn;
+                if (nb[e] < 0 || nb[e] > 3) {
+                    if (H->bc == NP_BC_DIRICHLET0) {  // ghost = -(own value)
+                        A[size_t(c) * m + c] -= w;
+                        continue;
+                    }
+                    nb[e] &= 3;
+                }
+                A[size_t(c) * m + (nb[0] | nb[1] << 2 | nb[2] << 4)] += w;
+            }
+        I[size_t(c) * m + c] = 1.0;
+    }
+    for (int p = 0; p < m; ++p) {
+        int piv = p;
+        for (int r = p + 1; r < m; ++r)
+            if (std::fabs(A[size_t(r) * m + p]) > std::fabs(A[size_t(piv) * m + p])) piv = r;
+        if (!(std::fabs(A[size_t(piv) * m + p]) > 0.0)) {
+            set_error("singular coarsest advection-diffusion operator");
+            return NP_EINVAL;
+        }
+        if (piv != p)
+            for (int q = 0; q < m; ++q) {
+                std::swap(A[size_t(p) * m + q], A[size_t(piv) * m + q]);
+                std::swap(I[size_t(p) * m + q], I[size_t(piv) * m + q]);
+            }
+        const double inv = 1.0 / A[size_t(p) * m + p];
+        for (int q = 0; q < m; ++q) {
+            A[size_t(p) * m + q] *= inv;
+            I[size_t(p) * m + q] *= inv;
+        }
+        for (int r = 0; r < m; ++r) {
+            if (r == p) continue;
+            const double l = A[size_t(r) * m + p];
+            if (l == 0.0) continue;
+            for (int q = 0; q < m; ++q) {
+                A[size_t(r) * m + q] -= l * A[size_t(p) * m + q];
+                I[size_t(r) * m + q] -= l * I[size_t(p) * m + q];
+            }
+        }
+    }
+    if (!H->ad_minv) NP_TRY(dmalloc((void **)&H->ad_minv, sizeof(double) * 64 * 64));
+    NP_HIP_TRY(hipMemcpyAsync(H->ad_minv, I.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(H->ad_key, key, sizeof key);
+    H->ad_key_scheme = op.scheme;
+    return NP_OK;
+}
+
+// Partials of ||x - xold||_1 (or ||x||_1 without xold) and their sum into the
+// per-cycle gauge, both gated by the controller.
+template <int D>
+static np_status ad_l1_gauge(Hier *H, const double *x, const double *xold, hipStream_t s) {
+    const int64_t m0 = cells(D, H->lg);
+    const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m0));
+    hipLaunchKernelGGL(k_l1_diff, dim3(nb), dim3(kBlock), 0, s, x, xold, m0, H->red, &H->ctl->stop);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_l1_store, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl, H->ad_l1);
+    NP_LAUNCH_CHECK();
+    return NP_OK;
+}
+
+// One V(nu1, nu2) cycle of the operator on x (level 0 uses x, f and t[0]),
+// opened by the convergence check of the input iterate; every launch is
+// gated by the controller.  l1: record the change of x over the cycle.
+template <int D>
+static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double *x, double h, const CycleOpts &co,
+                           bool l1, hipStream_t s) {
+    const int L = H->L, bc = H->bc, lg0 = H->lg;
+    const int *stop = &H->ctl->stop;
+    const int64_t m0 = cells(D, lg0);
+    if (l1) {
+        hipLaunchKernelGGL((k_copy<double>), dim3(blocks_for(m0)), dim3(kBlock), 0, s, x, H->xold, m0, stop);
+        NP_LAUNCH_CHECK();
+    }
+    std::vector<double *> cur(L + 1), oth(L + 1);
+    std::vector<const double *> F(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        cur[l] = l == 0 ? x : (double *)H->x[l];
+        oth[l] = (double *)H->t[l];
+        F[l] = l == 0 ? f : (const double *)H->f[l];
+    }
+    double hl = h;
+    for (int l = 0; l <= L; ++l, hl *= 2.0) {
+        const int lg = lg0 - l;
+        const int64_t m = cells(D, lg);
+        const AdW W = ad_weights(op, D, hl);
+        const double wd = co.omega / W.c0;
+        const bool zero = l > 0;
+        if (l == 0 && (co.nu1 == 0 || L == 0)) {  // the check on its own: no sweep opens this level
+            const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m));
+            hipLaunchKernelGGL((k_ad_resid<D>), dim3(nb), dim3(kBlock), 0, s, F[0], cur[0], nullptr, H->red, lg, bc,
+                               W, stop);
+            NP_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl);
+            NP_LAUNCH_CHECK();
+        }
+        if (l == L) {  // exact solve on the coarsest grid
+            hipLaunchKernelGGL((k_ad_coarse<D>), dim3(1), dim3(64), 0, s, F[L], cur[L], H->ad_minv, bc, W,
+                               zero ? 1 : 0, stop);
+            NP_LAUNCH_CHECK();
+            break;
+        }
+        if (zero && co.nu1 == 0) {
+            hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, cur[l], m, stop);
+            NP_LAUNCH_CHECK();
+        }
+        for (int it = 0; it < co.nu1; ++it) {
+            if (zero && it == 0) {
+                hipLaunchKernelGGL((k_ad_sweep<D, true, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l],
+                                   nullptr, oth[l], nullptr, lg, bc, W, wd, stop);
+            } else if (l == 0 && it == 0) {  // residual norm of the input iterate, then the stop rule
+                const unsigned nb = std::min<unsigned>(kNormBlocks, blocks_for(m));
+                hipLaunchKernelGGL((k_ad_sweep<D, false, true>), dim3(nb), dim3(kBlock), 0, s, F[l], cur[l], oth[l],
+                                   H->red, lg, bc, W, wd, stop);
+                NP_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl);
+            } else {
+                hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l],
+                                   cur[l], oth[l], nullptr, lg, bc, W, wd, stop);
+            }
+            NP_LAUNCH_CHECK();
+            std::swap(cur[l], oth[l]);
+        }
+        hipLaunchKernelGGL((k_ad_resid_restrict<D>), dim3(blocks_for(cells(D, lg - 1))), dim3(kBlock), 0, s, F[l],
+                           cur[l], (double *)H->f[l + 1], lg, bc, W, stop);
+        NP_LAUNCH_CHECK();
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const int lg = lg0 - l;
+        const int64_t m = cells(D, lg);
+        const double hh = h * double(int64_t(1) << l);
+        const AdW W = ad_weights(op, D, hh);
+        const double wd = co.omega / W.c0;
+        hipLaunchKernelGGL((k_prolong_add<D, double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, cur[l + 1], cur[l],
+                           lg - 1, bc, stop);
+        NP_LAUNCH_CHECK();
+        for (int it = 0; it < co.nu2; ++it) {
+            hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l], cur[l],
+                               oth[l], nullptr, lg, bc, W, wd, stop);
+            NP_LAUNCH_CHECK();
+            std::swap(cur[l], oth[l]);
+        }
+    }
+    if (cur[0] != x) {
+        hipLaunchKernelGGL((k_copy<double>), dim3(blocks_for(m0)), dim3(kBlock), 0, s, cur[0], x, m0, stop);
+        NP_LAUNCH_CHECK();
+    }
+    if (l1) NP_TRY(ad_l1_gauge<D>(H, x, H->xold, s));
+    return NP_OK;
+}
+
+// One sawtooth cycle of the operator (Section 2.2; Appendix B): the finest
+// residual (its norm is the convergence check), restricted level by level to
+// the coarsest grid; then from the coarsest up e = r / A_00 + P e_coarse
+// (copy or linear prolongation) and nu2 relaxed-Jacobi steps (alpha = omega)
+// on the level's residual equation; x += e_0.  Buffers as saw_cycle.
+template <int D>
+static np_status ad_saw_cycle(Hier *H, const np_ad_op &op, const double *f, double *x, double h,
+                              const np_mg_opts &o, bool l1, hipStream_t s) {
+    const int L = H->L, bc = H->bc, lg0 = H->lg;
+    const int *stop = &H->ctl->stop;
+    const int64_t m0 = cells(D, lg0);
+    std::vector<double *> r(L + 1), e(L + 1), t(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        r[l] = l == 0 ? (double *)H->t[0] : (double *)H->f[l];
+        e[l] = l == 0 ? H->saw : (double *)H->x[l];
+        t[l] = l == 0 ? H->saw + m0 : (double *)H->t[l];
+    }
+    const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m0));
+    hipLaunchKernelGGL((k_ad_resid<D>), dim3(nb), dim3(kBlock), 0, s, f, x, r[0], H->red, lg0, bc,
+                       ad_weights(op, D, h), stop);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl);
+    NP_LAUNCH_CHECK();
+    for (int l = 0; l < L; ++l) {
+        const int lgc = lg0 - l - 1;
+        hipLaunchKernelGGL((k_restrict_field<D>), dim3(blocks_for(cells(D, lgc))), dim3(kBlock), 0, s, r[l],
+                           r[l + 1], lgc, stop);
+        NP_LAUNCH_CHECK();
+    }
+    std::vector<double *> done(L + 2, nullptr);
+    for (int l = L; l >= 0; --l) {
+        const int lg = lg0 - l;
+        const int64_t ml = cells(D, lg);
+        const AdW W = ad_weights(op, D, h * double(int64_t(1) << l));
+        hipLaunchKernelGGL((k_saw_up<D>), dim3(blocks_for(ml)), dim3(kBlock), 0, s, r[l], done[l + 1], e[l], lg, bc,
+                           1.0 / W.c0, o.prolong, stop);
+        NP_LAUNCH_CHECK();
+        double *cur = e[l], *oth = t[l];
+        for (int it = 0; it < o.nu2; ++it) {
+            hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(ml)), dim3(kBlock), 0, s, r[l], cur,
+                               oth, nullptr, lg, bc, W, o.omega / W.c0, stop);
+            NP_LAUNCH_CHECK();
+            std::swap(cur, oth);
+        }
+        done[l] = cur;
+    }
+    hipLaunchKernelGGL(k_add_to, dim3(blocks_for(m0)), dim3(kBlock), 0, s, x, done[0], m0, stop);
+    NP_LAUNCH_CHECK();
+    if (l1) NP_TRY(ad_l1_gauge<D>(H, done[0], nullptr, s));
+    return NP_OK;
+}
+
+template <int D>
+static np_status solve_ad(Hier *H, const np_ad_op &op, const double *f, double *x, double h, double tol,
+                          const np_mg_opts &o, const CycleOpts &co, hipStream_t s, double nf, double *l1_out,
+                          np_mg_stats *stats) {
+    NP_TRY(ensure_levels(H));
+    const int64_t m0 = cells(D, H->lg);
+    const bool l1 = l1_out != nullptr;
+    if (o.cycle == 1 && !H->saw) NP_TRY(dmalloc((void **)&H->saw, sizeof(double) * 2 * m0));
+    if (l1 && o.cycle == 0 && !H->xold) NP_TRY(dmalloc((void **)&H->xold, sizeof(double) * m0));
+    if (l1 && !H->ad_l1) NP_TRY(dmalloc((void **)&H->ad_l1, sizeof(double) * 256));
+    if (o.cycle == 0) NP_TRY(ad_coarse(H, op, h * double(int64_t(1) << H->L), s));
+    NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
+    GraphKey key{o.cycle == 1 ? 7 : 6, o.prolong, 1, x, f, h, co.nu1, co.nu2, 0, co.omega,
+                 {op.dt, op.nu, op.a[0], op.a[1], op.a[2]}, op.scheme, l1 ? 1 : 0};
+    int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
+    for (;;) {
+        for (int b = 0; b < batch; ++b)
+            NP_TRY(run_graph(H, key, s, [&](hipStream_t q) {
+                return o.cycle == 1 ? ad_saw_cycle<D>(H, op, f, x, h, o, l1, q)
+                                    : ad_vcycle<D>(H, op, f, x, h, co, l1, q);
+            }));
+        NP_TRY(read_ctl(H, s));
+        if (H->hctl->stop) break;
+        batch = next_batch(*H->hctl, o, false);
+    }
+    const Ctl c = *H->hctl;
+    fill_stats(stats, c, c.k, c.k);
+    if (l1) {
+        const int n = std::min(c.k, 256);
+        for (int i = n; i < 256; ++i) l1_out[i] = 0.0;
+        if (n > 0) {
+            NP_HIP_TRY(hipMemcpyAsync(l1_out, H->ad_l1, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+            NP_HIP_TRY(hipStreamSynchronize(s));
+        }
+    }
+    return status_of(c, tol);
+}
+
+static np_status check_ad_op(const np_ad_op *op, int d) {
+    if (!op) { set_error("null operator"); return NP_EINVAL; }
+    if (!(op->dt > 0.0) || !std::isfinite(op->dt)) { set_error("dt must be positive"); return NP_EINVAL; }
+    if (!(op->nu >= 0.0) || !std::isfinite(op->nu)) { set_error("nu must be non-negative"); return NP_EINVAL; }
+    for (int e = 0; e < d; ++e)
+        if (!std::isfinite(op->a[e])) { set_error("non-finite velocity"); return NP_EINVAL; }
+    if (op->scheme != 0 && op->scheme != 1) { set_error("scheme must be 0 (upwind) or 1 (central)"); return NP_EINVAL; }
+    return NP_OK;
+}
+
+extern "C" np_status np_ad_implicit_solve(np_dims dims, double h, np_bc bc, const np_ad_op *op, const double *rhs,
+                                          double *x, double tol, const np_mg_opts *opts, np_mg_stats *stats,
+                                          double *l1_change) {
+    clear_error();
+    np_mg_opts o;
+    CycleOpts co;
+    fill_opts(opts, co, o);
+    int lg = -1;
+    NP_TRY(check_solve_args(dims, h, bc, rhs, x, tol, o, &lg));
+    NP_TRY(check_ad_op(op, dims.ndim));
+    if (o.smooth_prec != NP_FP64 || o.warm_start == 1) {
+        set_error("the advection-diffusion solve runs in FP64 from a zero or caller guess");
+        return NP_EINVAL;
+    }
+    np_ad_op op2 = *op;
+    for (int e = dims.ndim; e < 3; ++e) op2.a[e] = 0.0;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    if (l1_change) std::memset(l1_change, 0, sizeof(double) * 256);
+    const int d = dims.ndim;
+    hipStream_t s = (hipStream_t)o.stream;
+    Hier *H = nullptr;
+    NP_TRY(get_hier(d, lg, bc, NP_FP64, &H));
+    std::lock_guard<std::mutex> lk(H->mu);
+    const int64_t m = cells(d, lg);
+    NP_TRY(dsum(H, rhs, m, 1, 0, s));
+    NP_TRY(read_scalars(H, 1, s));
+    const double nf = H->hred[0];
+    if (!std::isfinite(nf)) {
+        set_error("non-finite right-hand side");
+        return NP_ENAN;
+    }
+    if (nf == 0.0 || o.warm_start == 0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
+        NP_LAUNCH_CHECK();
+    }
+    if (nf == 0.0) {
+        NP_HIP_TRY(hipStreamSynchronize(s));
+        return NP_OK;
+    }
+    np_status st = d == 2 ? solve_ad<2>(H, op2, rhs, x, h, tol, o, co, s, nf, l1_change, stats)
+                          : solve_ad<3>(H, op2, rhs, x, h, tol, o, co, s, nf, l1_change, stats);
+    if (st == NP_EHIP || st == NP_ENOMEM || st == NP_EINVAL) return st;
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return st;
+}
+
+extern "C" np_status np_ad_apply(np_dims dims, double h, np_bc bc, const np_ad_op *op, const double *x, double *y,
+                                 void *stream) {
+    int lg;
+    NP_TRY(op_prelude(dims, h, bc, &lg));
+    NP_TRY(check_ad_op(op, dims.ndim));
+    if (!x || !y) { set_error("null array"); return NP_EINVAL; }
+    np_ad_op op2 = *op;
+    for (int e = dims.ndim; e < 3; ++e) op2.a[e] = 0.0;
+    const int64_t m = cells(dims.ndim, lg);
+    hipStream_t s = (hipStream_t)stream;
+    const AdW W = ad_weights(op2, dims.ndim, h);
+    if (dims.ndim == 2) hipLaunchKernelGGL((k_ad_apply<2>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, y, lg, bc, W);
+    else hipLaunchKernelGGL((k_ad_apply<3>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, y, lg, bc, W);
+    NP_LAUNCH_CHECK();
+    NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }

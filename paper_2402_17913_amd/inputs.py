@@ -162,6 +162,14 @@ def gaussian_2d(n=301, gamma=40.0, spacing=1.0):
     return np.exp(-(X ** 2 + Y ** 2) / (2 * gamma ** 2))
 
 
+def gaussian_3d(n=64, gamma=10.0, spacing=1.0):
+    """Gaussian exp(-(x^2 + y^2 + z^2)/(2 gamma^2)) on n^3 cells of width `spacing`,
+    centres as gaussian_2d; array axes (z, y, x)."""
+    x = (np.arange(n) - (n - 1) / 2.0) * spacing
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / (2 * gamma ** 2))
+
+
 def batched_sizes(count=512, seed=0, choices=(64, 128, 256, 512, 1024)):
     """Sizes of the batched workload: `count` draws, uniform over `choices`."""
     rng = np.random.default_rng(seed)
