@@ -303,13 +303,83 @@ def leg_sawtooth(B, inputs, steps, warmup):
     return dict(workload="sawtooth_vs_v22_dirichlet_fp64_tol1e-10", **out)
 
 
+def ad_kernel_times(B, solve, steps):
+    """Per-kind duration of the finest-level kernels of the advection-diffusion
+    V-cycle, each launch bracketed by HIP events on its stream."""
+    import torch
+    out = {}
+    for name, mask in (("sweep", B.PROF_JACOBI), ("restrict", B.PROF_RESTRICT), ("prolong", B.PROF_PROLONG)):
+        B.np_prof_enable(mask)
+        for _ in range(steps):
+            solve()
+        torch.cuda.synchronize()
+        n, ms, by = B.np_prof_read()
+        B.np_prof_enable(0)
+        if n:
+            gbs = (by / n) / (ms / n * 1e-3) / 1e9
+            out[name] = dict(launches=n, avg_us=1e3 * ms / n, bytes_per_launch=by / n, gbs=gbs,
+                             frac=gbs / HBM_PEAK_GBS)
+    return out
+
+
+def leg_ad(B, inputs, steps, warmup):
+    """Implicit advection-diffusion multigrid (Section 2.2 backward Euler, Section 3.2
+    experiment): the paper's case (128^2, Dirichlet, u = v = 1, nu = 2, dt = 50, dx = 1,
+    Gaussian gamma = 10 at the centre, upwind, zero first estimate) with the paper's
+    L1 change gauge for V(2,2) and the sawtooth variants, then the same per-cell
+    coefficients at 4096^2 (gamma 320) and 256^3 (gamma 20): time to 1e-10 and the
+    finest-level kernels against HBM."""
+    import torch
+    out = {}
+    T0 = torch.from_numpy(inputs.gaussian_2d(128, gamma=10.0)).cuda()
+    x = torch.zeros_like(T0)
+    op = B.ad_op(50.0, 2.0, [1.0, 1.0], 0)
+    paper = {}
+    variants = (("v22", dict()),
+                ("sawtooth_printed", dict(cycle=B.CYCLE_SAWTOOTH, prolong=B.PROLONG_COPY, nu1=0, nu2=1, omega=1.0)),
+                ("sawtooth_linear", dict(cycle=B.CYCLE_SAWTOOTH, nu1=0, nu2=1, omega=1.0)),
+                ("sawtooth_damped_linear", dict(cycle=B.CYCLE_SAWTOOTH, nu1=0, nu2=2, omega=2.0 / 3.0)))
+    for vn, kw in variants:
+        st, s50 = B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, op, check=False, l1=True, fixed_cycles=50,
+                                         **kw)
+        l1 = s50["l1_change"]
+        below = [k + 1 for k, v in enumerate(l1) if v < 1e-5]
+        dt, (st, stats) = timed(lambda: B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, op, tol=TOL, check=False,
+                                                               max_cycles=100, **kw), max(1, steps // 2), 1)
+        paper[vn] = dict(l1_change_first=l1[0], l1_change_50=l1[-1], l1_reduction_50=l1[-1] / l1[0],
+                         first_cycle_l1_below_1e5=below[0] if below else None,
+                         status="converged" if st == 0 else "not converged (status %d)" % st,
+                         cycles_to_tol=stats["cycles"], rel_res=stats["rel_res"],
+                         ms_per_solve=1e3 * dt / max(1, steps // 2))
+        log("  ad paper %s: L1 change %.3g -> %.3g in 50 cycles; tol 1e-10: %s, %d cycles, %.2f ms" % (
+            vn, l1[0], l1[-1], paper[vn]["status"], stats["cycles"], paper[vn]["ms_per_solve"]))
+    out["paper_2d_128"] = paper
+    del T0, x
+    for name, d, n, gamma in (("2d_4096", 2, 4096, 320.0), ("3d_256", 3, 256, 20.0)):
+        T0 = torch.from_numpy(inputs.gaussian_2d(n, gamma=gamma) if d == 2 else
+                              inputs.gaussian_3d(n, gamma=gamma)).cuda()
+        x = torch.zeros_like(T0)
+        opd = B.ad_op(50.0, 2.0, [1.0] * d, 0)
+        solve = lambda: B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, opd, tol=TOL)
+        dt, (st, stats) = timed(solve, steps, warmup)
+        ker = ad_kernel_times(B, solve, 2)
+        out[name] = dict(dofs=T0.numel(), dofs_per_s=T0.numel() * steps / dt, ms_per_solve=1e3 * dt / steps,
+                         cycles=stats["cycles"], rel_res=stats["rel_res"], rho=stats["rho_est"],
+                         finest_level_kernels=ker)
+        log("  ad %s: %.2f ms, %d cycles, %.3g DOF/s; sweep %.1f us (%.2f of HBM peak)" % (
+            name, out[name]["ms_per_solve"], stats["cycles"], out[name]["dofs_per_s"],
+            ker.get("sweep", {}).get("avg_us", -1), ker.get("sweep", {}).get("frac", -1)))
+        del T0, x
+    return dict(workload="ad_implicit_dirichlet_upwind_C50_nu_dt100_gaussian_tol1e-10_fp64", **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth",
+    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth,ad",
                     help="other workloads to run after the headline (comma list, '' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -453,6 +523,8 @@ def main():
             others["c5"] = leg_c5(B, inputs)
         elif leg == "sawtooth":
             others["sawtooth"] = leg_sawtooth(B, inputs, args.steps, args.warmup)
+        elif leg == "ad":
+            others["ad"] = leg_ad(B, inputs, args.steps, args.warmup)
         else:
             sys.exit("unknown leg %s" % leg)
         B.np_release_all()

@@ -10,6 +10,7 @@
 #pragma once
 
 #include "mg_kernels.h"
+#include "mg_level.h"
 
 namespace np {
 
@@ -152,6 +153,92 @@ __global__ __launch_bounds__(64) void k_ad_coarse(const double *__restrict__ f, 
         double s = 0.0;
         for (int q = 0; q < m; ++q) s += Minv[t * m + q] * rs[q];
         x[t] = xs[t] + s;
+    }
+}
+
+// ------------------------------------------ 3D levels on z-marching tiles
+// The tiles of ZMarch (one FP64 cell per thread): planes k - 1, k, k + 1 of the
+// own column in registers, plane k with its halo in LDS, plane k + 1 loaded
+// while plane k is computed.  Requires n >= 128.
+
+// Publishes plane k of the tile to buffer b and returns (A x) at the thread's
+// cell (one barrier per plane; the buffer is written again two planes later).
+template <class Z>
+__device__ __forceinline__ double ad_zm_ax(const Z &z, typename Z::Plane &b, const AdW &W) {
+    b[z.ty + 1][z.tp + 1] = z.xc[0];
+    if (z.hw) b[z.hy][z.hx] = z.hv[0];
+    __syncthreads();
+    const int lc = z.tp + 1;
+    return W.c0 * z.xc[0] + (W.cm[0] * b[z.ty + 1][lc - 1] + W.cp[0] * b[z.ty + 1][lc + 1]) +
+           (W.cm[1] * b[z.ty][lc] + W.cp[1] * b[z.ty + 2][lc]) + (W.cm[2] * z.xm[0] + W.cp[2] * z.xp[0]);
+}
+
+typedef ZMarch<double, ZCfg<double>::TX, 1> AdZ;
+
+// Relaxed-Jacobi sweep (as k_ad_sweep) over zc planes per workgroup.  NORM:
+// per-workgroup partial of ||f - A x_in||^2.
+template <bool NORM>
+__global__ __launch_bounds__(kS3Threads) void k_ad_sweep3(const double *__restrict__ f, const double *__restrict__ xin,
+                                                          double *__restrict__ xout, double *__restrict__ partial,
+                                                          int lg, int bc, int zc, AdW W, double wdiag,
+                                                          const int *stop) {
+    __shared__ AdZ::Plane pl[2];
+    if (stop && *stop) return;
+    AdZ z(lg, bc, zc);
+    const LdC<double> v{xin};
+    z.start(v);
+    double fc = f[z.k0 * z.P + z.col];
+    double acc = 0.0;
+    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
+        z.prefetch(v, k);
+        const double fn = f[z.next(k) * z.P + z.col];
+        const double r = fc - ad_zm_ax(z, pl[q], W);
+        if (NORM) acc += r * r;
+        xout[k * z.P + z.col] = z.xc[0] + wdiag * r;
+        fc = fn;
+        z.advance();
+    }
+    if (NORM) {
+        acc = block_sum_n<kS3Threads>(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
+// Residual + restriction (as k_ad_resid_restrict): each thread sums its
+// residuals over a pair of planes, then one thread per coarse cell adds the
+// pair sums of its 2 x 2 row neighbours through LDS.  zc even.
+__global__ __launch_bounds__(kS3Threads) void k_ad_restrict3(const double *__restrict__ f,
+                                                             const double *__restrict__ x, double *__restrict__ fc,
+                                                             int lg, int bc, int zc, AdW W, const int *stop) {
+    __shared__ AdZ::Plane pl[2];
+    __shared__ double rs[AdZ::TY][AdZ::TP];
+    if (stop && *stop) return;
+    AdZ z(lg, bc, zc);
+    const LdC<double> v{x};
+    z.start(v);
+    const int lgc = lg - 1;
+    double f0 = f[z.k0 * z.P + z.col];
+    double pair = 0.0;
+    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
+        z.prefetch(v, k);
+        const double fn = f[z.next(k) * z.P + z.col];
+        const double r = f0 - ad_zm_ax(z, pl[q], W);
+        if (((k - z.k0) & 1) == 0) {
+            pair = r;
+        } else {
+            pair += r;
+            rs[z.ty][z.tp] = pair;
+            __syncthreads();
+            if (((z.tp | z.ty) & 1) == 0) {
+                const double t =
+                    ((rs[z.ty][z.tp] + rs[z.ty][z.tp + 1]) + rs[z.ty + 1][z.tp]) + rs[z.ty + 1][z.tp + 1];
+                const int64_t cc = ((int64_t(k >> 1) << (2 * lgc)) | (int64_t(z.j >> 1) << lgc)) + (z.i >> 1);
+                fc[cc] = t * 0.125;
+            }
+            // rs is written again two planes later, after plane k + 1's barrier
+        }
+        z.advance();
+        f0 = fn;
     }
 }
 

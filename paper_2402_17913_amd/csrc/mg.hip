@@ -1587,6 +1587,21 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
     const int L = H->L, bc = H->bc, lg0 = H->lg;
     const int *stop = &H->ctl->stop;
     const int64_t m0 = cells(D, lg0);
+    // 3D levels of at least 128^3 run on the z-marching tiles
+    auto zm3 = [](int lg) { return D == 3 && lg >= 7 && g_tune.sweep3; };
+    // one sweep of a level (not from zero, no norm)
+    auto ad_sweep = [&](const double *fl, const double *xi, double *xo, int lg, const AdW &W, double wd) {
+        if (zm3(lg)) {
+            const int zc = sweep3_planes(lg, 1, kPartials);
+            hipLaunchKernelGGL((k_ad_sweep3<false>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, fl, xi, xo,
+                               nullptr, lg, bc, zc, W, wd, stop);
+        } else {
+            hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, fl,
+                               xi, xo, nullptr, lg, bc, W, wd, stop);
+        }
+        NP_LAUNCH_CHECK();
+        return NP_OK;
+    };
     if (l1) {
         hipLaunchKernelGGL((k_copy<double>), dim3(blocks_for(m0)), dim3(kBlock), 0, s, x, H->xold, m0, stop);
         NP_LAUNCH_CHECK();
@@ -1624,25 +1639,46 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
             NP_LAUNCH_CHECK();
         }
         for (int it = 0; it < co.nu1; ++it) {
+            void *tok = nullptr;
+            const bool prof = l == 0 && it > 0 && (prof_on() & kProfJacobi);
+            if (prof) NP_TRY(prof_begin(s, &tok));
             if (zero && it == 0) {
                 hipLaunchKernelGGL((k_ad_sweep<D, true, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l],
                                    nullptr, oth[l], nullptr, lg, bc, W, wd, stop);
             } else if (l == 0 && it == 0) {  // residual norm of the input iterate, then the stop rule
-                const unsigned nb = std::min<unsigned>(kNormBlocks, blocks_for(m));
-                hipLaunchKernelGGL((k_ad_sweep<D, false, true>), dim3(nb), dim3(kBlock), 0, s, F[l], cur[l], oth[l],
-                                   H->red, lg, bc, W, wd, stop);
+                unsigned nb;
+                if (zm3(lg)) {
+                    const int zc = sweep3_planes(lg, 1, kPartials);
+                    nb = zblocks(lg, 1, zc);
+                    hipLaunchKernelGGL((k_ad_sweep3<true>), dim3(nb), dim3(kS3Threads), 0, s, F[l], cur[l], oth[l],
+                                       H->red, lg, bc, zc, W, wd, stop);
+                } else {
+                    nb = std::min<unsigned>(kNormBlocks, blocks_for(m));
+                    hipLaunchKernelGGL((k_ad_sweep<D, false, true>), dim3(nb), dim3(kBlock), 0, s, F[l], cur[l],
+                                       oth[l], H->red, lg, bc, W, wd, stop);
+                }
                 NP_LAUNCH_CHECK();
                 hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl);
             } else {
-                hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l],
-                                   cur[l], oth[l], nullptr, lg, bc, W, wd, stop);
+                NP_TRY(ad_sweep(F[l], cur[l], oth[l], lg, W, wd));
             }
             NP_LAUNCH_CHECK();
+            if (prof) NP_TRY(prof_end(s, tok, double(m) * 3 * sizeof(double)));
             std::swap(cur[l], oth[l]);
         }
-        hipLaunchKernelGGL((k_ad_resid_restrict<D>), dim3(blocks_for(cells(D, lg - 1))), dim3(kBlock), 0, s, F[l],
-                           cur[l], (double *)H->f[l + 1], lg, bc, W, stop);
+        void *tok = nullptr;
+        const bool prof = l == 0 && (prof_on() & kProfRestrict);
+        if (prof) NP_TRY(prof_begin(s, &tok));
+        if (zm3(lg)) {
+            const int zc = sweep3_planes(lg, 1, kPartials);
+            hipLaunchKernelGGL(k_ad_restrict3, dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, F[l], cur[l],
+                               (double *)H->f[l + 1], lg, bc, zc, W, stop);
+        } else {
+            hipLaunchKernelGGL((k_ad_resid_restrict<D>), dim3(blocks_for(cells(D, lg - 1))), dim3(kBlock), 0, s,
+                               F[l], cur[l], (double *)H->f[l + 1], lg, bc, W, stop);
+        }
         NP_LAUNCH_CHECK();
+        if (prof) NP_TRY(prof_end(s, tok, double(m) * (2 + 1.0 / (1 << D)) * sizeof(double)));
     }
     for (int l = L - 1; l >= 0; --l) {
         const int lg = lg0 - l;
@@ -1650,13 +1686,25 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
         const double hh = h * double(int64_t(1) << l);
         const AdW W = ad_weights(op, D, hh);
         const double wd = co.omega / W.c0;
-        hipLaunchKernelGGL((k_prolong_add<D, double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, cur[l + 1], cur[l],
-                           lg - 1, bc, stop);
+        void *tok = nullptr;
+        const bool prof = l == 0 && (prof_on() & kProfProlong);
+        if (prof) NP_TRY(prof_begin(s, &tok));
+        if (zm3(lg)) {
+            const int zc = sweep3_planes(lg, 1, kPartials);
+            hipLaunchKernelGGL((k_prolong3<double>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, cur[l + 1],
+                               cur[l], lg, bc, zc, stop);
+        } else {
+            hipLaunchKernelGGL((k_prolong_add<D, double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, cur[l + 1],
+                               cur[l], lg - 1, bc, stop);
+        }
         NP_LAUNCH_CHECK();
+        if (prof) NP_TRY(prof_end(s, tok, double(m) * (2 + 1.0 / (1 << D)) * sizeof(double)));
         for (int it = 0; it < co.nu2; ++it) {
-            hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l], cur[l],
-                               oth[l], nullptr, lg, bc, W, wd, stop);
-            NP_LAUNCH_CHECK();
+            void *tk = nullptr;
+            const bool pj = l == 0 && (prof_on() & kProfJacobi);
+            if (pj) NP_TRY(prof_begin(s, &tk));
+            NP_TRY(ad_sweep(F[l], cur[l], oth[l], lg, ad_weights(op, D, hh), wd));
+            if (pj) NP_TRY(prof_end(s, tk, double(m) * 3 * sizeof(double)));
             std::swap(cur[l], oth[l]);
         }
     }
