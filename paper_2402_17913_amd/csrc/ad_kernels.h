@@ -242,6 +242,120 @@ __global__ __launch_bounds__(kS3Threads) void k_ad_restrict3(const double *__res
     }
 }
 
+// ------------------------------------- small levels in one workgroup (LDS)
+// Weights of the levels handled by k_ad_tail, finest first.
+struct AdLevels {
+    AdW w[12];
+};
+
+// V(nu1, nu2) cycle on levels lg_t .. 2 (coarsest 4^d) in one workgroup,
+// every level in LDS, from a zero iterate on every level (the levels below
+// the finest ones of a cycle): first sweep x = wdiag f, nu1 - 1 further
+// sweeps, residual restriction, the exact solve Minv f on 4^d, then per
+// level up prolongation + nu2 sweeps.  f_t: right-hand side of level lg_t
+// (global); x_t: its correction (global).  nu1 >= 1; lg_t <= Tail<D>::LG.
+template <int D>
+__global__ __launch_bounds__(Tail<D>::NT) void k_ad_tail(const double *__restrict__ f_t, double *__restrict__ x_t,
+                                                         const double *__restrict__ Minv, int lg_t, int bc,
+                                                         AdLevels Wl, double omega, int nu1, int nu2,
+                                                         const int *stop) {
+    constexpr int NT = Tail<D>::NT;
+    __shared__ double xs[Tail<D>::levels_sum()];
+    __shared__ double fs[Tail<D>::levels_sum()];
+    __shared__ double ts[Tail<D>::cells(Tail<D>::LG)];
+    if (stop && *stop) return;
+    const int tid = threadIdx.x;
+    auto off = [&](int l) -> int64_t {  // level l follows the finer levels lg_t .. l + 1
+        return ((int64_t(1) << (D * (lg_t + 1))) - (int64_t(1) << (D * (l + 1)))) / ((int64_t(1) << D) - 1);
+    };
+    const int64_t mt = int64_t(1) << (D * lg_t);
+    for (int64_t c = tid; c < mt; c += NT) fs[c] = f_t[c];
+    __syncthreads();
+    for (int lg = lg_t; lg > 2; --lg) {
+        const int64_t m = int64_t(1) << (D * lg);
+        double *X = xs + off(lg), *F = fs + off(lg);
+        const AdW W = Wl.w[lg_t - lg];
+        const double wd = omega / W.c0;
+        for (int64_t c = tid; c < m; c += NT) X[c] = wd * F[c];
+        __syncthreads();
+        for (int it = 1; it < nu1; ++it) {
+            for (int64_t c = tid; c < m; c += NT) {
+                int i, j, k;
+                decode<D>(c, lg, i, j, k);
+                ts[c] = X[c] + wd * (F[c] - ad_ax<D>(X, c, i, j, k, lg, bc, W));
+            }
+            __syncthreads();
+            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
+            __syncthreads();
+        }
+        const int lgc = lg - 1;
+        const int64_t mc = int64_t(1) << (D * lgc);
+        double *Fc = fs + off(lgc);
+        for (int64_t cc = tid; cc < mc; cc += NT) {
+            int I, J, K;
+            decode<D>(cc, lgc, I, J, K);
+            double acc = 0.0;
+            for (int kk = 0; kk < (D == 3 ? 2 : 1); ++kk)
+                for (int jj = 0; jj < 2; ++jj)
+                    for (int ii = 0; ii < 2; ++ii) {
+                        const int i = 2 * I + ii, j = 2 * J + jj, k = D == 3 ? 2 * K + kk : 0;
+                        const int64_t cf = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
+                        acc += F[cf] - ad_ax<D>(X, cf, i, j, k, lg, bc, W);
+                    }
+            Fc[cc] = acc * (D == 3 ? 0.125 : 0.25);
+        }
+        __syncthreads();
+    }
+    {
+        constexpr int m = D == 3 ? 64 : 16;
+        double *X = xs + off(2), *F = fs + off(2);
+        if (tid < m) {
+            double acc = 0.0;
+            for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * F[q];
+            X[tid] = acc;
+        }
+        __syncthreads();
+    }
+    for (int lg = 3; lg <= lg_t; ++lg) {
+        const int64_t m = int64_t(1) << (D * lg);
+        const int lgc = lg - 1, nc = 1 << lgc;
+        double *X = xs + off(lg), *F = fs + off(lg), *E = xs + off(lgc);
+        const AdW W = Wl.w[lg_t - lg];
+        const double wd = omega / W.c0;
+        for (int64_t c = tid; c < m; c += NT) {
+            int i, j, k;
+            decode<D>(c, lg, i, j, k);
+            int oi, ni, oj, nj, ok = 0, nk = 0;
+            float si, sj, sk = 1.0f;
+            pro_axis(i, nc, bc, oi, ni, si);
+            pro_axis(j, nc, bc, oj, nj, sj);
+            if (D == 3) pro_axis(k, nc, bc, ok, nk, sk);
+            double s = 0.0;
+            for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (D == 3 ? (cz ? 0.25 : 0.75) : 1.0);
+                        const double sg = double((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
+                        s += w * (sg * E[(int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
+                                         (a ? ni : oi)]);
+                    }
+            X[c] += s;
+        }
+        __syncthreads();
+        for (int it = 0; it < nu2; ++it) {
+            for (int64_t c = tid; c < m; c += NT) {
+                int i, j, k;
+                decode<D>(c, lg, i, j, k);
+                ts[c] = X[c] + wd * (F[c] - ad_ax<D>(X, c, i, j, k, lg, bc, W));
+            }
+            __syncthreads();
+            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
+            __syncthreads();
+        }
+    }
+    for (int64_t c = tid; c < mt; c += NT) x_t[c] = xs[c];
+}
+
 // Partials of ||a - b||_1 (||a||_1 when b is null) over a strided grid (fixed
 // order), gated by the controller: the change of the iterate over the cycle
 // just run.

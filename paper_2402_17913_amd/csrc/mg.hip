@@ -1613,6 +1613,12 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
         oth[l] = (double *)H->t[l];
         F[l] = l == 0 ? f : (const double *)H->f[l];
     }
+    // level handed to the one-workgroup tail (0 = none): the first coarse level
+    // that fits it, unless it is the coarsest grid itself
+    int tl = 0;
+    if (g_tune.tail && co.nu1 >= 1)
+        for (int l = 1; l <= L; ++l)
+            if (lg0 - l <= Tail<D>::LG && lg0 - l > 2) { tl = l; break; }
     double hl = h;
     for (int l = 0; l <= L; ++l, hl *= 2.0) {
         const int lg = lg0 - l;
@@ -1620,6 +1626,14 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
         const AdW W = ad_weights(op, D, hl);
         const double wd = co.omega / W.c0;
         const bool zero = l > 0;
+        if (l > 0 && l == tl) {  // levels tl .. L in one workgroup
+            AdLevels Wl{};
+            for (int q = 0; q <= L - l; ++q) Wl.w[q] = ad_weights(op, D, hl * double(int64_t(1) << q));
+            hipLaunchKernelGGL((k_ad_tail<D>), dim3(1), dim3(Tail<D>::NT), 0, s, F[l], cur[l], H->ad_minv, lg, bc,
+                               Wl, co.omega, co.nu1, co.nu2, stop);
+            NP_LAUNCH_CHECK();
+            break;
+        }
         if (l == 0 && (co.nu1 == 0 || L == 0)) {  // the check on its own: no sweep opens this level
             const unsigned nb = std::min<unsigned>(kRedBlocks, blocks_for(m));
             hipLaunchKernelGGL((k_ad_resid<D>), dim3(nb), dim3(kBlock), 0, s, F[0], cur[0], nullptr, H->red, lg, bc,
@@ -1680,7 +1694,7 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
         NP_LAUNCH_CHECK();
         if (prof) NP_TRY(prof_end(s, tok, double(m) * (2 + 1.0 / (1 << D)) * sizeof(double)));
     }
-    for (int l = L - 1; l >= 0; --l) {
+    for (int l = (tl > 0 ? tl : L) - 1; l >= 0; --l) {
         const int lg = lg0 - l;
         const int64_t m = cells(D, lg);
         const double hh = h * double(int64_t(1) << l);
