@@ -242,6 +242,144 @@ __global__ __launch_bounds__(kS3Threads) void k_ad_restrict3(const double *__res
     }
 }
 
+// ------------------------------------------ 2D levels on row-marching strips
+// A workgroup of kR2 threads owns kR2 consecutive columns and ry consecutive
+// rows: rows j - 1, j, j + 1 of the own column in registers, row j with its
+// two halo cells in LDS (two buffers, one barrier per row), row j + 2 and the
+// halo of row j + 1 loaded while row j is computed.  Every thread issues the
+// halo load (threads without a halo cell reload their own cell), so no load
+// is conditional.  Requires n >= kR2.
+constexpr int kR2 = kBlock;
+
+struct RMarch {
+    int n, lg, bc, i, j0, hx;
+    bool hw;
+    int64_t hsrc;
+    double hsg;
+    double xm, xc, xp, hv, xpp, hn;
+    __device__ RMarch(int lg_, int bc_, int ry) : n(1 << lg_), lg(lg_), bc(bc_) {
+        const int strips = n / kR2;
+        const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+        const int t = int(threadIdx.x);
+        const int x0 = (blk % strips) * kR2;
+        j0 = (blk / strips) * ry;
+        i = x0 + t;
+        hw = t < 2;
+        hx = t == 0 ? 0 : kR2 + 1;
+        int gi = t == 0 ? x0 - 1 : (t == 1 ? x0 + kR2 : i);
+        hsg = 1.0;
+        if (gi < 0) {  // outside: wrap (periodic) or the adjacent cell negated (Dirichlet)
+            gi = bc ? n - 1 : 0;
+            if (!bc) hsg = -1.0;
+        } else if (gi >= n) {
+            gi = bc ? 0 : n - 1;
+            if (!bc) hsg = -1.0;
+        }
+        hsrc = gi;
+    }
+    __device__ __forceinline__ int64_t row(int j) const { return int64_t(j) << lg; }
+    // offset of the row above j and its sign (the top Dirichlet ghost is -(own value))
+    __device__ __forceinline__ int64_t up_at(int j) const { return j < n - 1 ? row(j + 1) : (bc ? 0 : row(j)); }
+    __device__ __forceinline__ double up_sg(int j) const { return (j < n - 1 || bc) ? 1.0 : -1.0; }
+    __device__ __forceinline__ int next(int j) const { return j + 1 < n ? j + 1 : n - 1; }
+    __device__ __forceinline__ void start(const double *__restrict__ x) {
+        xc = x[row(j0) + i];
+        if (j0 > 0) xm = x[row(j0 - 1) + i];
+        else if (bc) xm = x[row(n - 1) + i];
+        else xm = -xc;
+        xp = x[up_at(j0) + i] * up_sg(j0);
+        hv = hsg * x[row(j0) + hsrc];
+    }
+    __device__ __forceinline__ void prefetch(const double *__restrict__ x, int j) {
+        const int jn = next(j);
+        xpp = x[up_at(jn) + i] * up_sg(jn);
+        hn = hsg * x[row(jn) + hsrc];
+    }
+    // publish row j to b and return (A x) at the own cell
+    __device__ __forceinline__ double ax(double (&b)[kR2 + 2], const AdW &W) const {
+        b[threadIdx.x + 1] = xc;
+        if (hw) b[hx] = hv;
+        __syncthreads();
+        const int l = int(threadIdx.x) + 1;
+        return W.c0 * xc + (W.cm[0] * b[l - 1] + W.cp[0] * b[l + 1]) + (W.cm[1] * xm + W.cp[1] * xp);
+    }
+    __device__ __forceinline__ void advance() {
+        xm = xc;
+        xc = xp;
+        xp = xpp;
+        hv = hn;
+    }
+};
+
+// Rows per workgroup of a row-marching launch on an n^2 level: enough
+// workgroups to fill the chip, at least 4 rows.
+inline int r2_rows(int lg) {
+    const int n = 1 << lg, strips = n / kR2;
+    int ry = 32;
+    while (int64_t(strips) * (n / ry) < 2048 && ry > 4) ry /= 2;
+    return ry;
+}
+
+// Relaxed-Jacobi sweep (as k_ad_sweep) over ry rows per workgroup.  NORM:
+// per-workgroup partial of ||f - A x_in||^2.
+template <bool NORM>
+__global__ __launch_bounds__(kR2) void k_ad_sweep2(const double *__restrict__ f, const double *__restrict__ xin,
+                                                   double *__restrict__ xout, double *__restrict__ partial, int lg,
+                                                   int bc, int ry, AdW W, double wdiag, const int *stop) {
+    __shared__ double b[2][kR2 + 2];
+    if (stop && *stop) return;
+    RMarch z(lg, bc, ry);
+    z.start(xin);
+    double fc = f[z.row(z.j0) + z.i];
+    double acc = 0.0;
+    for (int j = z.j0, q = 0; j < z.j0 + ry; ++j, q ^= 1) {
+        z.prefetch(xin, j);
+        const double fn = f[z.row(z.next(j)) + z.i];
+        const double r = fc - z.ax(b[q], W);
+        if (NORM) acc += r * r;
+        xout[z.row(j) + z.i] = z.xc + wdiag * r;
+        fc = fn;
+        z.advance();
+    }
+    if (NORM) {
+        acc = block_sum(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
+// Residual + restriction on row-marching strips: each thread sums its
+// residuals over a pair of rows, then one thread per coarse cell adds its
+// right neighbour's pair sum through LDS.  ry even.
+__global__ __launch_bounds__(kR2) void k_ad_restrict2(const double *__restrict__ f, const double *__restrict__ x,
+                                                      double *__restrict__ fc, int lg, int bc, int ry, AdW W,
+                                                      const int *stop) {
+    __shared__ double b[2][kR2 + 2];
+    __shared__ double rs[kR2];
+    if (stop && *stop) return;
+    RMarch z(lg, bc, ry);
+    z.start(x);
+    const int lgc = lg - 1;
+    double f0 = f[z.row(z.j0) + z.i];
+    double pair = 0.0;
+    for (int j = z.j0, q = 0; j < z.j0 + ry; ++j, q ^= 1) {
+        z.prefetch(x, j);
+        const double fn = f[z.row(z.next(j)) + z.i];
+        const double r = f0 - z.ax(b[q], W);
+        if (((j - z.j0) & 1) == 0) {
+            pair = r;
+        } else {
+            pair += r;
+            rs[threadIdx.x] = pair;
+            __syncthreads();
+            if ((threadIdx.x & 1) == 0)
+                fc[(int64_t(j >> 1) << lgc) + (z.i >> 1)] = (rs[threadIdx.x] + rs[threadIdx.x + 1]) * 0.25;
+            // rs is written again two rows later, after row j + 1's barrier
+        }
+        f0 = fn;
+        z.advance();
+    }
+}
+
 // ------------------------------------- small levels in one workgroup (LDS)
 // Weights of the levels handled by k_ad_tail, finest first.
 struct AdLevels {

@@ -1589,12 +1589,18 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
     const int64_t m0 = cells(D, lg0);
     // 3D levels of at least 128^3 run on the z-marching tiles
     auto zm3 = [](int lg) { return D == 3 && lg >= 7 && g_tune.sweep3; };
+    // 2D levels of at least 1024^2 run on row-marching strips
+    auto rm2 = [](int lg) { return D == 2 && lg >= 10 && g_tune.sweep3; };
     // one sweep of a level (not from zero, no norm)
     auto ad_sweep = [&](const double *fl, const double *xi, double *xo, int lg, const AdW &W, double wd) {
         if (zm3(lg)) {
             const int zc = sweep3_planes(lg, 1, kPartials);
             hipLaunchKernelGGL((k_ad_sweep3<false>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, fl, xi, xo,
                                nullptr, lg, bc, zc, W, wd, stop);
+        } else if (rm2(lg)) {
+            const int ry = r2_rows(lg);
+            hipLaunchKernelGGL((k_ad_sweep2<false>), dim3(unsigned(cells(2, lg) / (kR2 * ry))), dim3(kR2), 0, s, fl,
+                               xi, xo, nullptr, lg, bc, ry, W, wd, stop);
         } else {
             hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, fl,
                                xi, xo, nullptr, lg, bc, W, wd, stop);
@@ -1666,6 +1672,11 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
                     nb = zblocks(lg, 1, zc);
                     hipLaunchKernelGGL((k_ad_sweep3<true>), dim3(nb), dim3(kS3Threads), 0, s, F[l], cur[l], oth[l],
                                        H->red, lg, bc, zc, W, wd, stop);
+                } else if (rm2(lg)) {
+                    const int ry = r2_rows(lg);
+                    nb = unsigned(cells(2, lg) / (kR2 * ry));
+                    hipLaunchKernelGGL((k_ad_sweep2<true>), dim3(nb), dim3(kR2), 0, s, F[l], cur[l], oth[l], H->red,
+                                       lg, bc, ry, W, wd, stop);
                 } else {
                     nb = std::min<unsigned>(kNormBlocks, blocks_for(m));
                     hipLaunchKernelGGL((k_ad_sweep<D, false, true>), dim3(nb), dim3(kBlock), 0, s, F[l], cur[l],
@@ -1687,6 +1698,10 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
             const int zc = sweep3_planes(lg, 1, kPartials);
             hipLaunchKernelGGL(k_ad_restrict3, dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, F[l], cur[l],
                                (double *)H->f[l + 1], lg, bc, zc, W, stop);
+        } else if (rm2(lg)) {
+            const int ry = r2_rows(lg);
+            hipLaunchKernelGGL(k_ad_restrict2, dim3(unsigned(cells(2, lg) / (kR2 * ry))), dim3(kR2), 0, s, F[l],
+                               cur[l], (double *)H->f[l + 1], lg, bc, ry, W, stop);
         } else {
             hipLaunchKernelGGL((k_ad_resid_restrict<D>), dim3(blocks_for(cells(D, lg - 1))), dim3(kBlock), 0, s,
                                F[l], cur[l], (double *)H->f[l + 1], lg, bc, W, stop);

@@ -68,7 +68,7 @@ def test_ad_apply(B, orc, d, n, bc, scheme):
 
 
 # ------------------------------------------------------------- fixed cycles
-@pytest.mark.parametrize("d,n", [(2, 4), (2, 16), (2, 128), (2, 512), (3, 8), (3, 32), (3, 64), (3, 128)])
+@pytest.mark.parametrize("d,n", [(2, 4), (2, 16), (2, 128), (2, 512), (2, 1024), (3, 8), (3, 32), (3, 64), (3, 128)])
 @pytest.mark.parametrize("bc", [DIR, PER])
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_ad_vcycles_match_oracle(B, orc, d, n, bc, scheme):
