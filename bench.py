@@ -303,22 +303,24 @@ def leg_sawtooth(B, inputs, steps, warmup):
     return dict(workload="sawtooth_vs_v22_dirichlet_fp64_tol1e-10", **out)
 
 
-def ad_kernel_times(B, solve, steps):
-    """Per-kind duration of the finest-level kernels of the advection-diffusion
-    V-cycle, each launch bracketed by HIP events on its stream."""
+def ad_level_live(B, T0, h, op):
+    """Finest-level kernels of the advection-diffusion solve timed live: SWEEP_REPS
+    back-to-back launches of the solver's own kernel and launch shape between HIP
+    events on the library stream (np_ad_prof_level), against HBM peak."""
     import torch
+    d, n = T0.dim(), T0.shape[0]
+    m = T0.numel()
+    x = torch.randn_like(T0)
+    y = torch.zeros_like(T0)
+    yc = torch.zeros((n // 2,) * d, dtype=torch.float64, device=T0.device)
     out = {}
-    for name, mask in (("sweep", B.PROF_JACOBI), ("restrict", B.PROF_RESTRICT), ("prolong", B.PROF_PROLONG)):
-        B.np_prof_enable(mask)
-        for _ in range(steps):
-            solve()
-        torch.cuda.synchronize()
-        n, ms, by = B.np_prof_read()
-        B.np_prof_enable(0)
-        if n:
-            gbs = (by / n) / (ms / n * 1e-3) / 1e9
-            out[name] = dict(launches=n, avg_us=1e3 * ms / n, bytes_per_launch=by / n, gbs=gbs,
-                             frac=gbs / HBM_PEAK_GBS)
+    for kname, kind, nbytes in (("sweep", B.PROF_LEVEL_SWEEP, 24 * m), ("restrict", B.PROF_LEVEL_RESTRICT,
+                                                                         16 * m + 8 * m // 2 ** d),
+                                ("prolong", B.PROF_LEVEL_PROLONG, 16 * m + 8 * m // 2 ** d)):
+        ms = B.np_ad_prof_level(kind, T0, x, y if kind == B.PROF_LEVEL_SWEEP else yc, h, B.BC_DIRICHLET0, op,
+                                reps=SWEEP_REPS)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[kname] = dict(avg_us=1e3 * ms, bytes_per_launch=nbytes, gbs=gbs, frac=gbs / HBM_PEAK_GBS)
     return out
 
 
@@ -362,7 +364,7 @@ def leg_ad(B, inputs, steps, warmup):
         opd = B.ad_op(50.0, 2.0, [1.0] * d, 0)
         solve = lambda: B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, opd, tol=TOL)
         dt, (st, stats) = timed(solve, steps, warmup)
-        ker = ad_kernel_times(B, solve, 2)
+        ker = ad_level_live(B, T0, 1.0, opd)
         out[name] = dict(dofs=T0.numel(), dofs_per_s=T0.numel() * steps / dt, ms_per_solve=1e3 * dt / steps,
                          cycles=stats["cycles"], rel_res=stats["rel_res"], rho=stats["rho_est"],
                          finest_level_kernels=ker)

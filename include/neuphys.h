@@ -202,6 +202,15 @@ np_status np_ad_implicit_solve(np_dims dims, double h, np_bc bc, const np_ad_op 
 np_status np_ad_apply(np_dims dims, double h, np_bc bc, const np_ad_op *op, const double *x, double *y,
                       void *stream);
 
+/* Timing of the finest-level kernels of np_ad_implicit_solve on this grid
+ * (the same kernels and launch shapes): `reps` back-to-back launches between
+ * two events on the stream, *avg_ms their average.  kind 0: relaxed-Jacobi
+ * sweep y = x + (2/3) (f - A x) / A_00; 1: residual restriction y = R (f - A x)
+ * (y coarse, n/2 per axis); 2: prolongation and correction x += P y (y coarse;
+ * f unused).  Device FP64 arrays; n >= 8. */
+np_status np_ad_prof_level(np_dims dims, double h, np_bc bc, const np_ad_op *op, int kind, const double *f,
+                           double *x, double *y, int reps, void *stream, double *avg_ms);
+
 /* ns_projection_step that also copies the pressure-correction right-hand
  * side -(1/dt) D q* and the increment dp it solved for into rhs_out and
  * dp_out (device FP64, n^d each; either may be NULL).  Used to generate

@@ -108,6 +108,7 @@ _SIGS = {
     "np_ad_implicit_solve": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _D, ctypes.POINTER(NpMgOpts),
                                   ctypes.POINTER(NpMgStats), ctypes.POINTER(_D)]),
     "np_ad_apply": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _P]),
+    "np_ad_prof_level": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
 }
 
 
@@ -364,6 +365,16 @@ def np_ad_implicit_solve(rhs, x, h, bc, op, tol=1e-10, check=True, l1=False, **o
 
 def np_ad_apply(x, y, h, bc, op):
     _check("np_ad_apply", lib.np_ad_apply(_dims(x), h, bc, ctypes.byref(op), _dev(x), _dev(y), _stream()))
+
+
+def np_ad_prof_level(kind, f, x, y, h, bc, op, reps=50):
+    """Average duration (ms) of `reps` back-to-back launches of the advection-diffusion
+    solver's level kernel `kind` (PROF_LEVEL_SWEEP/RESTRICT/PROLONG) on this grid."""
+    out = ctypes.c_double(0.0)
+    _check("np_ad_prof_level", lib.np_ad_prof_level(_dims(x), h, bc, ctypes.byref(op), kind,
+                                                    _dev(f) if f is not None else None, _dev(x), _dev(y), reps,
+                                                    _stream(), ctypes.byref(out)))
+    return out.value
 
 
 def np_op_apply(x, y, h, bc):

@@ -1578,6 +1578,86 @@ static np_status ad_l1_gauge(Hier *H, const double *x, const double *xold, hipSt
     return NP_OK;
 }
 
+// Level launchers.  3D levels of at least 128^3 run on the z-marching tiles,
+// 2D levels of at least 1024^2 on row-marching strips, smaller levels one
+// cell per thread.
+template <int D> static bool ad_zm3(int lg) { return D == 3 && lg >= 7 && g_tune.sweep3; }
+template <int D> static bool ad_rm2(int lg) { return D == 2 && lg >= 10 && g_tune.sweep3; }
+
+// One relaxed-Jacobi sweep xo = xi + wd (f - A xi).  partial != null: also
+// the per-workgroup partials of ||f - A xi||^2, their count into *np.
+template <int D>
+static np_status ad_launch_sweep(const double *f, const double *xi, double *xo, double *partial, unsigned *np, int lg,
+                                 int bc, const AdW &W, double wd, hipStream_t s, const int *stop) {
+    const int64_t m = cells(D, lg);
+    unsigned nb;
+    if (ad_zm3<D>(lg)) {
+        const int zc = sweep3_planes(lg, 1, kPartials);
+        nb = zblocks(lg, 1, zc);
+        if (partial)
+            hipLaunchKernelGGL((k_ad_sweep3<true>), dim3(nb), dim3(kS3Threads), 0, s, f, xi, xo, partial, lg, bc, zc,
+                               W, wd, stop);
+        else
+            hipLaunchKernelGGL((k_ad_sweep3<false>), dim3(nb), dim3(kS3Threads), 0, s, f, xi, xo, nullptr, lg, bc, zc,
+                               W, wd, stop);
+    } else if (ad_rm2<D>(lg)) {
+        const int ry = r2_rows(lg);
+        nb = unsigned(m / (kR2 * ry));
+        if (partial)
+            hipLaunchKernelGGL((k_ad_sweep2<true>), dim3(nb), dim3(kR2), 0, s, f, xi, xo, partial, lg, bc, ry, W, wd,
+                               stop);
+        else
+            hipLaunchKernelGGL((k_ad_sweep2<false>), dim3(nb), dim3(kR2), 0, s, f, xi, xo, nullptr, lg, bc, ry, W, wd,
+                               stop);
+    } else if (partial) {
+        nb = std::min<unsigned>(kNormBlocks, blocks_for(m));
+        hipLaunchKernelGGL((k_ad_sweep<D, false, true>), dim3(nb), dim3(kBlock), 0, s, f, xi, xo, partial, lg, bc, W,
+                           wd, stop);
+    } else {
+        nb = blocks_for(m);
+        hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(nb), dim3(kBlock), 0, s, f, xi, xo, nullptr, lg, bc, W,
+                           wd, stop);
+    }
+    NP_LAUNCH_CHECK();
+    if (np) *np = nb;
+    return NP_OK;
+}
+
+// fc = R (f - A x) onto the next coarser level.
+template <int D>
+static np_status ad_launch_restrict(const double *f, const double *x, double *fc, int lg, int bc, const AdW &W,
+                                    hipStream_t s, const int *stop) {
+    if (ad_zm3<D>(lg)) {
+        const int zc = sweep3_planes(lg, 1, kPartials);
+        hipLaunchKernelGGL(k_ad_restrict3, dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, f, x, fc, lg, bc, zc, W,
+                           stop);
+    } else if (ad_rm2<D>(lg)) {
+        const int ry = r2_rows(lg);
+        hipLaunchKernelGGL(k_ad_restrict2, dim3(unsigned(cells(2, lg) / (kR2 * ry))), dim3(kR2), 0, s, f, x, fc, lg,
+                           bc, ry, W, stop);
+    } else {
+        hipLaunchKernelGGL((k_ad_resid_restrict<D>), dim3(blocks_for(cells(D, lg - 1))), dim3(kBlock), 0, s, f, x, fc,
+                           lg, bc, W, stop);
+    }
+    NP_LAUNCH_CHECK();
+    return NP_OK;
+}
+
+// x += P ec from the next coarser level (lg: the fine level).
+template <int D>
+static np_status ad_launch_prolong(const double *ec, double *x, int lg, int bc, hipStream_t s, const int *stop) {
+    if (ad_zm3<D>(lg)) {
+        const int zc = sweep3_planes(lg, 1, kPartials);
+        hipLaunchKernelGGL((k_prolong3<double>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, ec, x, lg, bc, zc,
+                           stop);
+    } else {
+        hipLaunchKernelGGL((k_prolong_add<D, double>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, ec, x,
+                           lg - 1, bc, stop);
+    }
+    NP_LAUNCH_CHECK();
+    return NP_OK;
+}
+
 // One V(nu1, nu2) cycle of the operator on x (level 0 uses x, f and t[0]),
 // opened by the convergence check of the input iterate; every launch is
 // gated by the controller.  l1: record the change of x over the cycle.
@@ -1587,27 +1667,6 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
     const int L = H->L, bc = H->bc, lg0 = H->lg;
     const int *stop = &H->ctl->stop;
     const int64_t m0 = cells(D, lg0);
-    // 3D levels of at least 128^3 run on the z-marching tiles
-    auto zm3 = [](int lg) { return D == 3 && lg >= 7 && g_tune.sweep3; };
-    // 2D levels of at least 1024^2 run on row-marching strips
-    auto rm2 = [](int lg) { return D == 2 && lg >= 10 && g_tune.sweep3; };
-    // one sweep of a level (not from zero, no norm)
-    auto ad_sweep = [&](const double *fl, const double *xi, double *xo, int lg, const AdW &W, double wd) {
-        if (zm3(lg)) {
-            const int zc = sweep3_planes(lg, 1, kPartials);
-            hipLaunchKernelGGL((k_ad_sweep3<false>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, fl, xi, xo,
-                               nullptr, lg, bc, zc, W, wd, stop);
-        } else if (rm2(lg)) {
-            const int ry = r2_rows(lg);
-            hipLaunchKernelGGL((k_ad_sweep2<false>), dim3(unsigned(cells(2, lg) / (kR2 * ry))), dim3(kR2), 0, s, fl,
-                               xi, xo, nullptr, lg, bc, ry, W, wd, stop);
-        } else {
-            hipLaunchKernelGGL((k_ad_sweep<D, false, false>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, fl,
-                               xi, xo, nullptr, lg, bc, W, wd, stop);
-        }
-        NP_LAUNCH_CHECK();
-        return NP_OK;
-    };
     if (l1) {
         hipLaunchKernelGGL((k_copy<double>), dim3(blocks_for(m0)), dim3(kBlock), 0, s, x, H->xold, m0, stop);
         NP_LAUNCH_CHECK();
@@ -1665,74 +1724,39 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
             if (zero && it == 0) {
                 hipLaunchKernelGGL((k_ad_sweep<D, true, false>), dim3(blocks_for(m)), dim3(kBlock), 0, s, F[l],
                                    nullptr, oth[l], nullptr, lg, bc, W, wd, stop);
-            } else if (l == 0 && it == 0) {  // residual norm of the input iterate, then the stop rule
-                unsigned nb;
-                if (zm3(lg)) {
-                    const int zc = sweep3_planes(lg, 1, kPartials);
-                    nb = zblocks(lg, 1, zc);
-                    hipLaunchKernelGGL((k_ad_sweep3<true>), dim3(nb), dim3(kS3Threads), 0, s, F[l], cur[l], oth[l],
-                                       H->red, lg, bc, zc, W, wd, stop);
-                } else if (rm2(lg)) {
-                    const int ry = r2_rows(lg);
-                    nb = unsigned(cells(2, lg) / (kR2 * ry));
-                    hipLaunchKernelGGL((k_ad_sweep2<true>), dim3(nb), dim3(kR2), 0, s, F[l], cur[l], oth[l], H->red,
-                                       lg, bc, ry, W, wd, stop);
-                } else {
-                    nb = std::min<unsigned>(kNormBlocks, blocks_for(m));
-                    hipLaunchKernelGGL((k_ad_sweep<D, false, true>), dim3(nb), dim3(kBlock), 0, s, F[l], cur[l],
-                                       oth[l], H->red, lg, bc, W, wd, stop);
-                }
                 NP_LAUNCH_CHECK();
+            } else if (l == 0 && it == 0) {  // residual norm of the input iterate, then the stop rule
+                unsigned nb = 0;
+                NP_TRY(ad_launch_sweep<D>(F[l], cur[l], oth[l], H->red, &nb, lg, bc, W, wd, s, stop));
                 hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, int(nb), H->ctl);
+                NP_LAUNCH_CHECK();
             } else {
-                NP_TRY(ad_sweep(F[l], cur[l], oth[l], lg, W, wd));
+                NP_TRY(ad_launch_sweep<D>(F[l], cur[l], oth[l], nullptr, nullptr, lg, bc, W, wd, s, stop));
             }
-            NP_LAUNCH_CHECK();
             if (prof) NP_TRY(prof_end(s, tok, double(m) * 3 * sizeof(double)));
             std::swap(cur[l], oth[l]);
         }
         void *tok = nullptr;
         const bool prof = l == 0 && (prof_on() & kProfRestrict);
         if (prof) NP_TRY(prof_begin(s, &tok));
-        if (zm3(lg)) {
-            const int zc = sweep3_planes(lg, 1, kPartials);
-            hipLaunchKernelGGL(k_ad_restrict3, dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, F[l], cur[l],
-                               (double *)H->f[l + 1], lg, bc, zc, W, stop);
-        } else if (rm2(lg)) {
-            const int ry = r2_rows(lg);
-            hipLaunchKernelGGL(k_ad_restrict2, dim3(unsigned(cells(2, lg) / (kR2 * ry))), dim3(kR2), 0, s, F[l],
-                               cur[l], (double *)H->f[l + 1], lg, bc, ry, W, stop);
-        } else {
-            hipLaunchKernelGGL((k_ad_resid_restrict<D>), dim3(blocks_for(cells(D, lg - 1))), dim3(kBlock), 0, s,
-                               F[l], cur[l], (double *)H->f[l + 1], lg, bc, W, stop);
-        }
-        NP_LAUNCH_CHECK();
+        NP_TRY(ad_launch_restrict<D>(F[l], cur[l], (double *)H->f[l + 1], lg, bc, W, s, stop));
         if (prof) NP_TRY(prof_end(s, tok, double(m) * (2 + 1.0 / (1 << D)) * sizeof(double)));
     }
     for (int l = (tl > 0 ? tl : L) - 1; l >= 0; --l) {
         const int lg = lg0 - l;
         const int64_t m = cells(D, lg);
-        const double hh = h * double(int64_t(1) << l);
-        const AdW W = ad_weights(op, D, hh);
+        const AdW W = ad_weights(op, D, h * double(int64_t(1) << l));
         const double wd = co.omega / W.c0;
         void *tok = nullptr;
         const bool prof = l == 0 && (prof_on() & kProfProlong);
         if (prof) NP_TRY(prof_begin(s, &tok));
-        if (zm3(lg)) {
-            const int zc = sweep3_planes(lg, 1, kPartials);
-            hipLaunchKernelGGL((k_prolong3<double>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, cur[l + 1],
-                               cur[l], lg, bc, zc, stop);
-        } else {
-            hipLaunchKernelGGL((k_prolong_add<D, double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, cur[l + 1],
-                               cur[l], lg - 1, bc, stop);
-        }
-        NP_LAUNCH_CHECK();
+        NP_TRY(ad_launch_prolong<D>(cur[l + 1], cur[l], lg, bc, s, stop));
         if (prof) NP_TRY(prof_end(s, tok, double(m) * (2 + 1.0 / (1 << D)) * sizeof(double)));
         for (int it = 0; it < co.nu2; ++it) {
             void *tk = nullptr;
             const bool pj = l == 0 && (prof_on() & kProfJacobi);
             if (pj) NP_TRY(prof_begin(s, &tk));
-            NP_TRY(ad_sweep(F[l], cur[l], oth[l], lg, ad_weights(op, D, hh), wd));
+            NP_TRY(ad_launch_sweep<D>(F[l], cur[l], oth[l], nullptr, nullptr, lg, bc, W, wd, s, stop));
             if (pj) NP_TRY(prof_end(s, tk, double(m) * 3 * sizeof(double)));
             std::swap(cur[l], oth[l]);
         }
@@ -1907,4 +1931,55 @@ extern "C" np_status np_ad_apply(np_dims dims, double h, np_bc bc, const np_ad_o
     NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
+}
+
+// Back-to-back launches of an advection-diffusion level kernel the solver
+// uses on this grid (same kernel and launch shape) between two events on the
+// stream: kind 0 the sweep y = sweep(x); 1 the residual restriction y =
+// R (f - A x); 2 the prolongation x += P y.
+template <int D>
+static np_status time_ad_level(int kind, const np_ad_op &op, const double *f, double *x, double *y, int lg, int bc,
+                               double h, int reps, hipStream_t s, double *avg_ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    NP_HIP_TRY(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        set_error("hipEventCreate failed");
+        return NP_EHIP;
+    }
+    const AdW W = ad_weights(op, D, h);
+    auto run = [&]() -> np_status {
+        if (kind == 0)
+            return ad_launch_sweep<D>(f, x, y, nullptr, nullptr, lg, bc, W, (2.0 / 3.0) / W.c0, s, nullptr);
+        if (kind == 1) return ad_launch_restrict<D>(f, x, y, lg, bc, W, s, nullptr);
+        return ad_launch_prolong<D>(y, x, lg, bc, s, nullptr);
+    };
+    np_status st = run();  // warm-up
+    if (st == NP_OK && hipEventRecord(a, s) != hipSuccess) st = NP_EHIP;
+    for (int r = 0; r < reps && st == NP_OK; ++r) st = run();
+    float ms = 0.f;
+    if (st == NP_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                        hipEventElapsedTime(&ms, a, b) != hipSuccess))
+        st = NP_EHIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st == NP_EHIP) set_error("event timing failed");
+    if (st == NP_OK) *avg_ms = double(ms) / reps;
+    return st;
+}
+
+extern "C" np_status np_ad_prof_level(np_dims dims, double h, np_bc bc, const np_ad_op *op, int kind, const double *f,
+                                      double *x, double *y, int reps, void *stream, double *avg_ms) {
+    int lg;
+    NP_TRY(op_prelude(dims, h, bc, &lg));
+    NP_TRY(check_ad_op(op, dims.ndim));
+    if (!x || !y || !avg_ms || reps < 1 || x == y || kind < 0 || kind > 2 || (kind < 2 && !f) || lg < 3) {
+        set_error("bad argument");
+        return NP_EINVAL;
+    }
+    np_ad_op op2 = *op;
+    for (int e = dims.ndim; e < 3; ++e) op2.a[e] = 0.0;
+    hipStream_t s = (hipStream_t)stream;
+    return dims.ndim == 3 ? time_ad_level<3>(kind, op2, f, x, y, lg, bc, h, reps, s, avg_ms)
+                          : time_ad_level<2>(kind, op2, f, x, y, lg, bc, h, reps, s, avg_ms);
 }

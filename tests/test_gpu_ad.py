@@ -222,3 +222,23 @@ def test_ad_solver_reports_divergence(B):
     st, s = B.np_ad_implicit_solve(dev(T0), xg, 1.0, DIR, B.ad_op(50.0, 2.0, [1.0, 1.0]), check=False,
                                    cycle=B.CYCLE_SAWTOOTH, prolong=B.PROLONG_COPY, nu1=0, nu2=1, omega=1.0)
     assert st == B.NP_ENOCONV
+
+
+def test_ad_level_timing_entry(B, orc):
+    """np_ad_prof_level runs the solver's finest-level kernels (2D row-marching and 3D
+    z-marching shapes included) and reports a positive duration; the timed sweep and
+    restriction leave the oracle's values in y."""
+    for d, n in ((2, 1024), (3, 128), (2, 64)):
+        fh = np.random.default_rng(7).standard_normal((n,) * d)
+        xh = np.random.default_rng(8).standard_normal((n,) * d)
+        f, x = dev(fh), dev(xh)
+        y = dev(np.zeros((n,) * d))
+        yc = dev(np.zeros((n // 2,) * d))
+        op_g, op_o = ops(B, orc, d, DIR, 50.0, 2.0, [1.0, 1.0, 1.0], 0)
+        assert B.np_ad_prof_level(B.PROF_LEVEL_SWEEP, f, x, y, 1.0, DIR, op_g, reps=3) > 0.0
+        assert rel(host(y), orc.ad_jacobi(op_o, fh, xh, 1.0, omega=2.0 / 3.0)) < 1e-13
+        assert B.np_ad_prof_level(B.PROF_LEVEL_RESTRICT, f, x, yc, 1.0, DIR, op_g, reps=3) > 0.0
+        r = fh - orc.ad_apply(op_o, xh, 1.0)
+        rc = r.reshape(tuple(v for k in range(d) for v in (n // 2, 2))).mean(axis=tuple(range(1, 2 * d, 2)))
+        assert rel(host(yc), rc) < 1e-12
+        assert B.np_ad_prof_level(B.PROF_LEVEL_PROLONG, None, x.clone(), yc, 1.0, DIR, op_g, reps=3) > 0.0
