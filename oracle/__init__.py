@@ -56,6 +56,8 @@ def lib():
             "or_sawtooth": [_d, _i64, _f64, _d, _f64, _d, _d, _i64, _p, _p],
             "or_saw_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _f64, _d, _d, _d, _d, _i64, _p, _p, _p, _d],
             "or_ad_apply": [_p, _i64, _f64, _p, _p],
+            "or_ad_explicit_step": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _f64],
+            "or_ad_explicit_rate": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _p],
             "or_ad_jacobi": [_p, _i64, _f64, _f64, _p, _p, _p],
             "or_ad_vcycle": [_p, _i64, _f64, _d, _d, _f64, _i64, _p, _p],
             "or_ad_sawtooth": [_p, _i64, _f64, _f64, _d, _d, _i64, _p, _p],
@@ -274,6 +276,39 @@ def mg_solve(f, h, bc, tol=1e-10, nu1=2, nu2=2, omega=2.0 / 3.0, max_cycles=200,
     if st == -1:
         raise ValueError("oracle mg_solve: invalid arguments")
     return SolveResult(x, st, cyc.value, rr.value, hist[: min(cyc.value + 1, 256)])
+
+
+BC_NEUMANN = 2
+SCHEME_CENTRAL, SCHEME_UPWIND, SCHEME_FE = 0, 1, 2
+
+
+def ad_explicit_step(T, h, bc, dt, nu, a=None, scheme=SCHEME_CENTRAL):
+    """One predictor-corrector step with the chosen filter family; returns the new T."""
+    T = _arr(T).copy()
+    d, n = _grid(T)
+    keep = ap = None
+    if a is not None:
+        a = [_arr(c) for c in a]
+        ap, keep = _ptr_array(a)
+    if lib().or_ad_explicit_step(d, n, h, bc, scheme, _ptr(T), ap, dt, nu) != 0:
+        raise ValueError("oracle ad_explicit_step: invalid arguments")
+    del keep
+    return T
+
+
+def ad_explicit_rate(T, h, bc, nu, a=None, scheme=SCHEME_CENTRAL):
+    """The rate R(T) = a . D T + nu (diffusion filter * T) of the explicit step."""
+    T = _arr(T)
+    d, n = _grid(T)
+    keep = ap = None
+    if a is not None:
+        a = [_arr(c) for c in a]
+        ap, keep = _ptr_array(a)
+    R = np.empty_like(T)
+    if lib().or_ad_explicit_rate(d, n, h, bc, scheme, _ptr(T), ap, nu, _ptr(R)) != 0:
+        raise ValueError("oracle ad_explicit_rate: invalid arguments")
+    del keep
+    return R
 
 
 def ad_scalar_step(T, h, bc, dt, nu, a=None):

@@ -18,7 +18,10 @@
  *                     that makes the solution vanish on the cell faces that
  *                     bound the domain (reading of the paper's zero padding
  *                     for a cell-centred grid);
- *   OR_BC_PERIODIC:   ghost = value on the opposite side (wrap).
+ *   OR_BC_PERIODIC:   ghost = value on the opposite side (wrap);
+ *   OR_BC_NEUMANN:    ghost = the adjacent interior value (the copy padding
+ *                     of Section 2.4 for a zero normal derivative; used by
+ *                     the explicit step only).
  */
 #include <math.h>
 #include <stdint.h>
@@ -27,6 +30,7 @@
 
 #define OR_BC_DIRICHLET0 0
 #define OR_BC_PERIODIC 1
+#define OR_BC_NEUMANN 2
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -48,10 +52,10 @@ static double ghost_at(const double *x, int d, i64 n, int bc, i64 i, i64 j, i64 
     for (int a = 0; a < d; ++a) {
         if (c[a] < 0) {
             if (bc == OR_BC_PERIODIC) c[a] += n;
-            else { c[a] = -1 - c[a]; sign = -sign; }
+            else { c[a] = -1 - c[a]; if (bc == OR_BC_DIRICHLET0) sign = -sign; }
         } else if (c[a] >= n) {
             if (bc == OR_BC_PERIODIC) c[a] -= n;
-            else { c[a] = 2 * n - 1 - c[a]; sign = -sign; }
+            else { c[a] = 2 * n - 1 - c[a]; if (bc == OR_BC_DIRICHLET0) sign = -sign; }
         }
     }
     if (d == 2) c[2] = 0;
@@ -693,6 +697,128 @@ int or_ad_scalar_step(int d, i64 n, double h, int bc, double *T, const double *c
     ad_rate(d, n, h, bc, nu, a, Tp, R);
     for (i64 c = 0; c < m; ++c) T[c] = T[c] - dt * R[c];              /* corrector */
     free(R); free(Tp);
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Explicit advection-diffusion step with the filter families of Section 2.1
+ * and Appendix A, the same predictor-corrector as or_ad_scalar_step:
+ *   scheme 0: central first differences, 5-/7-point diffusion (Section 2.1);
+ *   scheme 1: first-order upwind advection (Section 2.1's upwind filter, read
+ *             with the value taken from upstream: backward difference for a
+ *             positive velocity component, forward for a negative one), the
+ *             same diffusion;
+ *   scheme 2: the finite-element filters of Appendix A: 2D 9-point
+ *             (bilinear) advection and diffusion, 3D 27-point (trilinear).
+ * Tables below are the printed filters.  In 2D the row is the x offset and
+ * the column the y offset (the paper's [T] matrix has rows l-1..l+1 and
+ * columns m-1..m+1).  In 3D the first index is the slice: read as z+1, z,
+ * z-1, which makes the printed z-advection filter +w dT/dz (the symmetric
+ * filters do not depend on it).  Each table multiplies its prefactor:
+ * diffusion nu/(4 h^2) (2D) and nu/(26 h^2) (3D), advection a_e/(12 h) (2D)
+ * and a_e/(72 h) (3D); the rate is R = sum_e a_e (D_e T) + nu (diffusion
+ * filter * T), every filter applied with the ghost rule of bc. */
+static const double FE2_DIFF[3][3] = {{-1, -2, -1}, {-2, 12, -2}, {-1, -2, -1}};
+static const double FE2_ADV[2][3][3] = {
+    {{-1, -4, -1}, {0, 0, 0}, {1, 4, 1}},  /* x */
+    {{-1, 0, 1}, {-4, 0, 4}, {-1, 0, 1}},  /* y */
+};
+static const double FE3_DIFF[3][3][3] = {
+    {{-2, -3, -2}, {-3, -6, -3}, {-2, -3, -2}},
+    {{-3, -6, -3}, {-6, 88, -6}, {-3, -6, -3}},
+    {{-2, -3, -2}, {-3, -6, -3}, {-2, -3, -2}},
+};
+static const double FE3_ADV[3][3][3][3] = {
+    { /* x */
+        {{-1, -4, -1}, {0, 0, 0}, {1, 4, 1}},
+        {{-4, -16, -4}, {0, 0, 0}, {4, 16, 4}},
+        {{-1, -4, -1}, {0, 0, 0}, {1, 4, 1}},
+    },
+    { /* y */
+        {{-1, 0, 1}, {-4, 0, 4}, {-1, 0, 1}},
+        {{-4, 0, 4}, {-16, 0, 16}, {-4, 0, 4}},
+        {{-1, 0, 1}, {-4, 0, 4}, {-1, 0, 1}},
+    },
+    { /* z */
+        {{1, 4, 1}, {4, 16, 4}, {1, 4, 1}},
+        {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}},
+        {{-1, -4, -1}, {-4, -16, -4}, {-1, -4, -1}},
+    },
+};
+
+/* Weight of a table at offset (dx, dy, dz). */
+static double fe_w2(const double t[3][3], int dx, int dy) { return t[dx + 1][dy + 1]; }
+static double fe_w3(const double t[3][3][3], int dx, int dy, int dz) { return t[1 - dz][dx + 1][dy + 1]; }
+
+static void adx_rate(int d, i64 n, double h, int bc, int scheme, double nu, const double *const *a,
+                     const double *T, double *R)
+{
+    const i64 nz = d == 3 ? n : 1;
+    const int kz = d == 3 ? 1 : 0;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 c = (k * n + j) * n + i;
+                const double tc = T[c];
+                double dif = 0.0, adv = 0.0;
+                if (scheme == 2) {
+                    for (int dz = -kz; dz <= kz; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const double v = ghost_at(T, d, n, bc, i + dx, j + dy, k + dz);
+                                if (d == 2) {
+                                    dif += fe_w2(FE2_DIFF, dx, dy) * v;
+                                    if (a)
+                                        for (int e = 0; e < 2; ++e) adv += a[e][c] * fe_w2(FE2_ADV[e], dx, dy) * v;
+                                } else {
+                                    dif += fe_w3(FE3_DIFF, dx, dy, dz) * v;
+                                    if (a)
+                                        for (int e = 0; e < 3; ++e) adv += a[e][c] * fe_w3(FE3_ADV[e], dx, dy, dz) * v;
+                                }
+                            }
+                    dif /= (d == 2 ? 4.0 : 26.0) * h * h;
+                    adv /= (d == 2 ? 12.0 : 72.0) * h;
+                } else {
+                    for (int e = 0; e < d; ++e) {
+                        const i64 o[3][2] = {{i - (e == 0), i + (e == 0)}, {j - (e == 1), j + (e == 1)},
+                                             {k - (e == 2), k + (e == 2)}};
+                        const double tm = ghost_at(T, d, n, bc, o[0][0], o[1][0], o[2][0]);
+                        const double tp = ghost_at(T, d, n, bc, o[0][1], o[1][1], o[2][1]);
+                        dif += 2.0 * tc - tm - tp;
+                        if (!a) continue;
+                        const double ae = a[e][c];
+                        if (scheme == 0) adv += ae * (tp - tm) / (2.0 * h);
+                        else adv += ae >= 0.0 ? ae * (tc - tm) / h : ae * (tp - tc) / h;
+                    }
+                    dif /= h * h;
+                }
+                R[c] = adv + nu * dif;
+            }
+}
+
+int or_ad_explicit_step(int d, i64 n, double h, int bc, int scheme, double *T, const double *const *a,
+                        double dt, double nu)
+{
+    if ((d != 2 && d != 3) || n < 3 || !(h > 0.0) || bc < 0 || bc > 2 || scheme < 0 || scheme > 2)
+        return OR_EINVAL;
+    const i64 m = ncells(d, n);
+    double *R = malloc(sizeof(double) * m), *Tp = malloc(sizeof(double) * m);
+    adx_rate(d, n, h, bc, scheme, nu, a, T, R);
+    for (i64 c = 0; c < m; ++c) Tp[c] = T[c] - dt * R[c];            /* predictor */
+    for (i64 c = 0; c < m; ++c) Tp[c] = 0.5 * (Tp[c] + T[c]);        /* T^{n+1/2} */
+    adx_rate(d, n, h, bc, scheme, nu, a, Tp, R);
+    for (i64 c = 0; c < m; ++c) T[c] = T[c] - dt * R[c];              /* corrector */
+    free(R); free(Tp);
+    return OR_OK;
+}
+
+/* The rate R(T) of or_ad_explicit_step alone (for the pins). */
+int or_ad_explicit_rate(int d, i64 n, double h, int bc, int scheme, const double *T, const double *const *a,
+                        double nu, double *R)
+{
+    if ((d != 2 && d != 3) || n < 3 || !(h > 0.0) || bc < 0 || bc > 2 || scheme < 0 || scheme > 2)
+        return OR_EINVAL;
+    adx_rate(d, n, h, bc, scheme, nu, a, T, R);
     return OR_OK;
 }
 

@@ -864,3 +864,120 @@ def test_ad_paper_experiment_readings(orc):
     assert lit.l1diff[-1] > lit.l1diff[0]
     assert lin.l1diff[-1] < 1e-3 * lin.l1diff[0]
     assert v.status == 0 and v.cycles < 30
+
+
+# ------------------- explicit step: filter families of Section 2.1 / Appendix A
+NEU = 2
+SCHEMES = (0, 1, 2)  # central, upwind, finite-element
+
+
+def interior(d, n, r=2):
+    """Mask of cells at least r cells from every face."""
+    s = (slice(r, n - r),) * d
+    m = np.zeros((n,) * d, dtype=bool)
+    m[s] = True
+    return m
+
+
+def coords(d, n, h):
+    """Cell-centre coordinates (x, y[, z]) as arrays of shape (n,)*d (x fastest)."""
+    c = (np.arange(n) + 0.5) * h
+    g = np.meshgrid(*([c] * d), indexing="ij")  # axis 0 slowest
+    return list(reversed(g))  # [x, y, z]
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_explicit_rates_exact_on_linear_fields(orc, d, scheme):
+    """Every filter family differentiates linear fields exactly (interior cells): the
+    rate is a . grad T, diffusion adds nothing.  Pins every table's axis, sign and scale."""
+    n, h = 8, 0.5
+    X = coords(d, n, h)
+    g = [0.7, -1.3, 0.4][:d]
+    T = sum(gi * xi for gi, xi in zip(g, X))
+    a = [np.full((n,) * d, v) for v in ([1.1, -0.6, 0.8][:d])]
+    R = orc.ad_explicit_rate(T, h, DIR, 0.9, a=a, scheme=scheme)
+    expect = sum(ai[0, 0] * gi if d == 2 else ai[0, 0, 0] * gi for ai, gi in zip(a, g))
+    assert np.max(np.abs(R[interior(d, n)] - expect)) < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_explicit_diffusion_consistent_on_quadratics(orc, d, scheme):
+    """Each diffusion filter is a consistent -Laplacian: nu (filter * x_e^2) = -2 nu on
+    interior cells, and mixed products x_e x_f give 0."""
+    n, h, nu = 8, 0.5, 0.7
+    X = coords(d, n, h)
+    m = interior(d, n)
+    for e in range(d):
+        R = orc.ad_explicit_rate(X[e] ** 2, h, DIR, nu, scheme=scheme)
+        assert np.max(np.abs(R[m] + 2 * nu)) < 1e-11
+        for f in range(e + 1, d):
+            R = orc.ad_explicit_rate(X[e] * X[f], h, DIR, nu, scheme=scheme)
+            assert np.max(np.abs(R[m])) < 1e-11
+
+
+def test_explicit_fe_advection_transverse_weights(orc):
+    """The finite-element first derivative averages across the other axes with weights
+    (1, 4, 1)/6: on x y^2 it gives y^2 + h^2/3 (2D), on x y^2 z^2 the product of two such
+    averages (3D); the central difference gives y^2 (y^2 z^2)."""
+    n, h = 8, 0.5
+    for d in (2, 3):
+        X = coords(d, n, h)
+        T = X[0] * X[1] ** 2 * (X[2] ** 2 if d == 3 else 1.0)
+        a = [np.ones((n,) * d)] + [np.zeros((n,) * d)] * (d - 1)
+        m = interior(d, n)
+        fe = orc.ad_explicit_rate(T, h, DIR, 0.0, a=a, scheme=2)
+        want = (X[1] ** 2 + h ** 2 / 3) * ((X[2] ** 2 + h ** 2 / 3) if d == 3 else 1.0)
+        assert np.max(np.abs(fe[m] - want[m])) < 1e-11
+        ce = orc.ad_explicit_rate(T, h, DIR, 0.0, a=a, scheme=0)
+        assert np.max(np.abs(ce[m] - (X[1] ** 2 * (X[2] ** 2 if d == 3 else 1.0))[m])) < 1e-11
+
+
+def test_explicit_upwind_takes_the_upstream_value(orc):
+    """Upwind on x^2: a (2x - h) for a > 0 (backward difference), a (2x + h) for a < 0."""
+    n, h = 8, 0.5
+    X = coords(2, n, h)
+    m = interior(2, n)
+    for av in (1.5, -0.8):
+        a = [np.full((n, n), av), np.zeros((n, n))]
+        R = orc.ad_explicit_rate(X[0] ** 2, h, DIR, 0.0, a=a, scheme=1)
+        want = av * (2 * X[0] - np.sign(av) * h)
+        assert np.max(np.abs(R[m] - want[m])) < 1e-12
+
+
+def test_explicit_fe_diffusion_2d_symbol(orc):
+    """The 2D finite-element diffusion filter is 16 delta - (1,2,1) x (1,2,1) over 4 h^2, so
+    on a periodic grid its Fourier symbol is (4/h^2)(1 - cos^2(tx/2) cos^2(ty/2))."""
+    n, h, nu = 16, 0.5, 1.0
+    T = np.random.default_rng(9).standard_normal((n, n))
+    R = orc.ad_explicit_rate(T, h, PER, nu, scheme=2)
+    t = 2 * np.pi * np.fft.fftfreq(n)
+    ty, tx = np.meshgrid(t, t, indexing="ij")
+    lam = 4.0 / h ** 2 * (1 - np.cos(tx / 2) ** 2 * np.cos(ty / 2) ** 2)
+    assert np.max(np.abs(np.fft.fft2(R) - lam * np.fft.fft2(T))) < 1e-9
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_explicit_conservation(orc, d, scheme):
+    """Diffusion with the copy padding (zero normal derivative) and constant-velocity
+    advection on a periodic grid conserve the total: the rate sums to zero."""
+    n, h = 8, 0.5
+    T = np.random.default_rng(10 + d + scheme).standard_normal((n,) * d)
+    assert abs(orc.ad_explicit_rate(T, h, NEU, 0.8, scheme=scheme).sum()) < 1e-10
+    a = [np.full((n,) * d, v) for v in ([0.9, -0.4, 0.3][:d])]
+    assert abs(orc.ad_explicit_rate(T, h, PER, 0.8, a=a, scheme=scheme).sum()) < 1e-10
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_explicit_central_is_the_scalar_step(orc, d, bc):
+    """Scheme 0 is the Section 2.1 step of or_ad_scalar_step (independent loops)."""
+    n = 9
+    rng = np.random.default_rng(11)
+    T = rng.standard_normal((n,) * d)
+    a = [rng.standard_normal((n,) * d) for _ in range(d)]
+    x1 = orc.ad_explicit_step(T, 0.5, bc, 0.01, 0.3, a=a, scheme=0)
+    x2 = orc.ad_scalar_step(T, 0.5, bc, 0.01, 0.3, a=a)
+    assert np.max(np.abs(x1 - x2)) < 1e-13
