@@ -375,13 +375,42 @@ def leg_ad(B, inputs, steps, warmup):
     return dict(workload="ad_implicit_dirichlet_upwind_C50_nu_dt100_gaussian_tol1e-10_fp64", **out)
 
 
+def leg_explicit(B, inputs, steps, warmup):
+    """Explicit advection-diffusion step with the paper's filter families (Section 2.1,
+    Appendix A): central, upwind and finite element, on 4096^2 (rotation) and 256^3
+    (divergence-free field), Dirichlet-0.  Throughput in cell-steps/s and the step's
+    algorithmic bytes (predictor: T and a read, T~ and a copy of T written; corrector:
+    the copy, T~ and a read, T written) against HBM peak."""
+    import torch
+    out = {}
+    for name, d, n in (("2d_4096", 2, 4096), ("3d_256", 3, 256)):
+        T, a, h, dt, nu = inputs.explicit_ad_case(d, n)
+        Tg = torch.from_numpy(T).cuda()
+        ag = [torch.from_numpy(c).cuda() for c in a]
+        m = Tg.numel()
+        nbytes = m * (8 * (1 + d + 2) + 8 * (2 + d + 1))  # predictor writes T~ and a copy of T
+        res = {}
+        for sname, scheme in (("central", 0), ("upwind", 1), ("finite_element", 2)):
+            dt_s, _ = timed(lambda: B.np_ad_explicit_step(Tg, h, dt, nu, B.BC_DIRICHLET0, a=ag, scheme=scheme),
+                            steps, warmup)
+            ms = 1e3 * dt_s / steps
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            res[sname] = dict(ms_per_step=ms, cell_steps_per_s=m / (ms * 1e-3), bytes_per_step=nbytes, gbs=gbs,
+                              frac=gbs / HBM_PEAK_GBS)
+            log("  explicit %s %s: %.3f ms/step, %.3g cell-steps/s, %.0f GB/s (%.2f of HBM peak)" % (
+                name, sname, ms, m / (ms * 1e-3), gbs, gbs / HBM_PEAK_GBS))
+        out[name] = res
+        del Tg, ag
+    return dict(workload="explicit_ad_step_dirichlet_gaussian_C0.1_fp64", **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth,ad",
+    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth,ad,explicit",
                     help="other workloads to run after the headline (comma list, '' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -527,6 +556,8 @@ def main():
             others["sawtooth"] = leg_sawtooth(B, inputs, args.steps, args.warmup)
         elif leg == "ad":
             others["ad"] = leg_ad(B, inputs, args.steps, args.warmup)
+        elif leg == "explicit":
+            others["explicit"] = leg_explicit(B, inputs, args.steps, args.warmup)
         else:
             sys.exit("unknown leg %s" % leg)
         B.np_release_all()

@@ -16,7 +16,8 @@
  *  - Boundary conditions are ghost values ("padding", Section 2.1):
  *    NP_BC_DIRICHLET0 sets the ghost to minus the adjacent interior value
  *    (zero on the boundary faces of the cell-centred grid); NP_BC_PERIODIC
- *    wraps.
+ *    wraps; NP_BC_NEUMANN (explicit steps only) copies the adjacent value,
+ *    a zero normal derivative.
  *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null
  *    stream).  Every call returns after its work on that stream is
  *    complete: convergence decisions need the residual norm on the host.
@@ -46,7 +47,7 @@ typedef enum {
     NP_ENOMEM = -5    /* device allocation failed */
 } np_status;
 
-typedef enum { NP_BC_DIRICHLET0 = 0, NP_BC_PERIODIC = 1 } np_bc;
+typedef enum { NP_BC_DIRICHLET0 = 0, NP_BC_PERIODIC = 1, NP_BC_NEUMANN = 2 } np_bc;
 
 /* Storage precision of the smoothing and transfer steps.  NP_FP64: plain
  * FP64 V-cycles.  NP_FP32 / NP_BF16: mixed-precision iterative refinement --
@@ -163,6 +164,23 @@ np_status np_last_autotune(int *inner_cycles, double *ms);
  */
 np_status np_ad_scalar_step(np_dims dims, double h, double *T, const double *const *a, double dt,
                             double nu, np_bc bc, const np_mg_opts *opts);
+
+/*
+ * The same predictor-corrector step with a choice of the paper's filter
+ * families (Section 2.1 and Appendix A): scheme 0 central (as
+ * np_ad_scalar_step); 1 first-order upwind advection, the value taken from
+ * upstream (backward difference for a positive velocity component, forward
+ * for a negative one; the printed upwind filter differences the other way)
+ * with 5-/7-point diffusion; 2 the finite-element filters: 2D 9-point
+ * advection (first difference averaged across the other axis with weights
+ * 1, 4, 1 over 6) and diffusion (16 delta - (1,2,1)x(1,2,1), over 4 h^2); 3D
+ * 27-point advection (weights (1,4,1)x(1,4,1)/36) and diffusion (88, -6, -3,
+ * -2 on centre, faces, edges, corners, over 26 h^2).  bc may also be
+ * NP_BC_NEUMANN: zero normal derivative by copying the adjacent value into
+ * the padding (Section 2.4).  Arguments and errors as np_ad_scalar_step.
+ */
+np_status np_ad_explicit_step(np_dims dims, double h, double *T, const double *const *a, double dt, double nu,
+                              np_bc bc, int scheme, const np_mg_opts *opts);
 
 /* ---------------------------------------------------------------------- */
 /* Implicit advection-diffusion (Section 2.2, the backward-Euler operator of

@@ -108,6 +108,7 @@ _SIGS = {
     "np_ad_implicit_solve": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _D, ctypes.POINTER(NpMgOpts),
                                   ctypes.POINTER(NpMgStats), ctypes.POINTER(_D)]),
     "np_ad_apply": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _P]),
+    "np_ad_explicit_step": (_I, [NpDims, _D, _P, _P, _D, _D, _I, _I, ctypes.POINTER(NpMgOpts)]),
     "np_ad_prof_level": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
 }
 
@@ -334,6 +335,22 @@ def np_cnn_train(rhs, p, weights_out, cfg=None, bc=BC_PERIODIC):
                                             ctypes.cast(pp, ctypes.c_void_p), js.encode(),
                                             weights_out.encode(), hist))
     return list(hist)[:epochs]
+
+
+BC_NEUMANN = 2
+SCHEME_CENTRAL, SCHEME_UPWIND, SCHEME_FE = 0, 1, 2
+
+
+def np_ad_explicit_step(T, h, dt, nu, bc, a=None, scheme=SCHEME_CENTRAL):
+    """One predictor-corrector advection-diffusion step in place, with the chosen filter
+    family (central, upwind, finite element); a: list of collocated velocity tensors."""
+    ap = None
+    if a is not None:
+        ap = (ctypes.c_void_p * 3)(*[_dev(c).value for c in a] + [None] * (3 - len(a)))
+    o = make_opts()
+    _check("np_ad_explicit_step", lib.np_ad_explicit_step(_dims(T), h, _dev(T),
+                                                          ctypes.cast(ap, ctypes.c_void_p) if ap else None, dt,
+                                                          nu, bc, scheme, ctypes.byref(o)))
 
 
 def np_ad_scalar_step(T, h, dt, nu, bc, a=None):

@@ -184,6 +184,123 @@ __global__ __launch_bounds__(kBlock) void k_ad_stage(const double *__restrict__ 
     out[c] = T[c] - dt * R;
 }
 
+// ------------------------------------- explicit step, filter families
+// The filters of Section 2.1 and Appendix A on any n >= 3 (all axes equal):
+// scheme 0 central (3-point first differences, 5-/7-point diffusion), 1
+// first-order upwind advection (the upstream value: backward difference for a
+// positive velocity component) with the same diffusion, 2 the finite-element
+// (bilinear / trilinear) filters: first derivatives averaged across the other
+// axes with weights (1, 4, 1)/6, diffusion 16 delta - (1,2,1)x(1,2,1) over
+// 4 h^2 (2D) or 88 / -6 / -3 / -2 on the centre, faces, edges and corners over
+// 26 h^2 (3D).  Boundary rule bc: 0 Dirichlet-0 (ghost = -value), 1 periodic,
+// 2 zero normal derivative (ghost = value, the copy padding of Section 2.4).
+
+// Index along one axis of the cell q (at most one cell outside [0, n)) and the
+// sign its value takes.
+__device__ __forceinline__ int adx_res(int q, int n, int bc, double &sg) {
+    sg = 1.0;
+    if (q < 0) {
+        if (bc == 1) return n - 1;
+        if (bc == 0) sg = -1.0;
+        return 0;
+    }
+    if (q >= n) {
+        if (bc == 1) return 0;
+        if (bc == 0) sg = -1.0;
+        return n - 1;
+    }
+    return q;
+}
+
+constexpr int kAdxX = 64, kAdxY = 4;  // workgroup: 64 cells along x, 4 rows
+
+// STAGE 0: out = T - dt R(T), and tcopy = T (so that the corrector can write
+// the caller's array); STAGE 1: out = T - dt R((Tt + T)/2).  One thread per
+// cell; the 3^d neighbourhood is gathered with the boundary rule, then every
+// filter of the family reads it.
+template <int D, int SCHEME, int STAGE>
+__global__ __launch_bounds__(kAdxX * kAdxY) void k_adx_stage(const double *__restrict__ T,
+                                                             const double *__restrict__ Tt,
+                                                             double *__restrict__ out, double *__restrict__ tcopy,
+                                                             APtrs ap, int n, int bc, double dt, double nu,
+                                                             double h) {
+    const int i = int(blockIdx.x) * kAdxX + int(threadIdx.x), j = int(blockIdx.y) * kAdxY + int(threadIdx.y);
+    const int k = D == 3 ? int(blockIdx.z) : 0;
+    if (i >= n || j >= n) return;
+    const int64_t nn = n;
+    double v[3][3][3] = {};  // [dz + 1][dy + 1][dx + 1]
+    int ix[3];
+    double sx[3];
+    for (int o = 0; o < 3; ++o) ix[o] = adx_res(i + o - 1, n, bc, sx[o]);
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+        if (D == 2 && dz != 0) continue;
+        double sz = 1.0;
+        const int kk = D == 3 ? adx_res(k + dz, n, bc, sz) : 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            double sy;
+            const int jj = adx_res(j + dy, n, bc, sy);
+            const int64_t row = (int64_t(kk) * nn + jj) * nn;
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (SCHEME != 2 && (dx != 0) + (dy != 0) + (dz != 0) > 1) continue;  // 5/7-point only
+                const int64_t q = row + ix[dx + 1];
+                const double t = STAGE == 0 ? T[q] : 0.5 * (Tt[q] + T[q]);
+                v[dz + 1][dy + 1][dx + 1] = sx[dx + 1] * sy * sz * t;
+            }
+        }
+    }
+    const double v0 = v[1][1][1];
+    const int64_t c = (int64_t(k) * nn + j) * nn + i;
+    double adv = 0.0, dif;
+    if (SCHEME == 2) {
+        const double w[3] = {1.0, 4.0, 1.0};
+        if (D == 2) {
+            const double b[3] = {1.0, 2.0, 1.0};
+            double sm = 0.0, gx = 0.0, gy = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) sm += b[p] * b[q] * v[1][p][q];
+                gx += w[p] * (v[1][p][2] - v[1][p][0]);
+                gy += w[p] * (v[1][2][p] - v[1][0][p]);
+            }
+            dif = (16.0 * v0 - sm) / (4.0 * h * h);
+            if (ap.has) adv = (ap.a[0][c] * gx + ap.a[1][c] * gy) / (12.0 * h);
+        } else {
+            const double cw[4] = {88.0, -6.0, -3.0, -2.0};  // by the number of nonzero offsets
+            double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) sm += cw[(p != 1) + (q != 1) + (r != 1)] * v[p][q][r];
+                    gx += w[p] * w[q] * (v[p][q][2] - v[p][q][0]);
+                    gy += w[p] * w[q] * (v[p][2][q] - v[p][0][q]);
+                    gz += w[p] * w[q] * (v[2][p][q] - v[0][p][q]);
+                }
+            dif = sm / (26.0 * h * h);
+            if (ap.has) adv = (ap.a[0][c] * gx + ap.a[1][c] * gy + ap.a[2][c] * gz) / (72.0 * h);
+        }
+    } else {
+        const double xm[3] = {v[1][1][0], v[1][0][1], v[0][1][1]}, xp[3] = {v[1][1][2], v[1][2][1], v[2][1][1]};
+        double lap = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            lap += (v0 - xm[e]) + (v0 - xp[e]);
+            if (!ap.has) continue;
+            const double ae = ap.a[e][c];
+            if (SCHEME == 0) adv += ae * (xp[e] - xm[e]) / (2.0 * h);
+            else adv += ae >= 0.0 ? ae * (v0 - xm[e]) / h : ae * (xp[e] - v0) / h;
+        }
+        dif = lap / (h * h);
+    }
+    out[c] = T[c] - dt * (adv + nu * dif);
+    if (STAGE == 0) tcopy[c] = T[c];
+}
+
 // ------------------------------------------------------------- workspace
 struct NsWork {
     int d = 0, lg = 0;
@@ -301,6 +418,28 @@ extern "C" np_status ns_projection_step(np_dims dims, double h, double *u, doubl
     return ns_projection_step_io(dims, h, u, v, w, p, dt, nu, bc, tol, opts, stats, nullptr, nullptr);
 }
 
+// Two scratch fields of m cells for the explicit steps (cached per device and size).
+static np_status ad_scratch(int64_t m, double **out) {
+    int dev = 0;
+    NP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ns_mu);
+    auto key = std::make_tuple(dev, m);
+    auto it = g_ad.find(key);
+    if (it != g_ad.end()) {
+        *out = it->second;
+        return NP_OK;
+    }
+    double *scr = nullptr;
+    if (hipMalloc((void **)&scr, sizeof(double) * 2 * m) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc failed");
+        return NP_ENOMEM;
+    }
+    g_ad[key] = scr;
+    *out = scr;
+    return NP_OK;
+}
+
 extern "C" np_status np_ad_scalar_step(np_dims dims, double h, double *T, const double *const *a, double dt,
                                        double nu, np_bc bc, const np_mg_opts *opts) {
     clear_error();
@@ -321,24 +460,8 @@ extern "C" np_status np_ad_scalar_step(np_dims dims, double h, double *T, const 
     }
     hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
     const int64_t m = dims.ndim == 3 ? n * n * n : n * n;
-    int dev = 0;
-    NP_HIP_TRY(hipGetDevice(&dev));
     double *scr = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_ns_mu);
-        auto key = std::make_tuple(dev, m);
-        auto it = g_ad.find(key);
-        if (it == g_ad.end()) {
-            if (hipMalloc((void **)&scr, sizeof(double) * 2 * m) != hipSuccess) {
-                (void)hipGetLastError();
-                set_error("hipMalloc failed");
-                return NP_ENOMEM;
-            }
-            g_ad[key] = scr;
-        } else {
-            scr = it->second;
-        }
-    }
+    NP_TRY(ad_scratch(m, &scr));
     Gen g{n, (int)bc};
     const unsigned nb = blocks_for(m);
     const double inv_2h = 0.5 / h, nu_inv_h2 = nu / (h * h);
@@ -353,6 +476,59 @@ extern "C" np_status np_ad_scalar_step(np_dims dims, double h, double *T, const 
     }
     NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipMemcpyAsync(T, scr + m, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return NP_OK;
+}
+
+extern "C" np_status np_ad_explicit_step(np_dims dims, double h, double *T, const double *const *a, double dt,
+                                         double nu, np_bc bc, int scheme, const np_mg_opts *opts) {
+    clear_error();
+    if (dims.ndim != 2 && dims.ndim != 3) { set_error("ndim must be 2 or 3"); return NP_EINVAL; }
+    const int64_t n = dims.n[0];
+    for (int e = 1; e < dims.ndim; ++e)
+        if (dims.n[e] != n) { set_error("all axes must have the same size"); return NP_EINVAL; }
+    if (n < 3 || n > (dims.ndim == 2 ? 16384 : 1024)) { set_error("n out of range"); return NP_EINVAL; }
+    if (!T || !(h > 0.0) || !(dt > 0.0) || !(nu >= 0.0) || !std::isfinite(h) || !std::isfinite(dt) ||
+        !std::isfinite(nu)) {
+        set_error("bad argument");
+        return NP_EINVAL;
+    }
+    if (bc != NP_BC_DIRICHLET0 && bc != NP_BC_PERIODIC && bc != NP_BC_NEUMANN) { set_error("unknown bc"); return NP_EINVAL; }
+    if (scheme < 0 || scheme > 2) { set_error("scheme must be 0 (central), 1 (upwind) or 2 (finite element)"); return NP_EINVAL; }
+    APtrs ap{{nullptr, nullptr, nullptr}, 0};
+    if (a) {
+        for (int e = 0; e < dims.ndim; ++e) {
+            if (!a[e]) { set_error("null velocity component"); return NP_EINVAL; }
+            ap.a[e] = a[e];
+        }
+        ap.has = 1;
+    }
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    const int64_t m = dims.ndim == 3 ? n * n * n : n * n;
+    double *scr = nullptr;
+    NP_TRY(ad_scratch(m, &scr));
+    const dim3 blk(kAdxX, kAdxY), grd(unsigned((n + kAdxX - 1) / kAdxX), unsigned((n + kAdxY - 1) / kAdxY),
+                                      dims.ndim == 3 ? unsigned(n) : 1u);
+    const int ni = int(n);
+    // predictor: scr = T~, scr + m = T^n; corrector: T = T^n - dt R((T~ + T^n)/2)
+#define NP_ADX(D, S)                                                                                              \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((k_adx_stage<D, S, 0>), grd, blk, 0, s, T, T, scr, scr + m, ap, ni, int(bc), dt, nu,   \
+                           h);                                                                                    \
+        hipLaunchKernelGGL((k_adx_stage<D, S, 1>), grd, blk, 0, s, scr + m, scr, T, nullptr, ap, ni, int(bc), dt, \
+                           nu, h);                                                                                \
+    } while (0)
+    if (dims.ndim == 2) {
+        if (scheme == 0) NP_ADX(2, 0);
+        else if (scheme == 1) NP_ADX(2, 1);
+        else NP_ADX(2, 2);
+    } else {
+        if (scheme == 0) NP_ADX(3, 0);
+        else if (scheme == 1) NP_ADX(3, 1);
+        else NP_ADX(3, 2);
+    }
+#undef NP_ADX
+    NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;
 }

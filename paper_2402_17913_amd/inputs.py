@@ -170,6 +170,27 @@ def gaussian_3d(n=64, gamma=10.0, spacing=1.0):
     return np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / (2 * gamma ** 2))
 
 
+def explicit_ad_case(d, n):
+    """Workload of the explicit advection-diffusion step: on n^d unit cells centred at
+    the origin, a Gaussian of width n/10 offset by n/8 along x, advected by a solid-body
+    rotation (2D: (-y, x) scaled to max speed 1) or by the divergence-free field
+    (sin y cos z, sin z cos x, sin x cos y) on [-pi, pi)^3 (3D, max speed 1); nu = 0.5,
+    dt = 0.1 (Courant number 0.1 as in the paper's explicit test).  Returns (T, a, h,
+    dt, nu)."""
+    h = 1.0
+    x = (np.arange(n) - (n - 1) / 2.0) * h
+    g = np.meshgrid(*([x] * d), indexing="ij")[::-1]  # [X, Y(, Z)], x fastest
+    r2 = (g[0] - n / 8.0) ** 2 + sum(c ** 2 for c in g[1:])
+    T = np.exp(-r2 / (2 * (n / 10.0) ** 2))
+    if d == 2:
+        R = (n - 1) / 2.0
+        a = [-g[1] / R, g[0] / R]
+    else:
+        s = [c * (2 * np.pi / n) for c in g]
+        a = [np.sin(s[1]) * np.cos(s[2]), np.sin(s[2]) * np.cos(s[0]), np.sin(s[0]) * np.cos(s[1])]
+    return T, [np.ascontiguousarray(c) for c in a], h, 0.1, 0.5
+
+
 def batched_sizes(count=512, seed=0, choices=(64, 128, 256, 512, 1024)):
     """Sizes of the batched workload: `count` draws, uniform over `choices`."""
     rng = np.random.default_rng(seed)
