@@ -57,6 +57,10 @@ def lib():
             "or_saw_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _f64, _d, _d, _d, _d, _i64, _p, _p, _p, _d],
             "or_ad_apply": [_p, _i64, _f64, _p, _p],
             "or_ad_explicit_step": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _f64],
+            "or_nsc_derivative": [_d, _i64, _f64, _d, _d, _p, _p],
+            "or_nsc_momentum": [_d, _i64, _f64, _d, _f64, _f64, _p, _p],
+            "or_nsc_project": [_d, _i64, _f64, _d, _f64, _p, _p, _f64, _d, _p, _p],
+            "or_nsc_step": [_d, _i64, _f64, _d, _f64, _f64, _p, _p, _f64, _d, _p],
             "or_ad_explicit_rate": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _p],
             "or_ad_jacobi": [_p, _i64, _f64, _f64, _p, _p, _p],
             "or_ad_vcycle": [_p, _i64, _f64, _d, _d, _f64, _i64, _p, _p],
@@ -69,7 +73,7 @@ def lib():
             fn.restype = _f64 if name == "or_rel_res" else (None if name in (
                 "or_apply_A", "or_residual", "or_jacobi", "or_restrict", "or_prolong_add",
                 "or_divergence", "or_gradient", "or_ns_momentum", "or_prolong_const_add", "or_ad_apply",
-                "or_ad_jacobi") else ctypes.c_int)
+                "or_ad_jacobi", "or_nsc_derivative", "or_nsc_momentum") else ctypes.c_int)
         _lib = L
     return _lib
 
@@ -309,6 +313,57 @@ def ad_explicit_rate(T, h, bc, nu, a=None, scheme=SCHEME_CENTRAL):
         raise ValueError("oracle ad_explicit_rate: invalid arguments")
     del keep
     return R
+
+
+def nsc_derivative(f, h, e, scheme=SCHEME_FE):
+    """D_e f of the collocated step (periodic): the scheme's first-derivative filter."""
+    f = _arr(f)
+    d, n = _grid(f)
+    g = np.empty_like(f)
+    lib().or_nsc_derivative(d, n, h, scheme, e, _ptr(f), _ptr(g))
+    return g
+
+
+def _qptrs(q):
+    q = [_arr(c).copy() for c in q]
+    return q, _ptr_array(q)
+
+
+def nsc_momentum(q, p, h, dt, nu, scheme=SCHEME_FE):
+    """Momentum predictor-corrector of the collocated step; returns q*."""
+    q, (qp, keep) = _qptrs(q)
+    p = _arr(p)
+    d, n = _grid(p)
+    lib().or_nsc_momentum(d, n, h, scheme, dt, nu, qp, _ptr(p))
+    del keep
+    return q
+
+
+def nsc_project(q, p, h, dt, scheme=SCHEME_FE, tol=1e-12, fixed_cycles=0):
+    """Pressure and velocity corrections of the collocated step; returns (q, p, dp, cycles)."""
+    q, (qp, keep) = _qptrs(q)
+    p = _arr(p).copy()
+    d, n = _grid(p)
+    dp = np.empty_like(p)
+    cyc = ctypes.c_int(0)
+    st = lib().or_nsc_project(d, n, h, scheme, dt, qp, _ptr(p), tol, fixed_cycles, ctypes.byref(cyc), _ptr(dp))
+    del keep
+    if st not in (0, -2):
+        raise ValueError("oracle nsc_project failed: %d" % st)
+    return q, p, dp, cyc.value
+
+
+def nsc_step(q, p, h, dt, nu, scheme=SCHEME_FE, tol=1e-12, fixed_cycles=0):
+    """One collocated projection step; returns (q, p, cycles)."""
+    q, (qp, keep) = _qptrs(q)
+    p = _arr(p).copy()
+    d, n = _grid(p)
+    cyc = ctypes.c_int(0)
+    st = lib().or_nsc_step(d, n, h, scheme, dt, nu, qp, _ptr(p), tol, fixed_cycles, ctypes.byref(cyc))
+    del keep
+    if st not in (0, -2):
+        raise ValueError("oracle nsc_step failed: %d" % st)
+    return q, p, cyc.value
 
 
 def ad_scalar_step(T, h, bc, dt, nu, a=None):

@@ -961,3 +961,102 @@ int or_ns_step(int d, i64 n, double h, double *u, double *v, double *w, double *
     free(rhs); free(dp);
     return st;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Projection step on a collocated grid with the paper's own discretisation
+ * choices (Section 2.4: velocity and pressure at the same nodes, the
+ * finite-element filters of Appendix A for the advection and diffusion
+ * terms, the projection algorithm), periodic boundaries.  scheme as in
+ * or_ad_explicit_step (0 central, 1 upwind advection, 2 finite element).
+ * The first derivative D_e of the scheme (the finite-element filter for
+ * scheme 2, the central difference otherwise) gives the pressure gradient
+ * and the divergence; the pressure equation uses the multigrid operator
+ * A = -Lap_h, so D.D differs from -A and the projection is approximate. */
+
+/* g = D_e f (periodic). */
+void or_nsc_derivative(int d, i64 n, double h, int scheme, int e, const double *f, double *g)
+{
+    const i64 nz = d == 3 ? n : 1;
+    const int kz = d == 3 ? 1 : 0;
+    for (i64 k = 0; k < nz; ++k)
+        for (i64 j = 0; j < n; ++j)
+            for (i64 i = 0; i < n; ++i) {
+                const i64 c = (k * n + j) * n + i;
+                double s = 0.0;
+                if (scheme == 2) {
+                    for (int dz = -kz; dz <= kz; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                const double v = ghost_at(f, d, n, OR_BC_PERIODIC, i + dx, j + dy, k + dz);
+                                s += (d == 2 ? fe_w2(FE2_ADV[e], dx, dy) : fe_w3(FE3_ADV[e], dx, dy, dz)) * v;
+                            }
+                    s /= (d == 2 ? 12.0 : 72.0) * h;
+                } else {
+                    const i64 o[3] = {e == 0, e == 1, e == 2};
+                    s = (ghost_at(f, d, n, OR_BC_PERIODIC, i + o[0], j + o[1], k + o[2]) -
+                         ghost_at(f, d, n, OR_BC_PERIODIC, i - o[0], j - o[1], k - o[2])) / (2.0 * h);
+                }
+                g[c] = s;
+            }
+}
+
+/* Momentum predictor-corrector (the projection algorithm's first step,
+ * sigma = 0) on collocated components q_c, advected by the lagged u^n = q^n:
+ *   R_c(w) = sum_e u^n_e D_e w + nu (diffusion filter * w) + D_c p^n,
+ *   q~_c = q^n_c - dt R_c(q^n_c),  q*_c = q^n_c - dt R_c((q~_c + q^n_c)/2),
+ * the advection and diffusion filters those of or_ad_explicit_step. */
+void or_nsc_momentum(int d, i64 n, double h, int scheme, double dt, double nu, double *const *q, const double *p)
+{
+    const i64 m = ncells(d, n);
+    double *qn[3] = {0, 0, 0}, *R = malloc(sizeof(double) * m), *g = malloc(sizeof(double) * m);
+    double *half = malloc(sizeof(double) * m);
+    for (int c = 0; c < d; ++c) {
+        qn[c] = malloc(sizeof(double) * m);
+        memcpy(qn[c], q[c], sizeof(double) * m);
+    }
+    for (int c = 0; c < d; ++c) {
+        or_nsc_derivative(d, n, h, scheme, c, p, g);
+        adx_rate(d, n, h, OR_BC_PERIODIC, scheme, nu, (const double *const *)qn, qn[c], R);
+        for (i64 x = 0; x < m; ++x) half[x] = 0.5 * ((qn[c][x] - dt * (R[x] + g[x])) + qn[c][x]);
+        adx_rate(d, n, h, OR_BC_PERIODIC, scheme, nu, (const double *const *)qn, half, R);
+        for (i64 x = 0; x < m; ++x) q[c][x] = qn[c][x] - dt * (R[x] + g[x]);
+    }
+    for (int c = 0; c < d; ++c) free(qn[c]);
+    free(R); free(g); free(half);
+}
+
+/* The pressure-correction and velocity-correction steps: A dp = -(1/dt)
+ * sum_e D_e q*_e (multigrid, periodic, mean-free), q = q* - dt D dp, p += dp.
+ * dp_out (may be NULL) receives dp. */
+int or_nsc_project(int d, i64 n, double h, int scheme, double dt, double *const *q, double *p, double tol,
+                   int fixed_cycles, int *cycles_out, double *dp_out)
+{
+    const i64 m = ncells(d, n);
+    double *rhs = calloc(m, sizeof(double)), *g = malloc(sizeof(double) * m), *dp = calloc(m, sizeof(double));
+    for (int e = 0; e < d; ++e) {
+        or_nsc_derivative(d, n, h, scheme, e, q[e], g);
+        for (i64 x = 0; x < m; ++x) rhs[x] += g[x];
+    }
+    for (i64 x = 0; x < m; ++x) rhs[x] *= -1.0 / dt;
+    double rr;
+    int st = or_mg_solve(d, n, h, OR_BC_PERIODIC, rhs, dp, tol, 2, 2, 2.0 / 3.0, 200, fixed_cycles, 0, 4,
+                         cycles_out, &rr, NULL, 0);
+    for (int e = 0; e < d; ++e) {
+        or_nsc_derivative(d, n, h, scheme, e, dp, g);
+        for (i64 x = 0; x < m; ++x) q[e][x] -= dt * g[x];
+    }
+    for (i64 x = 0; x < m; ++x) p[x] += dp[x];
+    if (dp_out) memcpy(dp_out, dp, sizeof(double) * m);
+    free(rhs); free(g); free(dp);
+    return st;
+}
+
+/* One collocated projection step: momentum, then the projection. */
+int or_nsc_step(int d, i64 n, double h, int scheme, double dt, double nu, double *const *q, double *p, double tol,
+                int fixed_cycles, int *cycles_out)
+{
+    if ((d != 2 && d != 3) || !is_pow2(n) || n < 4 || !(dt > 0.0) || nu < 0.0 || scheme < 0 || scheme > 2)
+        return OR_EINVAL;
+    or_nsc_momentum(d, n, h, scheme, dt, nu, q, p);
+    return or_nsc_project(d, n, h, scheme, dt, q, p, tol, fixed_cycles, cycles_out, NULL);
+}

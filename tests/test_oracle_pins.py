@@ -981,3 +981,98 @@ def test_explicit_central_is_the_scalar_step(orc, d, bc):
     x1 = orc.ad_explicit_step(T, 0.5, bc, 0.01, 0.3, a=a, scheme=0)
     x2 = orc.ad_scalar_step(T, 0.5, bc, 0.01, 0.3, a=a)
     assert np.max(np.abs(x1 - x2)) < 1e-13
+
+
+# ------------------------------- collocated projection step (Section 2.4 variant)
+def derivative_symbol(d, n, h, scheme, e):
+    """Real s with D_e = i s on periodic Fourier modes: sin(t_e)/h (central); the
+    finite-element derivative averages across the other axes with (1,4,1)/6, whose
+    symbol is (2 + cos t)/3 per axis."""
+    t = 2 * np.pi * np.fft.fftfreq(n)
+    th = np.meshgrid(*([t] * d), indexing="ij")[::-1]  # [tx, ty(, tz)]
+    s = np.sin(th[e]) / h
+    if scheme == 2:
+        for f in range(d):
+            if f != e:
+                s = s * (2 + np.cos(th[f])) / 3
+    return s, th
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_nsc_derivative_symbol(orc, d, n, scheme):
+    h = 0.5
+    f = np.random.default_rng(12).standard_normal((n,) * d)
+    for e in range(d):
+        s, _ = derivative_symbol(d, n, h, scheme, e)
+        g = orc.nsc_derivative(f, h, e, scheme=scheme)
+        assert np.max(np.abs(np.fft.fftn(g) - 1j * s * np.fft.fftn(f))) < 1e-9
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_nsc_projection_divergence_factor(orc, d, n, scheme):
+    """The collocated projection is approximate: on a periodic grid each Fourier mode of
+    the divergence is multiplied by 1 - |s|^2 / lambda_A, with i s_e the symbols of the
+    first-derivative filters and lambda_A that of the multigrid operator -Lap_h (Fourier
+    analysis of A dp = -(1/dt) D.q*, q = q* - dt D dp)."""
+    h, dt = 1.0, 0.1
+    rng = np.random.default_rng(13)
+    q = [rng.standard_normal((n,) * d) for _ in range(d)]
+    qo, _, _, _ = orc.nsc_project(q, np.zeros((n,) * d), h, dt, scheme=scheme, tol=1e-14, fixed_cycles=40)
+    div = lambda v: sum(orc.nsc_derivative(v[e], h, e, scheme=scheme) for e in range(d))
+    s2 = 0.0
+    for e in range(d):
+        se, th = derivative_symbol(d, n, h, scheme, e)
+        s2 = s2 + se ** 2
+    lam = sum((2 - 2 * np.cos(t)) / h ** 2 for t in th)
+    fac = np.where(lam > 0, 1 - s2 / np.where(lam > 0, lam, 1.0), 1.0)
+    before, after = np.fft.fftn(div(q)), np.fft.fftn(div(qo))
+    assert np.max(np.abs(after - fac * before)) < 1e-8 * np.max(np.abs(before))
+    # it never amplifies a mode, and leaves the modes the derivative filters cannot see
+    # (sin t = 0 along every axis, e.g. the checkerboard) untouched
+    assert np.max(fac) <= 1.0 + 1e-15 and np.min(fac) >= -1e-15
+    assert np.max(fac) == 1.0
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_nsc_shear_mode_heun_factor(orc, scheme):
+    """A shear mode u = sin(k y), v = 0 is divergence-free and not advected by itself:
+    the whole step multiplies it by Heun's factor 1 + z + z^2/2 with z = -dt nu
+    (2 - 2 cos(k h))/h^2 (every diffusion family reduces to that on a field constant in x)."""
+    n, h, dt, nu = 16, 1.0, 0.2, 0.7
+    y = np.arange(n) * h
+    kk = 2 * np.pi * 3 / (n * h)
+    u = np.repeat(np.sin(kk * y)[:, None], n, axis=1)
+    q, p, cyc = orc.nsc_step([u, np.zeros((n, n))], np.zeros((n, n)), h, dt, nu, scheme=scheme)
+    z = -dt * nu * (2 - 2 * np.cos(kk * h)) / h ** 2
+    assert np.max(np.abs(q[0] - (1 + z + z * z / 2) * u)) < 1e-13
+    assert np.max(np.abs(q[1])) < 1e-13 and np.max(np.abs(p)) < 1e-13
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_nsc_uniform_flow_is_steady(orc, d, scheme):
+    n = 8
+    # dyadic values: the filters' weighted sums of a constant cancel exactly, so the
+    # divergence is exactly zero (a rounding-level constant would be unreachable for a
+    # periodic pressure solve, whose null space is the constants)
+    q = [np.full((n,) * d, v) for v in (0.5, -0.25, 0.125)[:d]]
+    qo, p, cyc = orc.nsc_step(q, np.zeros((n,) * d), 1.0, 0.1, 0.5, scheme=scheme)
+    for a, b in zip(qo, q):
+        assert np.max(np.abs(a - b)) < 1e-14
+    assert cyc == 0
+
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_nsc_momentum_without_pressure_is_the_explicit_step(orc, d, scheme):
+    """With p = 0 each component's momentum update is the explicit step of that
+    component advected by the lagged velocity (periodic)."""
+    n = 8
+    rng = np.random.default_rng(14)
+    q = [rng.standard_normal((n,) * d) for _ in range(d)]
+    qs = orc.nsc_momentum(q, np.zeros((n,) * d), 0.5, 0.01, 0.3, scheme=scheme)
+    for c in range(d):
+        ref = orc.ad_explicit_step(q[c], 0.5, PER, 0.01, 0.3, a=q, scheme=scheme)
+        assert np.max(np.abs(qs[c] - ref)) < 1e-13
