@@ -404,13 +404,47 @@ def leg_explicit(B, inputs, steps, warmup):
     return dict(workload="explicit_ad_step_dirichlet_gaussian_C0.1_fp64", **out)
 
 
+def leg_collocated(B, inputs, nsteps=20):
+    """The projection step with the paper's collocated nodes and finite-element filters
+    (and the central family for comparison), periodic, from the seeded divergence-free
+    field: 2D 1024^2 and 3D 256^3, nu = 1e-3, pressure increment from zero to 1e-10.
+    Reports time per step, pressure cycles and how much divergence each projection
+    leaves (the approximate projection's signature)."""
+    import torch
+    out = {}
+    for name, d, n, steps in (("2d_1024", 2, 1024, nsteps), ("3d_256", 3, 256, max(2, nsteps // 4))):
+        g = inputs.divfree_velocity(d, n, seed=0)
+        res = {}
+        for sname, scheme in (("finite_element", 2), ("central", 0)):
+            B.np_release_all()
+            q = [torch.from_numpy(c).cuda() for c in g["q"]]
+            p = torch.zeros_like(q[0])
+            w = q[2] if d == 3 else None
+            cyc = []
+            B.ns_collocated_step(q[0], q[1], w, p, g["h"], g["dt"], 1e-3, scheme=scheme, tol=TOL)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, st = B.ns_collocated_step(q[0], q[1], w, p, g["h"], g["dt"], 1e-3, scheme=scheme, tol=TOL)
+                cyc.append(st["cycles"])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[sname] = dict(ms_per_step=1e3 * dt / steps, cell_steps_per_s=q[0].numel() * steps / dt,
+                              mean_cycles=sum(cyc) / len(cyc), steps=steps)
+            log("  collocated %s %s: %.2f ms/step, %.1f cycles/step" % (name, sname, 1e3 * dt / steps,
+                                                                       sum(cyc) / len(cyc)))
+            del q, p, w
+        out[name] = res
+    return dict(workload="ns_collocated_periodic_divfree_seed0_nu1e-3_fp64", **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth,ad,explicit",
+    ap.add_argument("--legs", default="c1,c2,c4,c5,sawtooth,ad,explicit,collocated",
                     help="other workloads to run after the headline (comma list, '' for none)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -558,6 +592,8 @@ def main():
             others["ad"] = leg_ad(B, inputs, args.steps, args.warmup)
         elif leg == "explicit":
             others["explicit"] = leg_explicit(B, inputs, args.steps, args.warmup)
+        elif leg == "collocated":
+            others["collocated"] = leg_collocated(B, inputs)
         else:
             sys.exit("unknown leg %s" % leg)
         B.np_release_all()

@@ -229,6 +229,23 @@ np_status np_ad_apply(np_dims dims, double h, np_bc bc, const np_ad_op *op, cons
 np_status np_ad_prof_level(np_dims dims, double h, np_bc bc, const np_ad_op *op, int kind, const double *f,
                            double *x, double *y, int reps, void *stream, double *avg_ms);
 
+/*
+ * The projection step with the paper's own discretisation choices (Section
+ * 2.4: velocity components and pressure at the same cell centres; the
+ * filter families of np_ad_explicit_step, scheme 0 central, 1 upwind
+ * advection, 2 finite element), periodic: the momentum predictor-corrector
+ * advected by the lagged velocity with the source -D p^n, A dp =
+ * -(1/dt) sum_e D_e q*_e by the multigrid (A = -Lap_h, 5-/7-point), q = q* -
+ * dt D dp, p += dp.  D is the scheme's first-derivative filter (finite
+ * element for scheme 2, central otherwise).  The projection is approximate:
+ * D.D differs from -A, so divergence modes the derivative filters cannot see
+ * (the checkerboard) are not removed.  u, v, w, p: device FP64 n^d (w NULL in
+ * 2D), in place; n a power of two.  opts and stats as mg_poisson_solve
+ * (warm_start must be 0).
+ */
+np_status ns_collocated_step(np_dims dims, double h, double *u, double *v, double *w, double *p, double dt,
+                             double nu, int scheme, double tol, const np_mg_opts *opts, np_mg_stats *stats);
+
 /* ns_projection_step that also copies the pressure-correction right-hand
  * side -(1/dt) D q* and the increment dp it solved for into rhs_out and
  * dp_out (device FP64, n^d each; either may be NULL).  Used to generate

@@ -109,6 +109,8 @@ _SIGS = {
                                   ctypes.POINTER(NpMgStats), ctypes.POINTER(_D)]),
     "np_ad_apply": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _P]),
     "np_ad_explicit_step": (_I, [NpDims, _D, _P, _P, _D, _D, _I, _I, ctypes.POINTER(NpMgOpts)]),
+    "ns_collocated_step": (_I, [NpDims, _D, _P, _P, _P, _P, _D, _D, _I, _D, ctypes.POINTER(NpMgOpts),
+                                ctypes.POINTER(NpMgStats)]),
     "np_ad_prof_level": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
 }
 
@@ -212,6 +214,18 @@ def ns_projection_step(u, v, w, p, h, dt, nu, bc=BC_PERIODIC, tol=1e-10, check=T
                                ctypes.byref(o), ctypes.byref(st))
     if check:
         _check("ns_projection_step", s)
+    return s, st.as_dict()
+
+
+def ns_collocated_step(u, v, w, p, h, dt, nu, scheme=2, tol=1e-10, check=True, **opts):
+    """Collocated projection step with the paper's filter families, in place; returns
+    (status, stats dict)."""
+    o = make_opts(**opts)
+    st = NpMgStats()
+    s = lib.ns_collocated_step(_dims(p), h, _dev(u), _dev(v), _dev(w), _dev(p), dt, nu, scheme, tol,
+                               ctypes.byref(o), ctypes.byref(st))
+    if check:
+        _check("ns_collocated_step", s)
     return s, st.as_dict()
 
 

@@ -214,21 +214,13 @@ __device__ __forceinline__ int adx_res(int q, int n, int bc, double &sg) {
 
 constexpr int kAdxX = 64, kAdxY = 4;  // workgroup: 64 cells along x, 4 rows
 
-// STAGE 0: out = T - dt R(T), and tcopy = T (so that the corrector can write
-// the caller's array); STAGE 1: out = T - dt R((Tt + T)/2).  One thread per
-// cell; the 3^d neighbourhood is gathered with the boundary rule, then every
-// filter of the family reads it.
-template <int D, int SCHEME, int STAGE>
-__global__ __launch_bounds__(kAdxX * kAdxY) void k_adx_stage(const double *__restrict__ T,
-                                                             const double *__restrict__ Tt,
-                                                             double *__restrict__ out, double *__restrict__ tcopy,
-                                                             APtrs ap, int n, int bc, double dt, double nu,
-                                                             double h) {
-    const int i = int(blockIdx.x) * kAdxX + int(threadIdx.x), j = int(blockIdx.y) * kAdxY + int(threadIdx.y);
-    const int k = D == 3 ? int(blockIdx.z) : 0;
-    if (i >= n || j >= n) return;
+// The 3^d neighbourhood v[dz + 1][dy + 1][dx + 1] of cell (i, j, k) of F
+// (HALF: of (F + G)/2) with the boundary rule; the 5/7-point families load
+// the face neighbours only (the other entries stay zero).
+template <int D, int SCHEME, bool HALF>
+__device__ __forceinline__ void adx_gather(const double *__restrict__ F, const double *__restrict__ G, int i, int j,
+                                           int k, int n, int bc, double (&v)[3][3][3]) {
     const int64_t nn = n;
-    double v[3][3][3] = {};  // [dz + 1][dy + 1][dx + 1]
     int ix[3];
     double sx[3];
     for (int o = 0; o < 3; ++o) ix[o] = adx_res(i + o - 1, n, bc, sx[o]);
@@ -246,59 +238,168 @@ __global__ __launch_bounds__(kAdxX * kAdxY) void k_adx_stage(const double *__res
             for (int dx = -1; dx <= 1; ++dx) {
                 if (SCHEME != 2 && (dx != 0) + (dy != 0) + (dz != 0) > 1) continue;  // 5/7-point only
                 const int64_t q = row + ix[dx + 1];
-                const double t = STAGE == 0 ? T[q] : 0.5 * (Tt[q] + T[q]);
+                const double t = HALF ? 0.5 * (G[q] + F[q]) : F[q];
                 v[dz + 1][dy + 1][dx + 1] = sx[dx + 1] * sy * sz * t;
             }
         }
     }
-    const double v0 = v[1][1][1];
-    const int64_t c = (int64_t(k) * nn + j) * nn + i;
-    double adv = 0.0, dif;
+}
+
+// First derivative along axis e of the gathered field: the finite-element
+// filter (scheme 2) or the central difference.
+template <int D, int SCHEME>
+__device__ __forceinline__ double adx_deriv(const double (&v)[3][3][3], int e, double h) {
     if (SCHEME == 2) {
         const double w[3] = {1.0, 4.0, 1.0};
+        double g = 0.0;
+        if (D == 2) {
+#pragma unroll
+            for (int p = 0; p < 3; ++p) g += w[p] * (e == 0 ? v[1][p][2] - v[1][p][0] : v[1][2][p] - v[1][0][p]);
+            return g / (12.0 * h);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                g += w[p] * w[q] *
+                     (e == 0 ? v[p][q][2] - v[p][q][0] : (e == 1 ? v[p][2][q] - v[p][0][q] : v[2][p][q] - v[0][p][q]));
+        return g / (72.0 * h);
+    }
+    const double xm = e == 0 ? v[1][1][0] : (e == 1 ? v[1][0][1] : v[0][1][1]);
+    const double xp = e == 0 ? v[1][1][2] : (e == 1 ? v[1][2][1] : v[2][1][1]);
+    return (xp - xm) / (2.0 * h);
+}
+
+// Advection + diffusion rate of the gathered field, a the velocity at the
+// cell (null: no advection).
+template <int D, int SCHEME>
+__device__ __forceinline__ double adx_rate_at(const double (&v)[3][3][3], const double *a, double nu, double h) {
+    const double v0 = v[1][1][1];
+    double adv = 0.0, dif;
+    if (SCHEME == 2) {
         if (D == 2) {
             const double b[3] = {1.0, 2.0, 1.0};
-            double sm = 0.0, gx = 0.0, gy = 0.0;
-#pragma unroll
-            for (int p = 0; p < 3; ++p) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) sm += b[p] * b[q] * v[1][p][q];
-                gx += w[p] * (v[1][p][2] - v[1][p][0]);
-                gy += w[p] * (v[1][2][p] - v[1][0][p]);
-            }
-            dif = (16.0 * v0 - sm) / (4.0 * h * h);
-            if (ap.has) adv = (ap.a[0][c] * gx + ap.a[1][c] * gy) / (12.0 * h);
-        } else {
-            const double cw[4] = {88.0, -6.0, -3.0, -2.0};  // by the number of nonzero offsets
-            double sm = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+            double sm = 0.0;
 #pragma unroll
             for (int p = 0; p < 3; ++p)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
+                for (int q = 0; q < 3; ++q) sm += b[p] * b[q] * v[1][p][q];
+            dif = (16.0 * v0 - sm) / (4.0 * h * h);
+        } else {
+            const double cw[4] = {88.0, -6.0, -3.0, -2.0};  // by the number of nonzero offsets
+            double sm = 0.0;
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
 #pragma unroll
                     for (int r = 0; r < 3; ++r) sm += cw[(p != 1) + (q != 1) + (r != 1)] * v[p][q][r];
-                    gx += w[p] * w[q] * (v[p][q][2] - v[p][q][0]);
-                    gy += w[p] * w[q] * (v[p][2][q] - v[p][0][q]);
-                    gz += w[p] * w[q] * (v[2][p][q] - v[0][p][q]);
-                }
             dif = sm / (26.0 * h * h);
-            if (ap.has) adv = (ap.a[0][c] * gx + ap.a[1][c] * gy + ap.a[2][c] * gz) / (72.0 * h);
         }
+        if (a)
+#pragma unroll
+            for (int e = 0; e < D; ++e) adv += a[e] * adx_deriv<D, 2>(v, e, h);
     } else {
         const double xm[3] = {v[1][1][0], v[1][0][1], v[0][1][1]}, xp[3] = {v[1][1][2], v[1][2][1], v[2][1][1]};
         double lap = 0.0;
 #pragma unroll
         for (int e = 0; e < D; ++e) {
             lap += (v0 - xm[e]) + (v0 - xp[e]);
-            if (!ap.has) continue;
-            const double ae = ap.a[e][c];
-            if (SCHEME == 0) adv += ae * (xp[e] - xm[e]) / (2.0 * h);
-            else adv += ae >= 0.0 ? ae * (v0 - xm[e]) / h : ae * (xp[e] - v0) / h;
+            if (!a) continue;
+            if (SCHEME == 0) adv += a[e] * (xp[e] - xm[e]) / (2.0 * h);
+            else adv += a[e] >= 0.0 ? a[e] * (v0 - xm[e]) / h : a[e] * (xp[e] - v0) / h;
         }
         dif = lap / (h * h);
     }
-    out[c] = T[c] - dt * (adv + nu * dif);
+    return adv + nu * dif;
+}
+
+// STAGE 0: out = T - dt R(T), and tcopy = T (so that the corrector can write
+// the caller's array); STAGE 1: out = T - dt R((Tt + T)/2).  One thread per
+// cell; the 3^d neighbourhood is gathered with the boundary rule, then every
+// filter of the family reads it.
+template <int D, int SCHEME, int STAGE>
+__global__ __launch_bounds__(kAdxX * kAdxY) void k_adx_stage(const double *__restrict__ T,
+                                                             const double *__restrict__ Tt,
+                                                             double *__restrict__ out, double *__restrict__ tcopy,
+                                                             APtrs ap, int n, int bc, double dt, double nu,
+                                                             double h) {
+    const int i = int(blockIdx.x) * kAdxX + int(threadIdx.x), j = int(blockIdx.y) * kAdxY + int(threadIdx.y);
+    const int k = D == 3 ? int(blockIdx.z) : 0;
+    if (i >= n || j >= n) return;
+    double v[3][3][3] = {};
+    adx_gather<D, SCHEME, STAGE == 1>(T, Tt, i, j, k, n, bc, v);
+    const int64_t c = (int64_t(k) * n + j) * n + i;
+    double a[3] = {0.0, 0.0, 0.0};
+    if (ap.has)
+#pragma unroll
+        for (int e = 0; e < D; ++e) a[e] = ap.a[e][c];
+    out[c] = T[c] - dt * adx_rate_at<D, SCHEME>(v, ap.has ? a : nullptr, nu, h);
     if (STAGE == 0) tcopy[c] = T[c];
+}
+
+// ----------------------------------------- collocated projection step
+// Velocity components and pressure at the same nodes (Section 2.4), periodic.
+// Momentum STAGE 0: out_c = q^n_c - dt (R_c(q^n_c) + D_c p); STAGE 1:
+// out_c = q^n_c - dt (R_c((qt_c + q^n_c)/2) + D_c p); R advects with the
+// lagged velocity q^n at the cell.  All components per thread.
+template <int D, int SCHEME, int STAGE>
+__global__ __launch_bounds__(kAdxX * kAdxY) void k_nsc_stage(Vel qn, Vel qt, double *__restrict__ o0,
+                                                             double *__restrict__ o1, double *__restrict__ o2,
+                                                             const double *__restrict__ p, int n, double dt,
+                                                             double nu, double h) {
+    const int i = int(blockIdx.x) * kAdxX + int(threadIdx.x), j = int(blockIdx.y) * kAdxY + int(threadIdx.y);
+    const int k = D == 3 ? int(blockIdx.z) : 0;
+    if (i >= n || j >= n) return;
+    const int64_t c = (int64_t(k) * n + j) * n + i;
+    double a[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < D; ++e) a[e] = qn.q[e][c];
+    double vp[3][3][3] = {};
+    adx_gather<D, SCHEME, false>(p, nullptr, i, j, k, n, 1, vp);
+    double *out[3] = {o0, o1, o2};
+#pragma unroll
+    for (int comp = 0; comp < D; ++comp) {
+        double v[3][3][3] = {};
+        adx_gather<D, SCHEME, STAGE == 1>(qn.q[comp], qt.q[comp], i, j, k, n, 1, v);
+        const double R = adx_rate_at<D, SCHEME>(v, a, nu, h) + adx_deriv<D, SCHEME>(vp, comp, h);
+        out[comp][c] = a[comp] - dt * R;
+    }
+}
+
+// rhs = scale * sum_e D_e q_e (scale = -1/dt).
+template <int D, int SCHEME>
+__global__ __launch_bounds__(kAdxX * kAdxY) void k_nsc_div(Vel q, double *__restrict__ rhs, int n, double h,
+                                                           double scale) {
+    const int i = int(blockIdx.x) * kAdxX + int(threadIdx.x), j = int(blockIdx.y) * kAdxY + int(threadIdx.y);
+    const int k = D == 3 ? int(blockIdx.z) : 0;
+    if (i >= n || j >= n) return;
+    double s = 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        double v[3][3][3] = {};
+        adx_gather<D, SCHEME, false>(q.q[e], nullptr, i, j, k, n, 1, v);
+        s += adx_deriv<D, SCHEME>(v, e, h);
+    }
+    rhs[(int64_t(k) * n + j) * n + i] = s * scale;
+}
+
+// q_c = qs_c - dt D_c dp; p += dp.
+template <int D, int SCHEME>
+__global__ __launch_bounds__(kAdxX * kAdxY) void k_nsc_correct(Vel qs, double *__restrict__ o0,
+                                                               double *__restrict__ o1, double *__restrict__ o2,
+                                                               double *__restrict__ p, const double *__restrict__ dp,
+                                                               int n, double dt, double h) {
+    const int i = int(blockIdx.x) * kAdxX + int(threadIdx.x), j = int(blockIdx.y) * kAdxY + int(threadIdx.y);
+    const int k = D == 3 ? int(blockIdx.z) : 0;
+    if (i >= n || j >= n) return;
+    const int64_t c = (int64_t(k) * n + j) * n + i;
+    double v[3][3][3] = {};
+    adx_gather<D, SCHEME, false>(dp, nullptr, i, j, k, n, 1, v);
+    double *out[3] = {o0, o1, o2};
+#pragma unroll
+    for (int e = 0; e < D; ++e) out[e][c] = qs.q[e][c] - dt * adx_deriv<D, SCHEME>(v, e, h);
+    p[c] += v[1][1][1];
 }
 
 // ------------------------------------------------------------- workspace
@@ -311,14 +412,16 @@ struct NsWork {
 std::mutex g_ns_mu;
 std::map<std::tuple<int, int, int>, NsWork *> g_ns;
 std::map<std::tuple<int, int64_t>, double *> g_ad;  // (dev, cells) -> 2 scratch fields
+std::map<std::tuple<int, int, int>, NsWork *> g_nsc;  // collocated step: 2*d fields + rhs + dp
 
-np_status ns_work(int d, int lg, NsWork **out) {
+np_status ns_work(int d, int lg, NsWork **out, bool collocated = false) {
     int dev = 0;
     NP_HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_ns_mu);
     auto key = std::make_tuple(dev, d, lg);
-    auto it = g_ns.find(key);
-    if (it != g_ns.end()) { *out = it->second; return NP_OK; }
+    auto &cache = collocated ? g_nsc : g_ns;
+    auto it = cache.find(key);
+    if (it != cache.end()) { *out = it->second; return NP_OK; }
     NsWork *W = new NsWork;
     W->d = d;
     W->lg = lg;
@@ -329,7 +432,7 @@ np_status ns_work(int d, int lg, NsWork **out) {
         set_error("hipMalloc failed for the projection-step workspace");
         return NP_ENOMEM;
     }
-    g_ns[key] = W;
+    cache[key] = W;
     *out = W;
     return NP_OK;
 }
@@ -343,6 +446,11 @@ void release_ns_cache() {
         delete kv.second;
     }
     g_ns.clear();
+    for (auto &kv : g_nsc) {
+        (void)hipFree(kv.second->buf);
+        delete kv.second;
+    }
+    g_nsc.clear();
     for (auto &kv : g_ad) (void)hipFree(kv.second);
     g_ad.clear();
 }
@@ -388,9 +496,71 @@ static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w,
     return st;
 }
 
+// Collocated projection step: momentum (two stages into qt, qs), rhs =
+// -(1/dt) D.qs, the multigrid solve A dp = rhs (periodic), q = qs - dt D dp,
+// p += dp.  Workspace as the staggered step's (own cache).
+template <int D, int SCHEME>
+static np_status nsc_step_impl(int lg, double h, double *u, double *v, double *w, double *p, double dt, double nu,
+                               double tol, const np_mg_opts *opts, np_mg_stats *stats) {
+    NsWork *W = nullptr;
+    NP_TRY(ns_work(D, lg, &W, true));
+    std::lock_guard<std::mutex> lk(W->mu);
+    hipStream_t s = opts ? (hipStream_t)opts->stream : nullptr;
+    const int n = 1 << lg;
+    const int64_t m = int64_t(1) << (D * lg);
+    double *qt[3] = {W->buf, W->buf + m, D == 3 ? W->buf + 2 * m : nullptr};
+    double *qs[3] = {W->buf + D * m, W->buf + (D + 1) * m, D == 3 ? W->buf + (D + 2) * m : nullptr};
+    double *rhs = W->buf + 2 * D * m, *dp = rhs + m;
+    Vel qn{{u, v, w}}, vt{{qt[0], qt[1], qt[2]}}, vs{{qs[0], qs[1], qs[2]}};
+    const dim3 blk(kAdxX, kAdxY), grd(unsigned((n + kAdxX - 1) / kAdxX), unsigned((n + kAdxY - 1) / kAdxY),
+                                      D == 3 ? unsigned(n) : 1u);
+    hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 0>), grd, blk, 0, s, qn, vt, qt[0], qt[1], qt[2], p, n, dt, nu, h);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 1>), grd, blk, 0, s, qn, vt, qs[0], qs[1], qs[2], p, n, dt, nu, h);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_nsc_div<D, SCHEME>), grd, blk, 0, s, vs, rhs, n, h, -1.0 / dt);
+    NP_LAUNCH_CHECK();
+    np_mg_opts o;
+    np_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.warm_start != 0) {
+        set_error("the collocated step solves the pressure increment from zero (warm_start 0)");
+        return NP_EINVAL;
+    }
+    np_dims dims{D, {int64_t(n), int64_t(n), D == 3 ? int64_t(n) : 1}};
+    np_status st = poisson_solve(dims, h, NP_BC_PERIODIC, rhs, dp, tol, &o, stats);
+    if (st == NP_EINVAL || st == NP_EHIP || st == NP_ENOMEM) return st;
+    hipLaunchKernelGGL((k_nsc_correct<D, SCHEME>), grd, blk, 0, s, vs, u, v, w, p, dp, n, dt, h);
+    NP_LAUNCH_CHECK();
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return st;
+}
+
 }  // namespace np
 
 using namespace np;
+
+extern "C" np_status ns_collocated_step(np_dims dims, double h, double *u, double *v, double *w, double *p,
+                                        double dt, double nu, int scheme, double tol, const np_mg_opts *opts,
+                                        np_mg_stats *stats) {
+    clear_error();
+    const int lg = check_grid(dims);
+    if (lg < 0) return NP_EINVAL;
+    if (!u || !v || !p || (dims.ndim == 3 && !w)) { set_error("null velocity or pressure array"); return NP_EINVAL; }
+    if (!(h > 0.0) || !(dt > 0.0) || !(nu >= 0.0) || !std::isfinite(h) || !std::isfinite(dt) || !std::isfinite(nu)) {
+        set_error("h, dt must be positive and nu non-negative");
+        return NP_EINVAL;
+    }
+    if (scheme < 0 || scheme > 2) { set_error("scheme must be 0 (central), 1 (upwind) or 2 (finite element)"); return NP_EINVAL; }
+    if (dims.ndim == 2) {
+        if (scheme == 0) return nsc_step_impl<2, 0>(lg, h, u, v, nullptr, p, dt, nu, tol, opts, stats);
+        if (scheme == 1) return nsc_step_impl<2, 1>(lg, h, u, v, nullptr, p, dt, nu, tol, opts, stats);
+        return nsc_step_impl<2, 2>(lg, h, u, v, nullptr, p, dt, nu, tol, opts, stats);
+    }
+    if (scheme == 0) return nsc_step_impl<3, 0>(lg, h, u, v, w, p, dt, nu, tol, opts, stats);
+    if (scheme == 1) return nsc_step_impl<3, 1>(lg, h, u, v, w, p, dt, nu, tol, opts, stats);
+    return nsc_step_impl<3, 2>(lg, h, u, v, w, p, dt, nu, tol, opts, stats);
+}
 
 extern "C" np_status ns_projection_step_io(np_dims dims, double h, double *u, double *v, double *w, double *p,
                                            double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
