@@ -421,6 +421,14 @@ def leg_collocated(B, inputs, nsteps=20):
             p = torch.zeros_like(q[0])
             w = q[2] if d == 3 else None
             cyc = []
+            div = torch.zeros_like(p)
+
+            def div_rms():  # rms of the scheme's divergence, in units of (velocity rms / h)
+                B.np_nsc_divergence(q[0], q[1], w, div, g["h"], scheme=scheme)
+                vel = sum(float(c.square().mean()) for c in q) ** 0.5
+                return float(div.square().mean()) ** 0.5 * g["h"] / vel
+
+            div0 = div_rms()
             B.ns_collocated_step(q[0], q[1], w, p, g["h"], g["dt"], 1e-3, scheme=scheme, tol=TOL)  # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -430,10 +438,11 @@ def leg_collocated(B, inputs, nsteps=20):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             res[sname] = dict(ms_per_step=1e3 * dt / steps, cell_steps_per_s=q[0].numel() * steps / dt,
-                              mean_cycles=sum(cyc) / len(cyc), steps=steps)
-            log("  collocated %s %s: %.2f ms/step, %.1f cycles/step" % (name, sname, 1e3 * dt / steps,
-                                                                       sum(cyc) / len(cyc)))
-            del q, p, w
+                              mean_cycles=sum(cyc) / len(cyc), steps=steps + 1,
+                              divergence_rms_scaled=[div0, div_rms()])
+            log("  collocated %s %s: %.2f ms/step, %.1f cycles/step, divergence rms (x h / |q|) %.2e -> %.2e" % (
+                name, sname, 1e3 * dt / steps, sum(cyc) / len(cyc), *res[sname]["divergence_rms_scaled"]))
+            del q, p, w, div
         out[name] = res
     return dict(workload="ns_collocated_periodic_divfree_seed0_nu1e-3_fp64", **out)
 

@@ -246,6 +246,12 @@ np_status np_ad_prof_level(np_dims dims, double h, np_bc bc, const np_ad_op *op,
 np_status ns_collocated_step(np_dims dims, double h, double *u, double *v, double *w, double *p, double dt,
                              double nu, int scheme, double tol, const np_mg_opts *opts, np_mg_stats *stats);
 
+/* div = sum_e D_e q_e with the first-derivative filter of ns_collocated_step's
+ * scheme (finite element for 2, central otherwise), periodic; device FP64
+ * n^d arrays (w NULL in 2D); synchronises the stream. */
+np_status np_nsc_divergence(np_dims dims, double h, const double *u, const double *v, const double *w, int scheme,
+                            double *div, void *stream);
+
 /* ns_projection_step that also copies the pressure-correction right-hand
  * side -(1/dt) D q* and the increment dp it solved for into rhs_out and
  * dp_out (device FP64, n^d each; either may be NULL).  Used to generate

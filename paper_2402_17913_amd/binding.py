@@ -111,6 +111,7 @@ _SIGS = {
     "np_ad_explicit_step": (_I, [NpDims, _D, _P, _P, _D, _D, _I, _I, ctypes.POINTER(NpMgOpts)]),
     "ns_collocated_step": (_I, [NpDims, _D, _P, _P, _P, _P, _D, _D, _I, _D, ctypes.POINTER(NpMgOpts),
                                 ctypes.POINTER(NpMgStats)]),
+    "np_nsc_divergence": (_I, [NpDims, _D, _P, _P, _P, _I, _P, _P]),
     "np_ad_prof_level": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
 }
 
@@ -227,6 +228,12 @@ def ns_collocated_step(u, v, w, p, h, dt, nu, scheme=2, tol=1e-10, check=True, *
     if check:
         _check("ns_collocated_step", s)
     return s, st.as_dict()
+
+
+def np_nsc_divergence(u, v, w, div, h, scheme=2):
+    """div = D.q with the collocated step's first-derivative filter (periodic)."""
+    _check("np_nsc_divergence", lib.np_nsc_divergence(_dims(u), h, _dev(u), _dev(v), _dev(w), scheme, _dev(div),
+                                                      _stream()))
 
 
 def ns_projection_step_io(u, v, w, p, h, dt, nu, rhs_out=None, dp_out=None, bc=BC_PERIODIC, tol=1e-10,

@@ -562,6 +562,30 @@ extern "C" np_status ns_collocated_step(np_dims dims, double h, double *u, doubl
     return nsc_step_impl<3, 2>(lg, h, u, v, w, p, dt, nu, tol, opts, stats);
 }
 
+extern "C" np_status np_nsc_divergence(np_dims dims, double h, const double *u, const double *v, const double *w,
+                                       int scheme, double *div, void *stream) {
+    clear_error();
+    const int lg = check_grid(dims);
+    if (lg < 0) return NP_EINVAL;
+    if (!u || !v || !div || (dims.ndim == 3 && !w) || !(h > 0.0)) { set_error("bad argument"); return NP_EINVAL; }
+    if (scheme < 0 || scheme > 2) { set_error("scheme must be 0, 1 or 2"); return NP_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    const int n = 1 << lg;
+    Vel q{{u, v, w}};
+    const dim3 blk(kAdxX, kAdxY), grd(unsigned((n + kAdxX - 1) / kAdxX), unsigned((n + kAdxY - 1) / kAdxY),
+                                      dims.ndim == 3 ? unsigned(n) : 1u);
+    if (dims.ndim == 2) {
+        if (scheme == 2) hipLaunchKernelGGL((k_nsc_div<2, 2>), grd, blk, 0, s, q, div, n, h, 1.0);
+        else hipLaunchKernelGGL((k_nsc_div<2, 0>), grd, blk, 0, s, q, div, n, h, 1.0);
+    } else {
+        if (scheme == 2) hipLaunchKernelGGL((k_nsc_div<3, 2>), grd, blk, 0, s, q, div, n, h, 1.0);
+        else hipLaunchKernelGGL((k_nsc_div<3, 0>), grd, blk, 0, s, q, div, n, h, 1.0);
+    }
+    NP_LAUNCH_CHECK();
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return NP_OK;
+}
+
 extern "C" np_status ns_projection_step_io(np_dims dims, double h, double *u, double *v, double *w, double *p,
                                            double dt, double nu, np_bc bc, double tol, const np_mg_opts *opts,
                                            np_mg_stats *stats, double *rhs_out, double *dp_out) {

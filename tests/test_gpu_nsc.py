@@ -95,3 +95,14 @@ def test_collocated_argument_checks(B):
         with pytest.raises(B.NeuphysError):
             B.ns_collocated_step(a, a.clone(), None, a.clone(), 1.0, args["dt"], 0.1, scheme=args["scheme"],
                                  warm_start=ws)
+
+
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_collocated_divergence_entry(B, orc, d, n, scheme):
+    q0, _, h, _ = case(d, n, 9)
+    q = [dev(c) for c in q0]
+    div = dev(np.zeros((n,) * d))
+    B.np_nsc_divergence(q[0], q[1], q[2] if d == 3 else None, div, h, scheme=scheme)
+    ref = sum(orc.nsc_derivative(q0[e], h, e, scheme=scheme) for e in range(d))
+    assert rel(host(div), ref) < 1e-12
