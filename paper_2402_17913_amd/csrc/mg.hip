@@ -1112,6 +1112,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
+        {"zmarch_explicit", &g_zmarch_explicit, 0, 1},
     };
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
@@ -1150,6 +1151,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "zero2")) return g_tune.zero2;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
+    if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
     return -1;
 }
 

@@ -135,5 +135,6 @@ void release_ns_cache();
 void release_batched_cache();
 extern int g_batched_graphs;
 extern int g_batched_autotune;
+extern int g_zmarch_explicit;
 
 }  // namespace np

@@ -271,9 +271,10 @@ __device__ __forceinline__ double adx_deriv(const double (&v)[3][3][3], int e, d
 }
 
 // Advection + diffusion rate of the gathered field, a the velocity at the
-// cell (null: no advection).
+// cell (used when has_a).
 template <int D, int SCHEME>
-__device__ __forceinline__ double adx_rate_at(const double (&v)[3][3][3], const double *a, double nu, double h) {
+__device__ __forceinline__ double adx_rate_at(const double (&v)[3][3][3], const double (&a)[3], bool has_a, double nu,
+                                              double h) {
     const double v0 = v[1][1][1];
     double adv = 0.0, dif;
     if (SCHEME == 2) {
@@ -296,7 +297,7 @@ __device__ __forceinline__ double adx_rate_at(const double (&v)[3][3][3], const 
                     for (int r = 0; r < 3; ++r) sm += cw[(p != 1) + (q != 1) + (r != 1)] * v[p][q][r];
             dif = sm / (26.0 * h * h);
         }
-        if (a)
+        if (has_a)
 #pragma unroll
             for (int e = 0; e < D; ++e) adv += a[e] * adx_deriv<D, 2>(v, e, h);
     } else {
@@ -305,7 +306,7 @@ __device__ __forceinline__ double adx_rate_at(const double (&v)[3][3][3], const 
 #pragma unroll
         for (int e = 0; e < D; ++e) {
             lap += (v0 - xm[e]) + (v0 - xp[e]);
-            if (!a) continue;
+            if (!has_a) continue;
             if (SCHEME == 0) adv += a[e] * (xp[e] - xm[e]) / (2.0 * h);
             else adv += a[e] >= 0.0 ? a[e] * (v0 - xm[e]) / h : a[e] * (xp[e] - v0) / h;
         }
@@ -334,8 +335,109 @@ __global__ __launch_bounds__(kAdxX * kAdxY) void k_adx_stage(const double *__res
     if (ap.has)
 #pragma unroll
         for (int e = 0; e < D; ++e) a[e] = ap.a[e][c];
-    out[c] = T[c] - dt * adx_rate_at<D, SCHEME>(v, ap.has ? a : nullptr, nu, h);
+    out[c] = T[c] - dt * adx_rate_at<D, SCHEME>(v, a, ap.has != 0, nu, h);
     if (STAGE == 0) tcopy[c] = T[c];
+}
+
+// 3D levels on z-marching tiles: a workgroup of kZx x kZy threads owns a
+// kZx x kZy column tile and zc planes; planes z - 1, z, z + 1 of the stage
+// input (with its halo ring, ghost rule applied) sit in a ring of three LDS
+// buffers, and each thread loads its share of plane z + 2 into registers
+// before computing plane z.  Every filter family reads its 3^3 (or 7-point)
+// neighbourhood from LDS; the velocity is read per cell.  Any n >= 3.
+constexpr int kZx = 64, kZy = 8, kZt = kZx * kZy;
+}  // namespace
+int g_zmarch_explicit = 1;  // tuning knob "zmarch_explicit"
+namespace {
+constexpr int kZslots = (kZx + 2) * (kZy + 2);
+constexpr int kZper = (kZslots + kZt - 1) / kZt;  // plane values loaded per thread
+
+template <int SCHEME, int STAGE>
+__global__ __launch_bounds__(kZt) void k_adx_stage3z(const double *__restrict__ T, const double *__restrict__ Tt,
+                                                     double *__restrict__ out, double *__restrict__ tcopy, APtrs ap,
+                                                     int n, int bc, int zc, double dt, double nu, double h) {
+    __shared__ double pl[3][kZy + 2][kZx + 2];
+    const int tx = int(threadIdx.x) % kZx, ty = int(threadIdx.x) / kZx;
+    const int ntx = (n + kZx - 1) / kZx, nty = (n + kZy - 1) / kZy;
+    const int blk = int(blockIdx.x);
+    const int x0 = (blk % ntx) * kZx, y0 = ((blk / ntx) % nty) * kZy, z0 = (blk / (ntx * nty)) * zc;
+    const int z1 = min(z0 + zc, n);
+    const int64_t nn = n, P = nn * nn;
+    // this thread's plane slots: offset within a plane (ghost rule along x, y) and sign
+    int64_t off[kZper];
+    double sg[kZper];
+    int ly[kZper], lx[kZper];
+    bool own[kZper];
+#pragma unroll
+    for (int r = 0; r < kZper; ++r) {
+        const int sidx = int(threadIdx.x) + r * kZt;
+        own[r] = sidx < kZslots;
+        const int t = own[r] ? sidx : 0;
+        ly[r] = t / (kZx + 2);
+        lx[r] = t % (kZx + 2);
+        double s1, s2;
+        const int gi = adx_res(min(x0 + lx[r] - 1, n), n, bc, s1);
+        const int gj = adx_res(min(y0 + ly[r] - 1, n), n, bc, s2);
+        off[r] = int64_t(gj) * nn + gi;
+        sg[r] = s1 * s2;
+    }
+    auto load = [&](int z, double (&val)[kZper]) {
+        double sz;
+        const int64_t kk = adx_res(z, n, bc, sz);
+#pragma unroll
+        for (int r = 0; r < kZper; ++r) {
+            const int64_t q = kk * P + off[r];
+            const double t = STAGE == 0 ? T[q] : 0.5 * (Tt[q] + T[q]);
+            val[r] = sz * sg[r] * t;
+        }
+    };
+    auto store = [&](int slot, const double (&val)[kZper]) {
+#pragma unroll
+        for (int r = 0; r < kZper; ++r)
+            if (own[r]) pl[slot][ly[r]][lx[r]] = val[r];
+    };
+    double nx[kZper];
+    load(z0 - 1, nx);
+    store((z0 + 2) % 3, nx);
+    load(z0, nx);
+    store(z0 % 3, nx);
+    load(z0 + 1, nx);
+    const int i = x0 + tx, j = y0 + ty;
+    for (int z = z0; z < z1; ++z) {
+        store((z + 1) % 3, nx);  // plane z + 1
+        __syncthreads();
+        if (z + 2 < z1 + 1) load(z + 2, nx);  // the next iteration's plane z + 2, in flight during the compute
+        if (i < n && j < n) {
+            double v[3][3][3] = {};
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int sl = (z + dz + 3) % 3;
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (SCHEME != 2 && (dx != 0) + (dy != 0) + (dz != 0) > 1) continue;
+                        v[dz + 1][dy + 1][dx + 1] = pl[sl][ty + 1 + dy][tx + 1 + dx];
+                    }
+            }
+            const int64_t c = int64_t(z) * P + int64_t(j) * nn + i;
+            double a[3] = {0.0, 0.0, 0.0};
+            if (ap.has)
+#pragma unroll
+                for (int e = 0; e < 3; ++e) a[e] = ap.a[e][c];
+            const double tc = T[c];
+            out[c] = tc - dt * adx_rate_at<3, SCHEME>(v, a, ap.has != 0, nu, h);
+            if (STAGE == 0) tcopy[c] = tc;
+        }
+        __syncthreads();  // every read of the oldest buffer is done before it takes plane z + 2
+    }
+}
+
+inline int adx_planes(int n) {
+    const int64_t tiles = int64_t((n + kZx - 1) / kZx) * ((n + kZy - 1) / kZy);
+    int zc = 32;
+    while (zc > 4 && tiles * ((n + zc - 1) / zc) < 2048) zc >>= 1;
+    return zc;
 }
 
 // ----------------------------------------- collocated projection step
@@ -362,7 +464,7 @@ __global__ __launch_bounds__(kAdxX * kAdxY) void k_nsc_stage(Vel qn, Vel qt, dou
     for (int comp = 0; comp < D; ++comp) {
         double v[3][3][3] = {};
         adx_gather<D, SCHEME, STAGE == 1>(qn.q[comp], qt.q[comp], i, j, k, n, 1, v);
-        const double R = adx_rate_at<D, SCHEME>(v, a, nu, h) + adx_deriv<D, SCHEME>(vp, comp, h);
+        const double R = adx_rate_at<D, SCHEME>(v, a, true, nu, h) + adx_deriv<D, SCHEME>(vp, comp, h);
         out[comp][c] = a[comp] - dt * R;
     }
 }
@@ -712,16 +814,31 @@ extern "C" np_status np_ad_explicit_step(np_dims dims, double h, double *T, cons
         hipLaunchKernelGGL((k_adx_stage<D, S, 1>), grd, blk, 0, s, scr + m, scr, T, nullptr, ap, ni, int(bc), dt, \
                            nu, h);                                                                                \
     } while (0)
+    // 3D: z-marching tiles (three LDS planes) from 32^3 up
+    const int zc = adx_planes(ni);
+    const unsigned nz3 = unsigned(((ni + kZx - 1) / kZx) * ((ni + kZy - 1) / kZy) * ((ni + zc - 1) / zc));
+#define NP_ADX3(S)                                                                                                \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((k_adx_stage3z<S, 0>), dim3(nz3), dim3(kZt), 0, s, T, T, scr, scr + m, ap, ni, int(bc), \
+                           zc, dt, nu, h);                                                                        \
+        hipLaunchKernelGGL((k_adx_stage3z<S, 1>), dim3(nz3), dim3(kZt), 0, s, scr + m, scr, T, nullptr, ap, ni,   \
+                           int(bc), zc, dt, nu, h);                                                               \
+    } while (0)
     if (dims.ndim == 2) {
         if (scheme == 0) NP_ADX(2, 0);
         else if (scheme == 1) NP_ADX(2, 1);
         else NP_ADX(2, 2);
+    } else if (ni >= 32 && g_zmarch_explicit) {
+        if (scheme == 0) NP_ADX3(0);
+        else if (scheme == 1) NP_ADX3(1);
+        else NP_ADX3(2);
     } else {
         if (scheme == 0) NP_ADX(3, 0);
         else if (scheme == 1) NP_ADX(3, 1);
         else NP_ADX(3, 2);
     }
 #undef NP_ADX
+#undef NP_ADX3
     NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipStreamSynchronize(s));
     return NP_OK;

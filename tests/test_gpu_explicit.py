@@ -99,3 +99,23 @@ def test_explicit_argument_checks(B):
             B.np_ad_explicit_step(T, args["h"], args["dt"], args["nu"], args["bc"], scheme=args["scheme"])
     with pytest.raises(B.NeuphysError):  # the copy padding is for the explicit steps only
         B.mg_poisson_solve(T, T.clone(), 1.0 / 16, NEU)
+
+
+@pytest.mark.parametrize("n", [32, 70, 128])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_explicit_zmarch_matches_per_cell_kernel(B, n, scheme):
+    """The 3D z-marching kernel (three LDS planes, partial tiles when n is not a multiple
+    of the tile) gives the per-cell kernel's result bit for bit (same neighbourhood, same
+    arithmetic), for every boundary rule."""
+    T, a, h, dt, nu = inputs.explicit_ad_case(3, n)
+    outs = []
+    for bc in (DIR, PER, NEU):
+        for zm in (1, 0):
+            B.np_set_tuning("zmarch_explicit", zm)
+            try:
+                Tg = dev(T)
+                B.np_ad_explicit_step(Tg, h, dt, nu, bc, a=[dev(c) for c in a], scheme=scheme)
+                outs.append(host(Tg))
+            finally:
+                B.np_set_tuning("zmarch_explicit", 1)
+        assert np.array_equal(outs[-2], outs[-1])
