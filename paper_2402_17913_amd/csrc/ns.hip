@@ -352,75 +352,114 @@ namespace {
 constexpr int kZslots = (kZx + 2) * (kZy + 2);
 constexpr int kZper = (kZslots + kZt - 1) / kZt;  // plane values loaded per thread
 
-template <int SCHEME, int STAGE>
-__global__ __launch_bounds__(kZt) void k_adx_stage3z(const double *__restrict__ T, const double *__restrict__ Tt,
-                                                     double *__restrict__ out, double *__restrict__ tcopy, APtrs ap,
-                                                     int n, int bc, int zc, double dt, double nu, double h) {
-    __shared__ double pl[3][kZy + 2][kZx + 2];
-    const int tx = int(threadIdx.x) % kZx, ty = int(threadIdx.x) / kZx;
-    const int ntx = (n + kZx - 1) / kZx, nty = (n + kZy - 1) / kZy;
-    const int blk = int(blockIdx.x);
-    const int x0 = (blk % ntx) * kZx, y0 = ((blk / ntx) % nty) * kZy, z0 = (blk / (ntx * nty)) * zc;
-    const int z1 = min(z0 + zc, n);
-    const int64_t nn = n, P = nn * nn;
-    // this thread's plane slots: offset within a plane (ghost rule along x, y) and sign
+// Plane ring of NF fields on a z-marching tile: each thread owns kZper slots
+// of the (kZx + 2) x (kZy + 2) plane (the tile and its halo ring, ghost rule
+// along x and y applied through the slot's source offset and sign).
+template <int NF>
+struct ZRing {
+    typedef double Plane[3][kZy + 2][kZx + 2];
+    int tx, ty, x0, y0, z0, z1, n, bc;
+    int64_t P;
     int64_t off[kZper];
     double sg[kZper];
     int ly[kZper], lx[kZper];
     bool own[kZper];
+    double nx[NF][kZper];  // plane z + 1 (then z + 2) in flight
+    __device__ ZRing(int n_, int bc_, int zc) : n(n_), bc(bc_) {
+        tx = int(threadIdx.x) % kZx;
+        ty = int(threadIdx.x) / kZx;
+        const int ntx = (n + kZx - 1) / kZx, nty = (n + kZy - 1) / kZy;
+        const int blk = int(blockIdx.x);
+        x0 = (blk % ntx) * kZx;
+        y0 = ((blk / ntx) % nty) * kZy;
+        z0 = (blk / (ntx * nty)) * zc;
+        z1 = min(z0 + zc, n);
+        P = int64_t(n) * n;
 #pragma unroll
-    for (int r = 0; r < kZper; ++r) {
-        const int sidx = int(threadIdx.x) + r * kZt;
-        own[r] = sidx < kZslots;
-        const int t = own[r] ? sidx : 0;
-        ly[r] = t / (kZx + 2);
-        lx[r] = t % (kZx + 2);
-        double s1, s2;
-        const int gi = adx_res(min(x0 + lx[r] - 1, n), n, bc, s1);
-        const int gj = adx_res(min(y0 + ly[r] - 1, n), n, bc, s2);
-        off[r] = int64_t(gj) * nn + gi;
-        sg[r] = s1 * s2;
+        for (int r = 0; r < kZper; ++r) {
+            const int sidx = int(threadIdx.x) + r * kZt;
+            own[r] = sidx < kZslots;
+            const int t = own[r] ? sidx : 0;
+            ly[r] = t / (kZx + 2);
+            lx[r] = t % (kZx + 2);
+            double s1, s2;
+            const int gi = adx_res(min(x0 + lx[r] - 1, n), n, bc, s1);
+            const int gj = adx_res(min(y0 + ly[r] - 1, n), n, bc, s2);
+            off[r] = int64_t(gj) * n + gi;
+            sg[r] = s1 * s2;
+        }
     }
-    auto load = [&](int z, double (&val)[kZper]) {
+    // load plane z of every field into nx; ld(f, q) is field f at index q
+    template <class LD>
+    __device__ __forceinline__ void load(const LD &ld, int z) {
         double sz;
         const int64_t kk = adx_res(z, n, bc, sz);
 #pragma unroll
-        for (int r = 0; r < kZper; ++r) {
-            const int64_t q = kk * P + off[r];
-            const double t = STAGE == 0 ? T[q] : 0.5 * (Tt[q] + T[q]);
-            val[r] = sz * sg[r] * t;
-        }
-    };
-    auto store = [&](int slot, const double (&val)[kZper]) {
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int r = 0; r < kZper; ++r)
-            if (own[r]) pl[slot][ly[r]][lx[r]] = val[r];
-    };
-    double nx[kZper];
-    load(z0 - 1, nx);
-    store((z0 + 2) % 3, nx);
-    load(z0, nx);
-    store(z0 % 3, nx);
-    load(z0 + 1, nx);
-    const int i = x0 + tx, j = y0 + ty;
-    for (int z = z0; z < z1; ++z) {
-        store((z + 1) % 3, nx);  // plane z + 1
-        __syncthreads();
-        if (z + 2 < z1 + 1) load(z + 2, nx);  // the next iteration's plane z + 2, in flight during the compute
+            for (int r = 0; r < kZper; ++r) nx[f][r] = sz * sg[r] * ld(f, kk * P + off[r]);
+    }
+    __device__ __forceinline__ void store(Plane *pl, int z) {
+        const int slot = (z + 3) % 3;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int r = 0; r < kZper; ++r)
+                if (own[r]) pl[f][slot][ly[r]][lx[r]] = nx[f][r];
+    }
+    // planes z0 - 1, z0 into LDS, plane z0 + 1 in flight
+    template <class LD>
+    __device__ __forceinline__ void start(const LD &ld, Plane *pl) {
+        load(ld, z0 - 1);
+        store(pl, z0 - 1);
+        load(ld, z0);
+        store(pl, z0);
+        load(ld, z0 + 1);
+    }
+    // The marching loop: plane z + 1 is stored, then plane z + 2 is issued
+    // before body(z) computes plane z; two barriers per plane (the store is
+    // visible; every read of the oldest buffer is done before it is overwritten).
+    template <class LD, class BODY>
+    __device__ __forceinline__ void march(const LD &ld, Plane *pl, const BODY &body) {
+        start(ld, pl);
+        for (int z = z0; z < z1; ++z) {
+            store(pl, z + 1);
+            __syncthreads();
+            if (z + 2 <= z1) load(ld, z + 2);
+            body(z);
+            __syncthreads();
+        }
+    }
+    // the thread's 3^3 (SCHEME != 2: 7-point) neighbourhood of field f at plane z
+    template <int SCHEME>
+    __device__ __forceinline__ void gather(const Plane &pf, int z, double (&v)[3][3][3]) const {
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int sl = (z + dz + 3) % 3;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (SCHEME != 2 && (dx != 0) + (dy != 0) + (dz != 0) > 1) continue;
+                    v[dz + 1][dy + 1][dx + 1] = pf[sl][ty + 1 + dy][tx + 1 + dx];
+                }
+        }
+    }
+};
+
+template <int SCHEME, int STAGE>
+__global__ __launch_bounds__(kZt) void k_adx_stage3z(const double *__restrict__ T, const double *__restrict__ Tt,
+                                                     double *__restrict__ out, double *__restrict__ tcopy, APtrs ap,
+                                                     int n, int bc, int zc, double dt, double nu, double h) {
+    __shared__ ZRing<1>::Plane pl[1];
+    ZRing<1> R(n, bc, zc);
+    auto ld = [&](int, int64_t q) { return STAGE == 0 ? T[q] : 0.5 * (Tt[q] + T[q]); };
+    const int i = R.x0 + R.tx, j = R.y0 + R.ty;
+    R.march(ld, pl, [&](int z) {
         if (i < n && j < n) {
             double v[3][3][3] = {};
-#pragma unroll
-            for (int dz = -1; dz <= 1; ++dz) {
-                const int sl = (z + dz + 3) % 3;
-#pragma unroll
-                for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        if (SCHEME != 2 && (dx != 0) + (dy != 0) + (dz != 0) > 1) continue;
-                        v[dz + 1][dy + 1][dx + 1] = pl[sl][ty + 1 + dy][tx + 1 + dx];
-                    }
-            }
-            const int64_t c = int64_t(z) * P + int64_t(j) * nn + i;
+            R.template gather<SCHEME>(pl[0], z, v);
+            const int64_t c = int64_t(z) * R.P + int64_t(j) * n + i;
             double a[3] = {0.0, 0.0, 0.0};
             if (ap.has)
 #pragma unroll
@@ -429,8 +468,85 @@ __global__ __launch_bounds__(kZt) void k_adx_stage3z(const double *__restrict__ 
             out[c] = tc - dt * adx_rate_at<3, SCHEME>(v, a, ap.has != 0, nu, h);
             if (STAGE == 0) tcopy[c] = tc;
         }
-        __syncthreads();  // every read of the oldest buffer is done before it takes plane z + 2
-    }
+    });
+}
+
+// Collocated momentum stage (as k_nsc_stage) on z-marching tiles: the three
+// components' stage input and the pressure in LDS rings.
+template <int SCHEME, int STAGE>
+__global__ __launch_bounds__(kZt) void k_nsc_stage3z(Vel qn, Vel qt, double *__restrict__ o0, double *__restrict__ o1,
+                                                     double *__restrict__ o2, const double *__restrict__ p, int n,
+                                                     int zc, double dt, double nu, double h) {
+    __shared__ ZRing<4>::Plane pl[4];
+    ZRing<4> R(n, 1, zc);
+    auto ld = [&](int f, int64_t q) {
+        if (f == 3) return p[q];
+        return STAGE == 0 ? qn.q[f][q] : 0.5 * (qt.q[f][q] + qn.q[f][q]);
+    };
+    const int i = R.x0 + R.tx, j = R.y0 + R.ty;
+    double *out[3] = {o0, o1, o2};
+    R.march(ld, pl, [&](int z) {
+        if (i < n && j < n) {
+            const int64_t c = int64_t(z) * R.P + int64_t(j) * n + i;
+            double a[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) a[e] = qn.q[e][c];
+            double vp[3][3][3] = {};
+            R.template gather<SCHEME>(pl[3], z, vp);
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                double v[3][3][3] = {};
+                R.template gather<SCHEME>(pl[comp], z, v);
+                const double Rr = adx_rate_at<3, SCHEME>(v, a, true, nu, h) + adx_deriv<3, SCHEME>(vp, comp, h);
+                out[comp][c] = a[comp] - dt * Rr;
+            }
+        }
+    });
+}
+
+// rhs = scale * sum_e D_e q_e on z-marching tiles.
+template <int SCHEME>
+__global__ __launch_bounds__(kZt) void k_nsc_div3z(Vel q, double *__restrict__ rhs, int n, int zc, double h,
+                                                   double scale) {
+    __shared__ ZRing<3>::Plane pl[3];
+    ZRing<3> R(n, 1, zc);
+    auto ld = [&](int f, int64_t x) { return q.q[f][x]; };
+    const int i = R.x0 + R.tx, j = R.y0 + R.ty;
+    R.march(ld, pl, [&](int z) {
+        if (i < n && j < n) {
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                double v[3][3][3] = {};
+                R.template gather<SCHEME>(pl[e], z, v);
+                s += adx_deriv<3, SCHEME>(v, e, h);
+            }
+            rhs[int64_t(z) * R.P + int64_t(j) * n + i] = s * scale;
+        }
+    });
+}
+
+// q_c = qs_c - dt D_c dp; p += dp, on z-marching tiles.
+template <int SCHEME>
+__global__ __launch_bounds__(kZt) void k_nsc_correct3z(Vel qs, double *__restrict__ o0, double *__restrict__ o1,
+                                                       double *__restrict__ o2, double *__restrict__ p,
+                                                       const double *__restrict__ dp, int n, int zc, double dt,
+                                                       double h) {
+    __shared__ ZRing<1>::Plane pl[1];
+    ZRing<1> R(n, 1, zc);
+    auto ld = [&](int, int64_t x) { return dp[x]; };
+    const int i = R.x0 + R.tx, j = R.y0 + R.ty;
+    double *out[3] = {o0, o1, o2};
+    R.march(ld, pl, [&](int z) {
+        if (i < n && j < n) {
+            const int64_t c = int64_t(z) * R.P + int64_t(j) * n + i;
+            double v[3][3][3] = {};
+            R.template gather<SCHEME>(pl[0], z, v);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) out[e][c] = qs.q[e][c] - dt * adx_deriv<3, SCHEME>(v, e, h);
+            p[c] += v[1][1][1];
+        }
+    });
 }
 
 inline int adx_planes(int n) {
@@ -616,11 +732,27 @@ static np_status nsc_step_impl(int lg, double h, double *u, double *v, double *w
     Vel qn{{u, v, w}}, vt{{qt[0], qt[1], qt[2]}}, vs{{qs[0], qs[1], qs[2]}};
     const dim3 blk(kAdxX, kAdxY), grd(unsigned((n + kAdxX - 1) / kAdxX), unsigned((n + kAdxY - 1) / kAdxY),
                                       D == 3 ? unsigned(n) : 1u);
-    hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 0>), grd, blk, 0, s, qn, vt, qt[0], qt[1], qt[2], p, n, dt, nu, h);
-    NP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 1>), grd, blk, 0, s, qn, vt, qs[0], qs[1], qs[2], p, n, dt, nu, h);
-    NP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_nsc_div<D, SCHEME>), grd, blk, 0, s, vs, rhs, n, h, -1.0 / dt);
+    // 3D from 32^3: z-marching tiles
+    const bool zm = D == 3 && n >= 32 && g_zmarch_explicit;
+    const int zc = adx_planes(n);
+    const unsigned nz3 = unsigned(((n + kZx - 1) / kZx) * ((n + kZy - 1) / kZy) * ((n + zc - 1) / zc));
+    if (zm) {
+        hipLaunchKernelGGL((k_nsc_stage3z<SCHEME, 0>), dim3(nz3), dim3(kZt), 0, s, qn, vt, qt[0], qt[1], qt[2], p, n,
+                           zc, dt, nu, h);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_nsc_stage3z<SCHEME, 1>), dim3(nz3), dim3(kZt), 0, s, qn, vt, qs[0], qs[1], qs[2], p, n,
+                           zc, dt, nu, h);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_nsc_div3z<SCHEME>), dim3(nz3), dim3(kZt), 0, s, vs, rhs, n, zc, h, -1.0 / dt);
+    } else {
+        hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 0>), grd, blk, 0, s, qn, vt, qt[0], qt[1], qt[2], p, n, dt, nu,
+                           h);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 1>), grd, blk, 0, s, qn, vt, qs[0], qs[1], qs[2], p, n, dt, nu,
+                           h);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_nsc_div<D, SCHEME>), grd, blk, 0, s, vs, rhs, n, h, -1.0 / dt);
+    }
     NP_LAUNCH_CHECK();
     np_mg_opts o;
     np_default_opts(&o);
@@ -632,7 +764,10 @@ static np_status nsc_step_impl(int lg, double h, double *u, double *v, double *w
     np_dims dims{D, {int64_t(n), int64_t(n), D == 3 ? int64_t(n) : 1}};
     np_status st = poisson_solve(dims, h, NP_BC_PERIODIC, rhs, dp, tol, &o, stats);
     if (st == NP_EINVAL || st == NP_EHIP || st == NP_ENOMEM) return st;
-    hipLaunchKernelGGL((k_nsc_correct<D, SCHEME>), grd, blk, 0, s, vs, u, v, w, p, dp, n, dt, h);
+    if (zm)
+        hipLaunchKernelGGL((k_nsc_correct3z<SCHEME>), dim3(nz3), dim3(kZt), 0, s, vs, u, v, w, p, dp, n, zc, dt, h);
+    else
+        hipLaunchKernelGGL((k_nsc_correct<D, SCHEME>), grd, blk, 0, s, vs, u, v, w, p, dp, n, dt, h);
     NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipStreamSynchronize(s));
     return st;
