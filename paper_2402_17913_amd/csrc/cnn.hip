@@ -76,22 +76,27 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, co
         for (int q = 0; q < kCh; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 14; ++s) {
-            const int tap = 2 * s + tsel;
+            // the 28th tap does not exist: read tap 26's operands and zero them by value
+            // (a select of values, never of addresses)
+            const bool live = 2 * s + tsel < kTaps;
+            const int tap = live ? 2 * s + tsel : kTaps - 1;
             const uint4 zz = make_uint4(0, 0, 0, 0);
-            const bool live = tap < kTaps;
             const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const uint4 a4 = live ? ws[(tap * kC + col) * 2 + cb] : zz;
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&a4);
+            const uint4 a4 = ws[(tap * kC + col) * 2 + cb];
+            const bf16x8 av = __builtin_bit_cast(bf16x8, live ? a4 : zz);
 #pragma unroll
             for (int q = 0; q < kCh; ++q) {
-                if (q >= nch) break;
-                const int hv = ((1 + dz) * 6 + (w + 1 + dy)) * hx + ((t0 + q) * 16 + col + 1 + dx);
-                const uint4 b4 = live ? xs[hv * 2 + cb] : zz;
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&b4);
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+                if (q < nch) {
+                    const int hv = ((1 + dz) * 6 + (w + 1 + dy)) * hx + ((t0 + q) * 16 + col + 1 + dx);
+                    const uint4 b4 = xs[hv * 2 + cb];
+                    const bf16x8 bv = __builtin_bit_cast(bf16x8, live ? b4 : zz);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+                }
             }
         }
-        for (int q = 0; q < nch; ++q) {
+#pragma unroll
+        for (int q = 0; q < kCh; ++q) {
+            if (q >= nch) continue;
             const int tt = t0 + q;
             // lane holds output channels 4*grp .. +3 of voxel `col`
             const int gx = x0 + tt * 16 + col, gy = y0 + w;

@@ -117,6 +117,7 @@ struct Tuning {
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
 };
 static Tuning g_tune;
+int g_zc3 = 0;
 
 // -------------------------------------------------------------- hierarchy
 // Level l has n_l = n / 2^l cells per axis, l = 0..L with n_L = 4.  Level 0
@@ -1112,11 +1113,12 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
-        {"zmarch_explicit", &g_zmarch_explicit, 0, 1},
+        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64},
     };
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
-            if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1))) {
+            if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
+                (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1))))) {
                 set_error("value %d out of range for %s", value, key);
                 return NP_EINVAL;
             }
@@ -1152,6 +1154,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
+    if (!std::strcmp(key, "zc3")) return g_zc3;
     return -1;
 }
 

@@ -417,3 +417,44 @@ def test_sawtooth_option_checks(B):
                dict(prolong=B.PROLONG_COPY), dict(cycle=2)):
         with pytest.raises(B.NeuphysError):
             B.mg_poisson_solve(a, a.clone(), 1 / 16, DIR, **kw)
+
+
+@pytest.mark.parametrize("d,n", [(2, 8192), (3, 1024)])
+def test_maximum_sizes(B, d, n):
+    """The largest grids the solver accepts (8192^2, 1024^3), Dirichlet, one sine mode
+    k = (1, 2[, 3]) as the right-hand side, whose discrete solution is f / lambda_k in
+    closed form (A's eigenvector).  The residual cannot be resolved below about
+    eps 4d / (h^2 lambda_k) relative (cancellation in A x at this size: 1e-9 at 8192^2),
+    so the tolerance is 1e-10 or 50 times that floor.  FP64, the FP32-storage mixed path
+    and (3D) the BF16-storage one reach it, and their error obeys ||x - x*|| <= ||r|| /
+    lambda_min (on the device).  At 8192^2 BF16 storage of the correction is too coarse:
+    its rounding, amplified by A (condition number ~1e7), keeps the residual above that
+    floor, and the solver must say so (NP_ENOCONV) instead of returning a wrong answer."""
+    import torch
+    say("maximum size", d, n)
+    h = 1.0 / n
+    c = (torch.arange(n, dtype=torch.float64, device="cuda") + 0.5) * h
+    ks = (1, 2, 3)[:d]
+    f = torch.sin(ks[0] * np.pi * c)
+    for a in range(1, d):
+        f = torch.sin(ks[a] * np.pi * c).reshape((n,) + (1,) * a) * f
+    f = f.contiguous()
+    lam = (4 / h ** 2) * sum(np.sin(k * np.pi * h / 2) ** 2 for k in ks)
+    lam_min = (4 * d / h ** 2) * np.sin(np.pi * h / 2) ** 2
+    tol = max(1e-10, 50 * np.finfo(np.float64).eps * 4 * d / (h ** 2 * lam))
+    nf = float(torch.linalg.vector_norm(f))
+    for p in (B.FP64, B.FP32, B.BF16):
+        x = torch.zeros_like(f)
+        st, stats = B.mg_poisson_solve(f, x, h, DIR, tol=tol, smooth_prec=p, check=False)
+        if p == B.BF16 and d == 2:
+            say("  prec", p, "status", st, "cycles", stats["cycles"], "rel_res", stats["rel_res"])
+            assert st == 0 or (st == B.NP_ENOCONV and stats["rel_res"] > tol)
+            if st != 0:
+                continue
+        assert st == 0 and stats["rel_res"] <= tol
+        rr = B.np_op_resid_norm(f, x, h, DIR) / nf
+        err = float(torch.linalg.vector_norm(x - f / lam))
+        say("  prec", p, "tol", tol, "cycles", stats["cycles"], "rel_res", rr, "error", err / (nf / lam))
+        assert rr <= tol * (1 + 1e-6)
+        assert err <= rr * nf / lam_min * (1 + 1e-6) + 1e-13 * nf / lam
+        del x
