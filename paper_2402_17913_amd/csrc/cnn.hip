@@ -65,57 +65,43 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, co
     const int w = tid >> 6, l = tid & 63;
     const int col = l & 15, grp = l >> 4;
     const int tsel = grp >> 1, cb = grp & 1;
-    // The wave's row in chunks of 16 voxels, up to four chunks at a time with one
-    // accumulator each: the MFMAs of different chunks are independent (no
-    // dependency chain through one accumulator) and share the weight fragment.
-    constexpr int kCh = 4;
-    for (int t0 = 0; t0 < txv / 16; t0 += kCh) {
-        const int nch = min(kCh, txv / 16 - t0);
-        f32x4 acc[kCh];
-#pragma unroll
-        for (int q = 0; q < kCh; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tt = 0; tt < txv / 16; ++tt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 14; ++s) {
-            // the 28th tap does not exist: read tap 26's operands and zero them by value
-            // (a select of values, never of addresses)
-            const bool live = 2 * s + tsel < kTaps;
-            const int tap = live ? 2 * s + tsel : kTaps - 1;
-            const uint4 zz = make_uint4(0, 0, 0, 0);
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const uint4 a4 = ws[(tap * kC + col) * 2 + cb];
-            const bf16x8 av = __builtin_bit_cast(bf16x8, live ? a4 : zz);
-#pragma unroll
-            for (int q = 0; q < kCh; ++q) {
-                if (q < nch) {
-                    const int hv = ((1 + dz) * 6 + (w + 1 + dy)) * hx + ((t0 + q) * 16 + col + 1 + dx);
-                    const uint4 b4 = xs[hv * 2 + cb];
-                    const bf16x8 bv = __builtin_bit_cast(bf16x8, live ? b4 : zz);
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kCh; ++q) {
-            if (q >= nch) continue;
-            const int tt = t0 + q;
-            // lane holds output channels 4*grp .. +3 of voxel `col`
-            const int gx = x0 + tt * 16 + col, gy = y0 + w;
-            const int64_t v = (((int64_t(z) << lg) + gy) << lg) + gx;
-            float o[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float t = acc[q][r] + (bias ? bias[4 * grp + r] : 0.f);
-                if (RELU) t = t > 0.f ? t : 0.f;
-                o[r] = t;
-            }
-            if (OUT32) {
-                *reinterpret_cast<float4 *>(reinterpret_cast<float *>(Y) + v * kC + 4 * grp) = make_float4(o[0], o[1], o[2], o[3]);
+            const int tap = 2 * s + tsel;
+            bf16x8 av, bv;
+            if (tap < kTaps) {
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                const uint4 a4 = ws[(tap * kC + col) * 2 + cb];
+                const int hv = ((1 + dz) * 6 + (w + 1 + dy)) * hx + (tt * 16 + col + 1 + dx);
+                const uint4 b4 = xs[hv * 2 + cb];
+                av = *reinterpret_cast<const bf16x8 *>(&a4);
+                bv = *reinterpret_cast<const bf16x8 *>(&b4);
             } else {
-                uint2 pk;
-                pk.x = uint32_t(f2b(o[0])) | (uint32_t(f2b(o[1])) << 16);
-                pk.y = uint32_t(f2b(o[2])) | (uint32_t(f2b(o[3])) << 16);
-                *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(Y) + v * kC + 4 * grp) = pk;
+                const uint4 zz = make_uint4(0, 0, 0, 0);
+                av = *reinterpret_cast<const bf16x8 *>(&zz);
+                bv = av;
             }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+        // lane holds output channels 4*grp .. +3 of voxel `col`
+        const int gx = x0 + tt * 16 + col, gy = y0 + w;
+        const int64_t v = (((int64_t(z) << lg) + gy) << lg) + gx;
+        float o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float t = acc[r] + (bias ? bias[4 * grp + r] : 0.f);
+            if (RELU) t = t > 0.f ? t : 0.f;
+            o[r] = t;
+        }
+        if (OUT32) {
+            *reinterpret_cast<float4 *>(reinterpret_cast<float *>(Y) + v * kC + 4 * grp) = make_float4(o[0], o[1], o[2], o[3]);
+        } else {
+            uint2 pk;
+            pk.x = uint32_t(f2b(o[0])) | (uint32_t(f2b(o[1])) << 16);
+            pk.y = uint32_t(f2b(o[2])) | (uint32_t(f2b(o[3])) << 16);
+            *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(Y) + v * kC + 4 * grp) = pk;
         }
     }
 }
