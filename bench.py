@@ -342,10 +342,12 @@ def leg_ad(B, inputs, steps, warmup):
                 ("sawtooth_linear", dict(cycle=B.CYCLE_SAWTOOTH, nu1=0, nu2=1, omega=1.0)),
                 ("sawtooth_damped_linear", dict(cycle=B.CYCLE_SAWTOOTH, nu1=0, nu2=2, omega=2.0 / 3.0)))
     for vn, kw in variants:
-        st, s50 = B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, op, check=False, l1=True, fixed_cycles=50,
-                                         **kw)
-        l1 = s50["l1_change"]
-        below = [k + 1 for k, v in enumerate(l1) if v < 1e-5]
+        # the paper's gauge over 256 cycles: the change at 50 cycles and the first cycle whose
+        # change falls below its tolerance 1e-5
+        st, sg = B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, op, check=False, l1=True, fixed_cycles=256,
+                                        **kw)
+        l1 = sg["l1_change"][:50]
+        below = [k + 1 for k, v in enumerate(sg["l1_change"]) if v < 1e-5]
         dt, (st, stats) = timed(lambda: B.np_ad_implicit_solve(T0, x, 1.0, B.BC_DIRICHLET0, op, tol=TOL, check=False,
                                                                max_cycles=100, **kw), max(1, steps // 2), 1)
         paper[vn] = dict(l1_change_first=l1[0], l1_change_50=l1[-1], l1_reduction_50=l1[-1] / l1[0],
@@ -353,8 +355,9 @@ def leg_ad(B, inputs, steps, warmup):
                          status="converged" if st == 0 else "not converged (status %d)" % st,
                          cycles_to_tol=stats["cycles"], rel_res=stats["rel_res"],
                          ms_per_solve=1e3 * dt / max(1, steps // 2))
-        log("  ad paper %s: L1 change %.3g -> %.3g in 50 cycles; tol 1e-10: %s, %d cycles, %.2f ms" % (
-            vn, l1[0], l1[-1], paper[vn]["status"], stats["cycles"], paper[vn]["ms_per_solve"]))
+        log("  ad paper %s: L1 change %.3g -> %.3g in 50 cycles, below 1e-5 from cycle %s; tol 1e-10: %s, %d "
+            "cycles, %.2f ms" % (vn, l1[0], l1[-1], paper[vn]["first_cycle_l1_below_1e5"], paper[vn]["status"],
+                                 stats["cycles"], paper[vn]["ms_per_solve"]))
     out["paper_2d_128"] = paper
     del T0, x
     for name, d, n, gamma in (("2d_4096", 2, 4096, 320.0), ("3d_256", 3, 256, 20.0)):
