@@ -32,6 +32,9 @@ constexpr int kTaps = 27;
 constexpr int kWsz = kTaps * kC * kC;  // weights per conv ([tap][out][in])
 constexpr int kPsz = kWsz + kC;        // + bias
 constexpr int kWgBlocks = 512;         // workgroups of a weight-gradient reduction
+}  // namespace
+int g_conv3z = 1;  // tuning knob "conv3z": z-marching convolution tiles (0 off, 1 automatic, else planes)
+namespace {
 
 __device__ __forceinline__ float b2f(uint16_t u) { return __uint_as_float(uint32_t(u) << 16); }
 __device__ __forceinline__ uint16_t f2b(float f) { return float_to_bf16(f); }
@@ -103,6 +106,90 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, co
             pk.y = uint32_t(f2b(o[2])) | (uint32_t(f2b(o[3])) << 16);
             *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(Y) + v * kC + 4 * grp) = pk;
         }
+    }
+}
+
+// Z-marching form of the same convolution (same MFMA sequence per output, so
+// the same bits): a workgroup of 256 threads (4 waves, one row each) owns a
+// TXV x 4 tile of the plane (TXV = min(64, n)) and zc consecutive planes.
+// Input planes z - 1, z, z + 1 with their one-voxel halo sit in a ring of
+// three LDS buffers, the weights are staged once per workgroup, and plane
+// z + 2 replaces plane z - 1 after plane z is computed, so each input plane is
+// read about once per workgroup instead of three times.
+constexpr int kCzT = 256, kCzY = 4;
+constexpr int kCzSlots = (64 + 2) * (kCzY + 2) * 2;  // uint4 per plane buffer (halo tile, two per voxel)
+
+// This thread's share of an input plane of k_conv3z, loaded straight into
+// its ring buffer: slot q holds half (q & 1) of voxel (q >> 1) of the halo tile.
+__device__ __forceinline__ void cz_fill(uint4 *__restrict__ dst, const uint4 *__restrict__ X4, int64_t base, int tid,
+                                        int hx, int x0, int y0, int lg) {
+    const int n = 1 << lg, nslot = hx * (kCzY + 2) * 2;
+    for (int q = tid; q < nslot; q += kCzT) {
+        const int v = q >> 1, half = q & 1, lx = v % hx, ly = v / hx;
+        dst[q] = X4[base + ((int64_t(wrapi(y0 + ly - 1, n)) << lg) + wrapi(x0 + lx - 1, n)) * 2 + half];
+    }
+}
+
+template <bool RELU, bool OUT32>
+__global__ __launch_bounds__(kCzT) void k_conv3z(const uint16_t *__restrict__ X, const uint16_t *__restrict__ W,
+                                                 const float *__restrict__ bias, void *__restrict__ Y, int lg, int zc) {
+    __shared__ uint4 xs[3][kCzSlots];
+    __shared__ uint4 ws[kTaps * kC * 2];
+    const int n = 1 << lg, txv = n < 64 ? n : 64, hx = txv + 2;
+    const int tiles_x = n / txv, tiles_y = n / kCzY;
+    const int b = blockIdx.x;
+    const int x0 = (b % tiles_x) * txv, y0 = ((b / tiles_x) % tiles_y) * kCzY, z0 = (b / (tiles_x * tiles_y)) * zc;
+    const int tid = threadIdx.x;
+    const uint4 *W4 = reinterpret_cast<const uint4 *>(W);
+    for (int q = tid; q < kTaps * kC * 2; q += kCzT) ws[q] = W4[q];
+    const uint4 *X4 = reinterpret_cast<const uint4 *>(X);
+    auto plane = [&](int z) { return int64_t(wrapi(z, n)) << (2 * lg + 1); };
+    cz_fill(xs[(z0 + 2) % 3], X4, plane(z0 - 1), tid, hx, x0, y0, lg);
+    cz_fill(xs[z0 % 3], X4, plane(z0), tid, hx, x0, y0, lg);
+    cz_fill(xs[(z0 + 1) % 3], X4, plane(z0 + 1), tid, hx, x0, y0, lg);
+    const int w = tid >> 6, l = tid & 63;
+    const int col = l & 15, grp = l >> 4;
+    const int tsel = grp >> 1, cb = grp & 1;
+    for (int z = z0; z < z0 + zc; ++z) {
+        __syncthreads();  // planes z - 1, z, z + 1 (and the weights) are in LDS
+        for (int tt = 0; tt < txv / 16; ++tt) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 14; ++s) {
+                // the 28th tap does not exist: read tap 26's operands and zero them by value
+                const bool live = 2 * s + tsel < kTaps;
+                const int tap = live ? 2 * s + tsel : kTaps - 1;
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                const uint4 a4 = ws[(tap * kC + col) * 2 + cb];
+                const int hv = (w + 1 + dy) * hx + (tt * 16 + col + 1 + dx);
+                const uint4 b4 = xs[(z + dz + 3) % 3][hv * 2 + cb];
+                const uint4 zz = make_uint4(0, 0, 0, 0);
+                const bf16x8 av = __builtin_bit_cast(bf16x8, live ? a4 : zz);
+                const bf16x8 bv = __builtin_bit_cast(bf16x8, live ? b4 : zz);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+            }
+            // lane holds output channels 4*grp .. +3 of voxel `col`
+            const int gx = x0 + tt * 16 + col, gy = y0 + w;
+            const int64_t v = (((int64_t(z) << lg) + gy) << lg) + gx;
+            float o[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float t = acc[r] + (bias ? bias[4 * grp + r] : 0.f);
+                if (RELU) t = t > 0.f ? t : 0.f;
+                o[r] = t;
+            }
+            if (OUT32) {
+                *reinterpret_cast<float4 *>(reinterpret_cast<float *>(Y) + v * kC + 4 * grp) =
+                    make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+                uint2 pk;
+                pk.x = uint32_t(f2b(o[0])) | (uint32_t(f2b(o[1])) << 16);
+                pk.y = uint32_t(f2b(o[2])) | (uint32_t(f2b(o[3])) << 16);
+                *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(Y) + v * kC + 4 * grp) = pk;
+            }
+        }
+        __syncthreads();  // every read of the oldest buffer is done before it takes plane z + 2
+        if (z + 2 <= z0 + zc) cz_fill(xs[(z + 2) % 3], X4, plane(z + 2), tid, hx, x0, y0, lg);
     }
 }
 
@@ -387,6 +474,23 @@ np_status conv(Net *N, int k, const uint16_t *X, void *Y, int lg, bool relu, boo
     const unsigned grid = unsigned((n / txv) * (n / 4) * n);
     const uint16_t *W = (flip ? N->wt : N->wb) + int64_t(k) * kWsz;
     const float *bias = flip ? nullptr : N->w + int64_t(k) * kPsz + kWsz;
+    // z-marching tiles: n / 32 planes per workgroup (measured best at n = 64, 128 and 256; below n = 64 the
+    // one-plane form keeps more workgroups in flight and wins)
+    int zc = g_conv3z == 1 ? n / 32 : (g_conv3z < n ? g_conv3z : n);
+    if (g_conv3z && zc >= 2) {
+        const int tiles = (n / txv) * (n / kCzY);
+        const unsigned g3 = unsigned(tiles * (n / zc));
+        if (relu && !out32)
+            hipLaunchKernelGGL((k_conv3z<true, false>), dim3(g3), dim3(kCzT), 0, s, X, W, bias, Y, lg, zc);
+        else if (!relu && out32)
+            hipLaunchKernelGGL((k_conv3z<false, true>), dim3(g3), dim3(kCzT), 0, s, X, W, bias, Y, lg, zc);
+        else if (!relu && !out32)
+            hipLaunchKernelGGL((k_conv3z<false, false>), dim3(g3), dim3(kCzT), 0, s, X, W, bias, Y, lg, zc);
+        else
+            hipLaunchKernelGGL((k_conv3z<true, true>), dim3(g3), dim3(kCzT), 0, s, X, W, bias, Y, lg, zc);
+        NP_LAUNCH_CHECK();
+        return NP_OK;
+    }
     if (relu && !out32) hipLaunchKernelGGL((k_conv<true, false>), dim3(grid), dim3(256), 0, s, X, W, bias, Y, lg);
     else if (!relu && out32) hipLaunchKernelGGL((k_conv<false, true>), dim3(grid), dim3(256), 0, s, X, W, bias, Y, lg);
     else if (!relu && !out32) hipLaunchKernelGGL((k_conv<false, false>), dim3(grid), dim3(256), 0, s, X, W, bias, Y, lg);

@@ -1113,12 +1113,13 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
-        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64},
+        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
     };
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
-                (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1))))) {
+                (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
+                (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
                 return NP_EINVAL;
             }
@@ -1155,6 +1156,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
     if (!std::strcmp(key, "zc3")) return g_zc3;
+    if (!std::strcmp(key, "conv3z")) return g_conv3z;
     return -1;
 }
 

@@ -86,6 +86,42 @@ def test_cnn_gradients_match_oracle(B):
     assert cosine(g, gref) >= 0.999 and rel_l2(g, gref) <= 2e-2
 
 
+@pytest.mark.parametrize("n,levels", [(16, 1), (32, 2), (64, 3)])
+def test_cnn_zmarch_tiles_bit_identical(B, n, levels):
+    """The z-marching convolution runs the same MFMA sequence per output as the
+    one-plane form, so forward outputs and gradients agree bit for bit, for the
+    automatic and for fixed plane counts (including one plane count above n)."""
+    import torch
+    from oracle import cnn
+    print("cnn zmarch", n, levels, flush=True)
+    ps = params_for(levels, seed=n + 1)
+    rng = np.random.default_rng(9)
+    f = cnn.bf16_round(rng.standard_normal((n, n, n)))
+    t = rng.standard_normal((n, n, n)).astype(np.float32)
+    x = torch.from_numpy(f.astype(np.float32)).cuda()
+    tt = torch.from_numpy(t).cuda()
+    net = B.Cnn(n, levels)
+    net.set_params(cnn.flatten(ps).astype(np.float32))
+    res = {}
+    try:
+        for v in (0, 1, 2, 8, 64):
+            B.np_set_tuning("conv3z", v)
+            y = torch.empty_like(x)
+            net.forward(x, y)
+            loss = net.gradients([x], [tt])
+            res[v] = (y.cpu().numpy(), loss, net.get_grads())
+    finally:
+        B.np_set_tuning("conv3z", 1)
+        net.close()
+    y0, l0, g0 = res[0]
+    assert np.isfinite(y0).all() and np.abs(y0).max() > 0
+    for v in (1, 2, 8, 64):
+        y, l, g = res[v]
+        assert np.array_equal(y, y0), v
+        assert l == l0, v
+        assert np.array_equal(g, g0), v
+
+
 @pytest.fixture(scope="module")
 def trained(B, tmp_path_factory):
     """A 2-level net on the 32^3 restriction of 64^3 projection steps, trained by

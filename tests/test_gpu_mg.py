@@ -226,7 +226,11 @@ def test_tuning_knobs_validate(B):
         B.np_set_tuning("no_such_knob", 1)
     with pytest.raises(B.NeuphysError):
         B.np_set_tuning("bz3", 3)
+    for key, bad in (("zc3", 3), ("zc3", 1), ("conv3z", 6), ("conv3z", 128)):
+        with pytest.raises(B.NeuphysError):
+            B.np_set_tuning(key, bad)
     assert B.np_get_tuning("fused") == 0 and B.np_get_tuning("tail") == 1
+    assert B.np_get_tuning("conv3z") == 1 and B.np_get_tuning("zc3") == 0
 
 
 def test_resid_norm(B, orc):
