@@ -569,32 +569,170 @@ template <int D> struct Tail {
     static constexpr int NT = D == 3 ? 512 : 1024;  // threads (3D FP64 needs the registers)
 };
 
-template <int D, class C> struct LdsLd {
-    const C *p;
-    __device__ __forceinline__ C operator()(int64_t q) const { return p[q]; }
-};
+// nb_sum for a level held in LDS, without branches: every neighbour is read
+// unconditionally (a Dirichlet ghost reads the cell itself and flips its sign,
+// a periodic one reads the wrapped cell), so the six reads are in flight
+// together.  Same values and summation order as nb_sum.
+template <int D, class C>
+__device__ __forceinline__ C nb_sum_lds(const C *X, int c, int i, int j, int k, int lg, int bc) {
+    const int last = (1 << lg) - 1, sy = 1 << lg, sz = 1 << (2 * lg);
+    const bool per = bc != 0;
+    const C xm = X[i > 0 ? c - 1 : (per ? c + last : c)];
+    const C xp = X[i < last ? c + 1 : (per ? c - last : c)];
+    const C ym = X[j > 0 ? c - sy : (per ? c + last * sy : c)];
+    const C yp = X[j < last ? c + sy : (per ? c - last * sy : c)];
+    C s = (((i > 0 || per) ? xm : -xm) + ((i < last || per) ? xp : -xp) + ((j > 0 || per) ? ym : -ym)) +
+          ((j < last || per) ? yp : -yp);
+    if (D == 3) {
+        const C zm = X[k > 0 ? c - sz : (per ? c + last * sz : c)];
+        const C zp = X[k < last ? c + sz : (per ? c - last * sz : c)];
+        s = (s + ((k > 0 || per) ? zm : -zm)) + ((k < last || per) ? zp : -zp);
+    }
+    return s;
+}
+
+// One weighted-Jacobi sweep T = X + wdiag (F - A X) (RESID: the residual
+// T = F - A X) of a level of the one-workgroup tail (all three in LDS).  Each thread marches along the last
+// axis over a run of one column's cells: the neighbours along that axis come
+// from registers, the in-plane ones from offsets fixed per column.  Same
+// values and summation order as nb_sum.  Needs n^(D-1) <= NT.
+template <int D, class C, int NT, bool RESID = false>
+__device__ __forceinline__ void tail_sweep(const C *__restrict__ X, const C *__restrict__ F, C *__restrict__ T,
+                                           int lg, int bc, C inv_h2, C wdiag) {
+    const int n = 1 << lg, last = n - 1, sm = D == 3 ? n * n : n;  // sm: cells per plane = marching stride
+    const int chunks = NT / sm < n ? NT / sm : n, len = n / chunks;
+    const int t = threadIdx.x;
+    if (t < sm * chunks) {
+        const bool per = bc != 0;
+        const int i = t & last, j = D == 3 ? (t >> lg) & last : 0, z0 = (t / sm) * len;
+        const int oxm = i > 0 ? -1 : (per ? last : 0), oxp = i < last ? 1 : (per ? -last : 0);
+        const bool fxm = i > 0 || per, fxp = i < last || per;
+        const int oym = j > 0 ? -n : (per ? last * n : 0), oyp = j < last ? n : (per ? -last * n : 0);
+        const bool fym = j > 0 || per, fyp = j < last || per;
+        int c = z0 * sm + (t & (sm - 1));
+        C xc = X[c];
+        C zm = X[z0 > 0 ? c - sm : (per ? c + last * sm : c)];
+        bool fzm = z0 > 0 || per;
+        for (int z = z0; z < z0 + len; ++z, c += sm) {
+            const C zp = X[z < last ? c + sm : (per ? c - last * sm : c)];
+            const bool fzp = z < last || per;
+            const C xm = X[c + oxm], xp = X[c + oxp];
+            C s = (fxm ? xm : -xc) + (fxp ? xp : -xc);
+            if (D == 3) {
+                const C ym = X[c + oym], yp = X[c + oyp];
+                s = (s + (fym ? ym : -xc)) + (fyp ? yp : -xc);
+            }
+            s = (s + (fzm ? zm : -xc)) + (fzp ? zp : -xc);
+            if (RESID) T[c] = F[c] - (C(2 * D) * xc - s) * inv_h2;  // the residual only
+            else T[c] = xc + wdiag * (F[c] - (C(2 * D) * xc - s) * inv_h2);
+            zm = xc;
+            fzm = true;
+            xc = zp;
+        }
+    }
+}
+
+// X += P E on a level of the one-workgroup tail (E: the next coarser level),
+// marching like tail_sweep: the in-plane interpolation indices and signs are
+// fixed per column.  Same terms and summation order as k_prolong_add.
+template <int D, class C, int NT>
+__device__ __forceinline__ void tail_prolong(const C *__restrict__ E, C *__restrict__ X, int lg, int bc) {
+    const int n = 1 << lg, last = n - 1, lgc = lg - 1, nc = n >> 1, sm = D == 3 ? n * n : n;
+    const int chunks = NT / sm < n ? NT / sm : n, len = n / chunks;
+    const int t = threadIdx.x;
+    if (t < sm * chunks) {
+        const int z0 = (t / sm) * len;
+        int oi, ni, oj = 0, nj = 0;
+        float si, sj = 1.0f;
+        pro_axis(t & last, nc, bc, oi, ni, si);
+        if (D == 3) pro_axis((t >> lg) & last, nc, bc, oj, nj, sj);
+        int c = z0 * sm + (t & (sm - 1));
+        for (int z = z0; z < z0 + len; ++z, c += sm) {
+            int oz, nz;
+            float sz;
+            pro_axis(z, nc, bc, oz, nz, sz);
+            C s = C(0);
+            if (D == 3) {
+                for (int cz = 0; cz < 2; ++cz)
+                    for (int b = 0; b < 2; ++b)
+                        for (int a = 0; a < 2; ++a) {
+                            const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(cz ? 0.25 : 0.75);
+                            const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sz : 1.0f));
+                            const int q = ((cz ? nz : oz) << (2 * lgc)) | ((b ? nj : oj) << lgc) | (a ? ni : oi);
+                            s += w * (sg * E[q]);
+                        }
+            } else {
+                // the marching axis is y
+                for (int b = 0; b < 2; ++b)
+                    for (int a = 0; a < 2; ++a) {
+                        const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(1.0);
+                        const C sg = C((a ? si : 1.0f) * (b ? sz : 1.0f) * 1.0f);
+                        const int q = ((b ? nz : oz) << lgc) | (a ? ni : oi);
+                        s += w * (sg * E[q]);
+                    }
+            }
+            X[c] = X[c] + s;
+        }
+    }
+}
 
 // V(nu1, nu2) cycle on levels lg_t .. 2 in one workgroup, every level in LDS
 // (xs, fs: all levels, finest first; ts: scratch of the finest level).
 // f_t: right-hand side of level lg_t (global); x_t: result (global); x_in:
 // starting iterate of level lg_t (global), or null for a zero iterate (then
 // the first sweep is w f).  Coarser levels always start from zero.
-// h_t: spacing of level lg_t.  nu1 >= 1 when x_in is null.
+// h_t: spacing of level lg_t.  nu1 >= 1 when x_in is null.  Entry (i, q) of
+// the coarsest inverse sits at Minv[i * m_rs + q * m_cs].
 template <int D, class S, int NT>
 __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>::C *fs, typename St<S>::C *ts,
                                            const S *__restrict__ f_t, S *__restrict__ x_t,
                                            const S *__restrict__ x_in, const double *__restrict__ Minv, int lg_t,
-                                           int bc, double h_t, double omega, int nu1, int nu2) {
+                                           int bc, double h_t, double omega, int nu1, int nu2,
+                                           int m_rs = D == 3 ? 64 : 16, int m_cs = 1) {
     typedef typename St<S>::C C;
     const int tid = threadIdx.x;
     // level l starts after the finer levels lg_t .. l+1 (geometric sum)
     auto off = [&](int l) -> int64_t {
         return ((int64_t(1) << (D * (lg_t + 1))) - (int64_t(1) << (D * (l + 1)))) / ((int64_t(1) << D) - 1);
     };
+    // cnt sweeps on level lg, alternating between X and ts; the result ends in X
+    auto sweeps = [&](C *X, const C *F, int lg, C inv_h2, C wdiag, int cnt) {
+        C *cur = X, *nxt = ts;
+        for (int it = 0; it < cnt; ++it) {
+            tail_sweep<D, C, NT>(cur, F, nxt, lg, bc, inv_h2, wdiag);
+            __syncthreads();
+            C *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (cur != X) {
+            const int m = 1 << (D * lg);
+            for (int c = tid; c < m; c += NT) X[c] = cur[c];
+            __syncthreads();
+        }
+    };
+    static_assert(Tail<D>::cells(Tail<D>::LG) >> Tail<D>::LG <= NT, "tail_sweep needs n^(D-1) <= NT");
     const int64_t mt = int64_t(1) << (D * lg_t);
-    for (int64_t c = tid; c < mt; c += NT) {
-        fs[off(lg_t) + c] = St<S>::ld(f_t + c);
-        if (x_in) xs[off(lg_t) + c] = St<S>::ld(x_in + c);
+    {
+        // all of this thread's loads first, then the LDS stores: one round trip to memory
+        constexpr int per = int((Tail<D>::cells(Tail<D>::LG) + NT - 1) / NT);
+        C fv[per], xv[per];
+#pragma unroll
+        for (int u = 0; u < per; ++u) {
+            const int c = tid + u * NT;
+            if (c < mt) {
+                fv[u] = St<S>::ld(f_t + c);
+                if (x_in) xv[u] = St<S>::ld(x_in + c);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < per; ++u) {
+            const int c = tid + u * NT;
+            if (c < mt) {
+                fs[off(lg_t) + c] = fv[u];
+                if (x_in) xs[off(lg_t) + c] = xv[u];
+            }
+        }
     }
     __syncthreads();
     double h = h_t;
@@ -610,23 +748,14 @@ __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>
             __syncthreads();
             it0 = 1;
         }
-        for (int it = it0; it < nu1; ++it) {
-            for (int64_t c = tid; c < m; c += NT) {
-                int i, j, k;
-                decode<D>(c, lg, i, j, k);
-                const C xc = X[c];
-                const C s = nb_sum<D, C>(LdsLd<D, C>{X}, c, i, j, k, lg, bc, xc);
-                ts[c] = xc + wdiag * (F[c] - (C(2 * D) * xc - s) * inv_h2);
-            }
-            __syncthreads();
-            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
-            __syncthreads();
-        }
-        // residual and restriction into the next level's rhs
+        sweeps(X, F, lg, inv_h2, wdiag, nu1 - it0);
+        // residual into ts, then its 2^d-cell average into the next level's rhs
+        tail_sweep<D, C, NT, true>(X, F, ts, lg, bc, inv_h2, wdiag);
+        __syncthreads();
         const int lgc = lg - 1;
-        const int64_t mc = int64_t(1) << (D * lgc);
+        const int mc = 1 << (D * lgc);
         C *Fc = fs + off(lgc);
-        for (int64_t cc = tid; cc < mc; cc += NT) {
+        for (int cc = tid; cc < mc; cc += NT) {
             int I, J, K;
             decode<D>(cc, lgc, I, J, K);
             C acc = C(0);
@@ -634,10 +763,7 @@ __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>
                 for (int jj = 0; jj < 2; ++jj)
                     for (int ii = 0; ii < 2; ++ii) {
                         const int i = 2 * I + ii, j = 2 * J + jj, k = D == 3 ? 2 * K + kk : 0;
-                        const int64_t cf = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
-                        const C xc = X[cf];
-                        const C s = nb_sum<D, C>(LdsLd<D, C>{X}, cf, i, j, k, lg, bc, xc);
-                        acc += F[cf] - (C(2 * D) * xc - s) * inv_h2;
+                        acc += ts[(k << (2 * lg)) | (j << lg) | i];
                     }
             Fc[cc] = acc * C(D == 3 ? 0.125 : 0.25);
         }
@@ -655,18 +781,18 @@ __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>
                 decode<D>(tid, 2, i, j, k);
                 const double xc = x_in ? double(X[tid]) : 0.0;
                 double s = 0.0;
-                if (x_in) s = double(nb_sum<D, C>(LdsLd<D, C>{X}, tid, i, j, k, 2, bc, X[tid]));
+                if (x_in) s = double(nb_sum_lds<D, C>(X, tid, i, j, k, 2, bc));
                 rr[tid] = double(F[tid]) - (double(2 * D) * xc - s) / (h * h);
             }
             __syncthreads();
             if (tid < m) {
                 double acc = 0.0;
-                for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * rr[q];
+                for (int q = 0; q < m; ++q) acc += Minv[tid * m_rs + q * m_cs] * rr[q];
                 X[tid] = C((x_in ? double(X[tid]) : 0.0) + acc);
             }
         } else if (tid < m) {
             double acc = 0.0;
-            for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * double(F[q]);
+            for (int q = 0; q < m; ++q) acc += Minv[tid * m_rs + q * m_cs] * double(F[q]);
             X[tid] = C(0.0 + acc);
         }
         __syncthreads();
@@ -674,43 +800,12 @@ __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>
     // --------------------------------------------------------------- up
     for (int lg = 3; lg <= lg_t; ++lg) {
         h *= 0.5;
-        const int64_t m = int64_t(1) << (D * lg);
-        const int lgc = lg - 1, nc = 1 << lgc;
+        const int lgc = lg - 1;
         C *X = xs + off(lg), *F = fs + off(lg), *E = xs + off(lgc);
         const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
-        for (int64_t c = tid; c < m; c += NT) {
-            int i, j, k;
-            decode<D>(c, lg, i, j, k);
-            int oi, ni, oj, nj, ok = 0, nk = 0;
-            float si, sj, sk = 1.0f;
-            pro_axis(i, nc, bc, oi, ni, si);
-            pro_axis(j, nc, bc, oj, nj, sj);
-            if (D == 3) pro_axis(k, nc, bc, ok, nk, sk);
-            C s = C(0);
-            for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
-                for (int b = 0; b < 2; ++b)
-                    for (int a = 0; a < 2; ++a) {
-                        const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(D == 3 ? (cz ? 0.25 : 0.75) : 1.0);
-                        const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
-                        const int64_t q = (int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
-                                          (a ? ni : oi);
-                        s += w * (sg * E[q]);
-                    }
-            X[c] = X[c] + s;
-        }
+        tail_prolong<D, C, NT>(E, X, lg, bc);
         __syncthreads();
-        for (int it = 0; it < nu2; ++it) {
-            for (int64_t c = tid; c < m; c += NT) {
-                int i, j, k;
-                decode<D>(c, lg, i, j, k);
-                const C xc = X[c];
-                const C s = nb_sum<D, C>(LdsLd<D, C>{X}, c, i, j, k, lg, bc, xc);
-                ts[c] = xc + wdiag * (F[c] - (C(2 * D) * xc - s) * inv_h2);
-            }
-            __syncthreads();
-            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
-            __syncthreads();
-        }
+        sweeps(X, F, lg, inv_h2, wdiag, nu2);
     }
     for (int64_t c = tid; c < mt; c += NT) St<S>::st(x_t + c, xs[off(lg_t) + c]);
 }
@@ -725,8 +820,14 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t,
     __shared__ C xs[Tail<D>::levels_sum()];
     __shared__ C fs[Tail<D>::levels_sum()];
     __shared__ C ts[Tail<D>::cells(Tail<D>::LG)];
+    // The coarsest inverse, staged in LDS transposed with padded rows: the loads
+    // are issued with the right-hand side's (one round trip to memory, not one per
+    // term of the product), and thread i reading entry (i, q) hits consecutive banks.
+    constexpr int m = D == 3 ? 64 : 16, mp = m + 1;
+    __shared__ double Ms[m * mp];
     if (stop && *stop) return;
-    tail_cycle<D, S, Tail<D>::NT>(xs, fs, ts, f_t, x_t, nullptr, Minv, lg_t, bc, h_t, omega, nu1, nu2);
+    for (int g = threadIdx.x; g < m * m; g += Tail<D>::NT) Ms[(g % m) * mp + g / m] = Minv[g];
+    tail_cycle<D, S, Tail<D>::NT>(xs, fs, ts, f_t, x_t, nullptr, Ms, lg_t, bc, h_t, omega, nu1, nu2, 1, mp);
 }
 
 }  // namespace np
