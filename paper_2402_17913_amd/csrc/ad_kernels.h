@@ -386,6 +386,52 @@ struct AdLevels {
     AdW w[12];
 };
 
+// One relaxed-Jacobi sweep T = X + wd (F - A X) (RESID: the residual T = F - A X)
+// of a level of k_ad_tail, all three in LDS.  Each thread marches along the
+// last axis over a run of one column's cells (neighbours along that axis from
+// registers, in-plane offsets fixed per column); same terms and grouping as
+// ad_ax.  Needs n^(D-1) <= NT.
+template <int D, int NT, bool RESID>
+__device__ __forceinline__ void ad_tail_sweep(const double *__restrict__ X, const double *__restrict__ F,
+                                              double *__restrict__ T, int lg, int bc, const AdW &W, double wd) {
+    const int n = 1 << lg, last = n - 1, sm = D == 3 ? n * n : n;
+    const int chunks = NT / sm < n ? NT / sm : n, len = n / chunks;
+    const int t = threadIdx.x;
+    if (t < sm * chunks) {
+        const bool per = bc != 0;
+        const int i = t & last, j = D == 3 ? (t >> lg) & last : 0, z0 = (t / sm) * len;
+        const int oxm = i > 0 ? -1 : (per ? last : 0), oxp = i < last ? 1 : (per ? -last : 0);
+        const bool fxm = i > 0 || per, fxp = i < last || per;
+        const int oym = j > 0 ? -n : (per ? last * n : 0), oyp = j < last ? n : (per ? -last * n : 0);
+        const bool fym = j > 0 || per, fyp = j < last || per;
+        int c = z0 * sm + (t & (sm - 1));
+        double xc = X[c];
+        double zm = X[z0 > 0 ? c - sm : (per ? c + last * sm : c)];
+        bool fzm = z0 > 0 || per;
+        for (int z = z0; z < z0 + len; ++z, c += sm) {
+            const double zp = X[z < last ? c + sm : (per ? c - last * sm : c)];
+            const bool fzp = z < last || per;
+            const double rxm = X[c + oxm], rxp = X[c + oxp];  // unconditional: no branch around a load
+            const double xm = fxm ? rxm : -xc, xp = fxp ? rxp : -xc;
+            const double am = fzm ? zm : -xc, ap = fzp ? zp : -xc;  // along the marching axis
+            double s;
+            if (D == 3) {
+                const double rym = X[c + oym], ryp = X[c + oyp];
+                const double ym = fym ? rym : -xc, yp = fyp ? ryp : -xc;
+                s = W.c0 * xc + (W.cm[0] * xm + W.cp[0] * xp) + (W.cm[1] * ym + W.cp[1] * yp);
+                s += W.cm[2] * am + W.cp[2] * ap;
+            } else {
+                s = W.c0 * xc + (W.cm[0] * xm + W.cp[0] * xp) + (W.cm[1] * am + W.cp[1] * ap);
+            }
+            if (RESID) T[c] = F[c] - s;
+            else T[c] = xc + wd * (F[c] - s);
+            zm = xc;
+            fzm = true;
+            xc = zp;
+        }
+    }
+}
+
 // V(nu1, nu2) cycle on levels lg_t .. 2 (coarsest 4^d) in one workgroup,
 // every level in LDS, from a zero iterate on every level (the levels below
 // the finest ones of a cycle): first sweep x = wdiag f, nu1 - 1 further
@@ -398,38 +444,61 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_ad_tail(const double *__restric
                                                          AdLevels Wl, double omega, int nu1, int nu2,
                                                          const int *stop) {
     constexpr int NT = Tail<D>::NT;
+    static_assert(Tail<D>::cells(Tail<D>::LG) >> Tail<D>::LG <= NT, "ad_tail_sweep needs n^(D-1) <= NT");
     __shared__ double xs[Tail<D>::levels_sum()];
     __shared__ double fs[Tail<D>::levels_sum()];
     __shared__ double ts[Tail<D>::cells(Tail<D>::LG)];
+    // the coarsest inverse, transposed with padded rows (thread i reading entry
+    // (i, q) hits consecutive banks); its loads go out with the right-hand side's
+    constexpr int mq = D == 3 ? 64 : 16, mp = mq + 1;
+    __shared__ double Ms[mq * mp];
     if (stop && *stop) return;
     const int tid = threadIdx.x;
     auto off = [&](int l) -> int64_t {  // level l follows the finer levels lg_t .. l + 1
         return ((int64_t(1) << (D * (lg_t + 1))) - (int64_t(1) << (D * (l + 1)))) / ((int64_t(1) << D) - 1);
     };
-    const int64_t mt = int64_t(1) << (D * lg_t);
-    for (int64_t c = tid; c < mt; c += NT) fs[c] = f_t[c];
+    const int mt = 1 << (D * lg_t);
+    {
+        constexpr int per = int(Tail<D>::cells(Tail<D>::LG) / NT);
+        double fv[per];
+#pragma unroll
+        for (int u = 0; u < per; ++u)
+            if (tid + u * NT < mt) fv[u] = f_t[tid + u * NT];
+        for (int g = tid; g < mq * mq; g += NT) Ms[(g % mq) * mp + g / mq] = Minv[g];
+#pragma unroll
+        for (int u = 0; u < per; ++u)
+            if (tid + u * NT < mt) fs[tid + u * NT] = fv[u];
+    }
     __syncthreads();
+    // cnt sweeps alternating between X and ts; the result ends in X
+    auto sweeps = [&](double *X, const double *F, int lg, const AdW &W, double wd, int cnt) {
+        double *cur = X, *nxt = ts;
+        for (int it = 0; it < cnt; ++it) {
+            ad_tail_sweep<D, NT, false>(cur, F, nxt, lg, bc, W, wd);
+            __syncthreads();
+            double *t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        if (cur != X) {
+            for (int c = tid; c < (1 << (D * lg)); c += NT) X[c] = cur[c];
+            __syncthreads();
+        }
+    };
     for (int lg = lg_t; lg > 2; --lg) {
-        const int64_t m = int64_t(1) << (D * lg);
+        const int m = 1 << (D * lg);
         double *X = xs + off(lg), *F = fs + off(lg);
         const AdW W = Wl.w[lg_t - lg];
         const double wd = omega / W.c0;
-        for (int64_t c = tid; c < m; c += NT) X[c] = wd * F[c];
+        for (int c = tid; c < m; c += NT) X[c] = wd * F[c];
         __syncthreads();
-        for (int it = 1; it < nu1; ++it) {
-            for (int64_t c = tid; c < m; c += NT) {
-                int i, j, k;
-                decode<D>(c, lg, i, j, k);
-                ts[c] = X[c] + wd * (F[c] - ad_ax<D>(X, c, i, j, k, lg, bc, W));
-            }
-            __syncthreads();
-            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
-            __syncthreads();
-        }
-        const int lgc = lg - 1;
-        const int64_t mc = int64_t(1) << (D * lgc);
+        sweeps(X, F, lg, W, wd, nu1 - 1);
+        // residual into ts, then its 2^d-cell average into the next level's rhs
+        ad_tail_sweep<D, NT, true>(X, F, ts, lg, bc, W, wd);
+        __syncthreads();
+        const int lgc = lg - 1, mc = 1 << (D * lgc);
         double *Fc = fs + off(lgc);
-        for (int64_t cc = tid; cc < mc; cc += NT) {
+        for (int cc = tid; cc < mc; cc += NT) {
             int I, J, K;
             decode<D>(cc, lgc, I, J, K);
             double acc = 0.0;
@@ -437,61 +506,30 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_ad_tail(const double *__restric
                 for (int jj = 0; jj < 2; ++jj)
                     for (int ii = 0; ii < 2; ++ii) {
                         const int i = 2 * I + ii, j = 2 * J + jj, k = D == 3 ? 2 * K + kk : 0;
-                        const int64_t cf = (int64_t(k) << (2 * lg)) | (int64_t(j) << lg) | i;
-                        acc += F[cf] - ad_ax<D>(X, cf, i, j, k, lg, bc, W);
+                        acc += ts[(k << (2 * lg)) | (j << lg) | i];
                     }
             Fc[cc] = acc * (D == 3 ? 0.125 : 0.25);
         }
         __syncthreads();
     }
     {
-        constexpr int m = D == 3 ? 64 : 16;
         double *X = xs + off(2), *F = fs + off(2);
-        if (tid < m) {
+        if (tid < mq) {
             double acc = 0.0;
-            for (int q = 0; q < m; ++q) acc += Minv[tid * m + q] * F[q];
+            for (int q = 0; q < mq; ++q) acc += Ms[tid + q * mp] * F[q];
             X[tid] = acc;
         }
         __syncthreads();
     }
     for (int lg = 3; lg <= lg_t; ++lg) {
-        const int64_t m = int64_t(1) << (D * lg);
-        const int lgc = lg - 1, nc = 1 << lgc;
+        const int lgc = lg - 1;
         double *X = xs + off(lg), *F = fs + off(lg), *E = xs + off(lgc);
         const AdW W = Wl.w[lg_t - lg];
-        const double wd = omega / W.c0;
-        for (int64_t c = tid; c < m; c += NT) {
-            int i, j, k;
-            decode<D>(c, lg, i, j, k);
-            int oi, ni, oj, nj, ok = 0, nk = 0;
-            float si, sj, sk = 1.0f;
-            pro_axis(i, nc, bc, oi, ni, si);
-            pro_axis(j, nc, bc, oj, nj, sj);
-            if (D == 3) pro_axis(k, nc, bc, ok, nk, sk);
-            double s = 0.0;
-            for (int cz = 0; cz < (D == 3 ? 2 : 1); ++cz)
-                for (int b = 0; b < 2; ++b)
-                    for (int a = 0; a < 2; ++a) {
-                        const double w = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (D == 3 ? (cz ? 0.25 : 0.75) : 1.0);
-                        const double sg = double((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
-                        s += w * (sg * E[(int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
-                                         (a ? ni : oi)]);
-                    }
-            X[c] += s;
-        }
+        tail_prolong<D, double, NT>(E, X, lg, bc);
         __syncthreads();
-        for (int it = 0; it < nu2; ++it) {
-            for (int64_t c = tid; c < m; c += NT) {
-                int i, j, k;
-                decode<D>(c, lg, i, j, k);
-                ts[c] = X[c] + wd * (F[c] - ad_ax<D>(X, c, i, j, k, lg, bc, W));
-            }
-            __syncthreads();
-            for (int64_t c = tid; c < m; c += NT) X[c] = ts[c];
-            __syncthreads();
-        }
+        sweeps(X, F, lg, W, omega / W.c0, nu2);
     }
-    for (int64_t c = tid; c < mt; c += NT) x_t[c] = xs[c];
+    for (int c = tid; c < mt; c += NT) x_t[c] = xs[c];
 }
 
 // Partials of ||a - b||_1 (||a||_1 when b is null) over a strided grid (fixed
