@@ -649,13 +649,15 @@ template <int D, class S> struct Ops {
                 // from a zero iterate: the first two sweeps in one pass where there are two
                 const int zm = zf && it == 0 ? (o.nu1 >= 2 && g_tune.zero2 ? 2 : 1) : 0;
                 int nb = 0;
-                NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, zm, ck ? H->red : nullptr, &nb, s, l == 0,
-                             stop));
+                // a sweep from a zero iterate reads no iterate: it writes in place, which saves the
+                // copy back into the caller's buffer at the end of the cycle
+                NP_TRY(sweep(F[l], zm ? nullptr : cur[l], zm ? cur[l] : oth[l], lg, bc, hl, o.omega, zm,
+                             ck ? H->red : nullptr, &nb, s, l == 0, stop));
                 if (ck) {
                     hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
                     NP_LAUNCH_CHECK();
                 }
-                std::swap(cur[l], oth[l]);
+                if (!zm) std::swap(cur[l], oth[l]);
                 if (zm == 2) ++it;
             }
             NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
