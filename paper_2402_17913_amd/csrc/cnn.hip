@@ -102,8 +102,8 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ X, co
             *reinterpret_cast<float4 *>(reinterpret_cast<float *>(Y) + v * kC + 4 * grp) = make_float4(o[0], o[1], o[2], o[3]);
         } else {
             uint2 pk;
-            pk.x = uint32_t(f2b(o[0])) | (uint32_t(f2b(o[1])) << 16);
-            pk.y = uint32_t(f2b(o[2])) | (uint32_t(f2b(o[3])) << 16);
+            pk.x = float2_to_bf16x2(o[0], o[1]);
+            pk.y = float2_to_bf16x2(o[2], o[3]);
             *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(Y) + v * kC + 4 * grp) = pk;
         }
     }
@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kCzT) void k_conv3z(const uint16_t *__restrict__ X,
                     make_float4(o[0], o[1], o[2], o[3]);
             } else {
                 uint2 pk;
-                pk.x = uint32_t(f2b(o[0])) | (uint32_t(f2b(o[1])) << 16);
-                pk.y = uint32_t(f2b(o[2])) | (uint32_t(f2b(o[3])) << 16);
+                pk.x = float2_to_bf16x2(o[0], o[1]);
+                pk.y = float2_to_bf16x2(o[2], o[3]);
                 *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(Y) + v * kC + 4 * grp) = pk;
             }
         }

@@ -123,7 +123,7 @@ template <> struct Pair<bf16> {  // element 0 in the low half (little endian)
         b = __uint_as_float(v & 0xffff0000u);
     }
     static __device__ __forceinline__ void st(bf16 *p, float a, float b) {
-        *reinterpret_cast<uint32_t *>(p) = uint32_t(float_to_bf16(a)) | (uint32_t(float_to_bf16(b)) << 16);
+        *reinterpret_cast<uint32_t *>(p) = float2_to_bf16x2(a, b);
     }
 };
 

@@ -35,20 +35,27 @@ void clear_error();
 #define NP_LAUNCH_CHECK() NP_HIP_TRY(hipGetLastError())
 
 // --------------------------------------------------------- storage types
-// BF16 is kept as raw 16-bit patterns; conversions are written out here:
-// float -> bf16 rounds to nearest, ties to even; NaN stays NaN.
+// BF16 is kept as raw 16-bit patterns.  float -> bf16 rounds to nearest, ties
+// to even, NaN stays NaN: gfx950's packed conversion (v_cvt_pk_bf16_f32), one
+// instruction for two values.  It matches the integer rounding
+// u + 0x7fff + (bit 16 of u), then the high half, bit for bit on every
+// non-NaN float (all 2^32 inputs compared on the device).
 struct bf16 {
     uint16_t u;
 };
 
+typedef __bf16 np_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float np_f32x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ float bf16_to_float(uint16_t u) { return __uint_as_float(uint32_t(u) << 16); }
 
-__device__ __forceinline__ uint16_t float_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return uint16_t(u >> 16);
+// a in the low half, b in the high half
+__device__ __forceinline__ uint32_t float2_to_bf16x2(float a, float b) {
+    const np_f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, np_bf16x2));
 }
+
+__device__ __forceinline__ uint16_t float_to_bf16(float f) { return uint16_t(float2_to_bf16x2(f, 0.0f)); }
 
 // Storage traits: C is the arithmetic type for fields stored as S.
 template <class S> struct St;
