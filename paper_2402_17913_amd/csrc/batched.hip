@@ -300,6 +300,270 @@ __global__ __launch_bounds__(kBlock) void kb_prolong(const S *__restrict__ Ec, S
     St<S>::st(x + c, St<S>::ld(x + c) + s);
 }
 
+// ------------------------------------------------------- row-marching tiles
+// Level kernels of the depths above the tail (n >= 128), marching along y: a
+// workgroup of kRmT threads is G = kRmT / TT groups of TT = min(n, 2 kRmT) / 2
+// threads; each thread owns two adjacent columns (one vector access per row)
+// and a group marches ry consecutive rows of one problem's grid, keeping rows
+// j - 1, j, j + 1 of its columns in registers.  Column neighbours come from a
+// row published in LDS (one barrier per row, two alternating buffers); the
+// strip's edge threads load the cell beyond the strip.  Same terms, signs and
+// summation orders as kb_sweep, kb_restrict and kb_prolong (Dirichlet ghosts).
+constexpr int kRmT = 256;
+constexpr int kRmBuf = 2 * kRmT + 2 * (kRmT / 64);  // G <= 4 groups (n >= 128) of 2 tt + 2 values
+
+struct RmTile {
+    int lg, n, tt, grp, l, i0, j0, slot;
+};
+
+// ry rows per group; the grid is slots x strips x row blocks
+__device__ __forceinline__ RmTile rm_tile(int k, int ry) {
+    RmTile t;
+    t.lg = k + 2;
+    t.n = 1 << t.lg;
+    const int tw = t.n < 2 * kRmT ? t.n : 2 * kRmT;  // columns per group
+    t.tt = tw / 2;
+    const int G = kRmT / t.tt, strips = t.n / tw, rblk = t.n / (G * ry), per = strips * rblk;
+    t.slot = int(blockIdx.x) / per;
+    const int b = int(blockIdx.x) % per, strip = b % strips, rb = b / strips;
+    t.grp = int(threadIdx.x) / t.tt;
+    t.l = int(threadIdx.x) % t.tt;
+    t.i0 = strip * tw + 2 * t.l;
+    t.j0 = (rb * G + t.grp) * ry;
+    return t;
+}
+
+inline unsigned rm_grid(int k, int ry, unsigned nsl) {
+    const int n = 1 << (k + 2), tw = n < 2 * kRmT ? n : 2 * kRmT, G = kRmT / (tw / 2);
+    return nsl * unsigned(n / tw) * unsigned(n / (G * ry));
+}
+
+// Rows per group: enough workgroups to fill the chip, at least 4 rows.
+inline int rm_rows(int k, unsigned nsl) {
+    int ry = 32;
+    while (rm_grid(k, ry, nsl) < 4096u && ry > 4) ry /= 2;
+    return ry;
+}
+
+// Marching state of one thread: its two cells on rows j - 1, j, j + 1 and the
+// value beyond the strip edge on row j (edge threads only).
+template <class S> struct RmRow {
+    typedef typename St<S>::C C;
+    const S *x;
+    int lg, last, i0, hcol;
+    bool hl, hr;  // this thread loads the left / right edge value
+    C hsg;
+    C m0, m1, c0, c1, p0, p1, hv;     // rows j - 1, j, j + 1; edge value of row j
+    C q0, q1, hn;                     // prefetched: row j + 2, edge value of row j + 1
+    __device__ RmRow(const S *x_, const RmTile &t) : x(x_), lg(t.lg), last(t.n - 1), i0(t.i0) {
+        hl = t.l == 0;
+        hr = t.l == t.tt - 1;
+        int hc = hl ? i0 - 1 : i0 + 2;
+        hsg = C(1);
+        if (hc < 0 || hc > last) {  // Dirichlet ghost: the edge cell itself, negated
+            hc = hc < 0 ? 0 : last;
+            hsg = C(-1);
+        }
+        hcol = hc;
+    }
+    __device__ __forceinline__ int64_t at(int j) const { return (int64_t(j) << lg) + i0; }
+    __device__ __forceinline__ C edge(int j) const {
+        return (hl || hr) ? hsg * St<S>::ld(x + ((int64_t(j) << lg) + hcol)) : C(0);
+    }
+    __device__ __forceinline__ void start(int j0) {
+        Pair<S>::ld(x + at(j0), c0, c1);
+        C a, b;
+        Pair<S>::ld(x + at(j0 > 0 ? j0 - 1 : j0), a, b);
+        m0 = j0 > 0 ? a : -c0;
+        m1 = j0 > 0 ? b : -c1;
+        Pair<S>::ld(x + at(j0 < last ? j0 + 1 : j0), a, b);
+        p0 = j0 < last ? a : -c0;
+        p1 = j0 < last ? b : -c1;
+        hv = edge(j0);
+    }
+    // loads for the row after j (row j + 2 and the edge value of row j + 1)
+    __device__ __forceinline__ void prefetch(int j) {
+        const int j2 = j + 2 <= last ? j + 2 : last, j1 = j + 1 <= last ? j + 1 : last;
+        C a, b;
+        Pair<S>::ld(x + at(j2), a, b);
+        q0 = j + 2 <= last ? a : -p0;
+        q1 = j + 2 <= last ? b : -p1;
+        hn = edge(j1);
+    }
+    // publish row j into buf (tt + 1 pairs wide, pair index l + 1) and form the
+    // neighbour sums of the two cells
+    __device__ __forceinline__ void sums(C *buf, int l, int tt, C &s0, C &s1) const {
+        buf[2 * l + 1] = c0;
+        buf[2 * l + 2] = c1;
+        if (hl) buf[0] = hv;
+        if (hr) buf[2 * tt + 1] = hv;
+        __syncthreads();
+        s0 = ((buf[2 * l] + c1) + m0) + p0;
+        s1 = ((c0 + buf[2 * l + 3]) + m1) + p1;
+    }
+    __device__ __forceinline__ void advance() {
+        m0 = c0;
+        m1 = c1;
+        c0 = p0;
+        c1 = p1;
+        p0 = q0;
+        p1 = q1;
+        hv = hn;
+    }
+};
+
+template <class S>
+__global__ __launch_bounds__(kRmT) void kb_sweep_rm(const S *__restrict__ F, const S *__restrict__ Xin,
+                                                    S *__restrict__ Xout, const int *__restrict__ slot_prob,
+                                                    const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                    const BGlobal *__restrict__ g, int k, int first, int cyc,
+                                                    double omega, int ry) {
+    typedef typename St<S>::C C;
+    __shared__ C buf[2][kRmBuf];  // two alternating rows per workgroup; group g at offset g (2 tt + 2)
+    const RmTile t = rm_tile(k, ry);
+    const int p = slot_prob[t.slot];
+    if (g->stop || st[p].stop) return;
+    const double h = depth_h(P[p], k);
+    const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / 4.0);
+    const bool zero = first && (k < P[p].L || cyc == 0);
+    const int64_t so = int64_t(t.slot) << (2 * t.lg);
+    const S *f = F + so;
+    S *xout = Xout + so;
+    if (zero) {
+        for (int j = t.j0; j < t.j0 + ry; ++j) {
+            const int64_t c = (int64_t(j) << t.lg) + t.i0;
+            C a, b;
+            Pair<S>::ld(f + c, a, b);
+            Pair<S>::st(xout + c, wdiag * a, wdiag * b);
+        }
+        return;
+    }
+    RmRow<S> r(Xin + so, t);
+    r.start(t.j0);
+    C f0, f1;
+    Pair<S>::ld(f + r.at(t.j0), f0, f1);
+    const int go = t.grp * (2 * t.tt + 2);
+    for (int j = t.j0, q = 0; j < t.j0 + ry; ++j, q ^= 1) {
+        r.prefetch(j);
+        C g0, g1;
+        Pair<S>::ld(f + r.at(j + 1 <= r.last ? j + 1 : r.last), g0, g1);
+        C s0, s1;
+        r.sums(buf[q] + go, t.l, t.tt, s0, s1);
+        const C o0 = r.c0 + wdiag * (f0 - (C(4) * r.c0 - s0) * inv_h2);
+        const C o1 = r.c1 + wdiag * (f1 - (C(4) * r.c1 - s1) * inv_h2);
+        Pair<S>::st(xout + r.at(j), o0, o1);
+        f0 = g0;
+        f1 = g1;
+        r.advance();
+    }
+}
+
+// Residual at depth k averaged into depth k - 1: each thread's column pair is
+// one coarse column, each pair of rows one coarse row.  ry even.
+template <class S>
+__global__ __launch_bounds__(kRmT) void kb_restrict_rm(const S *__restrict__ F, const S *__restrict__ X,
+                                                       S *__restrict__ Fc, const int *__restrict__ slot_prob,
+                                                       const BProb *__restrict__ P, const BState *__restrict__ st,
+                                                       const BGlobal *__restrict__ g, int k, int ry) {
+    typedef typename St<S>::C C;
+    __shared__ C buf[2][kRmBuf];
+    const RmTile t = rm_tile(k, ry);
+    const int p = slot_prob[t.slot];
+    if (g->stop || st[p].stop) return;
+    const double h = depth_h(P[p], k);
+    const C inv_h2 = C(1.0 / (h * h));
+    const int64_t so = int64_t(t.slot) << (2 * t.lg);
+    const S *f = F + so;
+    const int lgc = t.lg - 1;
+    S *fc = Fc + (int64_t(P[p].slot[k - 1]) << (2 * lgc));
+    RmRow<S> r(X + so, t);
+    r.start(t.j0);
+    C f0, f1;
+    Pair<S>::ld(f + r.at(t.j0), f0, f1);
+    const int go = t.grp * (2 * t.tt + 2);
+    C acc = C(0);
+    for (int j = t.j0, q = 0; j < t.j0 + ry; ++j, q ^= 1) {
+        r.prefetch(j);
+        C g0, g1;
+        Pair<S>::ld(f + r.at(j + 1 <= r.last ? j + 1 : r.last), g0, g1);
+        C s0, s1;
+        r.sums(buf[q] + go, t.l, t.tt, s0, s1);
+        const C r0 = f0 - (C(4) * r.c0 - s0) * inv_h2;
+        const C r1 = f1 - (C(4) * r.c1 - s1) * inv_h2;
+        if (!(j & 1)) acc = C(0);
+        acc += r0;
+        acc += r1;
+        if (j & 1) St<S>::st(fc + ((int64_t(j >> 1) << lgc) + (t.i0 >> 1)), acc * C(0.25));
+        f0 = g0;
+        f1 = g1;
+        r.advance();
+    }
+}
+
+// x(depth k) += P e(depth k - 1): each thread's column pair shares its own
+// coarse column; coarse rows J - 1, J, J + 1 (three values each: columns
+// I - 1, I, I + 1, clamped; ghost signs applied per term) stay in registers.
+template <class S>
+__global__ __launch_bounds__(kRmT) void kb_prolong_rm(const S *__restrict__ Ec, S *__restrict__ X,
+                                                      const int *__restrict__ slot_prob, const BProb *__restrict__ P,
+                                                      const BState *__restrict__ st, const BGlobal *__restrict__ g,
+                                                      int k, int ry) {
+    typedef typename St<S>::C C;
+    const RmTile t = rm_tile(k, ry);
+    const int p = slot_prob[t.slot];
+    if (g->stop || st[p].stop) return;
+    const int lgc = t.lg - 1, nc = t.n >> 1, I = t.i0 >> 1;
+    const S *ec = Ec + (int64_t(P[p].slot[k - 1]) << (2 * lgc));
+    S *x = X + (int64_t(t.slot) << (2 * t.lg));
+    // columns: own I; left neighbour (ghost at I = 0: own, sign -1); right (ghost at nc - 1)
+    const int cl = I > 0 ? I - 1 : 0, cr = I < nc - 1 ? I + 1 : nc - 1;
+    const float sl = I > 0 ? 1.0f : -1.0f, sr = I < nc - 1 ? 1.0f : -1.0f;
+    auto row = [&](int J, C &a, C &b, C &c) {
+        const S *e = ec + (int64_t(J) << lgc);
+        a = St<S>::ld(e + cl);
+        b = St<S>::ld(e + I);
+        c = St<S>::ld(e + cr);
+    };
+    const int J0 = t.j0 >> 1;
+    C ma, mb, mc, ca, cb, cc, pa, pb, pc;
+    row(J0 > 0 ? J0 - 1 : 0, ma, mb, mc);
+    row(J0, ca, cb, cc);
+    row(J0 < nc - 1 ? J0 + 1 : nc - 1, pa, pb, pc);
+    const C w00 = C(0.75) * C(0.75) * C(1.0), w10 = C(0.25) * C(0.75) * C(1.0);
+    const C w01 = C(0.75) * C(0.25) * C(1.0), w11 = C(0.25) * C(0.25) * C(1.0);
+    for (int J = J0; J < J0 + ry / 2; ++J) {
+        C na = C(0), nb = C(0), ncv = C(0);
+        if (J + 1 < J0 + ry / 2) row(J + 2 <= nc - 1 ? J + 2 : nc - 1, na, nb, ncv);
+        for (int dy = 0; dy < 2; ++dy) {
+            const int j = 2 * J + dy;
+            // neighbour coarse row and its sign
+            const bool ghost = dy ? J == nc - 1 : J == 0;
+            const float sj = ghost ? -1.0f : 1.0f;
+            const C ra = dy ? pa : ma, rb = dy ? pb : mb, rc = dy ? pc : mc;
+            C v0, v1;
+            Pair<S>::ld(x + ((int64_t(j) << t.lg) + t.i0), v0, v1);
+            // left fine cell: own column I, neighbour I - 1
+            C s = C(0);
+            s += w00 * (C(1.0f * 1.0f * 1.0f) * cb);
+            s += w10 * (C(sl * 1.0f * 1.0f) * ca);
+            s += w01 * (C(1.0f * sj * 1.0f) * rb);
+            s += w11 * (C(sl * sj * 1.0f) * ra);
+            // right fine cell: own column I, neighbour I + 1
+            C u = C(0);
+            u += w00 * (C(1.0f * 1.0f * 1.0f) * cb);
+            u += w10 * (C(sr * 1.0f * 1.0f) * cc);
+            u += w01 * (C(1.0f * sj * 1.0f) * rb);
+            u += w11 * (C(sr * sj * 1.0f) * rc);
+            Pair<S>::st(x + ((int64_t(j) << t.lg) + t.i0), v0 + s, v1 + u);
+        }
+        // rows J, J + 1, J + 2 become J - 1, J, J + 1 (a ghost row J + 1 = J at the top is J itself)
+        const bool top = J + 1 == nc - 1;
+        ma = ca; mb = cb; mc = cc;
+        ca = pa; cb = pb; cc = pc;
+        pa = top ? ca : na; pb = top ? cb : nb; pc = top ? cc : ncv;
+    }
+}
+
 // Depths min(L_p, kTailDepth) .. 0 of every problem, one workgroup each.
 template <class S>
 __global__ __launch_bounds__(Tail<2>::NT) void kb_tail(S *const *Xpool, S *const *Fpool, const double *__restrict__ Minv1,
@@ -351,7 +615,7 @@ struct Plan {
     std::vector<double *> y;                   // host copy of the pool pointers
     std::vector<double> h;                     // finest spacing per problem (for graph keys)
     hipStream_t cap = nullptr;
-    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (kind, inner, nu1, nu2, omega bits)
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;  // (kind, inner, nu1, nu2, omega bits)
     std::mutex mu;
 };
 
@@ -495,16 +759,25 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
             const int64_t m = int64_t(1) << (2 * (k + 2));
             S *cur = (S *)B->X[k], *oth = (S *)B->T[k];
             const S *F = (const S *)B->F[k];
+            const int ry = rm_rows(k, nsl);
             for (int it = 0; it < o.nu1; ++it) {
-                hipLaunchKernelGGL((kb_sweep<S>), dim3(unsigned(nsl * ((m + kSweepCells - 1) / kSweepCells))),
-                                   dim3(kBlock), 0, s, F, cur, oth, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k,
-                                   it == 0 ? 1 : 0, c, o.omega);
+                if (g_batched_rm)
+                    hipLaunchKernelGGL((kb_sweep_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s, F, cur, oth,
+                                       B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, it == 0 ? 1 : 0, c, o.omega, ry);
+                else
+                    hipLaunchKernelGGL((kb_sweep<S>), dim3(unsigned(nsl * ((m + kSweepCells - 1) / kSweepCells))),
+                                       dim3(kBlock), 0, s, F, cur, oth, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k,
+                                       it == 0 ? 1 : 0, c, o.omega);
                 NP_LAUNCH_CHECK();
                 std::swap(cur, oth);
             }
             const int n = 1 << (k + 2);
-            hipLaunchKernelGGL((kb_restrict<S>), dim3(unsigned(nsl * (n / RBlk<2>::FX) * (n / 2))), dim3(kBlock), 0, s,
-                               F, cur, (S *)B->F[k - 1], B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
+            if (g_batched_rm)
+                hipLaunchKernelGGL((kb_restrict_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s, F, cur,
+                                   (S *)B->F[k - 1], B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, ry);
+            else
+                hipLaunchKernelGGL((kb_restrict<S>), dim3(unsigned(nsl * (n / RBlk<2>::FX) * (n / 2))), dim3(kBlock), 0,
+                                   s, F, cur, (S *)B->F[k - 1], B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
             NP_LAUNCH_CHECK();
         }
         hipLaunchKernelGGL((kb_tail<S>), dim3(B->nprob), dim3(Tail<2>::NT), 0, s, Xp, Fp, B->d_Minv1, B->d_P,
@@ -516,13 +789,23 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
             // after an odd number of pre-sweeps the iterate sits in T
             S *cur = (o.nu1 & 1) ? (S *)B->T[k] : (S *)B->X[k];
             S *oth = (o.nu1 & 1) ? (S *)B->X[k] : (S *)B->T[k];
-            hipLaunchKernelGGL((kb_prolong<S>), dim3(unsigned(nsl * (m / kBlock))), dim3(kBlock), 0, s,
-                               (const S *)B->X[k - 1], cur, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
+            const int ry = rm_rows(k, nsl);
+            if (g_batched_rm)
+                hipLaunchKernelGGL((kb_prolong_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s,
+                                   (const S *)B->X[k - 1], cur, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, ry);
+            else
+                hipLaunchKernelGGL((kb_prolong<S>), dim3(unsigned(nsl * (m / kBlock))), dim3(kBlock), 0, s,
+                                   (const S *)B->X[k - 1], cur, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
             NP_LAUNCH_CHECK();
             for (int it = 0; it < o.nu2; ++it) {
-                hipLaunchKernelGGL((kb_sweep<S>), dim3(unsigned(nsl * ((m + kSweepCells - 1) / kSweepCells))),
-                                   dim3(kBlock), 0, s, (const S *)B->F[k], cur, oth, B->d_slot_prob[k], B->d_P,
-                                   B->d_st, B->d_g, k, 0, c, o.omega);
+                if (g_batched_rm)
+                    hipLaunchKernelGGL((kb_sweep_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s,
+                                       (const S *)B->F[k], cur, oth, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, 0,
+                                       c, o.omega, ry);
+                else
+                    hipLaunchKernelGGL((kb_sweep<S>), dim3(unsigned(nsl * ((m + kSweepCells - 1) / kSweepCells))),
+                                       dim3(kBlock), 0, s, (const S *)B->F[k], cur, oth, B->d_slot_prob[k], B->d_P,
+                                       B->d_st, B->d_g, k, 0, c, o.omega);
                 NP_LAUNCH_CHECK();
                 std::swap(cur, oth);
             }
@@ -536,7 +819,7 @@ np_status run_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t s) 
     if (!g_batched_graphs) return enqueue_step<S>(B, kind, inner, o, s);
     int64_t ob;
     std::memcpy(&ob, &o.omega, sizeof ob);
-    const auto key = std::make_tuple(kind, inner, o.nu1, o.nu2, int(ob ^ (ob >> 32)));
+    const auto key = std::make_tuple(kind, inner, o.nu1, o.nu2, int(ob ^ (ob >> 32)), g_batched_rm);
     auto it = B->graphs.find(key);
     if (it == B->graphs.end()) {
         NP_HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
@@ -606,6 +889,7 @@ np_status batched_run(Plan *B, int inner, const BOpts &o, const np_mg_opts &mo, 
 
 int g_batched_graphs = 1;
 int g_batched_autotune = 1;
+int g_batched_rm = 1;
 static thread_local int g_last_tune_inner = 0;
 static thread_local double g_last_tune_ms = 0.0;
 

@@ -1115,6 +1115,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
+        {"batched_rm", &g_batched_rm, 0, 1},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
     };
     for (auto &e : tab)
@@ -1156,6 +1157,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "zero2")) return g_tune.zero2;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
+    if (!std::strcmp(key, "batched_rm")) return g_batched_rm;
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
     if (!std::strcmp(key, "zc3")) return g_zc3;
     if (!std::strcmp(key, "conv3z")) return g_conv3z;

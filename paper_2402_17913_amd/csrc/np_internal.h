@@ -142,6 +142,7 @@ void release_ns_cache();
 void release_batched_cache();
 extern int g_batched_graphs;
 extern int g_batched_autotune;
+extern int g_batched_rm;
 extern int g_zmarch_explicit;
 extern int g_conv3z;
 extern int g_zc3;  // planes per workgroup of the 3D z-marching solver kernels (0: automatic)

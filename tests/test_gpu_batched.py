@@ -68,6 +68,29 @@ def test_batched_fp32_reaches_tolerance_and_matches_solo(B, orc):
         assert rel(xi, host(xs)) < 1e-9
 
 
+@pytest.mark.parametrize("prec", ["FP32", "FP64"])
+def test_batched_row_marching_kernels_bit_identical(B, prec):
+    """The row-marching level kernels (depths with n >= 128) compute the same terms in
+    the same order as the one-cell-per-thread ones: identical iterates after fixed
+    refinement steps, on sizes that give one, two and four row groups per workgroup
+    (n = 128, 256, >= 512) and several problems per depth."""
+    sizes = [128, 256, 512, 1024, 128, 64, 256, 512, 16, 1024, 128]
+    f, h = make(sizes, seed0=3000)
+    out = {}
+    try:
+        for rm in (0, 1):
+            B.np_set_tuning("batched_rm", rm)
+            x = [dev(np.zeros_like(a)) for a in f]
+            B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=getattr(B, prec),
+                                       inner_cycles=2, fixed_cycles=3)
+            out[rm] = [host(t) for t in x]
+    finally:
+        B.np_set_tuning("batched_rm", 1)
+    for n, a, b in zip(sizes, out[0], out[1]):
+        assert np.isfinite(a).all() and np.abs(a).max() > 0, n
+        assert np.array_equal(a, b), (n, rel(b, a))
+
+
 def test_batched_zero_rhs_and_repeat_calls(B, orc):
     import torch
     f, h = make([64, 128, 32], seed0=3000)
