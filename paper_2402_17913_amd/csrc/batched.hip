@@ -82,16 +82,30 @@ __global__ __launch_bounds__(kBlock) void kb_fnorm(const double *const *f, const
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// nf[p] = sqrt(sum of its partials); zero right-hand sides stop at once.
+// Sum of problem p's partials by one wavefront: lane l adds blocks l, l + 64,
+// ...; then a fixed butterfly.  Deterministic; the result is in every lane.
+__device__ __forceinline__ double prob_sum(const double *__restrict__ partial, const BProb &pp) {
+    const int lane = int(threadIdx.x) & 63;
+    double s = 0.0;
+    for (int b = lane; b < pp.nblocks; b += 64) s += partial[pp.first_block + b];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+
+// nf[p] = sqrt(sum of its partials); zero right-hand sides stop at once.  One
+// wavefront per problem.
 __global__ __launch_bounds__(1024) void kb_nf(const double *__restrict__ partial, BProb *__restrict__ P,
                                               BState *__restrict__ st, int nprob) {
-    for (int p = threadIdx.x; p < nprob; p += blockDim.x) {
-        double s = 0.0;
-        for (int b = 0; b < P[p].nblocks; ++b) s += partial[P[p].first_block + b];
-        P[p].nf = sqrt(s);
-        st[p].stop = s == 0.0 ? kConverged : kRunning;
-        st[p].k = 0;
-        st[p].hist[0] = 0.0;
+    const int w = int(threadIdx.x) >> 6, nw = int(blockDim.x) >> 6;
+    for (int p = w; p < nprob; p += nw) {
+        const double s = prob_sum(partial, P[p]);
+        if ((threadIdx.x & 63) == 0) {
+            P[p].nf = sqrt(s);
+            st[p].stop = s == 0.0 ? kConverged : kRunning;
+            st[p].k = 0;
+            st[p].hist[0] = 0.0;
+        }
     }
 }
 
@@ -165,32 +179,42 @@ __global__ __launch_bounds__(kBlock) void kb_ir(BPtrs<SL> ptr, SL *const *epool,
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// Per-problem convergence check after a refinement residual.
-__global__ __launch_bounds__(1024) void kb_check(const double *__restrict__ partial, const BProb *__restrict__ P,
-                                                 BState *__restrict__ st, BGlobal *__restrict__ g, int nprob) {
+// Per-problem convergence check after a refinement residual: one wavefront
+// per problem (grid: nprob / 4 workgroups of 4) sums its partials and its
+// first lane applies the stop rule.
+__global__ __launch_bounds__(256) void kb_check(const double *__restrict__ partial, const BProb *__restrict__ P,
+                                                BState *__restrict__ st, const BGlobal *__restrict__ g, int nprob) {
+    if (g->stop) return;
+    const int p = int(blockIdx.x) * 4 + (int(threadIdx.x) >> 6);
+    if (p >= nprob) return;
+    BState &s = st[p];
+    if (s.stop) return;
+    const double sum = prob_sum(partial, P[p]);
+    if (threadIdx.x & 63) return;
+    const int k = s.k;
+    const double rr = sqrt(sum) / P[p].nf;
+    if (k < kHist) s.hist[k] = rr;
+    int stp = kRunning;
+    if (!(rr <= 1.0e300)) stp = kNonFinite;
+    else if (g->fixed > 0) { if (k >= g->fixed) stp = kFixedDone; }
+    else if (rr <= g->tol) stp = kConverged;
+    else if (k >= g->maxc) stp = kMaxCycles;
+    else if (k >= 3 && k < kHist && s.hist[k - 3] < s.hist[k - 2] && s.hist[k - 2] < s.hist[k - 1] &&
+             s.hist[k - 1] < rr)
+        stp = kDiverged;
+    if (stp != kRunning) s.stop = stp;
+    else s.k = k + 1;
+}
+
+// After kb_check: the whole batch stops once no problem is still running.
+__global__ __launch_bounds__(1024) void kb_check_any(const BState *__restrict__ st, BGlobal *__restrict__ g,
+                                                     int nprob) {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
     if (g->stop) return;
-    for (int p = threadIdx.x; p < nprob; p += blockDim.x) {
-        BState &s = st[p];
-        if (s.stop) continue;
-        double sum = 0.0;
-        for (int b = 0; b < P[p].nblocks; ++b) sum += partial[P[p].first_block + b];
-        const int k = s.k;
-        const double rr = sqrt(sum) / P[p].nf;
-        if (k < kHist) s.hist[k] = rr;
-        int stp = kRunning;
-        if (!(rr <= 1.0e300)) stp = kNonFinite;
-        else if (g->fixed > 0) { if (k >= g->fixed) stp = kFixedDone; }
-        else if (rr <= g->tol) stp = kConverged;
-        else if (k >= g->maxc) stp = kMaxCycles;
-        else if (k >= 3 && k < kHist && s.hist[k - 3] < s.hist[k - 2] && s.hist[k - 2] < s.hist[k - 1] &&
-                 s.hist[k - 1] < rr)
-            stp = kDiverged;
-        if (stp != kRunning) s.stop = stp;
-        else { s.k = k + 1; any = 1; }
-    }
+    for (int p = threadIdx.x; p < nprob; p += blockDim.x)
+        if (st[p].stop == kRunning) any = 1;
     __syncthreads();
     if (threadIdx.x == 0 && !any) g->stop = 1;
 }
@@ -751,7 +775,10 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
     hipLaunchKernelGGL((kb_ir<S>), dim3(B->nblk), dim3(kBlock), 0, s, ptr, Xp, Fp, B->d_blk, B->d_P, B->d_st,
                        B->d_g, B->d_partial, kind == 0 ? 0 : 1);
     NP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(kb_check, dim3(1), dim3(1024), 0, s, B->d_partial, B->d_P, B->d_st, B->d_g, B->nprob);
+    hipLaunchKernelGGL(kb_check, dim3(unsigned((B->nprob + 3) / 4)), dim3(256), 0, s, B->d_partial, B->d_P, B->d_st,
+                       B->d_g, B->nprob);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(kb_check_any, dim3(1), dim3(1024), 0, s, B->d_st, B->d_g, B->nprob);
     NP_LAUNCH_CHECK();
     for (int c = 0; c < inner; ++c) {
         for (int k = B->K; k > kTailDepth; --k) {
