@@ -35,6 +35,7 @@ struct BProb {
     int L;                 // finest depth
     int first_block;       // first refinement block
     int nblocks;           // refinement blocks
+    int ir_first, ir_nblocks;  // the same for the row-marching refinement blocks
     int slot[kMaxDepth + 1];
     double h;              // finest spacing
     double nf;             // ||f||_2
@@ -84,10 +85,10 @@ __global__ __launch_bounds__(kBlock) void kb_fnorm(const double *const *f, const
 
 // Sum of problem p's partials by one wavefront: lane l adds blocks l, l + 64,
 // ...; then a fixed butterfly.  Deterministic; the result is in every lane.
-__device__ __forceinline__ double prob_sum(const double *__restrict__ partial, const BProb &pp) {
+__device__ __forceinline__ double prob_sum(const double *__restrict__ partial, int first, int nb) {
     const int lane = int(threadIdx.x) & 63;
     double s = 0.0;
-    for (int b = lane; b < pp.nblocks; b += 64) s += partial[pp.first_block + b];
+    for (int b = lane; b < nb; b += 64) s += partial[first + b];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     return s;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(1024) void kb_nf(const double *__restrict__ partial
                                               BState *__restrict__ st, int nprob) {
     const int w = int(threadIdx.x) >> 6, nw = int(blockDim.x) >> 6;
     for (int p = w; p < nprob; p += nw) {
-        const double s = prob_sum(partial, P[p]);
+        const double s = prob_sum(partial, P[p].first_block, P[p].nblocks);
         if ((threadIdx.x & 63) == 0) {
             P[p].nf = sqrt(s);
             st[p].stop = s == 0.0 ? kConverged : kRunning;
@@ -180,16 +181,19 @@ __global__ __launch_bounds__(kBlock) void kb_ir(BPtrs<SL> ptr, SL *const *epool,
 }
 
 // Per-problem convergence check after a refinement residual: one wavefront
-// per problem (grid: nprob / 4 workgroups of 4) sums its partials and its
-// first lane applies the stop rule.
+// per problem (grid: nprob / 4 workgroups of 4) sums its partials (of the
+// row-marching refinement blocks when ir_blocks) and its first lane applies
+// the stop rule.
 __global__ __launch_bounds__(256) void kb_check(const double *__restrict__ partial, const BProb *__restrict__ P,
-                                                BState *__restrict__ st, const BGlobal *__restrict__ g, int nprob) {
+                                                BState *__restrict__ st, const BGlobal *__restrict__ g, int nprob,
+                                                int ir_blocks) {
     if (g->stop) return;
     const int p = int(blockIdx.x) * 4 + (int(threadIdx.x) >> 6);
     if (p >= nprob) return;
     BState &s = st[p];
     if (s.stop) return;
-    const double sum = prob_sum(partial, P[p]);
+    const double sum = ir_blocks ? prob_sum(partial, P[p].ir_first, P[p].ir_nblocks)
+                                 : prob_sum(partial, P[p].first_block, P[p].nblocks);
     if (threadIdx.x & 63) return;
     const int k = s.k;
     const double rr = sqrt(sum) / P[p].nf;
@@ -371,15 +375,23 @@ inline int rm_rows(int k, unsigned nsl) {
 
 // Marching state of one thread: its two cells on rows j - 1, j, j + 1 and the
 // value beyond the strip edge on row j (edge threads only).
-template <class S> struct RmRow {
-    typedef typename St<S>::C C;
+// Loads of a level field in storage S for RmRow: a pair at an even index, one value.
+template <class S> struct PairLd {
     const S *x;
+    __device__ __forceinline__ void pair(int64_t q, typename St<S>::C &a, typename St<S>::C &b) const {
+        Pair<S>::ld(x + q, a, b);
+    }
+    __device__ __forceinline__ typename St<S>::C one(int64_t q) const { return St<S>::ld(x + q); }
+};
+
+template <class C, class L> struct RmRow {
+    L ld;
     int lg, last, i0, hcol;
     bool hl, hr;  // this thread loads the left / right edge value
     C hsg;
     C m0, m1, c0, c1, p0, p1, hv;     // rows j - 1, j, j + 1; edge value of row j
     C q0, q1, hn;                     // prefetched: row j + 2, edge value of row j + 1
-    __device__ RmRow(const S *x_, const RmTile &t) : x(x_), lg(t.lg), last(t.n - 1), i0(t.i0) {
+    __device__ RmRow(const L &ld_, const RmTile &t) : ld(ld_), lg(t.lg), last(t.n - 1), i0(t.i0) {
         hl = t.l == 0;
         hr = t.l == t.tt - 1;
         int hc = hl ? i0 - 1 : i0 + 2;
@@ -392,15 +404,15 @@ template <class S> struct RmRow {
     }
     __device__ __forceinline__ int64_t at(int j) const { return (int64_t(j) << lg) + i0; }
     __device__ __forceinline__ C edge(int j) const {
-        return (hl || hr) ? hsg * St<S>::ld(x + ((int64_t(j) << lg) + hcol)) : C(0);
+        return (hl || hr) ? hsg * ld.one((int64_t(j) << lg) + hcol) : C(0);
     }
     __device__ __forceinline__ void start(int j0) {
-        Pair<S>::ld(x + at(j0), c0, c1);
+        ld.pair(at(j0), c0, c1);
         C a, b;
-        Pair<S>::ld(x + at(j0 > 0 ? j0 - 1 : j0), a, b);
+        ld.pair(at(j0 > 0 ? j0 - 1 : j0), a, b);
         m0 = j0 > 0 ? a : -c0;
         m1 = j0 > 0 ? b : -c1;
-        Pair<S>::ld(x + at(j0 < last ? j0 + 1 : j0), a, b);
+        ld.pair(at(j0 < last ? j0 + 1 : j0), a, b);
         p0 = j0 < last ? a : -c0;
         p1 = j0 < last ? b : -c1;
         hv = edge(j0);
@@ -409,7 +421,7 @@ template <class S> struct RmRow {
     __device__ __forceinline__ void prefetch(int j) {
         const int j2 = j + 2 <= last ? j + 2 : last, j1 = j + 1 <= last ? j + 1 : last;
         C a, b;
-        Pair<S>::ld(x + at(j2), a, b);
+        ld.pair(at(j2), a, b);
         q0 = j + 2 <= last ? a : -p0;
         q1 = j + 2 <= last ? b : -p1;
         hn = edge(j1);
@@ -462,7 +474,7 @@ __global__ __launch_bounds__(kRmT) void kb_sweep_rm(const S *__restrict__ F, con
         }
         return;
     }
-    RmRow<S> r(Xin + so, t);
+    RmRow<C, PairLd<S>> r(PairLd<S>{Xin + so}, t);
     r.start(t.j0);
     C f0, f1;
     Pair<S>::ld(f + r.at(t.j0), f0, f1);
@@ -500,7 +512,7 @@ __global__ __launch_bounds__(kRmT) void kb_restrict_rm(const S *__restrict__ F, 
     const S *f = F + so;
     const int lgc = t.lg - 1;
     S *fc = Fc + (int64_t(P[p].slot[k - 1]) << (2 * lgc));
-    RmRow<S> r(X + so, t);
+    RmRow<C, PairLd<S>> r(PairLd<S>{X + so}, t);
     r.start(t.j0);
     C f0, f1;
     Pair<S>::ld(f + r.at(t.j0), f0, f1);
@@ -588,6 +600,105 @@ __global__ __launch_bounds__(kRmT) void kb_prolong_rm(const S *__restrict__ Ec, 
     }
 }
 
+// Refinement blocks of kb_ir_rm: on a problem with n >= 128 a row-marching
+// tile (strip a, row block b: G groups of kIrRows rows), else kIrCells
+// consecutive cells from a (b = -1).
+struct BIr {
+    int p, a, b;
+};
+constexpr int kIrRows = 16;
+
+// x_b = x_a + e (has_e) in FP64, as kb_ir forms it.
+template <class SL> struct IrLd {
+    const double *x;
+    const SL *e;
+    int he;
+    __device__ __forceinline__ double one(int64_t q) const { return he ? x[q] + double(St<SL>::ld(e + q)) : x[q]; }
+    __device__ __forceinline__ double operator()(int64_t q) const { return one(q); }
+    __device__ __forceinline__ void pair(int64_t q, double &a, double &b) const {
+        Pair<double>::ld(x + q, a, b);
+        if (he) {
+            typename St<SL>::C u, v;
+            Pair<SL>::ld(e + q, u, v);
+            a = a + double(u);
+            b = b + double(v);
+        }
+    }
+};
+
+// kb_ir on row-marching tiles (problems with n >= 128; smaller ones as kb_ir):
+// the same values per cell; one partial per block.
+template <class SL>
+__global__ __launch_bounds__(kBlock) void kb_ir_rm(BPtrs<SL> ptr, SL *const *epool, SL *const *rpool,
+                                                   const BIr *__restrict__ blk, const BProb *__restrict__ P,
+                                                   const BState *__restrict__ st, const BGlobal *__restrict__ g,
+                                                   double *__restrict__ partial, int has_e) {
+    static_assert(kBlock == kRmT, "row-marching refinement tiles use the level kernels' workgroup");
+    __shared__ double buf[2][kRmBuf];
+    const BIr bk = blk[blockIdx.x];
+    if (g->stop || st[bk.p].stop) return;
+    const BProb &pp = P[bk.p];
+    const int lg = pp.L + 2, n = 1 << lg;
+    const int64_t m = int64_t(1) << (2 * lg);
+    const double inv_h2 = 1.0 / (pp.h * pp.h);
+    const int64_t so = int64_t(pp.slot[pp.L]) * m;
+    const SL *e = epool[pp.L] + so;
+    SL *rlo = rpool[pp.L] + so;
+    const double *f = ptr.f[bk.p];
+    double *xo = ptr.xb[bk.p];
+    const IrLd<SL> ldx{ptr.xa[bk.p], e, has_e};
+    double acc = 0.0;
+    if (n < 128) {
+        for (int u = 0; u < kIrCells / kBlock; ++u) {
+            const int64_t c = int64_t(bk.a) + u * kBlock + threadIdx.x;
+            if (c < m) {
+                int i, j, k;
+                decode<2>(c, lg, i, j, k);
+                const double xc = ldx(c);
+                const double s = nb_sum<2, double>(ldx, c, i, j, k, lg, 0, xc);
+                const double r = f[c] - (4.0 * xc - s) * inv_h2;
+                if (has_e) xo[c] = xc;
+                St<SL>::st(rlo + c, typename St<SL>::C(r));
+                acc += r * r;
+            }
+        }
+    } else {
+        RmTile t;
+        t.lg = lg;
+        t.n = n;
+        const int tw = n < 2 * kRmT ? n : 2 * kRmT, G = kRmT / (tw / 2);
+        t.tt = tw / 2;
+        t.grp = int(threadIdx.x) / t.tt;
+        t.l = int(threadIdx.x) % t.tt;
+        t.i0 = bk.a * tw + 2 * t.l;
+        t.j0 = (bk.b * G + t.grp) * kIrRows;
+        t.slot = 0;
+        RmRow<double, IrLd<SL>> r(ldx, t);
+        r.start(t.j0);
+        double f0, f1;
+        Pair<double>::ld(f + r.at(t.j0), f0, f1);
+        const int go = t.grp * (2 * t.tt + 2);
+        for (int j = t.j0, q = 0; j < t.j0 + kIrRows; ++j, q ^= 1) {
+            r.prefetch(j);
+            double g0, g1;
+            Pair<double>::ld(f + r.at(j + 1 <= r.last ? j + 1 : r.last), g0, g1);
+            double s0, s1;
+            r.sums(buf[q] + go, t.l, t.tt, s0, s1);
+            const double r0 = f0 - (4.0 * r.c0 - s0) * inv_h2;
+            const double r1 = f1 - (4.0 * r.c1 - s1) * inv_h2;
+            if (has_e) Pair<double>::st(xo + r.at(j), r.c0, r.c1);
+            Pair<SL>::st(rlo + r.at(j), typename St<SL>::C(r0), typename St<SL>::C(r1));
+            acc += r0 * r0;
+            acc += r1 * r1;
+            f0 = g0;
+            f1 = g1;
+            r.advance();
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 // Depths min(L_p, kTailDepth) .. 0 of every problem, one workgroup each.
 template <class S>
 __global__ __launch_bounds__(Tail<2>::NT) void kb_tail(S *const *Xpool, S *const *Fpool, const double *__restrict__ Minv1,
@@ -631,6 +742,8 @@ struct Plan {
     BGlobal *d_g = nullptr, *h_g = nullptr;
     BBlk *d_blk = nullptr;
     int nblk = 0;
+    BIr *d_irblk = nullptr;
+    int nirblk = 0;
     double *d_partial = nullptr;
     double *d_Minv1 = nullptr;
     double *ypool = nullptr;                   // second FP64 iterate of every problem
@@ -663,7 +776,7 @@ void free_plan(Plan *B) {
     for (auto *p : B->F) (void)hipFree(p);
     for (auto *p : B->T) (void)hipFree(p);
     for (auto *p : B->d_slot_prob) (void)hipFree(p);
-    void *q[] = {B->d_Xpool, B->d_Fpool, B->d_P, B->d_st, B->d_g, B->d_blk, B->d_partial, B->d_Minv1,
+    void *q[] = {B->d_Xpool, B->d_Fpool, B->d_P, B->d_st, B->d_g, B->d_blk, B->d_irblk, B->d_partial, B->d_Minv1,
                  B->ypool, (void *)B->d_f, B->d_x, B->d_y};
     for (auto *p : q) if (p) (void)hipFree(p);
     if (B->h_st) (void)hipHostFree(B->h_st);
@@ -724,10 +837,25 @@ np_status build_plan(const std::vector<int> &lgs, const std::vector<double> &hs,
     }
     B->nblk = int(blk.size());
     NP_TRY(upload(&B->d_blk, blk));
+    std::vector<BIr> irb;
+    for (int p = 0; p < np_; ++p) {
+        const int n = 1 << lgs[p];
+        P[p].ir_first = int(irb.size());
+        if (n >= 128) {
+            const int tw = std::min(n, 2 * kRmT), G = kRmT / (tw / 2);
+            for (int b = 0; b < n / (G * kIrRows); ++b)
+                for (int a = 0; a < n / tw; ++a) irb.push_back(BIr{p, a, b});
+        } else {
+            for (int64_t c = 0; c < int64_t(n) * n; c += kIrCells) irb.push_back(BIr{p, int(c), -1});
+        }
+        P[p].ir_nblocks = int(irb.size()) - P[p].ir_first;
+    }
+    B->nirblk = int(irb.size());
+    NP_TRY(upload(&B->d_irblk, irb));
     NP_TRY(upload(&B->d_P, P));
     NP_TRY(upload(&B->d_Xpool, B->X));
     NP_TRY(upload(&B->d_Fpool, B->F));
-    NP_TRY(dmalloc((void **)&B->d_partial, sizeof(double) * B->nblk));
+    NP_TRY(dmalloc((void **)&B->d_partial, sizeof(double) * std::max(B->nblk, B->nirblk)));
     NP_TRY(dmalloc((void **)&B->d_st, sizeof(BState) * np_));
     NP_TRY(dmalloc((void **)&B->d_g, sizeof(BGlobal)));
     if (hipHostMalloc((void **)&B->h_st, sizeof(BState) * np_, hipHostMallocDefault) != hipSuccess ||
@@ -772,11 +900,15 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
     ptr.xa = kind == 2 ? (const double *const *)B->d_y : (const double *const *)B->d_x;
     ptr.xb = kind == 1 ? B->d_y : B->d_x;
     S *const *Xp = (S *const *)B->d_Xpool, *const *Fp = (S *const *)B->d_Fpool;
-    hipLaunchKernelGGL((kb_ir<S>), dim3(B->nblk), dim3(kBlock), 0, s, ptr, Xp, Fp, B->d_blk, B->d_P, B->d_st,
-                       B->d_g, B->d_partial, kind == 0 ? 0 : 1);
+    if (g_batched_rm)
+        hipLaunchKernelGGL((kb_ir_rm<S>), dim3(B->nirblk), dim3(kBlock), 0, s, ptr, Xp, Fp, B->d_irblk, B->d_P,
+                           B->d_st, B->d_g, B->d_partial, kind == 0 ? 0 : 1);
+    else
+        hipLaunchKernelGGL((kb_ir<S>), dim3(B->nblk), dim3(kBlock), 0, s, ptr, Xp, Fp, B->d_blk, B->d_P, B->d_st,
+                           B->d_g, B->d_partial, kind == 0 ? 0 : 1);
     NP_LAUNCH_CHECK();
     hipLaunchKernelGGL(kb_check, dim3(unsigned((B->nprob + 3) / 4)), dim3(256), 0, s, B->d_partial, B->d_P, B->d_st,
-                       B->d_g, B->nprob);
+                       B->d_g, B->nprob, g_batched_rm);
     NP_LAUNCH_CHECK();
     hipLaunchKernelGGL(kb_check_any, dim3(1), dim3(1024), 0, s, B->d_st, B->d_g, B->nprob);
     NP_LAUNCH_CHECK();
