@@ -391,9 +391,11 @@ struct AdLevels {
 // last axis over a run of one column's cells (neighbours along that axis from
 // registers, in-plane offsets fixed per column); same terms and grouping as
 // ad_ax.  Needs n^(D-1) <= NT.
-template <int D, int NT, bool RESID>
+template <int D, int NT, bool RESID, bool ZERO2 = false>
 __device__ __forceinline__ void ad_tail_sweep(const double *__restrict__ X, const double *__restrict__ F,
                                               double *__restrict__ T, int lg, int bc, const AdW &W, double wd) {
+    // ZERO2: the sweep after a first one from zero; its input iterate wd f is formed from F (X unused)
+    auto xv = [&](int q) -> double { return ZERO2 ? wd * F[q] : X[q]; };
     const int n = 1 << lg, last = n - 1, sm = D == 3 ? n * n : n;
     const int chunks = NT / sm < n ? NT / sm : n, len = n / chunks;
     const int t = threadIdx.x;
@@ -405,18 +407,18 @@ __device__ __forceinline__ void ad_tail_sweep(const double *__restrict__ X, cons
         const int oym = j > 0 ? -n : (per ? last * n : 0), oyp = j < last ? n : (per ? -last * n : 0);
         const bool fym = j > 0 || per, fyp = j < last || per;
         int c = z0 * sm + (t & (sm - 1));
-        double xc = X[c];
-        double zm = X[z0 > 0 ? c - sm : (per ? c + last * sm : c)];
+        double xc = xv(c);
+        double zm = xv(z0 > 0 ? c - sm : (per ? c + last * sm : c));
         bool fzm = z0 > 0 || per;
         for (int z = z0; z < z0 + len; ++z, c += sm) {
-            const double zp = X[z < last ? c + sm : (per ? c - last * sm : c)];
+            const double zp = xv(z < last ? c + sm : (per ? c - last * sm : c));
             const bool fzp = z < last || per;
-            const double rxm = X[c + oxm], rxp = X[c + oxp];  // unconditional: no branch around a load
+            const double rxm = xv(c + oxm), rxp = xv(c + oxp);  // unconditional: no branch around a load
             const double xm = fxm ? rxm : -xc, xp = fxp ? rxp : -xc;
             const double am = fzm ? zm : -xc, ap = fzp ? zp : -xc;  // along the marching axis
             double s;
             if (D == 3) {
-                const double rym = X[c + oym], ryp = X[c + oyp];
+                const double rym = xv(c + oym), ryp = xv(c + oyp);
                 const double ym = fym ? rym : -xc, yp = fyp ? ryp : -xc;
                 s = W.c0 * xc + (W.cm[0] * xm + W.cp[0] * xp) + (W.cm[1] * ym + W.cp[1] * yp);
                 s += W.cm[2] * am + W.cp[2] * ap;
@@ -490,9 +492,16 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_ad_tail(const double *__restric
         double *X = xs + off(lg), *F = fs + off(lg);
         const AdW W = Wl.w[lg_t - lg];
         const double wd = omega / W.c0;
-        for (int c = tid; c < m; c += NT) X[c] = wd * F[c];
-        __syncthreads();
-        sweeps(X, F, lg, W, wd, nu1 - 1);
+        if (nu1 >= 2) {
+            // the first two sweeps from zero in one pass, straight into X
+            ad_tail_sweep<D, NT, false, true>(F, F, X, lg, bc, W, wd);
+            __syncthreads();
+            sweeps(X, F, lg, W, wd, nu1 - 2);
+        } else {
+            for (int c = tid; c < m; c += NT) X[c] = wd * F[c];
+            __syncthreads();
+            sweeps(X, F, lg, W, wd, nu1 - 1);
+        }
         // residual into ts, then its 2^d-cell average into the next level's rhs
         ad_tail_sweep<D, NT, true>(X, F, ts, lg, bc, W, wd);
         __syncthreads();

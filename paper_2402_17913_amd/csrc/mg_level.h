@@ -596,9 +596,11 @@ __device__ __forceinline__ C nb_sum_lds(const C *X, int c, int i, int j, int k, 
 // axis over a run of one column's cells: the neighbours along that axis come
 // from registers, the in-plane ones from offsets fixed per column.  Same
 // values and summation order as nb_sum.  Needs n^(D-1) <= NT.
-template <int D, class C, int NT, bool RESID = false>
+template <int D, class C, int NT, bool RESID = false, bool ZERO2 = false>
 __device__ __forceinline__ void tail_sweep(const C *__restrict__ X, const C *__restrict__ F, C *__restrict__ T,
                                            int lg, int bc, C inv_h2, C wdiag) {
+    // ZERO2: the sweep after a first one from zero; its input iterate w f is formed from F (X unused)
+    auto xv = [&](int q) -> C { return ZERO2 ? wdiag * F[q] : X[q]; };
     const int n = 1 << lg, last = n - 1, sm = D == 3 ? n * n : n;  // sm: cells per plane = marching stride
     const int chunks = NT / sm < n ? NT / sm : n, len = n / chunks;
     const int t = threadIdx.x;
@@ -610,16 +612,16 @@ __device__ __forceinline__ void tail_sweep(const C *__restrict__ X, const C *__r
         const int oym = j > 0 ? -n : (per ? last * n : 0), oyp = j < last ? n : (per ? -last * n : 0);
         const bool fym = j > 0 || per, fyp = j < last || per;
         int c = z0 * sm + (t & (sm - 1));
-        C xc = X[c];
-        C zm = X[z0 > 0 ? c - sm : (per ? c + last * sm : c)];
+        C xc = xv(c);
+        C zm = xv(z0 > 0 ? c - sm : (per ? c + last * sm : c));
         bool fzm = z0 > 0 || per;
         for (int z = z0; z < z0 + len; ++z, c += sm) {
-            const C zp = X[z < last ? c + sm : (per ? c - last * sm : c)];
+            const C zp = xv(z < last ? c + sm : (per ? c - last * sm : c));
             const bool fzp = z < last || per;
-            const C xm = X[c + oxm], xp = X[c + oxp];
+            const C xm = xv(c + oxm), xp = xv(c + oxp);
             C s = (fxm ? xm : -xc) + (fxp ? xp : -xc);
             if (D == 3) {
-                const C ym = X[c + oym], yp = X[c + oyp];
+                const C ym = xv(c + oym), yp = xv(c + oyp);
                 s = (s + (fym ? ym : -xc)) + (fyp ? yp : -xc);
             }
             s = (s + (fzm ? zm : -xc)) + (fzp ? zp : -xc);
@@ -743,10 +745,17 @@ __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>
         const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
         int it0 = 0;
         if (!(x_in && lg == lg_t)) {
-            // first sweep from zero
-            for (int64_t c = tid; c < m; c += NT) X[c] = wdiag * F[c];
-            __syncthreads();
-            it0 = 1;
+            if (nu1 >= 2) {
+                // the first two sweeps from zero in one pass, straight into X
+                tail_sweep<D, C, NT, false, true>(F, F, X, lg, bc, inv_h2, wdiag);
+                __syncthreads();
+                it0 = 2;
+            } else {
+                // first sweep from zero
+                for (int64_t c = tid; c < m; c += NT) X[c] = wdiag * F[c];
+                __syncthreads();
+                it0 = 1;
+            }
         }
         sweeps(X, F, lg, inv_h2, wdiag, nu1 - it0);
         // residual into ts, then its 2^d-cell average into the next level's rhs
