@@ -218,14 +218,14 @@ def leg_c4(B, inputs, steps, warmup):
 def leg_c5(B, inputs, nsteps=10):
     """3D projection steps, 256^3 periodic, nu = 1e-3, seed 0 (held out from the
     network's training seeds 1..20): pressure increment from zero, from the previous
-    step's increment, and from the learned warm start; FP64 and FP32-inner solves."""
+    step's increment, and from the learned warm start; FP64, FP32-inner and BF16-inner solves."""
     import torch
     from paper_2402_17913_amd import learned
     n = 256
     wpath = os.path.join(ROOT, "paper_2402_17913_amd", "weights", "ns3d_periodic_256_in128_L4.npcnn")
     g = inputs.divfree_velocity(3, n, seed=0)
     out = {}
-    for prec_name, prec in (("fp64", B.FP64), ("fp32", B.FP32)):
+    for prec_name, prec in (("fp64", B.FP64), ("fp32", B.FP32), ("bf16", B.BF16)):
         for name, ws in (("zero_guess", 0), ("previous_dp_guess", 2), ("learned_guess", 1)):
             B.np_cnn_load(wpath if ws == 1 else None)
             q = [torch.from_numpy(c).cuda() for c in g["q"]]
