@@ -339,6 +339,81 @@ __global__ __launch_bounds__(kAdxX * kAdxY) void k_adx_stage(const double *__res
     if (STAGE == 0) tcopy[c] = T[c];
 }
 
+// 2D grids with n >= 1024, n a multiple of kAx2: row-marching tiles.  A
+// workgroup of kAx2 threads owns kAx2 consecutive columns and ry rows; each
+// step publishes the next row of the stage input (ghost rule and signs
+// applied, the strip's edge threads adding the cells beyond it) into a ring
+// of four LDS rows, so one barrier per row suffices, and every thread reads
+// its 3 x 3 (or 5-point) neighbourhood from rows j - 1, j, j + 1.  The values
+// and the rate are those of k_adx_stage, so the results are bit-identical.
+constexpr int kAx2 = 256;
+
+inline int adx_rows2(int n) {
+    int ry = 32;
+    while (int64_t(n / kAx2) * (n / ry) < 2048 && ry > 4) ry /= 2;
+    return ry;
+}
+
+template <int SCHEME, int STAGE>
+__global__ __launch_bounds__(kAx2) void k_adx_stage2r(const double *__restrict__ T, const double *__restrict__ Tt,
+                                                      double *__restrict__ out, double *__restrict__ tcopy,
+                                                      APtrs ap, int n, int bc, int ry, double dt, double nu,
+                                                      double h) {
+    __shared__ double rows[4][kAx2 + 2];
+    const int strips = n / kAx2, tid = int(threadIdx.x);
+    const int x0 = (int(blockIdx.x) % strips) * kAx2, j0 = (int(blockIdx.x) / strips) * ry;
+    const int i = x0 + tid;
+    // the edge threads also publish the column beyond the strip (ghost rule)
+    const bool hl = tid == 0, hr = tid == kAx2 - 1;
+    double hsx = 1.0;
+    const int hi = (hl || hr) ? adx_res(hl ? x0 - 1 : x0 + kAx2, n, bc, hsx) : 0;
+    const int64_t nn = n;
+    auto tv = [&](int64_t q) { return STAGE == 1 ? 0.5 * (Tt[q] + T[q]) : T[q]; };
+    // row jr of the stage input (jr may be -1 or n): own column and edge value
+    auto fetch = [&](int jr, double &own, double &edge) {
+        double sy;
+        const int jj = adx_res(jr < n ? jr : n, n, bc, sy);
+        own = (1.0 * sy * 1.0) * tv(int64_t(jj) * nn + i);
+        edge = (hl || hr) ? (hsx * sy * 1.0) * tv(int64_t(jj) * nn + hi) : 0.0;
+    };
+    auto publish = [&](int jr, double own, double edge) {
+        double *r = rows[jr & 3];
+        r[tid + 1] = own;
+        if (hl) r[0] = edge;
+        if (hr) r[kAx2 + 1] = edge;
+    };
+    double o, e;
+    fetch(j0 - 1, o, e);
+    publish(j0 - 1, o, e);
+    fetch(j0, o, e);
+    publish(j0, o, e);
+    double no, ne;
+    fetch(j0 + 1, no, ne);
+    for (int j = j0; j < j0 + ry; ++j) {
+        publish(j + 1, no, ne);
+        const int64_t c = int64_t(j) * nn + i;
+        double a[3] = {0.0, 0.0, 0.0};
+        if (ap.has)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) a[q] = ap.a[q][c];
+        const double tc = STAGE == 1 ? T[c] : 0.0;
+        __syncthreads();
+        if (j + 1 < j0 + ry) fetch(j + 2, no, ne);
+        double v[3][3][3] = {};
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (SCHEME != 2 && (dx != 0) + (dy != 0) > 1) continue;  // 5-point families
+                v[1][dy + 1][dx + 1] = rows[(j + dy) & 3][tid + 1 + dx];
+            }
+        // the stage input of the predictor is T itself: its own value is in the ring
+        const double t0 = STAGE == 1 ? tc : v[1][1][1];
+        out[c] = t0 - dt * adx_rate_at<2, SCHEME>(v, a, ap.has != 0, nu, h);
+        if (STAGE == 0) tcopy[c] = t0;
+    }
+}
+
 // 3D levels on z-marching tiles: a workgroup of kZx x kZy threads owns a
 // kZx x kZy column tile and zc planes; planes z - 1, z, z + 1 of the stage
 // input (with its halo ring, ghost rule applied) sit in a ring of three LDS
@@ -959,7 +1034,21 @@ extern "C" np_status np_ad_explicit_step(np_dims dims, double h, double *T, cons
         hipLaunchKernelGGL((k_adx_stage3z<S, 1>), dim3(nz3), dim3(kZt), 0, s, scr + m, scr, T, nullptr, ap, ni,   \
                            int(bc), zc, dt, nu, h);                                                               \
     } while (0)
-    if (dims.ndim == 2) {
+    // 2D: row-marching tiles from 1024^2 up (n a multiple of the strip width)
+    const int ry2 = adx_rows2(ni);
+    const unsigned nr2 = unsigned((ni / kAx2) * (ni / ry2));
+#define NP_ADX2(S)                                                                                                \
+    do {                                                                                                          \
+        hipLaunchKernelGGL((k_adx_stage2r<S, 0>), dim3(nr2), dim3(kAx2), 0, s, T, T, scr, scr + m, ap, ni,        \
+                           int(bc), ry2, dt, nu, h);                                                              \
+        hipLaunchKernelGGL((k_adx_stage2r<S, 1>), dim3(nr2), dim3(kAx2), 0, s, scr + m, scr, T, nullptr, ap, ni,  \
+                           int(bc), ry2, dt, nu, h);                                                              \
+    } while (0)
+    if (dims.ndim == 2 && ni >= 1024 && ni % kAx2 == 0 && g_zmarch_explicit) {
+        if (scheme == 0) NP_ADX2(0);
+        else if (scheme == 1) NP_ADX2(1);
+        else NP_ADX2(2);
+    } else if (dims.ndim == 2) {
         if (scheme == 0) NP_ADX(2, 0);
         else if (scheme == 1) NP_ADX(2, 1);
         else NP_ADX(2, 2);
@@ -973,6 +1062,7 @@ extern "C" np_status np_ad_explicit_step(np_dims dims, double h, double *T, cons
         else NP_ADX(3, 2);
     }
 #undef NP_ADX
+#undef NP_ADX2
 #undef NP_ADX3
     NP_LAUNCH_CHECK();
     NP_HIP_TRY(hipStreamSynchronize(s));

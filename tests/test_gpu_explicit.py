@@ -101,6 +101,29 @@ def test_explicit_argument_checks(B):
         B.mg_poisson_solve(T, T.clone(), 1.0 / 16, NEU)
 
 
+@pytest.mark.parametrize("n", [1024, 1280])
+@pytest.mark.parametrize("scheme", [0, 1, 2])
+def test_explicit_rowmarch_2d_matches_per_cell_kernel(B, n, scheme):
+    """The 2D row-marching kernel (ring of four LDS rows, strips of 256 columns; n a
+    multiple of 256 from 1024 up, 1280 not a power of two) gives the per-cell kernel's
+    result bit for bit, for every boundary rule, with and without a velocity."""
+    T, a, h, dt, nu = inputs.explicit_ad_case(2, n)
+    for bc in (DIR, PER, NEU):
+        for vel in (True, False):
+            outs = []
+            for zm in (1, 0):
+                B.np_set_tuning("zmarch_explicit", zm)
+                try:
+                    Tg = dev(T)
+                    B.np_ad_explicit_step(Tg, h, dt, nu, bc, a=[dev(c) for c in a] if vel else None,
+                                          scheme=scheme)
+                    outs.append(host(Tg))
+                finally:
+                    B.np_set_tuning("zmarch_explicit", 1)
+            assert np.isfinite(outs[0]).all()
+            assert np.array_equal(outs[0], outs[1]), (bc, vel)
+
+
 @pytest.mark.parametrize("n", [32, 70, 128])
 @pytest.mark.parametrize("scheme", [0, 1, 2])
 def test_explicit_zmarch_matches_per_cell_kernel(B, n, scheme):
