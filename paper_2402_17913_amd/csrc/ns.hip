@@ -369,11 +369,14 @@ __global__ __launch_bounds__(kAx2) void k_adx_stage2r(const double *__restrict__
     const int hi = (hl || hr) ? adx_res(hl ? x0 - 1 : x0 + kAx2, n, bc, hsx) : 0;
     const int64_t nn = n;
     auto tv = [&](int64_t q) { return STAGE == 1 ? 0.5 * (Tt[q] + T[q]) : T[q]; };
-    // row jr of the stage input (jr may be -1 or n): own column and edge value
-    auto fetch = [&](int jr, double &own, double &edge) {
+    // row jr of the stage input (jr may be -1 or n): own column and edge value;
+    // raw: T at the own column of that row (the corrector's T^n, kept for later)
+    auto fetch = [&](int jr, double &own, double &edge, double &raw) {
         double sy;
         const int jj = adx_res(jr < n ? jr : n, n, bc, sy);
-        own = (1.0 * sy * 1.0) * tv(int64_t(jj) * nn + i);
+        const int64_t q = int64_t(jj) * nn + i;
+        raw = T[q];
+        own = (1.0 * sy * 1.0) * (STAGE == 1 ? 0.5 * (Tt[q] + raw) : raw);
         edge = (hl || hr) ? (hsx * sy * 1.0) * tv(int64_t(jj) * nn + hi) : 0.0;
     };
     auto publish = [&](int jr, double own, double edge) {
@@ -382,13 +385,14 @@ __global__ __launch_bounds__(kAx2) void k_adx_stage2r(const double *__restrict__
         if (hl) r[0] = edge;
         if (hr) r[kAx2 + 1] = edge;
     };
-    double o, e;
-    fetch(j0 - 1, o, e);
+    double o, e, r;
+    fetch(j0 - 1, o, e, r);
     publish(j0 - 1, o, e);
-    fetch(j0, o, e);
+    fetch(j0, o, e, r);
     publish(j0, o, e);
-    double no, ne;
-    fetch(j0 + 1, no, ne);
+    double rc = r;  // T at the own column of row j
+    double no, ne, nr;
+    fetch(j0 + 1, no, ne, nr);
     for (int j = j0; j < j0 + ry; ++j) {
         publish(j + 1, no, ne);
         const int64_t c = int64_t(j) * nn + i;
@@ -396,9 +400,10 @@ __global__ __launch_bounds__(kAx2) void k_adx_stage2r(const double *__restrict__
         if (ap.has)
 #pragma unroll
             for (int q = 0; q < 2; ++q) a[q] = ap.a[q][c];
-        const double tc = STAGE == 1 ? T[c] : 0.0;
+        const double tc = rc;
+        rc = nr;
         __syncthreads();
-        if (j + 1 < j0 + ry) fetch(j + 2, no, ne);
+        if (j + 1 < j0 + ry) fetch(j + 2, no, ne, nr);
         double v[3][3][3] = {};
 #pragma unroll
         for (int dy = -1; dy <= 1; ++dy)
@@ -563,9 +568,10 @@ __global__ __launch_bounds__(kZt) void k_nsc_stage3z(Vel qn, Vel qt, double *__r
     R.march(ld, pl, [&](int z) {
         if (i < n && j < n) {
             const int64_t c = int64_t(z) * R.P + int64_t(j) * n + i;
+            // the velocity at the node: in the predictor it is the ring's own value
             double a[3];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) a[e] = qn.q[e][c];
+            for (int e = 0; e < 3; ++e) a[e] = STAGE == 0 ? pl[e][(z + 3) % 3][R.ty + 1][R.tx + 1] : qn.q[e][c];
             double vp[3][3][3] = {};
             R.template gather<SCHEME>(pl[3], z, vp);
 #pragma unroll
