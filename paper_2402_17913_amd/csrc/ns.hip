@@ -572,13 +572,19 @@ __global__ __launch_bounds__(kZt) void k_nsc_stage3z(Vel qn, Vel qt, double *__r
             double a[3];
 #pragma unroll
             for (int e = 0; e < 3; ++e) a[e] = STAGE == 0 ? pl[e][(z + 3) % 3][R.ty + 1][R.tx + 1] : qn.q[e][c];
-            double vp[3][3][3] = {};
-            R.template gather<SCHEME>(pl[3], z, vp);
+            // the pressure gradient first, so that one 3^3 neighbourhood is live at a time
+            double gp[3];
+            {
+                double vp[3][3][3] = {};
+                R.template gather<SCHEME>(pl[3], z, vp);
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) gp[comp] = adx_deriv<3, SCHEME>(vp, comp, h);
+            }
 #pragma unroll
             for (int comp = 0; comp < 3; ++comp) {
                 double v[3][3][3] = {};
                 R.template gather<SCHEME>(pl[comp], z, v);
-                const double Rr = adx_rate_at<3, SCHEME>(v, a, true, nu, h) + adx_deriv<3, SCHEME>(vp, comp, h);
+                const double Rr = adx_rate_at<3, SCHEME>(v, a, true, nu, h) + gp[comp];
                 out[comp][c] = a[comp] - dt * Rr;
             }
         }
