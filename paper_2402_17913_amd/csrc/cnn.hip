@@ -134,14 +134,12 @@ template <bool RELU, bool OUT32>
 __global__ __launch_bounds__(kCzT) void k_conv3z(const uint16_t *__restrict__ X, const uint16_t *__restrict__ W,
                                                  const float *__restrict__ bias, void *__restrict__ Y, int lg, int zc) {
     __shared__ uint4 xs[3][kCzSlots];
-    __shared__ uint4 ws[kTaps * kC * 2];
     const int n = 1 << lg, txv = n < 64 ? n : 64, hx = txv + 2;
     const int tiles_x = n / txv, tiles_y = n / kCzY;
     const int b = blockIdx.x;
     const int x0 = (b % tiles_x) * txv, y0 = ((b / tiles_x) % tiles_y) * kCzY, z0 = (b / (tiles_x * tiles_y)) * zc;
     const int tid = threadIdx.x;
     const uint4 *W4 = reinterpret_cast<const uint4 *>(W);
-    for (int q = tid; q < kTaps * kC * 2; q += kCzT) ws[q] = W4[q];
     const uint4 *X4 = reinterpret_cast<const uint4 *>(X);
     auto plane = [&](int z) { return int64_t(wrapi(z, n)) << (2 * lg + 1); };
     cz_fill(xs[(z0 + 2) % 3], X4, plane(z0 - 1), tid, hx, x0, y0, lg);
@@ -150,21 +148,29 @@ __global__ __launch_bounds__(kCzT) void k_conv3z(const uint16_t *__restrict__ X,
     const int w = tid >> 6, l = tid & 63;
     const int col = l & 15, grp = l >> 4;
     const int tsel = grp >> 1, cb = grp & 1;
+    // the lane's weight operands of the 14 steps depend on the lane only: held in registers
+    // (the 28th tap does not exist: its operands are zero)
+    bf16x8 wa[14];
+#pragma unroll
+    for (int s = 0; s < 14; ++s) {
+        const bool live = 2 * s + tsel < kTaps;
+        const uint4 a4 = W4[((live ? 2 * s + tsel : kTaps - 1) * kC + col) * 2 + cb];
+        wa[s] = __builtin_bit_cast(bf16x8, live ? a4 : make_uint4(0, 0, 0, 0));
+    }
     for (int z = z0; z < z0 + zc; ++z) {
-        __syncthreads();  // planes z - 1, z, z + 1 (and the weights) are in LDS
+        __syncthreads();  // planes z - 1, z, z + 1 are in LDS
         for (int tt = 0; tt < txv / 16; ++tt) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 14; ++s) {
-                // the 28th tap does not exist: read tap 26's operands and zero them by value
+                // the 28th tap does not exist: read tap 26's operand and zero it by value
                 const bool live = 2 * s + tsel < kTaps;
                 const int tap = live ? 2 * s + tsel : kTaps - 1;
                 const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                const uint4 a4 = ws[(tap * kC + col) * 2 + cb];
                 const int hv = (w + 1 + dy) * hx + (tt * 16 + col + 1 + dx);
                 const uint4 b4 = xs[(z + dz + 3) % 3][hv * 2 + cb];
                 const uint4 zz = make_uint4(0, 0, 0, 0);
-                const bf16x8 av = __builtin_bit_cast(bf16x8, live ? a4 : zz);
+                const bf16x8 av = wa[s];
                 const bf16x8 bv = __builtin_bit_cast(bf16x8, live ? b4 : zz);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
             }
@@ -474,9 +480,9 @@ np_status conv(Net *N, int k, const uint16_t *X, void *Y, int lg, bool relu, boo
     const unsigned grid = unsigned((n / txv) * (n / 4) * n);
     const uint16_t *W = (flip ? N->wt : N->wb) + int64_t(k) * kWsz;
     const float *bias = flip ? nullptr : N->w + int64_t(k) * kPsz + kWsz;
-    // z-marching tiles: n / 32 planes per workgroup (measured best at n = 64, 128 and 256; below n = 64 the
-    // one-plane form keeps more workgroups in flight and wins)
-    int zc = g_conv3z == 1 ? n / 32 : (g_conv3z < n ? g_conv3z : n);
+    // z-marching tiles: n / 32 planes per workgroup at n = 64, n / 16 from n = 128 (measured best; below
+    // n = 64 the one-plane form keeps more workgroups in flight and wins)
+    int zc = g_conv3z == 1 ? (n >= 128 ? n / 16 : n / 32) : (g_conv3z < n ? g_conv3z : n);
     if (g_conv3z && zc >= 2) {
         const int tiles = (n / txv) * (n / kCzY);
         const unsigned g3 = unsigned(tiles * (n / zc));
