@@ -401,7 +401,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256),
  * "zc3" (planes per workgroup of the 3D z-marching solver kernels: 0 automatic, else a power of two
  * from 2 to 64), "conv3z" (z-marching tiles for the network's convolutions: 0 off, 1 automatic planes per workgroup, else
- * a power of two from 2 to 64 planes).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
+ * a power of two from 2 to 64 planes), "wgrad_mfma" (0/1: the network's weight gradients on the matrix
+ * cores).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
  * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */
 np_status np_set_tuning(const char *key, int value);
 int np_get_tuning(const char *key);

@@ -31,8 +31,9 @@ constexpr int kC = 16;                 // channels
 constexpr int kTaps = 27;
 constexpr int kWsz = kTaps * kC * kC;  // weights per conv ([tap][out][in])
 constexpr int kPsz = kWsz + kC;        // + bias
-constexpr int kWgBlocks = 512;         // workgroups of a weight-gradient reduction
+constexpr int kWgBlocks = 768;         // workgroups of a weight-gradient reduction (three per CU)
 }  // namespace
+int g_wgrad_mfma = 1;  // tuning knob "wgrad_mfma": weight gradients on the matrix cores
 int g_conv3z = 1;  // tuning knob "conv3z": z-marching convolution tiles (0 off, 1 automatic, else planes)
 namespace {
 
@@ -251,13 +252,121 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, c
     if (c == 0) Pb[kWsz + o] = bacc;
 }
 
-// G[i] += sum over workgroups of P[blk][i] (fixed order).
+// The same partials on the matrix cores: per tap t, dW_t[o][c] = sum over
+// voxels v of dZ[v][o] X[v + t][c] is a 16 x 16 product with the voxels as the
+// contraction (v_mfma_f32_16x16x32_bf16, 32 voxels per step).  Both tiles are
+// staged channel-major in LDS, so a lane's operand (8 consecutive voxels of one
+// channel) is one 16-byte read for dZ and, for X shifted by the tap's dx, two
+// aligned 16-byte reads funnel-shifted by 0, 2 or 4 bytes (rows padded to a
+// multiple of 8 voxels).  Wave w owns taps w, w + 4, ... (seven or six), so no
+// partial crosses waves; the bias gradient is one more product with X = 1.
+constexpr int kWmT = 256;
+
+__device__ __forceinline__ uint32_t wm_shift(uint32_t lo, uint32_t hi, int bytes) {
+    return bytes == 0 ? lo : __builtin_amdgcn_alignbyte(hi, lo, bytes);
+}
+
+__global__ __launch_bounds__(kWmT) void k_wgrad_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ dZ,
+                                                     float *__restrict__ P, int lg) {
+    constexpr int HXP = 72;  // padded halo row (txv + 2 <= 66 voxels), a multiple of 8
+    __shared__ __align__(16) uint16_t xt[kC * 3 * 6 * HXP];   // [c][plane][row][x]
+    __shared__ __align__(16) uint16_t zt[kC * 64 * 4];        // [o][voxel of the tile]
+    const int n = 1 << lg, txv = n < 64 ? n : 64, hx = txv + 2;
+    const int tiles_x = n / txv, ntile = tiles_x * (n / 4) * n;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int ch = l & 15, g = l >> 4;  // operand channel (o for dZ, c for X); voxel run within 32
+    f32x4 acc[7];
+#pragma unroll
+    for (int u = 0; u < 7; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t one = 0x3f80;  // bf16 1.0
+    const uint4 ones = make_uint4(one | (uint32_t(one) << 16), one | (uint32_t(one) << 16),
+                                  one | (uint32_t(one) << 16), one | (uint32_t(one) << 16));
+    const uint4 *X4 = reinterpret_cast<const uint4 *>(X), *Z4 = reinterpret_cast<const uint4 *>(dZ);
+    for (int b = blockIdx.x; b < ntile; b += gridDim.x) {
+        const int tx = b % tiles_x, y4 = (b / tiles_x) % (n / 4), z = b / (tiles_x * (n / 4));
+        const int x0 = tx * txv, y0 = 4 * y4;
+        __syncthreads();  // the previous tile's operands are read
+        // X halo tile (3 planes x 6 rows x hx voxels), transposed to channel-major
+        for (int q = tid; q < hx * 6 * 3 * 2; q += kWmT) {
+            const int v = q >> 1, half = q & 1;
+            const int lx = v % hx, ly = (v / hx) % 6, lz = v / (hx * 6);
+            const uint4 d = X4[((((int64_t(wrapi(z + lz - 1, n)) << lg) + wrapi(y0 + ly - 1, n)) << lg) +
+                                wrapi(x0 + lx - 1, n)) * 2 + half];
+            const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                xt[(((8 * half + e) * 3 + lz) * 6 + ly) * HXP + lx] = uint16_t(dw[e >> 1] >> (16 * (e & 1)));
+        }
+        // dZ tile (4 rows x txv voxels), transposed
+        for (int q = tid; q < txv * 4 * 2; q += kWmT) {
+            const int v = q >> 1, half = q & 1;
+            const int lx = v % txv, ly = v / txv;
+            const uint4 d = Z4[((((int64_t(z) << lg) + y0 + ly) << lg) + x0 + lx) * 2 + half];
+            const uint32_t dw[4] = {d.x, d.y, d.z, d.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) zt[(8 * half + e) * 256 + v] = uint16_t(dw[e >> 1] >> (16 * (e & 1)));
+        }
+        __syncthreads();
+        for (int kb = 0; kb < txv * 4 / 32; ++kb) {
+            const int v0 = kb * 32 + 8 * g, ly = v0 / txv, lx0 = v0 % txv;  // 8 voxels of one row
+            const uint4 a4 = *reinterpret_cast<const uint4 *>(&zt[ch * 256 + v0]);
+            const bf16x8 av = __builtin_bit_cast(bf16x8, a4);
+#pragma unroll
+            for (int u = 0; u < 7; ++u) {
+                const int t = w + 4 * u;
+                if (t < kTaps) {
+                    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                    const int s0 = 1 + dx;  // the run starts s0 voxels into the aligned block
+                    const uint16_t *row = &xt[((ch * 3 + 1 + dz) * 6 + (ly + 1 + dy)) * HXP + lx0];
+                    const uint4 lo = *reinterpret_cast<const uint4 *>(row);
+                    const uint4 hi = *reinterpret_cast<const uint4 *>(row + 8);
+                    const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                    const int wsh = s0 >> 1, bsh = 2 * (s0 & 1);
+                    uint4 b4;
+                    b4.x = wm_shift(d[wsh + 0], d[wsh + 1], bsh);
+                    b4.y = wm_shift(d[wsh + 1], d[wsh + 2], bsh);
+                    b4.z = wm_shift(d[wsh + 2], d[wsh + 3], bsh);
+                    b4.w = wm_shift(d[wsh + 3], d[wsh + 4], bsh);
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, b4), acc[u], 0,
+                                                                     0, 0);
+                } else {
+                    // wave 3's seventh slot: the bias gradient, sum over voxels of dZ[v][o]
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, ones), acc[u],
+                                                                     0, 0, 0);
+                }
+            }
+        }
+    }
+    // lane holds C[o = 4 g + r][c = ch] of each of its products
+    float *Pb = P + int64_t(blockIdx.x) * kPsz;
+#pragma unroll
+    for (int u = 0; u < 7; ++u) {
+        const int t = w + 4 * u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (t < kTaps) Pb[t * 256 + (4 * g + r) * 16 + ch] = acc[u][r];
+            else if (ch == 0) Pb[kWsz + 4 * g + r] = acc[u][r];
+        }
+    }
+}
+
+// G[i] += sum over workgroups of P[blk][i] (fixed order): a workgroup owns 32
+// consecutive entries; its 8 slices of 32 threads sum every eighth partial,
+// then the slices are added in order through LDS.
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ P, int nblk, float *__restrict__ G) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= kPsz) return;
+    __shared__ float part[8][32];
+    const int li = threadIdx.x & 31, sl = threadIdx.x >> 5, i = blockIdx.x * 32 + li;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += P[int64_t(b) * kPsz + i];
-    G[i] += s;
+    if (i < kPsz)
+        for (int b = sl; b < nblk; b += 8) s += P[int64_t(b) * kPsz + i];
+    part[sl][li] = s;
+    __syncthreads();
+    if (sl == 0 && i < kPsz) {
+        float t = part[0][li];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) t += part[q][li];
+        G[i] += t;
+    }
 }
 
 // dZ = round_bf16(dY * (act > 0)) (act null: no mask).
@@ -516,9 +625,11 @@ np_status back(Net *N, int k, const uint16_t *in, const uint16_t *act, const flo
     NP_LAUNCH_CHECK();
     const int n = 1 << lg, txv = n < 64 ? n : 64, ntile = (n / txv) * (n / 4) * n;
     const int nblk = ntile < kWgBlocks ? ntile : kWgBlocks;
-    hipLaunchKernelGGL(k_wgrad, dim3(nblk), dim3(256), 0, s, in, N->Z[l], N->wpart, lg);
+    if (g_wgrad_mfma) hipLaunchKernelGGL(k_wgrad_mfma, dim3(nblk), dim3(kWmT), 0, s, in, N->Z[l], N->wpart, lg);
+    else hipLaunchKernelGGL(k_wgrad, dim3(nblk), dim3(256), 0, s, in, N->Z[l], N->wpart, lg);
     NP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(kPsz)), dim3(256), 0, s, N->wpart, nblk, N->g + int64_t(k) * kPsz);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(unsigned((kPsz + 31) / 32)), dim3(256), 0, s, N->wpart, nblk,
+                       N->g + int64_t(k) * kPsz);
     NP_LAUNCH_CHECK();
     if (gx) NP_TRY(conv(N, k, N->Z[l], gx, lg, false, true, true, s));
     return NP_OK;

@@ -1117,6 +1117,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
+        {"wgrad_mfma", &g_wgrad_mfma, 0, 1},
     };
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
@@ -1161,6 +1162,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
     if (!std::strcmp(key, "zc3")) return g_zc3;
     if (!std::strcmp(key, "conv3z")) return g_conv3z;
+    if (!std::strcmp(key, "wgrad_mfma")) return g_wgrad_mfma;
     return -1;
 }
 

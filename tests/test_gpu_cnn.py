@@ -122,6 +122,40 @@ def test_cnn_zmarch_tiles_bit_identical(B, n, levels):
         assert np.array_equal(g, g0), v
 
 
+@pytest.mark.parametrize("n,levels", [(16, 1), (32, 2), (64, 3)])
+def test_cnn_wgrad_matrix_cores_match_vector_path(B, n, levels):
+    """The weight gradients on the matrix cores (voxels as the contraction, FP32
+    accumulation in another order) agree with the FP32 vector-unit reduction to FP32
+    rounding, layer by layer, and so does the loss."""
+    import torch
+    from oracle import cnn
+    print("cnn wgrad", n, levels, flush=True)
+    ps = params_for(levels, seed=n + 5)
+    rng = np.random.default_rng(11)
+    f = cnn.bf16_round(rng.standard_normal((n, n, n)))
+    t = rng.standard_normal((n, n, n)).astype(np.float32)
+    x = torch.from_numpy(f.astype(np.float32)).cuda()
+    tt = torch.from_numpy(t).cuda()
+    net = B.Cnn(n, levels)
+    net.set_params(cnn.flatten(ps).astype(np.float32))
+    res = {}
+    try:
+        for v in (0, 1):
+            B.np_set_tuning("wgrad_mfma", v)
+            loss = net.gradients([x, x], [tt, tt])
+            res[v] = (loss, net.get_grads().astype(np.float64))
+    finally:
+        B.np_set_tuning("wgrad_mfma", 1)
+        net.close()
+    (l0, g0), (l1, g1) = res[0], res[1]
+    assert l0 == l1  # the forward pass and the loss do not depend on the gradient kernel
+    per = 27 * 16 * 16 + 16
+    for k in range(cnn.n_convs(levels)):
+        a, b = g1[k * per:(k + 1) * per], g0[k * per:(k + 1) * per]
+        print("  conv %d: rel L2 %.3e" % (k, rel_l2(a, b)), flush=True)
+        assert np.abs(b).max() > 0 and rel_l2(a, b) <= 1e-5
+
+
 @pytest.fixture(scope="module")
 def trained(B, tmp_path_factory):
     """A 2-level net on the 32^3 restriction of 64^3 projection steps, trained by
