@@ -260,13 +260,18 @@ def leg_c5(B, inputs, nsteps=10):
     xin = torch.randn((net.n_in,) * 3, dtype=torch.float32, device="cuda")
     y = torch.empty_like(xin)
     dt, _ = timed(lambda: net.forward(xin, y), 10, 2)
+    # one training step (forward, backward, Adam) on a batch of 4 synthetic pairs at the
+    # network's input size, on a copy of the trained weights
+    xb = [torch.randn((net.n_in,) * 3, dtype=torch.float32, device="cuda") for _ in range(4)]
+    tb = [torch.randn((net.n_in,) * 3, dtype=torch.float32, device="cuda") for _ in range(4)]
+    dts, _ = timed(lambda: net.train_step(xb, tb, 1e-4), 5, 1)
     net.close()
     meta = json.load(open(os.path.splitext(wpath)[0] + ".json"))
     return dict(workload="ns3d_256cube_periodic_divfree_seed0_nu1e-3_%dsteps" % nsteps, steps=nsteps,
                 network=dict(n_in=meta["n_in"], levels=meta["levels"], pairs=meta["pairs"],
                              training_seeds=meta["seeds"], epochs=meta["epochs"],
                              training_s=meta["training_s"], pair_generation_s=meta["pair_generation_s"],
-                             forward_ms=1e3 * dt / 10),
+                             forward_ms=1e3 * dt / 10, train_step_ms_batch4=1e3 * dts / 5),
                 **out)
 
 
