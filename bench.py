@@ -514,8 +514,10 @@ def main():
         for kind, kname, nbytes, y in ((B.PROF_LEVEL_SWEEP, "sweep", 3 * dofs * sz, yl),
                                        (B.PROF_LEVEL_RESTRICT, "restrict", (2 * dofs + dofs // 8) * sz, cl),
                                        (B.PROF_LEVEL_PROLONG, "prolong", (2 * dofs + dofs // 8) * sz, cl)):
-            ms = B.np_prof_level(kind, fl, xl if kind != B.PROF_LEVEL_PROLONG else yl, y, h, B.BC_DIRICHLET0, prec,
-                                 reps=SWEEP_REPS)
+            # median over 5 rounds of SWEEP_REPS back-to-back launches (each round: mean launch time)
+            rounds = sorted(B.np_prof_level(kind, fl, xl if kind != B.PROF_LEVEL_PROLONG else yl, y, h,
+                                            B.BC_DIRICHLET0, prec, reps=SWEEP_REPS) for _ in range(5))
+            ms = rounds[2]
             level_live[name][kname] = dict(avg_us=1e3 * ms, bytes_per_launch=nbytes,
                                            gbs=nbytes / (ms * 1e-3) / 1e9,
                                            frac=nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -580,7 +582,8 @@ def main():
             "traffic": measured_traffic(dom, head),
             "avg_us": avg_us,
             "bytes_per_launch": nbytes,
-            "timing": ("HIP events around %d back-to-back launches on the library stream" % SWEEP_REPS
+            "timing": ("HIP events around %d back-to-back launches on the library stream, median of 5 rounds"
+                       % SWEEP_REPS
                        if dom == "sweep" else "HIP events around each launch"),
             "copy_measured_gbs": copy_gbs,
             "finest_level_live": level_live,
