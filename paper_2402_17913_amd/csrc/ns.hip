@@ -419,46 +419,52 @@ __global__ __launch_bounds__(kAx2) void k_adx_stage2r(const double *__restrict__
     }
 }
 
-// 3D levels on z-marching tiles: a workgroup of kZx x kZy threads owns a
-// kZx x kZy column tile and zc planes; planes z - 1, z, z + 1 of the stage
+// 3D levels on z-marching tiles: a workgroup of kZx x TY threads owns a
+// kZx x TY column tile and zc planes; planes z - 1, z, z + 1 of the stage
 // input (with its halo ring, ghost rule applied) sit in a ring of three LDS
 // buffers, and each thread loads its share of plane z + 2 into registers
 // before computing plane z.  Every filter family reads its 3^3 (or 7-point)
 // neighbourhood from LDS; the velocity is read per cell.  Any n >= 3.
-constexpr int kZx = 64, kZy = 8, kZt = kZx * kZy;
+constexpr int kZx = 64;
 }  // namespace
 int g_zmarch_explicit = 1;  // tuning knob "zmarch_explicit"
 namespace {
-constexpr int kZslots = (kZx + 2) * (kZy + 2);
-constexpr int kZper = (kZslots + kZt - 1) / kZt;  // plane values loaded per thread
+// Tile rows per workgroup: 4 for the 27-point finite-element stages (their
+// register footprint leaves room for more, smaller workgroups per CU: measured
+// faster), 8 otherwise.
+constexpr int zrows(int scheme) { return scheme == 2 ? 4 : 8; }
 
-// Plane ring of NF fields on a z-marching tile: each thread owns kZper slots
-// of the (kZx + 2) x (kZy + 2) plane (the tile and its halo ring, ghost rule
-// along x and y applied through the slot's source offset and sign).
-template <int NF>
+// Plane ring of NF fields on a z-marching tile of kZx x TY columns: each
+// thread owns PER slots of the (kZx + 2) x (TY + 2) plane (the tile and its
+// halo ring, ghost rule along x and y applied through the slot's source offset
+// and sign).
+template <int NF, int TY>
 struct ZRing {
-    typedef double Plane[3][kZy + 2][kZx + 2];
+    static constexpr int T = kZx * TY;                          // threads
+    static constexpr int SLOTS = (kZx + 2) * (TY + 2);
+    static constexpr int PER = (SLOTS + T - 1) / T;             // plane values loaded per thread
+    typedef double Plane[3][TY + 2][kZx + 2];
     int tx, ty, x0, y0, z0, z1, n, bc;
     int64_t P;
-    int64_t off[kZper];
-    double sg[kZper];
-    int ly[kZper], lx[kZper];
-    bool own[kZper];
-    double nx[NF][kZper];  // plane z + 1 (then z + 2) in flight
+    int64_t off[PER];
+    double sg[PER];
+    int ly[PER], lx[PER];
+    bool own[PER];
+    double nx[NF][PER];  // plane z + 1 (then z + 2) in flight
     __device__ ZRing(int n_, int bc_, int zc) : n(n_), bc(bc_) {
         tx = int(threadIdx.x) % kZx;
         ty = int(threadIdx.x) / kZx;
-        const int ntx = (n + kZx - 1) / kZx, nty = (n + kZy - 1) / kZy;
+        const int ntx = (n + kZx - 1) / kZx, nty = (n + TY - 1) / TY;
         const int blk = int(blockIdx.x);
         x0 = (blk % ntx) * kZx;
-        y0 = ((blk / ntx) % nty) * kZy;
+        y0 = ((blk / ntx) % nty) * TY;
         z0 = (blk / (ntx * nty)) * zc;
         z1 = min(z0 + zc, n);
         P = int64_t(n) * n;
 #pragma unroll
-        for (int r = 0; r < kZper; ++r) {
-            const int sidx = int(threadIdx.x) + r * kZt;
-            own[r] = sidx < kZslots;
+        for (int r = 0; r < PER; ++r) {
+            const int sidx = int(threadIdx.x) + r * T;
+            own[r] = sidx < SLOTS;
             const int t = own[r] ? sidx : 0;
             ly[r] = t / (kZx + 2);
             lx[r] = t % (kZx + 2);
@@ -477,14 +483,14 @@ struct ZRing {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int r = 0; r < kZper; ++r) nx[f][r] = sz * sg[r] * ld(f, kk * P + off[r]);
+            for (int r = 0; r < PER; ++r) nx[f][r] = sz * sg[r] * ld(f, kk * P + off[r]);
     }
     __device__ __forceinline__ void store(Plane *pl, int z) {
         const int slot = (z + 3) % 3;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int r = 0; r < kZper; ++r)
+            for (int r = 0; r < PER; ++r)
                 if (own[r]) pl[f][slot][ly[r]][lx[r]] = nx[f][r];
     }
     // planes z0 - 1, z0 into LDS, plane z0 + 1 in flight
@@ -528,11 +534,14 @@ struct ZRing {
 };
 
 template <int SCHEME, int STAGE>
-__global__ __launch_bounds__(kZt) void k_adx_stage3z(const double *__restrict__ T, const double *__restrict__ Tt,
-                                                     double *__restrict__ out, double *__restrict__ tcopy, APtrs ap,
-                                                     int n, int bc, int zc, double dt, double nu, double h) {
-    __shared__ ZRing<1>::Plane pl[1];
-    ZRing<1> R(n, bc, zc);
+__global__ __launch_bounds__(kZx * zrows(SCHEME)) void k_adx_stage3z(const double *__restrict__ T,
+                                                                     const double *__restrict__ Tt,
+                                                                     double *__restrict__ out,
+                                                                     double *__restrict__ tcopy, APtrs ap, int n,
+                                                                     int bc, int zc, double dt, double nu, double h) {
+    typedef ZRing<1, zrows(SCHEME)> Ring;
+    __shared__ typename Ring::Plane pl[1];
+    Ring R(n, bc, zc);
     auto ld = [&](int, int64_t q) { return STAGE == 0 ? T[q] : 0.5 * (Tt[q] + T[q]); };
     const int i = R.x0 + R.tx, j = R.y0 + R.ty;
     R.march(ld, pl, [&](int z) {
@@ -554,11 +563,13 @@ __global__ __launch_bounds__(kZt) void k_adx_stage3z(const double *__restrict__ 
 // Collocated momentum stage (as k_nsc_stage) on z-marching tiles: the three
 // components' stage input and the pressure in LDS rings.
 template <int SCHEME, int STAGE>
-__global__ __launch_bounds__(kZt) void k_nsc_stage3z(Vel qn, Vel qt, double *__restrict__ o0, double *__restrict__ o1,
-                                                     double *__restrict__ o2, const double *__restrict__ p, int n,
-                                                     int zc, double dt, double nu, double h) {
-    __shared__ ZRing<4>::Plane pl[4];
-    ZRing<4> R(n, 1, zc);
+__global__ __launch_bounds__(kZx * zrows(SCHEME)) void k_nsc_stage3z(Vel qn, Vel qt, double *__restrict__ o0,
+                                                                     double *__restrict__ o1, double *__restrict__ o2,
+                                                                     const double *__restrict__ p, int n, int zc,
+                                                                     double dt, double nu, double h) {
+    typedef ZRing<4, zrows(SCHEME)> Ring;
+    __shared__ typename Ring::Plane pl[4];
+    Ring R(n, 1, zc);
     auto ld = [&](int f, int64_t q) {
         if (f == 3) return p[q];
         return STAGE == 0 ? qn.q[f][q] : 0.5 * (qt.q[f][q] + qn.q[f][q]);
@@ -593,10 +604,10 @@ __global__ __launch_bounds__(kZt) void k_nsc_stage3z(Vel qn, Vel qt, double *__r
 
 // rhs = scale * sum_e D_e q_e on z-marching tiles.
 template <int SCHEME>
-__global__ __launch_bounds__(kZt) void k_nsc_div3z(Vel q, double *__restrict__ rhs, int n, int zc, double h,
-                                                   double scale) {
-    __shared__ ZRing<3>::Plane pl[3];
-    ZRing<3> R(n, 1, zc);
+__global__ __launch_bounds__(kZx * 8) void k_nsc_div3z(Vel q, double *__restrict__ rhs, int n, int zc, double h,
+                                                       double scale) {
+    __shared__ ZRing<3, 8>::Plane pl[3];
+    ZRing<3, 8> R(n, 1, zc);
     auto ld = [&](int f, int64_t x) { return q.q[f][x]; };
     const int i = R.x0 + R.tx, j = R.y0 + R.ty;
     R.march(ld, pl, [&](int z) {
@@ -615,12 +626,12 @@ __global__ __launch_bounds__(kZt) void k_nsc_div3z(Vel q, double *__restrict__ r
 
 // q_c = qs_c - dt D_c dp; p += dp, on z-marching tiles.
 template <int SCHEME>
-__global__ __launch_bounds__(kZt) void k_nsc_correct3z(Vel qs, double *__restrict__ o0, double *__restrict__ o1,
-                                                       double *__restrict__ o2, double *__restrict__ p,
-                                                       const double *__restrict__ dp, int n, int zc, double dt,
-                                                       double h) {
-    __shared__ ZRing<1>::Plane pl[1];
-    ZRing<1> R(n, 1, zc);
+__global__ __launch_bounds__(kZx * 8) void k_nsc_correct3z(Vel qs, double *__restrict__ o0, double *__restrict__ o1,
+                                                           double *__restrict__ o2, double *__restrict__ p,
+                                                           const double *__restrict__ dp, int n, int zc, double dt,
+                                                           double h) {
+    __shared__ ZRing<1, 8>::Plane pl[1];
+    ZRing<1, 8> R(n, 1, zc);
     auto ld = [&](int, int64_t x) { return dp[x]; };
     const int i = R.x0 + R.tx, j = R.y0 + R.ty;
     double *out[3] = {o0, o1, o2};
@@ -636,11 +647,16 @@ __global__ __launch_bounds__(kZt) void k_nsc_correct3z(Vel qs, double *__restric
     });
 }
 
-inline int adx_planes(int n) {
-    const int64_t tiles = int64_t((n + kZx - 1) / kZx) * ((n + kZy - 1) / kZy);
+inline int adx_planes(int n, int ty) {
+    const int64_t tiles = int64_t((n + kZx - 1) / kZx) * ((n + ty - 1) / ty);
     int zc = 32;
     while (zc > 4 && tiles * ((n + zc - 1) / zc) < 2048) zc >>= 1;
     return zc;
+}
+
+// workgroups of a z-marching launch with ty-row tiles and zc planes each
+inline unsigned zgrid(int n, int ty, int zc) {
+    return unsigned(((n + kZx - 1) / kZx) * ((n + ty - 1) / ty) * ((n + zc - 1) / zc));
 }
 
 // ----------------------------------------- collocated projection step
@@ -821,16 +837,17 @@ static np_status nsc_step_impl(int lg, double h, double *u, double *v, double *w
                                       D == 3 ? unsigned(n) : 1u);
     // 3D from 32^3: z-marching tiles
     const bool zm = D == 3 && n >= 32 && g_zmarch_explicit;
-    const int zc = adx_planes(n);
-    const unsigned nz3 = unsigned(((n + kZx - 1) / kZx) * ((n + kZy - 1) / kZy) * ((n + zc - 1) / zc));
+    constexpr int tys = zrows(SCHEME);  // the momentum stages' tile rows; divergence and correction: 8
+    const int zcs = adx_planes(n, tys), zc = adx_planes(n, 8);
+    const unsigned nzs = zgrid(n, tys, zcs), nz3 = zgrid(n, 8, zc);
     if (zm) {
-        hipLaunchKernelGGL((k_nsc_stage3z<SCHEME, 0>), dim3(nz3), dim3(kZt), 0, s, qn, vt, qt[0], qt[1], qt[2], p, n,
-                           zc, dt, nu, h);
+        hipLaunchKernelGGL((k_nsc_stage3z<SCHEME, 0>), dim3(nzs), dim3(kZx * tys), 0, s, qn, vt, qt[0], qt[1], qt[2],
+                           p, n, zcs, dt, nu, h);
         NP_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_nsc_stage3z<SCHEME, 1>), dim3(nz3), dim3(kZt), 0, s, qn, vt, qs[0], qs[1], qs[2], p, n,
-                           zc, dt, nu, h);
+        hipLaunchKernelGGL((k_nsc_stage3z<SCHEME, 1>), dim3(nzs), dim3(kZx * tys), 0, s, qn, vt, qs[0], qs[1], qs[2],
+                           p, n, zcs, dt, nu, h);
         NP_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_nsc_div3z<SCHEME>), dim3(nz3), dim3(kZt), 0, s, vs, rhs, n, zc, h, -1.0 / dt);
+        hipLaunchKernelGGL((k_nsc_div3z<SCHEME>), dim3(nz3), dim3(kZx * 8), 0, s, vs, rhs, n, zc, h, -1.0 / dt);
     } else {
         hipLaunchKernelGGL((k_nsc_stage<D, SCHEME, 0>), grd, blk, 0, s, qn, vt, qt[0], qt[1], qt[2], p, n, dt, nu,
                            h);
@@ -852,7 +869,8 @@ static np_status nsc_step_impl(int lg, double h, double *u, double *v, double *w
     np_status st = poisson_solve(dims, h, NP_BC_PERIODIC, rhs, dp, tol, &o, stats);
     if (st == NP_EINVAL || st == NP_EHIP || st == NP_ENOMEM) return st;
     if (zm)
-        hipLaunchKernelGGL((k_nsc_correct3z<SCHEME>), dim3(nz3), dim3(kZt), 0, s, vs, u, v, w, p, dp, n, zc, dt, h);
+        hipLaunchKernelGGL((k_nsc_correct3z<SCHEME>), dim3(nz3), dim3(kZx * 8), 0, s, vs, u, v, w, p, dp, n, zc, dt,
+                           h);
     else
         hipLaunchKernelGGL((k_nsc_correct<D, SCHEME>), grd, blk, 0, s, vs, u, v, w, p, dp, n, dt, h);
     NP_LAUNCH_CHECK();
@@ -1037,14 +1055,15 @@ extern "C" np_status np_ad_explicit_step(np_dims dims, double h, double *T, cons
                            nu, h);                                                                                \
     } while (0)
     // 3D: z-marching tiles (three LDS planes) from 32^3 up
-    const int zc = adx_planes(ni);
-    const unsigned nz3 = unsigned(((ni + kZx - 1) / kZx) * ((ni + kZy - 1) / kZy) * ((ni + zc - 1) / zc));
 #define NP_ADX3(S)                                                                                                \
     do {                                                                                                          \
-        hipLaunchKernelGGL((k_adx_stage3z<S, 0>), dim3(nz3), dim3(kZt), 0, s, T, T, scr, scr + m, ap, ni, int(bc), \
-                           zc, dt, nu, h);                                                                        \
-        hipLaunchKernelGGL((k_adx_stage3z<S, 1>), dim3(nz3), dim3(kZt), 0, s, scr + m, scr, T, nullptr, ap, ni,   \
+        constexpr int ty = zrows(S);                                                                              \
+        const int zc = adx_planes(ni, ty);                                                                        \
+        const unsigned nz3 = zgrid(ni, ty, zc);                                                                   \
+        hipLaunchKernelGGL((k_adx_stage3z<S, 0>), dim3(nz3), dim3(kZx * ty), 0, s, T, T, scr, scr + m, ap, ni,    \
                            int(bc), zc, dt, nu, h);                                                               \
+        hipLaunchKernelGGL((k_adx_stage3z<S, 1>), dim3(nz3), dim3(kZx * ty), 0, s, scr + m, scr, T, nullptr, ap,  \
+                           ni, int(bc), zc, dt, nu, h);                                                           \
     } while (0)
     // 2D: row-marching tiles from 1024^2 up (n a multiple of the strip width)
     const int ry2 = adx_rows2(ni);
