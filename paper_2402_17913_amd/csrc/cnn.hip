@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void k_wgrad(const uint16_t *__restrict__ X, c
 // staged channel-major in LDS, so a lane's operand (8 consecutive voxels of one
 // channel) is one 16-byte read for dZ and, for X shifted by the tap's dx, two
 // aligned 16-byte reads funnel-shifted by 0, 2 or 4 bytes (rows padded to a
-// multiple of 8 voxels).  Wave w owns taps w, w + 4, ... (seven or six), so no
+// multiple of 8 voxels).  The three taps of a (dz, dy) group read one X row and
+// differ by the shift; wave w owns groups w, w + 4 (and 8 for wave 0), so no
 // partial crosses waves; the bias gradient is one more product with X = 1.
 constexpr int kWmT = 256;
 
@@ -275,9 +276,9 @@ __global__ __launch_bounds__(kWmT) void k_wgrad_mfma(const uint16_t *__restrict_
     const int tiles_x = n / txv, ntile = tiles_x * (n / 4) * n;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int ch = l & 15, g = l >> 4;  // operand channel (o for dZ, c for X); voxel run within 32
-    f32x4 acc[7];
+    f32x4 acc[9];
 #pragma unroll
-    for (int u = 0; u < 7; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < 9; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t one = 0x3f80;  // bf16 1.0
     const uint4 ones = make_uint4(one | (uint32_t(one) << 16), one | (uint32_t(one) << 16),
                                   one | (uint32_t(one) << 16), one | (uint32_t(one) << 16));
@@ -312,26 +313,28 @@ __global__ __launch_bounds__(kWmT) void k_wgrad_mfma(const uint16_t *__restrict_
             const uint4 a4 = *reinterpret_cast<const uint4 *>(&zt[ch * 256 + v0]);
             const bf16x8 av = __builtin_bit_cast(bf16x8, a4);
 #pragma unroll
-            for (int u = 0; u < 7; ++u) {
-                const int t = w + 4 * u;
-                if (t < kTaps) {
-                    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                    const int s0 = 1 + dx;  // the run starts s0 voxels into the aligned block
+            for (int jg = 0; jg < 3; ++jg) {
+                const int G = w + 4 * jg;  // tap group (dz, dy): its three taps share one X row
+                if (G < 9) {
+                    const int dz = G / 3 - 1, dy = G % 3 - 1;
                     const uint16_t *row = &xt[((ch * 3 + 1 + dz) * 6 + (ly + 1 + dy)) * HXP + lx0];
                     const uint4 lo = *reinterpret_cast<const uint4 *>(row);
                     const uint4 hi = *reinterpret_cast<const uint4 *>(row + 8);
                     const uint32_t d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-                    const int wsh = s0 >> 1, bsh = 2 * (s0 & 1);
-                    uint4 b4;
-                    b4.x = wm_shift(d[wsh + 0], d[wsh + 1], bsh);
-                    b4.y = wm_shift(d[wsh + 1], d[wsh + 2], bsh);
-                    b4.z = wm_shift(d[wsh + 2], d[wsh + 3], bsh);
-                    b4.w = wm_shift(d[wsh + 3], d[wsh + 4], bsh);
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, b4), acc[u], 0,
-                                                                     0, 0);
-                } else {
-                    // wave 3's seventh slot: the bias gradient, sum over voxels of dZ[v][o]
-                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, ones), acc[u],
+#pragma unroll
+                    for (int s0 = 0; s0 < 3; ++s0) {  // dx = s0 - 1: the run starts s0 voxels in
+                        const int wsh = s0 >> 1, bsh = 2 * (s0 & 1);
+                        uint4 b4;
+                        b4.x = wm_shift(d[wsh + 0], d[wsh + 1], bsh);
+                        b4.y = wm_shift(d[wsh + 1], d[wsh + 2], bsh);
+                        b4.z = wm_shift(d[wsh + 2], d[wsh + 3], bsh);
+                        b4.w = wm_shift(d[wsh + 3], d[wsh + 4], bsh);
+                        acc[3 * jg + s0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            av, __builtin_bit_cast(bf16x8, b4), acc[3 * jg + s0], 0, 0, 0);
+                    }
+                } else if (jg == 2 && w == 3) {
+                    // wave 3's spare slot: the bias gradient, sum over voxels of dZ[v][o]
+                    acc[6] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, ones), acc[6],
                                                                      0, 0, 0);
                 }
             }
@@ -340,13 +343,15 @@ __global__ __launch_bounds__(kWmT) void k_wgrad_mfma(const uint16_t *__restrict_
     // lane holds C[o = 4 g + r][c = ch] of each of its products
     float *Pb = P + int64_t(blockIdx.x) * kPsz;
 #pragma unroll
-    for (int u = 0; u < 7; ++u) {
-        const int t = w + 4 * u;
+    for (int jg = 0; jg < 3; ++jg) {
+        const int G = w + 4 * jg;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (t < kTaps) Pb[t * 256 + (4 * g + r) * 16 + ch] = acc[u][r];
-            else if (ch == 0) Pb[kWsz + 4 * g + r] = acc[u][r];
-        }
+        for (int s0 = 0; s0 < 3; ++s0)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (G < 9) Pb[(3 * G + s0) * 256 + (4 * g + r) * 16 + ch] = acc[3 * jg + s0][r];
+                else if (jg == 2 && w == 3 && s0 == 0 && ch == 0) Pb[kWsz + 4 * g + r] = acc[6][r];
+            }
     }
 }
 
