@@ -114,6 +114,7 @@ struct Tuning {
     int inner_bf16 = 2;
     int batch = 4;        // first batch of cycles enqueued before reading the controller
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
+    int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
 };
 static Tuning g_tune;
@@ -501,6 +502,26 @@ template <int D, class S> struct Ops {
         return NP_OK;
     }
 
+    // Whether prolongation + correction and the first post-sweep of a level run as one kernel.
+    static bool psweep_on(int lg, int nu2) { return D == 3 && lg >= 7 && g_tune.sweep3 && g_tune.psweep && nu2 >= 1; }
+
+    // xout = sweep(x + P ec) on a level of 2^lg cells per axis (k_psweep3; psweep_on holds).
+    static np_status psweep(const S *ec, const S *f, const S *x, S *xout, int lg, int bc, double h, double omega,
+                            hipStream_t s, bool finest, const int *stop) {
+        const int64_t m = cells(D, lg);
+        const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+        void *tok = nullptr;
+        const bool prof = finest && (prof_on() & kProfUp);
+        if (prof) NP_TRY(prof_begin(s, &tok));
+        constexpr int CPT = ZCfg<S>::CPT;
+        const int zc = sweep3_planes(lg, CPT, kPartials);
+        hipLaunchKernelGGL((k_psweep3<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, ec, f, x, xout, lg, bc,
+                           zc, inv_h2, wdiag, stop);
+        NP_LAUNCH_CHECK();
+        if (prof) NP_TRY(prof_end(s, tok, double(m) * 3 * sizeof(S) + double(m) / (1 << D) * sizeof(S)));
+        return NP_OK;
+    }
+
     static np_status coarse(const S *f, S *x, const double *Minv, int bc, double hc, bool zero,
                             hipStream_t s, const int *stop) {
         hipLaunchKernelGGL((k_coarse<D, S>), dim3(1), dim3(64), 0, s, f, x, Minv, bc, 1.0 / (hc * hc),
@@ -691,8 +712,15 @@ template <int D, class S> struct Ops {
                 res[l] = cur[l];
                 continue;
             }
-            NP_TRY(prolong_add(res[l + 1], cur[l], lg - 1, bc, s, stop));
-            for (int it = 0; it < o.nu2; ++it) {
+            int it = 0;
+            if (psweep_on(lg, o.nu2)) {
+                NP_TRY(psweep(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
+                std::swap(cur[l], oth[l]);
+                it = 1;
+            } else {
+                NP_TRY(prolong_add(res[l + 1], cur[l], lg - 1, bc, s, stop));
+            }
+            for (; it < o.nu2; ++it) {
                 NP_TRY(sweep(F[l], cur[l], oth[l], lg, bc, hl, o.omega, 0, nullptr, nullptr, s, l == 0, stop));
                 std::swap(cur[l], oth[l]);
             }
@@ -1113,7 +1141,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"bz2", &g_tune.bz2, 0, 1 << 14},       {"bz3", &g_tune.bz3, 0, 1 << 12},
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
-        {"zero2", &g_tune.zero2, 0, 1},
+        {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
@@ -1156,6 +1184,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "batch")) return g_tune.batch;
     if (!std::strcmp(key, "sweep3")) return g_tune.sweep3;
     if (!std::strcmp(key, "zero2")) return g_tune.zero2;
+    if (!std::strcmp(key, "psweep")) return g_tune.psweep;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "batched_rm")) return g_batched_rm;

@@ -422,6 +422,62 @@ __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restri
 // updates its CPT columns on fine planes 2K and 2K+1 from LDS values, while
 // the coarse plane K+2 is in flight (one coarse cell per thread, clamped
 // loads).  Weights 3/4 (own coarse cell) and 1/4 (neighbour) per axis.
+// Cell-centred trilinear prolongation on the z-marching tiles (shared by the
+// prolongation kernel and the fused prolongation + sweep, so that both do the
+// same arithmetic).  A thread t < CX * CY holds one cell of the tile's coarse
+// footprint (its coarse cells and a one-cell ring); load(K) is that cell's
+// value on coarse plane K, for K in [-2, nc + 1]: outside the grid the wrapped
+// value (periodic) or the adjacent interior value negated (Dirichlet), per axis.
+template <class S, int CX, int CY>
+struct CTile {
+    typedef typename St<S>::C C;
+    const S *ec;
+    int nc, bc, cx, cy;
+    bool cw;
+    int64_t csrc, Pc;
+    C csg;
+    __device__ CTile(const S *ec_, int lgc, int bc_, int x0, int y0) : ec(ec_), nc(1 << lgc), bc(bc_) {
+        const int t = int(threadIdx.x);
+        cw = t < CX * CY;
+        cx = t % CX;
+        cy = t / CX;
+        int gi = (x0 >> 1) - 1 + cx, gj = (y0 >> 1) - 1 + cy;
+        csg = C(1);
+        if (gi < 0) { gi = bc ? nc - 1 : 0; if (!bc) csg = -csg; }
+        if (gi >= nc) { gi = bc ? 0 : nc - 1; if (!bc) csg = -csg; }
+        if (gj < 0) { gj = bc ? nc - 1 : 0; if (!bc) csg = -csg; }
+        if (gj >= nc) { gj = bc ? 0 : nc - 1; if (!bc) csg = -csg; }
+        csrc = cw ? (int64_t(gj) << lgc) + gi : 0;
+        Pc = int64_t(1) << (2 * lgc);
+    }
+    __device__ __forceinline__ C load(int K) const {
+        C sg = csg;
+        int kk = K;
+        if (kk < 0) { kk = bc ? nc - 1 : 0; if (!bc) sg = -sg; }
+        if (kk >= nc) { kk = bc ? 0 : nc - 1; if (!bc) sg = -sg; }
+        return sg * St<S>::ld(ec + kk * Pc + csrc);
+    }
+};
+
+// Weighted pair 3/4 a + 1/4 b with one rounding (b / 4 is exact): written as an
+// explicit fused multiply-add so that every kernel that prolongates rounds the
+// same way whatever the compiler's contraction choices.
+__device__ __forceinline__ float wpair(float a, float b) { return __builtin_fmaf(0.75f, a, 0.25f * b); }
+__device__ __forceinline__ double wpair(double a, double b) { return __builtin_fma(0.75, a, 0.25 * b); }
+
+// In-plane bilinear value of a coarse plane tile at a fine column: own coarse
+// row / column (ly, lx) weighted 3/4, the neighbour on the fine cell's side
+// (ny, nx) 1/4, x first.
+template <class C, int CY, int CX>
+__device__ __forceinline__ C prolong_bil(const C (&pl)[CY][CX], int ly, int ny, int lx, int nx) {
+    return wpair(wpair(pl[ly][lx], pl[ly][nx]), wpair(pl[ny][lx], pl[ny][nx]));
+}
+// The prolongated value from the own coarse plane's and the neighbour plane's bilinear values.
+template <class C>
+__device__ __forceinline__ C prolong_mix(C eo, C en) {
+    return wpair(eo, en);
+}
+
 template <class S>
 __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ ec, S *__restrict__ x, int lg, int bc,
                                                          int zc, const int *stop) {
@@ -431,31 +487,16 @@ __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ e
     static_assert(CX * CY <= kS3Threads, "one coarse cell per thread");
     __shared__ C cp[3][CY][CX];
     if (stop && *stop) return;
-    const int n = 1 << lg, nc = n >> 1, lgc = lg - 1, ntx = n / TX, nty = n / TY;
+    const int n = 1 << lg, lgc = lg - 1, ntx = n / TX, nty = n / TY;
     const int blk = int(xcd_block(blockIdx.x, gridDim.x));
     const int t = int(threadIdx.x), tp = t % TP, ty = t / TP;
     const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
     const int x0 = bx * TX, y0 = by * TY, k0 = bz * zc, K0 = k0 >> 1;
     const int64_t P = int64_t(1) << (2 * lg), col = (int64_t(y0 + ty) << lg) + x0 + CPT * tp;
-    // coarse cell loaded by this thread: (cx, cy) in the tile, source column and sign
-    const bool cw = t < CX * CY;
-    const int cx = t % CX, cy = t / CX;
-    int gi = (x0 >> 1) - 1 + cx, gj = (y0 >> 1) - 1 + cy;
-    C csg = C(1);
-    if (gi < 0) { gi = bc ? nc - 1 : 0; if (!bc) csg = -csg; }
-    if (gi >= nc) { gi = bc ? 0 : nc - 1; if (!bc) csg = -csg; }
-    if (gj < 0) { gj = bc ? nc - 1 : 0; if (!bc) csg = -csg; }
-    if (gj >= nc) { gj = bc ? 0 : nc - 1; if (!bc) csg = -csg; }
-    const int64_t csrc = cw ? (int64_t(gj) << lgc) + gi : 0;
-    const int64_t Pc = int64_t(1) << (2 * lgc);
-    // value of coarse plane K (any K in [-1, nc]) at this thread's coarse cell
-    auto cload = [&](int K) -> C {
-        C sg = csg;
-        int kk = K;
-        if (kk < 0) { kk = bc ? nc - 1 : 0; if (!bc) sg = -sg; }
-        if (kk >= nc) { kk = bc ? 0 : nc - 1; if (!bc) sg = -sg; }
-        return sg * St<S>::ld(ec + kk * Pc + csrc);
-    };
+    const CTile<S, CX, CY> ct(ec, lgc, bc, x0, y0);
+    const bool cw = ct.cw;
+    const int cx = ct.cx, cy = ct.cy;
+    auto cload = [&](int K) -> C { return ct.load(K); };
     auto slot = [](int K) { return (K + 3) % 3; };
     {
         const C a = cload(K0 - 1), b = cload(K0), c = cload(K0 + 1);
@@ -474,7 +515,6 @@ __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ e
         nx[c] = lx[c] + ((ti & 1) ? 1 : -1);
     }
     const int ly = (ty >> 1) + 1, ny = ly + ((ty & 1) ? 1 : -1);
-    const C w0 = C(0.75), w1 = C(0.25);
     const LdC<S> vx{x};
     for (int K = K0; K < K0 + (zc >> 1); ++K) {
         const int64_t c0 = int64_t(2 * K) * P + col, c1 = c0 + P;
@@ -491,19 +531,108 @@ __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ e
         const C(&below)[CY][CX] = cp[slot(K - 1)];
         const C(&above)[CY][CX] = cp[slot(K + 1)];
         for (int c = 0; c < CPT; ++c) {
-            // in-plane bilinear value of a coarse plane at this column
-            auto bil = [&](const C(&pl)[CY][CX]) -> C {
-                return w0 * (w0 * pl[ly][lx[c]] + w1 * pl[ly][nx[c]]) + w1 * (w0 * pl[ny][lx[c]] + w1 * pl[ny][nx[c]]);
-            };
-            const C eo = bil(own), em = bil(below), ep = bil(above);
-            xa[c] = xa[c] + (w0 * eo + w1 * em);  // fine plane 2K: neighbour plane K - 1
-            xb[c] = xb[c] + (w0 * eo + w1 * ep);  // fine plane 2K + 1: neighbour plane K + 1
+            const C eo = prolong_bil(own, ly, ny, lx[c], nx[c]), em = prolong_bil(below, ly, ny, lx[c], nx[c]),
+                    ep = prolong_bil(above, ly, ny, lx[c], nx[c]);
+            xa[c] = xa[c] + prolong_mix(eo, em);  // fine plane 2K: neighbour plane K - 1
+            xb[c] = xb[c] + prolong_mix(eo, ep);  // fine plane 2K + 1: neighbour plane K + 1
         }
         store_cells<S, CPT>(x + c0, xa);
         store_cells<S, CPT>(x + c1, xb);
         __syncthreads();  // every read of slot(K - 1) is done
         if (cw) cp[slot(K + 2)][cy][cx] = nxt;
         __syncthreads();
+    }
+}
+
+// Round trip of a value through storage S (BF16: nearest even; identity otherwise).
+template <class S>
+__device__ __forceinline__ typename St<S>::C st_round(typename St<S>::C v) {
+    S t;
+    St<S>::st(&t, v);
+    return St<S>::ld(&t);
+}
+
+// Prolongation + correction of a level followed by its first Jacobi sweep, in
+// one z-marching pass: xout = sweep(xin + P ec), the corrected iterate never
+// stored.  Every value the sweep reads (own columns at z-1, z, z+1 and the
+// in-plane halo) is corrected where it is loaded, from a ring of four coarse
+// planes (with the tile's coarse ring) in LDS, and rounded to the storage
+// precision as the stored iterate of the two-kernel path is: the result equals
+// k_prolong3 then k_sweep3 bit for bit.  Ghost values are corrected at the
+// ghost position from the coarse ghosts; by the symmetry of the cell-centred
+// weights that is the ghost of the corrected value exactly (negated for
+// Dirichlet, wrapped for periodic).  zc even.
+template <class S>
+__global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec, const S *__restrict__ f,
+                                                        const S *__restrict__ xin, S *__restrict__ xout, int lg,
+                                                        int bc, int zc, typename St<S>::C inv_h2,
+                                                        typename St<S>::C wdiag, const int *stop) {
+    typedef typename St<S>::C C;
+    constexpr int CPT = ZCfg<S>::CPT, TX = ZCfg<S>::TX;
+    typedef ZMarch<C, TX, CPT> Z;
+    constexpr int CX = TX / 2 + 2, CY = Z::TY / 2 + 2;
+    static_assert(CX * CY <= kS3Threads, "one coarse cell per thread");
+    __shared__ typename Z::Plane pl[2];
+    __shared__ C cp[4][CY][CX];
+    if (stop && *stop) return;
+    Z z(lg, bc, zc);
+    const CTile<S, CX, CY> ct(ec, lg - 1, bc, z.i - CPT * z.tp, z.j - z.ty);
+    auto cs = [](int K) { return (K + 4) & 3; };  // ring slot of coarse plane K >= -2
+    // corrected value at fine position (fx, fy) of the tile (ghost frame, the ring
+    // at -1 and TX / TY) on fine plane p in [-1, n]
+    auto corr = [&](C raw, int fx, int fy, int p) -> C {
+        const int lx = (fx + 2) >> 1, nx = lx + ((fx & 1) ? 1 : -1);
+        const int ly = (fy + 2) >> 1, ny = ly + ((fy & 1) ? 1 : -1);
+        const int K = ((p + 2) >> 1) - 1, Kn = K + ((p & 1) ? 1 : -1);
+        const C eo = prolong_bil(cp[cs(K)], ly, ny, lx, nx), en = prolong_bil(cp[cs(Kn)], ly, ny, lx, nx);
+        return st_round<S>(raw + prolong_mix(eo, en));
+    };
+    auto corr_cells = [&](C (&v)[CPT], int p) {
+        for (int c = 0; c < CPT; ++c) v[c] = corr(v[c], CPT * z.tp + c, z.ty, p);
+    };
+    auto corr_halo = [&](C (&v)[CPT], int p) {
+        if (!z.hw) return;  // no slot: the value is not used
+        v[0] = corr(v[0], z.hx - 1, z.hy - 1, p);
+        if constexpr (CPT == 2) {
+            if (z.hrun) v[1] = corr(v[1], z.hx, z.hy - 1, p);
+        }
+    };
+    const LdC<S> vx{xin}, vf{f};
+    const int K0 = z.k0 >> 1;
+    {
+        const C a = ct.load(K0 - 1), b = ct.load(K0), c = ct.load(K0 + 1);
+        if (ct.cw) {
+            cp[cs(K0 - 1)][ct.cy][ct.cx] = a;
+            cp[cs(K0)][ct.cy][ct.cx] = b;
+            cp[cs(K0 + 1)][ct.cy][ct.cx] = c;
+        }
+    }
+    z.start(vx);
+    __syncthreads();
+    corr_cells(z.xm, z.k0 - 1);
+    corr_cells(z.xc, z.k0);
+    C fc[CPT], fn[CPT], s[CPT], out[CPT];
+    z.cells(vf, z.k0 * z.P + z.col, fc);
+    C cnext = C(0);
+    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
+        // the values loaded one plane ahead: plane k's halo and plane k + 1's column value.
+        // Coarse planes read here: k / 2 - 1 .. k / 2 + 1, all written before the last barrier.
+        corr_halo(z.hv, k);
+        corr_cells(z.xp, k + 1);
+        z.prefetch(vx, k);
+        z.cells(vf, z.next(k) * z.P + z.col, fn);
+        // coarse plane J + 2 is loaded on plane 2J and published on plane 2J + 1 (first read on
+        // plane 2J + 2); its slot held plane J - 2, last read on plane 2J - 2
+        if ((k & 1) == 0) cnext = ct.load((k >> 1) + 2);
+        else if (ct.cw) cp[cs((k >> 1) + 2)][ct.cy][ct.cx] = cnext;
+        z.neighbours(pl[q], s);
+        for (int c = 0; c < CPT; ++c) {
+            const C r = fc[c] - (C(6) * z.xc[c] - s[c]) * inv_h2;
+            out[c] = z.xc[c] + wdiag * r;
+            fc[c] = fn[c];
+        }
+        store_cells<S, CPT>(xout + k * z.P + z.col, out);
+        z.advance();
     }
 }
 

@@ -155,6 +155,39 @@ def test_sweep3_matches_direct_sweep(B, orc, bc):
 
 
 @pytest.mark.parametrize("bc", [DIR, PER])
+@pytest.mark.parametrize("nu2", [2, 1])
+def test_prolong_sweep_fusion_bit_identical(B, orc, bc, nu2):
+    """Prolongation + correction and the first post-sweep in one z-marching kernel
+    (levels of n >= 128) give the solves of the two-kernel path bit for bit, on every
+    precision path, with one and two post-sweeps; the FP64 result matches the oracle."""
+    n = 128
+    rng = np.random.default_rng(131 + bc)
+    f = rng.standard_normal((n, n, n))
+    if bc == PER:
+        f -= f.mean()
+    h = 1.0 / n
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("psweep", v)
+            for prec in (B.FP64, B.FP32, B.BF16):
+                say("psweep", v, bc, nu2, prec)
+                xg = dev(np.zeros_like(f))
+                kw = dict(fixed_cycles=3) if prec == B.FP64 else {}
+                st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, smooth_prec=prec, nu1=2, nu2=nu2, **kw)
+                out[(v, prec)] = (host(xg), stats)
+    finally:
+        B.np_set_tuning("psweep", 1)
+    for prec in (B.FP64, B.FP32, B.BF16):
+        a, sa = out[(1, prec)]
+        b, sb = out[(0, prec)]
+        assert sa["cycles"] == sb["cycles"], prec
+        assert np.array_equal(a, b), (prec, rel(a, b))
+    ref = orc.mg_solve(f, h, bc, fixed_cycles=3, nu1=2, nu2=nu2)
+    assert rel(out[(1, B.FP64)][0], ref.x) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
 def test_prof_level_runs_the_solver_kernels(B, orc, bc):
     """The timing hook launches the solver's level kernels (FP64, 128^3, the z-marching
     kernels): the sweep's output is one oracle Jacobi sweep, the restriction's is the
