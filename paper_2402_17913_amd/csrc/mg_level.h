@@ -590,11 +590,34 @@ __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec
     auto corr_cells = [&](C (&v)[CPT], int p) {
         for (int c = 0; c < CPT; ++c) v[c] = corr(v[c], CPT * z.tp + c, z.ty, p);
     };
-    auto corr_halo = [&](C (&v)[CPT], int p) {
+    // In the loop, each coarse plane's in-plane values at this thread's cells (own
+    // columns: bo; halo slot: bh) are formed once and serve the four fine planes
+    // that use it; a correction is then prolong_mix of two of them.
+    const int oly = (z.ty + 2) >> 1, ony = oly + ((z.ty & 1) ? 1 : -1);
+    const int hly = (z.hy + 1) >> 1, hny = hly + ((z.hy & 1) ? -1 : 1);  // fy = hy - 1
+    int olx[CPT], onx[CPT], hlx[CPT], hnx[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        const int fx = CPT * z.tp + c, gx = z.hx - 1 + c;
+        olx[c] = (fx + 2) >> 1;
+        onx[c] = olx[c] + ((fx & 1) ? 1 : -1);
+        hlx[c] = (gx + 2) >> 1;
+        hnx[c] = hlx[c] + ((gx & 1) ? 1 : -1);
+    }
+    auto bil_own = [&](int K, C (&e)[CPT]) {
+        for (int c = 0; c < CPT; ++c) e[c] = prolong_bil(cp[cs(K)], oly, ony, olx[c], onx[c]);
+    };
+    auto bil_halo = [&](int K, C (&e)[CPT]) {
         if (!z.hw) return;  // no slot: the value is not used
-        v[0] = corr(v[0], z.hx - 1, z.hy - 1, p);
+        for (int c = 0; c < CPT; ++c) e[c] = prolong_bil(cp[cs(K)], hly, hny, hlx[c], hnx[c]);
+    };
+    auto mix_cells = [&](C (&v)[CPT], const C (&eo)[CPT], const C (&en)[CPT]) {
+        for (int c = 0; c < CPT; ++c) v[c] = st_round<S>(v[c] + prolong_mix(eo[c], en[c]));
+    };
+    auto mix_halo = [&](C (&v)[CPT], const C (&eo)[CPT], const C (&en)[CPT]) {
+        if (!z.hw) return;
+        v[0] = st_round<S>(v[0] + prolong_mix(eo[0], en[0]));
         if constexpr (CPT == 2) {
-            if (z.hrun) v[1] = corr(v[1], z.hx, z.hy - 1, p);
+            if (z.hrun) v[1] = st_round<S>(v[1] + prolong_mix(eo[1], en[1]));
         }
     };
     const LdC<S> vx{xin}, vf{f};
@@ -611,18 +634,29 @@ __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec
     __syncthreads();
     corr_cells(z.xm, z.k0 - 1);
     corr_cells(z.xc, z.k0);
+    // own columns: planes J, J + 1 (J = k / 2); the halo slot's values are formed per plane
+    C oa[CPT], ob[CPT];
+    bil_own(K0, oa);
+    bil_own(K0 + 1, ob);
+    auto fix_halo = [&](int Ko, int Kn) {
+        if (!z.hw) return;
+        C ho[CPT], hn2[CPT];
+        bil_halo(Ko, ho);
+        bil_halo(Kn, hn2);
+        mix_halo(z.hv, ho, hn2);
+    };
     C fc[CPT], fn[CPT], s[CPT], out[CPT];
     z.cells(vf, z.k0 * z.P + z.col, fc);
     C cnext = C(0);
-    for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
-        // the values loaded one plane ahead: plane k's halo and plane k + 1's column value.
-        // Coarse planes read here: k / 2 - 1 .. k / 2 + 1, all written before the last barrier.
-        corr_halo(z.hv, k);
-        corr_cells(z.xp, k + 1);
+    // one fine plane: loads of the next, the corrections `fix` of the values loaded one
+    // plane ago (after the new loads are issued, so that they stay in flight),
+    // neighbours (one barrier), sweep and store
+    auto plane = [&](int k, int q, auto &&fix) {
         z.prefetch(vx, k);
         z.cells(vf, z.next(k) * z.P + z.col, fn);
-        // coarse plane J + 2 is loaded on plane 2J and published on plane 2J + 1 (first read on
-        // plane 2J + 2); its slot held plane J - 2, last read on plane 2J - 2
+        fix();
+        // coarse plane J + 2 is loaded on plane 2J and published on plane 2J + 1 (first read
+        // at the start of plane 2J + 2); its slot held plane J - 2, last read on plane 2J - 2
         if ((k & 1) == 0) cnext = ct.load((k >> 1) + 2);
         else if (ct.cw) cp[cs((k >> 1) + 2)][ct.cy][ct.cx] = cnext;
         z.neighbours(pl[q], s);
@@ -633,6 +667,22 @@ __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec
         }
         store_cells<S, CPT>(xout + k * z.P + z.col, out);
         z.advance();
+    };
+    for (int k = z.k0; k < z.k0 + zc; k += 2) {
+        const int J = k >> 1;
+        // plane 2J: halo of 2J (own J, neighbour J - 1); column value of 2J + 1 (J, J + 1)
+        plane(k, 0, [&] {
+            fix_halo(J, J - 1);
+            mix_cells(z.xp, oa, ob);
+        });
+        // plane 2J + 1: halo of 2J + 1 (J, J + 1); column value of 2J + 2 (J + 1, J)
+        plane(k + 1, 1, [&] {
+            fix_halo(J, J + 1);
+            mix_cells(z.xp, ob, oa);
+        });
+        // slide to J + 1: coarse plane J + 2 was published on plane 2J + 1
+        for (int c = 0; c < CPT; ++c) oa[c] = ob[c];
+        bil_own(J + 2, ob);
     }
 }
 
