@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "mg_fused.h"
@@ -488,11 +489,14 @@ template <int D, class S> struct Ops {
         void *tok = nullptr;
         const bool prof = lgc + 1 == H_lg_top && (prof_on() & kProfProlong);
         if (prof) NP_TRY(prof_begin(s, &tok));
-        if (D == 3 && lgc + 1 >= 7 && g_tune.sweep3) {
+        if (D == 3 && lgc + 1 >= 5 && g_tune.sweep3) {
+            // z-marching tiles from 32^3 up: the same arithmetic as the fused prolongation + sweep
             constexpr int CPT = ZCfg<S>::CPT;
             const int lg = lgc + 1, zc = sweep3_planes(lg, CPT, kPartials);
-            hipLaunchKernelGGL((k_prolong3<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, ec, x, lg, bc, zc,
-                               stop);
+            by_tile_width(lg, [&](auto tx) {
+                hipLaunchKernelGGL((k_prolong3<S, decltype(tx)::value>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads),
+                                   0, s, ec, x, lg, bc, zc, stop);
+            });
         } else {
             hipLaunchKernelGGL((k_prolong_add<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, x, lgc, bc,
                                stop);
@@ -503,7 +507,16 @@ template <int D, class S> struct Ops {
     }
 
     // Whether prolongation + correction and the first post-sweep of a level run as one kernel.
-    static bool psweep_on(int lg, int nu2) { return D == 3 && lg >= 7 && g_tune.sweep3 && g_tune.psweep && nu2 >= 1; }
+    static bool psweep_on(int lg, int nu2) { return D == 3 && lg >= 5 && g_tune.sweep3 && g_tune.psweep && nu2 >= 1; }
+
+    // Calls fn(std::integral_constant<int, TX>) with the z-marching tile width of a
+    // 3D level of 2^lg >= 32 cells per axis (128, or the level's width below that).
+    template <class Fn>
+    static void by_tile_width(int lg, Fn &&fn) {
+        if (lg >= 7) fn(std::integral_constant<int, 128>());
+        else if (lg == 6) fn(std::integral_constant<int, 64>());
+        else fn(std::integral_constant<int, 32>());
+    }
 
     // xout = sweep(x + P ec) on a level of 2^lg cells per axis (k_psweep3; psweep_on holds).
     static np_status psweep(const S *ec, const S *f, const S *x, S *xout, int lg, int bc, double h, double omega,
@@ -515,8 +528,10 @@ template <int D, class S> struct Ops {
         if (prof) NP_TRY(prof_begin(s, &tok));
         constexpr int CPT = ZCfg<S>::CPT;
         const int zc = sweep3_planes(lg, CPT, kPartials);
-        hipLaunchKernelGGL((k_psweep3<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, ec, f, x, xout, lg, bc,
-                           zc, inv_h2, wdiag, stop);
+        by_tile_width(lg, [&](auto tx) {
+            hipLaunchKernelGGL((k_psweep3<S, decltype(tx)::value>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s,
+                               ec, f, x, xout, lg, bc, zc, inv_h2, wdiag, stop);
+        });
         NP_LAUNCH_CHECK();
         if (prof) NP_TRY(prof_end(s, tok, double(m) * 3 * sizeof(S) + double(m) / (1 << D) * sizeof(S)));
         return NP_OK;

@@ -478,11 +478,11 @@ __device__ __forceinline__ C prolong_mix(C eo, C en) {
     return wpair(eo, en);
 }
 
-template <class S>
+template <class S, int TX = ZCfg<S>::TX>
 __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ ec, S *__restrict__ x, int lg, int bc,
                                                          int zc, const int *stop) {
     typedef typename St<S>::C C;
-    constexpr int CPT = ZCfg<S>::CPT, TX = ZCfg<S>::TX, TP = TX / CPT;
+    constexpr int CPT = ZCfg<S>::CPT, TP = TX / CPT;
     constexpr int TY = kS3Threads / TP, CX = TX / 2 + 2, CY = TY / 2 + 2;
     static_assert(CX * CY <= kS3Threads, "one coarse cell per thread");
     __shared__ C cp[3][CY][CX];
@@ -561,14 +561,15 @@ __device__ __forceinline__ typename St<S>::C st_round(typename St<S>::C v) {
 // k_prolong3 then k_sweep3 bit for bit.  Ghost values are corrected at the
 // ghost position from the coarse ghosts; by the symmetry of the cell-centred
 // weights that is the ghost of the corrected value exactly (negated for
-// Dirichlet, wrapped for periodic).  zc even.
-template <class S>
+// Dirichlet, wrapped for periodic).  zc even.  TX: tile width (n >= TX; 128
+// on the large levels, 64 and 32 on the 64^3 and 32^3 levels).
+template <class S, int TX = ZCfg<S>::TX>
 __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec, const S *__restrict__ f,
                                                         const S *__restrict__ xin, S *__restrict__ xout, int lg,
                                                         int bc, int zc, typename St<S>::C inv_h2,
                                                         typename St<S>::C wdiag, const int *stop) {
     typedef typename St<S>::C C;
-    constexpr int CPT = ZCfg<S>::CPT, TX = ZCfg<S>::TX;
+    constexpr int CPT = ZCfg<S>::CPT;
     typedef ZMarch<C, TX, CPT> Z;
     constexpr int CX = TX / 2 + 2, CY = Z::TY / 2 + 2;
     static_assert(CX * CY <= kS3Threads, "one coarse cell per thread");
@@ -692,7 +693,9 @@ __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec
 inline int sweep3_planes(int lg, int cpt, int64_t max_blocks) {
     const int n = 1 << lg;
     const int64_t cols = int64_t(n) * n / (int64_t(kS3Threads) * cpt);  // column tiles
-    int zc = n >= 256 ? 16 : 4;  // measured: 16 planes beat 8 at 256^3 in every precision
+    // measured: 16 planes beat 8 at 256^3 in every precision; levels below 128^3 are
+    // launch-bound and take the shortest chains (two planes)
+    int zc = n >= 256 ? 16 : (n >= 128 ? 4 : 2);
     if (g_zc3 >= 2 && g_zc3 <= n) zc = g_zc3;  // tuning knob "zc3" (a power of two)
     while (cols * (n / zc) > max_blocks && zc < n) zc *= 2;
     return zc;
