@@ -93,17 +93,28 @@ def sweep3_source_hash():
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
+def refine_source_hash():
+    """Hash of the refinement kernel's source (k_ir_resid3), recorded with its counters."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", "mg_level.h")).read()
+    body = src[src.index("// Refinement step of the mixed path on the z-marching tiles"):
+               src.index("// x += P ec on the z-marching tiles")]
+    return hashlib.sha256(body.encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel, head):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
-    summary, if the kernel's source is unchanged since the counters were taken."""
+    """HBM bytes per launch of the dominant kernel (the sweep or the refinement step)
+    from the committed rocprofv3 counter summary, if the kernel's source is unchanged
+    since the counters were taken."""
     import re
     path = SWEEP3_PROFILE.replace("fp32", head)
-    if kernel != "sweep" or not os.path.exists(path):
+    if kernel not in ("sweep", "refine") or not os.path.exists(path):
         return None
     txt = open(path).read()
-    m1 = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
-    m2 = re.search(r"kernel_source_sha256_16: (\w+)", txt)
-    if not (m1 and m2) or sweep3_source_hash() != m2.group(1):
+    tag, src_hash = ("", sweep3_source_hash) if kernel == "sweep" else ("refine_", refine_source_hash)
+    m1 = re.search(r"^%straffic_bytes_per_launch: (\d+)" % tag, txt, re.M)
+    m2 = re.search(r"^%skernel_source_sha256_16: (\w+)" % tag, txt, re.M)
+    if not (m1 and m2) or src_hash() != m2.group(1):
         return None
     return int(m1.group(1))
 
