@@ -403,6 +403,31 @@ def test_full_size_3d_256(B, orc):
             1e-13 * np.linalg.norm(uh)
 
 
+def test_full_size_fusion_bit_identical_256(B, orc):
+    """The benchmark's 256^3 solve on the BF16-storage path (and plain FP64 for a fixed
+    cycle count): the fused prolongation + sweep gives the two-kernel path's iterate bit
+    for bit, and the BF16 result meets the tolerance by the oracle's residual."""
+    n = 256
+    g = inputs.sine_rhs(3, n, seed=0)
+    f, h = g["f"], g["h"]
+    fg = dev(f)
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("psweep", v)
+            for p, kw in ((B.BF16, {}), (B.FP64, dict(fixed_cycles=2))):
+                say("full size fusion", v, p)
+                xg = dev(np.zeros_like(f))
+                st, stats = B.mg_poisson_solve(fg, xg, h, DIR, tol=1e-10, smooth_prec=p, **kw)
+                out[(v, p)] = (host(xg), stats["cycles"])
+    finally:
+        B.np_set_tuning("psweep", 1)
+    for p in (B.BF16, B.FP64):
+        assert out[(1, p)][1] == out[(0, p)][1]
+        assert np.array_equal(out[(1, p)][0], out[(0, p)][0]), p
+    assert orc.rel_res(f, out[(1, B.BF16)][0], h, DIR) <= 1e-10
+
+
 # --------------------------------------------- the paper's sawtooth cycle (GPU)
 @pytest.mark.parametrize("d,n", [(2, 4), (2, 64), (2, 256), (3, 16), (3, 64)])
 @pytest.mark.parametrize("bc", [DIR, PER])
