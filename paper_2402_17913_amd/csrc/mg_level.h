@@ -609,7 +609,9 @@ __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec
     };
     auto bil_halo = [&](int K, C (&e)[CPT]) {
         if (!z.hw) return;  // no slot: the value is not used
-        for (int c = 0; c < CPT; ++c) e[c] = prolong_bil(cp[cs(K)], hly, hny, hlx[c], hnx[c]);
+        // a single-cell slot has only its first cell (the second's columns may lie off the tile)
+        for (int c = 0; c < CPT; ++c)
+            e[c] = c == 0 || z.hrun ? prolong_bil(cp[cs(K)], hly, hny, hlx[c], hnx[c]) : C(0);
     };
     auto mix_cells = [&](C (&v)[CPT], const C (&eo)[CPT], const C (&en)[CPT]) {
         for (int c = 0; c < CPT; ++c) v[c] = st_round<S>(v[c] + prolong_mix(eo[c], en[c]));
