@@ -506,8 +506,12 @@ template <int D, class S> struct Ops {
         return NP_OK;
     }
 
-    // Whether prolongation + correction and the first post-sweep of a level run as one kernel.
-    static bool psweep_on(int lg, int nu2) { return D == 3 && lg >= 5 && g_tune.sweep3 && g_tune.psweep && nu2 >= 1; }
+    // Whether prolongation + correction and the first post-sweep of a level run as one kernel
+    // (2D: every level above the tail; 3D: levels of n >= 32 on the z-marching tiles).
+    static bool psweep_on(int lg, int nu2) {
+        if (!g_tune.psweep || nu2 < 1) return false;
+        return D == 2 || (lg >= 5 && g_tune.sweep3);
+    }
 
     // Calls fn(std::integral_constant<int, TX>) with the z-marching tile width of a
     // 3D level of 2^lg >= 32 cells per axis (128, or the level's width below that).
@@ -518,7 +522,8 @@ template <int D, class S> struct Ops {
         else fn(std::integral_constant<int, 32>());
     }
 
-    // xout = sweep(x + P ec) on a level of 2^lg cells per axis (k_psweep3; psweep_on holds).
+    // xout = sweep(x + P ec) on a level of 2^lg cells per axis (k_psweep3 in 3D, k_psweep in 2D;
+    // psweep_on holds).
     static np_status psweep(const S *ec, const S *f, const S *x, S *xout, int lg, int bc, double h, double omega,
                             hipStream_t s, bool finest, const int *stop) {
         const int64_t m = cells(D, lg);
@@ -526,12 +531,17 @@ template <int D, class S> struct Ops {
         void *tok = nullptr;
         const bool prof = finest && (prof_on() & kProfUp);
         if (prof) NP_TRY(prof_begin(s, &tok));
-        constexpr int CPT = ZCfg<S>::CPT;
-        const int zc = sweep3_planes(lg, CPT, kPartials);
-        by_tile_width(lg, [&](auto tx) {
-            hipLaunchKernelGGL((k_psweep3<S, decltype(tx)::value>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s,
-                               ec, f, x, xout, lg, bc, zc, inv_h2, wdiag, stop);
-        });
+        if constexpr (D == 3) {
+            constexpr int CPT = ZCfg<S>::CPT;
+            const int zc = sweep3_planes(lg, CPT, kPartials);
+            by_tile_width(lg, [&](auto tx) {
+                hipLaunchKernelGGL((k_psweep3<S, decltype(tx)::value>), dim3(zblocks(lg, CPT, zc)),
+                                   dim3(kS3Threads), 0, s, ec, f, x, xout, lg, bc, zc, inv_h2, wdiag, stop);
+            });
+        } else {
+            hipLaunchKernelGGL((k_psweep<D, S>), dim3(blocks_for(m)), dim3(kBlock), 0, s, ec, f, x, xout, lg, bc,
+                               inv_h2, wdiag, stop);
+        }
         NP_LAUNCH_CHECK();
         if (prof) NP_TRY(prof_end(s, tok, double(m) * 3 * sizeof(S) + double(m) / (1 << D) * sizeof(S)));
         return NP_OK;

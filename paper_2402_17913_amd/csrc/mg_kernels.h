@@ -120,20 +120,15 @@ __device__ __forceinline__ void pro_axis(int i, int nc, int bc, int &own, int &n
     }
 }
 
-// x += P ec, one thread per fine cell.  Per axis the own coarse cell has
-// weight 3/4 and the neighbour 1/4; ghost neighbours carry the sign of the
-// boundary rule.  lgc is the coarse level's log2 size.
+// (P ec) at fine cell (i, j, k), lgc the coarse level's log2 size.  Per axis
+// the own coarse cell has weight 3/4 and the neighbour 1/4; ghost neighbours
+// carry the sign of the boundary rule.  The 2^D terms in a fixed order, each
+// accumulated with one explicit fused multiply-add.
 template <int D, class S>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec, S *__restrict__ x,
-                                                        int lgc, int bc, const int *stop) {
+__device__ __forceinline__ typename St<S>::C pro_cell(const S *__restrict__ ec, int i, int j, int k, int lgc,
+                                                      int bc) {
     typedef typename St<S>::C C;
-    if (stop && *stop) return;
-    const int lg = lgc + 1, nc = 1 << lgc;
-    const int64_t m = int64_t(1) << (D * lg);
-    const int64_t c = int64_t(sizeof(S) < 8 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= m) return;
-    int i, j, k;
-    decode<D>(c, lg, i, j, k);
+    const int nc = 1 << lgc;
     int oi, ni, oj, nj, ok = 0, nk = 0;
     float si, sj, sk = 1.0f;
     pro_axis(i, nc, bc, oi, ni, si);
@@ -147,9 +142,59 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec
                 const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sk : 1.0f));
                 const int64_t q = (int64_t(cz ? nk : ok) << (2 * lgc)) | (int64_t(b ? nj : oj) << lgc) |
                                   (a ? ni : oi);
-                s += w * (sg * St<S>::ld(ec + q));
+                s = np_fma(w, sg * St<S>::ld(ec + q), s);
             }
-    St<S>::st(x + c, St<S>::ld(x + c) + s);
+    return s;
+}
+
+// x += P ec, one thread per fine cell.  lgc is the coarse level's log2 size.
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(const S *__restrict__ ec, S *__restrict__ x,
+                                                        int lgc, int bc, const int *stop) {
+    if (stop && *stop) return;
+    const int lg = lgc + 1;
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(sizeof(S) < 8 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int i, j, k;
+    decode<D>(c, lg, i, j, k);
+    St<S>::st(x + c, St<S>::ld(x + c) + pro_cell<D, S>(ec, i, j, k, lgc, bc));
+}
+
+// The corrected iterate x + P ec at flat index q, rounded to the storage
+// precision as the stored iterate of prolongation then sweep is.
+template <int D, class S> struct LdPro {
+    const S *x, *ec;
+    int lg, bc;
+    __device__ __forceinline__ typename St<S>::C operator()(int64_t q) const {
+        int i, j, k;
+        decode<D>(q, lg, i, j, k);
+        return st_round<S>(St<S>::ld(x + q) + pro_cell<D, S>(ec, i, j, k, lg - 1, bc));
+    }
+};
+
+// Prolongation + correction followed by one Jacobi sweep, one thread per fine
+// cell: xout = sweep(xin + P ec), the corrected iterate formed for the cell and
+// its neighbours where they are read (same arithmetic as k_prolong_add then
+// k_sweep, so the same result bit for bit).  Used on the 2D levels above the
+// one-workgroup tail, where every launch costs about as much as the work.
+template <int D, class S>
+__global__ __launch_bounds__(kBlock) void k_psweep(const S *__restrict__ ec, const S *__restrict__ f,
+                                                   const S *__restrict__ xin, S *__restrict__ xout, int lg, int bc,
+                                                   typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                   const int *stop) {
+    typedef typename St<S>::C C;
+    if (stop && *stop) return;
+    const int64_t m = int64_t(1) << (D * lg);
+    const int64_t c = int64_t(sizeof(S) < 8 ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= m) return;
+    int i, j, k;
+    decode<D>(c, lg, i, j, k);
+    const LdPro<D, S> ld{xin, ec, lg, bc};
+    const C fc = St<S>::ld(f + c), xc = ld(c);
+    const C s = nb_sum<D, C>(ld, c, i, j, k, lg, bc, xc);
+    const C r = fc - (C(2 * D) * xc - s) * inv_h2;
+    St<S>::st(xout + c, xc + wdiag * r);
 }
 
 // Exact solve on the 4^d coarsest grid: x <- x + Minv (f - A x), Minv the

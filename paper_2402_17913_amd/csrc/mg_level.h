@@ -544,14 +544,6 @@ __global__ __launch_bounds__(kS3Threads) void k_prolong3(const S *__restrict__ e
     }
 }
 
-// Round trip of a value through storage S (BF16: nearest even; identity otherwise).
-template <class S>
-__device__ __forceinline__ typename St<S>::C st_round(typename St<S>::C v) {
-    S t;
-    St<S>::st(&t, v);
-    return St<S>::ld(&t);
-}
-
 // Prolongation + correction of a level followed by its first Jacobi sweep, in
 // one z-marching pass: xout = sweep(xin + P ec), the corrected iterate never
 // stored.  Every value the sweep reads (own columns at z-1, z, z+1 and the
@@ -845,7 +837,7 @@ __device__ __forceinline__ void tail_prolong(const C *__restrict__ E, C *__restr
                             const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(cz ? 0.25 : 0.75);
                             const C sg = C((a ? si : 1.0f) * (b ? sj : 1.0f) * (cz ? sz : 1.0f));
                             const int q = ((cz ? nz : oz) << (2 * lgc)) | ((b ? nj : oj) << lgc) | (a ? ni : oi);
-                            s += w * (sg * E[q]);
+                            s = np_fma(w, sg * E[q], s);
                         }
             } else {
                 // the marching axis is y
@@ -854,7 +846,7 @@ __device__ __forceinline__ void tail_prolong(const C *__restrict__ E, C *__restr
                         const C w = C(a ? 0.25 : 0.75) * C(b ? 0.25 : 0.75) * C(1.0);
                         const C sg = C((a ? si : 1.0f) * (b ? sz : 1.0f) * 1.0f);
                         const int q = ((b ? nz : oz) << lgc) | (a ? ni : oi);
-                        s += w * (sg * E[q]);
+                        s = np_fma(w, sg * E[q], s);
                     }
             }
             X[c] = X[c] + s;

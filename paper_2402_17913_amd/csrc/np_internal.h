@@ -75,6 +75,20 @@ template <> struct St<bf16> {
     static __device__ __forceinline__ void st(bf16 *p, float v) { p->u = float_to_bf16(v); }
 };
 
+// Explicit fused multiply-add (one rounding): kernels that must round alike
+// (a fused kernel and the pair it replaces) spell their products this way, so
+// that the compiler's contraction choices cannot differ between them.
+__device__ __forceinline__ float np_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double np_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Round trip of a value through storage S (BF16: nearest even; identity otherwise).
+template <class S>
+__device__ __forceinline__ typename St<S>::C st_round(typename St<S>::C v) {
+    S t;
+    St<S>::st(&t, v);
+    return St<S>::ld(&t);
+}
+
 inline size_t prec_bytes(np_prec p) { return p == NP_FP64 ? 8 : (p == NP_FP32 ? 4 : 2); }
 
 // ------------------------------------------------------------ reductions

@@ -156,13 +156,14 @@ def test_sweep3_matches_direct_sweep(B, orc, bc):
 
 @pytest.mark.parametrize("bc", [DIR, PER])
 @pytest.mark.parametrize("nu2", [2, 1])
-def test_prolong_sweep_fusion_bit_identical(B, orc, bc, nu2):
-    """Prolongation + correction and the first post-sweep in one z-marching kernel
-    (levels of n >= 128) give the solves of the two-kernel path bit for bit, on every
-    precision path, with one and two post-sweeps; the FP64 result matches the oracle."""
-    n = 128
-    rng = np.random.default_rng(131 + bc)
-    f = rng.standard_normal((n, n, n))
+@pytest.mark.parametrize("d,n", [(3, 128), (2, 512)])
+def test_prolong_sweep_fusion_bit_identical(B, orc, bc, nu2, d, n):
+    """Prolongation + correction and the first post-sweep in one kernel (3D: z-marching,
+    levels 128^3, 64^3, 32^3; 2D: per cell, every level above the tail) give the solves
+    of the two-kernel path bit for bit, on every precision path, with one and two
+    post-sweeps; the FP64 result matches the oracle."""
+    rng = np.random.default_rng(131 + bc + d)
+    f = rng.standard_normal((n,) * d)
     if bc == PER:
         f -= f.mean()
     h = 1.0 / n
@@ -171,7 +172,7 @@ def test_prolong_sweep_fusion_bit_identical(B, orc, bc, nu2):
         for v in (1, 0):
             B.np_set_tuning("psweep", v)
             for prec in (B.FP64, B.FP32, B.BF16):
-                say("psweep", v, bc, nu2, prec)
+                say("psweep", v, d, n, bc, nu2, prec)
                 xg = dev(np.zeros_like(f))
                 kw = dict(fixed_cycles=3) if prec == B.FP64 else {}
                 st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, smooth_prec=prec, nu1=2, nu2=nu2, **kw)
