@@ -397,7 +397,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * state), "sweep3" (0/1: z-marching smoothing, restriction, prolongation
  * and refinement kernels on 3D levels of n >= 128), "zero2" (0/1: the first
  * two sweeps from a zero iterate in one pass), "psweep" (0/1: prolongation + correction and the
- * first post-sweep of 3D levels of n >= 128 in one pass), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
+ * first post-sweep in one pass: 2D levels above the tail, 3D levels of n >= 32), "ir_cpt" (1 or 2:
+ * cells per thread of the 3D refinement kernel), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
  * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit and collocated steps, n >= 32,
  * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256),
  * "zc3" (planes per workgroup of the 3D z-marching solver kernels: 0 automatic, else a power of two

@@ -116,6 +116,7 @@ struct Tuning {
     int batch = 4;        // first batch of cycles enqueued before reading the controller
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
+    int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
 };
 static Tuning g_tune;
@@ -1042,8 +1043,9 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
     }
     NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
     const bool zm = D == 3 && H->lg >= 7 && g_tune.sweep3;  // z-marching refinement kernel
-    const int zc = zm ? sweep3_planes(H->lg, 1, kPartials) : 0;
-    const unsigned nb = zm ? zblocks(H->lg, 1, zc)
+    const int icpt = g_tune.ir_cpt;                           // its cells per thread (1 or 2)
+    const int zc = zm ? sweep3_planes(H->lg, icpt, kPartials) : 0;
+    const unsigned nb = zm ? zblocks(H->lg, icpt, zc)
                            : unsigned(std::min<int64_t>((m + kIrCells - 1) / kIrCells, kPartials));
     const int *stop = &H->ctl->stop;
     // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles
@@ -1051,7 +1053,13 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         void *tok = nullptr;
         const bool prof = prof_on() & kProfRefine;
         if (prof) NP_TRY(prof_begin(q, &tok));
-        if (zm && has_e)
+        if (zm && has_e && icpt == 2)
+            hipLaunchKernelGGL((k_ir_resid3<SL, true, 2>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
+                               H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
+        else if (zm && icpt == 2)
+            hipLaunchKernelGGL((k_ir_resid3<SL, false, 2>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f,
+                               rlo, H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
+        else if (zm && has_e)
             hipLaunchKernelGGL((k_ir_resid3<SL, true>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
                                H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
         else if (zm)
@@ -1167,6 +1175,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
@@ -1210,6 +1219,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "sweep3")) return g_tune.sweep3;
     if (!std::strcmp(key, "zero2")) return g_tune.zero2;
     if (!std::strcmp(key, "psweep")) return g_tune.psweep;
+    if (!std::strcmp(key, "ir_cpt")) return g_tune.ir_cpt;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "batched_rm")) return g_batched_rm;

@@ -378,14 +378,16 @@ __global__ __launch_bounds__(kS3Threads) void k_restrict3(const S *__restrict__ 
 // Refinement step of the mixed path on the z-marching tiles (see
 // k_ir_resid): x_out = x + e (HAS_E; else x_out is not written and e is not
 // read), r = f - A x_out in FP64, r_lo = r rounded, per-workgroup partial of
-// r^2.  One cell per thread (the FP64 fields dominate its traffic).
-template <class SL, bool HAS_E>
+// r^2.  CPT cells per thread along x: 1, or 2 (16-byte FP64 and paired
+// low-precision accesses; the same arithmetic per cell).
+template <class SL, bool HAS_E, int CPT = 1>
 __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restrict__ x, const SL *__restrict__ e,
                                                           double *__restrict__ xout, const double *__restrict__ f,
                                                           SL *__restrict__ rlo, double *__restrict__ partial,
                                                           int lg, int bc, int zc, double inv_h2,
                                                           const int *stop) {
-    typedef ZMarch<double, ZCfg<double>::TX, 1> Z;
+    typedef ZMarch<double, ZCfg<double>::TX, CPT> Z;
+    typedef typename St<SL>::C CL;
     __shared__ typename Z::Plane pl[2];
     if (stop && *stop) return;
     Z z(lg, bc, zc);
@@ -395,21 +397,36 @@ __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restri
         __device__ __forceinline__ double operator()(int64_t q) const {
             return HAS_E ? x[q] + double(St<SL>::ld(e + q)) : x[q];
         }
+        __device__ __forceinline__ void pair(int64_t q, double &a, double &b) const {
+            Pair<double>::ld(x + q, a, b);
+            if (HAS_E) {
+                CL ea, eb;
+                Pair<SL>::ld(e + q, ea, eb);
+                a = a + double(ea);
+                b = b + double(eb);
+            }
+        }
     } v{x, e};
+    const LdC<double> vf{f};
     z.start(v);
-    double fc = f[z.k0 * z.P + z.col];
-    double acc = 0.0, s[1];
+    double fc[CPT], fn[CPT], s[CPT];
+    z.cells(vf, z.k0 * z.P + z.col, fc);
+    double acc = 0.0;
     for (int k = z.k0, q = 0; k < z.k0 + zc; ++k, q ^= 1) {
         z.prefetch(v, k);
-        const double fn = f[z.next(k) * z.P + z.col];
+        z.cells(vf, z.next(k) * z.P + z.col, fn);
         z.neighbours(pl[q], s);
-        const double r = fc - (6.0 * z.xc[0] - s[0]) * inv_h2;
         const int64_t c = k * z.P + z.col;
-        if (HAS_E) xout[c] = z.xc[0];
-        St<SL>::st(rlo + c, typename St<SL>::C(r));
-        acc += r * r;
+        CL rl[CPT];
+        for (int i = 0; i < CPT; ++i) {
+            const double r = fc[i] - (6.0 * z.xc[i] - s[i]) * inv_h2;
+            rl[i] = CL(r);
+            acc += r * r;
+            fc[i] = fn[i];
+        }
+        if (HAS_E) store_cells<double, CPT>(xout + c, z.xc);
+        store_cells<SL, CPT>(rlo + c, rl);
         z.advance();
-        fc = fn;
     }
     acc = block_sum_n<kS3Threads>(acc);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;

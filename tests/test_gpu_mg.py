@@ -189,6 +189,35 @@ def test_prolong_sweep_fusion_bit_identical(B, orc, bc, nu2, d, n):
 
 
 @pytest.mark.parametrize("bc", [DIR, PER])
+def test_refinement_two_cells_per_thread_bit_identical(B, orc, bc):
+    """The 3D refinement step with two cells per thread (16-byte FP64 accesses) gives
+    the one-cell form's mixed-precision solves bit for bit, with the same cycle and
+    refinement counts, and they meet the tolerance by the oracle's residual."""
+    n = 128
+    rng = np.random.default_rng(171 + bc)
+    f = rng.standard_normal((n, n, n))
+    if bc == PER:
+        f -= f.mean()
+    h = 1.0 / n
+    out = {}
+    try:
+        for v in (1, 2):
+            B.np_set_tuning("ir_cpt", v)
+            for prec in (B.FP32, B.BF16):
+                say("ir_cpt", v, bc, prec)
+                xg = dev(np.zeros_like(f))
+                st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, smooth_prec=prec)
+                out[(v, prec)] = (host(xg), stats["cycles"], stats["outer_iters"])
+    finally:
+        B.np_set_tuning("ir_cpt", 2)
+    for prec in (B.FP32, B.BF16):
+        a, b = out[(1, prec)], out[(2, prec)]
+        assert a[1:] == b[1:], prec
+        assert np.array_equal(a[0], b[0]), prec
+        assert orc.rel_res(f, b[0], h, bc) <= 1e-10
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
 def test_prof_level_runs_the_solver_kernels(B, orc, bc):
     """The timing hook launches the solver's level kernels (FP64, 128^3, the z-marching
     kernels): the sweep's output is one oracle Jacobi sweep, the restriction's is the
@@ -260,7 +289,7 @@ def test_tuning_knobs_validate(B):
         B.np_set_tuning("no_such_knob", 1)
     with pytest.raises(B.NeuphysError):
         B.np_set_tuning("bz3", 3)
-    for key, bad in (("zc3", 3), ("zc3", 1), ("conv3z", 6), ("conv3z", 128)):
+    for key, bad in (("zc3", 3), ("zc3", 1), ("conv3z", 6), ("conv3z", 128), ("ir_cpt", 0), ("ir_cpt", 3)):
         with pytest.raises(B.NeuphysError):
             B.np_set_tuning(key, bad)
     assert B.np_get_tuning("fused") == 0 and B.np_get_tuning("tail") == 1
