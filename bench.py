@@ -584,8 +584,9 @@ def main():
                        "fused_down": "k_fused: 2 sweeps + residual + restriction, finest level",
                        "fused_down_zero": "k_fused: zero-guess sweeps + residual + restriction",
                        "fused_up": "k_fused: prolongation + 2 sweeps, finest level"}[dom] +
-                      ({"fp32": " (FP32 correction and residual, one cell per thread)",
-                        "bf16": " (BF16 correction and residual, one cell per thread)"}[head] if dom == "refine" else
+                      (" (%s correction and residual, %s per thread)" % (
+                          head.upper(), "two cells" if B.np_get_tuning("ir_cpt") == 2 else "one cell")
+                       if dom == "refine" else
                        {"fp32": " (FP32 storage)", "bf16": " (BF16 storage, two cells per thread)"}[head]),
             "bound": "hbm",
             "achieved": achieved,
