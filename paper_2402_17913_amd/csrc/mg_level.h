@@ -600,9 +600,10 @@ __global__ __launch_bounds__(kS3Threads) void k_psweep3(const S *__restrict__ ec
     auto corr_cells = [&](C (&v)[CPT], int p) {
         for (int c = 0; c < CPT; ++c) v[c] = corr(v[c], CPT * z.tp + c, z.ty, p);
     };
-    // In the loop, each coarse plane's in-plane values at this thread's cells (own
-    // columns: bo; halo slot: bh) are formed once and serve the four fine planes
-    // that use it; a correction is then prolong_mix of two of them.
+    // In the loop a correction is prolong_mix of two coarse planes' in-plane values
+    // at the cell.  For the own columns each coarse plane's values are formed once
+    // and kept (oa, ob) for the fine planes that use them; the halo slot's are
+    // formed per plane (keeping them too costs occupancy, measured slower).
     const int oly = (z.ty + 2) >> 1, ony = oly + ((z.ty & 1) ? 1 : -1);
     const int hly = (z.hy + 1) >> 1, hny = hly + ((z.hy & 1) ? -1 : 1);  // fy = hy - 1
     int olx[CPT], onx[CPT], hlx[CPT], hnx[CPT];
