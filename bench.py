@@ -119,26 +119,60 @@ def measured_traffic(kernel, head):
     return int(m1.group(1))
 
 
-def cpu_baseline(f, h, cycles_needed):
-    """The oracle (single thread) on a bounded sample of the same solve: two of its
-    V-cycles plus the residual evaluation that precedes each, timed, then scaled to
-    the cycle count the solve needs (the GPU FP64 path runs the identical algorithm
-    and its cycle count is the oracle's)."""
+def host_threads():
+    """Host threads the oracle may use: OMP_NUM_THREADS when set (the CPU share of
+    the process), else the CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else len(os.sched_getaffinity(0))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(f, h, gpu_x):
+    """The oracle on the host cores.  All cores: its OpenMP timing build (-O3, the
+    solve's cell loops in parallel) runs full solves of the same 256^3 problem to
+    1e-10, one untimed then the median of three.  One core: the same build on a
+    bounded sample, two V-cycles with the residual evaluation around them, scaled to
+    the cycle count of a full solve.  The untimed solve's converged x is the FP64
+    oracle solution that each GPU path's result (gpu_x: name -> host array) is
+    compared with: max |x - x_oracle| / max |x_oracle|."""
     import numpy as np
 
     import oracle
-    oracle.lib()
-    x = np.zeros_like(f)
+    threads = host_threads()
+    ref = oracle.mg_solve(f, h, oracle.BC_DIRICHLET0, tol=TOL, threads=threads)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        res = oracle.mg_solve(f, h, oracle.BC_DIRICHLET0, tol=TOL, threads=threads)
+        times.append(time.perf_counter() - t0)
+    t_all = sorted(times)[1]
     sample_cycles = 2
     t0 = time.perf_counter()
-    for _ in range(sample_cycles):
-        oracle.residual(f, x, h, oracle.BC_DIRICHLET0)
-        x = oracle.vcycle(f, x, h, oracle.BC_DIRICHLET0)
-    t = (time.perf_counter() - t0) / sample_cycles
-    per_solve = t * cycles_needed
-    return dict(value=f.size / per_solve, unit="DOF/s", cores=1, kind="oracle",
-                sample="%d oracle V(2,2) cycles (+ residual) on the 256^3 workload, %.2f s each, "
-                       "scaled to the %d cycles of a full solve" % (sample_cycles, t, cycles_needed))
+    oracle.mg_solve(f, h, oracle.BC_DIRICHLET0, fixed_cycles=sample_cycles, threads=1)
+    t_one = (time.perf_counter() - t0) / sample_cycles * res.cycles
+    scale = float(np.abs(ref.x).max())
+    err = {name: float(np.abs(x - ref.x).max()) / scale for name, x in gpu_x.items()}
+    base = dict(value=f.size / t_all, unit="DOF/s", cores=threads, kind="oracle",
+                sample="full solves of the %d^3 workload to 1e-10 (%d cycles, rel_res %.2e) by the oracle's "
+                       "OpenMP timing build on %d threads: median of 3 after 1 untimed, %.2f s each"
+                       % (f.shape[0], res.cycles, res.rel_res, threads, t_all),
+                cpu_model=cpu_model(), seconds_per_solve=t_all, seconds_per_solve_runs=times,
+                single_thread=dict(value=f.size / t_one, unit="DOF/s", cores=1,
+                                   sample="%d oracle V(2,2) cycles with their residual checks on the same "
+                                          "problem, scaled to the %d cycles of a full solve (%.1f s)"
+                                          % (sample_cycles, res.cycles, t_one)),
+                note="the oracle is plain unfused C loops (a reference, not a tuned CPU multigrid)")
+    return base, dict(norm="max|x - x_oracle| / max|x_oracle|, x_oracle the oracle's FP64 solve to 1e-10",
+                      oracle_cycles=ref.cycles, oracle_rel_res=ref.rel_res, **err)
 
 
 def timed(fn, steps, warmup):
@@ -376,6 +410,16 @@ def leg_ad(B, inputs, steps, warmup):
                                  stats["cycles"], paper[vn]["ms_per_solve"]))
     out["paper_2d_128"] = paper
     del T0, x
+    out.update(ad_large(B, inputs, steps, warmup))
+    return dict(workload="ad_implicit_dirichlet_upwind_C50_nu_dt100_gaussian_tol1e-10_fp64", **out)
+
+
+def ad_large(B, inputs, steps, warmup):
+    """The advection-diffusion solve at 4096^2 (gamma 320) and 256^3 (gamma 20): time
+    to 1e-10 and the finest-level kernels against HBM (the same coefficients as the
+    paper's 128^2 case)."""
+    import torch
+    out = {}
     for name, d, n, gamma in (("2d_4096", 2, 4096, 320.0), ("3d_256", 3, 256, 20.0)):
         T0 = torch.from_numpy(inputs.gaussian_2d(n, gamma=gamma) if d == 2 else
                               inputs.gaussian_3d(n, gamma=gamma)).cuda()
@@ -391,7 +435,7 @@ def leg_ad(B, inputs, steps, warmup):
             name, out[name]["ms_per_solve"], stats["cycles"], out[name]["dofs_per_s"],
             ker.get("sweep", {}).get("avg_us", -1), ker.get("sweep", {}).get("frac", -1)))
         del T0, x
-    return dict(workload="ad_implicit_dirichlet_upwind_C50_nu_dt100_gaussian_tol1e-10_fp64", **out)
+    return out
 
 
 def leg_explicit(B, inputs, steps, warmup):
@@ -494,9 +538,10 @@ def main():
     dofs = f.size
     copy_gbs = copy_bandwidth()
     log("device copy: %.0f GB/s" % copy_gbs)
-    res = {}
+    res, gpu_x = {}, {}
     for name, prec in (("fp64", B.FP64), ("fp32", B.FP32), ("bf16", B.BF16)):
         dt, stats = time_path(B, fg, xg, h, prec, args.steps, args.warmup)
+        gpu_x[name] = xg.cpu().numpy()
         prof = kernel_times(B, fg, xg, h, prec, max(1, min(args.steps, 3)))
         res[name] = dict(seconds=dt, stats=stats, prof=prof, dofs_per_s=dofs * args.steps / dt)
         log("  kernels: " + ", ".join("%s %.1f us %.0f GB/s" % (k, v["avg_us"], v["gbs"])
@@ -605,9 +650,14 @@ def main():
         },
         "cpu_baseline": None,
     }
+    line["config"]["error_vs_fp64_oracle"] = None
     if not args.no_cpu:
         log("timing the oracle on the host ...")
-        line["cpu_baseline"] = cpu_baseline(f, h, res["fp64"]["stats"]["cycles"])
+        line["cpu_baseline"], line["config"]["error_vs_fp64_oracle"] = cpu_baseline(f, h, gpu_x)
+        log("  oracle: %.3g DOF/s on %d threads; error vs oracle %s" % (
+            line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"],
+            {k: v for k, v in line["config"]["error_vs_fp64_oracle"].items() if k in gpu_x}))
+    del gpu_x
     legs = [l for l in args.legs.split(",") if l]
     others = {}
     for leg in legs:
@@ -624,6 +674,8 @@ def main():
             others["sawtooth"] = leg_sawtooth(B, inputs, args.steps, args.warmup)
         elif leg == "ad":
             others["ad"] = leg_ad(B, inputs, args.steps, args.warmup)
+        elif leg == "ad_large":  # the large advection-diffusion solves only (kernel profiles)
+            others["ad_large"] = ad_large(B, inputs, args.steps, args.warmup)
         elif leg == "explicit":
             others["explicit"] = leg_explicit(B, inputs, args.steps, args.warmup)
         elif leg == "collocated":

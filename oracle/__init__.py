@@ -31,51 +31,69 @@ def lib():
     """Load liboracle.so, compiling it first only if it is not built."""
     global _lib
     if _lib is None:
-        path = os.path.join(_HERE, "liboracle.so")
-        if not os.path.exists(path):
-            _build.build()
-        L = ctypes.CDLL(path)
-        sig = {
-            "or_apply_A": [_d, _i64, _f64, _d, _p, _p],
-            "or_residual": [_d, _i64, _f64, _d, _p, _p, _p],
-            "or_rel_res": [_d, _i64, _f64, _d, _p, _p],
-            "or_jacobi": [_d, _i64, _f64, _d, _f64, _p, _p, _p],
-            "or_restrict": [_d, _i64, _p, _p],
-            "or_prolong_add": [_d, _i64, _d, _p, _p],
-            "or_coarse_solve": [_d, _i64, _f64, _d, _p, _p],
-            "or_vcycle": [_d, _i64, _f64, _d, _d, _d, _f64, _i64, _p, _p],
-            "or_mg_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _d, _d, _f64, _d, _d, _d, _i64,
-                            _p, _p, _p, _d],
-            "or_ad_scalar_step": [_d, _i64, _f64, _d, _p, _p, _f64, _f64],
-            "or_divergence": [_d, _i64, _f64, _p, _p],
-            "or_gradient": [_d, _i64, _f64, _p, _p],
-            "or_ns_momentum": [_d, _i64, _f64, _f64, _f64, _p, _p],
-            "or_ns_step": [_d, _i64, _f64, _p, _p, _p, _p, _f64, _f64, _f64, _d, _d, _f64, _d, _d,
-                           _i64, _p, _p],
-            "or_prolong_const_add": [_d, _i64, _p, _p],
-            "or_sawtooth": [_d, _i64, _f64, _d, _f64, _d, _d, _i64, _p, _p],
-            "or_saw_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _f64, _d, _d, _d, _d, _i64, _p, _p, _p, _d],
-            "or_ad_apply": [_p, _i64, _f64, _p, _p],
-            "or_ad_explicit_step": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _f64],
-            "or_nsc_derivative": [_d, _i64, _f64, _d, _d, _p, _p],
-            "or_nsc_momentum": [_d, _i64, _f64, _d, _f64, _f64, _p, _p],
-            "or_nsc_project": [_d, _i64, _f64, _d, _f64, _p, _p, _f64, _d, _p, _p],
-            "or_nsc_step": [_d, _i64, _f64, _d, _f64, _f64, _p, _p, _f64, _d, _p],
-            "or_ad_explicit_rate": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _p],
-            "or_ad_jacobi": [_p, _i64, _f64, _f64, _p, _p, _p],
-            "or_ad_vcycle": [_p, _i64, _f64, _d, _d, _f64, _i64, _p, _p],
-            "or_ad_sawtooth": [_p, _i64, _f64, _f64, _d, _d, _i64, _p, _p],
-            "or_ad_solve": [_p, _i64, _f64, _p, _p, _f64, _d, _d, _d, _f64, _d, _d, _d, _i64, _p, _p, _p, _p, _d],
-        }
-        for name, args in sig.items():
-            fn = getattr(L, name)
-            fn.argtypes = args
-            fn.restype = _f64 if name == "or_rel_res" else (None if name in (
-                "or_apply_A", "or_residual", "or_jacobi", "or_restrict", "or_prolong_add",
-                "or_divergence", "or_gradient", "or_ns_momentum", "or_prolong_const_add", "or_ad_apply",
-                "or_ad_jacobi", "or_nsc_derivative", "or_nsc_momentum") else ctypes.c_int)
-        _lib = L
+        _lib = _load("liboracle.so")
     return _lib
+
+
+_lib_omp = None
+
+
+def lib_timing():
+    """The host-timing build (liboracle_omp.so: -O3, OpenMP over the solve's cell
+    loops); used only to time the oracle for the benchmark's CPU baseline."""
+    global _lib_omp
+    if _lib_omp is None:
+        _lib_omp = _load("liboracle_omp.so")
+    return _lib_omp
+
+
+def _load(name):
+    path = os.path.join(_HERE, name)
+    if not os.path.exists(path):
+        _build.build()
+    L = ctypes.CDLL(path)
+    sig = {
+        "or_apply_A": [_d, _i64, _f64, _d, _p, _p],
+        "or_residual": [_d, _i64, _f64, _d, _p, _p, _p],
+        "or_rel_res": [_d, _i64, _f64, _d, _p, _p],
+        "or_jacobi": [_d, _i64, _f64, _d, _f64, _p, _p, _p],
+        "or_restrict": [_d, _i64, _p, _p],
+        "or_prolong_add": [_d, _i64, _d, _p, _p],
+        "or_coarse_solve": [_d, _i64, _f64, _d, _p, _p],
+        "or_vcycle": [_d, _i64, _f64, _d, _d, _d, _f64, _i64, _p, _p],
+        "or_mg_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _d, _d, _f64, _d, _d, _d, _i64,
+                        _p, _p, _p, _d],
+        "or_ad_scalar_step": [_d, _i64, _f64, _d, _p, _p, _f64, _f64],
+        "or_divergence": [_d, _i64, _f64, _p, _p],
+        "or_gradient": [_d, _i64, _f64, _p, _p],
+        "or_ns_momentum": [_d, _i64, _f64, _f64, _f64, _p, _p],
+        "or_ns_step": [_d, _i64, _f64, _p, _p, _p, _p, _f64, _f64, _f64, _d, _d, _f64, _d, _d,
+                       _i64, _p, _p],
+        "or_prolong_const_add": [_d, _i64, _p, _p],
+        "or_sawtooth": [_d, _i64, _f64, _d, _f64, _d, _d, _i64, _p, _p],
+        "or_saw_solve": [_d, _i64, _f64, _d, _p, _p, _f64, _f64, _d, _d, _d, _d, _i64, _p, _p, _p, _d],
+        "or_ad_apply": [_p, _i64, _f64, _p, _p],
+        "or_ad_explicit_step": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _f64],
+        "or_nsc_derivative": [_d, _i64, _f64, _d, _d, _p, _p],
+        "or_nsc_momentum": [_d, _i64, _f64, _d, _f64, _f64, _p, _p],
+        "or_nsc_project": [_d, _i64, _f64, _d, _f64, _p, _p, _f64, _d, _p, _p],
+        "or_nsc_step": [_d, _i64, _f64, _d, _f64, _f64, _p, _p, _f64, _d, _p],
+        "or_ad_explicit_rate": [_d, _i64, _f64, _d, _d, _p, _p, _f64, _p],
+        "or_ad_jacobi": [_p, _i64, _f64, _f64, _p, _p, _p],
+        "or_ad_vcycle": [_p, _i64, _f64, _d, _d, _f64, _i64, _p, _p],
+        "or_ad_sawtooth": [_p, _i64, _f64, _f64, _d, _d, _i64, _p, _p],
+        "or_ad_solve": [_p, _i64, _f64, _p, _p, _f64, _d, _d, _d, _f64, _d, _d, _d, _i64, _p, _p, _p, _p, _d],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = _f64 if name == "or_rel_res" else (None if name in (
+            "or_apply_A", "or_residual", "or_jacobi", "or_restrict", "or_prolong_add",
+            "or_divergence", "or_gradient", "or_ns_momentum", "or_prolong_const_add", "or_ad_apply",
+            "or_ad_jacobi", "or_nsc_derivative", "or_nsc_momentum") else ctypes.c_int)
+    L.or_threads.argtypes = [_d]
+    L.or_threads.restype = ctypes.c_int
+    return L
 
 
 def _arr(a):
@@ -267,14 +285,20 @@ class SolveResult:
 
 
 def mg_solve(f, h, bc, tol=1e-10, nu1=2, nu2=2, omega=2.0 / 3.0, max_cycles=200,
-             fixed_cycles=0, x0=None, n_coarsest=4):
+             fixed_cycles=0, x0=None, n_coarsest=4, threads=0):
+    """Multigrid solve (or_mg_solve).  threads > 0 runs the host-timing build with
+    that many OpenMP threads instead of the test build."""
     f = _arr(f)
     d, n = _grid(f)
     x = np.zeros_like(f) if x0 is None else _arr(x0).copy()
     cyc = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
     hist = np.zeros(256)
-    st = lib().or_mg_solve(d, n, h, bc, _ptr(f), _ptr(x), tol, nu1, nu2, omega, max_cycles,
+    L = lib()
+    if threads > 0:
+        L = lib_timing()
+        L.or_threads(threads)
+    st = L.or_mg_solve(d, n, h, bc, _ptr(f), _ptr(x), tol, nu1, nu2, omega, max_cycles,
                            fixed_cycles, 0 if x0 is None else 1, n_coarsest,
                            ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist), 256)
     if st == -1:

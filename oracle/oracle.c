@@ -10,6 +10,11 @@
  * Every routine is a direct, unfused loop over cells, written to be checked
  * against the paper by eye.  Floating point is FP64 throughout.
  *
+ * The OpenMP pragmas on the cell loops of the multigrid solve only matter in
+ * the separate host-timing build (compiled with -fopenmp); the build the
+ * tests load is compiled without it, so they are ignored there and every
+ * loop, reductions included, runs in the order written.
+ *
  * Grid convention.  A d-dimensional grid (d = 2 or 3) of n cells per axis,
  * cell index (i, j, k) with i fastest: idx = (k*n + j)*n + i.  Cell i has its
  * centre at (i + 1/2) h.  Two boundary treatments, both realised as padding
@@ -72,6 +77,7 @@ void or_apply_A(int d, i64 n, double h, int bc, const double *x, double *y)
 {
     const double inv_h2 = 1.0 / (h * h);
     const i64 nz = d == 3 ? n : 1;
+#pragma omp parallel for collapse(2) schedule(static)
     for (i64 k = 0; k < nz; ++k)
         for (i64 j = 0; j < n; ++j)
             for (i64 i = 0; i < n; ++i) {
@@ -89,12 +95,14 @@ void or_residual(int d, i64 n, double h, int bc, const double *f, const double *
 {
     const i64 m = ncells(d, n);
     or_apply_A(d, n, h, bc, x, r);
+#pragma omp parallel for schedule(static)
     for (i64 c = 0; c < m; ++c) r[c] = f[c] - r[c];
 }
 
 static double dot(i64 m, const double *a, const double *b)
 {
     double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
     for (i64 c = 0; c < m; ++c) s += a[c] * b[c];
     return s;
 }
@@ -123,6 +131,7 @@ void or_jacobi(int d, i64 n, double h, int bc, double omega, const double *f, co
     const i64 m = ncells(d, n);
     const double a00 = 2.0 * d / (h * h);
     or_apply_A(d, n, h, bc, x_in, x_out);
+#pragma omp parallel for schedule(static)
     for (i64 c = 0; c < m; ++c) x_out[c] = x_in[c] + omega * (f[c] - x_out[c]) / a00;
 }
 
@@ -133,6 +142,7 @@ void or_restrict(int d, i64 n, const double *r, double *fc)
 {
     const i64 nc = n / 2, nzc = d == 3 ? nc : 1;
     const double w = d == 3 ? 0.125 : 0.25;
+#pragma omp parallel for collapse(2) schedule(static)
     for (i64 K = 0; K < nzc; ++K)
         for (i64 J = 0; J < nc; ++J)
             for (i64 I = 0; I < nc; ++I) {
@@ -157,6 +167,7 @@ void or_restrict(int d, i64 n, const double *r, double *fc)
 void or_prolong_add(int d, i64 nc, int bc, const double *e, double *x)
 {
     const i64 n = 2 * nc, nz = d == 3 ? n : 1;
+#pragma omp parallel for collapse(2) schedule(static)
     for (i64 k = 0; k < nz; ++k)
         for (i64 j = 0; j < n; ++j)
             for (i64 i = 0; i < n; ++i) {
@@ -1059,4 +1070,21 @@ int or_nsc_step(int d, i64 n, double h, int scheme, double dt, double nu, double
         return OR_EINVAL;
     or_nsc_momentum(d, n, h, scheme, dt, nu, q, p);
     return or_nsc_project(d, n, h, scheme, dt, q, p, tol, fixed_cycles, cycles_out, NULL);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Thread count of the OpenMP loops in the host-timing build (nthreads > 0
+ * sets it); returns the count in effect: 1 in the test build. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int or_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
 }

@@ -797,6 +797,9 @@ static np_status run_graph(Hier *H, const GraphKey &key, hipStream_t s, F enqueu
         size_t v = 0;
         for (size_t i = 1; i < H->graphs.size(); ++i)
             if (H->graphs[i].used < H->graphs[v].used) v = i;
+        // the evicted graph may have been launched earlier in this call: it is
+        // destroyed only once the stream has finished every launch before it
+        NP_HIP_TRY(hipStreamSynchronize(s));
         (void)hipGraphExecDestroy(H->graphs[v].exec);
         H->graphs.erase(H->graphs.begin() + v);
     }

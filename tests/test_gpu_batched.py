@@ -117,6 +117,43 @@ def test_batched_autotuner(B, orc):
     assert B.np_last_autotune() == (0, 0.0)  # cached
 
 
+def test_batched_full_workload_judged_by_oracle(B, orc):
+    """The batched workload at its own size: 512 problems with sizes drawn by seed 0
+    from {64..1024}^2 (right-hand side seed 1000 + i), FP32 inner cycles with FP64
+    refinement and the autotuned settings, as the benchmark runs it.  Every problem's
+    result is judged by the oracle's relative residual."""
+    import torch
+    sizes = inputs.batched_sizes(512, seed=0)
+    print("batched 512: %d DOFs" % sum(n * n for n in sizes), flush=True)
+    f = [inputs.sine_rhs(2, n, seed=1000 + i)["f"] for i, n in enumerate(sizes)]
+    h = [1.0 / n for n in sizes]
+    fd = [dev(a) for a in f]
+    x = [torch.zeros_like(a) for a in fd]
+    st, stats = B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
+    assert st == 0
+    worst = 0.0
+    for i, (a, hh) in enumerate(zip(f, h)):
+        rr = orc.rel_res(a, host(x[i]), hh, DIR)
+        worst = max(worst, rr)
+        assert rr <= 1e-10, (i, sizes[i], rr)
+        assert abs(rr - stats[i]["rel_res"]) <= 1e-3 * rr + 1e-16, (i, rr, stats[i]["rel_res"])
+    print("batched 512: worst oracle rel_res %.3e" % worst, flush=True)
+
+
+def test_batched_fp64_matches_oracle_at_1024(B, orc):
+    """Cycle-for-cycle FP64 parity (as above) with the largest size of the workload,
+    1024^2, next to smaller problems of other depths."""
+    sizes = [1024, 64, 1024, 256]
+    f, h = make(sizes, seed0=5000)
+    k = 3
+    x = [dev(np.zeros_like(a)) for a in f]
+    st, stats = B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=B.FP64,
+                                           inner_cycles=1, fixed_cycles=k)
+    for i, (a, hh) in enumerate(zip(f, h)):
+        ref = orc.mg_solve(a, hh, DIR, fixed_cycles=k)
+        assert rel(host(x[i]), ref.x) < 1e-12, (sizes[i], rel(host(x[i]), ref.x))
+
+
 def test_batched_rejects_bad_input(B):
     import torch
     a = torch.zeros((16, 16), dtype=torch.float64, device="cuda")

@@ -55,6 +55,50 @@ def test_projection_step_parity(B, orc, d, n, seed):
     assert np.linalg.norm(div) / np.linalg.norm(orc.divergence(qs, h)) <= 1.5e-10
 
 
+def test_projection_step_parity_2d_1024(B, orc):
+    """One step of the 2D periodic workload at its own size (1024^2, seed 0, nu 1e-3,
+    dt = CFL 0.5) from a shared state with a seeded mean-free pressure, against the
+    oracle's step (Section 2.4, the projection algorithm) at the oracle's cycle count."""
+    n, d = 1024, 2
+    print("ns step 2d 1024", flush=True)
+    g = inputs.divfree_velocity(d, n, seed=0)
+    h, dt, nu = g["h"], g["dt"], 1e-3
+    rng = np.random.default_rng(11)
+    p = 0.1 * rng.standard_normal((n, n))
+    p -= p.mean()
+    q_ref, p_ref, cyc, rr, st = orc.ns_step(g["q"], p, h, dt, nu)
+    assert st == 0 and rr <= 1e-10
+    q = [dev(c) for c in g["q"]]
+    pg = dev(p)
+    st, stats = B.ns_projection_step(q[0], q[1], None, pg, h, dt, nu, fixed_cycles=cyc)
+    assert stats["cycles"] == cyc
+    errs = [rel(host(q[c]), q_ref[c]) for c in range(d)] + [rel(host(pg), p_ref)]
+    print("2d 1024: %d cycles, rel diffs %s" % (cyc, ["%.2e" % e for e in errs]), flush=True)
+    assert max(errs) < 1e-12
+
+
+def test_projection_step_parity_3d_256(B, orc):
+    """One step of the 3D periodic workload at its own size (256^3, seed 0) with two
+    pressure cycles (bounding the oracle's time): momentum stages, divergence, the
+    periodic 256^3 multigrid solve and the correction against the oracle's step."""
+    n, d = 256, 3
+    print("ns step 3d 256", flush=True)
+    g = inputs.divfree_velocity(d, n, seed=0)
+    h, dt, nu = g["h"], g["dt"], 1e-3
+    rng = np.random.default_rng(12)
+    p = 0.1 * rng.standard_normal((n,) * 3)
+    p -= p.mean()
+    q_ref, p_ref, cyc, rr, st = orc.ns_step(g["q"], p, h, dt, nu, fixed_cycles=2)
+    assert st == 0 and cyc == 2
+    q = [dev(c) for c in g["q"]]
+    pg = dev(p)
+    st, stats = B.ns_projection_step(q[0], q[1], q[2], pg, h, dt, nu, fixed_cycles=2)
+    assert stats["cycles"] == 2
+    errs = [rel(host(q[c]), q_ref[c]) for c in range(d)] + [rel(host(pg), p_ref)]
+    print("3d 256: rel diffs %s" % ["%.2e" % e for e in errs], flush=True)
+    assert max(errs) < 1e-12
+
+
 def test_projection_step_many_steps_drift(B, orc):
     """Ten steps from a shared start stay within 1e-11 of the oracle (reported drift)."""
     n, d = 64, 2

@@ -341,6 +341,45 @@ def test_3d_sine_rhs_closed_form(orc):
     assert np.linalg.norm(res.x - uh) <= bound * (1 + 1e-6) + 1e-14 * np.linalg.norm(uh)
 
 
+# ------------------------------------------------- the judge: relative residual
+@pytest.mark.parametrize("d,n", [(2, 8), (3, 4)])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_rel_res_matches_dense_definition(orc, d, n, bc):
+    """or_rel_res judges every GPU result (mixed, batched, learned).  Pinned to
+    ||f - A x||_2 / ||f||_2 with A assembled entry by entry (numpy), to exactly 1 at
+    x = 0 (r = f), to roundoff at the dense solution, and to invariance under a
+    common scaling of f and x: a wrong norm, a wrong denominator (||r_0|| or
+    ||A x||) or a dropped neighbour fails one of these."""
+    h = 1.0 / n
+    A = dense_laplacian(d, n, h, bc)
+    rng = np.random.default_rng(10 * d + bc)
+    f = rng.standard_normal((n,) * d)
+    if bc == PER:
+        f -= f.mean()
+    x = rng.standard_normal((n,) * d) / (2 * d / h ** 2)
+    want = np.linalg.norm(vec(f) - A @ vec(x)) / np.linalg.norm(vec(f))
+    got = orc.rel_res(f, x, h, bc)
+    assert abs(got - want) <= 1e-13 * want, (got, want)
+    assert orc.rel_res(f, np.zeros_like(f), h, bc) == 1.0
+    xs = (np.linalg.pinv(A) if bc == PER else np.linalg.inv(A)) @ vec(f)
+    assert orc.rel_res(f, xs.reshape(f.shape), h, bc) < 1e-13
+    assert abs(orc.rel_res(1e6 * f, 1e6 * x, h, bc) - got) <= 1e-13 * got
+
+
+def test_rel_res_of_a_scaled_eigenvector(orc):
+    """f = the Dirichlet eigenvector sin(j pi x) sin(k pi y) (eigenvalue lambda in
+    closed form) and x = a f give r = (1 - a lambda) f, so the relative residual is
+    |1 - a lambda| exactly: an independent closed form of the judge."""
+    n = 32
+    h = 1.0 / n
+    X, _ = inputs._mesh(2, n)
+    for (j, k), c in (((1, 1), 0.3), ((5, 2), 0.999), ((7, 30), 1.7), ((3, 3), -4.0)):
+        f = np.sin(j * np.pi * X[0]) * np.sin(k * np.pi * X[1])
+        lam = (4 / h ** 2) * (np.sin(j * np.pi * h / 2) ** 2 + np.sin(k * np.pi * h / 2) ** 2)
+        got = orc.rel_res(f, (c / lam) * f, h, DIR)
+        assert abs(got - abs(1 - c)) <= 1e-11, ((j, k), got, abs(1 - c))
+
+
 # ------------------------------------------------------------ P9: invariants
 def test_zero_rhs_gives_zero_cycles(orc):
     for bc in (DIR, PER):
