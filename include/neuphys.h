@@ -106,6 +106,24 @@ np_status mg_poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, 
                            double tol, const np_mg_opts *opts, np_mg_stats *stats);
 
 /*
+ * mg_poisson_solve for callers that cannot allocate device memory (code
+ * running under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same FP64 V-cycle solve, same arguments and results, but
+ * every workspace buffer lives in one static 48 MiB device array of the
+ * library (one copy per GPU, held until the process ends), so the call
+ * allocates nothing and keeps no per-shape cache.  That holds every 2D grid up
+ * to 1024^2 and every 3D grid up to 128^3, either boundary condition; larger
+ * grids are NP_EINVAL with a message giving the bytes needed.  Only
+ * opts->smooth_prec = NP_FP64, cycle = 0 and warm_start 0 or 2 are accepted
+ * (NP_EINVAL otherwise).  Cycles are enqueued directly (no graph replay).
+ * All calls on one GPU share its array and leave their contents in it: calls
+ * that overlap in time on the same GPU (other host threads, other streams)
+ * race and must be serialised by the caller.
+ */
+np_status mg_poisson_solve_noalloc(np_dims dims, double h, np_bc bc, const double *rhs, double *x,
+                                   double tol, const np_mg_opts *opts, np_mg_stats *stats);
+
+/*
  * One projection time step of the incompressible Navier-Stokes equations
  * (Section 2.4, the projection algorithm; momentum discretised as in
  * Sections 2.1 and 2.3 with sigma = 0) on a periodic staggered grid:

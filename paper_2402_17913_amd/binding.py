@@ -69,6 +69,8 @@ _SIGS = {
     "np_release_all": (None, []),
     "mg_poisson_solve": (_I, [NpDims, _D, _I, _P, _P, _D, ctypes.POINTER(NpMgOpts),
                               ctypes.POINTER(NpMgStats)]),
+    "mg_poisson_solve_noalloc": (_I, [NpDims, _D, _I, _P, _P, _D, ctypes.POINTER(NpMgOpts),
+                                      ctypes.POINTER(NpMgStats)]),
     "ns_projection_step": (_I, [NpDims, _D, _P, _P, _P, _P, _D, _D, _I, _D,
                                 ctypes.POINTER(NpMgOpts), ctypes.POINTER(NpMgStats)]),
     "np_ad_scalar_step": (_I, [NpDims, _D, _P, _P, _D, _D, _I, ctypes.POINTER(NpMgOpts)]),
@@ -179,6 +181,18 @@ def mg_poisson_solve(rhs, x, h, bc, tol=1e-10, check=True, **opts):
                              ctypes.byref(st))
     if check:
         _check("mg_poisson_solve", s)
+    return s, st.as_dict()
+
+
+def mg_poisson_solve_noalloc(rhs, x, h, bc, tol=1e-10, check=True, **opts):
+    """mg_poisson_solve in the library's static workspace (no device allocation);
+    returns (status, stats dict)."""
+    o = make_opts(**opts)
+    st = NpMgStats()
+    s = lib.mg_poisson_solve_noalloc(_dims(rhs), h, bc, _dev(rhs), _dev(x), tol, ctypes.byref(o),
+                                     ctypes.byref(st))
+    if check:
+        _check("mg_poisson_solve_noalloc", s)
     return s, st.as_dict()
 
 

@@ -175,6 +175,7 @@ struct Hier {
     hipStream_t cap = nullptr;  // capture stream
     std::vector<GraphEntry> graphs;
     uint64_t tick = 0;
+    bool direct = false;      // enqueue cycles directly, never capture or replay graphs
     std::mutex mu;            // one solve at a time per workspace
 };
 
@@ -767,7 +768,7 @@ template <int D, class S> struct Ops {
 template <class F>
 static np_status run_graph(Hier *H, const GraphKey &key, hipStream_t s, F enqueue) {
     // timed runs bracket individual launches with events: no graphs then
-    if (!g_tune.graphs || prof_on()) return enqueue(s);
+    if (!g_tune.graphs || prof_on() || H->direct) return enqueue(s);
     for (auto &g : H->graphs)
         if (g.key == key) {
             g.used = ++H->tick;
@@ -1375,6 +1376,142 @@ extern "C" np_status mg_poisson_solve(np_dims dims, double h, np_bc bc, const do
                                       double tol, const np_mg_opts *opts, np_mg_stats *stats) {
     clear_error();
     return poisson_solve(dims, h, bc, rhs, x, tol, opts, stats);
+}
+
+// ------------------------------------------- solve in a static workspace
+// mg_poisson_solve_noalloc keeps every buffer of the FP64 solve (controller,
+// norm partials, coarsest inverse, level-0 partner and periodic rhs copy, the
+// coarse levels) in one statically sized device array, `scratch`, so that a
+// call allocates no device memory.  In host code `scratch` names a host-side
+// stand-in: its device address is taken with hipGetSymbolAddress once per
+// device (with that device current) and only that address is used.
+constexpr size_t kScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch;  // device -> its copy of `scratch`
+
+np_status scratch_on(int dev, unsigned char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error("hipGetSymbolAddress of the static workspace failed: %s", hipGetErrorString(e));
+            return NP_EHIP;
+        }
+        it = g_scratch.emplace(dev, (unsigned char *)p).first;
+    }
+    *out = it->second;
+    return NP_OK;
+}
+
+// Carves 256-byte aligned pieces off the workspace (base == nullptr: counts only).
+struct Carver {
+    unsigned char *base;
+    size_t used = 0;
+    void *take(size_t bytes) {
+        void *p = base ? base + used : nullptr;
+        used += (bytes + 255) & ~size_t(255);
+        return p;
+    }
+};
+
+// Lays the FP64 solve's buffers for an n^d grid (n = 2^lg) into the workspace
+// at base (nullptr: only the size); returns the bytes needed.
+size_t layout_noalloc(Hier &H, unsigned char *base, int d, int lg, int bc) {
+    Carver c{base};
+    const int L = lg - 2;
+    H.ctl = (Ctl *)c.take(sizeof(Ctl));
+    H.red = (double *)c.take(sizeof(double) * (kPartials + 8));
+    H.Minv = (double *)c.take(sizeof(double) * 64 * 64);
+    H.x.assign(L + 1, nullptr);
+    H.f.assign(L + 1, nullptr);
+    H.t.assign(L + 1, nullptr);
+    H.t[0] = c.take(sizeof(double) * size_t(cells(d, lg)));
+    H.f64 = bc == NP_BC_PERIODIC ? (double *)c.take(sizeof(double) * size_t(cells(d, lg))) : nullptr;
+    for (int l = 1; l <= L; ++l) {
+        const size_t bytes = sizeof(double) * size_t(cells(d, lg - l));
+        H.x[l] = c.take(bytes);
+        H.f[l] = c.take(bytes);
+        H.t[l] = c.take(bytes);
+    }
+    return c.used;
+}
+}  // namespace
+
+extern "C" np_status mg_poisson_solve_noalloc(np_dims dims, double h, np_bc bc, const double *rhs, double *x,
+                                              double tol, const np_mg_opts *opts, np_mg_stats *stats) {
+    clear_error();
+    np_mg_opts o;
+    CycleOpts co;
+    fill_opts(opts, co, o);
+    int lg = -1;
+    NP_TRY(check_solve_args(dims, h, bc, rhs, x, tol, o, &lg));
+    if (o.smooth_prec != NP_FP64 || o.cycle != 0 || o.warm_start == 1) {
+        set_error("the static-workspace solve runs FP64 V-cycles from a zero or caller guess");
+        return NP_EINVAL;
+    }
+    const int d = dims.ndim;
+    Hier H;
+    const size_t need = layout_noalloc(H, nullptr, d, lg, bc);
+    if (need > kScratchBytes) {
+        set_error("grid needs %zu bytes of workspace, more than the static %zu", need, kScratchBytes);
+        return NP_EINVAL;
+    }
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    int dev = 0;
+    NP_HIP_TRY(hipGetDevice(&dev));
+    unsigned char *base = nullptr;
+    NP_TRY(scratch_on(dev, &base));
+    Ctl hctl;
+    double hred[8];
+    H.dev = dev;
+    H.d = d;
+    H.lg = lg;
+    H.L = lg - 2;
+    H.bc = bc;
+    H.prec = NP_FP64;
+    H.es = sizeof(double);
+    H.levels = true;
+    H.direct = true;
+    H.hctl = &hctl;
+    H.hred = hred;
+    layout_noalloc(H, base, d, lg, bc);
+    hipStream_t s = (hipStream_t)o.stream;
+    const int64_t m = cells(d, lg);
+    NP_TRY(ensure_coarse(&H, h, s));
+    const double *f = rhs;
+    if (bc == NP_BC_PERIODIC) {
+        NP_HIP_TRY(hipMemcpyAsync(H.f64, rhs, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+        NP_TRY(remove_mean(&H, H.f64, m, s));
+        f = H.f64;
+    }
+    NP_TRY(dsum(&H, f, m, 1, 0, s));
+    NP_TRY(read_scalars(&H, 1, s));
+    const double nf = hred[0];
+    if (!std::isfinite(nf)) {
+        set_error("non-finite right-hand side");
+        return NP_ENAN;
+    }
+    const bool warm = o.warm_start == 2 && nf != 0.0;
+    if (!warm) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
+        NP_LAUNCH_CHECK();
+    }
+    if (nf == 0.0) {
+        NP_HIP_TRY(hipStreamSynchronize(s));
+        return NP_OK;
+    }
+    np_status st = d == 2 ? solve_fp64<2>(&H, f, x, h, tol, o, co, s, !warm, nf, stats)
+                          : solve_fp64<3>(&H, f, x, h, tol, o, co, s, !warm, nf, stats);
+    if (st == NP_EHIP || st == NP_ENOMEM || st == NP_EINVAL) return st;
+    if (bc == NP_BC_PERIODIC) NP_TRY(remove_mean(&H, x, m, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return st;
 }
 
 // ------------------------------------------------------ single operators
