@@ -244,7 +244,8 @@ def leg_c4(B, inputs, steps, warmup):
     B.mg_poisson_solve_batched(fs, xs, hs, smooth_prec=B.FP32, inner_cycles=0)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
-    inner, _ = B.np_last_autotune()
+    inner, tune_ms = B.np_last_autotune()
+    settings = B.np_last_batched_settings()
     dt, (_, stats) = timed(lambda: B.mg_poisson_solve_batched(fs, xs, hs, smooth_prec=B.FP32, inner_cycles=0),
                            steps, warmup)
     worst = max(s["rel_res"] for s in stats)
@@ -256,7 +257,7 @@ def leg_c4(B, inputs, steps, warmup):
     hist = {str(c): sizes.count(c) for c in sorted(set(sizes))}
     return dict(workload="batched_poisson2d_512_sizes64-1024_seed0_fp32+fp64", problems=len(sizes), dofs=dofs,
                 size_histogram=hist, dofs_per_s=dofs * steps / dt, ms_per_batch=1e3 * dt / steps,
-                first_call_s=setup, autotuned_inner_cycles=inner, worst_rel_res=worst,
+                first_call_s=setup, autotune_ms=tune_ms, autotuned_settings=settings, worst_rel_res=worst,
                 one_at_a_time_dofs_per_s=dofs / dts, batched_over_one_at_a_time=(dofs * steps / dt) / (dofs / dts))
 
 
@@ -271,8 +272,12 @@ def leg_c5(B, inputs, nsteps=10):
     g = inputs.divfree_velocity(3, n, seed=0)
     out = {}
     for prec_name, prec in (("fp64", B.FP64), ("fp32", B.FP32), ("bf16", B.BF16)):
-        for name, ws in (("zero_guess", 0), ("previous_dp_guess", 2), ("learned_guess", 1)):
-            B.np_cnn_load(wpath if ws == 1 else None)
+        variants = [("zero_guess", 0, 0), ("previous_dp_guess", 2, 0), ("learned_guess", 1, 0)]
+        if prec == B.FP64:  # the learned coarse-grid correction runs on FP64 V-cycles
+            variants += [("learned_cgc_first_cycle", 0, 1), ("learned_cgc_every_cycle", 0, 256),
+                         ("previous_dp_guess_and_learned_cgc_first_cycle", 2, 1)]
+        for name, ws, cgc in variants:
+            B.np_cnn_load(wpath if ws == 1 or cgc > 0 else None)
             q = [torch.from_numpy(c).cuda() for c in g["q"]]
             p = torch.zeros_like(q[0])
             # untimed: one step from a copy of the state warms workspaces, graphs and
@@ -281,24 +286,26 @@ def leg_c5(B, inputs, nsteps=10):
             # variant (there is no previous increment before the first step)
             qw = [c.clone() for c in q]
             B.ns_projection_step(qw[0], qw[1], qw[2], p.clone(), g["h"], g["dt"], 1e-3, tol=TOL,
-                                 warm_start=1 if ws == 1 else 0, smooth_prec=prec)
+                                 warm_start=1 if ws == 1 else 0, smooth_prec=prec, cnn_cgc=cgc)
             for c in qw:
                 c.zero_()
             B.ns_projection_step(qw[0], qw[1], qw[2], torch.zeros_like(p), g["h"], g["dt"], 1e-3, tol=TOL,
                                  warm_start=0, smooth_prec=prec)
             del qw
-            cyc, fb = [], 0
+            cyc, fb, kept = [], 0, 0
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(nsteps):
                 _, st = B.ns_projection_step(q[0], q[1], q[2], p, g["h"], g["dt"], 1e-3, tol=TOL,
-                                             warm_start=ws, smooth_prec=prec)
+                                             warm_start=ws, smooth_prec=prec, cnn_cgc=cgc)
                 cyc.append(st["cycles"])
                 fb += st["used_fallback"]
+                kept += st["cgc_accepted"]
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             out["%s_%s" % (prec_name, name)] = dict(ms_per_step=1e3 * dt / nsteps, cycles=cyc,
-                                                    fallbacks=fb if ws == 1 else None)
+                                                    fallbacks=fb if ws == 1 else None,
+                                                    coarse_corrections_kept=kept if cgc else None)
             log("  C5 %s %s: %.2f ms/step, cycles %s" % (prec_name, name, 1e3 * dt / nsteps, cyc))
     B.np_cnn_load(None)
     net = B.Cnn(path=wpath)

@@ -76,6 +76,15 @@ typedef struct {
                              Jacobi steps with alpha = omega; FP64 only, nu1 must be 0 */
     int prolong;          /* sawtooth only: 0 linear (as the V-cycle), 1 the paper's copy of the
                              coarse value to its 2^d fine cells */
+    int cnn_cgc;          /* learned coarse-grid correction (the hybrid of Sections 1 and 4; the
+                             multigrid cycle as a U-Net, Appendix B): in the first cnn_cgc V-cycles
+                             of an FP64 3D solve, the coarse problem on the attached network's grid
+                             (np_cnn_attach) starts from the network's prediction for its
+                             restricted residual instead of zero, kept only if it lowers that
+                             level's energy-norm error (else zero, as without it); the cycle then
+                             continues below and above as usual.  0 = off (default).  Requires
+                             smooth_prec NP_FP64 and cycle 0; nothing happens without a network of
+                             a grid the hierarchy has. */
 } np_mg_opts;
 
 typedef struct {
@@ -85,6 +94,7 @@ typedef struct {
     double rel_res;       /* final ||f - A x||_2 / ||f||_2 in FP64 (f mean-free when periodic) */
     double rho_est;       /* geometric mean residual reduction per cycle / outer step */
     double hist[256];     /* rel_res before each cycle / outer step and after the last */
+    int cgc_accepted;     /* cnn_cgc > 0: cycles whose learned coarse-grid correction was kept */
 } np_mg_stats;
 
 /* Fills *opts with the defaults listed above. */
@@ -157,11 +167,18 @@ np_status ns_projection_step(np_dims dims, double h, double *u, double *v, doubl
  * replayed from captured HIP graphs; convergence is decided per problem on
  * the device and converged problems drop out of later launches.  Each
  * problem stops at ||f - A x||_2/||f||_2 <= tol (or after opts->fixed_cycles
- * refinement steps).  opts->inner_cycles = 0 lets the autotuner pick the
- * cycles per refinement step by timing full solves of this batch (first
- * call for a given size list; cached for the process).  Requires
- * nu1 >= 1, nu1 + nu2 even, warm_start = 0.  stats: host array of nprob or
- * NULL; cycles = inner cycles run, outer_iters = refinement steps.
+ * refinement steps).  opts->inner_cycles = 0 hands the settings to the
+ * autotuner, which picks the cycles per refinement step (1..4), the sweeps
+ * per level (nu1 = nu2 in 1..3, in place of the caller's) and the level
+ * kernels' tiles (row-marching or one cell pair per thread; the workgroups a
+ * row-marching launch aims for, which set its rows per group) by timing full
+ * solves of this batch.  Its choice is cached for the process and in a JSON
+ * file keyed by (GPU architecture, precision, omega, the multiset of sizes):
+ * $NEUPHYS_TUNE_CACHE if set (empty: no file), else
+ * $XDG_CACHE_HOME/neuphys/batched_autotune.json, else
+ * $HOME/.cache/neuphys/batched_autotune.json; a cached entry skips the tuning.
+ * Requires nu1 >= 1, nu1 + nu2 even, warm_start = 0.  stats: host array of
+ * nprob or NULL; cycles = inner cycles run, outer_iters = refinement steps.
  */
 np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, const double *h, np_bc bc,
                                    const double *const *rhs, double *const *x, double tol,
@@ -170,6 +187,15 @@ np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, const double 
 /* Inner cycles chosen by the last autotuning run on this thread and the
  * wall time it took (0, 0 if the last batched call did not tune). */
 np_status np_last_autotune(int *inner_cycles, double *ms);
+
+/* Settings the last batched solve on this thread ran with (host outputs,
+ * each nullable): inner cycles per refinement step, sweeps nu1 and nu2, the
+ * row-marching tiles (1) or one cell pair per thread (0), the workgroups a
+ * row-marching launch aims for, and where they came from: 0 the caller
+ * (inner_cycles > 0), 1 tuned by this call, 2 this process's cache, 3 the
+ * cache file. */
+np_status np_last_batched_settings(int *inner_cycles, int *nu1, int *nu2, int *row_marching, int *workgroups,
+                                   int *source);
 
 /*
  * One scalar advection-diffusion step, the second-order predictor-corrector
@@ -417,7 +443,9 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * two sweeps from a zero iterate in one pass), "psweep" (0/1: prolongation + correction and the
  * first post-sweep in one pass: 2D levels above the tail, 3D levels of n >= 32), "ir_cpt" (1 or 2:
  * cells per thread of the 3D refinement kernel), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
- * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit and collocated steps, n >= 32,
+ * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths),
+ * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
+ * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit and collocated steps, n >= 32,
  * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256),
  * "zc3" (planes per workgroup of the 3D z-marching solver kernels: 0 automatic, else a power of two
  * from 2 to 64), "conv3z" (z-marching tiles for the network's convolutions: 0 off, 1 automatic planes per workgroup, else

@@ -28,19 +28,19 @@ class NpMgOpts(ctypes.Structure):
                 ("max_cycles", ctypes.c_int), ("fixed_cycles", ctypes.c_int),
                 ("smooth_prec", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("warm_start", ctypes.c_int), ("stream", ctypes.c_void_p), ("cycle", ctypes.c_int),
-                ("prolong", ctypes.c_int)]
+                ("prolong", ctypes.c_int), ("cnn_cgc", ctypes.c_int)]
 
 
 class NpMgStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("outer_iters", ctypes.c_int),
                 ("used_fallback", ctypes.c_int), ("rel_res", ctypes.c_double),
-                ("rho_est", ctypes.c_double), ("hist", ctypes.c_double * 256)]
+                ("rho_est", ctypes.c_double), ("hist", ctypes.c_double * 256), ("cgc_accepted", ctypes.c_int)]
 
     def as_dict(self):
         n = min(256, max(self.outer_iters, self.cycles) + 1)
         return dict(cycles=self.cycles, outer_iters=self.outer_iters,
                     used_fallback=self.used_fallback, rel_res=self.rel_res,
-                    rho_est=self.rho_est, hist=list(self.hist[:n]))
+                    rho_est=self.rho_est, hist=list(self.hist[:n]), cgc_accepted=self.cgc_accepted)
 
 
 class NpAdOp(ctypes.Structure):
@@ -86,6 +86,7 @@ _SIGS = {
     "mg_poisson_solve_batched": (_I, [_I, ctypes.POINTER(NpDims), ctypes.POINTER(_D), _I, _P, _P, _D,
                                       ctypes.POINTER(NpMgOpts), ctypes.POINTER(NpMgStats)]),
     "np_last_autotune": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_D)]),
+    "np_last_batched_settings": (_I, [ctypes.POINTER(_I)] * 6),
     "ns_projection_step_io": (_I, [NpDims, _D, _P, _P, _P, _P, _D, _D, _I, _D, ctypes.POINTER(NpMgOpts),
                                    ctypes.POINTER(NpMgStats), _P, _P]),
     "np_cnn_create": (_I, [_I, _I, ctypes.POINTER(_P)]),
@@ -162,13 +163,13 @@ PROLONG_LINEAR, PROLONG_COPY = 0, 1
 
 
 def make_opts(nu1=2, nu2=2, omega=2.0 / 3.0, max_cycles=200, fixed_cycles=0, smooth_prec=FP64,
-              inner_cycles=0, warm_start=0, cycle=CYCLE_V, prolong=PROLONG_LINEAR):
+              inner_cycles=0, warm_start=0, cycle=CYCLE_V, prolong=PROLONG_LINEAR, cnn_cgc=0):
     o = NpMgOpts()
     lib.np_default_opts(ctypes.byref(o))
     o.nu1, o.nu2, o.omega = nu1, nu2, omega
     o.max_cycles, o.fixed_cycles = max_cycles, fixed_cycles
     o.smooth_prec, o.inner_cycles, o.warm_start = smooth_prec, inner_cycles, warm_start
-    o.cycle, o.prolong = cycle, prolong
+    o.cycle, o.prolong, o.cnn_cgc = cycle, prolong, cnn_cgc
     o.stream = _stream()
     return o
 
@@ -220,6 +221,20 @@ def np_last_autotune():
     ms = ctypes.c_double(0.0)
     lib.np_last_autotune(ctypes.byref(inner), ctypes.byref(ms))
     return inner.value, ms.value
+
+
+BATCHED_SOURCES = {0: "caller", 1: "tuned", 2: "process cache", 3: "file cache"}
+
+
+def np_last_batched_settings():
+    """Settings of this thread's last batched solve: dict(inner_cycles, nu1, nu2,
+    row_marching, workgroups, source) with source one of BATCHED_SOURCES."""
+    v = [ctypes.c_int(0) for _ in range(6)]
+    lib.np_last_batched_settings(*[ctypes.byref(x) for x in v])
+    names = ("inner_cycles", "nu1", "nu2", "row_marching", "workgroups", "source")
+    out = {k: x.value for k, x in zip(names, v)}
+    out["source"] = BATCHED_SOURCES[out["source"]]
+    return out
 
 
 def ns_projection_step(u, v, w, p, h, dt, nu, bc=BC_PERIODIC, tol=1e-10, check=True, **opts):

@@ -12,6 +12,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <unistd.h>
+#include <sys/stat.h>
+#include <string>
+#include <cstdlib>
+#include <cstdio>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -366,10 +371,11 @@ inline unsigned rm_grid(int k, int ry, unsigned nsl) {
     return nsl * unsigned(n / tw) * unsigned(n / (G * ry));
 }
 
-// Rows per group: enough workgroups to fill the chip, at least 4 rows.
-inline int rm_rows(int k, unsigned nsl) {
+// Rows per group: the most (up to 32, at least 4) that still give `wg`
+// workgroups, enough to fill the chip (the tile setting the autotuner picks).
+inline int rm_rows(int k, unsigned nsl, int wg) {
     int ry = 32;
-    while (rm_grid(k, ry, nsl) < 4096u && ry > 4) ry /= 2;
+    while (rm_grid(k, ry, nsl) < unsigned(wg) && ry > 4) ry /= 2;
     return ry;
 }
 
@@ -751,14 +757,24 @@ struct Plan {
     double **d_x = nullptr, **d_y = nullptr;
     std::vector<double *> y;                   // host copy of the pool pointers
     std::vector<double> h;                     // finest spacing per problem (for graph keys)
+    double omega_tune = 2.0 / 3.0;             // relaxation weight of the autotuner's trials
     hipStream_t cap = nullptr;
-    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;  // (kind, inner, nu1, nu2, omega bits)
+    std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;  // (kind, inner, nu1, nu2, omega bits, rm, wg)
     std::mutex mu;
 };
 
 std::mutex g_plan_mu;
 std::map<std::vector<int64_t>, Plan *> g_plans;
-std::map<std::vector<int64_t>, int> g_tuned;  // signature -> inner cycles chosen by the autotuner
+
+// Settings of a batched solve chosen by the autotuner: inner cycles per
+// refinement step, sweeps per level (nu1 = nu2 = nu) and the level-kernel
+// tiles (row-marching on/off, workgroups a row-marching launch aims for), with
+// the tuned batch's time.
+struct BTuned {
+    int inner = 0, nu = 2, rm = 1, wg = 4096;
+    double ms = 0.0;
+};
+std::map<std::string, BTuned> g_tuned;  // cache key -> settings (this process)
 
 np_status dmalloc(void **p, size_t bytes) {
     if (hipMalloc(p, bytes) != hipSuccess) {
@@ -889,6 +905,8 @@ np_status build_plan(const std::vector<int> &lgs, const std::vector<double> &hs,
 struct BOpts {
     int nu1, nu2;
     double omega;
+    int rm;  // row-marching level kernels above the tail depths (else one cell pair per thread)
+    int wg;  // row-marching: workgroups a level launch aims for (sets the rows per group)
 };
 
 // One refinement step: kind 0 (x_a = caller x, no correction yet), 1 (x -> y),
@@ -900,7 +918,7 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
     ptr.xa = kind == 2 ? (const double *const *)B->d_y : (const double *const *)B->d_x;
     ptr.xb = kind == 1 ? B->d_y : B->d_x;
     S *const *Xp = (S *const *)B->d_Xpool, *const *Fp = (S *const *)B->d_Fpool;
-    if (g_batched_rm)
+    if (o.rm)
         hipLaunchKernelGGL((kb_ir_rm<S>), dim3(B->nirblk), dim3(kBlock), 0, s, ptr, Xp, Fp, B->d_irblk, B->d_P,
                            B->d_st, B->d_g, B->d_partial, kind == 0 ? 0 : 1);
     else
@@ -908,7 +926,7 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
                            B->d_g, B->d_partial, kind == 0 ? 0 : 1);
     NP_LAUNCH_CHECK();
     hipLaunchKernelGGL(kb_check, dim3(unsigned((B->nprob + 3) / 4)), dim3(256), 0, s, B->d_partial, B->d_P, B->d_st,
-                       B->d_g, B->nprob, g_batched_rm);
+                       B->d_g, B->nprob, o.rm);
     NP_LAUNCH_CHECK();
     hipLaunchKernelGGL(kb_check_any, dim3(1), dim3(1024), 0, s, B->d_st, B->d_g, B->nprob);
     NP_LAUNCH_CHECK();
@@ -918,9 +936,9 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
             const int64_t m = int64_t(1) << (2 * (k + 2));
             S *cur = (S *)B->X[k], *oth = (S *)B->T[k];
             const S *F = (const S *)B->F[k];
-            const int ry = rm_rows(k, nsl);
+            const int ry = rm_rows(k, nsl, o.wg);
             for (int it = 0; it < o.nu1; ++it) {
-                if (g_batched_rm)
+                if (o.rm)
                     hipLaunchKernelGGL((kb_sweep_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s, F, cur, oth,
                                        B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, it == 0 ? 1 : 0, c, o.omega, ry);
                 else
@@ -931,7 +949,7 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
                 std::swap(cur, oth);
             }
             const int n = 1 << (k + 2);
-            if (g_batched_rm)
+            if (o.rm)
                 hipLaunchKernelGGL((kb_restrict_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s, F, cur,
                                    (S *)B->F[k - 1], B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, ry);
             else
@@ -948,8 +966,8 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
             // after an odd number of pre-sweeps the iterate sits in T
             S *cur = (o.nu1 & 1) ? (S *)B->T[k] : (S *)B->X[k];
             S *oth = (o.nu1 & 1) ? (S *)B->X[k] : (S *)B->T[k];
-            const int ry = rm_rows(k, nsl);
-            if (g_batched_rm)
+            const int ry = rm_rows(k, nsl, o.wg);
+            if (o.rm)
                 hipLaunchKernelGGL((kb_prolong_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s,
                                    (const S *)B->X[k - 1], cur, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, ry);
             else
@@ -957,7 +975,7 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
                                    (const S *)B->X[k - 1], cur, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
             NP_LAUNCH_CHECK();
             for (int it = 0; it < o.nu2; ++it) {
-                if (g_batched_rm)
+                if (o.rm)
                     hipLaunchKernelGGL((kb_sweep_rm<S>), dim3(rm_grid(k, ry, nsl)), dim3(kRmT), 0, s,
                                        (const S *)B->F[k], cur, oth, B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k, 0,
                                        c, o.omega, ry);
@@ -978,7 +996,7 @@ np_status run_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t s) 
     if (!g_batched_graphs) return enqueue_step<S>(B, kind, inner, o, s);
     int64_t ob;
     std::memcpy(&ob, &o.omega, sizeof ob);
-    const auto key = std::make_tuple(kind, inner, o.nu1, o.nu2, int(ob ^ (ob >> 32)), g_batched_rm);
+    const auto key = std::make_tuple(kind, inner, o.nu1, o.nu2, int(ob ^ (ob >> 32)), o.rm, o.wg);
     auto it = B->graphs.find(key);
     if (it == B->graphs.end()) {
         NP_HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
@@ -1044,18 +1062,165 @@ np_status batched_run(Plan *B, int inner, const BOpts &o, const np_mg_opts &mo, 
     return NP_OK;
 }
 
+// ---------------------------------------------------- autotuning cache
+// The tuned settings persist in a small JSON file keyed by (GPU architecture,
+// precision, omega, the multiset of problem sizes): $NEUPHYS_TUNE_CACHE if set
+// (empty: no file), else $XDG_CACHE_HOME/neuphys/batched_autotune.json, else
+// $HOME/.cache/neuphys/batched_autotune.json.  One entry per line:
+//   "<key>": {"inner": 4, "nu": 2, "rm": 1, "wg": 4096, "ms": 52.3},
+// A missing or unreadable file is a cache miss; a failed write is ignored.
+std::string tune_cache_path() {
+    if (const char *e = std::getenv("NEUPHYS_TUNE_CACHE")) return std::string(e);
+    if (const char *x = std::getenv("XDG_CACHE_HOME"); x && *x) return std::string(x) + "/neuphys/batched_autotune.json";
+    if (const char *h = std::getenv("HOME"); h && *h) return std::string(h) + "/.cache/neuphys/batched_autotune.json";
+    return std::string();
+}
+
+std::map<std::string, BTuned> read_tune_file(const std::string &path) {
+    std::map<std::string, BTuned> out;
+    if (path.empty()) return out;
+    FILE *fp = std::fopen(path.c_str(), "r");
+    if (!fp) return out;
+    char line[4096];
+    while (std::fgets(line, sizeof line, fp)) {
+        const char *a = std::strchr(line, '"');
+        const char *b = a ? std::strchr(a + 1, '"') : nullptr;
+        if (!b || b[1] != ':') continue;
+        BTuned t;
+        if (std::sscanf(b + 1, ": {\"inner\": %d, \"nu\": %d, \"rm\": %d, \"wg\": %d, \"ms\": %lf}", &t.inner, &t.nu,
+                        &t.rm, &t.wg, &t.ms) == 5 &&
+            t.inner >= 1 && t.inner <= 16 && t.nu >= 1 && t.nu <= 16 && (t.rm == 0 || t.rm == 1) && t.wg >= 1)
+            out[std::string(a + 1, b)] = t;
+    }
+    std::fclose(fp);
+    return out;
+}
+
+void write_tune_file(const std::string &path, const std::string &key, const BTuned &t) {
+    if (path.empty()) return;
+    auto all = read_tune_file(path);
+    all[key] = t;
+    for (size_t i = 1; i < path.size(); ++i)  // parent directories
+        if (path[i] == '/') (void)::mkdir(path.substr(0, i).c_str(), 0755);
+    const std::string tmp = path + ".tmp" + std::to_string(::getpid());
+    FILE *fp = std::fopen(tmp.c_str(), "w");
+    if (!fp) return;
+    std::fprintf(fp, "{\"neuphys_batched_autotune\": 1, \"entries\": {\n");
+    size_t i = 0;
+    for (const auto &kv : all)
+        std::fprintf(fp, "\"%s\": {\"inner\": %d, \"nu\": %d, \"rm\": %d, \"wg\": %d, \"ms\": %.4f}%s\n",
+                     kv.first.c_str(), kv.second.inner, kv.second.nu, kv.second.rm, kv.second.wg, kv.second.ms,
+                     ++i < all.size() ? "," : "");
+    std::fprintf(fp, "}}\n");
+    const bool ok = std::fclose(fp) == 0;
+    if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
+}
+
+// Cache key: architecture, precision, omega and the sorted multiset of sizes.
+std::string tune_key(int dev, int prec, double omega, std::vector<int> lgs) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    else (void)hipGetLastError();
+    std::sort(lgs.begin(), lgs.end());
+    char buf[96];
+    uint64_t ob;
+    std::memcpy(&ob, &omega, sizeof ob);
+    std::snprintf(buf, sizeof buf, "|%s|omega=%016llx|", prec == NP_FP32 ? "fp32" : "fp64", (unsigned long long)ob);
+    std::string key = arch + buf;
+    for (size_t i = 0; i < lgs.size();) {
+        size_t j = i;
+        while (j < lgs.size() && lgs[j] == lgs[i]) ++j;
+        key += std::to_string(1 << lgs[i]) + "x" + std::to_string(j - i) + (j < lgs.size() ? "," : "");
+        i = j;
+    }
+    return key;
+}
+
+// Picks the batch's settings by timing full solves of it: first the inner
+// cycles and sweeps per level jointly (inner 1..4 x nu 1..3 on row-marching
+// tiles aiming at 4096 workgroups), then the tiles for the winner (one cell
+// pair per thread; row-marching aiming at 1024 or 16384 workgroups).  A
+// candidate counts only if every problem converged; each runs once untimed
+// (capturing its graphs) and is timed as the faster of two runs.
+template <class Run>
+np_status autotune(Plan *B, int nprob, hipStream_t s, Run &run, int default_inner, BTuned *out) {
+    struct Ev {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Ev() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    NP_HIP_TRY(hipEventCreate(&ev.a));
+    NP_HIP_TRY(hipEventCreate(&ev.b));
+    BTuned best;
+    best.ms = 1e300;
+    bool found = false;
+    auto trial = [&](const BTuned &c) -> np_status {
+        const BOpts bo{c.nu, c.nu, B->omega_tune, c.rm, c.wg};
+        NP_TRY(run(c.inner, bo));
+        float tmin = 1e30f;
+        for (int r = 0; r < 2; ++r) {
+            NP_HIP_TRY(hipEventRecord(ev.a, s));
+            NP_TRY(run(c.inner, bo));
+            NP_HIP_TRY(hipEventRecord(ev.b, s));
+            NP_HIP_TRY(hipEventSynchronize(ev.b));
+            float ms = 0.0f;
+            NP_HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+            tmin = std::min(tmin, ms);
+        }
+        bool ok = true;
+        for (int p = 0; p < nprob; ++p) ok = ok && B->h_st[p].stop == kConverged;
+        if (ok && tmin < best.ms) {
+            best = c;
+            best.ms = tmin;
+            found = true;
+        }
+        return NP_OK;
+    };
+    for (int nu = 1; nu <= 3; ++nu)
+        for (int inner = 1; inner <= 4; ++inner) {
+            BTuned c;
+            c.inner = inner;
+            c.nu = nu;
+            c.rm = 1;
+            c.wg = 4096;
+            NP_TRY(trial(c));
+        }
+    if (found) {
+        const BTuned w = best;
+        const int tiles[3][2] = {{0, 4096}, {1, 1024}, {1, 16384}};
+        for (auto &tl : tiles) {
+            BTuned c = w;
+            c.rm = tl[0];
+            c.wg = tl[1];
+            NP_TRY(trial(c));
+        }
+        *out = best;
+    } else {
+        BTuned d;
+        d.inner = default_inner;
+        *out = d;
+    }
+    return NP_OK;
+}
+
 }  // namespace
 
 int g_batched_graphs = 1;
 int g_batched_autotune = 1;
 int g_batched_rm = 1;
+int g_batched_wg = 4096;
 static thread_local int g_last_tune_inner = 0;
 static thread_local double g_last_tune_ms = 0.0;
+static thread_local int g_last_settings[6] = {0, 0, 0, 0, 0, 0};  // inner, nu1, nu2, rm, wg, source
 
 void release_batched_cache() {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     for (auto &kv : g_plans) free_plan(kv.second);
     g_plans.clear();
+    g_tuned.clear();
 }
 
 }  // namespace np
@@ -1131,60 +1296,59 @@ extern "C" np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, co
     hipStream_t s = (hipStream_t)o.stream;
     NP_HIP_TRY(hipMemcpyAsync(B->d_f, rhs, sizeof(double *) * nprob, hipMemcpyHostToDevice, s));
     NP_HIP_TRY(hipMemcpyAsync(B->d_x, x, sizeof(double *) * nprob, hipMemcpyHostToDevice, s));
-    const BOpts bo{o.nu1, o.nu2, o.omega};
-    auto run = [&](int inner) -> np_status {
-        return o.smooth_prec == NP_FP32 ? batched_run<float>(B, inner, bo, o, tol, s)
-                                        : batched_run<double>(B, inner, bo, o, tol, s);
+    auto run = [&](int inner_, const BOpts &bo_) -> np_status {
+        return o.smooth_prec == NP_FP32 ? batched_run<float>(B, inner_, bo_, o, tol, s)
+                                        : batched_run<double>(B, inner_, bo_, o, tol, s);
     };
-    int inner = o.inner_cycles;
+    BOpts bo{o.nu1, o.nu2, o.omega, g_batched_rm, g_batched_wg};
+    int inner = o.inner_cycles, source = 0;
     g_last_tune_inner = 0;
     g_last_tune_ms = 0.0;
     if (inner == 0) {
-        // autotuner: inner cycles per refinement step, chosen by timing full
-        // solves of this batch; cached per sorted size list and precision
-        std::vector<int64_t> sig;
-        sig.push_back(o.smooth_prec);
-        std::vector<int> sl(lgs);
-        std::sort(sl.begin(), sl.end());
-        for (int v : sl) sig.push_back(v);
+        // the autotuner's settings for this batch: from this process's cache,
+        // else the file cache, else timed full solves of this batch
+        const std::string key = tune_key(dev, o.smooth_prec, o.omega, lgs);
+        const std::string path = tune_cache_path();
+        BTuned t;
         {
             std::lock_guard<std::mutex> lk2(g_plan_mu);
-            auto it = g_tuned.find(sig);
-            if (it != g_tuned.end()) inner = it->second;
-        }
-        if (inner == 0 && g_batched_autotune && o.fixed_cycles == 0) {
-            const auto t0 = std::chrono::steady_clock::now();
-            double best = 1e300;
-            int best_inner = 2;
-            hipEvent_t e0, e1;
-            NP_HIP_TRY(hipEventCreate(&e0));
-            NP_HIP_TRY(hipEventCreate(&e1));
-            for (int cand = 1; cand <= 4; ++cand) {
-                NP_TRY(run(cand));  // first run of a candidate captures its graphs
-                NP_HIP_TRY(hipEventRecord(e0, s));
-                NP_TRY(run(cand));
-                NP_HIP_TRY(hipEventRecord(e1, s));
-                NP_HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.0f;
-                NP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                bool ok = true;
-                for (int p = 0; p < nprob; ++p) ok = ok && B->h_st[p].stop == kConverged;
-                if (ok && ms < best) { best = ms; best_inner = cand; }
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) {
+                t = it->second;
+                source = 2;
+            } else {
+                auto file = read_tune_file(path);
+                auto jt = file.find(key);
+                if (jt != file.end()) {
+                    t = jt->second;
+                    g_tuned[key] = t;
+                    source = 3;
+                }
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            inner = best_inner;
+        }
+        if (source == 0 && g_batched_autotune && o.fixed_cycles == 0) {
+            const auto t0 = std::chrono::steady_clock::now();
+            B->omega_tune = o.omega;
+            NP_TRY(autotune(B, nprob, s, run, o.smooth_prec == NP_FP32 ? 3 : 1, &t));
+            g_last_tune_inner = t.inner;
+            g_last_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             {
                 std::lock_guard<std::mutex> lk2(g_plan_mu);
-                g_tuned[sig] = inner;
+                g_tuned[key] = t;
+                write_tune_file(path, key, t);
             }
-            g_last_tune_inner = inner;
-            g_last_tune_ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            source = 1;
         }
-        if (inner == 0) inner = o.smooth_prec == NP_FP32 ? 3 : 1;
+        if (source != 0) {
+            inner = t.inner;
+            bo = BOpts{t.nu, t.nu, o.omega, t.rm, t.wg};
+        } else {
+            inner = o.smooth_prec == NP_FP32 ? 3 : 1;
+        }
     }
-    NP_TRY(run(inner));
+    const int set[6] = {inner, bo.nu1, bo.nu2, bo.rm, bo.wg, source};
+    std::memcpy(g_last_settings, set, sizeof set);
+    NP_TRY(run(inner, bo));
     np_status st = NP_OK;
     for (int p = 0; p < nprob; ++p) {
         const BState &b = B->h_st[p];
@@ -1204,6 +1368,14 @@ extern "C" np_status mg_poisson_solve_batched(int nprob, const np_dims *dims, co
     if (st == NP_ENAN) set_error("non-finite residual in a batched problem");
     else if (st == NP_ENOCONV) set_error("a batched problem did not reach the tolerance");
     return st;
+}
+
+extern "C" np_status np_last_batched_settings(int *inner_cycles, int *nu1, int *nu2, int *row_marching,
+                                              int *workgroups, int *source) {
+    int *dst[6] = {inner_cycles, nu1, nu2, row_marching, workgroups, source};
+    for (int i = 0; i < 6; ++i)
+        if (dst[i]) *dst[i] = g_last_settings[i];
+    return NP_OK;
 }
 
 extern "C" np_status np_last_autotune(int *inner_cycles, double *ms) {

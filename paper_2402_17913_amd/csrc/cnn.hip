@@ -791,6 +791,46 @@ np_status cnn_warm_start(int d, int lg, int bc, const double *f, double *x0, con
     return NP_OK;
 }
 
+// log2 of the attached network's grid size per axis, -1 when none is attached.
+int cnn_attached_lg() {
+    std::lock_guard<std::mutex> lk(g_cnn_mu);
+    return g_attached ? g_attached->lg0 : -1;
+}
+
+// Network prediction on a coarse level of the solver's cycle (the learned
+// coarse-grid correction): xc = rms * N(fc / rms) on the attached network's own
+// grid, fc the level's restricted residual (device FP64, n_in^3 cells, n_in =
+// 2^lg), rms its root mean square.  *used = false (xc untouched) when no
+// network is attached, its grid is not 2^lg per axis, or fc is zero.  Reads
+// the rms on the host (the stream is synchronised).
+np_status cnn_coarse_guess(int lg, const double *fc, double *xc, hipStream_t s, bool *used) {
+    *used = false;
+    std::lock_guard<std::mutex> lk(g_cnn_mu);
+    Net *N = g_attached;
+    if (!N || N->lg0 != lg) return NP_OK;
+    std::lock_guard<std::mutex> lk2(N->mu);
+    const int64_t mc = vox(lg);
+    const unsigned nb2 = std::min<unsigned>(kRedBlocks, unsigned((mc + 255) / 256));
+    hipLaunchKernelGGL((k_sum<double>), dim3(nb2), dim3(256), 0, s, fc, mc, 1, N->lpart);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, N->lpart, int(nb2), N->lsum, 0);
+    NP_LAUNCH_CHECK();
+    NP_HIP_TRY(hipMemcpyAsync(N->hsum, N->lsum, sizeof(double), hipMemcpyDeviceToHost, s));
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    const double rms = std::sqrt(N->hsum[0] / double(mc));
+    if (!(rms > 0.0) || !std::isfinite(rms)) return NP_OK;
+    float *in = N->S1[0], *pred = N->S1[0] + mc;  // FP32 scratch (the gradient buffers are idle)
+    hipLaunchKernelGGL(k_to32, dim3(nb(mc)), dim3(256), 0, s, fc, in, 1.0 / rms, mc);
+    NP_LAUNCH_CHECK();
+    NP_TRY(forward(N, in, s));
+    hipLaunchKernelGGL(k_take0, dim3(nb(mc)), dim3(256), 0, s, N->out, pred, mc);
+    NP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_to64, dim3(nb(mc)), dim3(256), 0, s, pred, xc, rms, mc);
+    NP_LAUNCH_CHECK();
+    *used = true;
+    return NP_OK;
+}
+
 }  // namespace np
 
 using namespace np;

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -372,6 +373,15 @@ template <int D> struct Tile {
     static constexpr int TY = D == 3 ? 16 : 1;
 };
 
+// Learned coarse-grid correction (np_mg_opts.cnn_cgc): on the way down, at
+// `level` (after its right-hand side, the restricted residual, is written and
+// before its first sweep), fn may set the level's iterate buffer to a starting
+// correction and report whether it did; otherwise the level starts from zero.
+struct CgcHook {
+    int level = -1;
+    std::function<np_status(const void *f, void *x, double h, hipStream_t s, bool *used)> fn;
+};
+
 // log2 size of the finest level of the cycle being enqueued (for profiling
 // the finest-level launches only).
 static thread_local int H_lg_top = -1;
@@ -636,7 +646,7 @@ template <int D, class S> struct Ops {
     // read); check: the residual norm of x0 is reduced and the controller's
     // stop rule runs before the rest of the cycle.  The level-0 result is in x0.
     static np_status cycle(Hier *H, S *x0, const S *f0, S *t0, bool zero0, bool check, double h,
-                           const CycleOpts &o, hipStream_t s) {
+                           const CycleOpts &o, hipStream_t s, const CgcHook *hook = nullptr) {
         const int L = H->L, bc = H->bc;
         const int *stop = &H->ctl->stop;
         H_lg_top = H->lg;
@@ -660,7 +670,12 @@ template <int D, class S> struct Ops {
         // ------------------------------------------------------------ down
         for (int l = 0; l < L; ++l, hl *= 2.0) {
             const int lg = H->lg - l;
-            const bool zero = l > 0 || zero0;
+            bool zero = l > 0 || zero0;
+            if (hook && l > 0 && l == hook->level && !fl[l]) {
+                bool used = false;
+                NP_TRY(hook->fn(F[l], cur[l], hl, s, &used));
+                if (used) zero = false;
+            }
             S *fc = (S *)H->f[l + 1];
             if (fl[l]) {
                 int nb = 0;
@@ -936,9 +951,49 @@ static np_status solve_fp64(Hier *H, const double *f, double *x, double h, doubl
         return st0;
     }
     NP_TRY(init_ctl(H, o, nf, tol, x_zero ? 1 : 0, 1.0, s));
+    // learned coarse-grid correction in the first o.cnn_cgc cycles: the coarse
+    // problem on the attached network's grid starts from the network's
+    // prediction, kept only if it lowers that level's energy-norm error
+    // (2 e'r - e'A e > 0); these cycles are enqueued directly (the network
+    // reads norms on the host)
+    CgcHook hook;
+    int cgc = 0, accepted = 0;
+    if constexpr (D == 3) {
+        const int lnet = H->lg - cnn_attached_lg();
+        if (o.cnn_cgc > 0 && cnn_attached_lg() >= 0 && lnet >= 1 && lnet < H->L) {
+            cgc = o.cnn_cgc;
+            hook.level = lnet;
+            hook.fn = [&](const void *fl, void *xl, double hl, hipStream_t q, bool *used) -> np_status {
+                const int lgl = H->lg - lnet;
+                NP_TRY(cnn_coarse_guess(lgl, (const double *)fl, (double *)xl, q, used));
+                if (!*used) return NP_OK;
+                int nb = 0;
+                NP_TRY(O::energy((const double *)fl, (const double *)xl, lgl, H->bc, hl, H->red, q, &nb));
+                hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, q, H->red, nb, H->red + kPartials, 0);
+                NP_LAUNCH_CHECK();
+                NP_TRY(read_scalars(H, 1, q));
+                if (!(H->hred[0] > 0.0)) {
+                    *used = false;
+                    return NP_OK;
+                }
+                ++accepted;
+                return NP_OK;
+            };
+        }
+    }
     if (x_zero) {
-        GraphKey k0{0, 1, 0, x, f, h, co.nu1, co.nu2, 0, co.omega};
-        NP_TRY(run_graph(H, k0, s, [&](hipStream_t q) { return O::cycle(H, x, f, t0, true, false, h, co, q); }));
+        if (cgc > 0) {
+            NP_TRY(O::cycle(H, x, f, t0, true, false, h, co, s, &hook));
+            --cgc;
+        } else {
+            GraphKey k0{0, 1, 0, x, f, h, co.nu1, co.nu2, 0, co.omega};
+            NP_TRY(run_graph(H, k0, s, [&](hipStream_t q) { return O::cycle(H, x, f, t0, true, false, h, co, q); }));
+        }
+    }
+    for (; cgc > 0; --cgc) {
+        NP_TRY(O::cycle(H, x, f, t0, false, true, h, co, s, &hook));
+        NP_TRY(read_ctl(H, s));
+        if (H->hctl->stop) break;
     }
     GraphKey key{0, 0, 1, x, f, h, co.nu1, co.nu2, 0, co.omega};
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
@@ -951,6 +1006,7 @@ static np_status solve_fp64(Hier *H, const double *f, double *x, double h, doubl
     }
     const Ctl c = *H->hctl;
     fill_stats(stats, c, c.k, c.k);
+    if (stats) stats->cgc_accepted = accepted;
     return status_of(c, tol);
 }
 
@@ -1181,7 +1237,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
         {"ir_cpt", &g_tune.ir_cpt, 1, 2},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
-        {"batched_rm", &g_batched_rm, 0, 1},
+        {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
         {"wgrad_mfma", &g_wgrad_mfma, 0, 1},
     };
@@ -1227,6 +1283,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "batched_rm")) return g_batched_rm;
+    if (!std::strcmp(key, "batched_wg")) return g_batched_wg;
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
     if (!std::strcmp(key, "zc3")) return g_zc3;
     if (!std::strcmp(key, "conv3z")) return g_conv3z;
@@ -1265,6 +1322,10 @@ static np_status check_solve_args(const np_dims &dims, double h, int bc, const v
     if (o.prolong != 0 && o.prolong != 1) { set_error("prolong must be 0 (linear) or 1 (copy)"); return NP_EINVAL; }
     if (o.cycle == 0 && o.prolong != 0) {
         set_error("the copying prolongation is available with the sawtooth cycle only");
+        return NP_EINVAL;
+    }
+    if (o.cnn_cgc < 0 || o.cnn_cgc > 256 || (o.cnn_cgc > 0 && (o.smooth_prec != NP_FP64 || o.cycle != 0))) {
+        set_error("cnn_cgc must be in [0, 256], with FP64 V-cycles");
         return NP_EINVAL;
     }
     if (o.cycle == 1 && (o.nu1 != 0 || o.smooth_prec != NP_FP64 || o.warm_start == 1)) {
@@ -1451,7 +1512,7 @@ extern "C" np_status mg_poisson_solve_noalloc(np_dims dims, double h, np_bc bc, 
     fill_opts(opts, co, o);
     int lg = -1;
     NP_TRY(check_solve_args(dims, h, bc, rhs, x, tol, o, &lg));
-    if (o.smooth_prec != NP_FP64 || o.cycle != 0 || o.warm_start == 1) {
+    if (o.smooth_prec != NP_FP64 || o.cycle != 0 || o.warm_start == 1 || o.cnn_cgc != 0) {
         set_error("the static-workspace solve runs FP64 V-cycles from a zero or caller guess");
         return NP_EINVAL;
     }

@@ -15,6 +15,12 @@ namespace np {
 void set_error(const char *fmt, ...);
 void clear_error();
 
+// ---------------------------------------------------- learned correction
+// Attached network (cnn.hip): log2 of its grid per axis (-1 when none), and
+// its prediction xc = rms * N(fc / rms) on a coarse level of that size.
+int cnn_attached_lg();
+np_status cnn_coarse_guess(int lg, const double *fc, double *xc, hipStream_t s, bool *used);
+
 #define NP_HIP_TRY(expr)                                                                   \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \
@@ -157,6 +163,7 @@ void release_batched_cache();
 extern int g_batched_graphs;
 extern int g_batched_autotune;
 extern int g_batched_rm;
+extern int g_batched_wg;
 extern int g_zmarch_explicit;
 extern int g_conv3z;
 extern int g_wgrad_mfma;

@@ -104,25 +104,106 @@ def test_batched_zero_rhs_and_repeat_calls(B, orc):
             assert orc.rel_res(f[i], host(x[i]), h[i], DIR) <= 1e-10
 
 
-def test_batched_autotuner(B, orc):
+def test_batched_autotuner(B, orc, tmp_path, monkeypatch):
+    """inner_cycles = 0: the autotuner picks inner cycles, sweeps per level and tiles
+    from its candidate sets by timing this batch; the result meets the tolerance;
+    a second call takes the settings from the process cache without tuning."""
+    monkeypatch.setenv("NEUPHYS_TUNE_CACHE", str(tmp_path / "tune.json"))
     f, h = make([64, 128, 256, 128], seed0=4000)
     fd = [dev(a) for a in f]
     x = [dev(np.zeros_like(a)) for a in f]
     B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
     inner, ms = B.np_last_autotune()
-    assert 1 <= inner <= 4 and ms > 0
+    st = B.np_last_batched_settings()
+    print("tuned", st, "%.1f ms" % ms, flush=True)
+    assert 1 <= inner <= 4 and ms > 0 and st["source"] == "tuned" and st["inner_cycles"] == inner
+    assert 1 <= st["nu1"] == st["nu2"] <= 3 and st["row_marching"] in (0, 1)
+    assert st["workgroups"] in (1024, 4096, 16384)
     for i in range(len(f)):
         assert orc.rel_res(f[i], host(x[i]), h[i], DIR) <= 1e-10
     B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
     assert B.np_last_autotune() == (0, 0.0)  # cached
+    st2 = B.np_last_batched_settings()
+    assert st2["source"] == "process cache" and {k: st2[k] for k in st2 if k != "source"} == \
+        {k: st[k] for k in st if k != "source"}
 
 
-def test_batched_full_workload_judged_by_oracle(B, orc):
+def test_batched_autotune_file_cache_skips_tuning(B, orc, tmp_path, monkeypatch):
+    """The tuned settings are written to the cache file under a key of (architecture,
+    precision, omega, sizes); after the process cache is dropped (np_release_all) the
+    next call reads them from the file and does not tune."""
+    import json
+    path = tmp_path / "cache" / "tune.json"
+    monkeypatch.setenv("NEUPHYS_TUNE_CACHE", str(path))
+    sizes = [256, 64, 512, 64, 128]
+    f, h = make(sizes, seed0=4100)
+    fd = [dev(a) for a in f]
+    x = [dev(np.zeros_like(a)) for a in f]
+    B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
+    st = B.np_last_batched_settings()
+    assert st["source"] == "tuned"
+    doc = json.load(open(path))
+    (key, entry), = doc["entries"].items()
+    assert key.startswith("gfx") and "|fp32|" in key and key.endswith("64x2,128x1,256x1,512x1")
+    assert entry["inner"] == st["inner_cycles"] and entry["nu"] == st["nu1"] and entry["ms"] > 0
+    B.np_release_all()
+    x = [dev(np.zeros_like(a)) for a in f]
+    B.mg_poisson_solve_batched(fd, x, h, smooth_prec=B.FP32, inner_cycles=0)
+    assert B.np_last_autotune() == (0, 0.0)
+    st2 = B.np_last_batched_settings()
+    assert st2["source"] == "file cache"
+    assert {k: st2[k] for k in st2 if k != "source"} == {k: st[k] for k in st if k != "source"}
+    for i in range(len(f)):
+        assert orc.rel_res(f[i], host(x[i]), h[i], DIR) <= 1e-10
+    # another precision is another key: tuned again, both entries kept
+    B.mg_poisson_solve_batched(fd, [dev(np.zeros_like(a)) for a in f], h, smooth_prec=B.FP64, inner_cycles=0)
+    assert B.np_last_batched_settings()["source"] == "tuned"
+    assert len(json.load(open(path))["entries"]) == 2
+
+
+@pytest.mark.parametrize("prec", ["FP32", "FP64"])
+def test_batched_tiles_bit_identical(B, prec):
+    """The row-marching tile setting (workgroups per launch, hence rows per group)
+    changes only how cells are distributed: identical iterates for every setting
+    the autotuner may pick."""
+    sizes = [128, 256, 512, 1024, 64, 256]
+    f, h = make(sizes, seed0=3100)
+    out = {}
+    try:
+        for wg in (1024, 4096, 16384):
+            B.np_set_tuning("batched_wg", wg)
+            x = [dev(np.zeros_like(a)) for a in f]
+            B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=getattr(B, prec),
+                                       inner_cycles=2, fixed_cycles=3)
+            out[wg] = [host(t) for t in x]
+    finally:
+        B.np_set_tuning("batched_wg", 4096)
+    for i, n in enumerate(sizes):
+        assert np.abs(out[4096][i]).max() > 0
+        assert np.array_equal(out[1024][i], out[4096][i]) and np.array_equal(out[16384][i], out[4096][i]), n
+
+
+@pytest.mark.parametrize("nu", [1, 3])
+def test_batched_other_sweep_counts_match_oracle(B, orc, nu):
+    """The sweep counts the autotuner may pick are V(nu, nu) cycles: FP64 batched
+    cycles equal the oracle's V(nu, nu) cycles."""
+    sizes = [256, 32, 128]
+    f, h = make(sizes, seed0=4200)
+    x = [dev(np.zeros_like(a)) for a in f]
+    B.mg_poisson_solve_batched([dev(a) for a in f], x, h, smooth_prec=B.FP64, inner_cycles=1, fixed_cycles=3,
+                               nu1=nu, nu2=nu)
+    for i, (a, hh) in enumerate(zip(f, h)):
+        ref = orc.mg_solve(a, hh, DIR, fixed_cycles=3, nu1=nu, nu2=nu)
+        assert rel(host(x[i]), ref.x) < 1e-12, (sizes[i], nu)
+
+
+def test_batched_full_workload_judged_by_oracle(B, orc, tmp_path, monkeypatch):
     """The batched workload at its own size: 512 problems with sizes drawn by seed 0
     from {64..1024}^2 (right-hand side seed 1000 + i), FP32 inner cycles with FP64
     refinement and the autotuned settings, as the benchmark runs it.  Every problem's
     result is judged by the oracle's relative residual."""
     import torch
+    monkeypatch.setenv("NEUPHYS_TUNE_CACHE", str(tmp_path / "tune.json"))
     sizes = inputs.batched_sizes(512, seed=0)
     print("batched 512: %d DOFs" % sum(n * n for n in sizes), flush=True)
     f = [inputs.sine_rhs(2, n, seed=1000 + i)["f"] for i, n in enumerate(sizes)]
@@ -137,7 +218,8 @@ def test_batched_full_workload_judged_by_oracle(B, orc):
         worst = max(worst, rr)
         assert rr <= 1e-10, (i, sizes[i], rr)
         assert abs(rr - stats[i]["rel_res"]) <= 1e-3 * rr + 1e-16, (i, rr, stats[i]["rel_res"])
-    print("batched 512: worst oracle rel_res %.3e" % worst, flush=True)
+    print("batched 512: worst oracle rel_res %.3e, settings %s" % (worst, B.np_last_batched_settings()),
+          flush=True)
 
 
 def test_batched_fp64_matches_oracle_at_1024(B, orc):
