@@ -108,6 +108,7 @@ _SIGS = {
                           ctypes.POINTER(_D)]),
     "np_get_tuning": (_I, [ctypes.c_char_p]),
     "np_prof_level": (_I, [NpDims, _D, _I, _I, _I, _P, _P, _P, _I, _P, ctypes.POINTER(_D)]),
+    "np_op_level": (_I, [NpDims, _D, _I, _I, _I, _P, _P, _P, _P, _P]),
     "np_ad_implicit_solve": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _D, ctypes.POINTER(NpMgOpts),
                                   ctypes.POINTER(NpMgStats), ctypes.POINTER(_D)]),
     "np_ad_apply": (_I, [NpDims, _D, _I, ctypes.POINTER(NpAdOp), _P, _P, _P]),
@@ -503,6 +504,19 @@ def np_release_all():
 
 
 PROF_LEVEL_SWEEP, PROF_LEVEL_RESTRICT, PROF_LEVEL_PROLONG = 0, 1, 2
+
+
+LEVEL_ZERO2, LEVEL_RESTRICT, LEVEL_DOWN0, LEVEL_PSWEEP_SWEEP, LEVEL_UP2 = 0, 1, 2, 3, 4
+
+
+def np_op_level(kind, f, x, xout, c, h, bc, prec):
+    """One 3D level step (np_op_level kind LEVEL_*) on tensors of the precision
+    (float64, float32, or int16 holding BF16 bit patterns); xout / c may be None
+    where the kind does not use them."""
+    dt = {FP64: torch.float64, FP32: torch.float32, BF16: torch.int16}[prec]
+    _check("np_op_level", lib.np_op_level(_dims(x), h, bc, prec, kind, _dev(f, dt), _dev(x, dt),
+                                          _dev(xout, dt) if xout is not None else None,
+                                          _dev(c, dt) if c is not None else None, _stream()))
 
 
 def np_prof_level(kind, f, x, y, h, bc, prec, reps=50):

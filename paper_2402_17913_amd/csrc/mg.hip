@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "mg_fused.h"
+#include "mg_fused3.h"
 #include "mg_level.h"
 #include "mg_kernels.h"
 #include "ad_kernels.h"
@@ -119,6 +120,9 @@ struct Tuning {
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
+    int fuse3 = 0;        // temporally blocked down-leg (from zero) and up-leg kernels on 3D levels of n >= 32
+                          // (bit-identical, measured slower than the per-kernel path: off)
+    int fz3 = 0;          // planes per workgroup of those kernels (0 = automatic)
 };
 static Tuning g_tune;
 int g_zc3 = 0;
@@ -518,6 +522,75 @@ template <int D, class S> struct Ops {
         return NP_OK;
     }
 
+    // Whether a 3D level of 2^lg cells per axis runs the temporally blocked kernels (k_down0_3 for
+    // its down-leg from zero, k_up2_3 for its up-leg with two post-sweeps).
+    static bool fuse3_on(int lg) { return D == 3 && g_tune.fuse3 && g_tune.sweep3 && lg >= 5; }
+
+    // Planes per workgroup of the temporally blocked kernels (even; knob "fz3", 0 automatic).
+    static int fused3_planes(int lg) {
+        const int n = 1 << lg;
+        int zc = n >= 256 ? 8 : (n >= 128 ? 4 : 2);
+        if (g_tune.fz3 >= 2 && g_tune.fz3 <= n) zc = g_tune.fz3;
+        return zc;
+    }
+
+    // x = two sweeps from zero, fc = R (f - A x) on a 3D level (k_down0_3; fuse3_on holds).
+    static np_status down0(const S *f, S *x, S *fc, int lg, int bc, double h, double omega, hipStream_t s,
+                           bool finest, const int *stop) {
+        if constexpr (D == 3) {
+            const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+            constexpr int TY = FCfg<S>::TY;
+            const int n = 1 << lg, zc = fused3_planes(lg);
+            void *tok = nullptr;
+            const bool prof = finest && (prof_on() & kProfDownZero);
+            if (prof) NP_TRY(prof_begin(s, &tok));
+            by_tile_width(lg, [&](auto tx) {
+                constexpr int TX = decltype(tx)::value;
+                const unsigned nb = unsigned((n / TX) * (n / TY) * (n / zc));
+                hipLaunchKernelGGL((k_down0_3<S, TX, TY>), dim3(nb), dim3(FTile<TX, TY>::NT), 0, s, f, x, fc, lg, bc,
+                                   zc, inv_h2, wdiag, stop);
+            });
+            NP_LAUNCH_CHECK();
+            if (prof) {
+                const double m = double(cells(D, lg));
+                NP_TRY(prof_end(s, tok, m * sizeof(S) * 2 + m / 8 * sizeof(S)));
+            }
+            return NP_OK;
+        } else {
+            (void)f; (void)x; (void)fc; (void)lg; (void)bc; (void)h; (void)omega; (void)s; (void)finest; (void)stop;
+            return NP_EINVAL;
+        }
+    }
+
+    // xout = two sweeps of x + P ec on a 3D level (k_up2_3; fuse3_on holds).
+    static np_status up2(const S *ec, const S *f, const S *x, S *xout, int lg, int bc, double h, double omega,
+                         hipStream_t s, bool finest, const int *stop) {
+        if constexpr (D == 3) {
+            const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+            constexpr int TY = FCfg<S>::TY;
+            const int n = 1 << lg, zc = fused3_planes(lg);
+            void *tok = nullptr;
+            const bool prof = finest && (prof_on() & kProfUp);
+            if (prof) NP_TRY(prof_begin(s, &tok));
+            by_tile_width(lg, [&](auto tx) {
+                constexpr int TX = decltype(tx)::value;
+                const unsigned nb = unsigned((n / TX) * (n / TY) * (n / zc));
+                hipLaunchKernelGGL((k_up2_3<S, TX, TY>), dim3(nb), dim3(FTile<TX, TY>::NT), 0, s, ec, f, x, xout, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
+            });
+            NP_LAUNCH_CHECK();
+            if (prof) {
+                const double m = double(cells(D, lg));
+                NP_TRY(prof_end(s, tok, m * sizeof(S) * 3 + m / 8 * sizeof(S)));
+            }
+            return NP_OK;
+        } else {
+            (void)ec; (void)f; (void)x; (void)xout; (void)lg; (void)bc; (void)h; (void)omega; (void)s; (void)finest;
+            (void)stop;
+            return NP_EINVAL;
+        }
+    }
+
     // Whether prolongation + correction and the first post-sweep of a level run as one kernel
     // (2D: every level above the tail; 3D: levels of n >= 32 on the z-marching tiles).
     static bool psweep_on(int lg, int nu2) {
@@ -694,6 +767,12 @@ template <int D, class S> struct Ops {
                 std::swap(cur[l], oth[l]);  // the smoothed iterate is in the partner buffer
                 continue;
             }
+            if (zero && o.nu1 == 2 && g_tune.zero2 && fuse3_on(lg)) {
+                // both pre-sweeps from zero, the residual and the restriction in one pass
+                NP_TRY(down0(F[l], cur[l], fc, lg, bc, hl, o.omega, s, l == 0, stop));
+                if (l + 1 == tl) { hl *= 2.0; break; }
+                continue;
+            }
             bool zf = zero;
             if (zf && o.nu1 == 0) {
                 hipLaunchKernelGGL((k_zero<S>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, cur[l],
@@ -755,7 +834,12 @@ template <int D, class S> struct Ops {
                 continue;
             }
             int it = 0;
-            if (psweep_on(lg, o.nu2)) {
+            if (o.nu2 == 2 && fuse3_on(lg) && psweep_on(lg, o.nu2)) {
+                // prolongation + correction and both post-sweeps in one pass
+                NP_TRY(up2(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
+                std::swap(cur[l], oth[l]);
+                it = 2;
+            } else if (psweep_on(lg, o.nu2)) {
                 NP_TRY(psweep(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
                 std::swap(cur[l], oth[l]);
                 it = 1;
@@ -1235,7 +1319,8 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuse3", &g_tune.fuse3, 0, 1},
+        {"fz3", &g_tune.fz3, 0, 1024},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
@@ -1244,7 +1329,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
-                (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
+                ((e.v == &g_zc3 || e.v == &g_tune.fz3) && value != 0 && (value < 2 || (value & (value - 1)))) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
                 return NP_EINVAL;
@@ -1280,6 +1365,8 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "zero2")) return g_tune.zero2;
     if (!std::strcmp(key, "psweep")) return g_tune.psweep;
     if (!std::strcmp(key, "ir_cpt")) return g_tune.ir_cpt;
+    if (!std::strcmp(key, "fuse3")) return g_tune.fuse3;
+    if (!std::strcmp(key, "fz3")) return g_tune.fz3;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "batched_rm")) return g_batched_rm;
@@ -1723,6 +1810,48 @@ extern "C" np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec pre
     }
     set_error("unknown precision");
     return NP_EINVAL;
+}
+
+// One step of a 3D level on caller buffers in storage precision S (the
+// kernels the cycle runs on that level), for the checks of the temporally
+// blocked kernels against the per-kernel path.
+template <class S>
+static np_status op_level(int kind, const void *f, void *x, void *xout, void *c, int lg, int bc, double h,
+                          hipStream_t s) {
+    typedef Ops<3, S> O;
+    const double w = 2.0 / 3.0;
+    switch (kind) {
+    case 0: return O::sweep((const S *)f, nullptr, (S *)x, lg, bc, h, w, 2, nullptr, nullptr, s, false, nullptr);
+    case 1: return O::restrict_((const S *)f, (const S *)x, (S *)c, lg, bc, h, s, nullptr);
+    case 2: return O::down0((const S *)f, (S *)x, (S *)c, lg, bc, h, w, s, false, nullptr);
+    case 3:
+        NP_TRY(O::psweep((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr));
+        return O::sweep((const S *)f, (const S *)xout, (S *)x, lg, bc, h, w, 0, nullptr, nullptr, s, false, nullptr);
+    case 4: return O::up2((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr);
+    }
+    return NP_EINVAL;
+}
+
+extern "C" np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x,
+                                 void *xout, void *c, void *stream) {
+    int lg;
+    NP_TRY(op_prelude(dims, h, bc, &lg));
+    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 4 || !f || !x || ((kind >= 3) && (!xout || xout == x)) ||
+        (kind != 0 && !c)) {
+        set_error("np_op_level: 3D grids of n >= 32, kind 0..4, distinct non-null buffers");
+        return NP_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    np_status st = NP_EINVAL;
+    switch (prec) {
+    case NP_FP64: st = op_level<double>(kind, f, x, xout, c, lg, bc, h, s); break;
+    case NP_FP32: st = op_level<float>(kind, f, x, xout, c, lg, bc, h, s); break;
+    case NP_BF16: st = op_level<bf16>(kind, f, x, xout, c, lg, bc, h, s); break;
+    default: set_error("unknown precision"); return NP_EINVAL;
+    }
+    NP_TRY(st);
+    NP_HIP_TRY(hipStreamSynchronize(s));
+    return NP_OK;
 }
 
 extern "C" np_status np_op_resid_norm(np_dims dims, double h, np_bc bc, const double *f, const double *x,

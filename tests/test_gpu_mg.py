@@ -550,3 +550,115 @@ def test_maximum_sizes(B, d, n):
         assert rr <= tol * (1 + 1e-6)
         assert err <= rr * nf / lam_min * (1 + 1e-6) + 1e-13 * nf / lam
         del x
+
+
+# ------------------------------------------ temporally blocked 3D level kernels
+def level_arrays(prec, n, seed):
+    """Seeded fine f, x and coarse c in the storage precision (BF16 as int16 bits)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    out = []
+    for shape in ((n,) * 3, (n,) * 3, (n // 2,) * 3):
+        a = torch.from_numpy(rng.standard_normal(shape)).cuda()
+        if prec == B_FP32:
+            a = a.float()
+        elif prec == B_BF16:
+            a = a.to(torch.bfloat16).view(torch.int16)
+        out.append(a.contiguous())
+    return out
+
+
+B_FP64, B_FP32, B_BF16 = 0, 1, 2
+
+
+def as64(t):
+    import torch
+    return (t.view(torch.bfloat16) if t.dtype == torch.int16 else t).double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", [B_FP64, B_FP32, B_BF16])
+@pytest.mark.parametrize("n", [32, 64, 128, 256])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_fused3_level_kernels_match_per_kernel_path(B, prec, n, bc):
+    """k_down0_3 (two sweeps from zero + residual + restriction in one pass) and k_up2_3
+    (prolongation + correction + two sweeps in one pass) against the per-kernel path on
+    the same buffers: the iterates bit for bit; the restricted residual bit for bit
+    where the per-kernel path restricts on the z-marching tiles (n >= 128) and to
+    rounding below (the small-level restriction sums the children in another order)."""
+    import torch
+    say("fused3", prec, n, bc)
+    h = 1.0 / n
+    f, x, c = level_arrays(prec, n, 40 + n + bc + 10 * prec)
+    xa, xb = torch.zeros_like(x), torch.zeros_like(x)
+    ca, cb = torch.zeros_like(c), torch.zeros_like(c)
+    B.np_op_level(B.LEVEL_ZERO2, f, xa, None, None, h, bc, prec)
+    B.np_op_level(B.LEVEL_RESTRICT, f, xa, None, ca, h, bc, prec)
+    B.np_op_level(B.LEVEL_DOWN0, f, xb, None, cb, h, bc, prec)
+    say("  down x diff %.3e, c diff %.3e" % (rel(as64(xb), as64(xa)), rel(as64(cb), as64(ca))))
+    assert torch.equal(xa, xb)
+    if n >= 128:
+        assert torch.equal(ca, cb)
+    else:
+        tol = {B_FP64: 1e-13, B_FP32: 1e-5, B_BF16: 1e-2}[prec]
+        assert rel(as64(cb), as64(ca)) < tol
+    ya, yo = x.clone(), torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_PSWEEP_SWEEP, f, ya, yo, c, h, bc, prec)
+    yb = torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_UP2, f, x, yb, c, h, bc, prec)
+    say("  up diff %.3e" % rel(as64(yb), as64(ya)))
+    assert torch.equal(ya, yb)
+
+
+@pytest.mark.parametrize("n", [32, 64, 128])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_fused3_level_kernels_match_oracle(B, orc, n, bc):
+    """FP64: the fused down-leg and up-leg against the oracle's steps (Jacobi, residual,
+    restriction, prolongation) within 1e-12."""
+    say("fused3 oracle", n, bc)
+    h = 1.0 / n
+    f, x, c = level_arrays(B_FP64, n, 70 + n + bc)
+    fh, xh, ch = host(f), host(x), host(c)
+    xz, cz = torch_zeros_like(x), torch_zeros_like(c)
+    B.np_op_level(B.LEVEL_DOWN0, f, xz, None, cz, h, bc, B_FP64)
+    x1 = orc.jacobi(fh, np.zeros_like(fh), h, bc)
+    x2 = orc.jacobi(fh, x1, h, bc)
+    fc = orc.restrict(orc.residual(fh, x2, h, bc))
+    assert rel(host(xz), x2) < 1e-12 and rel(host(cz), fc) < 1e-12
+    y = torch_zeros_like(x)
+    B.np_op_level(B.LEVEL_UP2, f, x, y, c, h, bc, B_FP64)
+    yr = orc.prolong_add(ch, xh.copy(), bc)
+    yr = orc.jacobi(fh, orc.jacobi(fh, yr, h, bc), h, bc)
+    assert rel(host(y), yr) < 1e-12
+
+
+def torch_zeros_like(t):
+    import torch
+    return torch.zeros_like(t)
+
+
+def test_fused3_knob_same_solves(B, orc):
+    """Whole solves with the temporally blocked kernels on and off: FP64 fixed cycles
+    agree to rounding (the small levels restrict in another order), and every path's
+    result meets the tolerance by the oracle's residual, with cycle counts logged."""
+    n = 128
+    g = inputs.sine_rhs(3, n, seed=3)
+    f, h = g["f"], g["h"]
+    fg = dev(f)
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("fuse3", v)
+            for p in (B.FP64, B.FP32, B.BF16):
+                xg = dev(np.zeros_like(f))
+                st, stats = B.mg_poisson_solve(fg, xg, h, DIR, smooth_prec=p)
+                out[(v, p)] = (host(xg), stats["cycles"])
+                assert orc.rel_res(f, out[(v, p)][0], h, DIR) <= 1e-10
+            xg = dev(np.zeros_like(f))
+            B.mg_poisson_solve(fg, xg, h, DIR, fixed_cycles=3)
+            out[(v, "fixed")] = host(xg)
+    finally:
+        B.np_set_tuning("fuse3", 0)
+    say("fuse3 on/off cycles", [(k, v[1]) for k, v in out.items() if k[1] != "fixed"])
+    assert rel(out[(1, "fixed")], out[(0, "fixed")]) < 1e-13
+    ref = orc.mg_solve(f, h, DIR, fixed_cycles=3)
+    assert rel(out[(1, "fixed")], ref.x) < 1e-12
