@@ -459,7 +459,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * workgroup of those kernels: 0 automatic, else an even power of two), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
  * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths),
  * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
- * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit and collocated steps, n >= 32,
+ * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit, collocated and staggered
+ * momentum steps, n >= 32,
  * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256),
  * "zc3" (planes per workgroup of the 3D z-marching solver kernels: 0 automatic, else a power of two
  * from 2 to 64), "conv3z" (z-marching tiles for the network's convolutions: 0 off, 1 automatic planes per workgroup, else

@@ -1323,13 +1323,14 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"fz3", &g_tune.fz3, 0, 1024},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
-        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
+        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"mom_rows", &g_mom_rows, 4, 8}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
         {"wgrad_mfma", &g_wgrad_mfma, 0, 1},
     };
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
                 ((e.v == &g_zc3 || e.v == &g_tune.fz3) && value != 0 && (value < 2 || (value & (value - 1)))) ||
+                (e.v == &g_mom_rows && value != 4 && value != 8) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
                 return NP_EINVAL;
@@ -1372,6 +1373,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "batched_rm")) return g_batched_rm;
     if (!std::strcmp(key, "batched_wg")) return g_batched_wg;
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
+    if (!std::strcmp(key, "mom_rows")) return g_mom_rows;
     if (!std::strcmp(key, "zc3")) return g_zc3;
     if (!std::strcmp(key, "conv3z")) return g_conv3z;
     if (!std::strcmp(key, "wgrad_mfma")) return g_wgrad_mfma;

@@ -428,6 +428,7 @@ __global__ __launch_bounds__(kAx2) void k_adx_stage2r(const double *__restrict__
 constexpr int kZx = 64;
 }  // namespace
 int g_zmarch_explicit = 1;  // tuning knob "zmarch_explicit"
+int g_mom_rows = 4;         // tuning knob "mom_rows": tile rows of the staggered corrector stage (4 or 8)
 namespace {
 // Tile rows per workgroup: 4 for the 27-point finite-element stages (their
 // register footprint leaves room for more, smaller workgroups per CU: measured
@@ -647,6 +648,64 @@ __global__ __launch_bounds__(kZx * 8) void k_nsc_correct3z(Vel qs, double *__res
     });
 }
 
+// MAC momentum stage (as k_mom_stage, the same terms in the same order) on
+// z-marching tiles of kZx x TY columns: the advecting velocity q^n (three
+// components), the advanced field (the predictor's q^n itself; the
+// corrector's half-step average (q~ + q^n) / 2, fields 3..5) and p sit in
+// LDS rings of three planes with their halo ring, so every face average of the
+// advecting velocity (idx, idx + e_c, idx - e_e, idx + e_c - e_e) and every
+// neighbour of the advanced field is an LDS read.  Periodic.
+template <int STAGE, int TY>
+__global__ __launch_bounds__(kZx * TY) void k_mom_stage3z(Vel qn, Vel qt, double *__restrict__ o0,
+                                                          double *__restrict__ o1, double *__restrict__ o2,
+                                                          const double *__restrict__ p, int n, int zc, double dt,
+                                                          double nu, double h) {
+    constexpr int NF = STAGE == 0 ? 4 : 7, FP = NF - 1;
+    typedef ZRing<NF, TY> Ring;
+    __shared__ typename Ring::Plane pl[NF];
+    Ring R(n, 1, zc);
+    auto ld = [&](int f, int64_t q) -> double {
+        if (f < 3) return qn.q[f][q];
+        if (STAGE == 1 && f < 6) return 0.5 * (qt.q[f - 3][q] + qn.q[f - 3][q]);
+        return p[q];
+    };
+    const int i = R.x0 + R.tx, j = R.y0 + R.ty;
+    const double inv_2h = 0.5 / h, nu_inv_h2 = nu / (h * h), inv_h = 1.0 / h;
+    double *out[3] = {o0, o1, o2};
+    R.march(ld, pl, [&](int z) {
+        if (i < n && j < n) {
+            const int sl[3] = {(z + 2) % 3, z % 3, (z + 1) % 3};  // planes z - 1, z, z + 1
+            auto at = [&](int f, int dx, int dy, int dz) -> double {
+                return pl[f][sl[dz + 1]][R.ty + 1 + dy][R.tx + 1 + dx];
+            };
+            const int64_t c = int64_t(z) * R.P + int64_t(j) * n + i;
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                const int fin = STAGE == 0 ? comp : 3 + comp;
+                const int cx = comp == 0, cy = comp == 1, cz = comp == 2;  // e_c
+                const double qc = at(fin, 0, 0, 0);
+                double adv = 0.0, lap = -2.0 * 3 * qc;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int ex = e == 0, ey = e == 1, ez = e == 2;
+                    const double qp = at(fin, ex, ey, ez), qm = at(fin, -ex, -ey, -ez);
+                    double ae;
+                    if (e == comp) {
+                        ae = at(e, 0, 0, 0);
+                    } else {
+                        ae = 0.25 * (at(e, 0, 0, 0) + at(e, cx, cy, cz) + at(e, -ex, -ey, -ez) +
+                                     at(e, cx - ex, cy - ey, cz - ez));
+                    }
+                    adv += ae * (qp - qm) * inv_2h;
+                    lap += qp + qm;
+                }
+                const double F = adv - nu_inv_h2 * lap + (at(FP, cx, cy, cz) - at(FP, 0, 0, 0)) * inv_h;
+                out[comp][c] = at(comp, 0, 0, 0) - dt * F;
+            }
+        }
+    });
+}
+
 inline int adx_planes(int n, int ty) {
     const int64_t tiles = int64_t((n + kZx - 1) / kZx) * ((n + ty - 1) / ty);
     int zc = 32;
@@ -790,12 +849,28 @@ static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w,
     double *rhs = W->buf + 2 * D * m, *dp = rhs + m;
     Vel qn{{u, v, w}}, vt{{qt[0], qt[1], qt[2]}}, vs{{qs[0], qs[1], qs[2]}};
     const unsigned nb = blocks_for(m);
-    hipLaunchKernelGGL((k_mom_stage<D, 0>), dim3(nb), dim3(kBlock), 0, s, qn, vt, qt[0], qt[1], qt[2], p, lg, dt,
-                       nu, h);
-    NP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_mom_stage<D, 1>), dim3(nb), dim3(kBlock), 0, s, qn, vt, qs[0], qs[1], qs[2], p, lg, dt,
-                       nu, h);
-    NP_LAUNCH_CHECK();
+    const int n = 1 << lg;
+    if (D == 3 && n >= 32 && g_zmarch_explicit) {
+        // z-marching tiles: 8 tile rows for the predictor's four fields, 4 for the corrector's seven (LDS)
+        const int z8 = adx_planes(n, 8), z4 = adx_planes(n, 4);
+        hipLaunchKernelGGL((k_mom_stage3z<0, 8>), dim3(zgrid(n, 8, z8)), dim3(kZx * 8), 0, s, qn, vt, qt[0], qt[1],
+                           qt[2], p, n, z8, dt, nu, h);
+        NP_LAUNCH_CHECK();
+        if (g_mom_rows == 8)
+            hipLaunchKernelGGL((k_mom_stage3z<1, 8>), dim3(zgrid(n, 8, z8)), dim3(kZx * 8), 0, s, qn, vt, qs[0],
+                               qs[1], qs[2], p, n, z8, dt, nu, h);
+        else
+            hipLaunchKernelGGL((k_mom_stage3z<1, 4>), dim3(zgrid(n, 4, z4)), dim3(kZx * 4), 0, s, qn, vt, qs[0],
+                               qs[1], qs[2], p, n, z4, dt, nu, h);
+        NP_LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL((k_mom_stage<D, 0>), dim3(nb), dim3(kBlock), 0, s, qn, vt, qt[0], qt[1], qt[2], p, lg, dt,
+                           nu, h);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_mom_stage<D, 1>), dim3(nb), dim3(kBlock), 0, s, qn, vt, qs[0], qs[1], qs[2], p, lg, dt,
+                           nu, h);
+        NP_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL((k_div_rhs<D>), dim3(nb), dim3(kBlock), 0, s, vs, rhs, lg, -1.0 / (dt * h));
     NP_LAUNCH_CHECK();
     np_mg_opts o;
