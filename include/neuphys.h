@@ -408,9 +408,10 @@ np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double
  * device arrays of the precision (FP64 double, FP32 float, BF16 as uint16
  * bit patterns): f, x, xout fine (n^3), c coarse ((n/2)^3).  kind 0: x = two
  * weighted-Jacobi sweeps of A x = f from zero (omega 2/3); 1: c = R (f - A x);
- * 2: both in one pass (x and c written); 3: x <- sweep(sweep(x + P c)), the
- * prolongation + first sweep kernel then a sweep, xout used as the partner
- * buffer; 4: xout = sweep(sweep(x + P c)) in one pass (x unchanged).
+ * 2: both in one pass, the block kernel of the small levels (x and c written);
+ * 3: x <- sweep(sweep(x + P c)), the prolongation + first sweep kernel then a
+ * sweep, xout used as the partner buffer; 4: xout = sweep(sweep(x + P c)) in
+ * one pass, the block kernel (x unchanged).
  * Synchronises the stream. */
 np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x, void *xout,
                       void *c, void *stream);
@@ -454,9 +455,9 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * and refinement kernels on 3D levels of n >= 128), "zero2" (0/1: the first
  * two sweeps from a zero iterate in one pass), "psweep" (0/1: prolongation + correction and the
  * first post-sweep in one pass: 2D levels above the tail, 3D levels of n >= 32), "ir_cpt" (1 or 2:
- * cells per thread of the 3D refinement kernel), "fuse3" (0/1: temporally blocked 3D level kernels, n >= 32 --
- * the down-leg from a zero iterate and the up-leg with two post-sweeps, one pass each), "fz3" (planes per
- * workgroup of those kernels: 0 automatic, else an even power of two), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
+ * cells per thread of the 3D refinement kernel), "fuseb" (0/1: temporally blocked block kernels, 8^3 cells per workgroup, on 3D
+ * levels from 32^3 to 2^"fbmax" cells per axis -- the down-leg from a zero iterate and the up-leg with two
+ * post-sweeps, one pass each; default 1, fbmax 6), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
  * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths),
  * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
  * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit, collocated and staggered

@@ -120,9 +120,8 @@ struct Tuning {
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
-    int fuse3 = 0;        // temporally blocked down-leg (from zero) and up-leg kernels on 3D levels of n >= 32
-                          // (bit-identical, measured slower than the per-kernel path: off)
-    int fz3 = 0;          // planes per workgroup of those kernels (0 = automatic)
+    int fuseb = 1;        // temporally blocked down-leg (from zero) and up-leg block kernels on small 3D levels
+    int fbmax = 6;        // largest such level (log2 cells per axis)
 };
 static Tuning g_tune;
 int g_zc3 = 0;
@@ -522,34 +521,20 @@ template <int D, class S> struct Ops {
         return NP_OK;
     }
 
-    // Whether a 3D level of 2^lg cells per axis runs the temporally blocked kernels (k_down0_3 for
-    // its down-leg from zero, k_up2_3 for its up-leg with two post-sweeps).
-    static bool fuse3_on(int lg) { return D == 3 && g_tune.fuse3 && g_tune.sweep3 && lg >= 5; }
+    // Whether a 3D level runs the block kernels (k_down0_b, k_up2_b): levels from 32^3 up to 2^fbmax.
+    static bool fuseb_on(int lg) { return D == 3 && g_tune.fuseb && lg >= 5 && lg <= g_tune.fbmax; }
 
-    // Planes per workgroup of the temporally blocked kernels (even; knob "fz3", 0 automatic).
-    static int fused3_planes(int lg) {
-        const int n = 1 << lg;
-        int zc = n >= 256 ? 8 : (n >= 128 ? 4 : 2);
-        if (g_tune.fz3 >= 2 && g_tune.fz3 <= n) zc = g_tune.fz3;
-        return zc;
-    }
-
-    // x = two sweeps from zero, fc = R (f - A x) on a 3D level (k_down0_3; fuse3_on holds).
-    static np_status down0(const S *f, S *x, S *fc, int lg, int bc, double h, double omega, hipStream_t s,
-                           bool finest, const int *stop) {
+    // The block forms of down0 and up2 (8^3 cells per workgroup).
+    static np_status down0b(const S *f, S *x, S *fc, int lg, int bc, double h, double omega, hipStream_t s,
+                            bool finest, const int *stop) {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
-            constexpr int TY = FCfg<S>::TY;
-            const int n = 1 << lg, zc = fused3_planes(lg);
+            const unsigned nb = unsigned(int64_t(1) << (3 * (lg - 3)));
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDownZero);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            by_tile_width(lg, [&](auto tx) {
-                constexpr int TX = decltype(tx)::value;
-                const unsigned nb = unsigned((n / TX) * (n / TY) * (n / zc));
-                hipLaunchKernelGGL((k_down0_3<S, TX, TY>), dim3(nb), dim3(FTile<TX, TY>::NT), 0, s, f, x, fc, lg, bc,
-                                   zc, inv_h2, wdiag, stop);
-            });
+            hipLaunchKernelGGL((k_down0_b<S, 8>), dim3(nb), dim3(BTile<8>::NT), 0, s, f, x, fc, lg, bc, inv_h2, wdiag,
+                               stop);
             NP_LAUNCH_CHECK();
             if (prof) {
                 const double m = double(cells(D, lg));
@@ -561,23 +546,16 @@ template <int D, class S> struct Ops {
             return NP_EINVAL;
         }
     }
-
-    // xout = two sweeps of x + P ec on a 3D level (k_up2_3; fuse3_on holds).
-    static np_status up2(const S *ec, const S *f, const S *x, S *xout, int lg, int bc, double h, double omega,
-                         hipStream_t s, bool finest, const int *stop) {
+    static np_status up2b(const S *ec, const S *f, const S *x, S *xout, int lg, int bc, double h, double omega,
+                          hipStream_t s, bool finest, const int *stop) {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
-            constexpr int TY = FCfg<S>::TY;
-            const int n = 1 << lg, zc = fused3_planes(lg);
+            const unsigned nb = unsigned(int64_t(1) << (3 * (lg - 3)));
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfUp);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            by_tile_width(lg, [&](auto tx) {
-                constexpr int TX = decltype(tx)::value;
-                const unsigned nb = unsigned((n / TX) * (n / TY) * (n / zc));
-                hipLaunchKernelGGL((k_up2_3<S, TX, TY>), dim3(nb), dim3(FTile<TX, TY>::NT), 0, s, ec, f, x, xout, lg,
-                                   bc, zc, inv_h2, wdiag, stop);
-            });
+            hipLaunchKernelGGL((k_up2_b<S, 8>), dim3(nb), dim3(BTile<8>::NT), 0, s, ec, f, x, xout, lg, bc, inv_h2,
+                               wdiag, stop);
             NP_LAUNCH_CHECK();
             if (prof) {
                 const double m = double(cells(D, lg));
@@ -767,9 +745,12 @@ template <int D, class S> struct Ops {
                 std::swap(cur[l], oth[l]);  // the smoothed iterate is in the partner buffer
                 continue;
             }
-            if (zero && o.nu1 == 2 && g_tune.zero2 && fuse3_on(lg)) {
-                // both pre-sweeps from zero, the residual and the restriction in one pass
-                NP_TRY(down0(F[l], cur[l], fc, lg, bc, hl, o.omega, s, l == 0, stop));
+            if (zero && o.nu1 == 2 && g_tune.zero2 && fuseb_on(lg)) {
+                // both pre-sweeps from zero, the residual and the restriction in one pass; on level 0
+                // into the partner buffer, so that the one-pass up-leg ends in the caller's x
+                S *dst = l == 0 ? oth[0] : cur[l];
+                NP_TRY(down0b(F[l], dst, fc, lg, bc, hl, o.omega, s, l == 0, stop));
+                if (l == 0) std::swap(cur[0], oth[0]);
                 if (l + 1 == tl) { hl *= 2.0; break; }
                 continue;
             }
@@ -834,9 +815,10 @@ template <int D, class S> struct Ops {
                 continue;
             }
             int it = 0;
-            if (o.nu2 == 2 && fuse3_on(lg) && psweep_on(lg, o.nu2)) {
-                // prolongation + correction and both post-sweeps in one pass
-                NP_TRY(up2(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
+            // prolongation + correction and both post-sweeps in one pass (on level 0 only when the
+            // result lands in the caller's x)
+            if (o.nu2 == 2 && fuseb_on(lg) && psweep_on(lg, o.nu2) && (l > 0 || cur[0] != x0)) {
+                NP_TRY(up2b(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
                 std::swap(cur[l], oth[l]);
                 it = 2;
             } else if (psweep_on(lg, o.nu2)) {
@@ -1319,8 +1301,8 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuse3", &g_tune.fuse3, 0, 1},
-        {"fz3", &g_tune.fz3, 0, 1024},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},
+        {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
         {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"mom_rows", &g_mom_rows, 4, 8}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
@@ -1329,7 +1311,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
     for (auto &e : tab)
         if (std::strcmp(e.k, key) == 0) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
-                ((e.v == &g_zc3 || e.v == &g_tune.fz3) && value != 0 && (value < 2 || (value & (value - 1)))) ||
+                (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
                 (e.v == &g_mom_rows && value != 4 && value != 8) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
@@ -1366,8 +1348,8 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "zero2")) return g_tune.zero2;
     if (!std::strcmp(key, "psweep")) return g_tune.psweep;
     if (!std::strcmp(key, "ir_cpt")) return g_tune.ir_cpt;
-    if (!std::strcmp(key, "fuse3")) return g_tune.fuse3;
-    if (!std::strcmp(key, "fz3")) return g_tune.fz3;
+    if (!std::strcmp(key, "fuseb")) return g_tune.fuseb;
+    if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
     if (!std::strcmp(key, "batched_rm")) return g_batched_rm;
@@ -1825,11 +1807,11 @@ static np_status op_level(int kind, const void *f, void *x, void *xout, void *c,
     switch (kind) {
     case 0: return O::sweep((const S *)f, nullptr, (S *)x, lg, bc, h, w, 2, nullptr, nullptr, s, false, nullptr);
     case 1: return O::restrict_((const S *)f, (const S *)x, (S *)c, lg, bc, h, s, nullptr);
-    case 2: return O::down0((const S *)f, (S *)x, (S *)c, lg, bc, h, w, s, false, nullptr);
+    case 2: return O::down0b((const S *)f, (S *)x, (S *)c, lg, bc, h, w, s, false, nullptr);
     case 3:
         NP_TRY(O::psweep((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr));
         return O::sweep((const S *)f, (const S *)xout, (S *)x, lg, bc, h, w, 0, nullptr, nullptr, s, false, nullptr);
-    case 4: return O::up2((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr);
+    case 4: return O::up2b((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr);
     }
     return NP_EINVAL;
 }
