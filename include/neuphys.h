@@ -411,7 +411,11 @@ np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double
  * 2: both in one pass, the block kernel of the small levels (x and c written);
  * 3: x <- sweep(sweep(x + P c)), the prolongation + first sweep kernel then a
  * sweep, xout used as the partner buffer; 4: xout = sweep(sweep(x + P c)) in
- * one pass, the block kernel (x unchanged).
+ * one pass, the block kernel (x unchanged); 5: the same on z-marching tiles,
+ * the one-pass up-leg of levels from 128^3 to 1024^3; 6: xout =
+ * sweep(sweep(x)) in one z-marching pass, the two pre-sweeps of those levels
+ * from a nonzero iterate (c unused, may be NULL).  Kinds 5 and 6 need
+ * 128 <= n <= 1024.
  * Synchronises the stream. */
 np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x, void *xout,
                       void *c, void *stream);
@@ -457,14 +461,16 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * first post-sweep in one pass: 2D levels above the tail, 3D levels of n >= 32), "ir_cpt" (1 or 2:
  * cells per thread of the 3D refinement kernel), "fuseb" (0/1: temporally blocked block kernels, 8^3 cells per workgroup, on 3D
  * levels from 32^3 to 2^"fbmax" cells per axis -- the down-leg from a zero iterate and the up-leg with two
- * post-sweeps, one pass each; default 1, fbmax 6), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
+ * post-sweeps, one pass each; default 1, fbmax 6), "sweep2z" (0/1: two sweeps in one z-marching pass on 3D
+ * levels from 128^3 to 1024^3 -- the pre-sweeps of a nonzero iterate, with the convergence check, and the
+ * up-leg with prolongation + correction; default 1), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
  * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths),
  * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
  * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit, collocated and staggered
  * momentum steps, n >= 32,
  * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256),
  * "zc3" (planes per workgroup of the 3D z-marching solver kernels: 0 automatic, else a power of two
- * from 2 to 64), "conv3z" (z-marching tiles for the network's convolutions: 0 off, 1 automatic planes per workgroup, else
+ * from 2 to 64; it also sets the one-pass two-sweep kernels' planes), "conv3z" (z-marching tiles for the network's convolutions: 0 off, 1 automatic planes per workgroup, else
  * a power of two from 2 to 64 planes), "wgrad_mfma" (0/1: the network's weight gradients on the matrix
  * cores).  Returns NP_EINVAL for an unknown key or value.  Changing a knob
  * drops cached graphs.  np_get_tuning returns the value, -1 if unknown. */

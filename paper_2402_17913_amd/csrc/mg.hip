@@ -12,6 +12,7 @@
 
 #include "mg_fused.h"
 #include "mg_fused3.h"
+#include "mg_zfused.h"
 #include "mg_level.h"
 #include "mg_kernels.h"
 #include "ad_kernels.h"
@@ -120,6 +121,7 @@ struct Tuning {
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
+    int sweep2z = 1;      // two sweeps in one z-marching pass on 3D levels of n >= 128 (both legs)
     int fuseb = 1;        // temporally blocked down-leg (from zero) and up-leg block kernels on small 3D levels
     int fbmax = 6;        // largest such level (log2 cells per axis)
 };
@@ -569,6 +571,45 @@ template <int D, class S> struct Ops {
         }
     }
 
+    // Whether a 3D level of n >= 128 runs its two pre-sweeps, or its up-leg (prolongation + correction
+    // and two post-sweeps), as one z-marching pass (k_sweep2z); 32-bit offsets bound it to n <= 1024.
+    static bool z2_on(int lg) { return D == 3 && g_tune.sweep2z && g_tune.sweep3 && lg >= 7 && lg <= 10; }
+
+    // xout = sweep(sweep(x')) on a 3D level of 128 <= n <= 1024 (k_sweep2z), x' = x + P ec when ec is
+    // given, else x; with `partial`, also the per-workgroup partials of |f - A x|^2 (their count in *np).
+    static np_status sweep2z(const S *ec, const S *f, const S *x, S *xout, double *partial, int *np, int lg,
+                             int bc, double h, double omega, hipStream_t s, bool finest, const int *stop) {
+        if constexpr (D == 3) {
+            const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+            constexpr int CPT = ZCfg<S>::CPT;
+            const int zc = sweep2z_planes<S>(lg);
+            const unsigned nb = zblocks(lg, CPT, zc);
+            void *tok = nullptr;
+            const bool prof = finest && (prof_on() & (ec ? kProfUp : kProfJacobi));
+            if (prof) NP_TRY(prof_begin(s, &tok));
+            if (ec)
+                hipLaunchKernelGGL((k_sweep2z<S, true, false>), dim3(nb), dim3(kS3Threads), 0, s, ec, f, x, xout,
+                                   nullptr, lg, bc, zc, inv_h2, wdiag, stop);
+            else if (partial)
+                hipLaunchKernelGGL((k_sweep2z<S, false, true>), dim3(nb), dim3(kS3Threads), 0, s, nullptr, f, x,
+                                   xout, partial, lg, bc, zc, inv_h2, wdiag, stop);
+            else
+                hipLaunchKernelGGL((k_sweep2z<S, false, false>), dim3(nb), dim3(kS3Threads), 0, s, nullptr, f, x,
+                                   xout, nullptr, lg, bc, zc, inv_h2, wdiag, stop);
+            NP_LAUNCH_CHECK();
+            if (prof) {
+                const double m = double(cells(D, lg));
+                NP_TRY(prof_end(s, tok, m * sizeof(S) * 3 + (ec ? m / 8 * sizeof(S) : 0.0)));
+            }
+            if (np) *np = int(nb);
+            return NP_OK;
+        } else {
+            (void)ec; (void)f; (void)x; (void)xout; (void)partial; (void)np; (void)lg; (void)bc; (void)h;
+            (void)omega; (void)s; (void)finest; (void)stop;
+            return NP_EINVAL;
+        }
+    }
+
     // Whether prolongation + correction and the first post-sweep of a level run as one kernel
     // (2D: every level above the tail; 3D: levels of n >= 32 on the z-marching tiles).
     static bool psweep_on(int lg, int nu2) {
@@ -767,20 +808,37 @@ template <int D, class S> struct Ops {
                 hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
                 NP_LAUNCH_CHECK();
             }
+            if (!zf && o.nu1 == 2 && z2_on(lg)) {
+                // both pre-sweeps in one pass (with the residual check of the input iterate on level 0)
+                const bool ck = check && l == 0 && !zero;
+                int nb = 0;
+                NP_TRY(sweep2z(nullptr, F[l], cur[l], oth[l], ck ? H->red : nullptr, &nb, lg, bc, hl, o.omega, s,
+                               l == 0, stop));
+                if (ck) {
+                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+                    NP_LAUNCH_CHECK();
+                }
+                std::swap(cur[l], oth[l]);
+                NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
+                if (l + 1 == tl) { hl *= 2.0; break; }
+                continue;
+            }
             for (int it = 0; it < o.nu1; ++it) {
                 const bool ck = check && l == 0 && !zero && it == 0;  // residual of the input iterate
                 // from a zero iterate: the first two sweeps in one pass where there are two
                 const int zm = zf && it == 0 ? (o.nu1 >= 2 && g_tune.zero2 ? 2 : 1) : 0;
                 int nb = 0;
                 // a sweep from a zero iterate reads no iterate: it writes in place, which saves the
-                // copy back into the caller's buffer at the end of the cycle
-                NP_TRY(sweep(F[l], zm ? nullptr : cur[l], zm ? cur[l] : oth[l], lg, bc, hl, o.omega, zm,
+                // copy back into the caller's buffer at the end of the cycle -- on level 0 into the
+                // partner buffer when the one-pass up-leg (which ends in the other buffer) follows
+                const bool zpart = zm && l == 0 && o.nu2 == 2 && z2_on(lg) && psweep_on(lg, o.nu2);
+                NP_TRY(sweep(F[l], zm ? nullptr : cur[l], zm && !zpart ? cur[l] : oth[l], lg, bc, hl, o.omega, zm,
                              ck ? H->red : nullptr, &nb, s, l == 0, stop));
                 if (ck) {
                     hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
                     NP_LAUNCH_CHECK();
                 }
-                if (!zm) std::swap(cur[l], oth[l]);
+                if (!zm || zpart) std::swap(cur[l], oth[l]);
                 if (zm == 2) ++it;
             }
             NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
@@ -819,6 +877,11 @@ template <int D, class S> struct Ops {
             // result lands in the caller's x)
             if (o.nu2 == 2 && fuseb_on(lg) && psweep_on(lg, o.nu2) && (l > 0 || cur[0] != x0)) {
                 NP_TRY(up2b(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
+                std::swap(cur[l], oth[l]);
+                it = 2;
+            } else if (o.nu2 == 2 && z2_on(lg) && psweep_on(lg, o.nu2) && (l > 0 || cur[0] != x0)) {
+                NP_TRY(sweep2z(res[l + 1], F[l], cur[l], oth[l], nullptr, nullptr, lg, bc, hl, o.omega, s, l == 0,
+                               stop));
                 std::swap(cur[l], oth[l]);
                 it = 2;
             } else if (psweep_on(lg, o.nu2)) {
@@ -1301,7 +1364,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},  {"sweep2z", &g_tune.sweep2z, 0, 1},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1349,6 +1412,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "psweep")) return g_tune.psweep;
     if (!std::strcmp(key, "ir_cpt")) return g_tune.ir_cpt;
     if (!std::strcmp(key, "fuseb")) return g_tune.fuseb;
+    if (!std::strcmp(key, "sweep2z")) return g_tune.sweep2z;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
@@ -1812,6 +1876,11 @@ static np_status op_level(int kind, const void *f, void *x, void *xout, void *c,
         NP_TRY(O::psweep((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr));
         return O::sweep((const S *)f, (const S *)xout, (S *)x, lg, bc, h, w, 0, nullptr, nullptr, s, false, nullptr);
     case 4: return O::up2b((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr);
+    case 5:
+    case 6:
+        if (lg < 7 || lg > 10) { set_error("kinds 5 and 6 need 128 <= n <= 1024"); return NP_EINVAL; }
+        return O::sweep2z(kind == 5 ? (const S *)c : nullptr, (const S *)f, (const S *)x, (S *)xout, nullptr,
+                          nullptr, lg, bc, h, w, s, false, nullptr);
     }
     return NP_EINVAL;
 }
@@ -1820,9 +1889,9 @@ extern "C" np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec,
                                  void *xout, void *c, void *stream) {
     int lg;
     NP_TRY(op_prelude(dims, h, bc, &lg));
-    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 4 || !f || !x || ((kind >= 3) && (!xout || xout == x)) ||
-        (kind != 0 && !c)) {
-        set_error("np_op_level: 3D grids of n >= 32, kind 0..4, distinct non-null buffers");
+    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 6 || !f || !x || ((kind >= 3) && (!xout || xout == x)) ||
+        (kind != 0 && kind != 6 && !c)) {
+        set_error("np_op_level: 3D grids of n >= 32, kind 0..6, distinct non-null buffers");
         return NP_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;

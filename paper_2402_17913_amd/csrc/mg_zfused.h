@@ -1,0 +1,391 @@
+// Two Jacobi sweeps in one pass over a large 3D level (n >= 128) on z-marching
+// tiles:
+//   xout = sweep(sweep(x'))  with  x' = x + P ec  (CORR: the up-leg's
+//   prolongation + correction and both post-sweeps) or x' = x (the down-leg's
+//   two pre-sweeps; NORM: also the per-workgroup partial of |f - A x|^2, the
+//   convergence check of the input iterate).
+// A workgroup of kS3Threads threads owns a TX x TY column tile (32 threads per
+// row, CPT cells each) and zc planes.  The first sweep is formed on the tile
+// and on the one-cell ring around it one plane ahead of the second sweep, which
+// reads that ring as in-plane neighbours.  Each thread holds its own cells'
+// x' at z - 1, z, z + 1 and first sweep at z - 2 .. z in registers; the first
+// waves also carry one cell each of the one-cell ring (x' at z - 1 .. z + 1 and
+// f, first sweep formed there), the last waves one cell each of the two-cell
+// ring (x' at z only, an in-plane neighbour of the first sweep): ring work
+// falls on whole waves (lanes past the ring's end repeat its last cell, which
+// writes the same value twice), so the roles branch on the wave, not on lanes.
+// In-plane neighbours come from LDS.  The loop takes planes in odd/even pairs,
+// so which coarse planes a correction mixes, and which LDS slot a plane uses,
+// are fixed at compile time; plane indices map through the boundary rule
+// without branches, values are loaded two steps before the end of the step that
+// consumes (and signs) them, in two register sets named by the plane's parity,
+// and Dirichlet ghosts of the second sweep are selected over unconditional LDS
+// reads.
+// Ring cells outside the grid take x' at that position from the raw iterate by
+// the boundary rule plus the correction from the coarse ghosts, as k_psweep3
+// forms its halo; the second sweep reads a Dirichlet ghost as minus the cell's
+// own first-sweep value, as the per-kernel sweep does.  A correction is
+// prolong_mix of two coarse planes' in-plane values at the cell; each coarse
+// plane's value is formed once per position and kept while fine planes use it.
+// Same arithmetic and term order as k_psweep3 (or k_sweep3) then k_sweep3: the
+// result equals that pair bit for bit.  Offsets are 32-bit (n <= 1024).
+#pragma once
+
+#include "mg_level.h"
+#include "mg_fused3.h"
+
+namespace np {
+
+template <class S> struct Z2Cfg {
+    static constexpr int CPT = ZCfg<S>::CPT, TP = 32, TX = TP * CPT, TY = kS3Threads / TP;
+    static constexpr int W1 = TX + 2, H1 = TY + 2, W2 = TX + 4, H2 = TY + 4;
+    static constexpr int NR1 = 2 * (TX + 2) + 2 * TY;        // ring-1 cells
+    static constexpr int NR2 = 2 * (TX + 4) + 2 * (TY + 2);  // ring-2 cells
+    static constexpr int NW = kS3Threads / 64;               // waves per workgroup
+    static constexpr int NW1 = (NR1 + 63) / 64, NW2 = (NR2 + 63) / 64;  // waves carrying ring 1 / ring 2
+    static constexpr int CW = TX / 2 + 4, CH = TY / 2 + 4, CR = CW * CH;  // coarse cells the region reads
+    static_assert(NW1 + NW2 <= NW, "ring-1 and ring-2 slots on distinct waves");
+    static_assert(CR <= kS3Threads, "one coarse cell per thread");
+    static_assert(TX * TY == kS3Threads * CPT, "tile of one cell group per thread");
+};
+
+// Tile position (a, b) of ring cell r of the ring at distance `ring` around a
+// TX x TY tile: the row above, the row below (both with their corners), then
+// the left and the right column.
+template <int TX, int TY>
+__device__ __forceinline__ void ring_pos(int r, int ring, int &a, int &b) {
+    const int w = TX + 2 * ring, h = TY + 2 * (ring - 1);
+    if (r < w) { a = r - ring; b = -ring; return; }
+    r -= w;
+    if (r < w) { a = r - ring; b = TY + ring - 1; return; }
+    r -= w;
+    if (r < h) { a = -ring; b = r - (ring - 1); return; }
+    r -= h;
+    a = TX + ring - 1;
+    b = r - (ring - 1);
+}
+
+// LDS offsets, within a coarse plane tile, of the four coarse cells that the
+// in-plane bilinear value at fine tile position (a, b) mixes (x0, y0 even).
+template <int CW>
+__device__ __forceinline__ void coarse_offsets(int a, int b, int (&o)[4]) {
+    const int lo = (a >> 1) + 2, ln = lo + ((a & 1) ? 1 : -1);
+    const int ro = ((b >> 1) + 2) * CW, rn = ro + ((b & 1) ? CW : -CW);
+    o[0] = ro + lo;
+    o[1] = ro + ln;
+    o[2] = rn + lo;
+    o[3] = rn + ln;
+}
+
+template <class C>
+__device__ __forceinline__ C coarse_mix(const C *E, const int (&o)[4]) {
+    return wpair(wpair(E[o[0]], E[o[1]]), wpair(E[o[2]], E[o[3]]));
+}
+
+// Plane q in [-n - 1, 2n - 2] of an n-plane axis by the boundary rule, without
+// branches: periodic wraps; Dirichlet mirrors (-1 - q below, 2n - 1 - q above)
+// and flips the sign.
+__device__ __forceinline__ int plane_map(int q, int n, int bc, bool &flip) {
+    const int kp = (q + n) & (n - 1);
+    const int kd = min(max(q, -1 - q), 2 * n - 1 - q);
+    flip = !bc && kd != q;
+    return bc ? kp : kd;
+}
+
+// Planes per workgroup of k_sweep2z on an n^3 level: each chunk re-reads a few
+// planes of x and f above and below it, so chunks are as long as still gives
+// four workgroups per CU (1024), and at least four planes (measured: at 128^3
+// BF16, 512 workgroups of four planes beat 1024 of two); the tuning knob
+// "zc3" overrides.
+template <class S> inline int sweep2z_planes(int lg) {
+    const int n = 1 << lg;
+    const int64_t tiles = (int64_t(n) / Z2Cfg<S>::TX) * (n / Z2Cfg<S>::TY);
+    int zc = 4;
+    while (zc < n && tiles * (n / (2 * zc)) >= 1024) zc *= 2;
+    if (g_zc3 >= 2 && g_zc3 <= n) zc = g_zc3;
+    return zc;
+}
+
+template <class S, bool CORR, bool NORM>
+__global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec, const S *__restrict__ f,
+                                                        const S *__restrict__ xin, S *__restrict__ xout,
+                                                        double *__restrict__ partial, int lg, int bc, int zc,
+                                                        typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                        const int *stop) {
+    typedef typename St<S>::C C;
+    typedef Z2Cfg<S> G;
+    constexpr int TX = G::TX, TY = G::TY, CPT = G::CPT, TP = G::TP, W1 = G::W1, W2 = G::W2, CW = G::CW;
+    constexpr int BS = G::H1 * W1;          // one first-sweep plane in LDS
+    __shared__ C Ax[G::H2 * W2];            // x' of plane z, tile and two-cell ring
+    __shared__ C Bs[2 * BS];                // first sweep of planes z - 1, z (slot = plane & 1), tile and ring
+    __shared__ C Ec[CORR ? 4 : 1][CORR ? G::CR + 1 : 1];  // coarse planes (slot = plane & 3), one spare cell
+    if (stop && *stop) return;
+    const int n = 1 << lg, nc = n >> 1, ntx = n / TX, nty = n / TY;
+    const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+    const int t = int(threadIdx.x), tp = t % TP, ty = t / TP, ai = CPT * tp;
+    const int x0 = (blk % ntx) * TX, y0 = ((blk / ntx) % nty) * TY, k0 = (blk / (ntx * nty)) * zc;
+    const int pl = 2 * lg;  // log2 of a plane's cells
+    const uint32_t osrc = (uint32_t(y0 + ty) << lg) + uint32_t(x0 + ai);  // own cells, in-plane
+    // ring role of this thread's wave: 1 (one-cell ring), 2 (two-cell ring) or none
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool r1 = wv < G::NW1, r2 = wv >= G::NW - G::NW2;
+    int ra = 0, rb = 0;
+    if (r1) ring_pos<TX, TY>(min(t, G::NR1 - 1), 1, ra, rb);
+    if (r2) ring_pos<TX, TY>(min(t - 64 * (G::NW - G::NW2), G::NR2 - 1), 2, ra, rb);
+    uint32_t rsrc;
+    C rsg;
+    {
+        int s = 1;
+        const int gi = bmap(x0 + ra, n, bc, s), gj = bmap(y0 + rb, n, bc, s);
+        rsrc = (uint32_t(gj) << lg) + uint32_t(gi);
+        rsg = C(s);
+    }
+    const int own_a = (ty + 2) * W2 + ai + 2;    // Ax offset of the first own cell
+    const int own_b = (ty + 1) * W1 + ai + 1;    // Bs offset of the first own cell
+    const int ring_a = (rb + 2) * W2 + ra + 2;   // Ax offset of the ring cell
+    const int ring_b = (rb + 1) * W1 + ra + 1;   // Bs offset (ring 1)
+    // Dirichlet walls next to the own cells (the second sweep's ghosts)
+    bool dw[CPT], de[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        dw[c] = !bc && x0 + ai + c == 0;
+        de[c] = !bc && x0 + ai + c == n - 1;
+    }
+    const bool ds = !bc && y0 + ty == 0, dn = !bc && y0 + ty == n - 1;
+    auto poff = [&](int q, C &sg) -> uint32_t {  // offset of plane q and the sign of its values
+        bool flip;
+        const int k = plane_map(q, n, bc, flip);
+        sg = flip ? C(-1) : C(1);
+        return uint32_t(k) << pl;
+    };
+    auto ld_own = [&](const S *base, C (&v)[CPT]) {
+        if constexpr (CPT == 2) Pair<S>::ld(base + osrc, v[0], v[1]);
+        else v[0] = St<S>::ld(base + osrc);
+    };
+
+    // coarse staging and the kept in-plane values: for a position corrected at fine plane q,
+    // m0 / m1 hold coarse planes kk, kk + 1 with kk = floor((q - 1) / 2)
+    int oco[CPT][4], rco[4];
+    C m0[CPT], m1[CPT], rm0 = C(0), rm1 = C(0);
+    uint32_t csrc = 0;
+    C csg = C(1), ev = C(0);
+    const int ce = min(t, G::CR);  // this thread's coarse cell (the spare cell past the region)
+    if constexpr (CORR) {
+        for (int c = 0; c < CPT; ++c) coarse_offsets<CW>(ai + c, ty, oco[c]);
+        coarse_offsets<CW>(ra, rb, rco);
+        int s = 1;
+        const int gi = bmap((x0 >> 1) + t % CW - 2, nc, bc, s), gj = bmap((y0 >> 1) + t / CW - 2, nc, bc, s);
+        csrc = t < G::CR ? (uint32_t(gj) << (lg - 1)) + uint32_t(gi) : 0u;
+        csg = C(s);
+    }
+    auto eload = [&](int K) {  // this thread's cell of coarse plane K, in flight
+        bool flip;
+        const int k = plane_map(K, nc, bc, flip);
+        ev = (flip ? -csg : csg) * St<S>::ld(ec + (uint32_t(k) << (pl - 2)) + csrc);
+    };
+    auto estore = [&](int K) { Ec[K & 3][ce] = ev; };
+    // x' from a signed raw value at fine plane q: own coarse plane first (ODD: q odd)
+    auto corr = [&](C v, C a0, C a1, auto odd) -> C {
+        if constexpr (decltype(odd)::value) return st_round<S>(v + prolong_mix(a0, a1));
+        else return st_round<S>(v + prolong_mix(a1, a0));
+    };
+    // a sweep at an LDS position of plane z (in-plane neighbours from Ax), z-neighbours given
+    auto sweep1 = [&](int q, C xc, C xm, C xp, C fv, C &r) -> C {
+        const C t0 = ((Ax[q - 1] + Ax[q + 1]) + Ax[q - W2]) + Ax[q + W2];
+        const C s = (t0 + xm) + xp;
+        r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+
+    // registers: own x' at z - 1, z, z + 1; first sweep at z - 2 .. z; f at z, z - 1; ring values
+    C xo[3][CPT], so[2][CPT], fo[2][CPT];
+    C rx0 = C(0), rx1 = C(0), rx2 = C(0), rf = C(0);  // ring 1: x' at z - 1 .. z + 1, f at z; ring 2: rx1
+    // loads in flight for the step of parity u: own x(z + 2) and f(z + 1), ring x (z + 2 on ring 1,
+    // z + 1 on ring 2) and f(z + 1) (ring 1)
+    C pw[2][CPT], pf[2][CPT], prr[2] = {C(0), C(0)}, prf[2] = {C(0), C(0)};
+    for (int c = 0; c < CPT; ++c) so[0][c] = so[1][c] = fo[1][c] = C(0);
+    auto psign = [&](int q) -> C {  // sign of plane q's values by the boundary rule
+        return (!bc && (q < 0 || q >= n)) ? C(-1) : C(1);
+    };
+    // the loads that the step at plane z consumes, into set u; past the last planes used (x up to
+    // k0 + zc + 1, f and ring-2 x up to k0 + zc) the last one is read again, an L2 hit
+    auto pload = [&](int z, auto u) {
+        constexpr int U = decltype(u)::value;
+        C sg;
+        const uint32_t o2 = poff(min(z + 2, k0 + zc + 1), sg), o1 = poff(min(z + 1, k0 + zc), sg);
+        ld_own(xin + o2, pw[U]);
+        ld_own(f + o1, pf[U]);
+        // every wave loads (a wave without a ring cell reads its tile's first cell, unused): a load
+        // under a branch would keep the set's old value alive and cost register copies
+        prr[U] = St<S>::ld(xin + (r1 ? o2 : o1) + rsrc);
+        prf[U] = St<S>::ld(f + o1 + rsrc);
+    };
+    // ---------------------------------------------------------------- prologue
+    const int K0 = k0 >> 1, Kmax = (k0 + zc + 2) >> 1;  // coarse planes the chunk's corrections use
+    if constexpr (CORR) {
+        for (int K = K0 - 2; K <= K0 + 1; ++K) {
+            eload(K);
+            estore(K);
+        }
+    }
+    pload(k0 - 1, std::integral_constant<int, 1>{});
+    for (int z = 0; z < 3; ++z) {
+        C sg;
+        const uint32_t o = poff(k0 - 2 + z, sg);
+        ld_own(xin + o, xo[z]);
+        for (int c = 0; c < CPT; ++c) xo[z][c] *= sg;
+        if (r1) {
+            const C v = sg * rsg * St<S>::ld(xin + o + rsrc);
+            if (z == 0) rx0 = v;
+            else if (z == 1) rx1 = v;
+            else rx2 = v;
+        }
+    }
+    {
+        C sg;
+        const uint32_t o = poff(k0 - 1, sg);
+        if (r2) rx1 = sg * rsg * St<S>::ld(xin + o + rsrc);
+        ld_own(f + o, fo[0]);
+        if (r1) rf = St<S>::ld(f + o + rsrc);
+    }
+    if constexpr (CORR) {
+        __syncthreads();
+        // own and ring 1: planes k0 - 2 (coarse K0 - 2, K0 - 1), k0 - 1 and k0 (K0 - 1, K0)
+        for (int c = 0; c < CPT; ++c) {
+            m0[c] = coarse_mix(Ec[(K0 - 2) & 3], oco[c]);
+            m1[c] = coarse_mix(Ec[(K0 - 1) & 3], oco[c]);
+            xo[0][c] = corr(xo[0][c], m0[c], m1[c], std::false_type{});
+            m0[c] = m1[c];
+            m1[c] = coarse_mix(Ec[K0 & 3], oco[c]);
+            xo[1][c] = corr(xo[1][c], m0[c], m1[c], std::true_type{});
+            xo[2][c] = corr(xo[2][c], m0[c], m1[c], std::false_type{});
+        }
+        if (r1) {
+            rm0 = coarse_mix(Ec[(K0 - 2) & 3], rco);
+            rm1 = coarse_mix(Ec[(K0 - 1) & 3], rco);
+            rx0 = corr(rx0, rm0, rm1, std::false_type{});
+            rm0 = rm1;
+            rm1 = coarse_mix(Ec[K0 & 3], rco);
+            rx1 = corr(rx1, rm0, rm1, std::true_type{});
+            rx2 = corr(rx2, rm0, rm1, std::false_type{});
+        }
+        if (r2) {  // plane k0 - 1 (coarse K0 - 1, K0)
+            rm0 = coarse_mix(Ec[(K0 - 1) & 3], rco);
+            rm1 = coarse_mix(Ec[K0 & 3], rco);
+            rx1 = corr(rx1, rm0, rm1, std::true_type{});
+        }
+    }
+    double acc = 0.0;
+    // ------------------------------------------------------------------- march
+    // one step: first sweep of plane z, second sweep of plane z - 1; ODD = z odd
+    auto step = [&](int z, auto odd) {
+        constexpr bool ODD = decltype(odd)::value;
+        constexpr int U = ODD ? 1 : 0;
+        typedef std::integral_constant<bool, !ODD> Even;
+        if constexpr (CORR && ODD) {
+            if (z > k0) estore((z + 3) >> 1);  // loaded two steps ago
+            eload(min((z + 5) >> 1, Kmax));
+        }
+        pload(z + 1, std::integral_constant<int, 1 - U>{});  // for the next step
+        // x' of plane z into LDS
+        for (int c = 0; c < CPT; ++c) Ax[own_a + c] = xo[1][c];
+        if (r1 || r2) Ax[ring_a] = rx1;
+        __syncthreads();
+        // first sweep of plane z: own cells and the ring-1 cell (values at Dirichlet ghosts are
+        // formed too, and never selected)
+        C *B = Bs + (ODD ? BS : 0);
+        C sn[CPT];
+        for (int c = 0; c < CPT; ++c) {
+            C r;
+            sn[c] = st_round<S>(sweep1(own_a + c, xo[1][c], xo[0][c], xo[2][c], fo[0][c], r));
+            if (NORM && z >= k0 && z < k0 + zc) acc += double(r) * double(r);
+            B[own_b + c] = sn[c];
+        }
+        if (r1) {
+            C r;
+            B[ring_b] = st_round<S>(sweep1(ring_a, rx1, rx0, rx2, rf, r));
+        }
+        __syncthreads();
+        // second sweep of plane z - 1, own cells
+        if (z > k0) {
+            const int p = z - 1;
+            const C *L = Bs + (ODD ? 0 : BS);
+            const bool dzl = !bc && p == 0, dzu = !bc && p == n - 1;
+            C out[CPT];
+            for (int c = 0; c < CPT; ++c) {
+                const int q = own_b + c;
+                const C xc = so[1][c];
+                const C lw = L[q - 1], le = L[q + 1], ls = L[q - W1], ln = L[q + W1];
+                // Dirichlet ghosts: minus the cell's own value
+                const C xw = dw[c] ? -xc : lw;
+                const C xe = de[c] ? -xc : le;
+                const C ys = ds ? -xc : ls;
+                const C yn = dn ? -xc : ln;
+                const C zl = dzl ? -xc : so[0][c];
+                const C zu = dzu ? -xc : sn[c];
+                const C t0 = ((xw + xe) + ys) + yn;
+                const C s = (t0 + zl) + zu;
+                const C r = fo[1][c] - (C(6) * xc - s) * inv_h2;
+                out[c] = xc + wdiag * r;
+            }
+            store_cells<S, CPT>(xout + (uint32_t(p) << pl) + osrc, out);
+        }
+        // slide: the first sweep, f, and x' (the loads signed and corrected now)
+        const C sg2 = psign(z + 2), sg1 = psign(z + 1);
+        for (int c = 0; c < CPT; ++c) {
+            so[0][c] = so[1][c];
+            so[1][c] = sn[c];
+            fo[1][c] = fo[0][c];
+            fo[0][c] = pf[U][c];
+            xo[0][c] = xo[1][c];
+            xo[1][c] = xo[2][c];
+        }
+        if constexpr (CORR) {
+            if constexpr (ODD)  // x'(z + 2), z + 2 odd: coarse plane (z + 3) / 2 joins
+                for (int c = 0; c < CPT; ++c) {
+                    m0[c] = m1[c];
+                    m1[c] = coarse_mix(Ec[((z + 3) >> 1) & 3], oco[c]);
+                }
+            for (int c = 0; c < CPT; ++c) xo[2][c] = corr(sg2 * pw[U][c], m0[c], m1[c], odd);
+        } else {
+            for (int c = 0; c < CPT; ++c) xo[2][c] = sg2 * pw[U][c];
+        }
+        if (r1) {
+            rx0 = rx1;
+            rx1 = rx2;
+            rf = prf[U];
+            const C v = (sg2 * rsg) * prr[U];
+            if constexpr (CORR) {
+                if constexpr (ODD) {
+                    rm0 = rm1;
+                    rm1 = coarse_mix(Ec[((z + 3) >> 1) & 3], rco);
+                }
+                rx2 = corr(v, rm0, rm1, odd);
+            } else {
+                rx2 = v;
+            }
+        }
+        if (r2) {  // x'(z + 1), z + 1 odd when z is even: coarse plane (z + 2) / 2 joins
+            const C v = (sg1 * rsg) * prr[U];
+            if constexpr (CORR) {
+                if constexpr (!ODD) {
+                    rm0 = rm1;
+                    rm1 = coarse_mix(Ec[((z + 2) >> 1) & 3], rco);
+                }
+                rx1 = corr(v, rm0, rm1, Even{});
+            } else {
+                rx1 = v;
+            }
+        }
+    };
+    // k0 even: pairs (odd, even); the last step loads nothing, the one before it no coarse plane
+    for (int z = k0 - 1; z < k0 + zc; z += 2) {  // k0 even: pairs (odd, even)
+        step(z, std::true_type{});
+        step(z + 1, std::false_type{});
+    }
+    if constexpr (NORM) {
+        acc = block_sum_n<kS3Threads>(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
+}  // namespace np

@@ -631,6 +631,90 @@ def test_fused3_level_kernels_match_oracle(B, orc, n, bc):
     assert rel(host(y), yr) < 1e-12
 
 
+@pytest.mark.parametrize("prec", [B_FP64, B_FP32, B_BF16])
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_up2z_matches_per_kernel_path(B, prec, n, bc):
+    """The one-pass z-marching up-leg of the large levels (k_sweep2z with correction:
+    prolongation + correction and both post-sweeps, the first sweep formed one plane
+    ahead on the tile and a one-cell ring) against prolongation-into-sweep then
+    sweep: the same terms in the same order, bit for bit."""
+    import torch
+    say("up2z", prec, n, bc)
+    h = 1.0 / n
+    f, x, c = level_arrays(prec, n, 90 + n + bc + 10 * prec)
+    ya, yo = x.clone(), torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_PSWEEP_SWEEP, f, ya, yo, c, h, bc, prec)
+    yz = torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_UP2Z, f, x, yz, c, h, bc, prec)
+    say("  up2z diff %.3e" % rel(as64(yz), as64(ya)))
+    assert torch.equal(ya, yz)
+
+
+@pytest.mark.parametrize("prec", [B_FP64, B_FP32, B_BF16])
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_sweep2z_matches_two_sweeps(B, prec, n, bc):
+    """Two Jacobi sweeps in one z-marching pass (k_sweep2z without correction, the
+    down-leg of a nonzero iterate) against two launches of the single-sweep kernel:
+    bit for bit."""
+    import torch
+    say("sweep2z", prec, n, bc)
+    h = 1.0 / n
+    f, x, _ = level_arrays(prec, n, 120 + n + bc + 10 * prec)
+    y1, y2 = torch.zeros_like(x), torch.zeros_like(x)
+    B.np_prof_level(B.PROF_LEVEL_SWEEP, f, x, y1, h, bc, prec, reps=1)
+    B.np_prof_level(B.PROF_LEVEL_SWEEP, f, y1, y2, h, bc, prec, reps=1)
+    yz = torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_SWEEP2Z, f, x, yz, None, h, bc, prec)
+    say("  sweep2z diff %.3e" % rel(as64(yz), as64(y2)))
+    assert torch.equal(y2, yz)
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_sweep2z_knob_same_solves(B, orc, bc):
+    """Whole 128^3 solves with the one-pass two-sweep kernels on and off: FP64 fixed
+    cycles bit for bit equal and within 1e-12 of the oracle's cycles; every path to
+    the tolerance in the same cycle count with equal iterates, judged by the oracle's
+    residual (the residual check sums its partials over other tiles, so the checked
+    norms agree to rounding)."""
+    n = 128
+    g = inputs.sine_rhs(3, n, seed=4)
+    f, h = g["f"], g["h"]
+    if bc == PER:
+        f = f - f.mean()
+    fg = dev(f)
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("sweep2z", v)
+            for p in (B.FP64, B.FP32, B.BF16):
+                xg = dev(np.zeros_like(f))
+                st, stats = B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p)
+                out[(v, p)] = (host(xg), stats["cycles"], stats["rel_res"])
+                assert orc.rel_res(f, out[(v, p)][0], h, bc) <= 1e-10
+            xg = dev(np.zeros_like(f))
+            B.mg_poisson_solve(fg, xg, h, bc, fixed_cycles=3)
+            out[(v, "fixed")] = host(xg)
+    finally:
+        B.np_set_tuning("sweep2z", 1)
+    say("sweep2z on/off cycles", [(k, v[1], v[2]) for k, v in out.items() if k[1] != "fixed"])
+    assert np.array_equal(out[(1, "fixed")], out[(0, "fixed")])
+    for p in (B.FP64, B.FP32, B.BF16):
+        assert out[(1, p)][1] == out[(0, p)][1] and np.array_equal(out[(1, p)][0], out[(0, p)][0])
+        assert abs(out[(1, p)][2] / out[(0, p)][2] - 1) < 1e-9
+    ref = orc.mg_solve(f, h, bc, fixed_cycles=3)
+    assert rel(out[(1, "fixed")], ref.x) < 1e-12
+
+
+def test_up2z_needs_large_level(B):
+    import torch
+    f, x, c = level_arrays(B_FP64, 64, 1)
+    for kind in (B.LEVEL_UP2Z, B.LEVEL_SWEEP2Z):
+        with pytest.raises(B.NeuphysError):
+            B.np_op_level(kind, f, x, torch.zeros_like(x), c, 1.0 / 64, DIR, B_FP64)
+
+
 def torch_zeros_like(t):
     import torch
     return torch.zeros_like(t)
