@@ -414,7 +414,9 @@ np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double
  * one pass, the block kernel (x unchanged); 5: the same on z-marching tiles,
  * the one-pass up-leg of levels from 128^3 to 1024^3; 6: xout =
  * sweep(sweep(x)) in one z-marching pass, the two pre-sweeps of those levels
- * from a nonzero iterate (c unused, may be NULL).  Kinds 5 and 6 need
+ * from a nonzero iterate (c unused, may be NULL); 7: x = two sweeps from
+ * zero and c = R (f - A x) in one z-marching pass, the zero-start down-leg of
+ * those levels (xout unused, may be NULL).  Kinds 5 to 7 need
  * 128 <= n <= 1024.
  * Synchronises the stream. */
 np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x, void *xout,

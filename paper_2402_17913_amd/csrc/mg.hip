@@ -610,6 +610,31 @@ template <int D, class S> struct Ops {
         }
     }
 
+    // x = sweep(sweep(0)) and fc = R (f - A x) in one z-marching pass on a 3D level of
+    // 128 <= n <= 1024 (k_down0z).
+    static np_status down0z(const S *f, S *x, S *fc, int lg, int bc, double h, double omega, hipStream_t s,
+                            bool finest, const int *stop) {
+        if constexpr (D == 3) {
+            const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+            constexpr int CPT = ZCfg<S>::CPT;
+            const int zc = sweep2z_planes<S>(lg);
+            void *tok = nullptr;
+            const bool prof = finest && (prof_on() & kProfDownZero);
+            if (prof) NP_TRY(prof_begin(s, &tok));
+            hipLaunchKernelGGL((k_down0z<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, f, x, fc, lg, bc,
+                               zc, inv_h2, wdiag, stop);
+            NP_LAUNCH_CHECK();
+            if (prof) {
+                const double m = double(cells(D, lg));
+                NP_TRY(prof_end(s, tok, m * sizeof(S) * 2 + m / 8 * sizeof(S)));
+            }
+            return NP_OK;
+        } else {
+            (void)f; (void)x; (void)fc; (void)lg; (void)bc; (void)h; (void)omega; (void)s; (void)finest; (void)stop;
+            return NP_EINVAL;
+        }
+    }
+
     // Whether prolongation + correction and the first post-sweep of a level run as one kernel
     // (2D: every level above the tail; 3D: levels of n >= 32 on the z-marching tiles).
     static bool psweep_on(int lg, int nu2) {
@@ -786,11 +811,12 @@ template <int D, class S> struct Ops {
                 std::swap(cur[l], oth[l]);  // the smoothed iterate is in the partner buffer
                 continue;
             }
-            if (zero && o.nu1 == 2 && g_tune.zero2 && fuseb_on(lg)) {
+            if (zero && o.nu1 == 2 && g_tune.zero2 && (fuseb_on(lg) || z2_on(lg))) {
                 // both pre-sweeps from zero, the residual and the restriction in one pass; on level 0
                 // into the partner buffer, so that the one-pass up-leg ends in the caller's x
                 S *dst = l == 0 ? oth[0] : cur[l];
-                NP_TRY(down0b(F[l], dst, fc, lg, bc, hl, o.omega, s, l == 0, stop));
+                if (fuseb_on(lg)) NP_TRY(down0b(F[l], dst, fc, lg, bc, hl, o.omega, s, l == 0, stop));
+                else NP_TRY(down0z(F[l], dst, fc, lg, bc, hl, o.omega, s, l == 0, stop));
                 if (l == 0) std::swap(cur[0], oth[0]);
                 if (l + 1 == tl) { hl *= 2.0; break; }
                 continue;
@@ -1878,7 +1904,9 @@ static np_status op_level(int kind, const void *f, void *x, void *xout, void *c,
     case 4: return O::up2b((const S *)c, (const S *)f, (const S *)x, (S *)xout, lg, bc, h, w, s, false, nullptr);
     case 5:
     case 6:
-        if (lg < 7 || lg > 10) { set_error("kinds 5 and 6 need 128 <= n <= 1024"); return NP_EINVAL; }
+    case 7:
+        if (lg < 7 || lg > 10) { set_error("kinds 5 to 7 need 128 <= n <= 1024"); return NP_EINVAL; }
+        if (kind == 7) return O::down0z((const S *)f, (S *)x, (S *)c, lg, bc, h, w, s, false, nullptr);
         return O::sweep2z(kind == 5 ? (const S *)c : nullptr, (const S *)f, (const S *)x, (S *)xout, nullptr,
                           nullptr, lg, bc, h, w, s, false, nullptr);
     }
@@ -1889,9 +1917,9 @@ extern "C" np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec,
                                  void *xout, void *c, void *stream) {
     int lg;
     NP_TRY(op_prelude(dims, h, bc, &lg));
-    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 6 || !f || !x || ((kind >= 3) && (!xout || xout == x)) ||
+    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 7 || !f || !x || ((kind >= 3 && kind != 7) && (!xout || xout == x)) ||
         (kind != 0 && kind != 6 && !c)) {
-        set_error("np_op_level: 3D grids of n >= 32, kind 0..6, distinct non-null buffers");
+        set_error("np_op_level: 3D grids of n >= 32, kind 0..7, distinct non-null buffers");
         return NP_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;

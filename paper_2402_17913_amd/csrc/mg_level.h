@@ -760,7 +760,7 @@ template <int D> struct Tail {
         for (int l = LG; l >= 2; --l) s += cells(l);
         return s;
     }
-    static constexpr int NT = D == 3 ? 512 : 1024;  // threads (3D FP64 needs the registers)
+    static constexpr int NT = 1024;  // threads
 };
 
 // nb_sum for a level held in LDS, without branches: every neighbour is read

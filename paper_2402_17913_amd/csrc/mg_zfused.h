@@ -388,4 +388,185 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec
     }
 }
 
+// The down-leg of a large 3D level (n >= 128) from a zero iterate in one pass on
+// the same tiles: x2 = sweep(sweep(0)) and fc = R (f - A x2).  The first sweep
+// from zero is x1 = w f (pointwise, unrounded, as the per-kernel sweep forms
+// it); the second sweep is formed on the tile and the one-cell ring, one plane
+// ahead of the residual, which needs that ring as in-plane neighbours; x2 is
+// stored (rounded) and its residual summed over the 2 x 2 x 2 children of each
+// coarse cell in k_restrict3's order -- the cell pair of a thread (CPT = 2),
+// then the plane pair, then the row pair (and, CPT = 1, the column pair) by
+// lane shuffles inside the wave (rows ty and ty + 1 are lanes 32 apart).  Same
+// arithmetic and term order as k_sweep3 from zero then k_restrict3: both
+// outputs equal that pair bit for bit.
+template <class S>
+__global__ __launch_bounds__(kS3Threads) void k_down0z(const S *__restrict__ f, S *__restrict__ xout,
+                                                       S *__restrict__ fc, int lg, int bc, int zc,
+                                                       typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                       const int *stop) {
+    typedef typename St<S>::C C;
+    typedef Z2Cfg<S> G;
+    constexpr int TX = G::TX, TY = G::TY, CPT = G::CPT, TP = G::TP, W1 = G::W1, W2 = G::W2;
+    constexpr int BS = G::H1 * W1;
+    static_assert(TP == 32, "rows ty, ty + 1 are the two halves of a wave");
+    __shared__ C Ax[G::H2 * W2];  // x1 = w f of plane z, tile and two-cell ring
+    __shared__ C Bs[2 * BS];      // x2 of planes z - 1, z (slot = plane & 1), tile and ring
+    if (stop && *stop) return;
+    const int n = 1 << lg, ntx = n / TX, nty = n / TY, lgc = lg - 1;
+    const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+    const int t = int(threadIdx.x), tp = t % TP, ty = t / TP, ai = CPT * tp;
+    const int x0 = (blk % ntx) * TX, y0 = ((blk / ntx) % nty) * TY, k0 = (blk / (ntx * nty)) * zc;
+    const int pl = 2 * lg;
+    const uint32_t osrc = (uint32_t(y0 + ty) << lg) + uint32_t(x0 + ai);
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool r1 = wv < G::NW1, r2 = wv >= G::NW - G::NW2;
+    int ra = 0, rb = 0;
+    if (r1) ring_pos<TX, TY>(min(t, G::NR1 - 1), 1, ra, rb);
+    if (r2) ring_pos<TX, TY>(min(t - 64 * (G::NW - G::NW2), G::NR2 - 1), 2, ra, rb);
+    uint32_t rsrc;
+    C rsg;
+    {
+        int s = 1;
+        const int gi = bmap(x0 + ra, n, bc, s), gj = bmap(y0 + rb, n, bc, s);
+        rsrc = (uint32_t(gj) << lg) + uint32_t(gi);
+        rsg = C(s);
+    }
+    const int own_a = (ty + 2) * W2 + ai + 2, own_b = (ty + 1) * W1 + ai + 1;
+    const int ring_a = (rb + 2) * W2 + ra + 2, ring_b = (rb + 1) * W1 + ra + 1;
+    bool dw[CPT], de[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        dw[c] = !bc && x0 + ai + c == 0;
+        de[c] = !bc && x0 + ai + c == n - 1;
+    }
+    const bool ds = !bc && y0 + ty == 0, dn = !bc && y0 + ty == n - 1;
+    auto poff = [&](int q) -> uint32_t {
+        bool flip;
+        return uint32_t(plane_map(q, n, bc, flip)) << pl;
+    };
+    auto psign = [&](int q) -> C { return (!bc && (q < 0 || q >= n)) ? C(-1) : C(1); };
+    auto ld_own = [&](const S *base, C (&v)[CPT]) {
+        if constexpr (CPT == 2) Pair<S>::ld(base + osrc, v[0], v[1]);
+        else v[0] = St<S>::ld(base + osrc);
+    };
+    auto sweep1 = [&](int q, C xc, C xm, C xp, C fv) -> C {
+        const C t0 = ((Ax[q - 1] + Ax[q + 1]) + Ax[q - W2]) + Ax[q + W2];
+        const C s = (t0 + xm) + xp;
+        const C r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+    // registers: own f at z - 1 .. z + 1 and x1 = (signed) w f there; x2 at z - 2, z - 1;
+    // ring 1: the same at its cell; ring 2: x1 at z
+    C fo[3][CPT], xo[3][CPT], so[2][CPT];
+    C rf[3] = {C(0), C(0), C(0)}, rx[3] = {C(0), C(0), C(0)};
+    C pf[2][CPT], pr[2] = {C(0), C(0)};  // loads in flight (set = parity of the consuming step)
+    for (int c = 0; c < CPT; ++c) so[0][c] = so[1][c] = C(0);
+    // the step at plane z consumes own / ring-1 f(z + 2) and ring-2 f(z + 1); past the planes
+    // used (up to k0 + zc + 1 and k0 + zc) the last one is read again, an L2 hit
+    auto pload = [&](int z, auto u) {
+        constexpr int U = decltype(u)::value;
+        const uint32_t o2 = poff(min(z + 2, k0 + zc + 1)), o1 = poff(min(z + 1, k0 + zc));
+        ld_own(f + o2, pf[U]);
+        pr[U] = St<S>::ld(f + (r1 ? o2 : o1) + rsrc);
+    };
+    // prologue: f at k0 - 2 .. k0 (own, ring 1), k0 - 1 (ring 2)
+    for (int z = 0; z < 3; ++z) {
+        const int q = k0 - 2 + z;
+        ld_own(f + poff(q), fo[z]);
+        const C sg = psign(q);
+        for (int c = 0; c < CPT; ++c) xo[z][c] = sg * (wdiag * fo[z][c]);
+        if (r1) {
+            rf[z] = St<S>::ld(f + poff(q) + rsrc);
+            rx[z] = (sg * rsg) * (wdiag * rf[z]);
+        }
+    }
+    if (r2) {
+        const C v = St<S>::ld(f + poff(k0 - 1) + rsrc);
+        rx[1] = (psign(k0 - 1) * rsg) * (wdiag * v);
+    }
+    pload(k0 - 1, std::integral_constant<int, 1>{});
+    C pair = C(0);  // residual sum of the plane pair
+    auto step = [&](int z, auto odd) {
+        constexpr bool ODD = decltype(odd)::value;
+        constexpr int U = ODD ? 1 : 0;
+        pload(z + 1, std::integral_constant<int, 1 - U>{});
+        // x1 of plane z into LDS (own cells at z are fo[1] / xo[1])
+        for (int c = 0; c < CPT; ++c) Ax[own_a + c] = xo[1][c];
+        if (r1 || r2) Ax[ring_a] = rx[1];
+        __syncthreads();
+        // second sweep at plane z: own cells and the ring-1 cell; own values stored
+        C *B = Bs + (ODD ? BS : 0);
+        C sn[CPT];
+        for (int c = 0; c < CPT; ++c) {
+            sn[c] = st_round<S>(sweep1(own_a + c, xo[1][c], xo[0][c], xo[2][c], fo[1][c]));
+            B[own_b + c] = sn[c];
+        }
+        if (z >= k0 && z < k0 + zc) store_cells<S, CPT>(xout + (uint32_t(z) << pl) + osrc, sn);
+        if (r1) B[ring_b] = st_round<S>(sweep1(ring_a, rx[1], rx[0], rx[2], rf[1]));
+        __syncthreads();
+        // residual of x2 at plane p = z - 1, own cells, summed into the coarse cells
+        if (z > k0) {
+            const int p = z - 1;
+            const C *L = Bs + (ODD ? 0 : BS);
+            const bool dzl = !bc && p == 0, dzu = !bc && p == n - 1;
+            C r = C(0);
+            for (int c = 0; c < CPT; ++c) {
+                const int q = own_b + c;
+                const C xc = so[1][c];
+                const C lw = L[q - 1], le = L[q + 1], ls = L[q - W1], ln = L[q + W1];
+                const C xw = dw[c] ? -xc : lw;
+                const C xe = de[c] ? -xc : le;
+                const C ys = ds ? -xc : ls;
+                const C yn = dn ? -xc : ln;
+                const C zl = dzl ? -xc : so[0][c];
+                const C zu = dzu ? -xc : sn[c];
+                const C t0 = ((xw + xe) + ys) + yn;
+                const C s = (t0 + zl) + zu;
+                const C rc = fo[0][c] - (C(6) * xc - s) * inv_h2;
+                if (c == 0) r = rc;
+                else r += rc;
+            }
+            if (ODD) {  // p even: the first plane of the pair
+                pair = r;
+            } else {
+                pair += r;
+                const uint32_t cc = (uint32_t(p >> 1) << (2 * lgc)) + (uint32_t((y0 + ty) >> 1) << lgc) +
+                                    uint32_t((x0 + ai) >> 1);
+                if constexpr (CPT == 2) {
+                    const C o = __shfl_down(pair, 32);
+                    if ((ty & 1) == 0) St<S>::st(fc + cc, (pair + o) * C(0.125));
+                } else {
+                    const C b = __shfl_down(pair, 1), cy = __shfl_down(pair, 32),
+                            d = __shfl_down(pair, 33);
+                    if (((tp | ty) & 1) == 0) St<S>::st(fc + cc, (((pair + b) + cy) + d) * C(0.125));
+                }
+            }
+        }
+        // slide
+        const C sg2 = psign(z + 2), sg1 = psign(z + 1);
+        for (int c = 0; c < CPT; ++c) {
+            so[0][c] = so[1][c];
+            so[1][c] = sn[c];
+            fo[0][c] = fo[1][c];
+            fo[1][c] = fo[2][c];
+            fo[2][c] = pf[U][c];
+            xo[0][c] = xo[1][c];
+            xo[1][c] = xo[2][c];
+            xo[2][c] = sg2 * (wdiag * pf[U][c]);
+        }
+        if (r1) {
+            rf[0] = rf[1];
+            rf[1] = rf[2];
+            rf[2] = pr[U];
+            rx[0] = rx[1];
+            rx[1] = rx[2];
+            rx[2] = (sg2 * rsg) * (wdiag * pr[U]);
+        }
+        if (r2) rx[1] = (sg1 * rsg) * (wdiag * pr[U]);
+    };
+    for (int z = k0 - 1; z < k0 + zc; z += 2) {  // k0 even: pairs (odd, even)
+        step(z, std::true_type{});
+        step(z + 1, std::false_type{});
+    }
+}
+
 }  // namespace np

@@ -707,10 +707,48 @@ def test_sweep2z_knob_same_solves(B, orc, bc):
     assert rel(out[(1, "fixed")], ref.x) < 1e-12
 
 
+@pytest.mark.parametrize("prec", [B_FP64, B_FP32, B_BF16])
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_down0z_matches_per_kernel_path(B, prec, n, bc):
+    """The one-pass down-leg of the large levels from a zero iterate (k_down0z: both
+    pre-sweeps, the residual and the restriction) against the two-sweeps-from-zero
+    kernel then k_restrict3: iterate and coarse right-hand side bit for bit (the
+    children are summed in k_restrict3's order)."""
+    import torch
+    say("down0z", prec, n, bc)
+    h = 1.0 / n
+    f, x, c = level_arrays(prec, n, 150 + n + bc + 10 * prec)
+    xa, xb = torch.zeros_like(x), torch.zeros_like(x)
+    ca, cb = torch.zeros_like(c), torch.zeros_like(c)
+    B.np_op_level(B.LEVEL_ZERO2, f, xa, None, None, h, bc, prec)
+    B.np_op_level(B.LEVEL_RESTRICT, f, xa, None, ca, h, bc, prec)
+    B.np_op_level(B.LEVEL_DOWN0Z, f, xb, None, cb, h, bc, prec)
+    say("  down0z x diff %.3e, c diff %.3e" % (rel(as64(xb), as64(xa)), rel(as64(cb), as64(ca))))
+    assert torch.equal(xa, xb)
+    assert torch.equal(ca, cb)
+
+
+def test_down0z_matches_oracle(B, orc):
+    """FP64 at 128^3 (Dirichlet) and periodic: the one-pass down-leg against the
+    oracle's Jacobi, residual and restriction within 1e-12."""
+    for bc in (DIR, PER):
+        n = 128
+        h = 1.0 / n
+        f, x, c = level_arrays(B_FP64, n, 170 + bc)
+        fh = host(f)
+        xz, cz = torch_zeros_like(x), torch_zeros_like(c)
+        B.np_op_level(B.LEVEL_DOWN0Z, f, xz, None, cz, h, bc, B_FP64)
+        x1 = orc.jacobi(fh, np.zeros_like(fh), h, bc)
+        x2 = orc.jacobi(fh, x1, h, bc)
+        fc = orc.restrict(orc.residual(fh, x2, h, bc))
+        assert rel(host(xz), x2) < 1e-12 and rel(host(cz), fc) < 1e-12
+
+
 def test_up2z_needs_large_level(B):
     import torch
     f, x, c = level_arrays(B_FP64, 64, 1)
-    for kind in (B.LEVEL_UP2Z, B.LEVEL_SWEEP2Z):
+    for kind in (B.LEVEL_UP2Z, B.LEVEL_SWEEP2Z, B.LEVEL_DOWN0Z):
         with pytest.raises(B.NeuphysError):
             B.np_op_level(kind, f, x, torch.zeros_like(x), c, 1.0 / 64, DIR, B_FP64)
 
