@@ -588,11 +588,8 @@ def main():
     for name, v in level_live.items():
         log("  live %s: " % name + ", ".join("%s %.1f us %.0f GB/s" % (k, w["avg_us"], w["gbs"])
                                              for k, w in v.items()))
-    sweep_live = {k: v["sweep"] for k, v in level_live.items()}
-    if dom == "sweep":
-        avg_us, nbytes = sweep_live[head]["avg_us"], sweep_live[head]["bytes_per_launch"]
-    else:
-        avg_us, nbytes = kt[dom]["avg_us"], kt[dom]["bytes_per_launch"]
+    # the dominant kernel's own launches in the timed solves, each bracketed by HIP events
+    avg_us, nbytes = kt[dom]["avg_us"], kt[dom]["bytes_per_launch"]
     achieved = nbytes / (avg_us * 1e-6) / 1e9
     line = {
         "metric": "DOFs/s to 1e-10 rel. residual (MG V-cycle), learned/mixed vs plain FP64",
@@ -628,14 +625,17 @@ def main():
             "mixed_over_plain": res[head]["dofs_per_s"] / res["fp64"]["dofs_per_s"],
         },
         "roofline": {
-            "kernel": {"sweep": "k_sweep3: weighted-Jacobi sweep, finest level (z-marching)",
+            "kernel": {"sweep": "k_sweep2z: two weighted-Jacobi sweeps of a nonzero iterate in one pass, "
+                                "finest level (z-marching)",
                        "sweep_zero": "k_sweep3: first two sweeps from a zero iterate, finest level",
                        "restrict": "k_restrict3: residual + restriction, finest level",
                        "prolong": "k_prolong3: prolongation + correction, finest level",
                        "refine": "k_ir_resid3: FP64 update + residual of the refinement",
                        "fused_down": "k_fused: 2 sweeps + residual + restriction, finest level",
-                       "fused_down_zero": "k_fused: zero-guess sweeps + residual + restriction",
-                       "fused_up": "k_fused: prolongation + 2 sweeps, finest level"}[dom] +
+                       "fused_down_zero": "k_down0z: two sweeps from zero + residual + restriction in one "
+                                          "pass, finest level (z-marching)",
+                       "fused_up": "k_sweep2z: prolongation + correction and two sweeps in one pass, "
+                                   "finest level (z-marching)"}[dom] +
                       (" (%s correction and residual, %s per thread)" % (
                           head.upper(), "two cells" if B.np_get_tuning("ir_cpt") == 2 else "one cell")
                        if dom == "refine" else
@@ -648,9 +648,7 @@ def main():
             "traffic": measured_traffic(dom, head),
             "avg_us": avg_us,
             "bytes_per_launch": nbytes,
-            "timing": ("HIP events around %d back-to-back launches on the library stream, median of 5 rounds"
-                       % SWEEP_REPS
-                       if dom == "sweep" else "HIP events around each launch"),
+            "timing": "HIP events around each launch of the kernel in the timed solves, on the library stream",
             "copy_measured_gbs": copy_gbs,
             "finest_level_live": level_live,
             "level0_kernels_event_bracketed": {p: res[p]["prof"] for p in res},
