@@ -81,40 +81,42 @@ def copy_bandwidth(reps=5):
     return 2 * a.numel() * 8 / dt / 1e9
 
 
-SWEEP3_PROFILE = os.path.join(ROOT, "profiles", "k_sweep3_fp32_poisson3d_256.md")
+SOLVER_PROFILE = os.path.join(ROOT, "profiles", "mg_level_kernels_poisson3d_256.md")
+
+# source region of each finest-level kernel whose counter traffic the profile records:
+# (file under csrc/, first line, line after the region)
+KERNEL_SOURCES = {
+    "refine": ("mg_level.h", "// Refinement step of the mixed path on the z-marching tiles",
+               "// x += P ec on the z-marching tiles"),
+    "sweep": ("mg_zfused.h", "template <class S> struct Z2Cfg {", "// The down-leg of a large 3D level"),
+    "fused_up": ("mg_zfused.h", "template <class S> struct Z2Cfg {", "// The down-leg of a large 3D level"),
+    "fused_down_zero": ("mg_zfused.h", "// The down-leg of a large 3D level", "}  // namespace np"),
+    "restrict": ("mg_level.h", "// Residual + restriction on the z-marching tiles",
+                 "// Refinement step of the mixed path on the z-marching tiles"),
+}
 
 
-def sweep3_source_hash():
-    """Hash of the z-marching sweep's source (ZMarch and k_sweep3), which the
-    counter summary records: counters taken on other code are not reported."""
+def kernel_source_hash(kind):
+    """Hash of a finest-level kernel's source, which the counter summary records with
+    its traffic: counters taken on other code are not reported."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", "mg_level.h")).read()
-    body = src[src.index("struct ZMarch {"):src.index("// Residual + restriction on the z-marching tiles")]
-    return hashlib.sha256(body.encode()).hexdigest()[:16]
-
-
-def refine_source_hash():
-    """Hash of the refinement kernel's source (k_ir_resid3), recorded with its counters."""
-    import hashlib
-    src = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", "mg_level.h")).read()
-    body = src[src.index("// Refinement step of the mixed path on the z-marching tiles"):
-               src.index("// x += P ec on the z-marching tiles")]
+    fname, first, after = KERNEL_SOURCES[kind]
+    src = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", fname)).read()
+    body = src[src.index(first):src.index(after, src.index(first))]
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, head):
-    """HBM bytes per launch of the dominant kernel (the sweep or the refinement step)
-    from the committed rocprofv3 counter summary, if the kernel's source is unchanged
-    since the counters were taken."""
+    """HBM bytes per launch of the dominant kernel at the finest level from the
+    committed rocprofv3 counter summary, if the kernel's source is unchanged since
+    the counters were taken."""
     import re
-    path = SWEEP3_PROFILE.replace("fp32", head)
-    if kernel not in ("sweep", "refine") or not os.path.exists(path):
+    if kernel not in KERNEL_SOURCES or not os.path.exists(SOLVER_PROFILE):
         return None
-    txt = open(path).read()
-    tag, src_hash = ("", sweep3_source_hash) if kernel == "sweep" else ("refine_", refine_source_hash)
-    m1 = re.search(r"^%straffic_bytes_per_launch: (\d+)" % tag, txt, re.M)
-    m2 = re.search(r"^%skernel_source_sha256_16: (\w+)" % tag, txt, re.M)
-    if not (m1 and m2) or src_hash() != m2.group(1):
+    txt = open(SOLVER_PROFILE).read()
+    m1 = re.search(r"^traffic_%s_%s_bytes_per_launch: (\d+)" % (kernel, head), txt, re.M)
+    m2 = re.search(r"^traffic_%s_source_sha256_16: (\w+)" % kernel, txt, re.M)
+    if not (m1 and m2) or kernel_source_hash(kernel) != m2.group(1):
         return None
     return int(m1.group(1))
 
@@ -325,6 +327,29 @@ def leg_c5(B, inputs, nsteps=10):
                              training_s=meta["training_s"], pair_generation_s=meta["pair_generation_s"],
                              forward_ms=1e3 * dt / 10, train_step_ms_batch4=1e3 * dts / 5),
                 **out)
+
+
+def leg_c5_zero(B, inputs, nsteps=3):
+    """The 3D projection step of C5 (256^3 periodic, seed 0) from a zero pressure
+    increment only, FP64 and BF16-inner solves, no network: a short run for kernel
+    profiles of the momentum stages, the divergence, the correction and the solves."""
+    import torch
+    n = 256
+    g = inputs.divfree_velocity(3, n, seed=0)
+    out = {}
+    for prec_name, prec in (("fp64", B.FP64), ("bf16", B.BF16)):
+        q = [torch.from_numpy(c).cuda() for c in g["q"]]
+        p = torch.zeros_like(q[0])
+        B.ns_projection_step(q[0].clone(), q[1].clone(), q[2].clone(), p.clone(), g["h"], g["dt"], 1e-3, tol=TOL,
+                             smooth_prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            B.ns_projection_step(q[0], q[1], q[2], p, g["h"], g["dt"], 1e-3, tol=TOL, smooth_prec=prec)
+        torch.cuda.synchronize()
+        out[prec_name] = dict(ms_per_step=1e3 * (time.perf_counter() - t0) / nsteps)
+        log("  C5 zero-guess %s: %.2f ms/step" % (prec_name, out[prec_name]["ms_per_step"]))
+    return dict(workload="ns3d_256cube_periodic_divfree_seed0_nu1e-3_%dsteps_zero_guess" % nsteps, **out)
 
 
 def leg_sawtooth(B, inputs, steps, warmup):
@@ -679,6 +704,8 @@ def main():
             others["sawtooth"] = leg_sawtooth(B, inputs, args.steps, args.warmup)
         elif leg == "ad":
             others["ad"] = leg_ad(B, inputs, args.steps, args.warmup)
+        elif leg == "c5_zero":  # the 3D projection steps from zero only (kernel profiles)
+            others["c5_zero"] = leg_c5_zero(B, inputs)
         elif leg == "ad_large":  # the large advection-diffusion solves only (kernel profiles)
             others["ad_large"] = ad_large(B, inputs, args.steps, args.warmup)
         elif leg == "explicit":
