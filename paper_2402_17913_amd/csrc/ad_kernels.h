@@ -441,11 +441,11 @@ __device__ __forceinline__ void ad_tail_sweep(const double *__restrict__ X, cons
 // level up prolongation + nu2 sweeps.  f_t: right-hand side of level lg_t
 // (global); x_t: its correction (global).  nu1 >= 1; lg_t <= Tail<D>::LG.
 template <int D>
-__global__ __launch_bounds__(Tail<D>::NT) void k_ad_tail(const double *__restrict__ f_t, double *__restrict__ x_t,
+__global__ __launch_bounds__(Tail<D>::NT_AD) void k_ad_tail(const double *__restrict__ f_t, double *__restrict__ x_t,
                                                          const double *__restrict__ Minv, int lg_t, int bc,
                                                          AdLevels Wl, double omega, int nu1, int nu2,
                                                          const int *stop) {
-    constexpr int NT = Tail<D>::NT;
+    constexpr int NT = Tail<D>::NT_AD;
     static_assert(Tail<D>::cells(Tail<D>::LG) >> Tail<D>::LG <= NT, "ad_tail_sweep needs n^(D-1) <= NT");
     __shared__ double xs[Tail<D>::levels_sum()];
     __shared__ double fs[Tail<D>::levels_sum()];

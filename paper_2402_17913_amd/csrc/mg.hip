@@ -2182,7 +2182,7 @@ static np_status ad_vcycle(Hier *H, const np_ad_op &op, const double *f, double 
         if (l > 0 && l == tl) {  // levels tl .. L in one workgroup
             AdLevels Wl{};
             for (int q = 0; q <= L - l; ++q) Wl.w[q] = ad_weights(op, D, hl * double(int64_t(1) << q));
-            hipLaunchKernelGGL((k_ad_tail<D>), dim3(1), dim3(Tail<D>::NT), 0, s, F[l], cur[l], H->ad_minv, lg, bc,
+            hipLaunchKernelGGL((k_ad_tail<D>), dim3(1), dim3(Tail<D>::NT_AD), 0, s, F[l], cur[l], H->ad_minv, lg, bc,
                                Wl, co.omega, co.nu1, co.nu2, stop);
             NP_LAUNCH_CHECK();
             break;
