@@ -416,8 +416,9 @@ np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double
  * sweep(sweep(x)) in one z-marching pass, the two pre-sweeps of those levels
  * from a nonzero iterate (c unused, may be NULL); 7: x = two sweeps from
  * zero and c = R (f - A x) in one z-marching pass, the zero-start down-leg of
- * those levels (xout unused, may be NULL).  Kinds 5 to 7 need
- * 128 <= n <= 1024.
+ * those levels (xout unused, may be NULL); 8: xout = two sweeps of x and
+ * c = R (f - A xout) in one z-marching pass, the down-leg of a nonzero iterate
+ * (FP32 and FP64 storage).  Kinds 5 to 8 need 128 <= n <= 1024.
  * Synchronises the stream. */
 np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x, void *xout,
                       void *c, void *stream);
@@ -465,7 +466,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * levels from 32^3 to 2^"fbmax" cells per axis -- the down-leg from a zero iterate and the up-leg with two
  * post-sweeps, one pass each; default 1, fbmax 6), "sweep2z" (0/1: two sweeps in one z-marching pass on 3D
  * levels from 128^3 to 1024^3 -- the pre-sweeps of a nonzero iterate, with the convergence check, and the
- * up-leg with prolongation + correction; default 1), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
+ * up-leg with prolongation + correction; default 1), "down2z" (0/1: in FP32 and FP64, from 256^3, the
+ * residual and the restriction in the down-leg's two-sweep pass too; default 1), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
  * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths),
  * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
  * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit, collocated and staggered

@@ -506,7 +506,7 @@ def np_release_all():
 PROF_LEVEL_SWEEP, PROF_LEVEL_RESTRICT, PROF_LEVEL_PROLONG = 0, 1, 2
 
 
-LEVEL_ZERO2, LEVEL_RESTRICT, LEVEL_DOWN0, LEVEL_PSWEEP_SWEEP, LEVEL_UP2, LEVEL_UP2Z, LEVEL_SWEEP2Z, LEVEL_DOWN0Z = range(8)
+LEVEL_ZERO2, LEVEL_RESTRICT, LEVEL_DOWN0, LEVEL_PSWEEP_SWEEP, LEVEL_UP2, LEVEL_UP2Z, LEVEL_SWEEP2Z, LEVEL_DOWN0Z, LEVEL_DOWN2Z = range(9)
 
 
 def np_op_level(kind, f, x, xout, c, h, bc, prec):

@@ -122,6 +122,7 @@ struct Tuning {
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
     int zero2 = 1;        // first two sweeps from a zero iterate in one pass
     int sweep2z = 1;      // two sweeps in one z-marching pass on 3D levels of n >= 128 (both legs)
+    int down2z = 1;       // FP32/FP64 down-leg of a nonzero iterate with its restriction in that pass
     int fuseb = 1;        // temporally blocked down-leg (from zero) and up-leg block kernels on small 3D levels
     int fbmax = 6;        // largest such level (log2 cells per axis)
 };
@@ -635,6 +636,40 @@ template <int D, class S> struct Ops {
         }
     }
 
+    // x = sweep(sweep(xin)) and fc = R (f - A x) in one z-marching pass on a 3D level of
+    // 128 <= n <= 1024 in FP32 or FP64 storage (k_down2z); with `partial`, also the per-workgroup
+    // partials of |f - A xin|^2 (their count in *np).
+    // (from 256^3: at 128^3 measured no faster, FP64 28.2 against 26.6 us for the two passes)
+    static bool down2_on(int lg) { return z2_on(lg) && lg >= 8 && sizeof(S) >= 4 && g_tune.down2z; }
+    static np_status down2z(const S *f, const S *xin, S *x, S *fc, double *partial, int *np, int lg, int bc,
+                            double h, double omega, hipStream_t s, bool finest, const int *stop) {
+        if constexpr (D == 3 && sizeof(S) >= 4) {
+            const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+            const int zc = sweep2z_planes<S>(lg);
+            const unsigned nb = zblocks(lg, 1, zc);
+            void *tok = nullptr;
+            const bool prof = finest && (prof_on() & kProfDown);
+            if (prof) NP_TRY(prof_begin(s, &tok));
+            if (partial)
+                hipLaunchKernelGGL((k_down2z<S, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, x, fc, partial, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
+            else
+                hipLaunchKernelGGL((k_down2z<S, false>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, x, fc, nullptr,
+                                   lg, bc, zc, inv_h2, wdiag, stop);
+            NP_LAUNCH_CHECK();
+            if (prof) {
+                const double m = double(cells(D, lg));
+                NP_TRY(prof_end(s, tok, m * sizeof(S) * 3 + m / 8 * sizeof(S)));
+            }
+            if (np) *np = int(nb);
+            return NP_OK;
+        } else {
+            (void)f; (void)xin; (void)x; (void)fc; (void)partial; (void)np; (void)lg; (void)bc; (void)h; (void)omega;
+            (void)s; (void)finest; (void)stop;
+            return NP_EINVAL;
+        }
+    }
+
     // Whether prolongation + correction and the first post-sweep of a level run as one kernel
     // (2D: every level above the tail; 3D: levels of n >= 32 on the z-marching tiles).
     static bool psweep_on(int lg, int nu2) {
@@ -835,17 +870,23 @@ template <int D, class S> struct Ops {
                 NP_LAUNCH_CHECK();
             }
             if (!zf && o.nu1 == 2 && z2_on(lg)) {
-                // both pre-sweeps in one pass (with the residual check of the input iterate on level 0)
+                // both pre-sweeps in one pass (with the residual check of the input iterate on level 0),
+                // in FP32 and FP64 with the residual and the restriction in the same pass
                 const bool ck = check && l == 0 && !zero;
                 int nb = 0;
-                NP_TRY(sweep2z(nullptr, F[l], cur[l], oth[l], ck ? H->red : nullptr, &nb, lg, bc, hl, o.omega, s,
-                               l == 0, stop));
+                if (down2_on(lg)) {
+                    NP_TRY(down2z(F[l], cur[l], oth[l], fc, ck ? H->red : nullptr, &nb, lg, bc, hl, o.omega, s, l == 0,
+                                  stop));
+                } else {
+                    NP_TRY(sweep2z(nullptr, F[l], cur[l], oth[l], ck ? H->red : nullptr, &nb, lg, bc, hl, o.omega, s,
+                                   l == 0, stop));
+                }
                 if (ck) {
                     hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
                     NP_LAUNCH_CHECK();
                 }
                 std::swap(cur[l], oth[l]);
-                NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
+                if (!down2_on(lg)) NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
                 if (l + 1 == tl) { hl *= 2.0; break; }
                 continue;
             }
@@ -1390,7 +1431,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},  {"sweep2z", &g_tune.sweep2z, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1439,6 +1480,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "ir_cpt")) return g_tune.ir_cpt;
     if (!std::strcmp(key, "fuseb")) return g_tune.fuseb;
     if (!std::strcmp(key, "sweep2z")) return g_tune.sweep2z;
+    if (!std::strcmp(key, "down2z")) return g_tune.down2z;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
@@ -1905,8 +1947,14 @@ static np_status op_level(int kind, const void *f, void *x, void *xout, void *c,
     case 5:
     case 6:
     case 7:
-        if (lg < 7 || lg > 10) { set_error("kinds 5 to 7 need 128 <= n <= 1024"); return NP_EINVAL; }
+    case 8:
+        if (lg < 7 || lg > 10) { set_error("kinds 5 to 8 need 128 <= n <= 1024"); return NP_EINVAL; }
         if (kind == 7) return O::down0z((const S *)f, (S *)x, (S *)c, lg, bc, h, w, s, false, nullptr);
+        if (kind == 8) {
+            if (sizeof(S) < 4) { set_error("kind 8 runs FP32 and FP64 storage"); return NP_EINVAL; }
+            return O::down2z((const S *)f, (const S *)x, (S *)xout, (S *)c, nullptr, nullptr, lg, bc, h, w, s, false,
+                             nullptr);
+        }
         return O::sweep2z(kind == 5 ? (const S *)c : nullptr, (const S *)f, (const S *)x, (S *)xout, nullptr,
                           nullptr, lg, bc, h, w, s, false, nullptr);
     }
@@ -1917,9 +1965,9 @@ extern "C" np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec,
                                  void *xout, void *c, void *stream) {
     int lg;
     NP_TRY(op_prelude(dims, h, bc, &lg));
-    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 7 || !f || !x || ((kind >= 3 && kind != 7) && (!xout || xout == x)) ||
+    if (dims.ndim != 3 || lg < 5 || kind < 0 || kind > 8 || !f || !x || ((kind >= 3 && kind != 7) && (!xout || xout == x)) ||
         (kind != 0 && kind != 6 && !c)) {
-        set_error("np_op_level: 3D grids of n >= 32, kind 0..7, distinct non-null buffers");
+        set_error("np_op_level: 3D grids of n >= 32, kind 0..8, distinct non-null buffers");
         return NP_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;

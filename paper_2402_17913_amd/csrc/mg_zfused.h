@@ -569,4 +569,224 @@ __global__ __launch_bounds__(kS3Threads) void k_down0z(const S *__restrict__ f, 
     }
 }
 
+// The down-leg of a large 3D level from a nonzero iterate in one pass (one cell
+// per thread: FP32 and FP64 storage): x2 = sweep(sweep(x)) and fc = R (f - A x2),
+// with NORM the per-workgroup partials of |f - A x|^2 (the convergence check of
+// the input iterate).  Three stages run one plane apart: the first sweep at
+// plane z on the tile and a two-cell ring (reading x on a three-cell ring from
+// LDS), the second at z - 1 on the tile and a one-cell ring, the residual of x2
+// at z - 2 on the tile, summed over the children of each coarse cell in
+// k_restrict3's order (the plane pair, then the column pair and the row pair by
+// lane shuffles).  Ring cells go to whole waves as in k_sweep2z (ring 1 first,
+// then ring 3, ring 2 last) and share one register set.  The second sweep and
+// the residual read a Dirichlet ghost as minus the cell's own value, the first
+// sweep reads the iterate's ghosts by the boundary rule, as the per-kernel
+// kernels do: both outputs equal k_sweep3 twice then k_restrict3 bit for bit.
+template <class S> struct Z3Cfg {
+    static constexpr int TP = 32, TX = 32, TY = kS3Threads / TP;
+    static constexpr int W1 = TX + 2, H1 = TY + 2, W2 = TX + 4, H2 = TY + 4, W3 = TX + 6, H3 = TY + 6;
+    static constexpr int NR1 = 2 * (TX + 2) + 2 * TY, NR2 = 2 * (TX + 4) + 2 * (TY + 2),
+                         NR3 = 2 * (TX + 6) + 2 * (TY + 4);
+    static constexpr int NW = kS3Threads / 64;
+    static constexpr int NW1 = (NR1 + 63) / 64, NW2 = (NR2 + 63) / 64, NW3 = (NR3 + 63) / 64;
+    static_assert(NW1 + NW2 + NW3 <= NW, "ring slots on distinct waves");
+    static_assert(sizeof(S) >= 4, "one cell per thread: FP32 and FP64 storage");
+};
+
+template <class S, bool NORM>
+__global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, const S *__restrict__ xin,
+                                                       S *__restrict__ xout, S *__restrict__ fc,
+                                                       double *__restrict__ partial, int lg, int bc, int zc,
+                                                       typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                       const int *stop) {
+    typedef typename St<S>::C C;
+    typedef Z3Cfg<S> G;
+    constexpr int TX = G::TX, TY = G::TY, TP = G::TP, W1 = G::W1, W2 = G::W2, W3 = G::W3;
+    constexpr int B1 = G::H1 * W1, B2 = G::H2 * W2;
+    __shared__ C XA[G::H3 * W3];  // x of plane z, tile and three-cell ring
+    __shared__ C X1[2 * B2];      // first sweep of planes z - 1, z (slot = plane & 1), tile and two-cell ring
+    __shared__ C X2[2 * B1];      // second sweep of planes z - 2, z - 1, tile and one-cell ring
+    if (stop && *stop) return;
+    const int n = 1 << lg, ntx = n / TX, nty = n / TY, lgc = lg - 1;
+    const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+    const int t = int(threadIdx.x), tp = t % TP, ty = t / TP;
+    const int x0 = (blk % ntx) * TX, y0 = ((blk / ntx) % nty) * TY, k0 = (blk / (ntx * nty)) * zc;
+    const int pl = 2 * lg;
+    const uint32_t osrc = (uint32_t(y0 + ty) << lg) + uint32_t(x0 + tp);
+    // ring role of this thread's wave: 1, 3 (after ring 1) or 2 (the last waves), or none
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool r1 = wv < G::NW1, r3 = wv >= G::NW1 && wv < G::NW1 + G::NW3, r2 = wv >= G::NW - G::NW2;
+    const bool rr = r1 || r2 || r3;
+    int ra = 0, rb = 0;
+    if (r1) ring_pos<TX, TY>(min(t, G::NR1 - 1), 1, ra, rb);
+    if (r3) ring_pos<TX, TY>(min(t - 64 * G::NW1, G::NR3 - 1), 3, ra, rb);
+    if (r2) ring_pos<TX, TY>(min(t - 64 * (G::NW - G::NW2), G::NR2 - 1), 2, ra, rb);
+    uint32_t rsrc;
+    C rsg;
+    {
+        int s = 1;
+        const int gi = bmap(x0 + ra, n, bc, s), gj = bmap(y0 + rb, n, bc, s);
+        rsrc = (uint32_t(gj) << lg) + uint32_t(gi);
+        rsg = C(s);
+    }
+    const int own_a = (ty + 3) * W3 + tp + 3, own_1 = (ty + 2) * W2 + tp + 2, own_2 = (ty + 1) * W1 + tp + 1;
+    const int ring_a = (rb + 3) * W3 + ra + 3, ring_1 = (rb + 2) * W2 + ra + 2, ring_2 = (rb + 1) * W1 + ra + 1;
+    // Dirichlet walls next to a position (the ghosts of the second sweep and the residual)
+    auto wall = [&](int a, int b, bool &w, bool &e, bool &so, bool &no) {
+        w = !bc && x0 + a == 0;
+        e = !bc && x0 + a == n - 1;
+        so = !bc && y0 + b == 0;
+        no = !bc && y0 + b == n - 1;
+    };
+    bool ow, oe, os, on, qw, qe, qs, qn;
+    wall(tp, ty, ow, oe, os, on);
+    wall(ra, rb, qw, qe, qs, qn);
+    auto poff = [&](int q) -> uint32_t {
+        bool flip;
+        return uint32_t(plane_map(q, n, bc, flip)) << pl;
+    };
+    auto psign = [&](int q) -> C { return (!bc && (q < 0 || q >= n)) ? C(-1) : C(1); };
+    // a sweep at an LDS position with in-plane neighbours from frame L (row width W), z-neighbours
+    // given; the residual r of the input
+    auto sweepL = [&](const C *L, int W, int q, C xc, C xm, C xp, C fv, C &r) -> C {
+        const C t0 = ((L[q - 1] + L[q + 1]) + L[q - W]) + L[q + W];
+        const C s = (t0 + xm) + xp;
+        r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+    // the same with Dirichlet ghosts selected as minus the centre value
+    auto sweepD = [&](const C *L, int W, int q, C xc, C xm, C xp, C fv, bool w, bool e, bool so, bool no,
+                      bool zl, bool zu, C &r) -> C {
+        const C lw = L[q - 1], le = L[q + 1], ls = L[q - W], ln = L[q + W];
+        const C xw = w ? -xc : lw, xe = e ? -xc : le, ys = so ? -xc : ls, yn = no ? -xc : ln;
+        const C zm = zl ? -xc : xm, zp = zu ? -xc : xp;
+        const C t0 = ((xw + xe) + ys) + yn;
+        const C s = (t0 + zm) + zp;
+        r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+    // registers: own x at z - 1 .. z + 1, x1 at z - 2 .. z, x2 at z - 3, z - 2, f at z, z - 1, z - 2;
+    // ring (one set for every role): x at z - 1 .. z + 1 (ring 3: z only), x1 at z - 2 .. z (ring 1),
+    // f at z, z - 1
+    C xo[3], x1o[3], x2o[2], fo[3];
+    C rx[3] = {C(0), C(0), C(0)}, r1x[3] = {C(0), C(0), C(0)}, rf[2] = {C(0), C(0)};
+    C pw[2], pf[2], pr[2] = {C(0), C(0)}, pq[2] = {C(0), C(0)};  // loads in flight (set = step parity)
+    for (int i = 0; i < 3; ++i) x1o[i] = fo[i] = C(0);
+    x2o[0] = x2o[1] = C(0);
+    // the step at plane z consumes x(z + 2), f(z + 1) at the own cell and the ring cell (ring 3:
+    // x(z + 1)); past the planes used the last one is read again
+    auto pload = [&](int z, auto u) {
+        constexpr int U = decltype(u)::value;
+        const uint32_t o2 = poff(min(z + 2, k0 + zc + 2)), o1 = poff(min(z + 1, k0 + zc + 1));
+        pw[U] = St<S>::ld(xin + o2 + osrc);
+        pf[U] = St<S>::ld(f + o1 + osrc);
+        pr[U] = St<S>::ld(xin + (r3 ? o1 : o2) + rsrc);
+        pq[U] = St<S>::ld(f + o1 + rsrc);
+    };
+    // prologue: x at k0 - 3 .. k0 - 1, f at k0 - 2 (own, rings 1 and 2); ring 3: x at k0 - 2
+    for (int i = 0; i < 3; ++i) {
+        const int q = k0 - 3 + i;
+        xo[i] = psign(q) * St<S>::ld(xin + poff(q) + osrc);
+        rx[i] = (psign(q) * rsg) * St<S>::ld(xin + poff(q) + rsrc);
+    }
+    fo[0] = St<S>::ld(f + poff(k0 - 2) + osrc);
+    rf[0] = St<S>::ld(f + poff(k0 - 2) + rsrc);
+    if (r3) rx[1] = (psign(k0 - 2) * rsg) * St<S>::ld(xin + poff(k0 - 2) + rsrc);
+    pload(k0 - 2, std::integral_constant<int, 0>{});
+    double acc = 0.0;
+    C pair = C(0);
+    auto step = [&](int z, auto odd) {
+        constexpr bool ODD = decltype(odd)::value;
+        constexpr int U = ODD ? 1 : 0;
+        pload(z + 1, std::integral_constant<int, 1 - U>{});
+        // x of plane z into LDS: own cell and the ring cell (every role)
+        XA[own_a] = xo[1];
+        if (rr) XA[ring_a] = rx[1];
+        __syncthreads();
+        // stage A: first sweep at plane z, own cell, rings 1 and 2
+        C *L1 = X1 + (ODD ? B2 : 0);
+        {
+            C r;
+            const C v = st_round<S>(sweepL(XA, W3, own_a, xo[1], xo[0], xo[2], fo[0], r));
+            if (NORM && z >= k0 && z < k0 + zc) acc += double(r) * double(r);
+            L1[own_1] = v;
+            x1o[2] = v;  // x1 at z (registers slide at the end of the step)
+        }
+        if (r1 || r2) {
+            C r;
+            const C v = st_round<S>(sweepL(XA, W3, ring_a, rx[1], rx[0], rx[2], rf[0], r));
+            L1[ring_1] = v;
+            r1x[2] = v;
+        }
+        __syncthreads();
+        // stage B: second sweep at plane z - 1, own cell and ring 1
+        const int p = z - 1;
+        const C *M1 = X1 + (ODD ? 0 : B2);
+        C *L2 = X2 + (ODD ? 0 : B1);
+        const bool zl1 = !bc && p == 0, zu1 = !bc && p == n - 1;
+        C x2n = C(0);
+        if (z >= k0) {
+            C r;
+            x2n = st_round<S>(sweepD(M1, W2, own_1, x1o[1], x1o[0], x1o[2], fo[1], ow, oe, os, on, zl1, zu1, r));
+            L2[own_2] = x2n;
+            if (p >= k0 && p < k0 + zc) St<S>::st(xout + (uint32_t(p) << pl) + osrc, x2n);
+            if (r1) {
+                L2[ring_2] = st_round<S>(sweepD(M1, W2, ring_1, r1x[1], r1x[0], r1x[2], rf[1], qw, qe, qs, qn, zl1,
+                                                zu1, r));
+            }
+        }
+        __syncthreads();
+        // stage C: residual of x2 at plane z - 2, own cell, into the coarse cells
+        if (z >= k0 + 2) {
+            const int pc = z - 2;
+            const C *M2 = X2 + (ODD ? B1 : 0);
+            const bool zl = !bc && pc == 0, zu = !bc && pc == n - 1;
+            C r;
+            (void)sweepD(M2, W1, own_2, x2o[1], x2o[0], x2n, fo[2], ow, oe, os, on, zl, zu, r);
+            if (ODD) {  // pc odd: the second plane of the pair
+                pair += r;
+                const C b = __shfl_down(pair, 1), cy = __shfl_down(pair, 32), d = __shfl_down(pair, 33);
+                if (((tp | ty) & 1) == 0) {
+                    const uint32_t cc = (uint32_t(pc >> 1) << (2 * lgc)) + (uint32_t((y0 + ty) >> 1) << lgc) +
+                                        uint32_t((x0 + tp) >> 1);
+                    St<S>::st(fc + cc, (((pair + b) + cy) + d) * C(0.125));
+                }
+            } else {
+                pair = r;
+            }
+        }
+        // slide
+        const C sg2 = psign(z + 2), sg1 = psign(z + 1);
+        x2o[0] = x2o[1];
+        x2o[1] = x2n;
+        x1o[0] = x1o[1];
+        x1o[1] = x1o[2];
+        fo[2] = fo[1];
+        fo[1] = fo[0];
+        fo[0] = pf[U];
+        xo[0] = xo[1];
+        xo[1] = xo[2];
+        xo[2] = sg2 * pw[U];
+        r1x[0] = r1x[1];
+        r1x[1] = r1x[2];
+        rf[1] = rf[0];
+        rf[0] = pq[U];
+        if (r3) {
+            rx[1] = (sg1 * rsg) * pr[U];
+        } else {
+            rx[0] = rx[1];
+            rx[1] = rx[2];
+            rx[2] = (sg2 * rsg) * pr[U];
+        }
+    };
+    for (int z = k0 - 2; z < k0 + zc + 2; z += 2) {  // k0 even: pairs (even, odd)
+        step(z, std::false_type{});
+        step(z + 1, std::true_type{});
+    }
+    if constexpr (NORM) {
+        acc = block_sum_n<kS3Threads>(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
 }  // namespace np

@@ -745,10 +745,65 @@ def test_down0z_matches_oracle(B, orc):
         assert rel(host(xz), x2) < 1e-12 and rel(host(cz), fc) < 1e-12
 
 
+@pytest.mark.parametrize("prec", [B_FP64, B_FP32])
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_down2z_matches_per_kernel_path(B, prec, n, bc):
+    """The one-pass down-leg of a nonzero iterate (k_down2z: both pre-sweeps, the
+    residual and the restriction, FP32 and FP64 storage) against the two-sweep pass
+    then k_restrict3: iterate and coarse right-hand side bit for bit."""
+    import torch
+    say("down2z", prec, n, bc)
+    h = 1.0 / n
+    f, x, c = level_arrays(prec, n, 190 + n + bc + 10 * prec)
+    ya, ca = torch.zeros_like(x), torch.zeros_like(c)
+    B.np_op_level(B.LEVEL_SWEEP2Z, f, x, ya, None, h, bc, prec)
+    B.np_op_level(B.LEVEL_RESTRICT, f, ya, None, ca, h, bc, prec)
+    yb, cb = torch.zeros_like(x), torch.zeros_like(c)
+    B.np_op_level(B.LEVEL_DOWN2Z, f, x, yb, cb, h, bc, prec)
+    say("  down2z x diff %.3e, c diff %.3e" % (rel(as64(yb), as64(ya)), rel(as64(cb), as64(ca))))
+    assert torch.equal(ya, yb)
+    assert torch.equal(ca, cb)
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
+def test_down2z_knob_same_solves(B, orc, bc):
+    """Whole 256^3 solves with the one-pass nonzero down-leg on and off: FP64 fixed
+    cycles bit for bit and within 1e-12 of the oracle's; FP64 and FP32-mixed solves to
+    the tolerance in the same cycles with equal iterates, judged by the oracle."""
+    n = 256
+    g = inputs.sine_rhs(3, n, seed=6)
+    f, h = g["f"], g["h"]
+    if bc == PER:
+        f = f - f.mean()
+    fg = dev(f)
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("down2z", v)
+            for p in (B.FP64, B.FP32):
+                xg = dev(np.zeros_like(f))
+                st, stats = B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p)
+                out[(v, p)] = (host(xg), stats["cycles"], stats["rel_res"])
+                assert orc.rel_res(f, out[(v, p)][0], h, bc) <= 1e-10
+            xg = dev(np.zeros_like(f))
+            B.mg_poisson_solve(fg, xg, h, bc, fixed_cycles=3)
+            out[(v, "fixed")] = host(xg)
+    finally:
+        B.np_set_tuning("down2z", 1)
+    say("down2z on/off cycles", [(k, v[1], v[2]) for k, v in out.items() if k[1] != "fixed"])
+    assert np.array_equal(out[(1, "fixed")], out[(0, "fixed")])
+    for p in (B.FP64, B.FP32):
+        assert out[(1, p)][1] == out[(0, p)][1] and np.array_equal(out[(1, p)][0], out[(0, p)][0])
+        assert abs(out[(1, p)][2] / out[(0, p)][2] - 1) < 1e-9
+    ref = orc.mg_solve(f, h, bc, fixed_cycles=3)
+    assert rel(out[(1, "fixed")], ref.x) < 1e-12
+
+
 def test_up2z_needs_large_level(B):
     import torch
     f, x, c = level_arrays(B_FP64, 64, 1)
-    for kind in (B.LEVEL_UP2Z, B.LEVEL_SWEEP2Z, B.LEVEL_DOWN0Z):
+    for kind in (B.LEVEL_UP2Z, B.LEVEL_SWEEP2Z, B.LEVEL_DOWN0Z, B.LEVEL_DOWN2Z):
         with pytest.raises(B.NeuphysError):
             B.np_op_level(kind, f, x, torch.zeros_like(x), c, 1.0 / 64, DIR, B_FP64)
 
