@@ -418,7 +418,8 @@ np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double
  * zero and c = R (f - A x) in one z-marching pass, the zero-start down-leg of
  * those levels (xout unused, may be NULL); 8: xout = two sweeps of x and
  * c = R (f - A xout) in one z-marching pass, the down-leg of a nonzero iterate
- * (FP32 and FP64 storage).  Kinds 5 to 8 need 128 <= n <= 1024.
+ * (one cell per thread; the cycle runs it in FP32 and FP64).  Kinds 5 to 8
+ * need 128 <= n <= 1024.
  * Synchronises the stream. */
 np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x, void *xout,
                       void *c, void *stream);

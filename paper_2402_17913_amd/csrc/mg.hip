@@ -639,13 +639,14 @@ template <int D, class S> struct Ops {
     // x = sweep(sweep(xin)) and fc = R (f - A x) in one z-marching pass on a 3D level of
     // 128 <= n <= 1024 in FP32 or FP64 storage (k_down2z); with `partial`, also the per-workgroup
     // partials of |f - A xin|^2 (their count in *np).
-    // (from 256^3: at 128^3 measured no faster, FP64 28.2 against 26.6 us for the two passes)
+    // In the cycle: FP32 and FP64 from 256^3 (at 128^3 measured no faster, FP64 28.2 against 26.6 us
+    // for the two passes; BF16, on one-cell-per-thread tiles, 64 against 50 us at 256^3).
     static bool down2_on(int lg) { return z2_on(lg) && lg >= 8 && sizeof(S) >= 4 && g_tune.down2z; }
     static np_status down2z(const S *f, const S *xin, S *x, S *fc, double *partial, int *np, int lg, int bc,
                             double h, double omega, hipStream_t s, bool finest, const int *stop) {
-        if constexpr (D == 3 && sizeof(S) >= 4) {
+        if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
-            const int zc = sweep2z_planes<S>(lg);
+            const int zc = down2z_planes<S>(lg);
             const unsigned nb = zblocks(lg, 1, zc);
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDown);
@@ -1951,7 +1952,6 @@ static np_status op_level(int kind, const void *f, void *x, void *xout, void *c,
         if (lg < 7 || lg > 10) { set_error("kinds 5 to 8 need 128 <= n <= 1024"); return NP_EINVAL; }
         if (kind == 7) return O::down0z((const S *)f, (S *)x, (S *)c, lg, bc, h, w, s, false, nullptr);
         if (kind == 8) {
-            if (sizeof(S) < 4) { set_error("kind 8 runs FP32 and FP64 storage"); return NP_EINVAL; }
             return O::down2z((const S *)f, (const S *)x, (S *)xout, (S *)c, nullptr, nullptr, lg, bc, h, w, s, false,
                              nullptr);
         }

@@ -97,14 +97,15 @@ __device__ __forceinline__ int plane_map(int q, int n, int bc, bool &flip) {
 // four workgroups per CU (1024), and at least four planes (measured: at 128^3
 // BF16, 512 workgroups of four planes beat 1024 of two); the tuning knob
 // "zc3" overrides.
-template <class S> inline int sweep2z_planes(int lg) {
+inline int z2_planes(int lg, int tx, int ty) {
     const int n = 1 << lg;
-    const int64_t tiles = (int64_t(n) / Z2Cfg<S>::TX) * (n / Z2Cfg<S>::TY);
+    const int64_t tiles = (int64_t(n) / tx) * (n / ty);
     int zc = 4;
     while (zc < n && tiles * (n / (2 * zc)) >= 1024) zc *= 2;
     if (g_zc3 >= 2 && g_zc3 <= n) zc = g_zc3;
     return zc;
 }
+template <class S> inline int sweep2z_planes(int lg) { return z2_planes(lg, Z2Cfg<S>::TX, Z2Cfg<S>::TY); }
 
 template <class S, bool CORR, bool NORM>
 __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec, const S *__restrict__ f,
@@ -570,7 +571,8 @@ __global__ __launch_bounds__(kS3Threads) void k_down0z(const S *__restrict__ f, 
 }
 
 // The down-leg of a large 3D level from a nonzero iterate in one pass (one cell
-// per thread: FP32 and FP64 storage): x2 = sweep(sweep(x)) and fc = R (f - A x2),
+// per thread, 32 x 16 tiles, in every storage precision): x2 = sweep(sweep(x))
+// and fc = R (f - A x2),
 // with NORM the per-workgroup partials of |f - A x|^2 (the convergence check of
 // the input iterate).  Three stages run one plane apart: the first sweep at
 // plane z on the tile and a two-cell ring (reading x on a three-cell ring from
@@ -590,8 +592,8 @@ template <class S> struct Z3Cfg {
     static constexpr int NW = kS3Threads / 64;
     static constexpr int NW1 = (NR1 + 63) / 64, NW2 = (NR2 + 63) / 64, NW3 = (NR3 + 63) / 64;
     static_assert(NW1 + NW2 + NW3 <= NW, "ring slots on distinct waves");
-    static_assert(sizeof(S) >= 4, "one cell per thread: FP32 and FP64 storage");
 };
+template <class S> inline int down2z_planes(int lg) { return z2_planes(lg, Z3Cfg<S>::TX, Z3Cfg<S>::TY); }
 
 template <class S, bool NORM>
 __global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, const S *__restrict__ xin,
@@ -743,16 +745,28 @@ __global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, 
             const bool zl = !bc && pc == 0, zu = !bc && pc == n - 1;
             C r;
             (void)sweepD(M2, W1, own_2, x2o[1], x2o[0], x2n, fo[2], ow, oe, os, on, zl, zu, r);
-            if (ODD) {  // pc odd: the second plane of the pair
-                pair += r;
-                const C b = __shfl_down(pair, 1), cy = __shfl_down(pair, 32), d = __shfl_down(pair, 33);
-                if (((tp | ty) & 1) == 0) {
-                    const uint32_t cc = (uint32_t(pc >> 1) << (2 * lgc)) + (uint32_t((y0 + ty) >> 1) << lgc) +
-                                        uint32_t((x0 + tp) >> 1);
-                    St<S>::st(fc + cc, (((pair + b) + cy) + d) * C(0.125));
+            const uint32_t cc = (uint32_t(pc >> 1) << (2 * lgc)) + (uint32_t((y0 + ty) >> 1) << lgc) +
+                                uint32_t((x0 + tp) >> 1);
+            if constexpr (ZCfg<S>::CPT == 2) {
+                // k_restrict3 with two cells per thread: the x-pair of each plane, the plane pair,
+                // then the row pair
+                const C rx = r + __shfl_down(r, 1);
+                if (ODD) {
+                    pair += rx;
+                    const C o = __shfl_down(pair, 32);
+                    if (((tp | ty) & 1) == 0) St<S>::st(fc + cc, (pair + o) * C(0.125));
+                } else {
+                    pair = rx;
                 }
             } else {
-                pair = r;
+                // one cell per thread: the plane pair, then the column pair and the row pair
+                if (ODD) {  // pc odd: the second plane of the pair
+                    pair += r;
+                    const C b = __shfl_down(pair, 1), cy = __shfl_down(pair, 32), d = __shfl_down(pair, 33);
+                    if (((tp | ty) & 1) == 0) St<S>::st(fc + cc, (((pair + b) + cy) + d) * C(0.125));
+                } else {
+                    pair = r;
+                }
             }
         }
         // slide

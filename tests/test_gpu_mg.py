@@ -745,13 +745,14 @@ def test_down0z_matches_oracle(B, orc):
         assert rel(host(xz), x2) < 1e-12 and rel(host(cz), fc) < 1e-12
 
 
-@pytest.mark.parametrize("prec", [B_FP64, B_FP32])
+@pytest.mark.parametrize("prec", [B_FP64, B_FP32, B_BF16])
 @pytest.mark.parametrize("n", [128, 256])
 @pytest.mark.parametrize("bc", [DIR, PER])
 def test_down2z_matches_per_kernel_path(B, prec, n, bc):
     """The one-pass down-leg of a nonzero iterate (k_down2z: both pre-sweeps, the
-    residual and the restriction, FP32 and FP64 storage) against the two-sweep pass
-    then k_restrict3: iterate and coarse right-hand side bit for bit."""
+    residual and the restriction, one cell per thread) against the two-sweep pass then
+    k_restrict3: iterate and coarse right-hand side bit for bit (children summed in
+    k_restrict3's order for the storage, two cells per thread in BF16)."""
     import torch
     say("down2z", prec, n, bc)
     h = 1.0 / n
@@ -769,8 +770,9 @@ def test_down2z_matches_per_kernel_path(B, prec, n, bc):
 @pytest.mark.parametrize("bc", [DIR, PER])
 def test_down2z_knob_same_solves(B, orc, bc):
     """Whole 256^3 solves with the one-pass nonzero down-leg on and off: FP64 fixed
-    cycles bit for bit and within 1e-12 of the oracle's; FP64 and FP32-mixed solves to
-    the tolerance in the same cycles with equal iterates, judged by the oracle."""
+    cycles bit for bit and within 1e-12 of the oracle's; FP64, FP32- and BF16-mixed
+    solves to the tolerance in the same cycles with equal iterates, judged by the
+    oracle."""
     n = 256
     g = inputs.sine_rhs(3, n, seed=6)
     f, h = g["f"], g["h"]
@@ -781,7 +783,7 @@ def test_down2z_knob_same_solves(B, orc, bc):
     try:
         for v in (1, 0):
             B.np_set_tuning("down2z", v)
-            for p in (B.FP64, B.FP32):
+            for p in (B.FP64, B.FP32, B.BF16):
                 xg = dev(np.zeros_like(f))
                 st, stats = B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p)
                 out[(v, p)] = (host(xg), stats["cycles"], stats["rel_res"])
@@ -793,7 +795,7 @@ def test_down2z_knob_same_solves(B, orc, bc):
         B.np_set_tuning("down2z", 1)
     say("down2z on/off cycles", [(k, v[1], v[2]) for k, v in out.items() if k[1] != "fixed"])
     assert np.array_equal(out[(1, "fixed")], out[(0, "fixed")])
-    for p in (B.FP64, B.FP32):
+    for p in (B.FP64, B.FP32, B.BF16):
         assert out[(1, p)][1] == out[(0, p)][1] and np.array_equal(out[(1, p)][0], out[(0, p)][0])
         assert abs(out[(1, p)][2] / out[(0, p)][2] - 1) < 1e-9
     ref = orc.mg_solve(f, h, bc, fixed_cycles=3)
