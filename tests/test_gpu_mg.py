@@ -802,6 +802,36 @@ def test_down2z_knob_same_solves(B, orc, bc):
     assert rel(out[(1, "fixed")], ref.x) < 1e-12
 
 
+@pytest.mark.parametrize("prec", [B_FP64, B_BF16])
+def test_onepass_kernels_512(B, prec):
+    """The one-pass level kernels at 512^3 (Dirichlet), where a workgroup marches 64
+    (BF16) or 128 (FP64) planes: each against its per-kernel pair, bit for bit."""
+    import torch
+    n, bc = 512, DIR
+    say("one-pass 512", prec)
+    h = 1.0 / n
+    f, x, c = level_arrays(prec, n, 230 + prec)
+    ya, yo, yz = x.clone(), torch.zeros_like(x), torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_PSWEEP_SWEEP, f, ya, yo, c, h, bc, prec)
+    B.np_op_level(B.LEVEL_UP2Z, f, x, yz, c, h, bc, prec)
+    assert torch.equal(ya, yz)
+    del yo
+    y1, y2 = torch.zeros_like(x), torch.zeros_like(x)
+    B.np_prof_level(B.PROF_LEVEL_SWEEP, f, x, y1, h, bc, prec, reps=1)
+    B.np_prof_level(B.PROF_LEVEL_SWEEP, f, y1, y2, h, bc, prec, reps=1)
+    B.np_op_level(B.LEVEL_SWEEP2Z, f, x, yz, None, h, bc, prec)
+    assert torch.equal(y2, yz)
+    ca, cb = torch.zeros_like(c), torch.zeros_like(c)
+    B.np_op_level(B.LEVEL_RESTRICT, f, y2, None, ca, h, bc, prec)
+    B.np_op_level(B.LEVEL_DOWN2Z, f, x, yz, cb, h, bc, prec)
+    assert torch.equal(y2, yz) and torch.equal(ca, cb)
+    xa, xb = torch.zeros_like(x), torch.zeros_like(x)
+    B.np_op_level(B.LEVEL_ZERO2, f, xa, None, None, h, bc, prec)
+    B.np_op_level(B.LEVEL_RESTRICT, f, xa, None, ca, h, bc, prec)
+    B.np_op_level(B.LEVEL_DOWN0Z, f, xb, None, cb, h, bc, prec)
+    assert torch.equal(xa, xb) and torch.equal(ca, cb)
+
+
 def test_up2z_needs_large_level(B):
     import torch
     f, x, c = level_arrays(B_FP64, 64, 1)
