@@ -473,7 +473,9 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
  * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit, collocated and staggered
  * momentum steps, n >= 32,
- * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256),
+ * and row-marching tiles for the 2D explicit step, n >= 1024 a multiple of 256), "mom_rows" (4 or 8: tile rows
+ * of the staggered corrector stage on those tiles, default 4), "mom_ring" (2 or 3: planes per field in the staggered
+ * stages' LDS rings; 2 keeps the own column's out-of-ring z-neighbours in registers; default 2),
  * "zc3" (planes per workgroup of the 3D z-marching solver kernels: 0 automatic, else a power of two
  * from 2 to 64; it also sets the one-pass two-sweep kernels' planes), "conv3z" (z-marching tiles for the network's convolutions: 0 off, 1 automatic planes per workgroup, else
  * a power of two from 2 to 64 planes), "wgrad_mfma" (0/1: the network's weight gradients on the matrix

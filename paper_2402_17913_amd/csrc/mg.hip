@@ -1436,7 +1436,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
-        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"mom_rows", &g_mom_rows, 4, 8}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
+        {"zmarch_explicit", &g_zmarch_explicit, 0, 1}, {"mom_rows", &g_mom_rows, 4, 8}, {"mom_ring", &g_mom_ring, 2, 3}, {"zc3", &g_zc3, 0, 64}, {"conv3z", &g_conv3z, 0, 64},
         {"wgrad_mfma", &g_wgrad_mfma, 0, 1},
     };
     for (auto &e : tab)
@@ -1489,6 +1489,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "batched_wg")) return g_batched_wg;
     if (!std::strcmp(key, "zmarch_explicit")) return g_zmarch_explicit;
     if (!std::strcmp(key, "mom_rows")) return g_mom_rows;
+    if (!std::strcmp(key, "mom_ring")) return g_mom_ring;
     if (!std::strcmp(key, "zc3")) return g_zc3;
     if (!std::strcmp(key, "conv3z")) return g_conv3z;
     if (!std::strcmp(key, "wgrad_mfma")) return g_wgrad_mfma;

@@ -166,6 +166,7 @@ extern int g_batched_rm;
 extern int g_batched_wg;
 extern int g_zmarch_explicit;
 extern int g_mom_rows;
+extern int g_mom_ring;
 extern int g_conv3z;
 extern int g_wgrad_mfma;
 extern int g_zc3;  // planes per workgroup of the 3D z-marching solver kernels (0: automatic)

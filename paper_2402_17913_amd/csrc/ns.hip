@@ -429,6 +429,7 @@ constexpr int kZx = 64;
 }  // namespace
 int g_zmarch_explicit = 1;  // tuning knob "zmarch_explicit"
 int g_mom_rows = 4;         // tuning knob "mom_rows": tile rows of the staggered corrector stage (4 or 8)
+int g_mom_ring = 2;         // tuning knob "mom_ring": planes per field in the staggered stages' LDS rings (2 or 3)
 namespace {
 // Tile rows per workgroup: 4 for the 27-point finite-element stages (their
 // register footprint leaves room for more, smaller workgroups per CU: measured
@@ -457,9 +458,8 @@ struct ZRing {
         ty = int(threadIdx.x) / kZx;
         const int ntx = (n + kZx - 1) / kZx, nty = (n + TY - 1) / TY;
         // XCD-contiguous tiles, so that a tile's halo rows and planes (its neighbours' own cells)
-        // are read through the same L2: the projection step's momentum stages read 1.07x / 1.10x
-        // their algorithmic bytes so, 1.94x / 1.62x in launch order (their durations are the
-        // same either way: these stages are not bound by HBM traffic)
+        // are read through the same L2: the three-plane momentum stages read 1.07x / 1.10x their
+        // algorithmic bytes so, 1.94x / 1.62x in launch order
         const int blk = int(xcd_block(blockIdx.x, gridDim.x));
         x0 = (blk % ntx) * kZx;
         y0 = ((blk / ntx) % nty) * TY;
@@ -710,6 +710,197 @@ __global__ __launch_bounds__(kZx * TY) void k_mom_stage3z(Vel qn, Vel qt, double
     });
 }
 
+// LDS rings of two planes per field for the MAC momentum stage (periodic), on
+// tiles of X x TY columns.  While plane z is computed, field f holds planes
+// z + mom_lo(f) and z + mom_lo(f) + 1 (slot = plane & 1): mom_lo = 0 for the
+// fields read off the own column only up to z + 1 (the x and y velocity, the
+// advanced field, p), mom_lo = -1 for the z velocity (its face averages reach
+// z - 1 off the own column).  The one z-neighbour outside that pair is only ever
+// read at the thread's own column, so it sits in a register: plane z - 1 (saved
+// from LDS a step earlier) for mom_lo = 0, plane z + 1 (prefetched two steps
+// ahead) for the z velocity.
+// Slot order: the tile's TY + 2 rows of X interior columns first, one row per
+// wave when X = 64 (so every wave-wide load covers whole aligned 128-byte lines),
+// then the two halo columns of each row; slots past the end repeat the last one
+// (the same value to the same place), so no lane is masked.
+__host__ __device__ constexpr int mom_lo(int f) { return f == 2 ? -1 : 0; }
+
+template <int NF, int X, int TY>
+struct ZRing2 {
+    static constexpr int T = X * TY;
+    static constexpr int SLOTS = (X + 2) * (TY + 2);
+    static constexpr int PER = (SLOTS + T - 1) / T;
+    typedef double Plane[2][TY + 2][X + 2];
+    typedef double Regs[NF][PER];  // one plane of every field, in flight
+    int tx, ty, x0, y0, z0, z1, n;
+    int64_t P;
+    int64_t off[PER];
+    int ly[PER], lx[PER];
+    __device__ ZRing2(int n_, int zc) : n(n_) {
+        tx = int(threadIdx.x) % X;
+        ty = int(threadIdx.x) / X;
+        const int ntx = (n + X - 1) / X, nty = (n + TY - 1) / TY;
+        const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+        x0 = (blk % ntx) * X;
+        y0 = ((blk / ntx) % nty) * TY;
+        z0 = (blk / (ntx * nty)) * zc;
+        z1 = min(z0 + zc, n);
+        P = int64_t(n) * n;
+        constexpr int NI = X * (TY + 2);  // interior slots
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int t = min(int(threadIdx.x) + r * T, SLOTS - 1);
+            ly[r] = t < NI ? t / X : (t - NI) >> 1;
+            lx[r] = t < NI ? t % X + 1 : (((t - NI) & 1) ? X + 1 : 0);
+            double s1, s2;
+            const int gi = adx_res(min(x0 + lx[r] - 1, n), n, 1, s1);
+            const int gj = adx_res(min(y0 + ly[r] - 1, n), n, 1, s2);
+            off[r] = int64_t(gj) * n + gi;
+        }
+    }
+    __device__ __forceinline__ int64_t plane(int z) const {
+        double sz;
+        return int64_t(adx_res(z, n, 1, sz)) * P;
+    }
+    template <class LD>
+    __device__ __forceinline__ void load(const LD &ld, Regs &v, int f, int z) const {
+        const int64_t kk = plane(z);
+#pragma unroll
+        for (int r = 0; r < PER; ++r) v[f][r] = ld(f, kk + off[r]);
+    }
+    __device__ __forceinline__ void store(Plane &pf, const Regs &v, int f, int z) const {
+#pragma unroll
+        for (int r = 0; r < PER; ++r) pf[z & 1][ly[r]][lx[r]] = v[f][r];
+    }
+};
+
+// MAC momentum stage on z-marching tiles with two-plane LDS rings (ZRing2): the
+// same terms in the same order as k_mom_stage (and k_mom_stage3z), so the step
+// is bit-identical.  Fields: 0..2 q^n (the advecting velocity; the predictor's
+// advanced field too), the corrector's half-step average (q~ + q^n) / 2
+// (3..5), p (last).  The predictor stores that average, formed exactly as the
+// per-cell corrector forms it, instead of q~ (which nothing else reads): the
+// corrector then reads seven fields, not nine.  Periodic.
+template <int STAGE, int X, int TY>
+__global__ __launch_bounds__(X * TY) __attribute__((amdgpu_waves_per_eu(STAGE == 0 ? 4 : 1))) void k_mom_stage3r(
+    Vel qn, Vel qa, double *__restrict__ o0, double *__restrict__ o1, double *__restrict__ o2,
+    const double *__restrict__ p, int n, int zc, double dt, double nu, double h) {
+    constexpr int NF = STAGE == 0 ? 4 : 7, FP = NF - 1;
+    typedef ZRing2<NF, X, TY> Ring;
+    __shared__ typename Ring::Plane pl[NF];
+    const Ring R(n, zc);
+    const int zc0 = R.z0, zc1 = R.z1;
+    auto ld = [&](int f, int64_t q) -> double {
+        if (f < 3) return qn.q[f][q];
+        if (STAGE == 1 && f < 6) return qa.q[f - 3][q];
+        return p[q];
+    };
+    const int i = R.x0 + R.tx, j = R.y0 + R.ty;
+    const bool act = i < n && j < n;
+    const int64_t col = int64_t(min(j, n - 1)) * n + min(i, n - 1);
+    const double inv_2h = 0.5 / h, nu_inv_h2 = nu / (h * h), inv_h = 1.0 / h;
+    double *out[3] = {o0, o1, o2};
+    // Two planes of every field in flight (parity-named register sets, so the
+    // wait before a store leaves the other set's loads outstanding), and the own
+    // column's out-of-ring z-neighbours in registers: plane z - 1 of the
+    // mom_lo = 0 fields (prev), plane z + 1 of the z velocity (the predictor
+    // reads it: its advanced field is q^n itself), prefetched two steps ahead.
+    typename Ring::Regs sa, sb;
+    double prev[NF], wa = 0.0, wb = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        R.load(ld, sa, f, zc0 + mom_lo(f));
+        prev[f] = mom_lo(f) == 0 ? ld(f, R.plane(zc0 - 1) + col) : 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) R.store(pl[f], sa, f, zc0 + mom_lo(f));
+    // issued in the order the loop issues them (set a, then set b), so that the
+    // loop's waits leave the second set in flight
+#pragma unroll
+    for (int f = 0; f < NF; ++f) R.load(ld, sa, f, zc0 + 1 + mom_lo(f));
+    if (STAGE == 0) wa = ld(2, R.plane(zc0 + 1) + col);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) R.load(ld, sb, f, zc0 + 2 + mom_lo(f));
+    if (STAGE == 0) wb = ld(2, R.plane(zc0 + 2) + col);
+    // plane z: the set sv holds planes z + 1 + mom_lo, w the z velocity's own plane z + 1.
+    // The loads two steps ahead are unconditional (no branch for the wait counts to
+    // merge over): past the chunk's end they repeat plane z1 + mom_lo.
+    // The z velocity's own plane z + 1 passes through LDS (the thread's own word), so
+    // that its register is free before the next load into it: kept in a register
+    // while that load is in flight, it costs a copy at the loop's back edge and
+    // with it a wait for every load.
+    __shared__ double wst[STAGE == 0 ? TY : 1][X];
+    auto step = [&](int z, typename Ring::Regs &sv, double &w) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) R.store(pl[f], sv, f, z + 1 + mom_lo(f));
+        if (STAGE == 0) wst[R.ty][R.tx] = w;
+        __syncthreads();
+        const double wz = STAGE == 0 ? wst[R.ty][R.tx] : 0.0;
+        const int za = min(z + 3, zc1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) R.load(ld, sv, f, za + mom_lo(f));
+        if (STAGE == 0) w = ld(2, R.plane(za) + col);
+        if (act) {
+            auto at = [&](int f, int dx, int dy, int dz) -> double {
+                if (dz == -1 && mom_lo(f) == 0) return prev[f];  // own column only
+                if (dz == 1 && mom_lo(f) == -1) return wz;       // own column only (the z velocity)
+                return pl[f][(z + dz) & 1][R.ty + 1 + dy][R.tx + 1 + dx];
+            };
+            const int64_t c = int64_t(z) * R.P + int64_t(j) * n + i;
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+                const int fin = STAGE == 0 ? comp : 3 + comp;
+                const int cx = comp == 0, cy = comp == 1, cz = comp == 2;  // e_c
+                const double qc = at(fin, 0, 0, 0);
+                double adv = 0.0, lap = -2.0 * 3 * qc;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const int ex = e == 0, ey = e == 1, ez = e == 2;
+                    const double qp = at(fin, ex, ey, ez), qm = at(fin, -ex, -ey, -ez);
+                    double ae;
+                    if (e == comp) {
+                        ae = at(e, 0, 0, 0);
+                    } else {
+                        ae = 0.25 * (at(e, 0, 0, 0) + at(e, cx, cy, cz) + at(e, -ex, -ey, -ez) +
+                                     at(e, cx - ex, cy - ey, cz - ez));
+                    }
+                    adv += ae * (qp - qm) * inv_2h;
+                    lap += qp + qm;
+                }
+                const double F = adv - nu_inv_h2 * lap + (at(FP, cx, cy, cz) - at(FP, 0, 0, 0)) * inv_h;
+                const double qs = at(comp, 0, 0, 0) - dt * F;
+                out[comp][c] = STAGE == 0 ? 0.5 * (qs + at(comp, 0, 0, 0)) : qs;
+            }
+        }
+        // the own values of plane z are plane z - 1 of the next step
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (mom_lo(f) == 0) prev[f] = pl[f][z & 1][R.ty + 1][R.tx + 1];
+        __syncthreads();
+    };
+    // chunks of an even number of planes; the first pair outside the loop, so that the
+    // loop's waits never see the prologue's own-column loads (issued last) as pending
+    step(zc0, sa, wa);
+    step(zc0 + 1, sb, wb);
+    for (int z = zc0 + 2; z < zc1; z += 2) {
+        step(z, sa, wa);
+        step(z + 1, sb, wb);
+    }
+}
+
+// planes per workgroup of a two-plane-ring momentum launch: the most (up to 32)
+// that still gives 1024 workgroups; even
+inline int mom_planes(int n, int x, int ty) {
+    const int64_t tiles = int64_t((n + x - 1) / x) * ((n + ty - 1) / ty);
+    int zc = 32;
+    while (zc > 2 && tiles * ((n + zc - 1) / zc) < 1024) zc >>= 1;
+    return min(zc, n);
+}
+
+inline unsigned mom_grid(int n, int x, int ty, int zc) {
+    return unsigned(((n + x - 1) / x) * ((n + ty - 1) / ty) * ((n + zc - 1) / zc));
+}
+
 inline int adx_planes(int n, int ty) {
     const int64_t tiles = int64_t((n + kZx - 1) / kZx) * ((n + ty - 1) / ty);
     int zc = 32;
@@ -855,18 +1046,35 @@ static np_status ns_step_impl(int lg, double h, double *u, double *v, double *w,
     const unsigned nb = blocks_for(m);
     const int n = 1 << lg;
     if (D == 3 && n >= 32 && g_zmarch_explicit) {
-        // z-marching tiles: 8 tile rows for the predictor's four fields, 4 for the corrector's seven (LDS)
-        const int z8 = adx_planes(n, 8), z4 = adx_planes(n, 4);
-        hipLaunchKernelGGL((k_mom_stage3z<0, 8>), dim3(zgrid(n, 8, z8)), dim3(kZx * 8), 0, s, qn, vt, qt[0], qt[1],
-                           qt[2], p, n, z8, dt, nu, h);
-        NP_LAUNCH_CHECK();
-        if (g_mom_rows == 8)
-            hipLaunchKernelGGL((k_mom_stage3z<1, 8>), dim3(zgrid(n, 8, z8)), dim3(kZx * 8), 0, s, qn, vt, qs[0],
-                               qs[1], qs[2], p, n, z8, dt, nu, h);
-        else
-            hipLaunchKernelGGL((k_mom_stage3z<1, 4>), dim3(zgrid(n, 4, z4)), dim3(kZx * 4), 0, s, qn, vt, qs[0],
-                               qs[1], qs[2], p, n, z4, dt, nu, h);
-        NP_LAUNCH_CHECK();
+        if (g_mom_ring == 2) {
+            // two-plane rings: the predictor on 128 x 4 tiles (it stores the half-step average), the
+            // corrector on 64 x 4 (or 64 x 8) tiles
+            const int zp = mom_planes(n, 128, 4);
+            hipLaunchKernelGGL((k_mom_stage3r<0, 128, 4>), dim3(mom_grid(n, 128, 4, zp)), dim3(512), 0, s, qn, vt,
+                               qt[0], qt[1], qt[2], p, n, zp, dt, nu, h);
+            NP_LAUNCH_CHECK();
+            const int ty = g_mom_rows, zq = mom_planes(n, 64, ty);
+            if (ty == 8)
+                hipLaunchKernelGGL((k_mom_stage3r<1, 64, 8>), dim3(mom_grid(n, 64, 8, zq)), dim3(512), 0, s, qn, vt,
+                                   qs[0], qs[1], qs[2], p, n, zq, dt, nu, h);
+            else
+                hipLaunchKernelGGL((k_mom_stage3r<1, 64, 4>), dim3(mom_grid(n, 64, 4, zq)), dim3(256), 0, s, qn, vt,
+                                   qs[0], qs[1], qs[2], p, n, zq, dt, nu, h);
+            NP_LAUNCH_CHECK();
+        } else {
+            // three-plane rings: 8 tile rows for the predictor's four fields, 4 (or 8) for the corrector's seven
+            const int z8 = adx_planes(n, 8), z4 = adx_planes(n, 4);
+            hipLaunchKernelGGL((k_mom_stage3z<0, 8>), dim3(zgrid(n, 8, z8)), dim3(kZx * 8), 0, s, qn, vt, qt[0],
+                               qt[1], qt[2], p, n, z8, dt, nu, h);
+            NP_LAUNCH_CHECK();
+            if (g_mom_rows == 8)
+                hipLaunchKernelGGL((k_mom_stage3z<1, 8>), dim3(zgrid(n, 8, z8)), dim3(kZx * 8), 0, s, qn, vt, qs[0],
+                                   qs[1], qs[2], p, n, z8, dt, nu, h);
+            else
+                hipLaunchKernelGGL((k_mom_stage3z<1, 4>), dim3(zgrid(n, 4, z4)), dim3(kZx * 4), 0, s, qn, vt, qs[0],
+                                   qs[1], qs[2], p, n, z4, dt, nu, h);
+            NP_LAUNCH_CHECK();
+        }
     } else {
         hipLaunchKernelGGL((k_mom_stage<D, 0>), dim3(nb), dim3(kBlock), 0, s, qn, vt, qt[0], qt[1], qt[2], p, lg, dt,
                            nu, h);

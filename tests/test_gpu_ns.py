@@ -99,27 +99,33 @@ def test_projection_step_parity_3d_256(B, orc):
     assert max(errs) < 1e-12
 
 
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("n", [32, 64, 128])
 def test_projection_step_zmarch_matches_per_cell(B, n):
     """The staggered momentum stages on z-marching tiles (LDS rings of the advecting
-    velocity, the advanced field and p) against the one-cell-per-thread kernels: the
-    same terms in the same order, so the whole step agrees bit for bit."""
+    velocity, the advanced field and p; three planes per field, or two with the
+    out-of-ring z-neighbours of the own column in registers; 4 or 8 corrector tile
+    rows) against the one-cell-per-thread kernels: the same terms in the same order,
+    so the whole step agrees bit for bit."""
     import torch
     g = inputs.divfree_velocity(3, n, seed=7)
     rng = np.random.default_rng(8)
     p0 = 0.1 * rng.standard_normal((n,) * 3)
+    configs = [(0, 2, 4), (1, 2, 4), (1, 2, 8), (1, 3, 4), (1, 3, 8)]  # zmarch, ring planes, corrector rows
     out = {}
     try:
-        for v in (1, 0):
-            B.np_set_tuning("zmarch_explicit", v)
+        for cfg in configs:
+            for key, v in zip(("zmarch_explicit", "mom_ring", "mom_rows"), cfg):
+                B.np_set_tuning(key, v)
             q = [dev(c) for c in g["q"]]
             pg = dev(p0)
             B.ns_projection_step(q[0], q[1], q[2], pg, g["h"], g["dt"], 1e-3, fixed_cycles=3)
-            out[v] = [host(t) for t in q] + [host(pg)]
+            out[cfg] = [host(t) for t in q] + [host(pg)]
     finally:
-        B.np_set_tuning("zmarch_explicit", 1)
-    for a, b in zip(out[1], out[0]):
-        assert np.array_equal(a, b), rel(a, b)
+        for key, v in (("zmarch_explicit", 1), ("mom_ring", 2), ("mom_rows", 4)):
+            B.np_set_tuning(key, v)
+    for cfg in configs[1:]:
+        for a, b in zip(out[cfg], out[configs[0]]):
+            assert np.array_equal(a, b), (cfg, rel(a, b))
 
 
 def test_projection_step_many_steps_drift(B, orc):
