@@ -103,7 +103,10 @@ def kernel_source_hash(kind):
     fname, first, after = KERNEL_SOURCES[kind]
     src = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", fname)).read()
     body = src[src.index(first):src.index(after, src.index(first))]
-    return hashlib.sha256(body.encode()).hexdigest()[:16]
+    # the z-marching tile shape (cells per thread) that every one of these kernels takes
+    lvl = open(os.path.join(ROOT, "paper_2402_17913_amd", "csrc", "mg_level.h")).read()
+    cfg = lvl[lvl.index("template <class S> struct ZCfg {"):lvl.index("};", lvl.index("template <class S> struct ZCfg {"))]
+    return hashlib.sha256((cfg + body).encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, head):
@@ -672,7 +675,7 @@ def main():
                       (" (%s correction and residual, %s per thread)" % (
                           head.upper(), "two cells" if B.np_get_tuning("ir_cpt") == 2 else "one cell")
                        if dom == "refine" else
-                       {"fp32": " (FP32 storage)", "bf16": " (BF16 storage, two cells per thread)"}[head]),
+                       {"fp32": " (FP32 storage, two cells per thread)", "bf16": " (BF16 storage, two cells per thread)"}[head]),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -2184,9 +2184,12 @@ static np_status ad_launch_restrict(const double *f, const double *x, double *fc
 template <int D>
 static np_status ad_launch_prolong(const double *ec, double *x, int lg, int bc, hipStream_t s, const int *stop) {
     if (ad_zm3<D>(lg)) {
-        const int zc = sweep3_planes(lg, 1, kPartials);
-        hipLaunchKernelGGL((k_prolong3<double>), dim3(zblocks(lg, 1, zc)), dim3(kS3Threads), 0, s, ec, x, lg, bc, zc,
-                           stop);
+        // the solver's prolongation kernel: its tiles take ZCfg's cells per thread (the
+        // advection-diffusion sweep and restriction above take one)
+        constexpr int CPT = ZCfg<double>::CPT;
+        const int zc = sweep3_planes(lg, CPT, kPartials);
+        hipLaunchKernelGGL((k_prolong3<double>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, ec, x, lg, bc,
+                           zc, stop);
     } else {
         hipLaunchKernelGGL((k_prolong_add<D, double>), dim3(blocks_for(cells(D, lg))), dim3(kBlock), 0, s, ec, x,
                            lg - 1, bc, stop);

@@ -127,10 +127,14 @@ template <> struct Pair<bf16> {  // element 0 in the low half (little endian)
     }
 };
 
-// Tile shape of the z-marching kernels for storage S.
+// Tile shape of the z-marching kernels for storage S: two cells per thread
+// along x in every precision (paired accesses of 4, 8 or 16 bytes).  The
+// one-pass level kernels gained most: at 256^3 the up-leg FP64 109 -> 93 us,
+// FP32 54 -> 47 us, the zero-start down-leg FP64 91 -> 74 us, FP32 56 -> 48 us
+// against one cell per thread.
 template <class S> struct ZCfg {
-    static constexpr int TX = 128;                     // cells per tile row
-    static constexpr int CPT = sizeof(S) == 2 ? 2 : 1;  // cells per thread along x
+    static constexpr int TX = 128;  // cells per tile row
+    static constexpr int CPT = 2;   // cells per thread along x
 };
 
 template <class C, int TX, int CPT>

@@ -752,7 +752,7 @@ def test_down2z_matches_per_kernel_path(B, prec, n, bc):
     """The one-pass down-leg of a nonzero iterate (k_down2z: both pre-sweeps, the
     residual and the restriction, one cell per thread) against the two-sweep pass then
     k_restrict3: iterate and coarse right-hand side bit for bit (children summed in
-    k_restrict3's order for the storage, two cells per thread in BF16)."""
+    k_restrict3's order: two cells per thread, the x-pair first)."""
     import torch
     say("down2z", prec, n, bc)
     h = 1.0 / n
