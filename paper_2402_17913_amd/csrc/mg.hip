@@ -139,7 +139,8 @@ constexpr unsigned kNormBlocks = 2048;  // workgroups of a sweep that also reduc
 
 struct GraphKey {
     int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles; 5 sawtooth;
-               // advection-diffusion: 6 V-cycle, 7 sawtooth
+               // advection-diffusion: 6 V-cycle, 7 sawtooth; mixed from a zero iterate x does not hold:
+               // 8 first check, 9 first update
     int zero0, check;
     const void *x, *f;
     double h;
@@ -1281,8 +1282,12 @@ static np_status solve_saw(Hier *H, const double *f, double *x, double h, double
 }
 
 template <int D, class SL>
+// part0 (np0 partials of |f|^2, with f already rounded into the low-precision
+// right-hand side): the solve starts from a zero iterate that x does not hold --
+// the first check reads those partials, and the first update reads no iterate.
 static np_status solve_mixed(Hier *H, const double *f, double *x, double h, double tol, const np_mg_opts &o,
-                             const CycleOpts &co, hipStream_t s, double nf, bool warm, np_mg_stats *stats) {
+                             const CycleOpts &co, hipStream_t s, double nf, bool warm, np_mg_stats *stats,
+                             const double *part0 = nullptr, int np0 = 0) {
     typedef Ops<D, SL> O;
     NP_TRY(ensure_levels(H));
     const int64_t m = cells(D, H->lg);
@@ -1290,8 +1295,19 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
                                          : (H->prec == NP_BF16 ? g_tune.inner_bf16 : g_tune.inner_fp32);
     SL *e = (SL *)H->x[0], *rlo = (SL *)H->f[0], *tt = (SL *)H->t[0];
     double *xa = x, *xb = H->x64;
+    const bool zm = D == 3 && H->lg >= 7 && g_tune.sweep3;  // z-marching refinement kernel
+    const int icpt = g_tune.ir_cpt;                           // its cells per thread (1 or 2)
+    const bool cold = part0 && zm && icpt == 2;               // zero iterate, not held in x
+    if (part0 && !cold) {  // the kernels below read the zero iterate from x
+        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
+        NP_LAUNCH_CHECK();
+    }
     np_status st0;
     if (!warm && stop_before_first(o, tol, &st0)) {
+        if (cold) {  // the result is the zero iterate
+            hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
+            NP_LAUNCH_CHECK();
+        }
         Ctl c{};
         c.nhist = 1;
         c.hist[0] = 1.0;
@@ -1299,18 +1315,20 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         return st0;
     }
     NP_TRY(init_ctl(H, o, nf, tol, 0, 0.0, s));
-    const bool zm = D == 3 && H->lg >= 7 && g_tune.sweep3;  // z-marching refinement kernel
-    const int icpt = g_tune.ir_cpt;                           // its cells per thread (1 or 2)
     const int zc = zm ? sweep3_planes(H->lg, icpt, kPartials) : 0;
     const unsigned nb = zm ? zblocks(H->lg, icpt, zc)
                            : unsigned(std::min<int64_t>((m + kIrCells - 1) / kIrCells, kPartials));
     const int *stop = &H->ctl->stop;
-    // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles
-    auto step = [&](hipStream_t q, const double *xin, double *xout, int has_e) -> np_status {
+    // one refinement step: x_out = x_in + e (step > 0), r = f - A x_out, check, inner cycles;
+    // xz: x_in is zero and not read
+    auto step = [&](hipStream_t q, const double *xin, double *xout, int has_e, bool xz = false) -> np_status {
         void *tok = nullptr;
         const bool prof = prof_on() & kProfRefine;
         if (prof) NP_TRY(prof_begin(q, &tok));
-        if (zm && has_e && icpt == 2)
+        if (xz)
+            hipLaunchKernelGGL((k_ir_resid3<SL, true, 2, true>), dim3(nb), dim3(kS3Threads), 0, q, nullptr, e, xout,
+                               f, rlo, H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
+        else if (zm && has_e && icpt == 2)
             hipLaunchKernelGGL((k_ir_resid3<SL, true, 2>), dim3(nb), dim3(kS3Threads), 0, q, xin, e, xout, f, rlo,
                                H->red, H->lg, H->bc, zc, 1.0 / (h * h), stop);
         else if (zm && icpt == 2)
@@ -1326,7 +1344,9 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
             hipLaunchKernelGGL((k_ir_resid<D, SL>), dim3(nb), dim3(kBlock), 0, q, xin, e, xout, f, rlo, H->red,
                                H->lg, H->bc, 1.0 / (h * h), has_e, stop);
         NP_LAUNCH_CHECK();
-        if (prof) NP_TRY(prof_end(q, tok, double(m) * (has_e ? 8 + sizeof(SL) + 8 + 8 + sizeof(SL) : 8 + 8 + sizeof(SL))));
+        if (prof)
+            NP_TRY(prof_end(q, tok, double(m) * (has_e ? (xz ? 0 : 8) + sizeof(SL) + 8 + 8 + sizeof(SL)
+                                                        : 8 + 8 + sizeof(SL))));
         hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, q, H->red, int(nb), H->ctl);
         NP_LAUNCH_CHECK();
         return NP_OK;
@@ -1339,17 +1359,29 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
     // graphs: the first update (x = x0), the updates a -> b and b -> a, the inner cycles;
     // every batch ends with an update and its check, so that a converged solve
     // enqueues no further cycles
-    GraphKey k1{1, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    GraphKey k1{cold ? 8 : 1, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     GraphKey ka{2, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     GraphKey kb{3, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     GraphKey kc{4, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
-    NP_TRY(run_graph(H, k1, s, [&](hipStream_t q) { return step(q, xa, nullptr, 0); }));
+    GraphKey k0a{9, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    if (cold) {
+        // r = f is already rounded into r_lo; its check reads the norm's partials
+        NP_TRY(run_graph(H, k1, s, [&](hipStream_t q) -> np_status {
+            hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, q, part0, np0, H->ctl);
+            NP_LAUNCH_CHECK();
+            return NP_OK;
+        }));
+    } else {
+        NP_TRY(run_graph(H, k1, s, [&](hipStream_t q) { return step(q, xa, nullptr, 0); }));
+    }
     int launched = 1;
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles : std::max(1, g_tune.batch / 2);
     for (;;) {
         for (int b = 0; b < batch; ++b, ++launched) {
             NP_TRY(run_graph(H, kc, s, cycles));
-            if (launched & 1)
+            if (launched == 1 && cold)
+                NP_TRY(run_graph(H, k0a, s, [&](hipStream_t q) { return step(q, nullptr, xb, 1, true); }));
+            else if (launched & 1)
                 NP_TRY(run_graph(H, ka, s, [&](hipStream_t q) { return step(q, xa, xb, 1); }));
             else
                 NP_TRY(run_graph(H, kb, s, [&](hipStream_t q) { return step(q, xb, xa, 1); }));
@@ -1359,6 +1391,11 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         batch = next_batch(*H->hctl, o, true);
     }
     const Ctl c = *H->hctl;
+    // stopped at the first check: x never received an update, and the iterate is zero
+    if (cold && c.k == 0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
+        NP_LAUNCH_CHECK();
+    }
     // the iterate whose residual was checked last: x_a after an even number of updates
     if (c.k & 1) NP_HIP_TRY(hipMemcpyAsync(x, xb, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
     fill_stats(stats, c, c.k * inner, c.k);
@@ -1572,7 +1609,26 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
         NP_TRY(remove_mean(H, H->f64, m, s));
         f = H->f64;
     }
-    NP_TRY(dsum(H, f, m, 1, 0, s));
+    // The 3D mixed solve from a zero iterate on z-marching levels (n >= 128): its first
+    // residual is f itself, so the norm's pass also rounds f into the low-precision
+    // right-hand side, the first check reads the norm's partials, and x is not
+    // zeroed (the first update writes it).
+    const bool cold = HL && o.warm_start == 0 && o.cycle == 0 && d == 3 && lg >= 7 && g_tune.sweep3 &&
+                      g_tune.ir_cpt == 2;
+    unsigned np0 = 0;
+    if (cold) {
+        NP_TRY(ensure_levels(HL));
+        np0 = std::min<unsigned>(kRedBlocks, blocks_for(m));
+        if (o.smooth_prec == NP_FP32)
+            hipLaunchKernelGGL((k_sum_round<float>), dim3(np0), dim3(kBlock), 0, s, f, m, (float *)HL->f[0], H->red);
+        else
+            hipLaunchKernelGGL((k_sum_round<bf16>), dim3(np0), dim3(kBlock), 0, s, f, m, (bf16 *)HL->f[0], H->red);
+        NP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, H->red, int(np0), H->red + kPartials, 1);
+        NP_LAUNCH_CHECK();
+    } else {
+        NP_TRY(dsum(H, f, m, 1, 0, s));
+    }
     NP_TRY(read_scalars(H, 1, s));
     const double nf = H->hred[0];
     if (!std::isfinite(nf)) {
@@ -1580,7 +1636,7 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
         return NP_ENAN;
     }
     bool warm = o.warm_start == 2;
-    if (nf == 0.0 || !warm) {
+    if (nf == 0.0 || (!warm && !cold)) {
         hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(m)), dim3(kBlock), 0, s, x, m, nullptr);
         NP_LAUNCH_CHECK();
     }
@@ -1625,10 +1681,12 @@ np_status poisson_solve(np_dims dims, double h, np_bc bc, const double *rhs, dou
                     : solve_fp64<3>(H, f, x, h, tol, o, co, s, !warm, nf, stats);
     } else if (o.smooth_prec == NP_FP32) {
         st = d == 2 ? solve_mixed<2, float>(HL, f, x, h, tol, o, co, s, nf, warm, stats)
-                    : solve_mixed<3, float>(HL, f, x, h, tol, o, co, s, nf, warm, stats);
+                    : solve_mixed<3, float>(HL, f, x, h, tol, o, co, s, nf, warm, stats, cold ? H->red : nullptr,
+                                            int(np0));
     } else {
         st = d == 2 ? solve_mixed<2, bf16>(HL, f, x, h, tol, o, co, s, nf, warm, stats)
-                    : solve_mixed<3, bf16>(HL, f, x, h, tol, o, co, s, nf, warm, stats);
+                    : solve_mixed<3, bf16>(HL, f, x, h, tol, o, co, s, nf, warm, stats, cold ? H->red : nullptr,
+                                           int(np0));
     }
     if (st == NP_EHIP || st == NP_ENOMEM || st == NP_EINVAL) return st;
     if (stats) stats->used_fallback = fallback;

@@ -280,6 +280,24 @@ __global__ __launch_bounds__(kBlock) void k_sum(const S *__restrict__ v, int64_t
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
+// k_sum's squared-norm partials of an FP64 field (the same order) and the field
+// rounded to the storage S: the mixed solve's first residual r = f, and its
+// check, when the iterate starts at zero.
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_sum_round(const double *__restrict__ v, int64_t m,
+                                                      S *__restrict__ lo, double *__restrict__ partial) {
+    typedef typename St<S>::C C;
+    double acc = 0.0;
+    for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < m;
+         c += int64_t(gridDim.x) * blockDim.x) {
+        const double a = v[c];
+        acc += a * a;
+        St<S>::st(lo + c, C(a));
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
 // out[slot] = sum of partial[0..np) in a fixed order (sqrt when root).
 static __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int np,
                                                      double *__restrict__ out, int root) {

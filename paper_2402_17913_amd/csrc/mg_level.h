@@ -383,8 +383,9 @@ __global__ __launch_bounds__(kS3Threads) void k_restrict3(const S *__restrict__ 
 // k_ir_resid): x_out = x + e (HAS_E; else x_out is not written and e is not
 // read), r = f - A x_out in FP64, r_lo = r rounded, per-workgroup partial of
 // r^2.  CPT cells per thread along x: 1, or 2 (16-byte FP64 and paired
-// low-precision accesses; the same arithmetic per cell).
-template <class SL, bool HAS_E, int CPT = 1>
+// low-precision accesses; the same arithmetic per cell).  XZ: x is zero and
+// not read (x_out = 0 + e, the first update of a solve from a zero iterate).
+template <class SL, bool HAS_E, int CPT = 1, bool XZ = false>
 __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restrict__ x, const SL *__restrict__ e,
                                                           double *__restrict__ xout, const double *__restrict__ f,
                                                           SL *__restrict__ rlo, double *__restrict__ partial,
@@ -399,10 +400,12 @@ __global__ __launch_bounds__(kS3Threads) void k_ir_resid3(const double *__restri
         const double *x;
         const SL *e;
         __device__ __forceinline__ double operator()(int64_t q) const {
-            return HAS_E ? x[q] + double(St<SL>::ld(e + q)) : x[q];
+            const double xq = XZ ? 0.0 : x[q];
+            return HAS_E ? xq + double(St<SL>::ld(e + q)) : xq;
         }
         __device__ __forceinline__ void pair(int64_t q, double &a, double &b) const {
-            Pair<double>::ld(x + q, a, b);
+            if (XZ) a = b = 0.0;
+            else Pair<double>::ld(x + q, a, b);
             if (HAS_E) {
                 CL ea, eb;
                 Pair<SL>::ld(e + q, ea, eb);

@@ -218,6 +218,42 @@ def test_refinement_two_cells_per_thread_bit_identical(B, orc, bc):
 
 
 @pytest.mark.parametrize("bc", [DIR, PER])
+def test_mixed_zero_start_reads_no_iterate(B, orc, bc):
+    """A 3D mixed solve from a zero guess (z-marching levels) never reads the caller's x:
+    its first residual is f, rounded in the norm's pass, and its first update writes
+    x = 0 + e.  From an x full of NaNs it gives the solve of the path that zeroes x first
+    (the one-cell refinement kernel) bit for bit, with the same counts; a solve stopped
+    before any cycle (max_cycles 0, or tol >= 1) returns the zero iterate."""
+    n = 128
+    rng = np.random.default_rng(613 + bc)
+    f = rng.standard_normal((n, n, n))
+    if bc == PER:
+        f -= f.mean()
+    h = 1.0 / n
+    nan = np.full_like(f, np.nan)
+    out = {}
+    try:
+        for v in (1, 2):
+            B.np_set_tuning("ir_cpt", v)
+            for prec in (B.FP32, B.BF16):
+                say("zero start", v, bc, prec)
+                xg = dev(nan)
+                st, stats = B.mg_poisson_solve(dev(f), xg, h, bc, smooth_prec=prec)
+                out[(v, prec)] = (host(xg), stats["cycles"], stats["outer_iters"])
+    finally:
+        B.np_set_tuning("ir_cpt", 2)
+    for prec in (B.FP32, B.BF16):
+        a, b = out[(1, prec)], out[(2, prec)]
+        assert a[1:] == b[1:], prec
+        assert np.array_equal(a[0], b[0]), prec
+        assert orc.rel_res(f, b[0], h, bc) <= 1e-10
+        for kw in (dict(max_cycles=0), dict(tol=1.0)):
+            xg = dev(nan)
+            B.mg_poisson_solve(dev(f), xg, h, bc, smooth_prec=prec, check=False, **kw)
+            assert np.array_equal(host(xg), np.zeros_like(f)), (prec, kw)
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
 def test_prof_level_runs_the_solver_kernels(B, orc, bc):
     """The timing hook launches the solver's level kernels (FP64, 128^3, the z-marching
     kernels): the sweep's output is one oracle Jacobi sweep, the restriction's is the
