@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "mg_fused.h"
+#include "mg_block2.h"
 #include "mg_fused3.h"
 #include "mg_zfused.h"
 #include "mg_level.h"
@@ -125,6 +126,7 @@ struct Tuning {
     int down2z = 1;       // FP32/FP64 down-leg of a nonzero iterate with its restriction in that pass
     int fuseb = 1;        // temporally blocked down-leg (from zero) and up-leg block kernels on small 3D levels
     int fbmax = 6;        // largest such level (log2 cells per axis)
+    int blk2 = 1;         // 2D levels of 128^2 .. 1024^2: one block kernel per leg (64 x 16 cells per workgroup)
 };
 static Tuning g_tune;
 int g_zc3 = 0;
@@ -672,6 +674,28 @@ template <int D, class S> struct Ops {
         }
     }
 
+    // 2D levels of 128^2 .. 1024^2 above the tail: one block kernel per leg (k_lvl2_b: MODE 0 the
+    // down-leg from zero, 1 the down-leg of an iterate, 2 the up-leg), 64 x 16 cells per workgroup.
+    static bool blk2_on(int lg) { return D == 2 && g_tune.blk2 && lg >= 7 && lg <= 10 && lg > Tail<2>::LG; }
+    template <int MODE, bool NORM>
+    static np_status lvl2b(const S *ec, const S *f, const S *xin, S *xout, S *fc, double *partial, int *np, int lg,
+                           int bc, double h, double omega, hipStream_t s, const int *stop) {
+        if constexpr (D == 2) {
+            const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
+            const int n = 1 << lg;
+            const unsigned nb = unsigned((n / B2<S>::BX) * (n / B2<S>::BY));
+            hipLaunchKernelGGL((k_lvl2_b<S, MODE, NORM>), dim3(nb), dim3(B2<S>::NT), 0, s, ec, f, xin, xout, fc,
+                               partial, lg, bc, inv_h2, wdiag, stop);
+            NP_LAUNCH_CHECK();
+            if (np) *np = int(nb);
+            return NP_OK;
+        } else {
+            (void)ec; (void)f; (void)xin; (void)xout; (void)fc; (void)partial; (void)np; (void)lg; (void)bc; (void)h;
+            (void)omega; (void)s; (void)stop;
+            return NP_EINVAL;
+        }
+    }
+
     // Whether prolongation + correction and the first post-sweep of a level run as one kernel
     // (2D: every level above the tail; 3D: levels of n >= 32 on the z-marching tiles).
     static bool psweep_on(int lg, int nu2) {
@@ -848,6 +872,29 @@ template <int D, class S> struct Ops {
                 std::swap(cur[l], oth[l]);  // the smoothed iterate is in the partner buffer
                 continue;
             }
+            if (o.nu1 == 2 && blk2_on(lg) && (!zero || g_tune.zero2)) {
+                // 2D: both pre-sweeps, the residual and the restriction in one block kernel; from zero
+                // on level 0 into the partner buffer, so that the one-pass up-leg ends in the caller's x
+                if (zero) {
+                    S *dst = l == 0 ? oth[0] : cur[l];
+                    NP_TRY((lvl2b<0, false>(nullptr, F[l], nullptr, dst, fc, nullptr, nullptr, lg, bc, hl, o.omega, s,
+                                            stop)));
+                    if (l == 0) std::swap(cur[0], oth[0]);
+                } else if (check && l == 0) {
+                    int nb = 0;
+                    NP_TRY((lvl2b<1, true>(nullptr, F[l], cur[l], oth[l], fc, H->red, &nb, lg, bc, hl, o.omega, s,
+                                           stop)));
+                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+                    NP_LAUNCH_CHECK();
+                    std::swap(cur[l], oth[l]);
+                } else {
+                    NP_TRY((lvl2b<1, false>(nullptr, F[l], cur[l], oth[l], fc, nullptr, nullptr, lg, bc, hl, o.omega,
+                                            s, stop)));
+                    std::swap(cur[l], oth[l]);
+                }
+                if (l + 1 == tl) { hl *= 2.0; break; }
+                continue;
+            }
             if (zero && o.nu1 == 2 && g_tune.zero2 && (fuseb_on(lg) || z2_on(lg))) {
                 // both pre-sweeps from zero, the residual and the restriction in one pass; on level 0
                 // into the partner buffer, so that the one-pass up-leg ends in the caller's x
@@ -946,6 +993,11 @@ template <int D, class S> struct Ops {
             // result lands in the caller's x)
             if (o.nu2 == 2 && fuseb_on(lg) && psweep_on(lg, o.nu2) && (l > 0 || cur[0] != x0)) {
                 NP_TRY(up2b(res[l + 1], F[l], cur[l], oth[l], lg, bc, hl, o.omega, s, l == 0, stop));
+                std::swap(cur[l], oth[l]);
+                it = 2;
+            } else if (o.nu2 == 2 && blk2_on(lg) && psweep_on(lg, o.nu2) && (l > 0 || cur[0] != x0)) {
+                NP_TRY((lvl2b<2, false>(res[l + 1], F[l], cur[l], oth[l], nullptr, nullptr, nullptr, lg, bc, hl, o.omega,
+                                        s, stop)));
                 std::swap(cur[l], oth[l]);
                 it = 2;
             } else if (o.nu2 == 2 && z2_on(lg) && psweep_on(lg, o.nu2) && (l > 0 || cur[0] != x0)) {
@@ -1469,7 +1521,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1519,6 +1571,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "fuseb")) return g_tune.fuseb;
     if (!std::strcmp(key, "sweep2z")) return g_tune.sweep2z;
     if (!std::strcmp(key, "down2z")) return g_tune.down2z;
+    if (!std::strcmp(key, "blk2")) return g_tune.blk2;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;

@@ -254,6 +254,43 @@ def test_mixed_zero_start_reads_no_iterate(B, orc, bc):
 
 
 @pytest.mark.parametrize("bc", [DIR, PER])
+@pytest.mark.parametrize("n", [128, 256, 1024])
+def test_blk2_same_solves(B, orc, bc, n):
+    """2D levels of 128^2 .. 1024^2 on one block kernel per leg (knob blk2) against the
+    per-cell kernels: FP64 fixed cycles and FP64, FP32- and BF16-mixed solves to the
+    tolerance give the same iterates bit for bit in the same cycles, within 1e-12 of the
+    oracle's V-cycles (FP64) and meeting the tolerance by its residual."""
+    rng = np.random.default_rng(701 + n + bc)
+    f = rng.standard_normal((n, n))
+    if bc == PER:
+        f -= f.mean()
+    h = 1.0 / n
+    fg = dev(f)
+    out = {}
+    try:
+        for v in (1, 0):
+            B.np_set_tuning("blk2", v)
+            say("blk2", v, n, bc)
+            xg = dev(np.zeros_like(f))
+            B.mg_poisson_solve(fg, xg, h, bc, fixed_cycles=3)
+            out[(v, "fixed")] = host(xg)
+            for p in (B.FP64, B.FP32, B.BF16):
+                xg = dev(np.zeros_like(f))
+                st, stats = B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p)
+                out[(v, p)] = (host(xg), stats["cycles"])
+    finally:
+        B.np_set_tuning("blk2", 1)
+    assert np.array_equal(out[(1, "fixed")], out[(0, "fixed")])
+    for p in (B.FP64, B.FP32, B.BF16):
+        assert out[(1, p)][1] == out[(0, p)][1], p
+        assert np.array_equal(out[(1, p)][0], out[(0, p)][0]), p
+        assert orc.rel_res(f, out[(1, p)][0], h, bc) <= 1e-10
+    if n <= 256:
+        ref = orc.mg_solve(f, h, bc, fixed_cycles=3)
+        assert rel(out[(1, "fixed")], ref.x) < 1e-12
+
+
+@pytest.mark.parametrize("bc", [DIR, PER])
 def test_prof_level_runs_the_solver_kernels(B, orc, bc):
     """The timing hook launches the solver's level kernels (FP64, 128^3, the z-marching
     kernels): the sweep's output is one oracle Jacobi sweep, the restriction's is the
