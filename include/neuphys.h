@@ -465,7 +465,7 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * first post-sweep in one pass: 2D levels above the tail, 3D levels of n >= 32), "ir_cpt" (1 or 2:
  * cells per thread of the 3D refinement kernel), "fuseb" (0/1: temporally blocked block kernels, 8^3 cells per workgroup, on 3D
  * levels from 32^3 to 2^"fbmax" cells per axis -- the down-leg from a zero iterate and the up-leg with two
- * post-sweeps, one pass each; default 1, fbmax 6), "sweep2z" (0/1: two sweeps in one z-marching pass on 3D
+ * post-sweeps, one pass each; default 1, fbmax 6; "fbnt" their threads per workgroup, 512 or 1024, default 1024), "sweep2z" (0/1: two sweeps in one z-marching pass on 3D
  * levels from 128^3 to 1024^3 -- the pre-sweeps of a nonzero iterate, with the convergence check, and the
  * up-leg with prolongation + correction; default 1), "down2z" (0/1: in FP32 and FP64, from 256^3, the
  * residual and the restriction in the down-leg's two-sweep pass too; default 1), "blk2" (0/1: 2D levels of

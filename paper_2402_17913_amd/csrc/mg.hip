@@ -126,6 +126,7 @@ struct Tuning {
     int down2z = 1;       // FP32/FP64 down-leg of a nonzero iterate with its restriction in that pass
     int fuseb = 1;        // temporally blocked down-leg (from zero) and up-leg block kernels on small 3D levels
     int fbmax = 6;        // largest such level (log2 cells per axis)
+    int fbnt = 1024;      // threads per workgroup of those block kernels (512: one per cell, or 1024)
     int blk2 = 1;         // 2D levels of 128^2 .. 1024^2: one block kernel per leg (64 x 16 cells per workgroup)
 };
 static Tuning g_tune;
@@ -539,8 +540,12 @@ template <int D, class S> struct Ops {
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDownZero);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            hipLaunchKernelGGL((k_down0_b<S, 8>), dim3(nb), dim3(BTile<8>::NT), 0, s, f, x, fc, lg, bc, inv_h2, wdiag,
-                               stop);
+            if (g_tune.fbnt == 1024)
+                hipLaunchKernelGGL((k_down0_b<S, 8, 1024>), dim3(nb), dim3(1024), 0, s, f, x, fc, lg, bc, inv_h2, wdiag,
+                                   stop);
+            else
+                hipLaunchKernelGGL((k_down0_b<S, 8>), dim3(nb), dim3(BTile<8>::NT), 0, s, f, x, fc, lg, bc, inv_h2,
+                                   wdiag, stop);
             NP_LAUNCH_CHECK();
             if (prof) {
                 const double m = double(cells(D, lg));
@@ -560,8 +565,12 @@ template <int D, class S> struct Ops {
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfUp);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            hipLaunchKernelGGL((k_up2_b<S, 8>), dim3(nb), dim3(BTile<8>::NT), 0, s, ec, f, x, xout, lg, bc, inv_h2,
-                               wdiag, stop);
+            if (g_tune.fbnt == 1024)
+                hipLaunchKernelGGL((k_up2_b<S, 8, 1024>), dim3(nb), dim3(1024), 0, s, ec, f, x, xout, lg, bc, inv_h2,
+                                   wdiag, stop);
+            else
+                hipLaunchKernelGGL((k_up2_b<S, 8>), dim3(nb), dim3(BTile<8>::NT), 0, s, ec, f, x, xout, lg, bc,
+                                   inv_h2, wdiag, stop);
             NP_LAUNCH_CHECK();
             if (prof) {
                 const double m = double(cells(D, lg));
@@ -1521,7 +1530,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1533,6 +1542,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
                 (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
                 (e.v == &g_mom_rows && value != 4 && value != 8) ||
+                (e.v == &g_tune.fbnt && value != 512 && value != 1024) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
                 return NP_EINVAL;
@@ -1569,6 +1579,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "psweep")) return g_tune.psweep;
     if (!std::strcmp(key, "ir_cpt")) return g_tune.ir_cpt;
     if (!std::strcmp(key, "fuseb")) return g_tune.fuseb;
+    if (!std::strcmp(key, "fbnt")) return g_tune.fbnt;
     if (!std::strcmp(key, "sweep2z")) return g_tune.sweep2z;
     if (!std::strcmp(key, "down2z")) return g_tune.down2z;
     if (!std::strcmp(key, "blk2")) return g_tune.blk2;

@@ -36,9 +36,11 @@ __device__ __forceinline__ int bmap(int g, int n, int bc, int &sgn) {
     return g;
 }
 
-// Block of B^3 cells and its one- and two-cell rings.
-template <int B> struct BTile {
-    static constexpr int NT = B * B * B;
+// Block of B^3 cells and its one- and two-cell rings; NT_ threads (B^3 or more: the ring
+// stages then take fewer passes per thread).
+template <int B, int NT_ = B * B * B> struct BTile {
+    static_assert(NT_ >= B * B * B, "a thread per block cell");
+    static constexpr int NT = NT_;
     static constexpr int W1 = B + 2, R1 = W1 * W1 * W1, W2 = B + 4, R2 = W2 * W2 * W2;
     static constexpr int U1 = (R1 + NT - 1) / NT, U2 = (R2 + NT - 1) / NT;
 };
@@ -78,17 +80,17 @@ __device__ __forceinline__ int eval_pos(int &a, int &b, int &c, int x0, int y0, 
 // one-cell ring from f on a two-cell ring, x2 stored; the residuals of the
 // block's cells; their restriction, summed per coarse cell in the order of
 // k_restrict (z, then y, then x children, from zero).
-template <class S, int B>
-__global__ __launch_bounds__(BTile<B>::NT) void k_down0_b(const S *__restrict__ f, S *__restrict__ xout,
+template <class S, int B, int NTH = B * B * B>
+__global__ __launch_bounds__(NTH) void k_down0_b(const S *__restrict__ f, S *__restrict__ xout,
                                                           S *__restrict__ fc, int lg, int bc,
                                                           typename St<S>::C inv_h2, typename St<S>::C wdiag,
                                                           const int *stop) {
     typedef typename St<S>::C C;
-    typedef BTile<B> T;
+    typedef BTile<B, NTH> T;
     constexpr int NT = T::NT, W1 = T::W1, W2 = T::W2, Q2 = W2 * W2, Q1 = W1 * W1;
-    __shared__ C F[T::R2];  // f, boundary rule applied
-    __shared__ C X[T::R1];  // x2
-    __shared__ C Rr[NT];    // residuals of the block's cells
+    __shared__ C F[T::R2];     // f, boundary rule applied
+    __shared__ C X[T::R1];     // x2
+    __shared__ C Rr[B * B * B];  // residuals of the block's cells
     if (stop && *stop) return;
     const int n = 1 << lg, t = int(threadIdx.x);
     int x0, y0, z0;
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(BTile<B>::NT) void k_down0_b(const S *__restrict__ 
         if (own) St<S>::st(xout + ((int64_t(z0 + c) << lg) + y0 + b) * n + x0 + a, v);
     }
     __syncthreads();
-    {
+    if (t < B * B * B) {
         const int a = t % B, b = (t / B) % B, c = t / (B * B);
         const int q = ((c + 1) * W1 + b + 1) * W1 + a + 1;
         const C xc = X[q];
@@ -155,13 +157,13 @@ __global__ __launch_bounds__(BTile<B>::NT) void k_down0_b(const S *__restrict__ 
 // each position, ghosts from the coarse ghosts, as k_psweep3 does), the first
 // sweep on the block and a one-cell ring (Dirichlet ghosts minus the mirror),
 // the second sweep on the block, stored.
-template <class S, int B>
-__global__ __launch_bounds__(BTile<B>::NT) void k_up2_b(const S *__restrict__ ec, const S *__restrict__ f,
+template <class S, int B, int NTH = B * B * B>
+__global__ __launch_bounds__(NTH) void k_up2_b(const S *__restrict__ ec, const S *__restrict__ f,
                                                         const S *__restrict__ xin, S *__restrict__ xout, int lg,
                                                         int bc, typename St<S>::C inv_h2, typename St<S>::C wdiag,
                                                         const int *stop) {
     typedef typename St<S>::C C;
-    typedef BTile<B> T;
+    typedef BTile<B, NTH> T;
     constexpr int NT = T::NT, W1 = T::W1, W2 = T::W2, Q2 = W2 * W2, Q1 = W1 * W1;
     constexpr int CW = B / 2 + 4, CR = CW * CW * CW;  // coarse cells of the region and their neighbours
     __shared__ C E[CR];
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(BTile<B>::NT) void k_up2_b(const S *__restrict__ ec
         Y[e] = v;
     }
     __syncthreads();
-    {
+    if (t < B * B * B) {
         const int a = t % B, b = (t / B) % B, c = t / (B * B);
         const int64_t g = ((int64_t(z0 + c) << lg) + y0 + b) * n + x0 + a;
         const int q = ((c + 1) * W1 + b + 1) * W1 + a + 1;

@@ -667,19 +667,26 @@ def test_fused3_level_kernels_match_per_kernel_path(B, prec, n, bc):
     ca, cb = torch.zeros_like(c), torch.zeros_like(c)
     B.np_op_level(B.LEVEL_ZERO2, f, xa, None, None, h, bc, prec)
     B.np_op_level(B.LEVEL_RESTRICT, f, xa, None, ca, h, bc, prec)
-    B.np_op_level(B.LEVEL_DOWN0, f, xb, None, cb, h, bc, prec)
-    say("  down x diff %.3e, c diff %.3e" % (rel(as64(xb), as64(xa)), rel(as64(cb), as64(ca))))
-    assert torch.equal(xa, xb)
-    if n < 128:
-        assert torch.equal(ca, cb)
-    else:
-        assert rel(as64(cb), as64(ca)) < {B_FP64: 1e-13, B_FP32: 1e-5, B_BF16: 1e-2}[prec]
     ya, yo = x.clone(), torch.zeros_like(x)
     B.np_op_level(B.LEVEL_PSWEEP_SWEEP, f, ya, yo, c, h, bc, prec)
-    yb = torch.zeros_like(x)
-    B.np_op_level(B.LEVEL_UP2, f, x, yb, c, h, bc, prec)
-    say("  up diff %.3e" % rel(as64(yb), as64(ya)))
-    assert torch.equal(ya, yb)
+    knob = B.np_get_tuning("fbnt")
+    try:
+        for nt in (512, 1024):  # one thread per block cell, or twice as many
+            B.np_set_tuning("fbnt", nt)
+            xb, cb = torch.zeros_like(x), torch.zeros_like(c)
+            B.np_op_level(B.LEVEL_DOWN0, f, xb, None, cb, h, bc, prec)
+            say("  %d down x diff %.3e, c diff %.3e" % (nt, rel(as64(xb), as64(xa)), rel(as64(cb), as64(ca))))
+            assert torch.equal(xa, xb)
+            if n < 128:
+                assert torch.equal(ca, cb)
+            else:
+                assert rel(as64(cb), as64(ca)) < {B_FP64: 1e-13, B_FP32: 1e-5, B_BF16: 1e-2}[prec]
+            yb = torch.zeros_like(x)
+            B.np_op_level(B.LEVEL_UP2, f, x, yb, c, h, bc, prec)
+            say("  %d up diff %.3e" % (nt, rel(as64(yb), as64(ya))))
+            assert torch.equal(ya, yb)
+    finally:
+        B.np_set_tuning("fbnt", knob)
 
 
 @pytest.mark.parametrize("n", [32, 64, 128])
