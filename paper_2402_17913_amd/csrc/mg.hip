@@ -127,6 +127,7 @@ struct Tuning {
     int fuseb = 1;        // temporally blocked down-leg (from zero) and up-leg block kernels on small 3D levels
     int fbmax = 6;        // largest such level (log2 cells per axis)
     int fbnt = 1024;      // threads per workgroup of those block kernels (512: one per cell, or 1024)
+    int z2wg = 1;         // one-pass kernels that fit fewer than four workgroups per CU aim at 512 workgroups
     int blk2 = 1;         // 2D levels of 128^2 .. 1024^2: one block kernel per leg (64 x 16 cells per workgroup)
 };
 static Tuning g_tune;
@@ -595,7 +596,7 @@ template <int D, class S> struct Ops {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
             constexpr int CPT = ZCfg<S>::CPT;
-            const int zc = sweep2z_planes<S>(lg);
+            const int zc = sweep2z_planes<S>(lg, ec && g_tune.z2wg ? 512 : 1024);
             const unsigned nb = zblocks(lg, CPT, zc);
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & (ec ? kProfUp : kProfJacobi));
@@ -630,7 +631,7 @@ template <int D, class S> struct Ops {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
             constexpr int CPT = ZCfg<S>::CPT;
-            const int zc = sweep2z_planes<S>(lg);
+            const int zc = sweep2z_planes<S>(lg, sizeof(S) == 8 && g_tune.z2wg ? 512 : 1024);
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDownZero);
             if (prof) NP_TRY(prof_begin(s, &tok));
@@ -1530,7 +1531,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1583,6 +1584,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "sweep2z")) return g_tune.sweep2z;
     if (!std::strcmp(key, "down2z")) return g_tune.down2z;
     if (!std::strcmp(key, "blk2")) return g_tune.blk2;
+    if (!std::strcmp(key, "z2wg")) return g_tune.z2wg;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;

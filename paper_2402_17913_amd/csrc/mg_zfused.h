@@ -94,18 +94,22 @@ __device__ __forceinline__ int plane_map(int q, int n, int bc, bool &flip) {
 
 // Planes per workgroup of k_sweep2z on an n^3 level: each chunk re-reads a few
 // planes of x and f above and below it, so chunks are as long as still gives
-// four workgroups per CU (1024), and at least four planes (measured: at 128^3
-// BF16, 512 workgroups of four planes beat 1024 of two); the tuning knob
-// "zc3" overrides.
-inline int z2_planes(int lg, int tx, int ty) {
+// `wg` workgroups -- four per CU (1024), or two (512) for the kernels that fit
+// fewer than four per CU (the up-leg in every precision and FP64's zero-start
+// down-leg: at 256^3 one round of two per CU beat a second round at a third of
+// the occupancy) -- and at least four planes (measured: at 128^3 BF16, 512
+// workgroups of four planes beat 1024 of two); the tuning knob "zc3" overrides.
+inline int z2_planes(int lg, int tx, int ty, int wg = 1024) {
     const int n = 1 << lg;
     const int64_t tiles = (int64_t(n) / tx) * (n / ty);
     int zc = 4;
-    while (zc < n && tiles * (n / (2 * zc)) >= 1024) zc *= 2;
+    while (zc < n && tiles * (n / (2 * zc)) >= wg) zc *= 2;
     if (g_zc3 >= 2 && g_zc3 <= n) zc = g_zc3;
     return zc;
 }
-template <class S> inline int sweep2z_planes(int lg) { return z2_planes(lg, Z2Cfg<S>::TX, Z2Cfg<S>::TY); }
+template <class S> inline int sweep2z_planes(int lg, int wg = 1024) {
+    return z2_planes(lg, Z2Cfg<S>::TX, Z2Cfg<S>::TY, wg);
+}
 
 template <class S, bool CORR, bool NORM>
 __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec, const S *__restrict__ f,
