@@ -118,6 +118,7 @@ struct Tuning {
     int inner_fp32 = 3;   // default inner cycles per refinement step
     int inner_bf16 = 2;
     int batch = 4;        // first batch of cycles enqueued before reading the controller
+    int greps = 8;        // most cycles (outer steps) one graph holds: 1, 2, 4 or 8
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
@@ -142,7 +143,7 @@ constexpr int kPartials = 65536;
 constexpr unsigned kNormBlocks = 2048;  // workgroups of a sweep that also reduces the residual norm  // per-workgroup partial sums (fixed order)
 
 struct GraphKey {
-    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 update a->b, 3 update b->a, 4 inner cycles; 5 sawtooth;
+    int kind;  // 0: FP64 cycle; mixed: 1 first update, 2 inner cycles + update (a->b or b->a); 5 sawtooth;
                // advection-diffusion: 6 V-cycle, 7 sawtooth; mixed from a zero iterate x does not hold:
                // 8 first check, 9 first update
     int zero0, check;
@@ -152,10 +153,12 @@ struct GraphKey {
     double omega;
     double ad[5];  // advection-diffusion operator: dt, nu, a[3] (zero otherwise)
     int ad_scheme, ad_l1;
+    int reps, par;  // run_graphs: the repetitions one graph holds, the parity of its first
     bool operator==(const GraphKey &o) const {
         return kind == o.kind && zero0 == o.zero0 && check == o.check && x == o.x && f == o.f && h == o.h &&
                nu1 == o.nu1 && nu2 == o.nu2 && inner == o.inner && omega == o.omega &&
-               std::memcmp(ad, o.ad, sizeof ad) == 0 && ad_scheme == o.ad_scheme && ad_l1 == o.ad_l1;
+               std::memcmp(ad, o.ad, sizeof ad) == 0 && ad_scheme == o.ad_scheme && ad_l1 == o.ad_l1 &&
+               reps == o.reps && par == o.par;
     }
 };
 struct GraphEntry {
@@ -1069,7 +1072,7 @@ static np_status run_graph(Hier *H, const GraphKey &key, hipStream_t s, F enqueu
         set_error("graph instantiation failed: %s", hipGetErrorString(e));
         return NP_EHIP;
     }
-    if (H->graphs.size() >= 12) {  // evict the least recently used
+    if (H->graphs.size() >= 32) {  // evict the least recently used
         size_t v = 0;
         for (size_t i = 1; i < H->graphs.size(); ++i)
             if (H->graphs[i].used < H->graphs[v].used) v = i;
@@ -1081,6 +1084,27 @@ static np_status run_graph(Hier *H, const GraphKey &key, hipStream_t s, F enqueu
     }
     H->graphs.push_back(GraphEntry{key, exec, ++H->tick});
     NP_HIP_TRY(hipGraphLaunch(exec, s));
+    return NP_OK;
+}
+
+// count repetitions of enqueue(q, j), j = j0, j0 + 1, ..., as graphs of 8, 4, 2 and 1 of them
+// (key.reps tells them apart): the stream leaves a gap of several microseconds between
+// consecutive graph launches, which a graph of several cycles pays once.  parity: what
+// enqueue does depends on the parity of j, and key.par holds that of each graph's first j.
+template <class F>
+static np_status run_graphs(Hier *H, GraphKey key, hipStream_t s, int count, int j0, bool parity, F enqueue) {
+    while (count > 0) {
+        const int g = g_tune.greps;
+        const int r = count >= 8 && g >= 8 ? 8 : count >= 4 && g >= 4 ? 4 : count >= 2 && g >= 2 ? 2 : 1;
+        key.reps = r;
+        key.par = parity ? (j0 & 1) : 0;
+        NP_TRY(run_graph(H, key, s, [&](hipStream_t q) -> np_status {
+            for (int i = 0; i < r; ++i) NP_TRY(enqueue(q, j0 + i));
+            return NP_OK;
+        }));
+        count -= r;
+        j0 += r;
+    }
     return NP_OK;
 }
 
@@ -1258,8 +1282,8 @@ static np_status solve_fp64(Hier *H, const double *f, double *x, double h, doubl
     GraphKey key{0, 0, 1, x, f, h, co.nu1, co.nu2, 0, co.omega};
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
     for (;;) {
-        for (int b = 0; b < batch; ++b)
-            NP_TRY(run_graph(H, key, s, [&](hipStream_t q) { return O::cycle(H, x, f, t0, false, true, h, co, q); }));
+        NP_TRY(run_graphs(H, key, s, batch, 0, false,
+                          [&](hipStream_t q, int) { return O::cycle(H, x, f, t0, false, true, h, co, q); }));
         NP_TRY(read_ctl(H, s));
         if (H->hctl->stop) break;
         batch = next_batch(*H->hctl, o, false);
@@ -1332,8 +1356,8 @@ static np_status solve_saw(Hier *H, const double *f, double *x, double h, double
     GraphKey key{5, o.prolong, 1, x, f, h, 0, o.nu2, 0, o.omega};
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
     for (;;) {
-        for (int b = 0; b < batch; ++b)
-            NP_TRY(run_graph(H, key, s, [&](hipStream_t q) { return saw_cycle<D>(H, f, x, h, o, q); }));
+        NP_TRY(run_graphs(H, key, s, batch, 0, false,
+                          [&](hipStream_t q, int) { return saw_cycle<D>(H, f, x, h, o, q); }));
         NP_TRY(read_ctl(H, s));
         if (H->hctl->stop) break;
         batch = next_batch(*H->hctl, o, false);
@@ -1418,14 +1442,17 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
         for (int c = 0; c < inner; ++c) NP_TRY(O::cycle(H, e, rlo, tt, c == 0, false, h, co, q));
         return NP_OK;
     };
-    // graphs: the first update (x = x0), the updates a -> b and b -> a, the inner cycles;
-    // every batch ends with an update and its check, so that a converged solve
-    // enqueues no further cycles
+    // graphs: the first update (x = x0); outer steps j = 1, 2, ...: the inner cycles, then
+    // the update a -> b (j odd) or b -> a (j even), several steps to a graph; every batch
+    // ends with an update and its check, so that a converged solve enqueues no further cycles
     GraphKey k1{cold ? 8 : 1, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
-    GraphKey ka{2, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
-    GraphKey kb{3, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
-    GraphKey kc{4, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    GraphKey ks{2, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
     GraphKey k0a{9, 0, 0, xa, f, h, co.nu1, co.nu2, inner, co.omega};
+    auto outer = [&](hipStream_t q, int j) -> np_status {
+        NP_TRY(cycles(q));
+        if (j == 1 && cold) return step(q, nullptr, xb, 1, true);
+        return (j & 1) ? step(q, xa, xb, 1) : step(q, xb, xa, 1);
+    };
     if (cold) {
         // r = f is already rounded into r_lo; its check reads the norm's partials
         NP_TRY(run_graph(H, k1, s, [&](hipStream_t q) -> np_status {
@@ -1439,15 +1466,14 @@ static np_status solve_mixed(Hier *H, const double *f, double *x, double h, doub
     int launched = 1;
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles : std::max(1, g_tune.batch / 2);
     for (;;) {
-        for (int b = 0; b < batch; ++b, ++launched) {
-            NP_TRY(run_graph(H, kc, s, cycles));
-            if (launched == 1 && cold)
-                NP_TRY(run_graph(H, k0a, s, [&](hipStream_t q) { return step(q, nullptr, xb, 1, true); }));
-            else if (launched & 1)
-                NP_TRY(run_graph(H, ka, s, [&](hipStream_t q) { return step(q, xa, xb, 1); }));
-            else
-                NP_TRY(run_graph(H, kb, s, [&](hipStream_t q) { return step(q, xb, xa, 1); }));
+        int b = batch;
+        if (launched == 1 && cold) {  // the first update, from a zero x, in a graph of its own
+            NP_TRY(run_graphs(H, k0a, s, 1, 1, false, outer));
+            --b;
+            ++launched;
         }
+        NP_TRY(run_graphs(H, ks, s, b, launched, true, outer));
+        launched += b;
         NP_TRY(read_ctl(H, s));
         if (H->hctl->stop) break;
         batch = next_batch(*H->hctl, o, true);
@@ -1531,7 +1557,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1544,6 +1570,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
                 (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
                 (e.v == &g_mom_rows && value != 4 && value != 8) ||
                 (e.v == &g_tune.fbnt && value != 512 && value != 1024) ||
+                (e.v == &g_tune.greps && (value & (value - 1))) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
                 return NP_EINVAL;
@@ -1585,6 +1612,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "down2z")) return g_tune.down2z;
     if (!std::strcmp(key, "blk2")) return g_tune.blk2;
     if (!std::strcmp(key, "z2wg")) return g_tune.z2wg;
+    if (!std::strcmp(key, "greps")) return g_tune.greps;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;
@@ -2501,11 +2529,9 @@ static np_status solve_ad(Hier *H, const np_ad_op &op, const double *f, double *
                  {op.dt, op.nu, op.a[0], op.a[1], op.a[2]}, op.scheme, l1 ? 1 : 0};
     int batch = o.fixed_cycles > 0 ? o.fixed_cycles + 1 : g_tune.batch;
     for (;;) {
-        for (int b = 0; b < batch; ++b)
-            NP_TRY(run_graph(H, key, s, [&](hipStream_t q) {
-                return o.cycle == 1 ? ad_saw_cycle<D>(H, op, f, x, h, o, l1, q)
-                                    : ad_vcycle<D>(H, op, f, x, h, co, l1, q);
-            }));
+        NP_TRY(run_graphs(H, key, s, batch, 0, false, [&](hipStream_t q, int) {
+            return o.cycle == 1 ? ad_saw_cycle<D>(H, op, f, x, h, o, l1, q) : ad_vcycle<D>(H, op, f, x, h, co, l1, q);
+        }));
         NP_TRY(read_ctl(H, s));
         if (H->hctl->stop) break;
         batch = next_batch(*H->hctl, o, false);

@@ -290,6 +290,52 @@ def test_blk2_same_solves(B, orc, bc, n):
         assert rel(out[(1, "fixed")], ref.x) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(128, 128), (64, 64, 64), (256, 256, 256)])
+def test_graph_reps_same_solves(B, orc, shape):
+    """Cycles replayed as graphs of up to 8 (knob greps) against one graph per cycle:
+    FP64 solves to the tolerance and for fixed cycles, FP32- and BF16-mixed solves from a
+    zero and from a nonzero guess, the sawtooth cycle and the advection-diffusion
+    V-cycle give the same iterates and histories bit for bit; the tolerance-stopped
+    results meet the tolerance by the oracle's residual."""
+    n, d = shape[0], len(shape)
+    bc = DIR if d == 3 else PER
+    rng = np.random.default_rng(811 + n + d)
+    f = rng.standard_normal(shape)
+    if bc == PER:
+        f -= f.mean()
+    x0 = 1e-3 * rng.standard_normal(shape)
+    h = 1.0 / n
+    fg = dev(f)
+    op = B.ad_op(1.0, 0.1, [1.0] * d, 0)
+    out = {}
+
+    def run(tag, fn, start):
+        xg = dev(start)
+        _, stats = fn(xg)
+        out[tag] = (host(xg), stats["cycles"], stats["outer_iters"], stats["hist"])
+
+    try:
+        for v in (8, 1):
+            B.np_set_tuning("greps", v)
+            say("greps", v, shape, bc)
+            z = np.zeros_like(f)
+            run((v, "fixed"), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, fixed_cycles=11), z)
+            run((v, "saw"), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, cycle=B.CYCLE_SAWTOOTH, nu1=0,
+                                                          fixed_cycles=6), z)
+            run((v, "ad"), lambda xg: B.np_ad_implicit_solve(fg, xg, 1.0, bc, op), z)
+            for p in (B.FP64, B.FP32, B.BF16):
+                run((v, p, 0), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p), z)
+                run((v, p, 2), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p, warm_start=2), x0)
+    finally:
+        B.np_set_tuning("greps", 8)
+    for k in [key for key in out if key[0] == 8]:
+        a, b = out[k], out[(1,) + k[1:]]
+        assert np.array_equal(a[0], b[0]), k
+        assert a[1:] == b[1:], k
+        if len(k) == 3:
+            assert orc.rel_res(f, a[0], h, bc) <= 1e-10, k
+
+
 @pytest.mark.parametrize("bc", [DIR, PER])
 def test_prof_level_runs_the_solver_kernels(B, orc, bc):
     """The timing hook launches the solver's level kernels (FP64, 128^3, the z-marching
