@@ -119,6 +119,7 @@ struct Tuning {
     int inner_bf16 = 2;
     int batch = 4;        // first batch of cycles enqueued before reading the controller
     int greps = 8;        // most cycles (outer steps) one graph holds: 1, 2, 4 or 8
+    int tailck = 1;       // the cycle's convergence check run by the one-workgroup tail kernel
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
@@ -493,10 +494,12 @@ template <int D, class S> struct Ops {
         return resid_restrict(f, x, fc, lg, bc, h, s, stop);
     }
 
+    // ctl: the tail first runs the convergence check on the np partials.
     static np_status tail(const S *f, S *x, const double *Minv, int lg, int bc, double h, const CycleOpts &o,
-                          hipStream_t s, const int *stop) {
+                          hipStream_t s, const int *stop, const double *partial = nullptr, int np = 0,
+                          Ctl *ctl = nullptr) {
         hipLaunchKernelGGL((k_tail<D, S>), dim3(1), dim3(Tail<D>::NT), 0, s, f, x, Minv, lg, bc, h, o.omega, o.nu1,
-                           o.nu2, stop);
+                           o.nu2, stop, partial, np, ctl);
         NP_LAUNCH_CHECK();
         return NP_OK;
     }
@@ -857,6 +860,21 @@ template <int D, class S> struct Ops {
         if (g_tune.tail && o.nu1 >= 1)
             for (int l = 1; l <= L; ++l)
                 if (H->lg - l <= Tail<D>::LG && H->lg - l > 2 && !fl[l]) { tl = l; break; }
+        // the check of level 0's partials: by the tail kernel where there is one and the level-0
+        // down-leg writes only the partner buffer (safe): the tail then comes before every launch
+        // that writes x0, and the levels between touch neither x0 nor the partials; else by a
+        // launch of its own
+        const bool defer = tl > 0 && !hook && g_tune.tailck;
+        int pend = -1;
+        auto check_now = [&](int nb, bool safe = true) -> np_status {
+            if (defer && safe) {
+                pend = nb;
+                return NP_OK;
+            }
+            hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
+            NP_LAUNCH_CHECK();
+            return NP_OK;
+        };
         double hl = h;
         // ------------------------------------------------------------ down
         for (int l = 0; l < L; ++l, hl *= 2.0) {
@@ -876,8 +894,7 @@ template <int D, class S> struct Ops {
                 } else if (check && l == 0) {
                     NP_TRY((fused<2, PRE_NONE, true, true>(cur[l], F[l], oth[l], nullptr, fc, H->red, lg, bc, hl,
                                                            o.omega, s, stop, true, &nb)));
-                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
-                    NP_LAUNCH_CHECK();
+                    NP_TRY(check_now(nb));
                 } else {
                     NP_TRY((fused<2, PRE_NONE, true, false>(cur[l], F[l], oth[l], nullptr, fc, nullptr, lg, bc, hl,
                                                             o.omega, s, stop, l == 0, &nb)));
@@ -897,8 +914,7 @@ template <int D, class S> struct Ops {
                     int nb = 0;
                     NP_TRY((lvl2b<1, true>(nullptr, F[l], cur[l], oth[l], fc, H->red, &nb, lg, bc, hl, o.omega, s,
                                            stop)));
-                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
-                    NP_LAUNCH_CHECK();
+                    NP_TRY(check_now(nb));
                     std::swap(cur[l], oth[l]);
                 } else {
                     NP_TRY((lvl2b<1, false>(nullptr, F[l], cur[l], oth[l], fc, nullptr, nullptr, lg, bc, hl, o.omega,
@@ -928,8 +944,7 @@ template <int D, class S> struct Ops {
             if (check && l == 0 && !zero && o.nu1 == 0) {
                 int nb = 0;
                 NP_TRY(resid_sq(F[0], cur[0], lg, bc, hl, H->red, s, stop, &nb));
-                hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
-                NP_LAUNCH_CHECK();
+                NP_TRY(check_now(nb));
             }
             if (!zf && o.nu1 == 2 && z2_on(lg)) {
                 // both pre-sweeps in one pass (with the residual check of the input iterate on level 0),
@@ -943,10 +958,7 @@ template <int D, class S> struct Ops {
                     NP_TRY(sweep2z(nullptr, F[l], cur[l], oth[l], ck ? H->red : nullptr, &nb, lg, bc, hl, o.omega, s,
                                    l == 0, stop));
                 }
-                if (ck) {
-                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
-                    NP_LAUNCH_CHECK();
-                }
+                if (ck) NP_TRY(check_now(nb));
                 std::swap(cur[l], oth[l]);
                 if (!down2_on(lg)) NP_TRY(restrict_(F[l], cur[l], fc, lg, bc, hl, s, stop));
                 if (l + 1 == tl) { hl *= 2.0; break; }
@@ -963,10 +975,7 @@ template <int D, class S> struct Ops {
                 const bool zpart = zm && l == 0 && o.nu2 == 2 && z2_on(lg) && psweep_on(lg, o.nu2);
                 NP_TRY(sweep(F[l], zm ? nullptr : cur[l], zm && !zpart ? cur[l] : oth[l], lg, bc, hl, o.omega, zm,
                              ck ? H->red : nullptr, &nb, s, l == 0, stop));
-                if (ck) {
-                    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, H->red, nb, H->ctl);
-                    NP_LAUNCH_CHECK();
-                }
+                if (ck) NP_TRY(check_now(nb, o.nu1 == 1));  // a second sweep would write x0 back
                 if (!zm || zpart) std::swap(cur[l], oth[l]);
                 if (zm == 2) ++it;
             }
@@ -976,7 +985,8 @@ template <int D, class S> struct Ops {
         if (tl > 0) {
             // levels tl .. L in one workgroup; hl is the spacing of level tl
             hl = h * double(int64_t(1) << tl);
-            NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop));
+            if (pend >= 0) NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop, H->red, pend, H->ctl));
+            else NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop));
             res[tl] = cur[tl];
         } else {
             // coarsest level: exact solve (zero guess unless the whole grid is 4^d)
@@ -1557,7 +1567,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1613,6 +1623,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "blk2")) return g_tune.blk2;
     if (!std::strcmp(key, "z2wg")) return g_tune.z2wg;
     if (!std::strcmp(key, "greps")) return g_tune.greps;
+    if (!std::strcmp(key, "tailck")) return g_tune.tailck;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;

@@ -465,21 +465,26 @@ enum StopReason { kRunning = 0, kConverged = 1, kFixedDone = 2, kMaxCycles = 3, 
 // Convergence check before cycle k: rr = sqrt(sum of partials)/||f|| (fixed
 // summation order), recorded in hist[k]; then the stop rule: non-finite,
 // fixed count reached, rr <= tol, k >= max, or three consecutive increases.
-static __global__ __launch_bounds__(kBlock) void k_check(const double *__restrict__ partial, int np,
-                                                  Ctl *__restrict__ c) {
-    if (c->stop) return;
-    // four interleaved accumulators (fixed assignment): deterministic
+// Run by a whole workgroup of NT >= kBlock threads: the first kBlock sum the
+// partials (four interleaved accumulators, a fixed assignment) and the others
+// add zeros, so that every NT gives the same sum.  Returns the stop state to
+// thread 0 (0 to the others).
+template <int NT>
+__device__ __forceinline__ int check_block(const double *__restrict__ partial, int np, Ctl *__restrict__ c) {
+    if (c->stop) return threadIdx.x == 0 ? c->stop : 0;  // uniform: one value for the workgroup
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = threadIdx.x;
-    for (; b + 3 * kBlock < np; b += 4 * kBlock) {
-        a0 += partial[b];
-        a1 += partial[b + kBlock];
-        a2 += partial[b + 2 * kBlock];
-        a3 += partial[b + 3 * kBlock];
+    if (int(threadIdx.x) < kBlock) {
+        int b = threadIdx.x;
+        for (; b + 3 * kBlock < np; b += 4 * kBlock) {
+            a0 += partial[b];
+            a1 += partial[b + kBlock];
+            a2 += partial[b + 2 * kBlock];
+            a3 += partial[b + 3 * kBlock];
+        }
+        for (; b < np; b += kBlock) a0 += partial[b];
     }
-    for (; b < np; b += kBlock) a0 += partial[b];
-    double acc = block_sum((a0 + a1) + (a2 + a3));
-    if (threadIdx.x != 0) return;
+    const double acc = block_sum_n<NT>((a0 + a1) + (a2 + a3));
+    if (threadIdx.x != 0) return 0;
     const int k = c->k;
     const double rr = sqrt(acc) / c->nf;
     if (k < 256) c->hist[k] = rr;
@@ -494,6 +499,12 @@ static __global__ __launch_bounds__(kBlock) void k_check(const double *__restric
         st = kDiverged;
     if (st != kRunning) c->stop = st;
     else c->k = k + 1;
+    return st;
+}
+
+static __global__ __launch_bounds__(kBlock) void k_check(const double *__restrict__ partial, int np,
+                                                  Ctl *__restrict__ c) {
+    (void)check_block<kBlock>(partial, np, c);
 }
 
 // y = A x (FP64).

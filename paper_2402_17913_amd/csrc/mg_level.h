@@ -1022,12 +1022,15 @@ __device__ __forceinline__ void tail_cycle(typename St<S>::C *xs, typename St<S>
     for (int64_t c = tid; c < mt; c += NT) St<S>::st(x_t + c, xs[off(lg_t) + c]);
 }
 
-// One-workgroup V-cycle from a zero iterate on levels lg_t .. 2.
+// One-workgroup V-cycle from a zero iterate on levels lg_t .. 2.  ctl: first the
+// cycle's convergence check on the np partials of the finest level's residual
+// norm (the check of k_check), and nothing more if it stops the solve.
 template <int D, class S>
 __global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t, S *__restrict__ x_t,
                                                       const double *__restrict__ Minv, int lg_t, int bc,
                                                       double h_t, double omega, int nu1, int nu2,
-                                                      const int *stop) {
+                                                      const int *stop, const double *__restrict__ partial,
+                                                      int np, Ctl *ctl) {
     typedef typename St<S>::C C;
     __shared__ C xs[Tail<D>::levels_sum()];
     __shared__ C fs[Tail<D>::levels_sum()];
@@ -1038,6 +1041,13 @@ __global__ __launch_bounds__(Tail<D>::NT) void k_tail(const S *__restrict__ f_t,
     constexpr int m = D == 3 ? 64 : 16, mp = m + 1;
     __shared__ double Ms[m * mp];
     if (stop && *stop) return;
+    if (ctl) {
+        __shared__ int halt;
+        const int st = check_block<Tail<D>::NT>(partial, np, ctl);
+        if (threadIdx.x == 0) halt = st;
+        __syncthreads();
+        if (halt) return;
+    }
     for (int g = threadIdx.x; g < m * m; g += Tail<D>::NT) Ms[(g % m) * mp + g / m] = Minv[g];
     tail_cycle<D, S, Tail<D>::NT>(xs, fs, ts, f_t, x_t, nullptr, Ms, lg_t, bc, h_t, omega, nu1, nu2, 1, mp);
 }

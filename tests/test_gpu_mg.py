@@ -290,13 +290,15 @@ def test_blk2_same_solves(B, orc, bc, n):
         assert rel(out[(1, "fixed")], ref.x) < 1e-12
 
 
+@pytest.mark.parametrize("knob,on,off", [("greps", 8, 1), ("tailck", 1, 0)])
 @pytest.mark.parametrize("shape", [(128, 128), (64, 64, 64), (256, 256, 256)])
-def test_graph_reps_same_solves(B, orc, shape):
-    """Cycles replayed as graphs of up to 8 (knob greps) against one graph per cycle:
-    FP64 solves to the tolerance and for fixed cycles, FP32- and BF16-mixed solves from a
-    zero and from a nonzero guess, the sawtooth cycle and the advection-diffusion
-    V-cycle give the same iterates and histories bit for bit; the tolerance-stopped
-    results meet the tolerance by the oracle's residual."""
+def test_launch_grouping_same_solves(B, orc, shape, knob, on, off):
+    """Cycles replayed as graphs of up to 8 (knob greps) against one graph per cycle, and
+    the convergence check run by the one-workgroup tail kernel (knob tailck) against its
+    own launch: FP64 solves to the tolerance and for fixed cycles, FP32- and BF16-mixed
+    solves from a zero and from a nonzero guess, the sawtooth cycle and the
+    advection-diffusion V-cycle give the same iterates and histories bit for bit; the
+    tolerance-stopped results meet the tolerance by the oracle's residual."""
     n, d = shape[0], len(shape)
     bc = DIR if d == 3 else PER
     rng = np.random.default_rng(811 + n + d)
@@ -315,9 +317,9 @@ def test_graph_reps_same_solves(B, orc, shape):
         out[tag] = (host(xg), stats["cycles"], stats["outer_iters"], stats["hist"])
 
     try:
-        for v in (8, 1):
-            B.np_set_tuning("greps", v)
-            say("greps", v, shape, bc)
+        for v in (on, off):
+            B.np_set_tuning(knob, v)
+            say(knob, v, shape, bc)
             z = np.zeros_like(f)
             run((v, "fixed"), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, fixed_cycles=11), z)
             run((v, "saw"), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, cycle=B.CYCLE_SAWTOOTH, nu1=0,
@@ -327,9 +329,9 @@ def test_graph_reps_same_solves(B, orc, shape):
                 run((v, p, 0), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p), z)
                 run((v, p, 2), lambda xg: B.mg_poisson_solve(fg, xg, h, bc, smooth_prec=p, warm_start=2), x0)
     finally:
-        B.np_set_tuning("greps", 8)
-    for k in [key for key in out if key[0] == 8]:
-        a, b = out[k], out[(1,) + k[1:]]
+        B.np_set_tuning(knob, on)
+    for k in [key for key in out if key[0] == on]:
+        a, b = out[k], out[(off,) + k[1:]]
         assert np.array_equal(a[0], b[0]), k
         assert a[1:] == b[1:], k
         if len(k) == 3:
