@@ -120,6 +120,7 @@ struct Tuning {
     int batch = 4;        // first batch of cycles enqueued before reading the controller
     int greps = 8;        // most cycles (outer steps) one graph holds: 1, 2, 4 or 8
     int tailck = 1;       // the cycle's convergence check run by the one-workgroup tail kernel
+    int zbar = 1;         // barriers per plane step of the 3D zero-start down-leg pass (1 or 2)
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
@@ -641,8 +642,12 @@ template <int D, class S> struct Ops {
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDownZero);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            hipLaunchKernelGGL((k_down0z<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, f, x, fc, lg, bc,
-                               zc, inv_h2, wdiag, stop);
+            if (g_tune.zbar == 1)
+                hipLaunchKernelGGL((k_down0z1<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, f, x, fc, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
+            else
+                hipLaunchKernelGGL((k_down0z<S>), dim3(zblocks(lg, CPT, zc)), dim3(kS3Threads), 0, s, f, x, fc, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
             NP_LAUNCH_CHECK();
             if (prof) {
                 const double m = double(cells(D, lg));
@@ -1567,7 +1572,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1}, {"zbar", &g_tune.zbar, 1, 2},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1624,6 +1629,7 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "z2wg")) return g_tune.z2wg;
     if (!std::strcmp(key, "greps")) return g_tune.greps;
     if (!std::strcmp(key, "tailck")) return g_tune.tailck;
+    if (!std::strcmp(key, "zbar")) return g_tune.zbar;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;

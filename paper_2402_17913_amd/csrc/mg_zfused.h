@@ -574,6 +574,182 @@ __global__ __launch_bounds__(kS3Threads) void k_down0z(const S *__restrict__ f, 
     }
 }
 
+// k_down0z with one barrier per plane step: the second sweep runs one plane
+// behind the first (at z - 1, reading x1 of that plane from the other of two
+// LDS slots) and the residual one plane behind it (at z - 2, reading x2 from
+// the slot the previous step filled), so every LDS read of a step comes from a
+// slot written before the previous step's barrier.  Same tiles, arithmetic and
+// term order: the outputs equal k_down0z's bit for bit.
+template <class S>
+__global__ __launch_bounds__(kS3Threads) void k_down0z1(const S *__restrict__ f, S *__restrict__ xout,
+                                                        S *__restrict__ fc, int lg, int bc, int zc,
+                                                        typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                        const int *stop) {
+    typedef typename St<S>::C C;
+    typedef Z2Cfg<S> G;
+    constexpr int TX = G::TX, TY = G::TY, CPT = G::CPT, TP = G::TP, W1 = G::W1, W2 = G::W2;
+    constexpr int AS = G::H2 * W2, BS = G::H1 * W1;
+    static_assert(TP == 32, "rows ty, ty + 1 are the two halves of a wave");
+    __shared__ C Ax[2 * AS];  // x1 = w f of planes z - 1, z (slot = plane & 1), tile and two-cell ring
+    __shared__ C Bs[2 * BS];  // x2 of planes z - 2, z - 1 (slot = plane & 1), tile and ring
+    if (stop && *stop) return;
+    const int n = 1 << lg, ntx = n / TX, nty = n / TY, lgc = lg - 1;
+    const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+    const int t = int(threadIdx.x), tp = t % TP, ty = t / TP, ai = CPT * tp;
+    const int x0 = (blk % ntx) * TX, y0 = ((blk / ntx) % nty) * TY, k0 = (blk / (ntx * nty)) * zc;
+    const int pl = 2 * lg;
+    const uint32_t osrc = (uint32_t(y0 + ty) << lg) + uint32_t(x0 + ai);
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool r1 = wv < G::NW1, r2 = wv >= G::NW - G::NW2;
+    int ra = 0, rb = 0;
+    if (r1) ring_pos<TX, TY>(min(t, G::NR1 - 1), 1, ra, rb);
+    if (r2) ring_pos<TX, TY>(min(t - 64 * (G::NW - G::NW2), G::NR2 - 1), 2, ra, rb);
+    uint32_t rsrc;
+    C rsg;
+    {
+        int s = 1;
+        const int gi = bmap(x0 + ra, n, bc, s), gj = bmap(y0 + rb, n, bc, s);
+        rsrc = (uint32_t(gj) << lg) + uint32_t(gi);
+        rsg = C(s);
+    }
+    const int own_a = (ty + 2) * W2 + ai + 2, own_b = (ty + 1) * W1 + ai + 1;
+    const int ring_a = (rb + 2) * W2 + ra + 2, ring_b = (rb + 1) * W1 + ra + 1;
+    bool dw[CPT], de[CPT];
+    for (int c = 0; c < CPT; ++c) {
+        dw[c] = !bc && x0 + ai + c == 0;
+        de[c] = !bc && x0 + ai + c == n - 1;
+    }
+    const bool ds = !bc && y0 + ty == 0, dn = !bc && y0 + ty == n - 1;
+    auto poff = [&](int q) -> uint32_t {
+        bool flip;
+        return uint32_t(plane_map(q, n, bc, flip)) << pl;
+    };
+    auto psign = [&](int q) -> C { return (!bc && (q < 0 || q >= n)) ? C(-1) : C(1); };
+    auto ld_own = [&](const S *base, C (&v)[CPT]) {
+        if constexpr (CPT == 2) Pair<S>::ld(base + osrc, v[0], v[1]);
+        else v[0] = St<S>::ld(base + osrc);
+    };
+    auto sweep1 = [&](const C *A, int q, C xc, C xm, C xp, C fv) -> C {
+        const C t0 = ((A[q - 1] + A[q + 1]) + A[q - W2]) + A[q + W2];
+        const C s = (t0 + xm) + xp;
+        const C r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+    // registers at the start of step z: own f and x1 = (signed) w f at z - 2 .. z, x2 at
+    // z - 3, z - 2; ring cells (both rings) the same f and x1 at their cell
+    C fo[3][CPT], xo[3][CPT], so[2][CPT];
+    C rf[3] = {C(0), C(0), C(0)}, rx[3] = {C(0), C(0), C(0)};
+    C pf[2][CPT], pr[2] = {C(0), C(0)};  // loads in flight (set = parity of the issuing step)
+    for (int c = 0; c < CPT; ++c) so[0][c] = so[1][c] = fo[0][c] = xo[0][c] = C(0);
+    // f of plane z (own and ring cells), consumed at the end of step z - 1; past the last
+    // plane used (k0 + zc + 1) the last one is read again, an L2 hit
+    auto pload = [&](int z, auto u) {
+        constexpr int U = decltype(u)::value;
+        const uint32_t o = poff(min(z, k0 + zc + 1));
+        ld_own(f + o, pf[U]);
+        pr[U] = St<S>::ld(f + o + rsrc);
+    };
+    // prologue: f and x1 at k0 - 2, k0 - 1
+    for (int z = 1; z < 3; ++z) {
+        const int q = k0 - 3 + z;
+        ld_own(f + poff(q), fo[z]);
+        rf[z] = St<S>::ld(f + poff(q) + rsrc);
+        const C sg = psign(q);
+        for (int c = 0; c < CPT; ++c) xo[z][c] = sg * (wdiag * fo[z][c]);
+        rx[z] = (sg * rsg) * (wdiag * rf[z]);
+    }
+    pload(k0, std::integral_constant<int, 0>{});
+    C pair = C(0);  // residual sum of the plane pair
+    auto step = [&](int z, auto odd) {
+        constexpr bool ODD = decltype(odd)::value;
+        constexpr int U = ODD ? 1 : 0;
+        pload(z + 2, std::integral_constant<int, U>{});
+        // x1 of plane z into its slot
+        C *A = Ax + (ODD ? AS : 0);
+        for (int c = 0; c < CPT; ++c) A[own_a + c] = xo[2][c];
+        if (r1 || r2) A[ring_a] = rx[2];
+        C sn[CPT];
+        if (z >= k0) {
+            // second sweep at plane z - 1 from x1 there (the other slot): own cells and the ring-1 cell
+            const C *Am = Ax + (ODD ? 0 : AS);
+            C *B = Bs + (ODD ? 0 : BS);
+            for (int c = 0; c < CPT; ++c) {
+                sn[c] = st_round<S>(sweep1(Am, own_a + c, xo[1][c], xo[0][c], xo[2][c], fo[1][c]));
+                B[own_b + c] = sn[c];
+            }
+            if (z > k0 && z <= k0 + zc) store_cells<S, CPT>(xout + (uint32_t(z - 1) << pl) + osrc, sn);
+            if (r1) B[ring_b] = st_round<S>(sweep1(Am, ring_a, rx[1], rx[0], rx[2], rf[1]));
+        } else {
+            for (int c = 0; c < CPT; ++c) sn[c] = C(0);
+        }
+        // residual of x2 at plane p = z - 2 (its slot was filled before the last barrier),
+        // own cells, summed into the coarse cells
+        if (z >= k0 + 2) {
+            const int p = z - 2;
+            const C *L = Bs + (ODD ? BS : 0);
+            const bool dzl = !bc && p == 0, dzu = !bc && p == n - 1;
+            C r = C(0);
+            for (int c = 0; c < CPT; ++c) {
+                const int q = own_b + c;
+                const C xc = so[1][c];
+                const C lw = L[q - 1], le = L[q + 1], ls = L[q - W1], ln = L[q + W1];
+                const C xw = dw[c] ? -xc : lw;
+                const C xe = de[c] ? -xc : le;
+                const C ys = ds ? -xc : ls;
+                const C yn = dn ? -xc : ln;
+                const C zl = dzl ? -xc : so[0][c];
+                const C zu = dzu ? -xc : sn[c];
+                const C t0 = ((xw + xe) + ys) + yn;
+                const C s = (t0 + zl) + zu;
+                const C rc = fo[0][c] - (C(6) * xc - s) * inv_h2;
+                if (c == 0) r = rc;
+                else r += rc;
+            }
+            if (!ODD) {  // p even: the first plane of the pair
+                pair = r;
+            } else {
+                pair += r;
+                const uint32_t cc = (uint32_t(p >> 1) << (2 * lgc)) + (uint32_t((y0 + ty) >> 1) << lgc) +
+                                    uint32_t((x0 + ai) >> 1);
+                if constexpr (CPT == 2) {
+                    const C o = __shfl_down(pair, 32);
+                    if ((ty & 1) == 0) St<S>::st(fc + cc, (pair + o) * C(0.125));
+                } else {
+                    const C b = __shfl_down(pair, 1), cy = __shfl_down(pair, 32),
+                            d = __shfl_down(pair, 33);
+                    if (((tp | ty) & 1) == 0) St<S>::st(fc + cc, (((pair + b) + cy) + d) * C(0.125));
+                }
+            }
+        }
+        __syncthreads();
+        // slide: f of plane z + 1 (issued by step z - 1)
+        const C sg1 = psign(z + 1);
+        for (int c = 0; c < CPT; ++c) {
+            so[0][c] = so[1][c];
+            so[1][c] = sn[c];
+            fo[0][c] = fo[1][c];
+            fo[1][c] = fo[2][c];
+            fo[2][c] = pf[1 - U][c];
+            xo[0][c] = xo[1][c];
+            xo[1][c] = xo[2][c];
+            xo[2][c] = sg1 * (wdiag * pf[1 - U][c]);
+        }
+        if (r1 || r2) {
+            rf[0] = rf[1];
+            rf[1] = rf[2];
+            rf[2] = pr[1 - U];
+            rx[0] = rx[1];
+            rx[1] = rx[2];
+            rx[2] = (sg1 * rsg) * (wdiag * pr[1 - U]);
+        }
+    };
+    step(k0 - 1, std::true_type{});  // k0 even: x1 of plane k0 - 1 only
+    for (int z = k0; z < k0 + zc + 2; z += 2) {
+        step(z, std::false_type{});
+        step(z + 1, std::true_type{});
+    }
+}
+
 // The down-leg of a large 3D level from a nonzero iterate in one pass (one cell
 // per thread, 32 x 16 tiles, in every storage precision): x2 = sweep(sweep(x))
 // and fc = R (f - A x2),

@@ -290,12 +290,13 @@ def test_blk2_same_solves(B, orc, bc, n):
         assert rel(out[(1, "fixed")], ref.x) < 1e-12
 
 
-@pytest.mark.parametrize("knob,on,off", [("greps", 8, 1), ("tailck", 1, 0)])
+@pytest.mark.parametrize("knob,on,off", [("greps", 8, 1), ("tailck", 1, 0), ("zbar", 1, 2)])
 @pytest.mark.parametrize("shape", [(128, 128), (64, 64, 64), (256, 256, 256)])
 def test_launch_grouping_same_solves(B, orc, shape, knob, on, off):
-    """Cycles replayed as graphs of up to 8 (knob greps) against one graph per cycle, and
-    the convergence check run by the one-workgroup tail kernel (knob tailck) against its
-    own launch: FP64 solves to the tolerance and for fixed cycles, FP32- and BF16-mixed
+    """Cycles replayed as graphs of up to 8 (knob greps) against one graph per cycle, the
+    convergence check run by the one-workgroup tail kernel (knob tailck) against its own
+    launch, and the 3D zero-start down-leg pass with one barrier per plane step (knob
+    zbar) against two: FP64 solves to the tolerance and for fixed cycles, FP32- and BF16-mixed
     solves from a zero and from a nonzero guess, the sawtooth cycle and the
     advection-diffusion V-cycle give the same iterates and histories bit for bit; the
     tolerance-stopped results meet the tolerance by the oracle's residual."""
