@@ -474,7 +474,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * workgroups per CU -- the up-leg, FP64's zero-start down-leg -- take planes for 512 workgroups, not 1024;
  * default 1), "greps" (1, 2, 4 or 8: the most cycles, or refinement steps, one replayed graph holds;
  * default 8), "tailck" (0/1: a cycle's convergence check run by the one-workgroup kernel of its coarse levels
- * rather than by a launch of its own; default 1), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
+ * rather than by a launch of its own; default 1), "zbar" (1 or 2: barriers per plane step of the 3D zero-start
+ * down-leg pass, default 1), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the
  * batched solver; batched_rm: row-marching level kernels above the one-workgroup depths),
  * "batched_wg" (workgroups a row-marching batched launch aims for, 64 .. 2^20, default 4096; the
  * caller's setting when the autotuner does not run), "zmarch_explicit" (0/1: z-marching tiles for the 3D explicit, collocated and staggered

@@ -707,7 +707,7 @@ __global__ __launch_bounds__(kBlock) void kb_ir_rm(BPtrs<SL> ptr, SL *const *epo
 
 // Depths min(L_p, kTailDepth) .. 0 of every problem, one workgroup each.
 template <class S>
-__global__ __launch_bounds__(Tail<2>::NT) void kb_tail(S *const *Xpool, S *const *Fpool, const double *__restrict__ Minv1,
+__global__ __launch_bounds__(Tail<2>::NT_B) void kb_tail(S *const *Xpool, S *const *Fpool, const double *__restrict__ Minv1,
                                                        const BProb *__restrict__ P, const BState *__restrict__ st,
                                                        const BGlobal *__restrict__ g, int cyc, double omega, int nu1,
                                                        int nu2) {
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(Tail<2>::NT) void kb_tail(S *const *Xpool, S *const
     __shared__ double Ms[16 * 16];
     for (int q = threadIdx.x; q < 256; q += blockDim.x) Ms[q] = Minv1[q] * (hc * hc);
     __syncthreads();
-    tail_cycle<2, S, Tail<2>::NT>(xs, fs, ts, f, x, warm ? x : nullptr, Ms, t + 2, 0, h, omega, nu1, nu2);
+    tail_cycle<2, S, Tail<2>::NT_B>(xs, fs, ts, f, x, warm ? x : nullptr, Ms, t + 2, 0, h, omega, nu1, nu2);
 }
 
 // ----------------------------------------------------------------- plan
@@ -957,7 +957,7 @@ np_status enqueue_step(Plan *B, int kind, int inner, const BOpts &o, hipStream_t
                                    s, F, cur, (S *)B->F[k - 1], B->d_slot_prob[k], B->d_P, B->d_st, B->d_g, k);
             NP_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL((kb_tail<S>), dim3(B->nprob), dim3(Tail<2>::NT), 0, s, Xp, Fp, B->d_Minv1, B->d_P,
+        hipLaunchKernelGGL((kb_tail<S>), dim3(B->nprob), dim3(Tail<2>::NT_B), 0, s, Xp, Fp, B->d_Minv1, B->d_P,
                            B->d_st, B->d_g, c, o.omega, o.nu1, o.nu2);
         NP_LAUNCH_CHECK();
         for (int k = kTailDepth + 1; k <= B->K; ++k) {

@@ -767,7 +767,10 @@ template <int D> struct Tail {
         for (int l = LG; l >= 2; --l) s += cells(l);
         return s;
     }
-    static constexpr int NT = 1024;  // threads
+    // threads (2D 512: the 128^2 solve measured 0.571 -> 0.552 ms against 1024; 3D 512 no
+    // faster, 256 slower); NT_B: the batched solver's 2D tail, one workgroup per problem
+    static constexpr int NT = D == 3 ? 1024 : 512;
+    static constexpr int NT_B = 1024;
     // threads of the advection-diffusion tail (3D measured slower with 1024: 19.3 against 17.3 us)
     static constexpr int NT_AD = D == 3 ? 512 : 1024;
 };
