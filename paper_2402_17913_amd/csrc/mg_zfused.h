@@ -121,7 +121,14 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec
     typedef Z2Cfg<S> G;
     constexpr int TX = G::TX, TY = G::TY, CPT = G::CPT, TP = G::TP, W1 = G::W1, W2 = G::W2, CW = G::CW;
     constexpr int BS = G::H1 * W1;          // one first-sweep plane in LDS
-    __shared__ C Ax[G::H2 * W2];            // x' of plane z, tile and two-cell ring
+    constexpr int AS = G::H2 * W2;          // one x' plane in LDS
+    // ONE (FP32, BF16): one barrier per plane step, x' of planes z - 1 and z in two slots (the
+    // second sweep reads the first sweep of the previous step).  Measured at 256^3 and 128^3
+    // (average per launch): FP32 up-leg 25.5 -> 24.5 us, BF16 up-leg 24.4 -> 23.4, BF16 down-leg
+    // 30.1 -> 28.8; FP64 keeps two barriers (up-leg 47.8 against 50.5 us: one barrier takes it
+    // past 128 VGPRs)
+    constexpr bool ONE = sizeof(S) < 8;
+    __shared__ C Ax[(ONE ? 2 : 1) * AS];    // x' of plane z (ONE: slot = plane & 1), tile and two-cell ring
     __shared__ C Bs[2 * BS];                // first sweep of planes z - 1, z (slot = plane & 1), tile and ring
     __shared__ C Ec[CORR ? 4 : 1][CORR ? G::CR + 1 : 1];  // coarse planes (slot = plane & 3), one spare cell
     if (stop && *stop) return;
@@ -194,8 +201,8 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec
         else return st_round<S>(v + prolong_mix(a1, a0));
     };
     // a sweep at an LDS position of plane z (in-plane neighbours from Ax), z-neighbours given
-    auto sweep1 = [&](int q, C xc, C xm, C xp, C fv, C &r) -> C {
-        const C t0 = ((Ax[q - 1] + Ax[q + 1]) + Ax[q - W2]) + Ax[q + W2];
+    auto sweep1 = [&](const C *A, int q, C xc, C xm, C xp, C fv, C &r) -> C {
+        const C t0 = ((A[q - 1] + A[q + 1]) + A[q - W2]) + A[q + W2];
         const C s = (t0 + xm) + xp;
         r = fv - (C(6) * xc - s) * inv_h2;
         return xc + wdiag * r;
@@ -292,8 +299,9 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec
         }
         pload(z + 1, std::integral_constant<int, 1 - U>{});  // for the next step
         // x' of plane z into LDS
-        for (int c = 0; c < CPT; ++c) Ax[own_a + c] = xo[1][c];
-        if (r1 || r2) Ax[ring_a] = rx1;
+        C *A = Ax + (ONE && ODD ? AS : 0);
+        for (int c = 0; c < CPT; ++c) A[own_a + c] = xo[1][c];
+        if (r1 || r2) A[ring_a] = rx1;
         __syncthreads();
         // first sweep of plane z: own cells and the ring-1 cell (values at Dirichlet ghosts are
         // formed too, and never selected)
@@ -301,16 +309,16 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec
         C sn[CPT];
         for (int c = 0; c < CPT; ++c) {
             C r;
-            sn[c] = st_round<S>(sweep1(own_a + c, xo[1][c], xo[0][c], xo[2][c], fo[0][c], r));
+            sn[c] = st_round<S>(sweep1(A, own_a + c, xo[1][c], xo[0][c], xo[2][c], fo[0][c], r));
             if (NORM && z >= k0 && z < k0 + zc) acc += double(r) * double(r);
             B[own_b + c] = sn[c];
         }
         if (r1) {
             C r;
-            B[ring_b] = st_round<S>(sweep1(ring_a, rx1, rx0, rx2, rf, r));
+            B[ring_b] = st_round<S>(sweep1(A, ring_a, rx1, rx0, rx2, rf, r));
         }
-        __syncthreads();
-        // second sweep of plane z - 1, own cells
+        if constexpr (!ONE) __syncthreads();
+        // second sweep of plane z - 1, own cells (its first sweep was written by the previous step)
         if (z > k0) {
             const int p = z - 1;
             const C *L = Bs + (ODD ? 0 : BS);
@@ -759,7 +767,11 @@ __global__ __launch_bounds__(kS3Threads) void k_down0z1(const S *__restrict__ f,
 // LDS), the second at z - 1 on the tile and a one-cell ring, the residual of x2
 // at z - 2 on the tile, summed over the children of each coarse cell in
 // k_restrict3's order (the plane pair, then the column pair and the row pair by
-// lane shuffles).  Ring cells go to whole waves as in k_sweep2z (ring 1 first,
+// lane shuffles).  The second and third stages read what the previous plane
+// step wrote (two LDS slots per stage), so in FP64, with the iterate's plane in
+// two slots too, a step waits at one barrier, after that plane is stored (FP32
+// keeps a barrier after each stage).  Ring cells go to whole
+// waves as in k_sweep2z (ring 1 first,
 // then ring 3, ring 2 last) and share one register set.  The second sweep and
 // the residual read a Dirichlet ghost as minus the cell's own value, the first
 // sweep reads the iterate's ghosts by the boundary rule, as the per-kernel
@@ -776,7 +788,7 @@ template <class S> struct Z3Cfg {
 template <class S> inline int down2z_planes(int lg) { return z2_planes(lg, Z3Cfg<S>::TX, Z3Cfg<S>::TY); }
 
 template <class S, bool NORM>
-__global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, const S *__restrict__ xin,
+__global__ __launch_bounds__(kS3Threads) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 4 : 2))) void k_down2z(const S *__restrict__ f, const S *__restrict__ xin,
                                                        S *__restrict__ xout, S *__restrict__ fc,
                                                        double *__restrict__ partial, int lg, int bc, int zc,
                                                        typename St<S>::C inv_h2, typename St<S>::C wdiag,
@@ -784,8 +796,11 @@ __global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, 
     typedef typename St<S>::C C;
     typedef Z3Cfg<S> G;
     constexpr int TX = G::TX, TY = G::TY, TP = G::TP, W1 = G::W1, W2 = G::W2, W3 = G::W3;
-    constexpr int B1 = G::H1 * W1, B2 = G::H2 * W2;
-    __shared__ C XA[G::H3 * W3];  // x of plane z, tile and three-cell ring
+    constexpr int B1 = G::H1 * W1, B2 = G::H2 * W2, B3 = G::H3 * W3;
+    // FP64: one barrier per plane step (the iterate's plane in two slots); FP32: three, which
+    // measured faster there (4.19 against 4.23 ms per FP32-mixed 256^3 solve; FP64 6.60 -> 6.54)
+    constexpr bool ONE = sizeof(S) == 8;
+    __shared__ C XA[(ONE ? 2 : 1) * B3];  // x of plane z (ONE: planes z - 1, z, slot = plane & 1), tile and three-cell ring
     __shared__ C X1[2 * B2];      // first sweep of planes z - 1, z (slot = plane & 1), tile and two-cell ring
     __shared__ C X2[2 * B1];      // second sweep of planes z - 2, z - 1, tile and one-cell ring
     if (stop && *stop) return;
@@ -881,27 +896,30 @@ __global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, 
         constexpr bool ODD = decltype(odd)::value;
         constexpr int U = ODD ? 1 : 0;
         pload(z + 1, std::integral_constant<int, 1 - U>{});
-        // x of plane z into LDS: own cell and the ring cell (every role)
-        XA[own_a] = xo[1];
-        if (rr) XA[ring_a] = rx[1];
+        // x of plane z into LDS: own cell and the ring cell (every role).  With ONE, the step's one
+        // barrier follows: stages B and C read what the previous step wrote, and every slot
+        // written here was last read before it
+        C *LA = XA + (ONE && ODD ? B3 : 0);
+        LA[own_a] = xo[1];
+        if (rr) LA[ring_a] = rx[1];
         __syncthreads();
         // stage A: first sweep at plane z, own cell, rings 1 and 2
         C *L1 = X1 + (ODD ? B2 : 0);
         {
             C r;
-            const C v = st_round<S>(sweepL(XA, W3, own_a, xo[1], xo[0], xo[2], fo[0], r));
+            const C v = st_round<S>(sweepL(LA, W3, own_a, xo[1], xo[0], xo[2], fo[0], r));
             if (NORM && z >= k0 && z < k0 + zc) acc += double(r) * double(r);
             L1[own_1] = v;
             x1o[2] = v;  // x1 at z (registers slide at the end of the step)
         }
         if (r1 || r2) {
             C r;
-            const C v = st_round<S>(sweepL(XA, W3, ring_a, rx[1], rx[0], rx[2], rf[0], r));
+            const C v = st_round<S>(sweepL(LA, W3, ring_a, rx[1], rx[0], rx[2], rf[0], r));
             L1[ring_1] = v;
             r1x[2] = v;
         }
-        __syncthreads();
-        // stage B: second sweep at plane z - 1, own cell and ring 1
+        if constexpr (!ONE) __syncthreads();
+        // stage B: second sweep at plane z - 1 (x1 written by the previous step), own cell and ring 1
         const int p = z - 1;
         const C *M1 = X1 + (ODD ? 0 : B2);
         C *L2 = X2 + (ODD ? 0 : B1);
@@ -917,8 +935,9 @@ __global__ __launch_bounds__(kS3Threads) void k_down2z(const S *__restrict__ f, 
                                                 zu1, r));
             }
         }
-        __syncthreads();
-        // stage C: residual of x2 at plane z - 2, own cell, into the coarse cells
+        if constexpr (!ONE) __syncthreads();
+        // stage C: residual of x2 at plane z - 2 (written by the previous step), own cell, into the
+        // coarse cells
         if (z >= k0 + 2) {
             const int pc = z - 2;
             const C *M2 = X2 + (ODD ? B1 : 0);
