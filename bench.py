@@ -667,15 +667,16 @@ def main():
                        "restrict": "k_restrict3: residual + restriction, finest level",
                        "prolong": "k_prolong3: prolongation + correction, finest level",
                        "refine": "k_ir_resid3: FP64 update + residual of the refinement",
-                       "fused_down": "k_fused: 2 sweeps + residual + restriction, finest level",
-                       "fused_down_zero": "k_down0z: two sweeps from zero + residual + restriction in one "
+                       "fused_down": "k_down2z: two sweeps of a nonzero iterate + residual + restriction "
+                                     "in one pass, finest level (z-marching)",
+                       "fused_down_zero": "k_down0z1: two sweeps from zero + residual + restriction in one "
                                           "pass, finest level (z-marching)",
                        "fused_up": "k_sweep2z: prolongation + correction and two sweeps in one pass, "
                                    "finest level (z-marching)"}[dom] +
                       (" (%s correction and residual, %s per thread)" % (
                           head.upper(), "two cells" if B.np_get_tuning("ir_cpt") == 2 else "one cell")
                        if dom == "refine" else
-                       {"fp32": " (FP32 storage, two cells per thread)", "bf16": " (BF16 storage, two cells per thread)"}[head]),
+                       " (%s storage, %s per thread)" % (head.upper(), "one cell" if dom == "fused_down" else "two cells")),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

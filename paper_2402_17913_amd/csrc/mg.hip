@@ -663,9 +663,11 @@ template <int D, class S> struct Ops {
     // x = sweep(sweep(xin)) and fc = R (f - A x) in one z-marching pass on a 3D level of
     // 128 <= n <= 1024 in FP32 or FP64 storage (k_down2z); with `partial`, also the per-workgroup
     // partials of |f - A xin|^2 (their count in *np).
-    // In the cycle: FP32 and FP64 from 256^3 (at 128^3 measured no faster, FP64 28.2 against 26.6 us
-    // for the two passes; BF16, on one-cell-per-thread tiles, 64 against 50 us at 256^3).
-    static bool down2_on(int lg) { return z2_on(lg) && lg >= 8 && sizeof(S) >= 4 && g_tune.down2z; }
+    // In the cycle: FP64 from 256^3 (at 128^3 measured no faster, 28.2 against 26.6 us for the two
+    // passes).  FP32 and BF16 take the two passes: the FP32-mixed 256^3 solve measured the same
+    // either way (4.155 against 4.161 ms) once the two-sweep pass waited at one barrier per plane;
+    // BF16, on one-cell-per-thread tiles, 64 against 50 us at 256^3.
+    static bool down2_on(int lg) { return z2_on(lg) && lg >= 8 && sizeof(S) == 8 && g_tune.down2z; }
     static np_status down2z(const S *f, const S *xin, S *x, S *fc, double *partial, int *np, int lg, int bc,
                             double h, double omega, hipStream_t s, bool finest, const int *stop) {
         if constexpr (D == 3) {
