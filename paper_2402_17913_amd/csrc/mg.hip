@@ -1165,20 +1165,13 @@ static void fill_opts(const np_mg_opts *opts, CycleOpts &co, np_mg_opts &o) {
     co.omega = o.omega;
 }
 
-// Initialises the device controller (k done, history entry 0 if known).
+// Initialises the device controller (k done, history entry 0 if known) with a
+// kernel on the stream: its arguments carry the values, so no host buffer has
+// to outlive the call and the host does not wait.
 static np_status init_ctl(Hier *H, const np_mg_opts &o, double nf, double tol, int k0, double h0, hipStream_t s) {
-    Ctl *c = H->hctl;
-    std::memset(c, 0, sizeof(Ctl));
-    c->stop = kRunning;
-    c->k = k0;
-    c->fixed = o.fixed_cycles;
-    c->maxc = o.max_cycles;
-    c->nf = nf;
-    c->tol = tol;
-    c->nhist = k0;
-    if (k0 > 0) c->hist[0] = h0;
-    NP_HIP_TRY(hipMemcpyAsync(H->ctl, c, sizeof(Ctl), hipMemcpyHostToDevice, s));
-    NP_HIP_TRY(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kBlock), 0, s, H->ctl, k0, o.fixed_cycles, o.max_cycles, nf, tol,
+                       h0);
+    NP_LAUNCH_CHECK();
     return NP_OK;
 }
 

@@ -502,6 +502,23 @@ __device__ __forceinline__ int check_block(const double *__restrict__ partial, i
     return st;
 }
 
+// The controller at the start of a solve: running, k0 cycles done (history
+// entry 0 = h0 when k0 > 0), the rest of the history zero.
+static __global__ __launch_bounds__(kBlock) void k_init_ctl(Ctl *__restrict__ c, int k0, int fixed, int maxc,
+                                                     double nf, double tol, double h0) {
+    for (int i = threadIdx.x; i < 256; i += kBlock) c->hist[i] = (i == 0 && k0 > 0) ? h0 : 0.0;
+    if (threadIdx.x == 0) {
+        c->stop = kRunning;
+        c->k = k0;
+        c->fixed = fixed;
+        c->maxc = maxc;
+        c->nf = nf;
+        c->tol = tol;
+        c->nhist = k0;
+        c->pad = 0;
+    }
+}
+
 static __global__ __launch_bounds__(kBlock) void k_check(const double *__restrict__ partial, int np,
                                                   Ctl *__restrict__ c) {
     (void)check_block<kBlock>(partial, np, c);
