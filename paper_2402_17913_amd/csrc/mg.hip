@@ -155,7 +155,7 @@ struct GraphKey {
     double omega;
     double ad[5];  // advection-diffusion operator: dt, nu, a[3] (zero otherwise)
     int ad_scheme, ad_l1;
-    int reps, par;  // run_graphs: the repetitions one graph holds, the parity of its first
+    int reps, par;  // run_graphs: the repetitions one graph holds, the parity of the first one
     bool operator==(const GraphKey &o) const {
         return kind == o.kind && zero0 == o.zero0 && check == o.check && x == o.x && f == o.f && h == o.h &&
                nu1 == o.nu1 && nu2 == o.nu2 && inner == o.inner && omega == o.omega &&
@@ -992,8 +992,10 @@ template <int D, class S> struct Ops {
         if (tl > 0) {
             // levels tl .. L in one workgroup; hl is the spacing of level tl
             hl = h * double(int64_t(1) << tl);
-            if (pend >= 0) NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop, H->red, pend, H->ctl));
-            else NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop));
+            if (pend >= 0)  // with the check of level 0's partials
+                NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop, H->red, pend, H->ctl));
+            else
+                NP_TRY(tail(F[tl], cur[tl], H->Minv, H->lg - tl, bc, hl, o, s, stop));
             res[tl] = cur[tl];
         } else {
             // coarsest level: exact solve (zero guess unless the whole grid is 4^d)
