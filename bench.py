@@ -91,6 +91,7 @@ KERNEL_SOURCES = {
     "sweep": ("mg_zfused.h", "template <class S> struct Z2Cfg {", "// The down-leg of a large 3D level"),
     "fused_up": ("mg_zfused.h", "template <class S> struct Z2Cfg {", "// The down-leg of a large 3D level"),
     "fused_down_zero": ("mg_zfused.h", "// The down-leg of a large 3D level", "}  // namespace np"),
+    "fused_down": ("mg_zfused.h", "// k_down2z on two cells per thread", "}  // namespace np"),
     "restrict": ("mg_level.h", "// Residual + restriction on the z-marching tiles",
                  "// Refinement step of the mixed path on the z-marching tiles"),
 }
@@ -667,7 +668,7 @@ def main():
                        "restrict": "k_restrict3: residual + restriction, finest level",
                        "prolong": "k_prolong3: prolongation + correction, finest level",
                        "refine": "k_ir_resid3: FP64 update + residual of the refinement",
-                       "fused_down": "k_down2z: two sweeps of a nonzero iterate + residual + restriction "
+                       "fused_down": "k_down2z2: two sweeps of a nonzero iterate + residual + restriction "
                                      "in one pass, finest level (z-marching)",
                        "fused_down_zero": "k_down0z1: two sweeps from zero + residual + restriction in one "
                                           "pass, finest level (z-marching)",
@@ -676,7 +677,7 @@ def main():
                       (" (%s correction and residual, %s per thread)" % (
                           head.upper(), "two cells" if B.np_get_tuning("ir_cpt") == 2 else "one cell")
                        if dom == "refine" else
-                       " (%s storage, %s per thread)" % (head.upper(), "one cell" if dom == "fused_down" else "two cells")),
+                       " (%s storage, two cells per thread)" % head.upper()),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

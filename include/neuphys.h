@@ -418,7 +418,7 @@ np_status np_op_vcycle(np_dims dims, double h, np_bc bc, const double *f, double
  * zero and c = R (f - A x) in one z-marching pass, the zero-start down-leg of
  * those levels (xout unused, may be NULL); 8: xout = two sweeps of x and
  * c = R (f - A xout) in one z-marching pass, the down-leg of a nonzero iterate
- * (one cell per thread; the cycle runs it in FP64).  Kinds 5 to 8
+ * (the cycle runs it in FP64 and FP32; knob "d2cpt" picks one or two cells per thread).  Kinds 5 to 8
  * need 128 <= n <= 1024.
  * Synchronises the stream. */
 np_status np_op_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind, const void *f, void *x, void *xout,
@@ -467,8 +467,10 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * levels from 32^3 to 2^"fbmax" cells per axis -- the down-leg from a zero iterate and the up-leg with two
  * post-sweeps, one pass each; default 1, fbmax 6; "fbnt" their threads per workgroup, 512 or 1024, default 1024), "sweep2z" (0/1: two sweeps in one z-marching pass on 3D
  * levels from 128^3 to 1024^3 -- the pre-sweeps of a nonzero iterate, with the convergence check, and the
- * up-leg with prolongation + correction; default 1), "down2z" (0/1: in FP64, from 256^3, the
- * residual and the restriction in the down-leg's two-sweep pass too; default 1), "blk2" (0/1: 2D levels of
+ * up-leg with prolongation + correction; default 1), "down2z" (0/1: in FP64 and FP32, from 256^3, the
+ * residual and the restriction in the down-leg's two-sweep pass too; default 1), "d2cpt" (1 or 2: that pass on
+ * one cell per thread or two, default 2; FP32 takes it only with 2), "d2wg" (512 or 1024: workgroups the
+ * two-cell form aims for, default 512), "blk2" (0/1: 2D levels of
  * 128^2 .. 1024^2 take one block kernel per leg, both sweeps with the residual and restriction, or prolongation +
  * correction with both post-sweeps; default 1), "z2wg" (0/1: the 3D one-pass kernels that fit fewer than four
  * workgroups per CU -- the up-leg, FP64's zero-start down-leg -- take planes for 512 workgroups, not 1024;

@@ -121,6 +121,8 @@ struct Tuning {
     int greps = 8;        // most cycles (outer steps) one graph holds: 1, 2, 4 or 8
     int tailck = 1;       // the cycle's convergence check run by the one-workgroup tail kernel
     int zbar = 1;         // barriers per plane step of the 3D zero-start down-leg pass (1 or 2)
+    int d2cpt = 2;        // cells per thread of the 3D nonzero down-leg pass (1: k_down2z, 2: k_down2z2)
+    int d2wg = 512;       // workgroups k_down2z2 aims for (512 or 1024)
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
@@ -663,21 +665,32 @@ template <int D, class S> struct Ops {
     // x = sweep(sweep(xin)) and fc = R (f - A x) in one z-marching pass on a 3D level of
     // 128 <= n <= 1024 in FP32 or FP64 storage (k_down2z); with `partial`, also the per-workgroup
     // partials of |f - A xin|^2 (their count in *np).
-    // In the cycle: FP64 from 256^3 (at 128^3 measured no faster, 28.2 against 26.6 us for the two
-    // passes).  FP32 and BF16 take the two passes: the FP32-mixed 256^3 solve measured the same
-    // either way (4.155 against 4.161 ms) once the two-sweep pass waited at one barrier per plane;
-    // BF16, on one-cell-per-thread tiles, 64 against 50 us at 256^3.
-    static bool down2_on(int lg) { return z2_on(lg) && lg >= 8 && sizeof(S) == 8 && g_tune.down2z; }
+    // In the cycle: FP64 and FP32 from 256^3 (at 128^3 the one-cell form measured no faster, FP64
+    // 28.2 against 26.6 us for the two passes).  On two cells per thread (k_down2z2, 512
+    // workgroups) the 256^3 solves measured FP32-mixed 4.17 -> 4.01 ms and FP64 6.47 -> 6.18 ms
+    // against the one-cell form in FP64 and the two passes in FP32; BF16 keeps the two passes
+    // (4.455 against 4.48 ms).
+    static bool down2_on(int lg) {
+        return z2_on(lg) && lg >= 8 && (sizeof(S) == 8 || (sizeof(S) == 4 && g_tune.d2cpt == 2)) &&
+               g_tune.down2z;
+    }
     static np_status down2z(const S *f, const S *xin, S *x, S *fc, double *partial, int *np, int lg, int bc,
                             double h, double omega, hipStream_t s, bool finest, const int *stop) {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
-            const int zc = down2z_planes<S>(lg);
-            const unsigned nb = zblocks(lg, 1, zc);
+            const bool two = g_tune.d2cpt == 2;  // two cells per thread (k_down2z2)
+            const int zc = two ? sweep2z_planes<S>(lg, g_tune.d2wg) : down2z_planes<S>(lg);
+            const unsigned nb = zblocks(lg, two ? 2 : 1, zc);
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDown);
             if (prof) NP_TRY(prof_begin(s, &tok));
-            if (partial)
+            if (two && partial)
+                hipLaunchKernelGGL((k_down2z2<S, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, x, fc, partial, lg,
+                                   bc, zc, inv_h2, wdiag, stop);
+            else if (two)
+                hipLaunchKernelGGL((k_down2z2<S, false>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, x, fc, nullptr,
+                                   lg, bc, zc, inv_h2, wdiag, stop);
+            else if (partial)
                 hipLaunchKernelGGL((k_down2z<S, true>), dim3(nb), dim3(kS3Threads), 0, s, f, xin, x, fc, partial, lg,
                                    bc, zc, inv_h2, wdiag, stop);
             else
@@ -1569,7 +1582,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1}, {"zbar", &g_tune.zbar, 1, 2},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1}, {"zbar", &g_tune.zbar, 1, 2}, {"d2cpt", &g_tune.d2cpt, 1, 2}, {"d2wg", &g_tune.d2wg, 512, 1024},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1581,7 +1594,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
                 (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
                 (e.v == &g_mom_rows && value != 4 && value != 8) ||
-                (e.v == &g_tune.fbnt && value != 512 && value != 1024) ||
+                ((e.v == &g_tune.fbnt || e.v == &g_tune.d2wg) && value != 512 && value != 1024) ||
                 (e.v == &g_tune.greps && (value & (value - 1))) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
@@ -1627,6 +1640,8 @@ extern "C" int np_get_tuning(const char *key) {
     if (!std::strcmp(key, "greps")) return g_tune.greps;
     if (!std::strcmp(key, "tailck")) return g_tune.tailck;
     if (!std::strcmp(key, "zbar")) return g_tune.zbar;
+    if (!std::strcmp(key, "d2cpt")) return g_tune.d2cpt;
+    if (!std::strcmp(key, "d2wg")) return g_tune.d2wg;
     if (!std::strcmp(key, "fbmax")) return g_tune.fbmax;
     if (!std::strcmp(key, "batched_graphs")) return g_batched_graphs;
     if (!std::strcmp(key, "batched_autotune")) return g_batched_autotune;

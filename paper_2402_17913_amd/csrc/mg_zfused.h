@@ -1002,4 +1002,234 @@ __global__ __launch_bounds__(kS3Threads) __attribute__((amdgpu_waves_per_eu(size
     }
 }
 
+// k_down2z on two cells per thread: the 64 x 16 tiles of k_sweep2z (paired
+// accesses), the same three stages one plane apart and one barrier per plane
+// step (each stage's LDS plane in two slots).  Rings 1 and 2 take whole waves
+// as in k_sweep2z; the three-cell ring, whose cells only carry the iterate of
+// the plane into LDS, is a second slot of the ring-1 waves.  The residual's
+// children are summed in k_restrict3's order (the cell pair, the plane pair,
+// then the row pair by a lane shuffle).  Same values as k_down2z bit for bit.
+template <class S> struct Z4Cfg {
+    typedef Z2Cfg<S> G2;
+    static constexpr int TP = G2::TP, TX = G2::TX, TY = G2::TY, CPT = G2::CPT;
+    static constexpr int W1 = TX + 2, H1 = TY + 2, W2 = TX + 4, H2 = TY + 4, W3 = TX + 6, H3 = TY + 6;
+    static constexpr int NR1 = G2::NR1, NR2 = G2::NR2, NR3 = 2 * (TX + 6) + 2 * (TY + 4);
+    static constexpr int NW = G2::NW, NW1 = G2::NW1, NW2 = G2::NW2;
+    static_assert(CPT == 2 && TP == 32, "two cells per thread, rows ty and ty + 1 in the two halves of a wave");
+    static_assert(NR3 <= 64 * NW1, "the three-cell ring fits the ring-1 waves");
+};
+
+template <class S, bool NORM>
+__global__ __launch_bounds__(kS3Threads) void k_down2z2(const S *__restrict__ f, const S *__restrict__ xin,
+                                                        S *__restrict__ xout, S *__restrict__ fc,
+                                                        double *__restrict__ partial, int lg, int bc, int zc,
+                                                        typename St<S>::C inv_h2, typename St<S>::C wdiag,
+                                                        const int *stop) {
+    typedef typename St<S>::C C;
+    typedef Z4Cfg<S> G;
+    constexpr int TX = G::TX, TY = G::TY, TP = G::TP, W1 = G::W1, W2 = G::W2, W3 = G::W3;
+    constexpr int B1 = G::H1 * W1, B2 = G::H2 * W2, B3 = G::H3 * W3;
+    __shared__ C XA[2 * B3];  // x of planes z - 1, z (slot = plane & 1), tile and three-cell ring
+    __shared__ C X1[2 * B2];  // first sweep of planes z - 1, z, tile and two-cell ring
+    __shared__ C X2[2 * B1];  // second sweep of planes z - 2, z - 1, tile and one-cell ring
+    if (stop && *stop) return;
+    const int n = 1 << lg, ntx = n / TX, nty = n / TY, lgc = lg - 1;
+    const int blk = int(xcd_block(blockIdx.x, gridDim.x));
+    const int t = int(threadIdx.x), tp = t % TP, ty = t / TP, ai = 2 * tp;
+    const int x0 = (blk % ntx) * TX, y0 = ((blk / ntx) % nty) * TY, k0 = (blk / (ntx * nty)) * zc;
+    const int pl = 2 * lg;
+    const uint32_t osrc = (uint32_t(y0 + ty) << lg) + uint32_t(x0 + ai);
+    // ring roles of this thread's wave: ring 1 (also a three-cell-ring slot) on the first waves,
+    // ring 2 on the last, none between
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const bool r1 = wv < G::NW1, r2 = wv >= G::NW - G::NW2, rr = r1 || r2;
+    int ra = 0, rb = 0, ta = 0, tb = 0;
+    if (r1) {
+        ring_pos<TX, TY>(min(t, G::NR1 - 1), 1, ra, rb);
+        ring_pos<TX, TY>(min(t, G::NR3 - 1), 3, ta, tb);
+    }
+    if (r2) ring_pos<TX, TY>(min(t - 64 * (G::NW - G::NW2), G::NR2 - 1), 2, ra, rb);
+    uint32_t rsrc, tsrc;
+    C rsg, tsg;
+    {
+        int s1 = 1, s3 = 1;
+        const int gi = bmap(x0 + ra, n, bc, s1), gj = bmap(y0 + rb, n, bc, s1);
+        rsrc = (uint32_t(gj) << lg) + uint32_t(gi);
+        rsg = C(s1);
+        const int hi = bmap(x0 + ta, n, bc, s3), hj = bmap(y0 + tb, n, bc, s3);
+        tsrc = (uint32_t(hj) << lg) + uint32_t(hi);
+        tsg = C(s3);
+    }
+    const int own_a = (ty + 3) * W3 + ai + 3, own_1 = (ty + 2) * W2 + ai + 2, own_2 = (ty + 1) * W1 + ai + 1;
+    const int ring_a = (rb + 3) * W3 + ra + 3, ring_1 = (rb + 2) * W2 + ra + 2, ring_2 = (rb + 1) * W1 + ra + 1;
+    const int r3_a = (tb + 3) * W3 + ta + 3;
+    // Dirichlet walls next to a position (the ghosts of the second sweep and the residual)
+    bool dw[2], de[2];
+    for (int c = 0; c < 2; ++c) {
+        dw[c] = !bc && x0 + ai + c == 0;
+        de[c] = !bc && x0 + ai + c == n - 1;
+    }
+    const bool ds = !bc && y0 + ty == 0, dn = !bc && y0 + ty == n - 1;
+    const bool qw = !bc && x0 + ra == 0, qe = !bc && x0 + ra == n - 1;
+    const bool qs = !bc && y0 + rb == 0, qn = !bc && y0 + rb == n - 1;
+    auto poff = [&](int q) -> uint32_t {
+        bool flip;
+        return uint32_t(plane_map(q, n, bc, flip)) << pl;
+    };
+    auto psign = [&](int q) -> C { return (!bc && (q < 0 || q >= n)) ? C(-1) : C(1); };
+    auto ld2 = [&](const S *base, C (&v)[2]) { Pair<S>::ld(base + osrc, v[0], v[1]); };
+    // a sweep at an LDS position with in-plane neighbours from frame L (row width W), z-neighbours
+    // given; the residual r of the input
+    auto sweepL = [&](const C *L, int W, int q, C xc, C xm, C xp, C fv, C &r) -> C {
+        const C t0 = ((L[q - 1] + L[q + 1]) + L[q - W]) + L[q + W];
+        const C s = (t0 + xm) + xp;
+        r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+    // the same with Dirichlet ghosts selected as minus the centre value
+    auto sweepD = [&](const C *L, int W, int q, C xc, C xm, C xp, C fv, bool w, bool e, bool so, bool no,
+                      bool zl, bool zu, C &r) -> C {
+        const C lw = L[q - 1], le = L[q + 1], ls = L[q - W], ln = L[q + W];
+        const C xw = w ? -xc : lw, xe = e ? -xc : le, ys = so ? -xc : ls, yn = no ? -xc : ln;
+        const C zm = zl ? -xc : xm, zp = zu ? -xc : xp;
+        const C t0 = ((xw + xe) + ys) + yn;
+        const C s = (t0 + zm) + zp;
+        r = fv - (C(6) * xc - s) * inv_h2;
+        return xc + wdiag * r;
+    };
+    // registers: own x at z - 1 .. z + 1, x1 at z - 2 .. z, x2 at z - 3, z - 2, f at z, z - 1, z - 2;
+    // ring cell (rings 1 and 2): x at z - 1 .. z + 1, x1 at z - 2 .. z (ring 1), f at z, z - 1;
+    // three-cell-ring slot: x at z
+    C xo[3][2], x1o[3][2], x2o[2][2], fo[3][2];
+    C rx[3] = {C(0), C(0), C(0)}, r1x[3] = {C(0), C(0), C(0)}, rf[2] = {C(0), C(0)}, r3x = C(0);
+    C pw[2][2], pf[2][2], pr[2] = {C(0), C(0)}, pq[2] = {C(0), C(0)}, p3[2] = {C(0), C(0)};  // in flight
+    for (int c = 0; c < 2; ++c) {
+        for (int i = 0; i < 3; ++i) x1o[i][c] = fo[i][c] = C(0);
+        x2o[0][c] = x2o[1][c] = C(0);
+    }
+    // the step at plane z consumes x(z + 2) and f(z + 1) at the own cells and the ring cell, and
+    // x(z + 1) at the three-cell-ring slot; past the planes used the last one is read again
+    auto pload = [&](int z, auto u) {
+        constexpr int U = decltype(u)::value;
+        const uint32_t o2 = poff(min(z + 2, k0 + zc + 2)), o1 = poff(min(z + 1, k0 + zc + 1));
+        ld2(xin + o2, pw[U]);
+        ld2(f + o1, pf[U]);
+        pr[U] = St<S>::ld(xin + o2 + rsrc);
+        pq[U] = St<S>::ld(f + o1 + rsrc);
+        p3[U] = St<S>::ld(xin + o1 + tsrc);
+    };
+    // prologue: x at k0 - 3 .. k0 - 1, f at k0 - 2 (own, ring); three-cell ring: x at k0 - 2
+    for (int i = 0; i < 3; ++i) {
+        const int q = k0 - 3 + i;
+        const C sg = psign(q);
+        ld2(xin + poff(q), xo[i]);
+        for (int c = 0; c < 2; ++c) xo[i][c] *= sg;
+        rx[i] = (sg * rsg) * St<S>::ld(xin + poff(q) + rsrc);
+    }
+    ld2(f + poff(k0 - 2), fo[0]);
+    rf[0] = St<S>::ld(f + poff(k0 - 2) + rsrc);
+    r3x = (psign(k0 - 2) * tsg) * St<S>::ld(xin + poff(k0 - 2) + tsrc);
+    pload(k0 - 2, std::integral_constant<int, 0>{});
+    double acc = 0.0;
+    C pair = C(0);
+    auto step = [&](int z, auto odd) {
+        constexpr bool ODD = decltype(odd)::value;
+        constexpr int U = ODD ? 1 : 0;
+        pload(z + 1, std::integral_constant<int, 1 - U>{});
+        // x of plane z into its slot: own cells, the ring cell, the three-cell-ring slot.  The
+        // step's one barrier follows: stages B and C read what the previous step wrote, and
+        // every slot written here was last read before it
+        C *LA = XA + (ODD ? B3 : 0);
+        for (int c = 0; c < 2; ++c) LA[own_a + c] = xo[1][c];
+        if (rr) LA[ring_a] = rx[1];
+        if (r1) LA[r3_a] = r3x;
+        __syncthreads();
+        // stage A: first sweep at plane z, own cells, rings 1 and 2
+        C *L1 = X1 + (ODD ? B2 : 0);
+        for (int c = 0; c < 2; ++c) {
+            C r;
+            const C v = st_round<S>(sweepL(LA, W3, own_a + c, xo[1][c], xo[0][c], xo[2][c], fo[0][c], r));
+            if (NORM && z >= k0 && z < k0 + zc) acc += double(r) * double(r);
+            L1[own_1 + c] = v;
+            x1o[2][c] = v;  // x1 at z (registers slide at the end of the step)
+        }
+        if (rr) {
+            C r;
+            const C v = st_round<S>(sweepL(LA, W3, ring_a, rx[1], rx[0], rx[2], rf[0], r));
+            L1[ring_1] = v;
+            r1x[2] = v;
+        }
+        // stage B: second sweep at plane z - 1 (x1 written by the previous step), own cells and ring 1
+        const int p = z - 1;
+        const C *M1 = X1 + (ODD ? 0 : B2);
+        C *L2 = X2 + (ODD ? 0 : B1);
+        const bool zl1 = !bc && p == 0, zu1 = !bc && p == n - 1;
+        C x2n[2] = {C(0), C(0)};
+        if (z >= k0) {
+            C r;
+            for (int c = 0; c < 2; ++c) {
+                x2n[c] = st_round<S>(sweepD(M1, W2, own_1 + c, x1o[1][c], x1o[0][c], x1o[2][c], fo[1][c], dw[c],
+                                            de[c], ds, dn, zl1, zu1, r));
+                L2[own_2 + c] = x2n[c];
+            }
+            if (p >= k0 && p < k0 + zc) Pair<S>::st(xout + (uint32_t(p) << pl) + osrc, x2n[0], x2n[1]);
+            if (r1) {
+                L2[ring_2] = st_round<S>(sweepD(M1, W2, ring_1, r1x[1], r1x[0], r1x[2], rf[1], qw, qe, qs, qn, zl1,
+                                                zu1, r));
+            }
+        }
+        // stage C: residual of x2 at plane z - 2 (written by the previous step), own cells, into the
+        // coarse cells: the cell pair, the plane pair, then the row pair
+        if (z >= k0 + 2) {
+            const int pc = z - 2;
+            const C *M2 = X2 + (ODD ? B1 : 0);
+            const bool zl = !bc && pc == 0, zu = !bc && pc == n - 1;
+            C rc[2];
+            for (int c = 0; c < 2; ++c)
+                (void)sweepD(M2, W1, own_2 + c, x2o[1][c], x2o[0][c], x2n[c], fo[2][c], dw[c], de[c], ds, dn, zl, zu,
+                             rc[c]);
+            const C rxp = rc[0] + rc[1];
+            if (ODD) {  // pc odd: the second plane of the pair
+                pair += rxp;
+                const uint32_t cc = (uint32_t(pc >> 1) << (2 * lgc)) + (uint32_t((y0 + ty) >> 1) << lgc) +
+                                    uint32_t((x0 + ai) >> 1);
+                const C o = __shfl_down(pair, 32);
+                if ((ty & 1) == 0) St<S>::st(fc + cc, (pair + o) * C(0.125));
+            } else {
+                pair = rxp;
+            }
+        }
+        // slide
+        const C sg2 = psign(z + 2), sg1 = psign(z + 1);
+        for (int c = 0; c < 2; ++c) {
+            x2o[0][c] = x2o[1][c];
+            x2o[1][c] = x2n[c];
+            x1o[0][c] = x1o[1][c];
+            x1o[1][c] = x1o[2][c];
+            fo[2][c] = fo[1][c];
+            fo[1][c] = fo[0][c];
+            fo[0][c] = pf[U][c];
+            xo[0][c] = xo[1][c];
+            xo[1][c] = xo[2][c];
+            xo[2][c] = sg2 * pw[U][c];
+        }
+        r1x[0] = r1x[1];
+        r1x[1] = r1x[2];
+        rf[1] = rf[0];
+        rf[0] = pq[U];
+        rx[0] = rx[1];
+        rx[1] = rx[2];
+        rx[2] = (sg2 * rsg) * pr[U];
+        r3x = (sg1 * tsg) * p3[U];
+    };
+    for (int z = k0 - 2; z < k0 + zc + 2; z += 2) {  // k0 even: pairs (even, odd)
+        step(z, std::false_type{});
+        step(z + 1, std::true_type{});
+    }
+    if constexpr (NORM) {
+        acc = block_sum_n<kS3Threads>(acc);
+        if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    }
+}
+
 }  // namespace np
