@@ -469,8 +469,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * levels from 128^3 to 1024^3 -- the pre-sweeps of a nonzero iterate, with the convergence check, and the
  * up-leg with prolongation + correction; default 1), "down2z" (0/1: in FP64 and FP32, from 256^3, the
  * residual and the restriction in the down-leg's two-sweep pass too; default 1), "d2cpt" (1 or 2: that pass on
- * one cell per thread or two, default 2; FP32 takes it only with 2), "d2wg" (512 or 1024: workgroups the
- * two-cell form aims for, default 512), "blk2" (0/1: 2D levels of
+ * one cell per thread or two, default 2; FP32 takes it only with 2), "d2wg" (256, 512 or 1024: workgroups the
+ * two-cell form aims for; default 0, which takes 256 in FP64 and 512 in FP32), "blk2" (0/1: 2D levels of
  * 128^2 .. 1024^2 take one block kernel per leg, both sweeps with the residual and restriction, or prolongation +
  * correction with both post-sweeps; default 1), "z2wg" (0/1: the 3D one-pass kernels that fit fewer than four
  * workgroups per CU -- the up-leg, FP64's zero-start down-leg -- take planes for 512 workgroups, not 1024;

@@ -122,7 +122,7 @@ struct Tuning {
     int tailck = 1;       // the cycle's convergence check run by the one-workgroup tail kernel
     int zbar = 1;         // barriers per plane step of the 3D zero-start down-leg pass (1 or 2)
     int d2cpt = 2;        // cells per thread of the 3D nonzero down-leg pass (1: k_down2z, 2: k_down2z2)
-    int d2wg = 512;       // workgroups k_down2z2 aims for (512 or 1024)
+    int d2wg = 0;         // workgroups k_down2z2 aims for (256, 512 or 1024; 0: 256 in FP64, 512 otherwise)
     int sweep3 = 1;       // z-marching sweep, restriction, prolongation and refinement kernels (3D, n >= 128)
     int psweep = 1;       // prolongation + correction and the first post-sweep in one z-marching kernel
     int ir_cpt = 2;       // cells per thread of the 3D z-marching refinement kernel (1 or 2)
@@ -679,7 +679,10 @@ template <int D, class S> struct Ops {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
             const bool two = g_tune.d2cpt == 2;  // two cells per thread (k_down2z2)
-            const int zc = two ? sweep2z_planes<S>(lg, g_tune.d2wg) : down2z_planes<S>(lg);
+            // two cells per thread: one workgroup per CU in FP64 (148 VGPRs: the FP64 solve measured
+            // 6.18 ms at 512 workgroups, 5.95 at 256), two in FP32 (85: 3.97 ms at 512, 4.13 at 256)
+            const int wg2 = g_tune.d2wg ? g_tune.d2wg : (sizeof(S) == 8 ? 256 : 512);
+            const int zc = two ? sweep2z_planes<S>(lg, wg2) : down2z_planes<S>(lg);
             const unsigned nb = zblocks(lg, two ? 2 : 1, zc);
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & kProfDown);
@@ -1582,7 +1585,7 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
         {"inner_fp32", &g_tune.inner_fp32, 1, 64}, {"inner_bf16", &g_tune.inner_bf16, 1, 64},
         {"batch", &g_tune.batch, 1, 64},        {"sweep3", &g_tune.sweep3, 0, 1},
         {"zero2", &g_tune.zero2, 0, 1},         {"psweep", &g_tune.psweep, 0, 1},
-        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1}, {"zbar", &g_tune.zbar, 1, 2}, {"d2cpt", &g_tune.d2cpt, 1, 2}, {"d2wg", &g_tune.d2wg, 512, 1024},
+        {"ir_cpt", &g_tune.ir_cpt, 1, 2},      {"fuseb", &g_tune.fuseb, 0, 1}, {"fbnt", &g_tune.fbnt, 512, 1024},  {"sweep2z", &g_tune.sweep2z, 0, 1}, {"down2z", &g_tune.down2z, 0, 1}, {"blk2", &g_tune.blk2, 0, 1}, {"z2wg", &g_tune.z2wg, 0, 1}, {"greps", &g_tune.greps, 1, 8}, {"tailck", &g_tune.tailck, 0, 1}, {"zbar", &g_tune.zbar, 1, 2}, {"d2cpt", &g_tune.d2cpt, 1, 2}, {"d2wg", &g_tune.d2wg, 0, 1024},
         {"fbmax", &g_tune.fbmax, 5, 10},
         {"batched_graphs", &g_batched_graphs, 0, 1}, {"batched_autotune", &g_batched_autotune, 0, 1},
         {"batched_rm", &g_batched_rm, 0, 1},    {"batched_wg", &g_batched_wg, 64, 1 << 20},
@@ -1594,7 +1597,8 @@ extern "C" np_status np_set_tuning(const char *key, int value) {
             if (value < e.lo || value > e.hi || ((e.v == &g_tune.bz2 || e.v == &g_tune.bz3) && (value & 1)) ||
                 (e.v == &g_zc3 && value != 0 && (value < 2 || (value & (value - 1)))) ||
                 (e.v == &g_mom_rows && value != 4 && value != 8) ||
-                ((e.v == &g_tune.fbnt || e.v == &g_tune.d2wg) && value != 512 && value != 1024) ||
+                (e.v == &g_tune.fbnt && value != 512 && value != 1024) ||
+                (e.v == &g_tune.d2wg && value != 0 && value != 256 && value != 512 && value != 1024) ||
                 (e.v == &g_tune.greps && (value & (value - 1))) ||
                 (e.v == &g_conv3z && value > 1 && (value & (value - 1)))) {
                 set_error("value %d out of range for %s", value, key);
