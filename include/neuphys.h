@@ -473,8 +473,8 @@ np_status np_prof_level(np_dims dims, double h, np_bc bc, np_prec prec, int kind
  * two-cell form aims for; default 0, which takes 256 in FP64 and 512 in FP32), "blk2" (0/1: 2D levels of
  * 128^2 .. 1024^2 take one block kernel per leg, both sweeps with the residual and restriction, or prolongation +
  * correction with both post-sweeps; default 1), "z2wg" (0/1: the 3D one-pass kernels that fit fewer than four
- * workgroups per CU -- the up-leg, FP64's zero-start down-leg -- take planes for 512 workgroups, not 1024;
- * default 1), "greps" (1, 2, 4 or 8: the most cycles, or refinement steps, one replayed graph holds;
+ * workgroups per CU -- the up-leg, FP64's zero-start down-leg -- take planes for 512 workgroups, not 1024
+ * (the FP64 up-leg for 256); default 1), "greps" (1, 2, 4 or 8: the most cycles, or refinement steps, one replayed graph holds;
  * default 8), "tailck" (0/1: a cycle's convergence check run by the one-workgroup kernel of its coarse levels
  * rather than by a launch of its own; default 1), "zbar" (1 or 2: barriers per plane step of the 3D zero-start
  * down-leg pass, default 1), "batched_graphs", "batched_autotune" and "batched_rm" (0/1 for the

@@ -605,7 +605,8 @@ template <int D, class S> struct Ops {
         if constexpr (D == 3) {
             const C inv_h2 = C(1.0 / (h * h)), wdiag = C(omega * h * h / (2.0 * D));
             constexpr int CPT = ZCfg<S>::CPT;
-            const int zc = sweep2z_planes<S>(lg, ec && g_tune.z2wg ? 512 : 1024);
+            // up-leg: 512 workgroups (two per CU), 256 in FP64 (one per CU at 129 VGPRs)
+            const int zc = sweep2z_planes<S>(lg, ec && g_tune.z2wg ? (sizeof(S) == 8 ? 256 : 512) : 1024);
             const unsigned nb = zblocks(lg, CPT, zc);
             void *tok = nullptr;
             const bool prof = finest && (prof_on() & (ec ? kProfUp : kProfJacobi));

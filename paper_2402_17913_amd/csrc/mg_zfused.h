@@ -122,12 +122,13 @@ __global__ __launch_bounds__(kS3Threads) void k_sweep2z(const S *__restrict__ ec
     constexpr int TX = G::TX, TY = G::TY, CPT = G::CPT, TP = G::TP, W1 = G::W1, W2 = G::W2, CW = G::CW;
     constexpr int BS = G::H1 * W1;          // one first-sweep plane in LDS
     constexpr int AS = G::H2 * W2;          // one x' plane in LDS
-    // ONE (FP32, BF16): one barrier per plane step, x' of planes z - 1 and z in two slots (the
-    // second sweep reads the first sweep of the previous step).  Measured at 256^3 and 128^3
-    // (average per launch): FP32 up-leg 25.5 -> 24.5 us, BF16 up-leg 24.4 -> 23.4, BF16 down-leg
-    // 30.1 -> 28.8; FP64 keeps two barriers (up-leg 47.8 against 50.5 us: one barrier takes it
-    // past 128 VGPRs)
-    constexpr bool ONE = sizeof(S) < 8;
+    // one barrier per plane step, x' of planes z - 1 and z in two slots (the second sweep reads
+    // the first sweep of the previous step).  Measured at 256^3 and 128^3 (average per launch):
+    // FP32 up-leg 25.5 -> 24.5 us, BF16 up-leg 24.4 -> 23.4, BF16 down-leg 30.1 -> 28.8.  In FP64
+    // it takes the up-leg past 128 VGPRs (one workgroup per CU): at 512 workgroups 47.8 against
+    // 50.5 us, but launched as 256 workgroups (one round) the FP64 solve measured 5.99 -> 5.90 ms
+    // (two barriers at 256: 5.92 ms)
+    constexpr bool ONE = true;
     __shared__ C Ax[(ONE ? 2 : 1) * AS];    // x' of plane z (ONE: slot = plane & 1), tile and two-cell ring
     __shared__ C Bs[2 * BS];                // first sweep of planes z - 1, z (slot = plane & 1), tile and ring
     __shared__ C Ec[CORR ? 4 : 1][CORR ? G::CR + 1 : 1];  // coarse planes (slot = plane & 3), one spare cell
